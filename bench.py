@@ -1,0 +1,182 @@
+"""Benchmark: one step = the whole hot path on one batch of synthetic input.
+
+A step builds the index (boundary + renumbering, APSP of every component,
+BG assembly, all-pairs distances in BG) and answers one batch of query pairs,
+on the 256x256 grid with random diagonals (65,536 vertices, 1,024 blocks of
+8x8, 100,000 uniform pairs).  Inputs are resident in HBM before timing.
+
+Prints ONE JSON line.  `value` is Floyd-Warshall relaxations per second over
+the whole step (sum of |C|^3 over components plus V_BG^3, divided by the
+step time, queries included).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz; a relaxation costs one
+# add and half of a three-input min (1.5 VALU operations) in the kernels.
+VALU_OPS_PER_S = 256 * 64 * 2.4e9
+RELAX_PEAK = VALU_OPS_PER_S / 1.5
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--queries", type=int, default=100_000)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    return p.parse_args()
+
+
+def cpu_baseline(g, st, budget_s):
+    """The oracle on a bounded sample of the same workload, scaled up."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n, k = g["n"], g["k"]
+    t0 = time.perf_counter()
+    members, apsp = oracle.component_apsp(n, g["eu"], g["ev"], g["w"], g["part"], k,
+                                          nthreads=threads)
+    t_comp = time.perf_counter() - t0
+    bg_ids, bverts, bu, bv, bw = oracle.boundary_graph(n, g["eu"], g["ev"], g["w"], g["part"], k,
+                                                       members, apsp)
+    V = len(bg_ids)
+    # time a few sources first, then size the sample to the budget
+    t0 = time.perf_counter()
+    oracle.bg_apsp(bg_ids, bu, bv, bw, sources=np.arange(64), nthreads=threads)
+    per_src = (time.perf_counter() - t0) / 64
+    nsrc = int(min(V, max(64, budget_s * 0.6 / max(per_src, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.bg_apsp(bg_ids, bu, bv, bw, sources=np.arange(nsrc), nthreads=threads)
+    t_bg_sample = time.perf_counter() - t0
+    t_bg = t_bg_sample * V / nsrc
+    relax = st["relax_comp"] + st["relax_bg"]
+    build_s = t_comp + t_bg
+    # the paper's baseline for queries: one Dijkstra per query on G
+    nq = 64
+    t0 = time.perf_counter()
+    oracle.dijkstra(n, g["eu"], g["ev"], g["w"], g["v1"][:nq], nthreads=threads)
+    q_s = (time.perf_counter() - t0) / nq
+    return {
+        "value": relax / build_s, "unit": "relax/s (Floyd-Warshall equivalent)",
+        "cores": threads, "kind": "oracle",
+        "sample": ("all %d component Floyd-Warshalls (%.2f s) + Dijkstra in BG from %d of %d "
+                   "sources (%.2f s, scaled x%.1f); index build extrapolated to %.1f s"
+                   % (k, t_comp, nsrc, V, t_bg_sample, V / nsrc, build_s)),
+        "build_s": build_s,
+        "queries_per_s": 1.0 / q_s,
+        "query_sample": "Dijkstra on G from the first %d query sources" % nq,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the index of one GPU's share is built and "
+              "queried locally; multi-GPU sharding is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1503_07192_amd import spq, workloads as W
+
+    torch.cuda.set_device(0)
+    g = W.grid256d(queries=args.queries)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+    eu, ev, w, part = dev(g["eu"]), dev(g["ev"]), dev(g["w"]), dev(g["part"])
+    v1, v2 = dev(g["v1"]), dev(g["v2"])
+    out = torch.empty_like(v1)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def step(record):
+        idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        spq.query_batch(idx, v1, v2, out, stream=stream)
+        e1.record(stream)
+        st = spq.index_stats(idx)
+        e1.synchronize()
+        if record is not None:
+            st["ms_query"] = e0.elapsed_time(e1)
+            record.append(st)
+        idx.free()
+
+    for _ in range(args.warmup):
+        step(None)
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    st = recs[-1]
+    relax = st["relax_comp"] + st["relax_bg"]
+    ms_step = elapsed * 1e3 / args.steps
+    q = len(g["v1"])
+    mq = np.array([r["ms_query"] for r in recs])
+    bg_ms = np.array([r["ms_bg_apsp"] for r in recs])
+    inner_rate = np.median(st["relax_bg"] / (bg_ms * 1e-3))
+
+    # one query per launch (the plain comparator), after the timed region
+    idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], stream=stream)
+    lat = []
+    for i in range(200):
+        a, b = v1[i:i + 1], v2[i:i + 1]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        spq.query_batch(idx, a, b, out[i:i + 1], stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1) * 1e3)
+    idx.free()
+    lat = np.array(lat)
+
+    # bytes the query kernel must move: both row prefixes, the BG block, ids, result
+    nbv = st["v_bg"] / st["k"]
+    qbytes = 4 * (nbv + nbv * nbv + nbv) + 12 + 16
+
+    line = {
+        "metric": "min-plus relaxations/s (index build); queries/s + p50/p99 query latency",
+        "value": relax * args.steps / elapsed,
+        "unit": "relax/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "grid256d: 256x256 grid + random cell diagonals, weights U[1,1000], "
+                               "1,024 blocks of 8x8, %d uniform query pairs" % q,
+                   "n": g["n"], "m": g["m"], "k": g["k"], "v_bg": st["v_bg"], "queries": q},
+        "phase_ms": {key: float(np.median([r[key] for r in recs]))
+                     for key in ("ms_partition", "ms_components", "ms_bg_assembly",
+                                 "ms_bg_apsp", "ms_query")},
+        "relax_per_step": relax,
+        "queries_per_s": q / (np.median(mq) * 1e-3),
+        "query_batch_ms_p50": float(np.percentile(mq, 50)),
+        "query_batch_ms_p99": float(np.percentile(mq, 99)),
+        "single_query_us_p50": float(np.percentile(lat, 50)),
+        "single_query_us_p99": float(np.percentile(lat, 99)),
+        "roofline": {"bound": "alu", "kernel": "BG Floyd-Warshall rounds (diag+panel+inner)",
+                     "achieved": inner_rate / 1e12, "peak": RELAX_PEAK / 1e12,
+                     "unit": "Trelax/s", "frac": inner_rate / RELAX_PEAK, "traffic": None},
+        "query_roofline": {"bound": "hbm", "achieved": q * qbytes / (np.median(mq) * 1e-3) / 1e9,
+                           "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                           "frac": q * qbytes / (np.median(mq) * 1e-3) / HBM_PEAK,
+                           "bytes_per_query": qbytes},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(g, st, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * spq.h - exact shortest-path distance queries on a partitioned planar graph,
+ * computed on one AMD Instinct MI355X (gfx950).
+ *
+ * The data structure is the one of Chapuis & Djidjev, "Shortest-Path Queries
+ * in Planar Graphs on GPU-Accelerated Architectures" (arXiv 1503.07192):
+ *
+ *   preprocessing (Algorithm 1)
+ *     - the boundary: vertices with a neighbour in another component (Sec. 2);
+ *       vertices are renumbered so that every component is contiguous and its
+ *       boundary vertices come first (Sec. 4, Fig. 1);
+ *     - APSP(C): all-pairs distances inside the subgraph induced by each
+ *       component C (Phase 2);
+ *     - BG: the boundary vertices, joined by the edges of G between them and,
+ *       inside each component, by edges weighted with the APSP(C) distance;
+ *       then all-pairs distances in BG (Phase 3; by Lemma 1 they equal the
+ *       distances in G).
+ *   query (Algorithm 2)
+ *     dist(v1,v2) = min over b1 in B(C1), b2 in B(C2) of
+ *                   dist_C1(v1,b1) + dist_BG(b1,b2) + dist_C2(b2,v2),
+ *     and, when C1 = C2, also dist_C1(v1,v2).
+ *
+ * Arithmetic is exact int32.  SPQ_INF (2^31-1) means "no path".  Graphs are
+ * undirected: the edge (u,v,w) may be walked both ways.  Every call returns a
+ * status; nothing aborts or throws across this interface.  The library is
+ * bound to the HIP device current at spq_build_index; call the other
+ * functions with that device current.
+ */
+#ifndef SPQ_H
+#define SPQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPQ_INF 2147483647
+#define SPQ_BAD_PAIR (-1) /* query output for a vertex id outside [0, n) */
+
+typedef enum {
+  SPQ_OK = 0,
+  SPQ_EINVAL = 1,  /* bad argument: id, weight, partition, empty component */
+  SPQ_ENOMEM = 2,  /* device allocation failed */
+  SPQ_EDEVICE = 3, /* a HIP call failed */
+  SPQ_ERANGE = 4   /* distances might not fit below SPQ_INF */
+} spq_status;
+
+typedef struct spq_index spq_index; /* opaque; owns all its device memory */
+
+typedef struct {
+  int32_t bg_tile;     /* tile of the BG Floyd-Warshall: 0 (default 128), 64, 128 */
+  int32_t reserved[7]; /* must be 0 */
+} spq_build_opts;
+
+typedef struct {
+  int32_t n, k;            /* vertices, components */
+  int64_t m;               /* edges as given */
+  int32_t v_bg;            /* boundary vertices = BG vertices */
+  int32_t v_bg_padded;     /* BG matrix side after padding to the tile */
+  int32_t max_comp;        /* largest component */
+  int32_t max_boundary;    /* largest |B(C)| */
+  int64_t comp_bytes;      /* bytes of all APSP(C) tables (padded) */
+  int64_t bg_bytes;        /* bytes of the BG distance matrix (padded) */
+  double relax_comp;       /* sum over C of |C|^3: Floyd-Warshall relaxations, Phase 2 */
+  double relax_bg;         /* v_bg^3: Floyd-Warshall relaxations in BG, Phase 3 */
+  float ms_partition;      /* device time: boundary, renumbering (through the host plan) */
+  float ms_components;     /* device time: APSP(C) initialisation + Floyd-Warshall */
+  float ms_bg_assembly;    /* device time: BG matrix assembly */
+  float ms_bg_apsp;        /* device time: Floyd-Warshall in BG */
+} spq_stats;
+
+/*
+ * Preprocessing, Algorithm 1.
+ *   n, m          vertex and edge counts (n >= 1, m >= 0)
+ *   eu, ev, w     DEVICE arrays of m int32: edge (eu[i], ev[i]) of weight w[i];
+ *                 0 <= w < SPQ_INF; self-loops are ignored; parallel edges
+ *                 keep the lightest
+ *   part          DEVICE array of n int32 in [0, k): the component of each
+ *                 vertex (the k-partition of Section 2); every component
+ *                 must be non-empty
+ *   opts          may be NULL
+ *   stream        hipStream_t the work is queued on (NULL = default stream)
+ *   out           receives the index; on error *out is NULL
+ * The inputs are read during the call only and stay owned by the caller.
+ * The call blocks until the partition sizes are known (one small device to
+ * host copy), then queues the remaining work on `stream` and returns; the
+ * index is usable by work queued later on the same stream.
+ * Errors: SPQ_EINVAL (bad id, weight or part, empty component, k < 1),
+ * SPQ_ERANGE (the total edge weight reaches SPQ_INF, so a distance might not
+ * fit), SPQ_ENOMEM, SPQ_EDEVICE.
+ */
+spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
+                           const int32_t* w, const int32_t* part, int32_t k,
+                           const spq_build_opts* opts, void* stream, spq_index** out);
+
+/*
+ * Queries, Algorithm 2: out[i] = dist(v1[i], v2[i]) for i < q.
+ *   v1, v2, out   DEVICE arrays of q int32, owned by the caller
+ *   stream        hipStream_t (NULL = default stream); the call is asynchronous
+ * A pair with an id outside [0, n) yields SPQ_BAD_PAIR in its slot; other
+ * slots are unaffected.  Read-only on the index: calls may run concurrently
+ * on different streams.  Errors: SPQ_EINVAL (null index, q < 0), SPQ_EDEVICE.
+ */
+spq_status spq_query_batch(const spq_index* idx, int64_t q, const int32_t* v1,
+                           const int32_t* v2, int32_t* out, void* stream);
+
+/* Sizes, work counts and per-phase device times (waits for the build). */
+spq_status spq_index_stats(const spq_index* idx, spq_stats* st);
+
+/*
+ * The renumbering (Section 4, Fig. 1), copied to HOST arrays (any may be NULL):
+ *   comp[n]    component of each vertex
+ *   local[n]   index of the vertex inside its component; boundary vertices
+ *              take 0 .. nb[c]-1 in ascending id order, then the interior
+ *              vertices in ascending id order
+ *   nb[k]      |B(C)|
+ *   off[k+1]   first renumbered vertex of each component
+ *   bgoff[k+1] first BG vertex of each component (BG id = bgoff[c] + local)
+ * Synchronous.
+ */
+spq_status spq_index_layout(const spq_index* idx, int32_t* comp, int32_t* local,
+                            int32_t* nb, int32_t* off, int32_t* bgoff);
+
+/* APSP(C) of component c, |C| x |C| int32 row-major in the local order above,
+ * copied to the HOST array out.  Synchronous. */
+spq_status spq_index_component(const spq_index* idx, int32_t c, int32_t* out);
+
+/* Rows [row0, row0+nrows) of the BG distance matrix (v_bg columns each),
+ * copied to the HOST array out.  Synchronous. */
+spq_status spq_index_bg_rows(const spq_index* idx, int32_t row0, int32_t nrows,
+                             int32_t* out);
+
+/* Releases the index and its device memory (waits for its work). NULL is ok. */
+void spq_free_index(spq_index* idx);
+
+/* Message of the last error on this thread ("" if none). */
+const char* spq_last_error(void);
+
+/*
+ * Test hooks: the Floyd-Warshall kernels on caller-owned DEVICE buffers.
+ * Inputs must be symmetric (undirected graphs), 0 on the diagonal, with
+ * entries in [0, SPQ_INF]; they are closed in place to all-pairs distances.
+ *
+ * spq_fw_components: count matrices; matrix i has side size[i] (HOST array)
+ *   and starts at element off[i] (HOST array) of `data`; its leading
+ *   dimension is ld[i] (HOST array), a multiple of 64 with ld[i] >= size[i].
+ *   Rows and columns in [size[i], ld[i]) must hold SPQ_INF off the diagonal
+ *   and 0 on it.  One workgroup closes one whole matrix (the APSP(C) kernel).
+ * spq_fw_dense: one v x v matrix with leading dimension ld (a multiple of
+ *   tile, padded like above); blocked Floyd-Warshall in rounds of three
+ *   kernels (the BG kernel).  tile is 64 or 128.
+ * spq_fw_components stages its size tables on the device and returns when
+ * the work is done; spq_fw_dense is asynchronous on `stream`.
+ * Errors: SPQ_EINVAL, SPQ_ENOMEM, SPQ_EDEVICE.
+ */
+spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* off,
+                             const int32_t* ld, int32_t* data, void* stream);
+spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t* data, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPQ_H */

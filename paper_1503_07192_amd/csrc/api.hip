@@ -1,0 +1,341 @@
+// C-ABI of the shortest-path query library: index construction (Algorithm 1),
+// batched queries (Algorithm 2), inspection and test hooks.  Declarations and
+// their contracts are in include/spq.h.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/spq.h"
+#include "spq_internal.h"
+
+using spq::u32;
+
+namespace {
+
+thread_local std::string g_err;
+
+spq_status fail(spq_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      return fail(e_ == hipErrorOutOfMemory ? SPQ_ENOMEM : SPQ_EDEVICE,                \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+    }                                                                                  \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)count);
+}
+
+int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
+
+}  // namespace
+
+struct spq_index {
+  int device = 0;
+  int32_t n = 0, k = 0, V = 0, Vp = 0, tile = 128, max_comp = 0, max_nb = 0;
+  int64_t m = 0, comp_elems = 0;
+  std::vector<int32_t> h_cnt, h_nb, h_off, h_bgoff, h_P, h_order;
+  std::vector<int64_t> h_moff;
+  std::vector<unsigned long long> h_sumc;
+  // device memory owned by the index
+  int32_t *comp = nullptr, *local = nullptr, *nb = nullptr, *off = nullptr, *bgoff = nullptr;
+  int32_t *P = nullptr, *order = nullptr, *bgcomp = nullptr, *bglocal = nullptr;
+  int32_t *cnt = nullptr, *fill = nullptr;
+  int64_t* moff = nullptr;
+  uint8_t* flag = nullptr;
+  unsigned long long *sumc = nullptr, *total = nullptr;
+  u32 *err = nullptr, *members = nullptr, *M = nullptr, *BG = nullptr;
+  hipEvent_t ev[5] = {};
+  bool events = false;
+  double relax_comp = 0, relax_bg = 0;
+
+  ~spq_index() {
+    if (events) {
+      (void)hipEventSynchronize(ev[4]);
+      for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+    void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
+                    cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+extern "C" {
+
+const char* spq_last_error(void) { return g_err.c_str(); }
+
+spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
+                           const int32_t* w, const int32_t* part, int32_t k,
+                           const spq_build_opts* opts, void* stream, spq_index** out) {
+  g_err.clear();
+  if (!out) return fail(SPQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || m < 0 || k < 1) return fail(SPQ_EINVAL, "need n >= 1, m >= 0, k >= 1");
+  if (k > n) return fail(SPQ_EINVAL, "k > n: some component would be empty");
+  if (!part || (m > 0 && (!eu || !ev || !w))) return fail(SPQ_EINVAL, "null input array");
+  if (n > 0x7fffffff - 1) return fail(SPQ_EINVAL, "n too large");
+  int tile = 128;
+  if (opts) {
+    if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
+      return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
+    if (opts->bg_tile) tile = opts->bg_tile;
+    for (int i = 0; i < 7; i++)
+      if (opts->reserved[i]) return fail(SPQ_EINVAL, "reserved options must be 0");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  spq_index* X = new spq_index();
+  auto guard = [&](spq_status st) {
+    delete X;
+    return st;
+  };
+  X->n = n;
+  X->k = k;
+  X->m = m;
+  X->tile = tile;
+  {
+    hipError_t e = hipGetDevice(&X->device);
+    if (e != hipSuccess) return guard(fail(SPQ_EDEVICE, hipGetErrorString(e)));
+  }
+#define TRY(expr)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return guard(fail(e_ == hipErrorOutOfMemory ? SPQ_ENOMEM : SPQ_EDEVICE,              \
+                        std::string(#expr) + ": " + hipGetErrorString(e_)));               \
+  } while (0)
+
+  for (auto& e : X->ev) TRY(hipEventCreate(&e));
+  X->events = true;
+  TRY(hipEventRecord(X->ev[0], s));
+
+  // ---- boundary detection and sizes (device), then the plan (host)
+  TRY(dalloc(&X->cnt, k));
+  TRY(dalloc(&X->nb, k));
+  TRY(dalloc(&X->flag, n));
+  TRY(dalloc(&X->sumc, k));
+  TRY(dalloc(&X->total, 1));
+  TRY(dalloc(&X->err, 1));
+  TRY(hipMemsetAsync(X->cnt, 0, sizeof(int32_t) * k, s));
+  TRY(hipMemsetAsync(X->nb, 0, sizeof(int32_t) * k, s));
+  TRY(hipMemsetAsync(X->flag, 0, n, s));
+  TRY(hipMemsetAsync(X->sumc, 0, sizeof(unsigned long long) * k, s));
+  TRY(hipMemsetAsync(X->total, 0, sizeof(unsigned long long), s));
+  TRY(hipMemsetAsync(X->err, 0, sizeof(u32), s));
+  spq::PartArgs pa{};
+  pa.n = n; pa.k = k; pa.m = m;
+  pa.eu = eu; pa.ev = ev; pa.w = w; pa.part = part;
+  pa.cnt = X->cnt; pa.nb = X->nb; pa.flag = X->flag; pa.sumc = X->sumc;
+  pa.total = X->total; pa.err = X->err;
+  TRY(spq::launch_partition_scan(pa, s));
+  u32 herr = 0;
+  unsigned long long htotal = 0;
+  X->h_cnt.resize(k);
+  X->h_nb.resize(k);
+  X->h_sumc.resize(k);
+  TRY(hipMemcpyAsync(&herr, X->err, sizeof(u32), hipMemcpyDeviceToHost, s));
+  TRY(hipMemcpyAsync(&htotal, X->total, sizeof(htotal), hipMemcpyDeviceToHost, s));
+  TRY(hipMemcpyAsync(X->h_cnt.data(), X->cnt, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
+  TRY(hipMemcpyAsync(X->h_nb.data(), X->nb, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
+  TRY(hipMemcpyAsync(X->h_sumc.data(), X->sumc, sizeof(unsigned long long) * k,
+                     hipMemcpyDeviceToHost, s));
+  TRY(hipStreamSynchronize(s));
+  if (herr & spq::ERR_PART) return guard(fail(SPQ_EINVAL, "part[v] outside [0, k)"));
+  if (herr & spq::ERR_VERTEX) return guard(fail(SPQ_EINVAL, "edge endpoint outside [0, n)"));
+  if (herr & spq::ERR_WEIGHT) return guard(fail(SPQ_EINVAL, "edge weight outside [0, SPQ_INF)"));
+  for (int32_t c = 0; c < k; c++)
+    if (X->h_cnt[c] == 0) return guard(fail(SPQ_EINVAL, "component " + std::to_string(c) + " is empty"));
+  // Every finite distance is at most the total edge weight, so below SPQ_INF
+  // all sums stay exact.
+  if (htotal >= (unsigned long long)SPQ_INF)
+    return guard(fail(SPQ_ERANGE, "total edge weight " + std::to_string(htotal) +
+                                      " reaches SPQ_INF; distances might not fit in int32"));
+
+  X->h_off.assign(k + 1, 0);
+  X->h_bgoff.assign(k + 1, 0);
+  X->h_P.resize(k);
+  X->h_moff.resize(k);
+  for (int32_t c = 0; c < k; c++) {
+    X->h_off[c + 1] = X->h_off[c] + X->h_cnt[c];
+    X->h_bgoff[c + 1] = X->h_bgoff[c] + X->h_nb[c];
+    X->h_P[c] = (int32_t)round_up(X->h_cnt[c], spq::COMP_TILE);
+    X->h_moff[c] = X->comp_elems;
+    X->comp_elems += (int64_t)X->h_P[c] * X->h_P[c];
+    X->max_comp = std::max(X->max_comp, X->h_cnt[c]);
+    X->max_nb = std::max(X->max_nb, X->h_nb[c]);
+    X->relax_comp += (double)X->h_cnt[c] * X->h_cnt[c] * X->h_cnt[c];
+  }
+  X->V = X->h_bgoff[k];
+  X->Vp = (int32_t)round_up(X->V, tile);
+  X->relax_bg = (double)X->V * X->V * X->V;
+  X->h_order.resize(k);
+  std::iota(X->h_order.begin(), X->h_order.end(), 0);
+  std::stable_sort(X->h_order.begin(), X->h_order.end(),
+                   [&](int32_t a, int32_t b) { return X->h_P[a] > X->h_P[b]; });
+
+  // ---- index memory
+  TRY(dalloc(&X->comp, n));
+  TRY(dalloc(&X->local, n));
+  TRY(dalloc(&X->off, k + 1));
+  TRY(dalloc(&X->bgoff, k + 1));
+  TRY(dalloc(&X->P, k));
+  TRY(dalloc(&X->order, k));
+  TRY(dalloc(&X->moff, k));
+  TRY(dalloc(&X->bgcomp, X->V));
+  TRY(dalloc(&X->bglocal, X->V));
+  TRY(dalloc(&X->fill, k));
+  TRY(dalloc(&X->members, n));
+  TRY(dalloc(&X->M, X->comp_elems));
+  if (X->Vp > 0) TRY(dalloc(&X->BG, (int64_t)X->Vp * X->Vp));
+  TRY(hipMemcpyAsync(X->off, X->h_off.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
+  TRY(hipMemcpyAsync(X->bgoff, X->h_bgoff.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
+  TRY(hipMemcpyAsync(X->P, X->h_P.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+  TRY(hipMemcpyAsync(X->order, X->h_order.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+  TRY(hipMemcpyAsync(X->moff, X->h_moff.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
+  TRY(hipMemsetAsync(X->fill, 0, sizeof(int32_t) * k, s));
+
+  // ---- renumbering (Section 4, Fig. 1)
+  pa.off = X->off; pa.bgoff = X->bgoff; pa.fill = X->fill; pa.members = X->members;
+  pa.comp = X->comp; pa.local = X->local; pa.bgcomp = X->bgcomp; pa.bglocal = X->bglocal;
+  TRY(spq::launch_renumber(pa, s));
+  TRY(hipEventRecord(X->ev[1], s));
+
+  // ---- Phase 2: APSP(C) for every component
+  spq::CompArgs ca{};
+  ca.k = k; ca.m = m; ca.eu = eu; ca.ev = ev; ca.w = w; ca.comp = X->comp; ca.local = X->local;
+  ca.P = X->P; ca.moff = X->moff; ca.M = X->M;
+  TRY(spq::launch_components(ca, s));
+  TRY(spq::launch_comp_fw(k, X->order, X->P, X->moff, X->M, s));
+  TRY(hipEventRecord(X->ev[2], s));
+
+  // ---- Phase 3: BG and its all-pairs distances
+  spq::BgArgs ba{};
+  ba.V = X->V; ba.Vp = X->Vp; ba.m = m; ba.eu = eu; ba.ev = ev; ba.w = w;
+  ba.comp = X->comp; ba.local = X->local; ba.bgoff = X->bgoff; ba.nb = X->nb;
+  ba.bgcomp = X->bgcomp; ba.bglocal = X->bglocal; ba.P = X->P; ba.moff = X->moff;
+  ba.M = X->M; ba.BG = X->BG;
+  TRY(spq::launch_bg_assembly(ba, s));
+  TRY(hipEventRecord(X->ev[3], s));
+  TRY(spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, s));
+  TRY(hipEventRecord(X->ev[4], s));
+#undef TRY
+  *out = X;
+  return SPQ_OK;
+}
+
+spq_status spq_query_batch(const spq_index* X, int64_t q, const int32_t* v1, const int32_t* v2,
+                           int32_t* out, void* stream) {
+  if (!X) return fail(SPQ_EINVAL, "index is NULL");
+  if (q < 0) return fail(SPQ_EINVAL, "q < 0");
+  if (q == 0) return SPQ_OK;
+  if (!v1 || !v2 || !out) return fail(SPQ_EINVAL, "null query array");
+  spq::QueryArgs a{};
+  a.q = q; a.v1 = v1; a.v2 = v2; a.out = out; a.n = X->n;
+  a.comp = X->comp; a.local = X->local; a.nb = X->nb; a.bgoff = X->bgoff; a.P = X->P;
+  a.moff = X->moff; a.M = X->M; a.BG = X->BG; a.ldbg = X->Vp;
+  HIP_TRY(spq::launch_query(a, reinterpret_cast<hipStream_t>(stream)));
+  return SPQ_OK;
+}
+
+spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
+  if (!X || !st) return fail(SPQ_EINVAL, "null argument");
+  std::memset(st, 0, sizeof(*st));
+  st->n = X->n; st->k = X->k; st->m = X->m; st->v_bg = X->V; st->v_bg_padded = X->Vp;
+  st->max_comp = X->max_comp; st->max_boundary = X->max_nb;
+  st->comp_bytes = X->comp_elems * 4;
+  st->bg_bytes = (int64_t)X->Vp * X->Vp * 4;
+  st->relax_comp = X->relax_comp;
+  st->relax_bg = X->relax_bg;
+  HIP_TRY(hipEventSynchronize(X->ev[4]));
+  HIP_TRY(hipEventElapsedTime(&st->ms_partition, X->ev[0], X->ev[1]));
+  HIP_TRY(hipEventElapsedTime(&st->ms_components, X->ev[1], X->ev[2]));
+  HIP_TRY(hipEventElapsedTime(&st->ms_bg_assembly, X->ev[2], X->ev[3]));
+  HIP_TRY(hipEventElapsedTime(&st->ms_bg_apsp, X->ev[3], X->ev[4]));
+  return SPQ_OK;
+}
+
+spq_status spq_index_layout(const spq_index* X, int32_t* comp, int32_t* local, int32_t* nb,
+                            int32_t* off, int32_t* bgoff) {
+  if (!X) return fail(SPQ_EINVAL, "index is NULL");
+  HIP_TRY(hipEventSynchronize(X->ev[4]));
+  if (comp) HIP_TRY(hipMemcpy(comp, X->comp, sizeof(int32_t) * X->n, hipMemcpyDeviceToHost));
+  if (local) HIP_TRY(hipMemcpy(local, X->local, sizeof(int32_t) * X->n, hipMemcpyDeviceToHost));
+  if (nb) std::memcpy(nb, X->h_nb.data(), sizeof(int32_t) * X->k);
+  if (off) std::memcpy(off, X->h_off.data(), sizeof(int32_t) * (X->k + 1));
+  if (bgoff) std::memcpy(bgoff, X->h_bgoff.data(), sizeof(int32_t) * (X->k + 1));
+  return SPQ_OK;
+}
+
+spq_status spq_index_component(const spq_index* X, int32_t c, int32_t* out) {
+  if (!X || !out) return fail(SPQ_EINVAL, "null argument");
+  if (c < 0 || c >= X->k) return fail(SPQ_EINVAL, "component id out of range");
+  HIP_TRY(hipEventSynchronize(X->ev[4]));
+  const int32_t N = X->h_cnt[c], P = X->h_P[c];
+  HIP_TRY(hipMemcpy2D(out, sizeof(int32_t) * N, X->M + X->h_moff[c], sizeof(int32_t) * P,
+                      sizeof(int32_t) * N, N, hipMemcpyDeviceToHost));
+  return SPQ_OK;
+}
+
+spq_status spq_index_bg_rows(const spq_index* X, int32_t row0, int32_t nrows, int32_t* out) {
+  if (!X || !out) return fail(SPQ_EINVAL, "null argument");
+  if (row0 < 0 || nrows < 0 || (int64_t)row0 + nrows > X->V)
+    return fail(SPQ_EINVAL, "BG rows out of range");
+  if (nrows == 0) return SPQ_OK;
+  HIP_TRY(hipEventSynchronize(X->ev[4]));
+  HIP_TRY(hipMemcpy2D(out, sizeof(int32_t) * X->V, X->BG + (int64_t)row0 * X->Vp,
+                      sizeof(int32_t) * X->Vp, sizeof(int32_t) * X->V, nrows,
+                      hipMemcpyDeviceToHost));
+  return SPQ_OK;
+}
+
+void spq_free_index(spq_index* X) { delete X; }
+
+spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* off,
+                             const int32_t* ld, int32_t* data, void* stream) {
+  if (count < 0 || (count > 0 && (!size || !off || !ld || !data)))
+    return fail(SPQ_EINVAL, "bad arguments");
+  if (count == 0) return SPQ_OK;
+  for (int32_t i = 0; i < count; i++)
+    if (size[i] < 1 || ld[i] < size[i] || ld[i] % spq::COMP_TILE || off[i] < 0 || off[i] % 4)
+      return fail(SPQ_EINVAL, "matrix " + std::to_string(i) + ": bad size, ld or offset");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<int32_t> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  int32_t *d_order = nullptr, *d_P = nullptr;
+  int64_t* d_off = nullptr;
+  HIP_TRY(dalloc(&d_order, count));
+  HIP_TRY(dalloc(&d_P, count));
+  HIP_TRY(dalloc(&d_off, count));
+  HIP_TRY(hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_P, ld, sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_off, off, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
+  HIP_TRY(spq::launch_comp_fw(count, d_order, d_P, d_off, reinterpret_cast<u32*>(data), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  (void)hipFree(d_order);
+  (void)hipFree(d_P);
+  (void)hipFree(d_off);
+  return SPQ_OK;
+}
+
+spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t* data, void* stream) {
+  if (tile != 64 && tile != 128) return fail(SPQ_EINVAL, "tile must be 64 or 128");
+  if (v < 0 || ld < v || ld % tile || (v > 0 && !data)) return fail(SPQ_EINVAL, "bad v or ld");
+  if (v == 0) return SPQ_OK;
+  HIP_TRY(spq::launch_dense_fw(reinterpret_cast<u32*>(data), ld, tile, ld / tile,
+                               reinterpret_cast<hipStream_t>(stream)));
+  return SPQ_OK;
+}
+
+}  // extern "C"

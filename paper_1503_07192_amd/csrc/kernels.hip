@@ -1,0 +1,501 @@
+// HIP kernels of the shortest-path query structure (gfx950).
+//
+// Steps, in the order the build runs them:
+//   partition  k_count_part, k_edges_scan, k_count_boundary, k_members, k_rank
+//              (boundary detection and the Fig. 1 renumbering, Sections 2, 4)
+//   APSP(C)    k_comp_init, k_comp_edges, k_comp_fw (Algorithm 1, Phase 2)
+//   BG         k_bg_init, k_bg_edges (Algorithm 1, Phase 2 clique edges and
+//              Phase 3 boundary graph), k_fw_diag / k_fw_panel / k_fw_inner
+//              (all-pairs distances in BG)
+//   query      k_query (Algorithm 2)
+#include "spq_internal.h"
+#include "tiles.h"
+
+namespace spq {
+
+// ------------------------------------------------------------ partition ---
+__global__ void k_count_part(int32_t n, const int32_t* __restrict__ part, int32_t k,
+                             int32_t* __restrict__ cnt, u32* __restrict__ err) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int32_t p = part[v];
+  if (p < 0 || p >= k) {
+    atomicOr(err, ERR_PART);
+    return;
+  }
+  atomicAdd(&cnt[p], 1);
+}
+
+// Validates the edges, marks the boundary (Section 2: a vertex with a
+// neighbour in another component) and sums the weights: per component for
+// edges inside it, and in total.
+__global__ void k_edges_scan(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                             const int32_t* __restrict__ w, int32_t n, const int32_t* __restrict__ part,
+                             int32_t k, uint8_t* __restrict__ flag, unsigned long long* __restrict__ sumc,
+                             unsigned long long* __restrict__ total, u32* __restrict__ err) {
+  unsigned long long acc = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = eu[e], v = ev[e], x = w[e];
+    if (u < 0 || u >= n || v < 0 || v >= n) {
+      atomicOr(err, ERR_VERTEX);
+      continue;
+    }
+    if (x < 0 || (u32)x >= INF) {
+      atomicOr(err, ERR_WEIGHT);
+      continue;
+    }
+    int32_t pu = part[u], pv = part[v];
+    if (pu < 0 || pu >= k || pv < 0 || pv >= k) continue;  // reported by k_count_part
+    if (pu != pv) {
+      flag[u] = 1;
+      flag[v] = 1;
+    } else if (u != v) {
+      atomicAdd(&sumc[pu], (unsigned long long)x);
+    }
+    acc += (unsigned long long)x;
+  }
+  // wave reduction, then one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(total, acc);
+}
+
+__global__ void k_count_boundary(int32_t n, const int32_t* __restrict__ part,
+                                 const uint8_t* __restrict__ flag, int32_t* __restrict__ nb) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (flag[v]) atomicAdd(&nb[part[v]], 1);
+}
+
+// Groups the vertices by component (arbitrary order inside a component); the
+// boundary flag rides in bit 31.
+__global__ void k_members(int32_t n, const int32_t* __restrict__ part, const uint8_t* __restrict__ flag,
+                          const int32_t* __restrict__ off, int32_t* __restrict__ fill,
+                          u32* __restrict__ members) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int32_t c = part[v];
+  int32_t slot = atomicAdd(&fill[c], 1);
+  members[off[c] + slot] = (u32)v | ((u32)flag[v] << 31);
+}
+
+// Renumbering (Section 4, Fig. 1): inside each component the boundary vertices
+// come first, each group in ascending vertex id.  The rank of a vertex is the
+// number of members of its component with the same flag and a smaller id.
+__global__ void k_rank(int32_t n, int32_t k, const u32* __restrict__ members,
+                       const int32_t* __restrict__ off, const int32_t* __restrict__ nb,
+                       const int32_t* __restrict__ bgoff, int32_t* __restrict__ comp,
+                       int32_t* __restrict__ local, int32_t* __restrict__ bgcomp,
+                       int32_t* __restrict__ bglocal) {
+  int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= n) return;
+  // component of this position: largest c with off[c] <= pos
+  int32_t lo = 0, hi = k - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= pos) lo = mid; else hi = mid - 1;
+  }
+  const int32_t c = lo;
+  const u32 me = members[pos];
+  const u32 id = me & 0x7fffffffu, f = me >> 31;
+  int32_t rank = 0;
+  for (int32_t x = off[c]; x < off[c + 1]; x++) {
+    u32 o = members[x];
+    rank += ((o >> 31) == f) & ((o & 0x7fffffffu) < id);
+  }
+  int32_t l = f ? rank : nb[c] + rank;
+  comp[id] = c;
+  local[id] = l;
+  if (f) {
+    bgcomp[bgoff[c] + l] = c;
+    bglocal[bgoff[c] + l] = l;
+  }
+}
+
+// --------------------------------------------------------------- APSP(C) --
+// Component matrices are P x P (P = |C| rounded up to 64), row-major at
+// element moff[c].  Initial value (Section 4): 0 on the diagonal, INF
+// elsewhere; edges are scattered next.  Padding rows/columns stay isolated.
+__global__ void k_comp_init(const int32_t* __restrict__ P, const int64_t* __restrict__ moff,
+                            u32* __restrict__ M) {
+  const int32_t c = blockIdx.x;
+  const int32_t p = P[c];
+  u32* base = M + moff[c];
+  const int64_t quads = (int64_t)p * p / 4;
+  for (int64_t q = threadIdx.x; q < quads; q += blockDim.x) {
+    int64_t e = q * 4;
+    int32_t i = (int32_t)(e / p), j = (int32_t)(e % p);
+    uint4 v = make_uint4(INF, INF, INF, INF);
+    if (i >= j && i < j + 4) {
+      if (i == j) v.x = 0;
+      if (i == j + 1) v.y = 0;
+      if (i == j + 2) v.z = 0;
+      if (i == j + 3) v.w = 0;
+    }
+    reinterpret_cast<uint4*>(base)[q] = v;
+  }
+}
+
+// Edges inside a component become matrix entries; parallel edges keep the
+// lightest one, self-loops are dropped.
+__global__ void k_comp_edges(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                             const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
+                             const int32_t* __restrict__ local, const int32_t* __restrict__ P,
+                             const int64_t* __restrict__ moff, u32* __restrict__ M) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = eu[e], v = ev[e];
+    if (u == v) continue;
+    int32_t c = comp[u];
+    if (c != comp[v]) continue;
+    int64_t p = P[c];
+    u32* base = M + moff[c];
+    int32_t lu = local[u], lv = local[v];
+    atomicMin(base + lu * p + lv, (u32)w[e]);
+    atomicMin(base + lv * p + lu, (u32)w[e]);
+  }
+}
+
+// Phase 2: one workgroup closes one whole component matrix by blocked
+// Floyd-Warshall with 64 x 64 tiles (diagonal tile, then its row - written
+// twice, once transposed as the column - then all other tiles).  The matrix
+// stays in global memory between the tile steps; it is a few hundred KB at
+// most and stays in L2.  order[] lists components largest first.
+__global__ __launch_bounds__(256) void k_comp_fw(const int32_t* __restrict__ order,
+                                                 const int32_t* __restrict__ P,
+                                                 const int64_t* __restrict__ moff, u32* M) {
+  constexpr int T = 64;
+  __shared__ __attribute__((aligned(16))) u32 sA[T * T];
+  __shared__ __attribute__((aligned(16))) u32 sB[T * T];
+  __shared__ __attribute__((aligned(16))) u32 rb[4 * T];
+  const int32_t c = order[blockIdx.x];
+  const int64_t p = P[c];
+  const int nt = (int)(p / T);
+  u32* base = M + moff[c];
+  u32 t[T / 16][T / 16];
+  for (int r = 0; r < nt; r++) {
+    u32* D = base + (int64_t)r * T * p + r * T;
+    tile_load<T>(t, D, p);
+    fw_tile<T>(t, rb);
+    tile_store<T>(t, D, p);
+    if (nt == 1) break;
+    tile_to_lds<T>(t, sA);
+    __syncthreads();
+    // row r and (by symmetry) column r of tiles
+    for (int j = 0; j < nt; j++) {
+      if (j == r) continue;
+      u32* Rj = base + (int64_t)r * T * p + j * T;
+      tile_load<T>(t, Rj, p);
+      tile_to_lds<T>(t, sB);
+      __syncthreads();
+      minplus_lds<T>(t, sA, sB, T);
+      tile_store<T>(t, Rj, p);
+      tile_store_t<T>(t, base + (int64_t)j * T * p + r * T, p);
+      __syncthreads();
+    }
+    __threadfence_block();
+    __syncthreads();
+    // the remaining tiles: T(i,j) = min(T(i,j), T(i,r) (x) T(r,j)), with
+    // T(i,r)^T = T(r,i) already laid out as the transposed left operand
+    for (int i = 0; i < nt; i++) {
+      if (i == r) continue;
+      tile_load<T>(t, base + (int64_t)r * T * p + i * T, p);
+      tile_to_lds<T>(t, sA);
+      for (int j = 0; j < nt; j++) {
+        if (j == r) continue;
+        tile_load<T>(t, base + (int64_t)r * T * p + j * T, p);
+        tile_to_lds<T>(t, sB);
+        u32* Cij = base + (int64_t)i * T * p + j * T;
+        tile_load<T>(t, Cij, p);
+        __syncthreads();
+        minplus_lds<T>(t, sA, sB, T);
+        tile_store<T>(t, Cij, p);
+        __syncthreads();
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// -------------------------------------------------------------------- BG --
+// BG matrix, Vp x Vp (Vp = V rounded up to the tile): within one component
+// the APSP(C) distance between its boundary vertices (the clique edges of
+// Algorithm 1; they are never heavier than a G edge between the same pair),
+// 0 on the diagonal, INF elsewhere and on the padding.
+__global__ void k_bg_init(int32_t V, int64_t Vp, const int32_t* __restrict__ bgcomp,
+                          const int32_t* __restrict__ bglocal, const int32_t* __restrict__ nb,
+                          const int32_t* __restrict__ bgoff, const int32_t* __restrict__ P,
+                          const int64_t* __restrict__ moff, const u32* __restrict__ M,
+                          u32* __restrict__ BG) {
+  const int64_t row = blockIdx.x;
+  u32* out = BG + row * Vp;
+  // BG ids are grouped by component, so the row's own component is the
+  // column range [lo, hi)
+  int64_t lo = 0, hi = 0;
+  const u32* mrow = nullptr;
+  if (row < V) {
+    const int32_t cr = bgcomp[row];
+    lo = bgoff[cr];
+    hi = lo + nb[cr];
+    mrow = M + moff[cr] + (int64_t)bglocal[row] * P[cr] - lo;
+  }
+  for (int64_t q0 = (int64_t)threadIdx.x * 4; q0 < Vp; q0 += (int64_t)blockDim.x * 4) {
+    u32 v[4];
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      const int64_t q = q0 + s;
+      v[s] = (q == row) ? 0u : (q >= lo && q < hi) ? mrow[q] : INF;
+    }
+    *reinterpret_cast<uint4*>(out + q0) = make_uint4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// Edges of G between boundary vertices of different components.
+__global__ void k_bg_edges(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                           const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
+                           const int32_t* __restrict__ local, const int32_t* __restrict__ bgoff,
+                           int64_t Vp, u32* __restrict__ BG) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = eu[e], v = ev[e];
+    int32_t cu = comp[u], cv = comp[v];
+    if (cu == cv) continue;
+    int64_t a = bgoff[cu] + local[u], b = bgoff[cv] + local[v];
+    atomicMin(BG + a * Vp + b, (u32)w[e]);
+    atomicMin(BG + b * Vp + a, (u32)w[e]);
+  }
+}
+
+// Blocked Floyd-Warshall on one symmetric matrix, round r of nt:
+//   k_fw_diag   closes the diagonal tile (r, r)
+//   k_fw_panel  tile (r, j) = D (x) tile (r, j) for j != r, stored twice
+//               (as (r, j) and transposed as (j, r))
+//   k_fw_inner  tile (i, j) = min(tile (i, j), tile (r, i)^T (x) tile (r, j))
+template <int T>
+__global__ __launch_bounds__(256) void k_fw_diag(u32* __restrict__ A, int64_t ld, int r) {
+  __shared__ __attribute__((aligned(16))) u32 rb[4 * T];
+  u32 t[T / 16][T / 16];
+  u32* D = A + (int64_t)r * T * ld + (int64_t)r * T;
+  tile_load<T>(t, D, ld);
+  fw_tile<T>(t, rb);
+  tile_store<T>(t, D, ld);
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_fw_panel(u32* __restrict__ A, int64_t ld, int r) {
+  __shared__ __attribute__((aligned(16))) u32 sD[T * T];
+  __shared__ __attribute__((aligned(16))) u32 sB[T * T];
+  const int j = (int)blockIdx.x + ((int)blockIdx.x >= r);
+  u32 t[T / 16][T / 16];
+  tile_load<T>(t, A + (int64_t)r * T * ld + (int64_t)r * T, ld);
+  tile_to_lds<T>(t, sD);
+  u32* Rj = A + (int64_t)r * T * ld + (int64_t)j * T;
+  tile_load<T>(t, Rj, ld);
+  tile_to_lds<T>(t, sB);
+  __syncthreads();
+  minplus_lds<T>(t, sD, sB, T);
+  tile_store<T>(t, Rj, ld);
+  tile_store_t<T>(t, A + (int64_t)j * T * ld + (int64_t)r * T, ld);
+}
+
+// Interior tiles.  The k dimension is streamed through LDS in chunks of KC
+// rows of the two operand tiles (double buffered, next chunk prefetched into
+// registers while the current one is consumed).
+template <int T, int KC>
+__global__ __launch_bounds__(256) void k_fw_inner(u32* __restrict__ A, int64_t ld, int r, int nt) {
+  constexpr int Q = KC * T / 4 / 256;  // uint4 per thread per operand chunk
+  static_assert(Q >= 1 && KC * T / 4 % 256 == 0, "chunk must split evenly");
+  __shared__ __attribute__((aligned(16))) u32 sA[2][KC * T];
+  __shared__ __attribute__((aligned(16))) u32 sB[2][KC * T];
+  const int m1 = nt - 1;
+  const int bi = (int)(blockIdx.x / m1), bj = (int)(blockIdx.x % m1);
+  const int i = bi + (bi >= r), j = bj + (bj >= r);
+  const u32* Ar = A + (int64_t)r * T * ld + (int64_t)i * T;  // tile (r, i)
+  const u32* Br = A + (int64_t)r * T * ld + (int64_t)j * T;  // tile (r, j)
+  u32* Cij = A + (int64_t)i * T * ld + (int64_t)j * T;
+  u32 t[T / 16][T / 16];
+  tile_load<T>(t, Cij, ld);
+  uint4 pa[Q], pb[Q];
+  // chunk 0 straight to LDS buffer 0
+#pragma unroll
+  for (int s = 0; s < Q; s++) {
+    const int e = threadIdx.x + s * 256;
+    const int row = e / (T / 4), c4 = e % (T / 4);
+    pa[s] = *reinterpret_cast<const uint4*>(Ar + (int64_t)row * ld + c4 * 4);
+    pb[s] = *reinterpret_cast<const uint4*>(Br + (int64_t)row * ld + c4 * 4);
+  }
+#pragma unroll
+  for (int s = 0; s < Q; s++) {
+    const int e = threadIdx.x + s * 256;
+    reinterpret_cast<uint4*>(sA[0])[e] = pa[s];
+    reinterpret_cast<uint4*>(sB[0])[e] = pb[s];
+  }
+  __syncthreads();
+  constexpr int NCH = T / KC;
+#pragma unroll
+  for (int ch = 0; ch < NCH; ch++) {
+    const bool more = ch + 1 < NCH;
+    if (more) {
+      const int kc = (ch + 1) * KC;
+#pragma unroll
+      for (int s = 0; s < Q; s++) {
+        const int e = threadIdx.x + s * 256;
+        const int row = e / (T / 4), c4 = e % (T / 4);
+        pa[s] = *reinterpret_cast<const uint4*>(Ar + (int64_t)(kc + row) * ld + c4 * 4);
+        pb[s] = *reinterpret_cast<const uint4*>(Br + (int64_t)(kc + row) * ld + c4 * 4);
+      }
+    }
+    minplus_lds<T>(t, sA[ch & 1], sB[ch & 1], KC);
+    if (more) {
+#pragma unroll
+      for (int s = 0; s < Q; s++) {
+        const int e = threadIdx.x + s * 256;
+        reinterpret_cast<uint4*>(sA[(ch + 1) & 1])[e] = pa[s];
+        reinterpret_cast<uint4*>(sB[(ch + 1) & 1])[e] = pb[s];
+      }
+    }
+    __syncthreads();
+  }
+  tile_store<T>(t, Cij, ld);
+}
+
+// ----------------------------------------------------------------- query --
+// Algorithm 2, one wavefront per query.  Lane j takes b2 = j (+64, ...):
+//   t(b2) = min over b1 of dist_C1(v1, b1) + dist_BG(b1, b2)     (lines 2-7)
+//   r     = min over b2 of t(b2) + dist_C2(b2, v2)                (lines 9-12)
+//   r     = min(r, dist_C1(v1, v2)) if C1 = C2                    (line 13)
+// dist_C1(v1, .) is the prefix of v1's row of APSP(C1) (boundary first), held
+// one value per lane and broadcast with readlane; dist_C2(b2, v2) is read from
+// v2's row (the matrix is symmetric), and the BG block rows are contiguous.
+__global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restrict__ v1,
+                                               const int32_t* __restrict__ v2, int32_t* __restrict__ out,
+                                               int32_t n, const int32_t* __restrict__ comp,
+                                               const int32_t* __restrict__ local,
+                                               const int32_t* __restrict__ nb,
+                                               const int32_t* __restrict__ bgoff,
+                                               const int32_t* __restrict__ P,
+                                               const int64_t* __restrict__ moff,
+                                               const u32* __restrict__ M, const u32* __restrict__ BG,
+                                               int64_t ldbg) {
+  const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (qi >= q) return;
+  const int32_t a = v1[qi], b = v2[qi];
+  if (a < 0 || a >= n || b < 0 || b >= n) {
+    if (lane == 0) out[qi] = -1;
+    return;
+  }
+  const int32_t c1 = comp[a], c2 = comp[b];
+  const int32_t l1 = local[a], l2 = local[b];
+  const int32_t nb1 = nb[c1], nb2 = nb[c2];
+  const u32* row1 = M + moff[c1] + (int64_t)l1 * P[c1];
+  const u32* row2 = M + moff[c2] + (int64_t)l2 * P[c2];
+  const u32* blk = BG + (int64_t)bgoff[c1] * ldbg + bgoff[c2];
+  u32 best = INF;
+  for (int32_t b2base = 0; b2base < nb2; b2base += 64) {
+    const int32_t b2 = b2base + lane;
+    const bool act = b2 < nb2;
+    const u32* col = blk + (act ? b2 : 0);
+    u32 t = INF;
+    for (int32_t b1base = 0; b1base < nb1; b1base += 64) {
+      const int32_t cnt = min(64, nb1 - b1base);
+      const u32 mine = (lane < cnt) ? row1[b1base + lane] : INF;
+      const u32* cp = col + (int64_t)b1base * ldbg;
+      for (int32_t x = 0; x < cnt; x++) {
+        const u32 d1 = (u32)__builtin_amdgcn_readlane((int)mine, x);
+        const u32 g = act ? cp[(int64_t)x * ldbg] : INF;
+        t = min(t, d1 + g);
+      }
+    }
+    if (act) best = min(best, min(t, INF) + row2[b2]);
+  }
+  for (int o = 32; o > 0; o >>= 1) best = min(best, (u32)__shfl_xor((int)best, o));
+  if (lane == 0) {
+    if (c1 == c2) best = min(best, row1[l2]);
+    out[qi] = (int32_t)min(best, INF);
+  }
+}
+
+// ---------------------------------------------------------------- launch --
+#define LAUNCH_CHECK() return hipGetLastError()
+
+static inline unsigned blocks_for(int64_t items, int per = 256) {
+  int64_t b = (items + per - 1) / per;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_partition_scan(const PartArgs& a, hipStream_t s) {
+  if (a.n > 0) k_count_part<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.part, a.k, a.cnt, a.err);
+  if (a.m > 0) {
+    unsigned g = blocks_for(a.m);
+    if (g > 4096) g = 4096;
+    k_edges_scan<<<g, 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.n, a.part, a.k, a.flag, a.sumc, a.total,
+                                   a.err);
+  }
+  if (a.n > 0) k_count_boundary<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.part, a.flag, a.nb);
+  LAUNCH_CHECK();
+}
+
+hipError_t launch_renumber(const PartArgs& a, hipStream_t s) {
+  k_members<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.part, a.flag, a.off, a.fill, a.members);
+  k_rank<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.k, a.members, a.off, a.nb, a.bgoff, a.comp, a.local,
+                                         a.bgcomp, a.bglocal);
+  LAUNCH_CHECK();
+}
+
+hipError_t launch_components(const CompArgs& a, hipStream_t s) {
+  k_comp_init<<<a.k, 256, 0, s>>>(a.P, a.moff, a.M);
+  if (a.m > 0) {
+    unsigned g = blocks_for(a.m);
+    if (g > 8192) g = 8192;
+    k_comp_edges<<<g, 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.P, a.moff, a.M);
+  }
+  LAUNCH_CHECK();
+}
+
+hipError_t launch_comp_fw(int32_t count, const int32_t* order, const int32_t* P, const int64_t* moff,
+                          u32* M, hipStream_t s) {
+  if (count > 0) k_comp_fw<<<count, 256, 0, s>>>(order, P, moff, M);
+  LAUNCH_CHECK();
+}
+
+hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s) {
+  if (a.Vp == 0) return hipSuccess;
+  k_bg_init<<<(unsigned)a.Vp, 256, 0, s>>>(a.V, a.Vp, a.bgcomp, a.bglocal, a.nb, a.bgoff, a.P,
+                                          a.moff, a.M, a.BG);
+  if (a.m > 0) {
+    unsigned g = blocks_for(a.m);
+    if (g > 8192) g = 8192;
+    k_bg_edges<<<g, 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.Vp, a.BG);
+  }
+  LAUNCH_CHECK();
+}
+
+template <int T>
+static hipError_t fw_rounds(u32* A, int64_t ld, int nt, hipStream_t s) {
+  for (int r = 0; r < nt; r++) {
+    k_fw_diag<T><<<1, 256, 0, s>>>(A, ld, r);
+    if (nt > 1) {
+      k_fw_panel<T><<<nt - 1, 256, 0, s>>>(A, ld, r);
+      k_fw_inner<T, 32><<<(unsigned)((nt - 1) * (nt - 1)), 256, 0, s>>>(A, ld, r, nt);
+    }
+  }
+  LAUNCH_CHECK();
+}
+
+hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
+  if (tile == 64) return fw_rounds<64>(A, ld, nt, s);
+  return fw_rounds<128>(A, ld, nt, s);
+}
+
+hipError_t launch_query(const QueryArgs& a, hipStream_t s) {
+  if (a.q <= 0) return hipSuccess;
+  int64_t blocks = (a.q + 3) / 4;
+  k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.comp, a.local, a.nb,
+                                           a.bgoff, a.P, a.moff, a.M, a.BG, a.ldbg);
+  LAUNCH_CHECK();
+}
+
+}  // namespace spq

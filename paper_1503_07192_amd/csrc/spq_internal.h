@@ -1,0 +1,71 @@
+// Internal declarations shared by the kernels and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spq {
+
+typedef uint32_t u32;
+
+enum : u32 { ERR_PART = 1u, ERR_VERTEX = 2u, ERR_WEIGHT = 4u };
+
+// Component tables are padded to a multiple of this side.
+constexpr int COMP_TILE = 64;
+
+struct PartArgs {
+  int32_t n, k;
+  int64_t m;
+  const int32_t *eu, *ev, *w, *part;
+  int32_t* cnt;               // [k] vertices per component
+  int32_t* nb;                // [k] boundary vertices per component
+  uint8_t* flag;              // [n] boundary flag
+  unsigned long long* sumc;   // [k] weight of the edges inside each component
+  unsigned long long* total;  // [1] weight of all edges
+  u32* err;                   // [1] ERR_* bits
+  const int32_t* off;         // [k+1] first vertex of each component
+  const int32_t* bgoff;       // [k+1] first BG id of each component
+  int32_t* fill;              // [k] scratch counters (zeroed)
+  u32* members;               // [n] scratch
+  int32_t *comp, *local;      // [n]
+  int32_t *bgcomp, *bglocal;  // [V]
+};
+
+struct CompArgs {
+  int32_t k;
+  int64_t m;
+  const int32_t *eu, *ev, *w, *comp, *local, *P;
+  const int64_t* moff;
+  u32* M;
+};
+
+struct BgArgs {
+  int32_t V;
+  int64_t Vp, m;
+  const int32_t *eu, *ev, *w, *comp, *local, *bgoff, *nb, *bgcomp, *bglocal, *P;
+  const int64_t* moff;
+  const u32* M;
+  u32* BG;
+};
+
+struct QueryArgs {
+  int64_t q;
+  const int32_t *v1, *v2;
+  int32_t* out;
+  int32_t n;
+  const int32_t *comp, *local, *nb, *bgoff, *P;
+  const int64_t* moff;
+  const u32 *M, *BG;
+  int64_t ldbg;
+};
+
+hipError_t launch_partition_scan(const PartArgs& a, hipStream_t s);
+hipError_t launch_renumber(const PartArgs& a, hipStream_t s);
+hipError_t launch_components(const CompArgs& a, hipStream_t s);
+hipError_t launch_comp_fw(int32_t count, const int32_t* order, const int32_t* P, const int64_t* moff,
+                          u32* M, hipStream_t s);
+hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s);
+hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s);
+hipError_t launch_query(const QueryArgs& a, hipStream_t s);
+
+}  // namespace spq

@@ -1,0 +1,210 @@
+"""Python binding of the C-ABI in include/spq.h (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libspq.so``; this module only
+checks and converts arguments.  There is no fallback: if the library is not
+built, ``load()`` raises.
+
+Device arrays are torch tensors on the current HIP device (int32,
+contiguous); streams default to torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libspq.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "spq.h")
+
+SPQ_INF = 2147483647
+SPQ_BAD_PAIR = -1
+STATUS = {0: "SPQ_OK", 1: "SPQ_EINVAL", 2: "SPQ_ENOMEM", 3: "SPQ_EDEVICE", 4: "SPQ_ERANGE"}
+
+
+class SpqError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("bg_tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("k", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("v_bg", ctypes.c_int32), ("v_bg_padded", ctypes.c_int32),
+                ("max_comp", ctypes.c_int32), ("max_boundary", ctypes.c_int32),
+                ("comp_bytes", ctypes.c_int64), ("bg_bytes", ctypes.c_int64),
+                ("relax_comp", ctypes.c_double), ("relax_bg", ctypes.c_double),
+                ("ms_partition", ctypes.c_float), ("ms_components", ctypes.c_float),
+                ("ms_bg_assembly", ctypes.c_float), ("ms_bg_apsp", ctypes.c_float)]
+
+
+_lib = None
+P = ctypes.c_void_p
+I32, I64 = ctypes.c_int32, ctypes.c_int64
+_SIGS = {
+    "spq_build_index": (I32, [I32, I64, P, P, P, P, I32, ctypes.POINTER(BuildOpts), P,
+                              ctypes.POINTER(P)]),
+    "spq_query_batch": (I32, [P, I64, P, P, P, P]),
+    "spq_index_stats": (I32, [P, ctypes.POINTER(Stats)]),
+    "spq_index_layout": (I32, [P, P, P, P, P, P]),
+    "spq_index_component": (I32, [P, I32, P]),
+    "spq_index_bg_rows": (I32, [P, I32, I32, P]),
+    "spq_free_index": (None, [P]),
+    "spq_last_error": (ctypes.c_char_p, []),
+    "spq_fw_components": (I32, [I32, P, P, P, P, P]),
+    "spq_fw_dense": (I32, [I32, I32, I32, P, P]),
+}
+
+
+def header_functions():
+    """Names of the functions declared in include/spq.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spq_\w+)\s*\(", text)))
+
+
+def load():
+    """The built library; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libspq.so is not built: run `python -m paper_1503_07192_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return load().spq_last_error().decode()
+
+
+def _check(st):
+    if st != 0:
+        raise SpqError(st, last_error())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_i32(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a torch tensor on the HIP device" % name)
+    if t.dtype != torch.int32 or not t.is_contiguous():
+        raise TypeError("%s must be contiguous int32" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Index:
+    """Owns an spq_index (freed with the object)."""
+
+    def __init__(self, handle, n, k):
+        self._h = handle
+        self.n, self.k = n, k
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("index already freed")
+        return self._h
+
+    def free(self):
+        if self._h:
+            load().spq_free_index(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_index(n, eu, ev, w, part, k, bg_tile=0, stream=None) -> Index:
+    """Algorithm 1 on device tensors; see spq_build_index."""
+    L = load()
+    opts = BuildOpts(bg_tile=bg_tile)
+    h = ctypes.c_void_p()
+    m = int(eu.numel())
+    st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),
+                           _dev_i32(part, "part"), int(k), ctypes.byref(opts), _stream(stream),
+                           ctypes.byref(h))
+    _check(st)
+    return Index(h, int(n), int(k))
+
+
+def query_batch(index: Index, v1, v2, out=None, stream=None):
+    """Algorithm 2 for every pair; returns the int32 device tensor `out`."""
+    import torch
+    q = int(v1.numel())
+    if int(v2.numel()) != q:
+        raise ValueError("v1 and v2 differ in length")
+    if out is None:
+        out = torch.empty(q, dtype=torch.int32, device=v1.device)
+    elif int(out.numel()) != q:
+        raise ValueError("out has the wrong length")
+    _check(load().spq_query_batch(index.handle, q, _dev_i32(v1, "v1"), _dev_i32(v2, "v2"),
+                                  _dev_i32(out, "out"), _stream(stream)))
+    return out
+
+
+def index_stats(index: Index) -> dict:
+    s = Stats()
+    _check(load().spq_index_stats(index.handle, ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+
+def index_layout(index: Index) -> dict:
+    n, k = index.n, index.k
+    comp = np.empty(n, np.int32)
+    local = np.empty(n, np.int32)
+    nb = np.empty(k, np.int32)
+    off = np.empty(k + 1, np.int32)
+    bgoff = np.empty(k + 1, np.int32)
+    _check(load().spq_index_layout(index.handle, comp.ctypes.data, local.ctypes.data,
+                                   nb.ctypes.data, off.ctypes.data, bgoff.ctypes.data))
+    return dict(comp=comp, local=local, nb=nb, off=off, bgoff=bgoff)
+
+
+def index_component(index: Index, c: int, size: int):
+    out = np.empty((size, size), np.int32)
+    _check(load().spq_index_component(index.handle, int(c), out.ctypes.data))
+    return out
+
+
+def index_bg_rows(index: Index, row0: int, nrows: int, v_bg: int):
+    out = np.empty((nrows, v_bg), np.int32)
+    _check(load().spq_index_bg_rows(index.handle, int(row0), int(nrows), out.ctypes.data))
+    return out
+
+
+def fw_components(size, off, ld, data, stream=None):
+    size = np.ascontiguousarray(size, np.int32)
+    off = np.ascontiguousarray(off, np.int64)
+    ld = np.ascontiguousarray(ld, np.int32)
+    _check(load().spq_fw_components(len(size), size.ctypes.data, off.ctypes.data, ld.ctypes.data,
+                                    _dev_i32(data, "data"), _stream(stream)))
+    return data
+
+
+def fw_dense(v, ld, tile, data, stream=None):
+    _check(load().spq_fw_dense(int(v), int(ld), int(tile), _dev_i32(data, "data"),
+                               _stream(stream)))
+    return data

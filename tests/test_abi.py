@@ -1,0 +1,45 @@
+"""The C-ABI library on the CPU: it loads, exports what include/spq.h declares,
+and rejects bad arguments before touching a device."""
+import ctypes
+
+import pytest
+
+from paper_1503_07192_amd import spq
+
+
+def test_library_exports_every_header_symbol():
+    L = spq.load()
+    names = spq.header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(spq._SIGS)
+
+
+def test_argument_errors_without_device():
+    L = spq.load()
+    h = ctypes.c_void_p()
+    assert L.spq_build_index(0, 0, None, None, None, None, 1, None, None, ctypes.byref(h)) == 1
+    assert "n >= 1" in spq.last_error()
+    assert L.spq_build_index(5, 0, None, None, None, None, 6, None, None, ctypes.byref(h)) == 1
+    assert "empty" in spq.last_error()
+    assert L.spq_build_index(5, 3, None, None, None, None, 2, None, None, ctypes.byref(h)) == 1
+    opts = spq.BuildOpts(bg_tile=96)
+    assert L.spq_build_index(5, 0, None, None, None, ctypes.c_void_p(8), 2, ctypes.byref(opts),
+                             None, ctypes.byref(h)) == 1
+    assert "bg_tile" in spq.last_error()
+    assert L.spq_build_index(5, 0, None, None, None, None, 2, None, None, None) == 1
+    assert L.spq_query_batch(None, 3, None, None, None, None) == 1
+    assert L.spq_fw_dense(10, 10, 3, None, None) == 1
+    assert L.spq_fw_dense(10, 8, 64, None, None) == 1
+    assert L.spq_fw_dense(0, 0, 64, None, None) == 0
+    assert L.spq_fw_components(-1, None, None, None, None, None) == 1
+    assert L.spq_index_stats(None, None) == 1
+    L.spq_free_index(None)
+
+
+def test_python_binding_rejects_host_tensors():
+    torch = pytest.importorskip("torch")
+    x = torch.zeros(4, dtype=torch.int32)
+    with pytest.raises(TypeError):
+        spq.build_index(4, x, x, x, x, 1)

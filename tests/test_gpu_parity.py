@@ -1,0 +1,331 @@
+"""Parity of the HIP path with the CPU oracle, element by element (tolerance 0).
+
+Every kernel output is compared with what the oracle computes from the same
+seeded inputs: APSP(C) with Floyd-Warshall on the induced component, BG rows
+with Dijkstra on G (Lemma 1 makes them equal), query answers with Dijkstra on
+G (Lemma 3).  The Floyd-Warshall kernels are also driven directly on
+adversarial matrices.  A value the kernels report is min(exact distance,
+2^31-1): stored sums never wrap, so an exact distance at or above the
+sentinel shows as the sentinel.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import O_INF
+from paper_1503_07192_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+spq = pytest.importorskip("paper_1503_07192_amd.spq")
+
+pytestmark = pytest.mark.gpu
+INF32 = 2**31 - 1
+
+
+def clamp32(d):
+    d = np.asarray(d, np.int64)
+    return np.where(d >= INF32, INF32, d).astype(np.int32)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+
+
+def build(g, **kw):
+    print("build %s n=%d m=%d k=%d" % (g.get("name", "?"), g["n"], len(g["eu"]), g["k"]), flush=True)
+    idx = spq.build_index(g["n"], dev(g["eu"]), dev(g["ev"]), dev(g["w"]), dev(g["part"]), g["k"], **kw)
+    torch.cuda.synchronize()
+    return idx
+
+
+def local_order(lay, c):
+    """Vertices of component c in the index's local order."""
+    vs = np.flatnonzero(lay["comp"] == c)
+    return vs[np.argsort(lay["local"][vs], kind="stable")]
+
+
+def check_layout(g, lay):
+    n, k = g["n"], g["k"]
+    assert np.array_equal(lay["comp"], g["part"])
+    flag = oracle.boundary(n, g["eu"], g["ev"], g["part"])
+    for c in range(k):
+        vs = local_order(lay, c)
+        assert np.array_equal(np.sort(lay["local"][vs]), np.arange(len(vs)))
+        b = vs[: lay["nb"][c]]
+        i = vs[lay["nb"][c]:]
+        assert flag[b].all() and not flag[i].any()
+        assert (np.diff(b) > 0).all() and (np.diff(i) > 0).all()
+        assert lay["off"][c + 1] - lay["off"][c] == len(vs)
+        assert lay["bgoff"][c + 1] - lay["bgoff"][c] == lay["nb"][c]
+
+
+def check_components(g, idx, lay, comps=None):
+    comps = list(range(g["k"])) if comps is None else list(comps)
+    members, apsp = oracle.component_apsp(g["n"], g["eu"], g["ev"], g["w"], g["part"], g["k"],
+                                          comps=comps)
+    for c, mem, A in zip(comps, members, apsp):
+        vs = local_order(lay, c)
+        p = np.searchsorted(mem, vs)
+        got = spq.index_component(idx, c, len(vs))
+        want = clamp32(A[np.ix_(p, p)])
+        assert np.array_equal(got, want), "component %d" % c
+
+
+def bg_vertices(lay):
+    out = []
+    for c in range(len(lay["nb"])):
+        out.append(local_order(lay, c)[: lay["nb"][c]])
+    return np.concatenate(out) if out else np.zeros(0, np.int64)
+
+
+def check_bg_rows(g, idx, lay, rows):
+    verts = bg_vertices(lay)
+    V = len(verts)
+    if V == 0:
+        return
+    rows = np.unique(np.asarray(rows))
+    D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], verts[rows])
+    want = clamp32(D[:, verts])
+    for r, wrow in zip(rows, want):
+        got = spq.index_bg_rows(idx, int(r), 1, V)[0]
+        assert np.array_equal(got, wrow), "BG row %d" % r
+
+
+def run_queries(idx, v1, v2):
+    out = spq.query_batch(idx, dev(v1), dev(v2))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check_queries(g, idx, v1, v2):
+    got = run_queries(idx, v1, v2)
+    D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], v1)
+    want = clamp32(D[np.arange(len(v1)), v2])
+    bad = np.flatnonzero(got != want)
+    assert len(bad) == 0, "first mismatch pair %s: got %d want %d" % (
+        (v1[bad[0]], v2[bad[0]]), got[bad[0]], want[bad[0]])
+
+
+def all_pairs(n):
+    a, b = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return a.ravel().astype(np.int32), b.ravel().astype(np.int32)
+
+
+# ------------------------------------------------ Floyd-Warshall kernels
+def random_symmetric(rng, N, ld, density, wlo, whi):
+    A = np.full((ld, ld), INF32, np.int64)
+    mask = np.triu(rng.random((N, N)) < density, 1)
+    wts = rng.integers(wlo, whi + 1, size=(N, N))
+    sub = np.where(mask, wts, INF32)
+    sub = np.minimum(sub, sub.T)
+    A[:N, :N] = sub
+    np.fill_diagonal(A, 0)
+    return A
+
+
+def oracle_closure(A, N):
+    d = np.where(A[:N, :N] == INF32, O_INF, A[:N, :N]).astype(np.int64)
+    return clamp32(oracle.fw(d))
+
+
+WEIGHTS = [("tiny", 0, 3), ("mid", 1, 10**6), ("nearinf", 2**30, INF32 - 1)]
+
+
+@pytest.mark.parametrize("wname,wlo,whi", WEIGHTS, ids=[w[0] for w in WEIGHTS])
+def test_fw_components_kernel(wname, wlo, whi):
+    rng = np.random.default_rng(21)
+    sizes = [1, 2, 3, 63, 64, 65, 100, 128, 129, 191, 200, 257, 300]
+    mats, offs, lds, off = [], [], [], 0
+    for N in sizes:
+        ld = -(-N // 64) * 64
+        dens = min(1.0, 4.0 / N) if N > 4 else 0.6
+        mats.append(random_symmetric(rng, N, ld, dens, wlo, whi))
+        offs.append(off)
+        lds.append(ld)
+        off += ld * ld
+    data = np.concatenate([m.ravel() for m in mats]).astype(np.int32)
+    d = dev(data)
+    spq.fw_components(sizes, offs, lds, d)
+    got = d.cpu().numpy()
+    for N, m, o, ld in zip(sizes, mats, offs, lds):
+        g = got[o:o + ld * ld].reshape(ld, ld)
+        assert np.array_equal(g[:N, :N], oracle_closure(m, N)), "N=%d" % N
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("v", [1, 5, 64, 100, 129, 300, 520])
+def test_fw_dense_kernel(tile, v):
+    rng = np.random.default_rng(1000 + v + tile)
+    ld = -(-v // tile) * tile
+    for wlo, whi in [(0, 3), (1, 10**6), (2**30, INF32 - 1)]:
+        A = random_symmetric(rng, v, ld, min(1.0, 3.0 / max(v, 1)), wlo, whi)
+        d = dev(A.ravel())
+        spq.fw_dense(v, ld, tile, d)
+        torch.cuda.synchronize()
+        got = d.cpu().numpy().reshape(ld, ld)
+        assert np.array_equal(got[:v, :v], oracle_closure(A, v)), (wlo, whi)
+        # padding stays isolated
+        if ld > v:
+            assert (got[:v, v:] == INF32).all() and (got[v:, :v] == INF32).all()
+
+
+def test_fw_dense_empty_and_dense_graph():
+    rng = np.random.default_rng(3)
+    v, ld = 200, 256
+    A = np.full((ld, ld), INF32, np.int64)
+    np.fill_diagonal(A, 0)
+    d = dev(A.ravel())
+    spq.fw_dense(v, ld, 128, d)
+    torch.cuda.synchronize()
+    assert np.array_equal(d.cpu().numpy().reshape(ld, ld)[:v, :v], clamp32(A[:v, :v]))
+    B = random_symmetric(rng, v, ld, 1.0, 0, 1000)
+    d = dev(B.ravel())
+    spq.fw_dense(v, ld, 128, d)
+    torch.cuda.synchronize()
+    assert np.array_equal(d.cpu().numpy().reshape(ld, ld)[:v, :v], oracle_closure(B, v))
+
+
+# ------------------------------------------------------------ the index
+def small_cases():
+    rng = np.random.default_rng(5)
+    cases = []
+    for t in range(12):
+        R, C = int(rng.integers(2, 10)), int(rng.integers(2, 10))
+        eu, ev, w = W.random_grid(rng, R, C, keep=0.85, diag=0.3, wlo=0, whi=30)
+        n = R * C
+        if t % 2:
+            k = int(rng.integers(1, min(n, 7) + 1))
+            part = W.random_partition(rng, n, k)
+        else:
+            part, k = W.block_partition(R, C, 3, 3)
+        cases.append(dict(name="grid%d" % t, n=n, eu=eu, ev=ev, w=w, part=part, k=k))
+    for t in range(8):
+        n = int(rng.integers(1, 14))
+        eu, ev, w = W.random_graph(rng, n, int(rng.integers(0, 30)), 0, 9)
+        k = int(rng.integers(1, n + 1))
+        cases.append(dict(name="multi%d" % t, n=n, eu=eu, ev=ev, w=w,
+                          part=W.random_partition(rng, n, k), k=k))
+    # components above one 64-tile: 2 and 3 tile rounds, k = 1 on 400 vertices
+    eu, ev, w = W.random_grid(rng, 24, 24, keep=0.9, diag=0.2)
+    part, k = W.block_partition(24, 24, 12, 12)
+    cases.append(dict(name="blocks144", n=576, eu=eu, ev=ev, w=w, part=part, k=k))
+    eu, ev, w = W.random_grid(rng, 20, 20, keep=0.95)
+    cases.append(dict(name="k1_400", n=400, eu=eu, ev=ev, w=w, part=np.zeros(400, np.int32), k=1))
+    eu, ev, w = W.random_grid(rng, 20, 30, keep=0.9, diag=0.3)
+    cases.append(dict(name="rand2_600", n=600, eu=eu, ev=ev, w=w,
+                      part=W.random_partition(rng, 600, 2), k=2))
+    cases.append(dict(name="single", n=1, eu=np.zeros(0, np.int32), ev=np.zeros(0, np.int32),
+                      w=np.zeros(0, np.int32), part=np.zeros(1, np.int32), k=1))
+    cases.append(dict(name="noedges", n=10, eu=np.zeros(0, np.int32), ev=np.zeros(0, np.int32),
+                      w=np.zeros(0, np.int32), part=np.arange(10, dtype=np.int32) % 3, k=3))
+    return cases
+
+
+CASES = small_cases()
+
+
+@pytest.mark.parametrize("g", CASES, ids=[c["name"] for c in CASES])
+def test_index_small_graphs_all_pairs(g):
+    idx = build(g)
+    lay = spq.index_layout(idx)
+    check_layout(g, lay)
+    check_components(g, idx, lay)
+    st = spq.index_stats(idx)
+    check_bg_rows(g, idx, lay, np.arange(st["v_bg"]))
+    v1, v2 = all_pairs(g["n"])
+    check_queries(g, idx, v1, v2)
+
+
+def test_grid32_everything():
+    g = W.grid32()
+    idx = build(g)
+    lay = spq.index_layout(idx)
+    check_layout(g, lay)
+    st = spq.index_stats(idx)
+    assert st["v_bg"] == 348 and st["k"] == 16 and st["max_comp"] == 64
+    check_components(g, idx, lay)
+    check_bg_rows(g, idx, lay, np.arange(348))
+    check_queries(g, idx, g["v1"], g["v2"])
+    v1, v2 = all_pairs(g["n"])
+    check_queries(g, idx, v1, v2)
+
+
+def test_grid32_bg_tile_and_repeat_are_bitwise_identical():
+    g = W.grid32()
+    a = build(g, bg_tile=64)
+    b = build(g, bg_tile=128)
+    c = build(g, bg_tile=128)
+    ra, rb, rc = (spq.index_bg_rows(x, 0, 348, 348) for x in (a, b, c))
+    assert np.array_equal(ra, rb) and np.array_equal(rb, rc)
+    v1, v2 = all_pairs(g["n"])
+    qa, qb = run_queries(a, v1, v2), run_queries(b, v1, v2)
+    assert np.array_equal(qa, qb)
+
+
+def test_grid256d_full_size():
+    """The benchmark workload: every component, sampled BG rows and queries."""
+    g = W.grid256d()
+    idx = build(g)
+    lay = spq.index_layout(idx)
+    check_layout(g, lay)
+    st = spq.index_stats(idx)
+    assert st["v_bg"] == 27_900 and st["k"] == 1024
+    check_components(g, idx, lay)
+    rng = np.random.default_rng(77)
+    rows = np.concatenate([[0, 1, 27_899], rng.integers(0, 27_900, 200)])
+    check_bg_rows(g, idx, lay, rows)
+    q = len(g["v1"])
+    out = run_queries(idx, g["v1"], g["v2"])
+    assert out.shape == (q,)
+    check_queries(g, idx, g["v1"][:3000], g["v2"][:3000])
+    # the same pairs inside the full batch
+    sub = run_queries(idx, g["v1"][:3000], g["v2"][:3000])
+    assert np.array_equal(sub, out[:3000])
+    # symmetry of the answers and d(v, v) = 0 over the whole batch
+    rev = run_queries(idx, g["v2"], g["v1"])
+    assert np.array_equal(rev, out)
+    same = run_queries(idx, g["v1"], g["v1"])
+    assert (same == 0).all()
+
+
+def test_query_invalid_ids_and_empty_batch():
+    g = W.grid32()
+    idx = build(g)
+    v1 = np.array([0, -1, 5, 1024, 3], np.int32)
+    v2 = np.array([1, 2, 2000, 4, 3], np.int32)
+    out = run_queries(idx, v1, v2)
+    assert out[1] == spq.SPQ_BAD_PAIR and out[2] == spq.SPQ_BAD_PAIR and out[3] == spq.SPQ_BAD_PAIR
+    assert out[4] == 0
+    D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], [0])
+    assert out[0] == D[0, 1]
+    e = torch.empty(0, dtype=torch.int32, device="cuda")
+    assert spq.query_batch(idx, e, e).numel() == 0
+
+
+def test_build_errors():
+    g = W.grid32()
+    def expect(status, **over):
+        h = dict(g)
+        h.update(over)
+        with pytest.raises(spq.SpqError) as ei:
+            build(h)
+        assert ei.value.name == status, ei.value
+    bad = g["part"].copy()
+    bad[7] = 16
+    expect("SPQ_EINVAL", part=bad)
+    w = g["w"].copy()
+    w[3] = -1
+    expect("SPQ_EINVAL", w=w)
+    w = g["w"].copy()
+    w[3] = INF32
+    expect("SPQ_EINVAL", w=w)
+    eu = g["eu"].copy()
+    eu[0] = 1024
+    expect("SPQ_EINVAL", eu=eu)
+    expect("SPQ_EINVAL", part=np.where(g["part"] == 3, 4, g["part"]).astype(np.int32))
+    w = g["w"].copy()
+    w[:3] = 2**30
+    expect("SPQ_ERANGE", w=w)
+    # the index still builds after errors
+    idx = build(g)
+    assert spq.index_stats(idx)["v_bg"] == 348
