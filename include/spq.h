@@ -50,7 +50,9 @@ typedef struct spq_index spq_index; /* opaque; owns all its device memory */
 
 typedef struct {
   int32_t bg_tile;     /* tile of the BG Floyd-Warshall: 0 (default 128), 64, 128 */
-  int32_t reserved[7]; /* must be 0 */
+  int32_t profile;     /* 1: time every interior-tile launch of the BG
+                          Floyd-Warshall with HIP events (see spq_stats) */
+  int32_t reserved[6]; /* must be 0 */
 } spq_build_opts;
 
 typedef struct {
@@ -64,6 +66,12 @@ typedef struct {
   int64_t bg_bytes;        /* bytes of the BG distance matrix (padded) */
   double relax_comp;       /* sum over C of |C|^3: Floyd-Warshall relaxations, Phase 2 */
   double relax_bg;         /* v_bg^3: Floyd-Warshall relaxations in BG, Phase 3 */
+  double relax_comp_exec;  /* relaxations the kernels execute for Phase 2 (padded
+                              tiles; symmetric tiles computed once) */
+  double relax_bg_exec;    /* same for BG */
+  double relax_fw_inner;   /* executed by the BG interior-tile launches */
+  int64_t fw_inner_launches; /* number of BG interior-tile launches */
+  float ms_fw_inner;       /* their summed device time (only with opts.profile) */
   float ms_partition;      /* device time: boundary, renumbering (through the host plan) */
   float ms_components;     /* device time: APSP(C) initialisation + Floyd-Warshall */
   float ms_bg_assembly;    /* device time: BG matrix assembly */

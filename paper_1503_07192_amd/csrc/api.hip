@@ -59,13 +59,16 @@ struct spq_index {
   u32 *err = nullptr, *members = nullptr, *M = nullptr, *BG = nullptr;
   hipEvent_t ev[5] = {};
   bool events = false;
-  double relax_comp = 0, relax_bg = 0;
+  std::vector<hipEvent_t> prof;  // pairs around the BG interior-tile launches
+  double relax_comp = 0, relax_bg = 0, relax_comp_exec = 0, relax_bg_exec = 0, relax_inner = 0;
+  int64_t inner_launches = 0;
 
   ~spq_index() {
     if (events) {
       (void)hipEventSynchronize(ev[4]);
       for (auto& e : ev) (void)hipEventDestroy(e);
     }
+    for (auto& e : prof) (void)hipEventDestroy(e);
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG};
     for (void* p : ptrs)
@@ -88,11 +91,13 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   if (!part || (m > 0 && (!eu || !ev || !w))) return fail(SPQ_EINVAL, "null input array");
   if (n > 0x7fffffff - 1) return fail(SPQ_EINVAL, "n too large");
   int tile = 128;
+  bool profile = false;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
     if (opts->bg_tile) tile = opts->bg_tile;
-    for (int i = 0; i < 7; i++)
+    profile = opts->profile != 0;
+    for (int i = 0; i < 6; i++)
       if (opts->reserved[i]) return fail(SPQ_EINVAL, "reserved options must be 0");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -176,10 +181,22 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     X->max_comp = std::max(X->max_comp, X->h_cnt[c]);
     X->max_nb = std::max(X->max_nb, X->h_nb[c]);
     X->relax_comp += (double)X->h_cnt[c] * X->h_cnt[c] * X->h_cnt[c];
+    // one workgroup runs the blocked rounds on 64-tiles, i <= j interior tiles only
+    const int64_t ntc = X->h_P[c] / spq::COMP_TILE;
+    X->relax_comp_exec += (double)ntc * 64.0 * 64.0 * 64.0 *
+                          (1.0 + (ntc - 1) + (double)(ntc - 1) * ntc / 2.0);
   }
   X->V = X->h_bgoff[k];
   X->Vp = (int32_t)round_up(X->V, tile);
   X->relax_bg = (double)X->V * X->V * X->V;
+  {
+    const int64_t nt = X->Vp / tile;
+    X->relax_bg_exec = spq::dense_fw_exec_relax(nt, tile);
+    if (nt > 1) {
+      X->inner_launches = nt;
+      X->relax_inner = (double)nt * (double)(nt - 1) * nt / 2.0 * tile * tile * (double)tile;
+    }
+  }
   X->h_order.resize(k);
   std::iota(X->h_order.begin(), X->h_order.end(), 0);
   std::stable_sort(X->h_order.begin(), X->h_order.end(),
@@ -228,7 +245,12 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   ba.M = X->M; ba.BG = X->BG;
   TRY(spq::launch_bg_assembly(ba, s));
   TRY(hipEventRecord(X->ev[3], s));
-  TRY(spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, s));
+  if (profile && X->inner_launches > 0) {
+    X->prof.resize(2 * X->inner_launches);
+    for (auto& e : X->prof) TRY(hipEventCreate(&e));
+  }
+  TRY(spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, s,
+                           X->prof.empty() ? nullptr : X->prof.data()));
   TRY(hipEventRecord(X->ev[4], s));
 #undef TRY
   *out = X;
@@ -258,7 +280,16 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   st->bg_bytes = (int64_t)X->Vp * X->Vp * 4;
   st->relax_comp = X->relax_comp;
   st->relax_bg = X->relax_bg;
+  st->relax_comp_exec = X->relax_comp_exec;
+  st->relax_bg_exec = X->relax_bg_exec;
+  st->relax_fw_inner = X->relax_inner;
+  st->fw_inner_launches = X->inner_launches;
   HIP_TRY(hipEventSynchronize(X->ev[4]));
+  for (size_t i = 0; i + 1 < X->prof.size(); i += 2) {
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, X->prof[i], X->prof[i + 1]));
+    st->ms_fw_inner += ms;
+  }
   HIP_TRY(hipEventElapsedTime(&st->ms_partition, X->ev[0], X->ev[1]));
   HIP_TRY(hipEventElapsedTime(&st->ms_components, X->ev[1], X->ev[2]));
   HIP_TRY(hipEventElapsedTime(&st->ms_bg_assembly, X->ev[2], X->ev[3]));
@@ -334,7 +365,7 @@ spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t* data, void
   if (v < 0 || ld < v || ld % tile || (v > 0 && !data)) return fail(SPQ_EINVAL, "bad v or ld");
   if (v == 0) return SPQ_OK;
   HIP_TRY(spq::launch_dense_fw(reinterpret_cast<u32*>(data), ld, tile, ld / tile,
-                               reinterpret_cast<hipStream_t>(stream)));
+                               reinterpret_cast<hipStream_t>(stream), nullptr));
   return SPQ_OK;
 }
 

@@ -196,12 +196,13 @@ __global__ __launch_bounds__(256) void k_comp_fw(const int32_t* __restrict__ ord
     __threadfence_block();
     __syncthreads();
     // the remaining tiles: T(i,j) = min(T(i,j), T(i,r) (x) T(r,j)), with
-    // T(i,r)^T = T(r,i) already laid out as the transposed left operand
+    // T(i,r)^T = T(r,i) already laid out as the transposed left operand;
+    // only i <= j is computed, T(j,i) receives the transpose
     for (int i = 0; i < nt; i++) {
       if (i == r) continue;
       tile_load<T>(t, base + (int64_t)r * T * p + i * T, p);
       tile_to_lds<T>(t, sA);
-      for (int j = 0; j < nt; j++) {
+      for (int j = i; j < nt; j++) {
         if (j == r) continue;
         tile_load<T>(t, base + (int64_t)r * T * p + j * T, p);
         tile_to_lds<T>(t, sB);
@@ -210,6 +211,7 @@ __global__ __launch_bounds__(256) void k_comp_fw(const int32_t* __restrict__ ord
         __syncthreads();
         minplus_lds<T>(t, sA, sB, T);
         tile_store<T>(t, Cij, p);
+        if (j != i) tile_store_t<T>(t, base + (int64_t)j * T * p + i * T, p);
         __syncthreads();
       }
     }
@@ -299,17 +301,32 @@ __global__ __launch_bounds__(256) void k_fw_panel(u32* __restrict__ A, int64_t l
   tile_store_t<T>(t, A + (int64_t)j * T * ld + (int64_t)r * T, ld);
 }
 
-// Interior tiles.  The k dimension is streamed through LDS in chunks of KC
-// rows of the two operand tiles (double buffered, next chunk prefetched into
-// registers while the current one is consumed).
+// Upper-triangle enumeration: block b -> (bi, bj), 0 <= bi <= bj < m, row by
+// row (row bi holds m - bi blocks).
+__device__ __forceinline__ void tri_index(int b, int m, int& bi, int& bj) {
+  const float fm = 2.0f * m + 1.0f;
+  int i = (int)((fm - sqrtf(fm * fm - 8.0f * (float)b)) * 0.5f);
+  if (i < 0) i = 0;
+  if (i > m - 1) i = m - 1;
+  while (i > 0 && i * (2 * m - i + 1) / 2 > b) i--;
+  while (i + 1 < m && (i + 1) * (2 * m - i) / 2 <= b) i++;
+  bi = i;
+  bj = i + (b - i * (2 * m - i + 1) / 2);
+}
+
+// Interior tiles.  The matrix is symmetric, so only tiles (i, j) with i <= j
+// are computed; tile (j, i) receives the transpose.  The k dimension is
+// streamed through LDS in chunks of KC rows of the two operand tiles (double
+// buffered, next chunk prefetched into registers while the current one is
+// consumed).
 template <int T, int KC>
 __global__ __launch_bounds__(256) void k_fw_inner(u32* __restrict__ A, int64_t ld, int r, int nt) {
   constexpr int Q = KC * T / 4 / 256;  // uint4 per thread per operand chunk
   static_assert(Q >= 1 && KC * T / 4 % 256 == 0, "chunk must split evenly");
   __shared__ __attribute__((aligned(16))) u32 sA[2][KC * T];
   __shared__ __attribute__((aligned(16))) u32 sB[2][KC * T];
-  const int m1 = nt - 1;
-  const int bi = (int)(blockIdx.x / m1), bj = (int)(blockIdx.x % m1);
+  int bi, bj;
+  tri_index((int)blockIdx.x, nt - 1, bi, bj);
   const int i = bi + (bi >= r), j = bj + (bj >= r);
   const u32* Ar = A + (int64_t)r * T * ld + (int64_t)i * T;  // tile (r, i)
   const u32* Br = A + (int64_t)r * T * ld + (int64_t)j * T;  // tile (r, j)
@@ -358,16 +375,19 @@ __global__ __launch_bounds__(256) void k_fw_inner(u32* __restrict__ A, int64_t l
     __syncthreads();
   }
   tile_store<T>(t, Cij, ld);
+  if (i != j) tile_store_t<T>(t, A + (int64_t)j * T * ld + (int64_t)i * T, ld);
 }
 
 // ----------------------------------------------------------------- query --
-// Algorithm 2, one wavefront per query.  Lane j takes b2 = j (+64, ...):
+// Algorithm 2, one wavefront per query:
 //   t(b2) = min over b1 of dist_C1(v1, b1) + dist_BG(b1, b2)     (lines 2-7)
 //   r     = min over b2 of t(b2) + dist_C2(b2, v2)                (lines 9-12)
 //   r     = min(r, dist_C1(v1, v2)) if C1 = C2                    (line 13)
-// dist_C1(v1, .) is the prefix of v1's row of APSP(C1) (boundary first), held
-// one value per lane and broadcast with readlane; dist_C2(b2, v2) is read from
-// v2's row (the matrix is symmetric), and the BG block rows are contiguous.
+// dist_C1(v1, .) is the prefix of v1's row of APSP(C1) (boundary first);
+// dist_C2(b2, v2) is read from v2's row (the matrix is symmetric); each row
+// of the BG block is contiguous.  When |B(C2)| <= 32 the wave splits into
+// two half-waves that take even and odd b1, so both halves stream BG rows.
+// The b1 loop keeps 8 row loads in flight per lane.
 __global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restrict__ v1,
                                                const int32_t* __restrict__ v2, int32_t* __restrict__ out,
                                                int32_t n, const int32_t* __restrict__ comp,
@@ -392,22 +412,31 @@ __global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restr
   const u32* row1 = M + moff[c1] + (int64_t)l1 * P[c1];
   const u32* row2 = M + moff[c2] + (int64_t)l2 * P[c2];
   const u32* blk = BG + (int64_t)bgoff[c1] * ldbg + bgoff[c2];
+  const int W = nb2 <= 32 ? 32 : 64;  // lanes per group
+  const int G = 64 / W;               // groups, each takes b1 = g (mod G)
+  const int g = lane / W, jj = lane % W;
   u32 best = INF;
-  for (int32_t b2base = 0; b2base < nb2; b2base += 64) {
-    const int32_t b2 = b2base + lane;
+  for (int32_t b2base = 0; b2base < nb2; b2base += W) {
+    const int32_t b2 = b2base + jj;
     const bool act = b2 < nb2;
     const u32* col = blk + (act ? b2 : 0);
     u32 t = INF;
-    for (int32_t b1base = 0; b1base < nb1; b1base += 64) {
-      const int32_t cnt = min(64, nb1 - b1base);
-      const u32 mine = (lane < cnt) ? row1[b1base + lane] : INF;
-      const u32* cp = col + (int64_t)b1base * ldbg;
-      for (int32_t x = 0; x < cnt; x++) {
-        const u32 d1 = (u32)__builtin_amdgcn_readlane((int)mine, x);
-        const u32 g = act ? cp[(int64_t)x * ldbg] : INF;
-        t = min(t, d1 + g);
+    int32_t b1 = g;
+    for (; b1 + 7 * G < nb1; b1 += 8 * G) {
+      u32 d[8], x[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        d[u] = row1[b1 + u * G];
+        x[u] = act ? col[(int64_t)(b1 + u * G) * ldbg] : INF;
       }
+#pragma unroll
+      for (int u = 0; u < 8; u++) t = min(t, d[u] + x[u]);
     }
+    for (; b1 < nb1; b1 += G) {
+      const u32 x = act ? col[(int64_t)b1 * ldbg] : INF;
+      t = min(t, row1[b1] + x);
+    }
+    if (G == 2) t = min(t, (u32)__shfl_xor((int)t, 32));
     if (act) best = min(best, min(t, INF) + row2[b2]);
   }
   for (int o = 32; o > 0; o >>= 1) best = min(best, (u32)__shfl_xor((int)best, o));
@@ -473,21 +502,34 @@ hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s) {
 }
 
 template <int T>
-static hipError_t fw_rounds(u32* A, int64_t ld, int nt, hipStream_t s) {
+static hipError_t fw_rounds(u32* A, int64_t ld, int nt, hipStream_t s, hipEvent_t* ev) {
   for (int r = 0; r < nt; r++) {
     k_fw_diag<T><<<1, 256, 0, s>>>(A, ld, r);
     if (nt > 1) {
       k_fw_panel<T><<<nt - 1, 256, 0, s>>>(A, ld, r);
-      k_fw_inner<T, 32><<<(unsigned)((nt - 1) * (nt - 1)), 256, 0, s>>>(A, ld, r, nt);
+      if (ev) {
+        hipError_t e = hipEventRecord(ev[2 * r], s);
+        if (e != hipSuccess) return e;
+      }
+      k_fw_inner<T, 32><<<(unsigned)((nt - 1) * nt / 2), 256, 0, s>>>(A, ld, r, nt);
+      if (ev) {
+        hipError_t e = hipEventRecord(ev[2 * r + 1], s);
+        if (e != hipSuccess) return e;
+      }
     }
   }
   LAUNCH_CHECK();
 }
 
-hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s) {
+hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev) {
   if (nt <= 0) return hipSuccess;
-  if (tile == 64) return fw_rounds<64>(A, ld, nt, s);
-  return fw_rounds<128>(A, ld, nt, s);
+  if (tile == 64) return fw_rounds<64>(A, ld, nt, s, ev);
+  return fw_rounds<128>(A, ld, nt, s, ev);
+}
+
+double dense_fw_exec_relax(int64_t nt, int tile) {
+  const double t3 = (double)tile * tile * tile;
+  return (double)nt * t3 * (1.0 + (nt - 1) + (double)(nt - 1) * nt / 2.0);
 }
 
 hipError_t launch_query(const QueryArgs& a, hipStream_t s) {

@@ -65,7 +65,11 @@ hipError_t launch_components(const CompArgs& a, hipStream_t s);
 hipError_t launch_comp_fw(int32_t count, const int32_t* order, const int32_t* P, const int64_t* moff,
                           u32* M, hipStream_t s);
 hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s);
-hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s);
+// ev: NULL, or 2*nt events recorded around each interior-tile launch
+hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev);
+// relaxations executed by launch_dense_fw (diagonal, panel and upper-triangle
+// interior tiles of every round)
+double dense_fw_exec_relax(int64_t nt, int tile);
 hipError_t launch_query(const QueryArgs& a, hipStream_t s);
 
 }  // namespace spq

@@ -32,7 +32,8 @@ class SpqError(RuntimeError):
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("bg_tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("bg_tile", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):
@@ -41,6 +42,9 @@ class Stats(ctypes.Structure):
                 ("max_comp", ctypes.c_int32), ("max_boundary", ctypes.c_int32),
                 ("comp_bytes", ctypes.c_int64), ("bg_bytes", ctypes.c_int64),
                 ("relax_comp", ctypes.c_double), ("relax_bg", ctypes.c_double),
+                ("relax_comp_exec", ctypes.c_double), ("relax_bg_exec", ctypes.c_double),
+                ("relax_fw_inner", ctypes.c_double), ("fw_inner_launches", ctypes.c_int64),
+                ("ms_fw_inner", ctypes.c_float),
                 ("ms_partition", ctypes.c_float), ("ms_components", ctypes.c_float),
                 ("ms_bg_assembly", ctypes.c_float), ("ms_bg_apsp", ctypes.c_float)]
 
@@ -137,10 +141,10 @@ class Index:
             pass
 
 
-def build_index(n, eu, ev, w, part, k, bg_tile=0, stream=None) -> Index:
+def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, stream=None) -> Index:
     """Algorithm 1 on device tensors; see spq_build_index."""
     L = load()
-    opts = BuildOpts(bg_tile=bg_tile)
+    opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)))
     h = ctypes.c_void_p()
     m = int(eu.numel())
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),
