@@ -52,7 +52,9 @@ typedef struct {
   int32_t bg_tile;     /* tile of the BG Floyd-Warshall: 0 (default 128), 64, 128 */
   int32_t profile;     /* 1: time every interior-tile launch of the BG
                           Floyd-Warshall with HIP events (see spq_stats) */
-  int32_t reserved[6]; /* must be 0 */
+  int32_t plain;       /* 1: one kernel launch per component for APSP(C)
+                          instead of one launch for all (comparison path) */
+  int32_t reserved[5]; /* must be 0 */
 } spq_build_opts;
 
 typedef struct {

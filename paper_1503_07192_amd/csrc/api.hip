@@ -57,6 +57,7 @@ struct spq_index {
   uint8_t* flag = nullptr;
   unsigned long long *sumc = nullptr, *total = nullptr;
   u32 *err = nullptr, *members = nullptr, *M = nullptr, *BG = nullptr;
+  uint4* vrec = nullptr;
   hipEvent_t ev[5] = {};
   bool events = false;
   std::vector<hipEvent_t> prof;  // pairs around the BG interior-tile launches
@@ -70,7 +71,8 @@ struct spq_index {
     }
     for (auto& e : prof) (void)hipEventDestroy(e);
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
-                    cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG};
+                    cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
+                    vrec};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
@@ -91,13 +93,14 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   if (!part || (m > 0 && (!eu || !ev || !w))) return fail(SPQ_EINVAL, "null input array");
   if (n > 0x7fffffff - 1) return fail(SPQ_EINVAL, "n too large");
   int tile = 128;
-  bool profile = false;
+  bool profile = false, plain = false;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
     if (opts->bg_tile) tile = opts->bg_tile;
     profile = opts->profile != 0;
-    for (int i = 0; i < 6; i++)
+    plain = opts->plain != 0;
+    for (int i = 0; i < 5; i++)
       if (opts->reserved[i]) return fail(SPQ_EINVAL, "reserved options must be 0");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -214,6 +217,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   TRY(dalloc(&X->bglocal, X->V));
   TRY(dalloc(&X->fill, k));
   TRY(dalloc(&X->members, n));
+  TRY(dalloc(&X->vrec, 2 * (int64_t)n));
   TRY(dalloc(&X->M, X->comp_elems));
   if (X->Vp > 0) TRY(dalloc(&X->BG, (int64_t)X->Vp * X->Vp));
   TRY(hipMemcpyAsync(X->off, X->h_off.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
@@ -226,6 +230,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   // ---- renumbering (Section 4, Fig. 1)
   pa.off = X->off; pa.bgoff = X->bgoff; pa.fill = X->fill; pa.members = X->members;
   pa.comp = X->comp; pa.local = X->local; pa.bgcomp = X->bgcomp; pa.bglocal = X->bglocal;
+  pa.moff = X->moff; pa.P = X->P; pa.vrec = X->vrec;
   TRY(spq::launch_renumber(pa, s));
   TRY(hipEventRecord(X->ev[1], s));
 
@@ -234,7 +239,11 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   ca.k = k; ca.m = m; ca.eu = eu; ca.ev = ev; ca.w = w; ca.comp = X->comp; ca.local = X->local;
   ca.P = X->P; ca.moff = X->moff; ca.M = X->M;
   TRY(spq::launch_components(ca, s));
-  TRY(spq::launch_comp_fw(k, X->order, X->P, X->moff, X->M, s));
+  if (plain) {
+    for (int32_t c = 0; c < k; c++) TRY(spq::launch_comp_fw(1, X->order + c, X->P, X->moff, X->M, s));
+  } else {
+    TRY(spq::launch_comp_fw(k, X->order, X->P, X->moff, X->M, s));
+  }
   TRY(hipEventRecord(X->ev[2], s));
 
   // ---- Phase 3: BG and its all-pairs distances
@@ -265,8 +274,7 @@ spq_status spq_query_batch(const spq_index* X, int64_t q, const int32_t* v1, con
   if (!v1 || !v2 || !out) return fail(SPQ_EINVAL, "null query array");
   spq::QueryArgs a{};
   a.q = q; a.v1 = v1; a.v2 = v2; a.out = out; a.n = X->n;
-  a.comp = X->comp; a.local = X->local; a.nb = X->nb; a.bgoff = X->bgoff; a.P = X->P;
-  a.moff = X->moff; a.M = X->M; a.BG = X->BG; a.ldbg = X->Vp;
+  a.vrec = X->vrec; a.M = X->M; a.BG = X->BG; a.ldbg = X->Vp;
   HIP_TRY(spq::launch_query(a, reinterpret_cast<hipStream_t>(stream)));
   return SPQ_OK;
 }

@@ -319,8 +319,13 @@ __device__ __forceinline__ void tri_index(int b, int m, int& bi, int& bj) {
 // streamed through LDS in chunks of KC rows of the two operand tiles (double
 // buffered, next chunk prefetched into registers while the current one is
 // consumed).
+#ifdef SPQ_INNER_WPE
+#define SPQ_INNER_ATTR __attribute__((amdgpu_waves_per_eu(SPQ_INNER_WPE, SPQ_INNER_WPE)))
+#else
+#define SPQ_INNER_ATTR
+#endif
 template <int T, int KC>
-__global__ __launch_bounds__(256) void k_fw_inner(u32* __restrict__ A, int64_t ld, int r, int nt) {
+__global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict__ A, int64_t ld, int r, int nt) {
   constexpr int Q = KC * T / 4 / 256;  // uint4 per thread per operand chunk
   static_assert(Q >= 1 && KC * T / 4 % 256 == 0, "chunk must split evenly");
   __shared__ __attribute__((aligned(16))) u32 sA[2][KC * T];
@@ -379,23 +384,34 @@ __global__ __launch_bounds__(256) void k_fw_inner(u32* __restrict__ A, int64_t l
 }
 
 // ----------------------------------------------------------------- query --
+// Per-vertex record read by the query kernel in one 32-byte load: where the
+// vertex's row of APSP(C) starts, its component, its local index, and the
+// component's first BG id and boundary count.
+__global__ void k_vrec(int32_t n, const int32_t* __restrict__ comp, const int32_t* __restrict__ local,
+                       const int64_t* __restrict__ moff, const int32_t* __restrict__ P,
+                       const int32_t* __restrict__ bgoff, const int32_t* __restrict__ nb,
+                       uint4* __restrict__ vrec) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t c = comp[v], l = local[v];
+  const uint64_t row = (uint64_t)(moff[c] + (int64_t)l * P[c]);
+  vrec[2 * v] = make_uint4((u32)row, (u32)(row >> 32), (u32)c, (u32)l);
+  vrec[2 * v + 1] = make_uint4((u32)bgoff[c], (u32)nb[c], 0u, 0u);
+}
+
 // Algorithm 2, one wavefront per query:
 //   t(b2) = min over b1 of dist_C1(v1, b1) + dist_BG(b1, b2)     (lines 2-7)
 //   r     = min over b2 of t(b2) + dist_C2(b2, v2)                (lines 9-12)
 //   r     = min(r, dist_C1(v1, v2)) if C1 = C2                    (line 13)
-// dist_C1(v1, .) is the prefix of v1's row of APSP(C1) (boundary first);
-// dist_C2(b2, v2) is read from v2's row (the matrix is symmetric); each row
-// of the BG block is contiguous.  When |B(C2)| <= 32 the wave splits into
-// two half-waves that take even and odd b1, so both halves stream BG rows.
-// The b1 loop keeps 8 row loads in flight per lane.
+// dist_C1(v1, .) is the prefix of v1's row of APSP(C1) (boundary first), held
+// one value per lane and broadcast with ds_bpermute; dist_C2(b2, v2) is read
+// from v2's row (the matrix is symmetric); each row of the BG block is
+// contiguous.  When |B(C2)| <= 32 the wave splits into two half-waves that
+// take even and odd b1, so both halves stream BG rows.  Each lane keeps 8
+// row loads in flight.
 __global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restrict__ v1,
                                                const int32_t* __restrict__ v2, int32_t* __restrict__ out,
-                                               int32_t n, const int32_t* __restrict__ comp,
-                                               const int32_t* __restrict__ local,
-                                               const int32_t* __restrict__ nb,
-                                               const int32_t* __restrict__ bgoff,
-                                               const int32_t* __restrict__ P,
-                                               const int64_t* __restrict__ moff,
+                                               int32_t n, const uint4* __restrict__ vrec,
                                                const u32* __restrict__ M, const u32* __restrict__ BG,
                                                int64_t ldbg) {
   const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -406,12 +422,12 @@ __global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restr
     if (lane == 0) out[qi] = -1;
     return;
   }
-  const int32_t c1 = comp[a], c2 = comp[b];
-  const int32_t l1 = local[a], l2 = local[b];
-  const int32_t nb1 = nb[c1], nb2 = nb[c2];
-  const u32* row1 = M + moff[c1] + (int64_t)l1 * P[c1];
-  const u32* row2 = M + moff[c2] + (int64_t)l2 * P[c2];
-  const u32* blk = BG + (int64_t)bgoff[c1] * ldbg + bgoff[c2];
+  const uint4 ra = vrec[2 * (int64_t)a], ra2 = vrec[2 * (int64_t)a + 1];
+  const uint4 rb = vrec[2 * (int64_t)b], rb2 = vrec[2 * (int64_t)b + 1];
+  const u32* row1 = M + ((uint64_t)ra.x | ((uint64_t)ra.y << 32));
+  const u32* row2 = M + ((uint64_t)rb.x | ((uint64_t)rb.y << 32));
+  const int32_t nb1 = (int32_t)ra2.y, nb2 = (int32_t)rb2.y;
+  const u32* blk = BG + (int64_t)ra2.x * ldbg + rb2.x;
   const int W = nb2 <= 32 ? 32 : 64;  // lanes per group
   const int G = 64 / W;               // groups, each takes b1 = g (mod G)
   const int g = lane / W, jj = lane % W;
@@ -421,27 +437,28 @@ __global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restr
     const bool act = b2 < nb2;
     const u32* col = blk + (act ? b2 : 0);
     u32 t = INF;
-    int32_t b1 = g;
-    for (; b1 + 7 * G < nb1; b1 += 8 * G) {
-      u32 d[8], x[8];
+    for (int32_t b1base = 0; b1base < nb1; b1base += 64) {
+      const int32_t cnt = min(64, nb1 - b1base);
+      const u32 r1 = (lane < cnt) ? row1[b1base + lane] : INF;
+      const u32* cb = col + (int64_t)b1base * ldbg;
+      for (int32_t x0 = 0; x0 < cnt; x0 += 8 * G) {  // uniform over the wave
+        u32 d[8], xv[8];
 #pragma unroll
-      for (int u = 0; u < 8; u++) {
-        d[u] = row1[b1 + u * G];
-        x[u] = act ? col[(int64_t)(b1 + u * G) * ldbg] : INF;
+        for (int u = 0; u < 8; u++) {
+          const int idx = x0 + g + u * G;
+          xv[u] = (act && idx < cnt) ? cb[(int64_t)idx * ldbg] : INF;
+          d[u] = (u32)__shfl((int)r1, idx & 63);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) t = min(t, d[u] + xv[u]);
       }
-#pragma unroll
-      for (int u = 0; u < 8; u++) t = min(t, d[u] + x[u]);
-    }
-    for (; b1 < nb1; b1 += G) {
-      const u32 x = act ? col[(int64_t)b1 * ldbg] : INF;
-      t = min(t, row1[b1] + x);
     }
     if (G == 2) t = min(t, (u32)__shfl_xor((int)t, 32));
     if (act) best = min(best, min(t, INF) + row2[b2]);
   }
   for (int o = 32; o > 0; o >>= 1) best = min(best, (u32)__shfl_xor((int)best, o));
   if (lane == 0) {
-    if (c1 == c2) best = min(best, row1[l2]);
+    if (ra.z == rb.z) best = min(best, row1[rb.w]);
     out[qi] = (int32_t)min(best, INF);
   }
 }
@@ -470,6 +487,7 @@ hipError_t launch_renumber(const PartArgs& a, hipStream_t s) {
   k_members<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.part, a.flag, a.off, a.fill, a.members);
   k_rank<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.k, a.members, a.off, a.nb, a.bgoff, a.comp, a.local,
                                          a.bgcomp, a.bglocal);
+  k_vrec<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.comp, a.local, a.moff, a.P, a.bgoff, a.nb, a.vrec);
   LAUNCH_CHECK();
 }
 
@@ -501,6 +519,10 @@ hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s) {
   LAUNCH_CHECK();
 }
 
+#ifndef SPQ_INNER_KC
+#define SPQ_INNER_KC 16
+#endif
+
 template <int T>
 static hipError_t fw_rounds(u32* A, int64_t ld, int nt, hipStream_t s, hipEvent_t* ev) {
   for (int r = 0; r < nt; r++) {
@@ -511,7 +533,7 @@ static hipError_t fw_rounds(u32* A, int64_t ld, int nt, hipStream_t s, hipEvent_
         hipError_t e = hipEventRecord(ev[2 * r], s);
         if (e != hipSuccess) return e;
       }
-      k_fw_inner<T, 32><<<(unsigned)((nt - 1) * nt / 2), 256, 0, s>>>(A, ld, r, nt);
+      k_fw_inner<T, SPQ_INNER_KC><<<(unsigned)((nt - 1) * nt / 2), 256, 0, s>>>(A, ld, r, nt);
       if (ev) {
         hipError_t e = hipEventRecord(ev[2 * r + 1], s);
         if (e != hipSuccess) return e;
@@ -535,8 +557,7 @@ double dense_fw_exec_relax(int64_t nt, int tile) {
 hipError_t launch_query(const QueryArgs& a, hipStream_t s) {
   if (a.q <= 0) return hipSuccess;
   int64_t blocks = (a.q + 3) / 4;
-  k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.comp, a.local, a.nb,
-                                           a.bgoff, a.P, a.moff, a.M, a.BG, a.ldbg);
+  k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.vrec, a.M, a.BG, a.ldbg);
   LAUNCH_CHECK();
 }
 

@@ -29,6 +29,9 @@ struct PartArgs {
   u32* members;               // [n] scratch
   int32_t *comp, *local;      // [n]
   int32_t *bgcomp, *bglocal;  // [V]
+  const int64_t* moff;        // [k] first element of each APSP(C)
+  const int32_t* P;           // [k] padded side of each APSP(C)
+  uint4* vrec;                // [2n] per-vertex query records
 };
 
 struct CompArgs {
@@ -53,8 +56,7 @@ struct QueryArgs {
   const int32_t *v1, *v2;
   int32_t* out;
   int32_t n;
-  const int32_t *comp, *local, *nb, *bgoff, *P;
-  const int64_t* moff;
+  const uint4* vrec;
   const u32 *M, *BG;
   int64_t ldbg;
 };

@@ -121,7 +121,10 @@ __device__ __forceinline__ void minplus_lds(u32 (&c)[T / 16][T / 16], const u32*
   const int tx = tid_x(), ty = tid_y();
   const u32* ap = At + ty * 4;
   const u32* bp = B + tx * 4;
-#pragma unroll 2
+#ifndef SPQ_MP_UNROLL
+#define SPQ_MP_UNROLL 2
+#endif
+#pragma unroll SPQ_MP_UNROLL
   for (int k = 0; k < K; k += 2) {
     u32 a0[R], a1[R], b0[R], b1[R];
 #pragma unroll

@@ -33,7 +33,7 @@ class SpqError(RuntimeError):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("bg_tile", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("plain", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -141,10 +141,11 @@ class Index:
             pass
 
 
-def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, stream=None) -> Index:
+def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False,
+                stream=None) -> Index:
     """Algorithm 1 on device tensors; see spq_build_index."""
     L = load()
-    opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)))
+    opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)), plain=int(bool(plain)))
     h = ctypes.c_void_p()
     m = int(eu.numel())
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),

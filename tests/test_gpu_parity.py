@@ -250,13 +250,16 @@ def test_grid32_everything():
     check_queries(g, idx, v1, v2)
 
 
-def test_grid32_bg_tile_and_repeat_are_bitwise_identical():
+def test_grid32_bg_tile_plain_and_repeat_are_bitwise_identical():
     g = W.grid32()
     a = build(g, bg_tile=64)
     b = build(g, bg_tile=128)
     c = build(g, bg_tile=128)
-    ra, rb, rc = (spq.index_bg_rows(x, 0, 348, 348) for x in (a, b, c))
-    assert np.array_equal(ra, rb) and np.array_equal(rb, rc)
+    d = build(g, plain=True)
+    ra, rb, rc, rd = (spq.index_bg_rows(x, 0, 348, 348) for x in (a, b, c, d))
+    assert np.array_equal(ra, rb) and np.array_equal(rb, rc) and np.array_equal(rb, rd)
+    for comp in range(16):
+        assert np.array_equal(spq.index_component(b, comp, 64), spq.index_component(d, comp, 64))
     v1, v2 = all_pairs(g["n"])
     qa, qb = run_queries(a, v1, v2), run_queries(b, v1, v2)
     assert np.array_equal(qa, qb)
