@@ -54,7 +54,11 @@ typedef struct {
                           Floyd-Warshall with HIP events (see spq_stats) */
   int32_t plain;       /* 1: one kernel launch per component for APSP(C)
                           instead of one launch for all (comparison path) */
-  int32_t reserved[5]; /* must be 0 */
+  int32_t bg_method;   /* 0 auto (flat up to 32,768 BG vertices), 1 flat
+                          Floyd-Warshall on all of BG, 2 two-level */
+  int32_t group_comps; /* two-level: consecutive components per group
+                          (0 = auto: about 4,096 BG vertices per group) */
+  int32_t reserved[3]; /* must be 0 */
 } spq_build_opts;
 
 typedef struct {
@@ -74,6 +78,10 @@ typedef struct {
   double relax_fw_inner;   /* executed by the BG interior-tile launches */
   int64_t fw_inner_launches; /* number of BG interior-tile launches */
   float ms_fw_inner;       /* their summed device time (only with opts.profile) */
+  int32_t bg_method;       /* 1 flat, 2 two-level */
+  int32_t ngroups;         /* groups of the two-level method (1 when flat) */
+  int32_t v_bg2;           /* level-2 boundary vertices (two-level) */
+  int32_t pad0;
   float ms_partition;      /* device time: boundary, renumbering (through the host plan) */
   float ms_components;     /* device time: APSP(C) initialisation + Floyd-Warshall */
   float ms_bg_assembly;    /* device time: BG matrix assembly */
@@ -96,6 +104,11 @@ typedef struct {
  * The call blocks until the partition sizes are known (one small device to
  * host copy), then queues the remaining work on `stream` and returns; the
  * index is usable by work queued later on the same stream.
+ * BG distances are closed either by Floyd-Warshall on the whole BG matrix
+ * (flat) or by the two-level method: BG split into groups of consecutive
+ * components, each group closed, the graph of the group boundaries closed,
+ * and the remaining distances composed as in Algorithm 2 one level up.  Both
+ * give the same distances.
  * Errors: SPQ_EINVAL (bad id, weight or part, empty component, k < 1),
  * SPQ_ERANGE (the total edge weight reaches SPQ_INF, so a distance might not
  * fit), SPQ_ENOMEM, SPQ_EDEVICE.

@@ -58,6 +58,16 @@ struct spq_index {
   unsigned long long *sumc = nullptr, *total = nullptr;
   u32 *err = nullptr, *members = nullptr, *M = nullptr, *BG = nullptr;
   uint4* vrec = nullptr;
+  // groups (all components in group 0 for the flat store)
+  int32_t method = 1, ngroups = 1, Vgp = 0, V2 = 0, m2pmax = 0;
+  int64_t V2p = 0, h_elems = 0;
+  std::vector<int32_t> h_grp, h_gbg0, h_gV, h_m2, h_b2off;
+  std::vector<int64_t> h_pairbase;
+  int32_t *grp = nullptr, *gbg0 = nullptr, *gV = nullptr, *bgrow = nullptr, *bgnb = nullptr;
+  int32_t *bggrp = nullptr, *b2list = nullptr, *b2rank = nullptr, *m2 = nullptr, *b2off = nullptr;
+  uint8_t* flag2 = nullptr;
+  u32 *Mg = nullptr, *R = nullptr, *XT = nullptr, *BG2 = nullptr, *H = nullptr;
+  int64_t* pairbase = nullptr;
   hipEvent_t ev[5] = {};
   bool events = false;
   std::vector<hipEvent_t> prof;  // pairs around the BG interior-tile launches
@@ -72,7 +82,8 @@ struct spq_index {
     for (auto& e : prof) (void)hipEventDestroy(e);
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
-                    vrec};
+                    vrec, grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
+                    b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
@@ -94,13 +105,18 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   if (n > 0x7fffffff - 1) return fail(SPQ_EINVAL, "n too large");
   int tile = 128;
   bool profile = false, plain = false;
+  int32_t method_opt = 0, group_comps = 0;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
     if (opts->bg_tile) tile = opts->bg_tile;
     profile = opts->profile != 0;
     plain = opts->plain != 0;
-    for (int i = 0; i < 5; i++)
+    method_opt = opts->bg_method;
+    group_comps = opts->group_comps;
+    if (method_opt < 0 || method_opt > 2) return fail(SPQ_EINVAL, "bg_method must be 0, 1 or 2");
+    if (group_comps < 0) return fail(SPQ_EINVAL, "group_comps < 0");
+    for (int i = 0; i < 3; i++)
       if (opts->reserved[i]) return fail(SPQ_EINVAL, "reserved options must be 0");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -190,15 +206,40 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
                           (1.0 + (ntc - 1) + (double)(ntc - 1) * ntc / 2.0);
   }
   X->V = X->h_bgoff[k];
-  X->Vp = (int32_t)round_up(X->V, tile);
   X->relax_bg = (double)X->V * X->V * X->V;
-  {
+  X->method = method_opt ? method_opt : (X->V > 32768 ? 2 : 1);
+  int32_t cpg = k;
+  if (X->method == 2) {
+    if (group_comps > 0) {
+      cpg = std::min(group_comps, k);
+    } else {
+      // about 4,096 BG vertices per group, a power of two of components
+      const double avg_nb = std::max(1.0, (double)X->V / k);
+      cpg = 1;
+      while (cpg * 2 <= k && cpg * 2 * avg_nb <= 4096.0 * 1.41) cpg *= 2;
+    }
+  }
+  X->ngroups = (k + cpg - 1) / cpg;
+  X->h_grp.resize(k);
+  X->h_gbg0.resize(X->ngroups);
+  X->h_gV.resize(X->ngroups);
+  for (int32_t c = 0; c < k; c++) X->h_grp[c] = c / cpg;
+  for (int32_t g = 0; g < X->ngroups; g++) {
+    X->h_gbg0[g] = X->h_bgoff[g * cpg];
+    X->h_gV[g] = X->h_bgoff[std::min((g + 1) * cpg, k)] - X->h_gbg0[g];
+    X->Vgp = std::max<int32_t>(X->Vgp, (int32_t)round_up(X->h_gV[g], 128));
+  }
+  if (X->method == 1) {
+    X->Vp = (int32_t)round_up(X->V, tile);
     const int64_t nt = X->Vp / tile;
     X->relax_bg_exec = spq::dense_fw_exec_relax(nt, tile);
     if (nt > 1) {
       X->inner_launches = nt;
       X->relax_inner = (double)nt * (double)(nt - 1) * nt / 2.0 * tile * tile * (double)tile;
     }
+  } else {
+    X->Vgp = std::max<int32_t>(X->Vgp, 128);
+    X->relax_bg_exec = X->ngroups * spq::dense_fw_exec_relax(X->Vgp / 128, 128);
   }
   X->h_order.resize(k);
   std::iota(X->h_order.begin(), X->h_order.end(), 0);
@@ -219,7 +260,13 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   TRY(dalloc(&X->members, n));
   TRY(dalloc(&X->vrec, 2 * (int64_t)n));
   TRY(dalloc(&X->M, X->comp_elems));
-  if (X->Vp > 0) TRY(dalloc(&X->BG, (int64_t)X->Vp * X->Vp));
+  if (X->method == 1 && X->Vp > 0) TRY(dalloc(&X->BG, (int64_t)X->Vp * X->Vp));
+  TRY(dalloc(&X->grp, k));
+  TRY(dalloc(&X->gbg0, X->ngroups));
+  TRY(dalloc(&X->gV, X->ngroups));
+  TRY(hipMemcpyAsync(X->grp, X->h_grp.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+  TRY(hipMemcpyAsync(X->gbg0, X->h_gbg0.data(), sizeof(int32_t) * X->ngroups, hipMemcpyHostToDevice, s));
+  TRY(hipMemcpyAsync(X->gV, X->h_gV.data(), sizeof(int32_t) * X->ngroups, hipMemcpyHostToDevice, s));
   TRY(hipMemcpyAsync(X->off, X->h_off.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
   TRY(hipMemcpyAsync(X->bgoff, X->h_bgoff.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
   TRY(hipMemcpyAsync(X->P, X->h_P.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
@@ -230,7 +277,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   // ---- renumbering (Section 4, Fig. 1)
   pa.off = X->off; pa.bgoff = X->bgoff; pa.fill = X->fill; pa.members = X->members;
   pa.comp = X->comp; pa.local = X->local; pa.bgcomp = X->bgcomp; pa.bglocal = X->bglocal;
-  pa.moff = X->moff; pa.P = X->P; pa.vrec = X->vrec;
+  pa.moff = X->moff; pa.P = X->P; pa.vrec = X->vrec; pa.grp = X->grp; pa.gbg0 = X->gbg0;
   TRY(spq::launch_renumber(pa, s));
   TRY(hipEventRecord(X->ev[1], s));
 
@@ -247,6 +294,70 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   TRY(hipEventRecord(X->ev[2], s));
 
   // ---- Phase 3: BG and its all-pairs distances
+  if (X->method == 2) {
+    spq::HierArgs ha{};
+    const int32_t G = X->ngroups, V = X->V, Vgp = X->Vgp;
+    TRY(dalloc(&X->Mg, (int64_t)G * Vgp * Vgp));
+    TRY(dalloc(&X->flag2, V));
+    TRY(dalloc(&X->b2list, (int64_t)G * Vgp));
+    TRY(dalloc(&X->b2rank, V));
+    TRY(dalloc(&X->m2, G));
+    TRY(dalloc(&X->b2off, G + 1));
+    TRY(dalloc(&X->bgrow, V));
+    TRY(dalloc(&X->bgnb, V));
+    TRY(dalloc(&X->bggrp, V));
+    if (V > 0) TRY(hipMemsetAsync(X->flag2, 0, V, s));
+    ha.V = V; ha.ngroups = G; ha.Vgp = Vgp; ha.m = m;
+    ha.eu = eu; ha.ev = ev; ha.w = w; ha.comp = X->comp; ha.local = X->local; ha.bgoff = X->bgoff;
+    ha.nb = X->nb; ha.bgcomp = X->bgcomp; ha.bglocal = X->bglocal; ha.P = X->P; ha.moff = X->moff;
+    ha.M = X->M; ha.grp = X->grp; ha.gbg0 = X->gbg0; ha.gV = X->gV; ha.bgrow = X->bgrow;
+    ha.bgnb = X->bgnb; ha.bggrp = X->bggrp; ha.Mg = X->Mg; ha.flag2 = X->flag2; ha.b2list = X->b2list;
+    ha.b2rank = X->b2rank; ha.m2 = X->m2;
+    TRY(hipEventRecord(X->ev[3], s));
+    TRY(spq::launch_hier_level1(ha, s));
+    X->h_m2.resize(G);
+    TRY(hipMemcpyAsync(X->h_m2.data(), X->m2, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    X->h_b2off.assign(G + 1, 0);
+    int32_t m2max = 0;
+    for (int32_t g = 0; g < G; g++) {
+      X->h_b2off[g + 1] = X->h_b2off[g] + X->h_m2[g];
+      m2max = std::max(m2max, X->h_m2[g]);
+    }
+    X->V2 = X->h_b2off[G];
+    X->V2p = round_up(X->V2, 128);
+    X->m2pmax = (int32_t)std::max<int64_t>(128, round_up(m2max, 128));
+    X->h_pairbase.assign((size_t)G * G, 0);
+    for (int32_t a1 = 0; a1 < G; a1++)
+      for (int32_t a2 = a1; a2 < G; a2++) {
+        X->h_pairbase[(size_t)a1 * G + a2] = X->h_elems;
+        X->h_elems += (int64_t)X->h_gV[a1] * X->h_gV[a2];
+      }
+    // executed relaxations of level 2
+    if (X->V2p > 0) X->relax_bg_exec += spq::dense_fw_exec_relax(X->V2p / 128, 128);
+    for (int32_t a1 = 0; a1 < G; a1++)
+      for (int32_t a2 = a1; a2 < G; a2++) {
+        if (X->V2p > 0)
+          X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * (Vgp / 128) * 128.0 * 128.0 *
+                              (double)round_up(X->h_m2[a1], 16);
+        X->relax_bg_exec += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) *
+                            128.0 * 128.0 * (double)round_up(X->h_m2[a2], 16);
+      }
+    TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
+    TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
+    TRY(dalloc(&X->XT, (int64_t)G * X->m2pmax * Vgp));
+    if (X->V2p > 0) TRY(dalloc(&X->BG2, X->V2p * X->V2p));
+    TRY(dalloc(&X->H, X->h_elems));
+    TRY(dalloc(&X->pairbase, (int64_t)G * G));
+    TRY(hipMemcpyAsync(X->pairbase, X->h_pairbase.data(), sizeof(int64_t) * G * G,
+                       hipMemcpyHostToDevice, s));
+    ha.m2pmax = X->m2pmax; ha.V2 = X->V2; ha.V2p = X->V2p; ha.b2off = X->b2off; ha.R = X->R;
+    ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
+    TRY(spq::launch_hier_level2(ha, s));
+    TRY(hipEventRecord(X->ev[4], s));
+    *out = X;
+    return SPQ_OK;
+  }
   spq::BgArgs ba{};
   ba.V = X->V; ba.Vp = X->Vp; ba.m = m; ba.eu = eu; ba.ev = ev; ba.w = w;
   ba.comp = X->comp; ba.local = X->local; ba.bgoff = X->bgoff; ba.nb = X->nb;
@@ -275,6 +386,8 @@ spq_status spq_query_batch(const spq_index* X, int64_t q, const int32_t* v1, con
   spq::QueryArgs a{};
   a.q = q; a.v1 = v1; a.v2 = v2; a.out = out; a.n = X->n;
   a.vrec = X->vrec; a.M = X->M; a.BG = X->BG; a.ldbg = X->Vp;
+  a.H = X->method == 2 ? X->H : nullptr; a.pairbase = X->pairbase; a.gV = X->gV;
+  a.ngroups = X->ngroups;
   HIP_TRY(spq::launch_query(a, reinterpret_cast<hipStream_t>(stream)));
   return SPQ_OK;
 }
@@ -292,6 +405,13 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   st->relax_bg_exec = X->relax_bg_exec;
   st->relax_fw_inner = X->relax_inner;
   st->fw_inner_launches = X->inner_launches;
+  st->bg_method = X->method;
+  st->ngroups = X->ngroups;
+  st->v_bg2 = X->V2;
+  if (X->method == 2) {
+    st->v_bg_padded = X->Vgp;
+    st->bg_bytes = (int64_t)X->h_elems * 4;
+  }
   HIP_TRY(hipEventSynchronize(X->ev[4]));
   for (size_t i = 0; i + 1 < X->prof.size(); i += 2) {
     float ms = 0;
@@ -333,6 +453,22 @@ spq_status spq_index_bg_rows(const spq_index* X, int32_t row0, int32_t nrows, in
     return fail(SPQ_EINVAL, "BG rows out of range");
   if (nrows == 0) return SPQ_OK;
   HIP_TRY(hipEventSynchronize(X->ev[4]));
+  if (X->method == 2) {
+    u32* tmp = nullptr;
+    HIP_TRY(dalloc(&tmp, X->V));
+    spq::HierArgs ha{};
+    ha.V = X->V; ha.ngroups = X->ngroups; ha.bggrp = X->bggrp; ha.bgrow = X->bgrow; ha.bgnb = X->bgnb;
+    ha.bglocal = X->bglocal; ha.gV = X->gV; ha.pairbase = X->pairbase; ha.H = X->H;
+    hipError_t e = hipSuccess;
+    for (int32_t r = 0; r < nrows && e == hipSuccess; r++) {
+      e = spq::launch_hier_row(ha, row0 + r, tmp, nullptr);
+      if (e == hipSuccess)
+        e = hipMemcpy(out + (int64_t)r * X->V, tmp, sizeof(int32_t) * X->V, hipMemcpyDeviceToHost);
+    }
+    (void)hipFree(tmp);
+    HIP_TRY(e);
+    return SPQ_OK;
+  }
   HIP_TRY(hipMemcpy2D(out, sizeof(int32_t) * X->V, X->BG + (int64_t)row0 * X->Vp,
                       sizeof(int32_t) * X->Vp, sizeof(int32_t) * X->V, nrows,
                       hipMemcpyDeviceToHost));

@@ -1,0 +1,457 @@
+// Two-level all-pairs distances in BG.
+//
+// The preprocessing of Algorithm 1 applied once more, one level up: BG itself
+// is partitioned into groups of consecutive components.  For a group S:
+//   * BG_S = the subgraph of BG induced by S's boundary vertices (the clique
+//     edges of S's components plus the G edges between them), closed by
+//     Floyd-Warshall: d_S (a batch of equally sized matrices);
+//   * B2(S) = vertices of BG_S with a BG edge leaving S (the boundary of the
+//     group partition, Section 2's definition applied to BG).
+// BG2 = the B2 vertices of all groups, joined by d_S between the B2 vertices
+// of one group and by the G edges between groups; closed by Floyd-Warshall it
+// holds d_BG between B2 vertices (Lemma 1 for the group partition).  Every
+// other BG distance is Algorithm 2's formula at the group level (Lemma 3):
+//   D(S1,S2)[x][y] = min over a in B2(S1), b in B2(S2) of
+//                    d_S1(x,a) + d_BG2(a,b) + d_S2(b,y),
+//   and when S1 = S2 also d_S1(x,y).
+// It is evaluated as two min-plus products, XT = D2(S1,S2)^T (x) R_S1 and
+// D = XT^T (x) R_S2, where R_S = rows B2(S) of d_S (by symmetry, the columns
+// too).  Only S1 <= S2 is stored; a query swaps its endpoints otherwise.
+//
+// Storage of D(S1,S2) (V_S1 x V_S2 values at pairbase[S1][S2]): the rows of
+// one component C1 of S1 form a band; inside it, the block of component C2 of
+// S2 is nb(C1) x nb(C2) contiguous values, so a query reads one contiguous
+// block.  Element (x, y) is at
+//   rowoff(x) * V_S2 + nb(x) * rowoff(y) + loc(x) * nb(y) + loc(y)
+// with rowoff = first BG id of the component inside its group, loc = index
+// inside the component's boundary.
+#include "spq_internal.h"
+#include "tiles.h"
+
+namespace spq {
+
+// Group matrix init: 0 on the diagonal, the APSP(C) distance inside one
+// component, INF elsewhere and on the padding.
+__global__ void k_grp_init(int32_t Vgp, const int32_t* __restrict__ gbg0, const int32_t* __restrict__ gV,
+                           const int32_t* __restrict__ bgcomp, const int32_t* __restrict__ bglocal,
+                           const int32_t* __restrict__ bgoff, const int32_t* __restrict__ nb,
+                           const int32_t* __restrict__ P, const int64_t* __restrict__ moff,
+                           const u32* __restrict__ M, u32* __restrict__ Mg) {
+  const int s = blockIdx.y;
+  const int64_t p = blockIdx.x;
+  u32* out = Mg + ((int64_t)s * Vgp + p) * Vgp;
+  const int32_t g0 = gbg0[s];
+  int64_t lo = 0, hi = 0;
+  const u32* mrow = nullptr;
+  if (p < gV[s]) {
+    const int32_t x = g0 + (int32_t)p;
+    const int32_t c = bgcomp[x];
+    lo = bgoff[c] - g0;
+    hi = lo + nb[c];
+    mrow = M + moff[c] + (int64_t)bglocal[x] * P[c] - lo;
+  }
+  for (int64_t q0 = (int64_t)threadIdx.x * 4; q0 < Vgp; q0 += (int64_t)blockDim.x * 4) {
+    u32 v[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int64_t q = q0 + t;
+      v[t] = (q == p) ? 0u : (q >= lo && q < hi) ? mrow[q] : INF;
+    }
+    *reinterpret_cast<uint4*>(out + q0) = make_uint4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// G edges between boundary vertices of different components: inside a group
+// they become entries of the group matrix; between groups they mark both ends
+// as level-2 boundary vertices.
+__global__ void k_grp_edges(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                            const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
+                            const int32_t* __restrict__ local, const int32_t* __restrict__ bgoff,
+                            const int32_t* __restrict__ grp, const int32_t* __restrict__ gbg0,
+                            int32_t Vgp, u32* __restrict__ Mg, uint8_t* __restrict__ flag2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = eu[e], v = ev[e];
+    const int32_t cu = comp[u], cv = comp[v];
+    if (cu == cv) continue;
+    const int32_t su = grp[cu], sv = grp[cv];
+    const int32_t xu = bgoff[cu] + local[u], xv = bgoff[cv] + local[v];
+    if (su == sv) {
+      u32* base = Mg + (int64_t)su * Vgp * Vgp;
+      const int64_t a = xu - gbg0[su], b = xv - gbg0[su];
+      atomicMin(base + a * Vgp + b, (u32)w[e]);
+      atomicMin(base + b * Vgp + a, (u32)w[e]);
+    } else {
+      flag2[xu] = 1;
+      flag2[xv] = 1;
+    }
+  }
+}
+
+// One workgroup per group: lists the level-2 boundary vertices of the group in
+// ascending order (b2list), their rank (b2rank, -1 if not one) and count.
+__global__ __launch_bounds__(256) void k_b2_scan(const int32_t* __restrict__ gbg0,
+                                                 const int32_t* __restrict__ gV,
+                                                 const uint8_t* __restrict__ flag2, int32_t Vgp,
+                                                 int32_t* __restrict__ b2list, int32_t* __restrict__ b2rank,
+                                                 int32_t* __restrict__ m2) {
+  __shared__ int32_t wsum[4];
+  const int s = blockIdx.x;
+  const int32_t g0 = gbg0[s], V = gV[s];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int32_t base = 0;
+  for (int32_t c0 = 0; c0 < V; c0 += 256) {
+    const int32_t p = c0 + (int32_t)threadIdx.x;
+    const bool f = p < V && flag2[g0 + p];
+    const unsigned long long bal = __ballot(f);
+    const int32_t before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wid] = __popcll(bal);
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+    for (int i = 0; i < 4; i++) {
+      if (i < wid) woff += wsum[i];
+      tot += wsum[i];
+    }
+    if (p < V) {
+      if (f) {
+        const int32_t r = base + woff + before;
+        b2list[(int64_t)s * Vgp + r] = p;
+        b2rank[g0 + p] = r;
+      } else {
+        b2rank[g0 + p] = -1;
+      }
+    }
+    base += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) m2[s] = base;
+}
+
+// R_S: rows B2(S) of d_S (m2pmax rows per group, INF rows past m2[S]).
+__global__ void k_r_gather(int32_t Vgp, int32_t m2pmax, const int32_t* __restrict__ m2,
+                           const int32_t* __restrict__ b2list, const u32* __restrict__ Mg,
+                           u32* __restrict__ R) {
+  const int s = blockIdx.y;
+  const int32_t i = blockIdx.x;
+  uint4* dst = reinterpret_cast<uint4*>(R + ((int64_t)s * m2pmax + i) * Vgp);
+  const int32_t n4 = Vgp / 4;
+  if (i < m2[s]) {
+    const uint4* src =
+        reinterpret_cast<const uint4*>(Mg + ((int64_t)s * Vgp + b2list[(int64_t)s * Vgp + i]) * Vgp);
+    for (int32_t q = threadIdx.x; q < n4; q += blockDim.x) dst[q] = src[q];
+  } else {
+    for (int32_t q = threadIdx.x; q < n4; q += blockDim.x) dst[q] = make_uint4(INF, INF, INF, INF);
+  }
+}
+
+// BG2 matrix init: d_S between B2 vertices of one group, 0 on the diagonal,
+// INF elsewhere and on the padding.
+__global__ void k_bg2_init(int32_t V2, int64_t V2p, int32_t ngroups, const int32_t* __restrict__ b2off,
+                           const int32_t* __restrict__ b2list, int32_t Vgp, const u32* __restrict__ Mg,
+                           u32* __restrict__ BG2) {
+  const int64_t i = blockIdx.x;
+  u32* out = BG2 + i * V2p;
+  int64_t lo = 0, hi = 0;
+  const u32* prow = nullptr;
+  const int32_t* list = nullptr;
+  if (i < V2) {
+    int32_t a = 0, b = ngroups - 1;  // group of B2 id i: largest s with b2off[s] <= i
+    while (a < b) {
+      const int32_t mid = (a + b + 1) >> 1;
+      if (b2off[mid] <= i) a = mid; else b = mid - 1;
+    }
+    lo = b2off[a];
+    hi = b2off[a + 1];
+    list = b2list + (int64_t)a * Vgp;
+    prow = Mg + ((int64_t)a * Vgp + list[i - lo]) * Vgp;
+  }
+  for (int64_t q0 = (int64_t)threadIdx.x * 4; q0 < V2p; q0 += (int64_t)blockDim.x * 4) {
+    u32 v[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int64_t q = q0 + t;
+      v[t] = (q == i) ? 0u : (q >= lo && q < hi) ? prow[list[q - lo]] : INF;
+    }
+    *reinterpret_cast<uint4*>(out + q0) = make_uint4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+__global__ void k_bg2_edges(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                            const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
+                            const int32_t* __restrict__ local, const int32_t* __restrict__ bgoff,
+                            const int32_t* __restrict__ grp, const int32_t* __restrict__ b2off,
+                            const int32_t* __restrict__ b2rank, int64_t V2p, u32* __restrict__ BG2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = eu[e], v = ev[e];
+    const int32_t cu = comp[u], cv = comp[v];
+    if (cu == cv) continue;
+    const int32_t su = grp[cu], sv = grp[cv];
+    if (su == sv) continue;
+    const int64_t a = b2off[su] + b2rank[bgoff[cu] + local[u]];
+    const int64_t b = b2off[sv] + b2rank[bgoff[cv] + local[v]];
+    atomicMin(BG2 + a * V2p + b, (u32)w[e]);
+    atomicMin(BG2 + b * V2p + a, (u32)w[e]);
+  }
+}
+
+// Per BG vertex: first BG id of its component inside its group, and the
+// component's boundary count (the layout terms of D(S1,S2)).
+__global__ void k_hier_vmeta(int32_t V, const int32_t* __restrict__ bgcomp, const int32_t* __restrict__ bgoff,
+                             const int32_t* __restrict__ nb, const int32_t* __restrict__ grp,
+                             const int32_t* __restrict__ gbg0, int32_t* __restrict__ bgrow,
+                             int32_t* __restrict__ bgnb, int32_t* __restrict__ bggrp) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= V) return;
+  const int32_t c = bgcomp[x], s = grp[c];
+  bgrow[x] = bgoff[c] - gbg0[s];
+  bgnb[x] = nb[c];
+  bggrp[x] = s;
+}
+
+// ------------------------------------------------------- min-plus products --
+// c (128 x 128 in registers) = min(c, min over k < K of At[k][i] + B[k][j]).
+// Rows k of At and B are ldA / ldB apart; K is a multiple of 16 and is
+// streamed through LDS 16 rows at a time (double buffered, next chunk
+// prefetched into registers).  With MASKED, rows k >= kvalid and columns
+// i >= avalid of At read as INF without touching memory, and rows k >= kvalid
+// of B likewise.
+template <bool MASKED>
+__device__ __forceinline__ uint4 mp_load_a(const u32* At, int64_t ldA, int k, int col, int kvalid,
+                                           int avalid) {
+  if (!MASKED) return *reinterpret_cast<const uint4*>(At + (int64_t)k * ldA + col);
+  if (k >= kvalid) return make_uint4(INF, INF, INF, INF);
+  const u32* p = At + (int64_t)k * ldA + col;
+  if (col + 3 < avalid) return *reinterpret_cast<const uint4*>(p);
+  return make_uint4(col < avalid ? p[0] : INF, col + 1 < avalid ? p[1] : INF,
+                    col + 2 < avalid ? p[2] : INF, INF);
+}
+
+template <bool MASKED>
+__device__ __forceinline__ uint4 mp_load_b(const u32* B, int64_t ldB, int k, int col, int kvalid) {
+  if (MASKED && k >= kvalid) return make_uint4(INF, INF, INF, INF);
+  return *reinterpret_cast<const uint4*>(B + (int64_t)k * ldB + col);
+}
+
+template <bool MASKED>
+__device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int64_t ldA, const u32* B,
+                                             int64_t ldB, int K, int kvalid, int avalid, u32* sA,
+                                             u32* sB) {
+  constexpr int T = 128, KC = 16;
+  const int nch = K / KC;
+  if (nch <= 0) return;
+  // two uint4 of each operand per thread per chunk: rows e/32, columns 4*(e%32)
+  const int e0 = threadIdx.x, e1 = threadIdx.x + 256;
+  const int r0 = e0 >> 5, c0 = (e0 & 31) * 4, r1 = e1 >> 5, c1 = (e1 & 31) * 4;
+  uint4 pa0 = mp_load_a<MASKED>(At, ldA, r0, c0, kvalid, avalid);
+  uint4 pa1 = mp_load_a<MASKED>(At, ldA, r1, c1, kvalid, avalid);
+  uint4 pb0 = mp_load_b<MASKED>(B, ldB, r0, c0, kvalid);
+  uint4 pb1 = mp_load_b<MASKED>(B, ldB, r1, c1, kvalid);
+  reinterpret_cast<uint4*>(sA)[e0] = pa0;
+  reinterpret_cast<uint4*>(sA)[e1] = pa1;
+  reinterpret_cast<uint4*>(sB)[e0] = pb0;
+  reinterpret_cast<uint4*>(sB)[e1] = pb1;
+  __syncthreads();
+  for (int ch = 0; ch < nch; ch++) {
+    // the last iteration reloads its own chunk into the idle buffer (unused)
+    const int kn = (ch + 1 < nch ? ch + 1 : ch) * KC;
+    pa0 = mp_load_a<MASKED>(At, ldA, kn + r0, c0, kvalid, avalid);
+    pa1 = mp_load_a<MASKED>(At, ldA, kn + r1, c1, kvalid, avalid);
+    pb0 = mp_load_b<MASKED>(B, ldB, kn + r0, c0, kvalid);
+    pb1 = mp_load_b<MASKED>(B, ldB, kn + r1, c1, kvalid);
+    const int cur = (ch & 1) * KC * T, nxt = ((ch + 1) & 1) * KC * T;
+    minplus_lds<T>(c, sA + cur, sB + cur, KC);
+    reinterpret_cast<uint4*>(sA + nxt)[e0] = pa0;
+    reinterpret_cast<uint4*>(sA + nxt)[e1] = pa1;
+    reinterpret_cast<uint4*>(sB + nxt)[e0] = pb0;
+    reinterpret_cast<uint4*>(sB + nxt)[e1] = pb1;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void fill_inf(u32 (&c)[8][8]) {
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+#pragma unroll
+    for (int j = 0; j < 8; j++) c[i][j] = INF;
+}
+
+// XT[S2] (m2pmax x Vgp, rows b in B2(S2), columns x of S1) =
+//   min over a in B2(S1) of D2[a][b] + R_S1[a][x],   for S2 = S1 + blockIdx.y.
+// Rows b >= m2[S2] are stored as INF.
+__global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t Vgp, int32_t m2pmax,
+                                               const int32_t* __restrict__ m2,
+                                               const int32_t* __restrict__ b2off,
+                                               const u32* __restrict__ BG2, int64_t V2p,
+                                               const u32* __restrict__ R, u32* __restrict__ XT) {
+  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
+  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
+  const int32_t s2 = s1 + (int32_t)blockIdx.y;
+  const int ntx = Vgp / 128;
+  const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
+  const int32_t ka = m2[s1], mb = m2[s2];
+  u32 c[8][8];
+  fill_inf(c);
+  if (ti * 128 < mb) {
+    const u32* At = BG2 + (int64_t)b2off[s1] * V2p + b2off[s2] + ti * 128;
+    const u32* B = R + (int64_t)s1 * m2pmax * Vgp + tj * 128;
+    mp_stream128<true>(c, At, V2p, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB);
+  }
+  u32* out = XT + ((int64_t)s2 * m2pmax + ti * 128) * Vgp + tj * 128;
+  const int tx = tid_x(), ty = tid_y();
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int row = h * 64 + ty * 4 + a;
+      const bool live = ti * 128 + row < mb;
+#pragma unroll
+      for (int h2 = 0; h2 < 2; h2++) {
+        const int i = h * 4 + a, j = h2 * 4;
+        uint4 v = live ? make_uint4(c[i][j], c[i][j + 1], c[i][j + 2], c[i][j + 3])
+                       : make_uint4(INF, INF, INF, INF);
+        *reinterpret_cast<uint4*>(out + (int64_t)row * Vgp + h2 * 64 + tx * 4) = v;
+      }
+    }
+}
+
+// D(S1,S2) tile (rows x of S1, columns y of S2) for S2 = S1 + blockIdx.y:
+//   min over b in B2(S2) of XT[S2][b][x] + R_S2[b][y], and d_S1 when S1 = S2;
+// stored in the component-pair layout described at the top of the file.
+__global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t ngroups, int32_t Vgp, int32_t m2pmax,
+                                              const int32_t* __restrict__ m2,
+                                              const int32_t* __restrict__ gV,
+                                              const int32_t* __restrict__ gbg0,
+                                              const u32* __restrict__ XT, const u32* __restrict__ R,
+                                              const u32* __restrict__ Mg,
+                                              const int64_t* __restrict__ pairbase,
+                                              const int32_t* __restrict__ bgrow,
+                                              const int32_t* __restrict__ bgnb,
+                                              const int32_t* __restrict__ bglocal, u32* __restrict__ H) {
+  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
+  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
+  const int32_t s2 = s1 + (int32_t)blockIdx.y;
+  const int ntx = Vgp / 128;
+  const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
+  const int32_t V1 = gV[s1], V2 = gV[s2];
+  if (ti * 128 >= V1 || tj * 128 >= V2) return;
+  u32 c[8][8];
+  if (s1 == s2)
+    tile_load<128>(c, Mg + (int64_t)s1 * Vgp * Vgp + (int64_t)ti * 128 * Vgp + tj * 128, Vgp);
+  else
+    fill_inf(c);
+  const int32_t kb = m2[s2];
+  const u32* At = XT + (int64_t)s2 * m2pmax * Vgp + ti * 128;
+  const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
+  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB);
+  u32* base = H + pairbase[(int64_t)s1 * ngroups + s2];
+  const int tx = tid_x(), ty = tid_y();
+  const int32_t g1 = gbg0[s1], g2 = gbg0[s2];
+  int64_t colpart[8];
+  int32_t colnb[8];
+  bool colok[8];
+#pragma unroll
+  for (int h2 = 0; h2 < 2; h2++)
+#pragma unroll
+    for (int a2 = 0; a2 < 4; a2++) {
+      const int32_t y = tj * 128 + h2 * 64 + tx * 4 + a2;
+      const int j = h2 * 4 + a2;
+      colok[j] = y < V2;
+      const int32_t yg = g2 + (colok[j] ? y : 0);
+      colpart[j] = bgrow[yg];   // times nb(x) below
+      colnb[j] = bgnb[yg];
+      colpart[j] = (colpart[j] << 32) | (uint32_t)bglocal[yg];
+    }
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int32_t x = ti * 128 + h * 64 + ty * 4 + a;
+      if (x >= V1) continue;
+      const int32_t xg = g1 + x;
+      const int64_t rbase = (int64_t)bgrow[xg] * V2;
+      const int64_t nbx = bgnb[xg], locx = bglocal[xg];
+      const int i = h * 4 + a;
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        if (!colok[j]) continue;
+        const int64_t rowy = colpart[j] >> 32, locy = colpart[j] & 0xffffffffll;
+        base[rbase + nbx * rowy + locx * colnb[j] + locy] = c[i][j];
+      }
+    }
+}
+
+// One BG row (BG id x) gathered from the two-level store, for inspection.
+__global__ void k_hier_row(int32_t x, int32_t V, int32_t ngroups, const int32_t* __restrict__ bggrp,
+                           const int32_t* __restrict__ bgrow, const int32_t* __restrict__ bgnb,
+                           const int32_t* __restrict__ bglocal, const int32_t* __restrict__ gV,
+                           const int64_t* __restrict__ pairbase, const u32* __restrict__ H,
+                           u32* __restrict__ out) {
+  const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= V) return;
+  int32_t a = x, b = (int32_t)y;
+  if (bggrp[a] > bggrp[b]) {
+    a = (int32_t)y;
+    b = x;
+  }
+  const int32_t sa = bggrp[a], sb = bggrp[b];
+  const int64_t off = pairbase[(int64_t)sa * ngroups + sb] + (int64_t)bgrow[a] * gV[sb] +
+                      (int64_t)bgnb[a] * bgrow[b] + (int64_t)bglocal[a] * bgnb[b] + bglocal[b];
+  out[y] = H[off];
+}
+
+// ---------------------------------------------------------------- launch --
+static inline unsigned hblocks(int64_t items) {
+  int64_t b = (items + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 8192) b = 8192;
+  return (unsigned)b;
+}
+
+hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s) {
+  k_hier_vmeta<<<hblocks(a.V), 256, 0, s>>>(a.V, a.bgcomp, a.bgoff, a.nb, a.grp, a.gbg0,
+                                                              a.bgrow, a.bgnb, a.bggrp);
+  k_grp_init<<<dim3((unsigned)a.Vgp, (unsigned)a.ngroups), 256, 0, s>>>(
+      a.Vgp, a.gbg0, a.gV, a.bgcomp, a.bglocal, a.bgoff, a.nb, a.P, a.moff, a.M, a.Mg);
+  if (a.m > 0)
+    k_grp_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
+                                             a.gbg0, a.Vgp, a.Mg, a.flag2);
+  hipError_t e = launch_dense_fw_batch(a.Mg, a.Vgp, 128, a.Vgp / 128, a.ngroups,
+                                       (int64_t)a.Vgp * a.Vgp, s, nullptr);
+  if (e != hipSuccess) return e;
+  k_b2_scan<<<(unsigned)a.ngroups, 256, 0, s>>>(a.gbg0, a.gV, a.flag2, a.Vgp, a.b2list, a.b2rank, a.m2);
+  return hipGetLastError();
+}
+
+hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s) {
+  k_r_gather<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(a.Vgp, a.m2pmax, a.m2,
+                                                                           a.b2list, a.Mg, a.R);
+  if (a.V2p > 0) {
+    k_bg2_init<<<(unsigned)a.V2p, 256, 0, s>>>(a.V2, a.V2p, a.ngroups, a.b2off, a.b2list, a.Vgp, a.Mg,
+                                               a.BG2);
+    if (a.m > 0)
+      k_bg2_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
+                                               a.b2off, a.b2rank, a.V2p, a.BG2);
+    hipError_t e = launch_dense_fw(a.BG2, a.V2p, 128, (int)(a.V2p / 128), s, nullptr);
+    if (e != hipSuccess) return e;
+  }
+  const int ntx = a.Vgp / 128, ntm = a.m2pmax / 128;
+  for (int32_t s1 = 0; s1 < a.ngroups; s1++) {
+    const unsigned pairs = (unsigned)(a.ngroups - s1);
+    if (a.V2p > 0)
+      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(s1, a.Vgp, a.m2pmax, a.m2, a.b2off,
+                                                                 a.BG2, a.V2p, a.R, a.XT);
+    k_mp_y<<<dim3((unsigned)(ntx * ntx), pairs), 256, 0, s>>>(
+        s1, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
+        a.bgnb, a.bglocal, a.H);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s) {
+  k_hier_row<<<(unsigned)((a.V + 255) / 256 > 0 ? (a.V + 255) / 256 : 1), 256, 0, s>>>(x, a.V, a.ngroups, a.bggrp, a.bgrow, a.bgnb,
+                                                          a.bglocal, a.gV, a.pairbase, a.H, out);
+  return hipGetLastError();
+}
+
+}  // namespace spq

@@ -274,9 +274,14 @@ __global__ void k_bg_edges(int64_t m, const int32_t* __restrict__ eu, const int3
 //   k_fw_panel  tile (r, j) = D (x) tile (r, j) for j != r, stored twice
 //               (as (r, j) and transposed as (j, r))
 //   k_fw_inner  tile (i, j) = min(tile (i, j), tile (r, i)^T (x) tile (r, j))
+//
+// A batch of equally sized matrices is handled by blockIdx.y: matrix y starts
+// gstride elements after matrix y-1.
 template <int T>
-__global__ __launch_bounds__(256) void k_fw_diag(u32* __restrict__ A, int64_t ld, int r) {
+__global__ __launch_bounds__(256) void k_fw_diag(u32* __restrict__ A, int64_t ld, int r,
+                                                 int64_t gstride) {
   __shared__ __attribute__((aligned(16))) u32 rb[4 * T];
+  A += (int64_t)blockIdx.y * gstride;
   u32 t[T / 16][T / 16];
   u32* D = A + (int64_t)r * T * ld + (int64_t)r * T;
   tile_load<T>(t, D, ld);
@@ -285,9 +290,11 @@ __global__ __launch_bounds__(256) void k_fw_diag(u32* __restrict__ A, int64_t ld
 }
 
 template <int T>
-__global__ __launch_bounds__(256) void k_fw_panel(u32* __restrict__ A, int64_t ld, int r) {
+__global__ __launch_bounds__(256) void k_fw_panel(u32* __restrict__ A, int64_t ld, int r,
+                                                  int64_t gstride) {
   __shared__ __attribute__((aligned(16))) u32 sD[T * T];
   __shared__ __attribute__((aligned(16))) u32 sB[T * T];
+  A += (int64_t)blockIdx.y * gstride;
   const int j = (int)blockIdx.x + ((int)blockIdx.x >= r);
   u32 t[T / 16][T / 16];
   tile_load<T>(t, A + (int64_t)r * T * ld + (int64_t)r * T, ld);
@@ -325,11 +332,13 @@ __device__ __forceinline__ void tri_index(int b, int m, int& bi, int& bj) {
 #define SPQ_INNER_ATTR
 #endif
 template <int T, int KC>
-__global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict__ A, int64_t ld, int r, int nt) {
+__global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict__ A, int64_t ld, int r, int nt,
+                                                                int64_t gstride) {
   constexpr int Q = KC * T / 4 / 256;  // uint4 per thread per operand chunk
   static_assert(Q >= 1 && KC * T / 4 % 256 == 0, "chunk must split evenly");
   __shared__ __attribute__((aligned(16))) u32 sA[2][KC * T];
   __shared__ __attribute__((aligned(16))) u32 sB[2][KC * T];
+  A += (int64_t)blockIdx.y * gstride;
   int bi, bj;
   tri_index((int)blockIdx.x, nt - 1, bi, bj);
   const int i = bi + (bi >= r), j = bj + (bj >= r);
@@ -390,13 +399,14 @@ __global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict
 __global__ void k_vrec(int32_t n, const int32_t* __restrict__ comp, const int32_t* __restrict__ local,
                        const int64_t* __restrict__ moff, const int32_t* __restrict__ P,
                        const int32_t* __restrict__ bgoff, const int32_t* __restrict__ nb,
+                       const int32_t* __restrict__ grp, const int32_t* __restrict__ gbg0,
                        uint4* __restrict__ vrec) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int32_t c = comp[v], l = local[v];
+  const int32_t c = comp[v], l = local[v], s = grp[c];
   const uint64_t row = (uint64_t)(moff[c] + (int64_t)l * P[c]);
   vrec[2 * v] = make_uint4((u32)row, (u32)(row >> 32), (u32)c, (u32)l);
-  vrec[2 * v + 1] = make_uint4((u32)bgoff[c], (u32)nb[c], 0u, 0u);
+  vrec[2 * v + 1] = make_uint4((u32)bgoff[c], (u32)nb[c], (u32)s, (u32)(bgoff[c] - gbg0[s]));
 }
 
 // Algorithm 2, one wavefront per query:
@@ -413,7 +423,9 @@ __global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restr
                                                const int32_t* __restrict__ v2, int32_t* __restrict__ out,
                                                int32_t n, const uint4* __restrict__ vrec,
                                                const u32* __restrict__ M, const u32* __restrict__ BG,
-                                               int64_t ldbg) {
+                                               int64_t ldbg, const u32* __restrict__ H,
+                                               const int64_t* __restrict__ pairbase,
+                                               const int32_t* __restrict__ gV, int32_t ngroups) {
   const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (qi >= q) return;
@@ -422,12 +434,25 @@ __global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restr
     if (lane == 0) out[qi] = -1;
     return;
   }
-  const uint4 ra = vrec[2 * (int64_t)a], ra2 = vrec[2 * (int64_t)a + 1];
-  const uint4 rb = vrec[2 * (int64_t)b], rb2 = vrec[2 * (int64_t)b + 1];
+  uint4 ra = vrec[2 * (int64_t)a], ra2 = vrec[2 * (int64_t)a + 1];
+  uint4 rb = vrec[2 * (int64_t)b], rb2 = vrec[2 * (int64_t)b + 1];
+  const u32* blk;
+  if (H) {
+    // two-level store keeps group pairs S1 <= S2 only; dist is symmetric, so
+    // swap the endpoints when needed
+    if (ra2.z > rb2.z) {
+      const uint4 t = ra, t2 = ra2;
+      ra = rb; ra2 = rb2; rb = t; rb2 = t2;
+    }
+    blk = H + pairbase[(int64_t)ra2.z * ngroups + rb2.z] + (int64_t)ra2.w * gV[rb2.z] +
+          (int64_t)ra2.y * rb2.w;
+    ldbg = rb2.y;
+  } else {
+    blk = BG + (int64_t)ra2.x * ldbg + rb2.x;
+  }
   const u32* row1 = M + ((uint64_t)ra.x | ((uint64_t)ra.y << 32));
   const u32* row2 = M + ((uint64_t)rb.x | ((uint64_t)rb.y << 32));
   const int32_t nb1 = (int32_t)ra2.y, nb2 = (int32_t)rb2.y;
-  const u32* blk = BG + (int64_t)ra2.x * ldbg + rb2.x;
   const int W = nb2 <= 32 ? 32 : 64;  // lanes per group
   const int G = 64 / W;               // groups, each takes b1 = g (mod G)
   const int g = lane / W, jj = lane % W;
@@ -487,7 +512,8 @@ hipError_t launch_renumber(const PartArgs& a, hipStream_t s) {
   k_members<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.part, a.flag, a.off, a.fill, a.members);
   k_rank<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.k, a.members, a.off, a.nb, a.bgoff, a.comp, a.local,
                                          a.bgcomp, a.bglocal);
-  k_vrec<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.comp, a.local, a.moff, a.P, a.bgoff, a.nb, a.vrec);
+  k_vrec<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.comp, a.local, a.moff, a.P, a.bgoff, a.nb, a.grp,
+                                         a.gbg0, a.vrec);
   LAUNCH_CHECK();
 }
 
@@ -524,16 +550,18 @@ hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s) {
 #endif
 
 template <int T>
-static hipError_t fw_rounds(u32* A, int64_t ld, int nt, hipStream_t s, hipEvent_t* ev) {
+static hipError_t fw_rounds(u32* A, int64_t ld, int nt, int batch, int64_t gstride, hipStream_t s,
+                           hipEvent_t* ev) {
   for (int r = 0; r < nt; r++) {
-    k_fw_diag<T><<<1, 256, 0, s>>>(A, ld, r);
+    k_fw_diag<T><<<dim3(1, batch), 256, 0, s>>>(A, ld, r, gstride);
     if (nt > 1) {
-      k_fw_panel<T><<<nt - 1, 256, 0, s>>>(A, ld, r);
+      k_fw_panel<T><<<dim3(nt - 1, batch), 256, 0, s>>>(A, ld, r, gstride);
       if (ev) {
         hipError_t e = hipEventRecord(ev[2 * r], s);
         if (e != hipSuccess) return e;
       }
-      k_fw_inner<T, SPQ_INNER_KC><<<(unsigned)((nt - 1) * nt / 2), 256, 0, s>>>(A, ld, r, nt);
+      k_fw_inner<T, SPQ_INNER_KC><<<dim3((unsigned)((nt - 1) * nt / 2), batch), 256, 0, s>>>(
+          A, ld, r, nt, gstride);
       if (ev) {
         hipError_t e = hipEventRecord(ev[2 * r + 1], s);
         if (e != hipSuccess) return e;
@@ -544,9 +572,14 @@ static hipError_t fw_rounds(u32* A, int64_t ld, int nt, hipStream_t s, hipEvent_
 }
 
 hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev) {
-  if (nt <= 0) return hipSuccess;
-  if (tile == 64) return fw_rounds<64>(A, ld, nt, s, ev);
-  return fw_rounds<128>(A, ld, nt, s, ev);
+  return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev);
+}
+
+hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
+                                 hipStream_t s, hipEvent_t* ev) {
+  if (nt <= 0 || batch <= 0) return hipSuccess;
+  if (tile == 64) return fw_rounds<64>(A, ld, nt, batch, gstride, s, ev);
+  return fw_rounds<128>(A, ld, nt, batch, gstride, s, ev);
 }
 
 double dense_fw_exec_relax(int64_t nt, int tile) {
@@ -557,7 +590,8 @@ double dense_fw_exec_relax(int64_t nt, int tile) {
 hipError_t launch_query(const QueryArgs& a, hipStream_t s) {
   if (a.q <= 0) return hipSuccess;
   int64_t blocks = (a.q + 3) / 4;
-  k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.vrec, a.M, a.BG, a.ldbg);
+  k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.vrec, a.M, a.BG, a.ldbg,
+                                           a.H, a.pairbase, a.gV, a.ngroups);
   LAUNCH_CHECK();
 }
 

@@ -31,6 +31,7 @@ struct PartArgs {
   int32_t *bgcomp, *bglocal;  // [V]
   const int64_t* moff;        // [k] first element of each APSP(C)
   const int32_t* P;           // [k] padded side of each APSP(C)
+  const int32_t *grp, *gbg0;  // [k] group of each component, [groups] its first BG id
   uint4* vrec;                // [2n] per-vertex query records
 };
 
@@ -59,7 +60,32 @@ struct QueryArgs {
   const uint4* vrec;
   const u32 *M, *BG;
   int64_t ldbg;
+  // two-level store (H != nullptr): pair offsets and group sizes
+  const u32* H;
+  const int64_t* pairbase;
+  const int32_t* gV;
+  int32_t ngroups;
 };
+
+// Two-level BG (hier.hip).
+struct HierArgs {
+  int32_t V, ngroups, Vgp, m2pmax, V2;
+  int64_t m, V2p;
+  const int32_t *eu, *ev, *w, *comp, *local, *bgoff, *nb, *bgcomp, *bglocal, *P;
+  const int64_t* moff;
+  const u32* M;
+  const int32_t *grp, *gbg0, *gV;  // [k], [ngroups], [ngroups]
+  int32_t *bgrow, *bgnb, *bggrp;   // [V]
+  u32* Mg;                         // ngroups x Vgp x Vgp
+  uint8_t* flag2;                  // [V]
+  int32_t *b2list, *b2rank, *m2;   // ngroups x Vgp, [V], [ngroups]
+  const int32_t* b2off;            // [ngroups+1]
+  u32 *R, *XT, *BG2, *H;
+  const int64_t* pairbase;         // ngroups x ngroups
+};
+hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
+hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s);
+hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s);
 
 hipError_t launch_partition_scan(const PartArgs& a, hipStream_t s);
 hipError_t launch_renumber(const PartArgs& a, hipStream_t s);
@@ -69,6 +95,9 @@ hipError_t launch_comp_fw(int32_t count, const int32_t* order, const int32_t* P,
 hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s);
 // ev: NULL, or 2*nt events recorded around each interior-tile launch
 hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev);
+// `batch` matrices of the same shape, gstride elements apart
+hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
+                                 hipStream_t s, hipEvent_t* ev);
 // relaxations executed by launch_dense_fw (diagonal, panel and upper-triangle
 // interior tiles of every round)
 double dense_fw_exec_relax(int64_t nt, int tile);

@@ -43,3 +43,22 @@ def test_python_binding_rejects_host_tensors():
     x = torch.zeros(4, dtype=torch.int32)
     with pytest.raises(TypeError):
         spq.build_index(4, x, x, x, x, 1)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of spq_build_opts and spq_stats match the C header."""
+    import subprocess
+    fields = [f for f, _ in spq.Stats._fields_]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "spq.h"', "int main(void) {",
+           'printf("%zu %zu\\n", sizeof(spq_build_opts), sizeof(spq_stats));']
+    src += ['printf("%%zu\\n", offsetof(spq_stats, %s));' % f for f in fields]
+    src += ["return 0; }"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", str(spq.HEADER.rsplit("/", 1)[0]), str(c), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    assert int(out[0]) == ctypes.sizeof(spq.BuildOpts)
+    assert int(out[1]) == ctypes.sizeof(spq.Stats)
+    for f, off in zip(fields, out[2:]):
+        assert int(off) == getattr(spq.Stats, f).offset, f

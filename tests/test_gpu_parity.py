@@ -332,3 +332,46 @@ def test_build_errors():
     # the index still builds after errors
     idx = build(g)
     assert spq.index_stats(idx)["v_bg"] == 348
+
+
+# ------------------------------------------------------ two-level BG method
+TWO_LEVEL = [c for c in CASES if c["k"] >= 1]
+
+
+@pytest.mark.parametrize("g", TWO_LEVEL, ids=[c["name"] for c in TWO_LEVEL])
+def test_two_level_small_graphs_all_pairs(g):
+    for gc in sorted({1, 2, max(1, g["k"] // 2)}):
+        idx = build(g, bg_method=2, group_comps=gc)
+        st = spq.index_stats(idx)
+        assert st["bg_method"] == 2 and st["ngroups"] == -(-g["k"] // gc)
+        lay = spq.index_layout(idx)
+        check_layout(g, lay)
+        check_components(g, idx, lay)
+        check_bg_rows(g, idx, lay, np.arange(st["v_bg"]))
+        v1, v2 = all_pairs(g["n"])
+        check_queries(g, idx, v1, v2)
+
+
+@pytest.mark.parametrize("gc", [1, 2, 3, 4, 8, 16])
+def test_grid32_two_level_equals_flat(gc):
+    g = W.grid32()
+    flat = build(g, bg_method=1)
+    two = build(g, bg_method=2, group_comps=gc)
+    assert np.array_equal(spq.index_bg_rows(flat, 0, 348, 348), spq.index_bg_rows(two, 0, 348, 348))
+    v1, v2 = all_pairs(g["n"])
+    assert np.array_equal(run_queries(flat, v1, v2), run_queries(two, v1, v2))
+
+
+def test_grid256d_two_level_equals_flat():
+    g = W.grid256d()
+    flat = build(g, bg_method=1)
+    qf = run_queries(flat, g["v1"], g["v2"])
+    rows = np.random.default_rng(8).integers(0, 27_900, 40)
+    rf = [spq.index_bg_rows(flat, int(r), 1, 27_900) for r in rows]
+    flat.free()
+    two = build(g, bg_method=2, group_comps=32)
+    st = spq.index_stats(two)
+    assert st["ngroups"] == 32 and st["v_bg2"] > 0
+    assert np.array_equal(run_queries(two, g["v1"], g["v2"]), qf)
+    for r, want in zip(rows, rf):
+        assert np.array_equal(spq.index_bg_rows(two, int(r), 1, 27_900), want)
