@@ -68,6 +68,11 @@ struct spq_index {
   uint8_t* flag2 = nullptr;
   u32 *Mg = nullptr, *R = nullptr, *XT = nullptr, *BG2 = nullptr, *H = nullptr;
   int64_t* pairbase = nullptr;
+  // exactness certificate (total weight >= INF)
+  bool certify = false;
+  int32_t *bgvert = nullptr, *label = nullptr, *bglabel = nullptr;
+  u32* cert = nullptr;  // [4]: changed, bad, max APSP(C), max BG
+  u32 cert_mc = 0, cert_mbg = 0;
   hipEvent_t ev[5] = {};
   bool events = false;
   std::vector<hipEvent_t> prof;  // pairs around the BG interior-tile launches
@@ -83,11 +88,51 @@ struct spq_index {
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
                     vrec, grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
-                    b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase};
+                    b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
+                    bgvert, label, bglabel, cert};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
 };
+
+// Runs the exactness certificate when the build asked for it (total edge
+// weight >= SPQ_INF): connected components of G, then the checks of
+// range.hip.  Synchronous.
+static spq_status certify(spq_index* X, int64_t m, const int32_t* eu, const int32_t* ev,
+                          hipStream_t s) {
+  if (!X->certify) return SPQ_OK;
+  const int32_t n = X->n;
+  HIP_TRY(dalloc(&X->label, n));
+  HIP_TRY(dalloc(&X->bglabel, X->V));
+  HIP_TRY(dalloc(&X->cert, 4));
+  HIP_TRY(spq::launch_cc_init(n, X->label, s));
+  u32 h[4] = {1, 0, 0, 0};
+  int rounds = 0;
+  while (h[0]) {
+    if (++rounds > 256) return fail(SPQ_ERANGE, "connected components did not settle");
+    HIP_TRY(hipMemsetAsync(X->cert, 0, sizeof(u32), s));
+    HIP_TRY(spq::launch_cc_round(m, eu, ev, n, X->label, X->cert, s));
+    HIP_TRY(hipMemcpyAsync(h, X->cert, sizeof(u32), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  HIP_TRY(hipMemsetAsync(X->cert, 0, 4 * sizeof(u32), s));
+  spq::CertArgs c{};
+  c.V = X->V; c.ngroups = X->ngroups; c.Vgp = X->Vgp; c.Vp = X->Vp; c.comp_elems = X->comp_elems;
+  c.M = X->M; c.BG = X->BG; c.H = X->method == 2 ? X->H : nullptr; c.bgvert = X->bgvert;
+  c.label = X->label; c.gV = X->gV; c.gbg0 = X->gbg0; c.bgrow = X->bgrow; c.bgnb = X->bgnb;
+  c.bglocal = X->bglocal; c.pairbase = X->pairbase; c.bglabel = X->bglabel;
+  c.bad = X->cert + 1; c.mc = X->cert + 2; c.mbg = X->cert + 3;
+  HIP_TRY(spq::launch_certificate(c, s));
+  HIP_TRY(hipMemcpyAsync(h, X->cert, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h[1]) return fail(SPQ_ERANGE, "a BG distance between connected vertices reaches SPQ_INF");
+  if (2ull * h[2] + h[3] >= (unsigned long long)SPQ_INF)
+    return fail(SPQ_ERANGE, "query sums could reach SPQ_INF (max APSP(C) " + std::to_string(h[2]) +
+                                ", max BG " + std::to_string(h[3]) + ")");
+  X->cert_mc = h[2];
+  X->cert_mbg = h[3];
+  return SPQ_OK;
+}
 
 extern "C" {
 
@@ -182,10 +227,15 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   for (int32_t c = 0; c < k; c++)
     if (X->h_cnt[c] == 0) return guard(fail(SPQ_EINVAL, "component " + std::to_string(c) + " is empty"));
   // Every finite distance is at most the total edge weight, so below SPQ_INF
-  // all sums stay exact.
-  if (htotal >= (unsigned long long)SPQ_INF)
-    return guard(fail(SPQ_ERANGE, "total edge weight " + std::to_string(htotal) +
-                                      " reaches SPQ_INF; distances might not fit in int32"));
+  // all sums stay exact.  Otherwise the build certifies its result (range.hip),
+  // which needs every component's own weight below SPQ_INF.
+  if (htotal >= (unsigned long long)SPQ_INF) {
+    X->certify = true;
+    for (int32_t c = 0; c < k; c++)
+      if (X->h_sumc[c] >= (unsigned long long)SPQ_INF)
+        return guard(fail(SPQ_ERANGE, "edge weights inside component " + std::to_string(c) +
+                                          " reach SPQ_INF; distances might not fit in int32"));
+  }
 
   X->h_off.assign(k + 1, 0);
   X->h_bgoff.assign(k + 1, 0);
@@ -256,6 +306,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   TRY(dalloc(&X->moff, k));
   TRY(dalloc(&X->bgcomp, X->V));
   TRY(dalloc(&X->bglocal, X->V));
+  TRY(dalloc(&X->bgvert, X->V));
   TRY(dalloc(&X->fill, k));
   TRY(dalloc(&X->members, n));
   TRY(dalloc(&X->vrec, 2 * (int64_t)n));
@@ -278,6 +329,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   pa.off = X->off; pa.bgoff = X->bgoff; pa.fill = X->fill; pa.members = X->members;
   pa.comp = X->comp; pa.local = X->local; pa.bgcomp = X->bgcomp; pa.bglocal = X->bglocal;
   pa.moff = X->moff; pa.P = X->P; pa.vrec = X->vrec; pa.grp = X->grp; pa.gbg0 = X->gbg0;
+  pa.bgvert = X->bgvert;
   TRY(spq::launch_renumber(pa, s));
   TRY(hipEventRecord(X->ev[1], s));
 
@@ -355,6 +407,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
     TRY(spq::launch_hier_level2(ha, s));
     TRY(hipEventRecord(X->ev[4], s));
+    spq_status cs = certify(X, m, eu, ev, s);
+    if (cs != SPQ_OK) return guard(cs);
     *out = X;
     return SPQ_OK;
   }
@@ -373,6 +427,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
                            X->prof.empty() ? nullptr : X->prof.data()));
   TRY(hipEventRecord(X->ev[4], s));
 #undef TRY
+  spq_status cs = certify(X, m, eu, ev, s);
+  if (cs != SPQ_OK) return guard(cs);
   *out = X;
   return SPQ_OK;
 }

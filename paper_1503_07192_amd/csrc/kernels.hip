@@ -86,7 +86,7 @@ __global__ void k_rank(int32_t n, int32_t k, const u32* __restrict__ members,
                        const int32_t* __restrict__ off, const int32_t* __restrict__ nb,
                        const int32_t* __restrict__ bgoff, int32_t* __restrict__ comp,
                        int32_t* __restrict__ local, int32_t* __restrict__ bgcomp,
-                       int32_t* __restrict__ bglocal) {
+                       int32_t* __restrict__ bglocal, int32_t* __restrict__ bgvert) {
   int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pos >= n) return;
   // component of this position: largest c with off[c] <= pos
@@ -109,6 +109,7 @@ __global__ void k_rank(int32_t n, int32_t k, const u32* __restrict__ members,
   if (f) {
     bgcomp[bgoff[c] + l] = c;
     bglocal[bgoff[c] + l] = l;
+    bgvert[bgoff[c] + l] = (int32_t)id;
   }
 }
 
@@ -511,7 +512,7 @@ hipError_t launch_partition_scan(const PartArgs& a, hipStream_t s) {
 hipError_t launch_renumber(const PartArgs& a, hipStream_t s) {
   k_members<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.part, a.flag, a.off, a.fill, a.members);
   k_rank<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.k, a.members, a.off, a.nb, a.bgoff, a.comp, a.local,
-                                         a.bgcomp, a.bglocal);
+                                         a.bgcomp, a.bglocal, a.bgvert);
   k_vrec<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.comp, a.local, a.moff, a.P, a.bgoff, a.nb, a.grp,
                                          a.gbg0, a.vrec);
   LAUNCH_CHECK();

@@ -29,6 +29,7 @@ struct PartArgs {
   u32* members;               // [n] scratch
   int32_t *comp, *local;      // [n]
   int32_t *bgcomp, *bglocal;  // [V]
+  int32_t* bgvert;            // [V] vertex of each BG id
   const int64_t* moff;        // [k] first element of each APSP(C)
   const int32_t* P;           // [k] padded side of each APSP(C)
   const int32_t *grp, *gbg0;  // [k] group of each component, [groups] its first BG id
@@ -86,6 +87,21 @@ struct HierArgs {
 hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
 hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s);
 hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s);
+
+// Exactness certificate (range.hip).
+struct CertArgs {
+  int32_t V, ngroups, Vgp;
+  int64_t Vp, comp_elems;
+  const u32 *M, *BG, *H;
+  const int32_t *bgvert, *label, *gV, *gbg0, *bgrow, *bgnb, *bglocal;
+  const int64_t* pairbase;
+  int32_t* bglabel;
+  u32 *bad, *mc, *mbg;
+};
+hipError_t launch_cc_init(int32_t n, int32_t* label, hipStream_t s);
+hipError_t launch_cc_round(int64_t m, const int32_t* eu, const int32_t* ev, int32_t n, int32_t* label,
+                           u32* changed, hipStream_t s);
+hipError_t launch_certificate(const CertArgs& a, hipStream_t s);
 
 hipError_t launch_partition_scan(const PartArgs& a, hipStream_t s);
 hipError_t launch_renumber(const PartArgs& a, hipStream_t s);

@@ -375,3 +375,84 @@ def test_grid256d_two_level_equals_flat():
     assert np.array_equal(run_queries(two, g["v1"], g["v2"]), qf)
     for r, want in zip(rows, rf):
         assert np.array_equal(spq.index_bg_rows(two, int(r), 1, 27_900), want)
+
+
+# ------------------------------------------------ exactness certificate
+def _path(n, wt, breaks, offset=0):
+    eu = np.arange(offset, offset + n - 1, dtype=np.int32)
+    return eu, eu + 1, np.full(n - 1, wt, np.int32)
+
+
+@pytest.mark.parametrize("method", [1, 2])
+def test_certificate_accepts_large_total_weight(method):
+    # two disjoint 4-vertex paths, weights 5e8: total 3e9 >= INF, every
+    # distance <= 1.5e9 < INF
+    a = _path(4, 500_000_000, None, 0)
+    b = _path(4, 500_000_000, None, 4)
+    g = dict(name="bigpaths", n=8, eu=np.concatenate([a[0], b[0]]), ev=np.concatenate([a[1], b[1]]),
+             w=np.concatenate([a[2], b[2]]), part=np.array([0, 0, 1, 1, 2, 2, 3, 3], np.int32), k=4)
+    idx = build(g, bg_method=method, group_comps=2)
+    lay = spq.index_layout(idx)
+    check_components(g, idx, lay)
+    check_bg_rows(g, idx, lay, np.arange(spq.index_stats(idx)["v_bg"]))
+    v1, v2 = all_pairs(8)
+    check_queries(g, idx, v1, v2)
+
+
+@pytest.mark.parametrize("n", [5, 7, 9])
+@pytest.mark.parametrize("method", [1, 2])
+def test_certificate_rejects_unrepresentable_distance(n, method):
+    # a path whose end-to-end distance (>= 2.4e9) does not fit below INF
+    eu, ev, w = _path(n, 600_000_000, None)
+    part = (np.minimum(np.arange(n) // 2, 2) if n < 9 else np.minimum(np.arange(n) // 2, 4)).astype(np.int32)
+    g = dict(name="longpath", n=n, eu=eu, ev=ev, w=w, part=part, k=int(part.max()) + 1)
+    with pytest.raises(spq.SpqError) as ei:
+        build(g, bg_method=method, group_comps=1)
+    assert ei.value.name == "SPQ_ERANGE"
+
+
+# ------------------------------------------- Delaunay, 1M points, 4,096 parts
+def check_layout_fast(g, lay, flag):
+    """check_layout, vectorized for large graphs."""
+    comp, local = lay["comp"], lay["local"]
+    assert np.array_equal(comp, g["part"])
+    order = np.lexsort((local, comp))
+    c_sorted, l_sorted = comp[order], local[order]
+    starts = lay["off"][:-1]
+    assert np.array_equal(np.bincount(comp, minlength=g["k"]), np.diff(lay["off"]))
+    assert np.array_equal(l_sorted, np.arange(g["n"]) - starts[c_sorted])
+    assert np.array_equal(np.bincount(comp[flag], minlength=g["k"]), lay["nb"])
+    isb = l_sorted < lay["nb"][c_sorted]
+    assert np.array_equal(flag[order], isb)
+    # ascending ids inside each (component, boundary flag) run
+    key = c_sorted.astype(np.int64) * 2 + (~isb)
+    same = key[1:] == key[:-1]
+    assert (order[1:][same] > order[:-1][same]).all()
+
+
+def test_delaunay1m_two_level():
+    g = W.delaunay1m()
+    print("delaunay1m: n=%d m=%d k=%d" % (g["n"], g["m"], g["k"]), flush=True)
+    idx = build(g)
+    st = spq.index_stats(idx)
+    print({k: st[k] for k in ("v_bg", "bg_method", "ngroups", "v_bg2", "max_comp", "max_boundary",
+                              "bg_bytes", "ms_components", "ms_bg_apsp")}, flush=True)
+    assert st["bg_method"] == 2 and st["ngroups"] == 64
+    lay = spq.index_layout(idx)
+    flag = oracle.boundary(g["n"], g["eu"], g["ev"], g["part"])
+    assert st["v_bg"] == int(flag.sum())
+    check_layout_fast(g, lay, flag)
+    rng = np.random.default_rng(31)
+    comps = np.concatenate([[0, g["k"] - 1], rng.choice(g["k"], 40, replace=False)])
+    comps = np.concatenate([comps, [int(np.argmax(np.bincount(g["part"])))]])
+    check_components(g, idx, lay, np.unique(comps))
+    check_bg_rows(g, idx, lay, np.concatenate([[0, st["v_bg"] - 1], rng.integers(0, st["v_bg"], 30)]))
+    # source-grouped query sample: 100 sources x 20 targets, plus same-vertex pairs
+    src = rng.integers(0, g["n"], 100).astype(np.int32)
+    v1 = np.repeat(src, 20)
+    v2 = rng.integers(0, g["n"], v1.size).astype(np.int32)
+    v2[::20] = v1[::20]
+    got = run_queries(idx, v1, v2)
+    D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], src)
+    want = clamp32(D[np.repeat(np.arange(100), 20), v2])
+    assert np.array_equal(got, want)
