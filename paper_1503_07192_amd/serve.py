@@ -1,0 +1,320 @@
+"""Continuous-batching query server on a resident index.
+
+Requests (batches of query pairs) arrive over time.  The scheduler keeps a
+FIFO admission queue and a fixed set of slots; each slot is one HIP stream
+with its own pinned staging buffers and device buffers.  Whenever a slot is
+free, the requests at the head of the queue are coalesced into one launch of
+``spq_query_batch`` on that slot, as many as fit in the slot's pair capacity
+and in the device memory budget (memory-based admission).  Several slots are
+in flight at once, so requests that arrive while others run are admitted as
+soon as a slot and memory free up, and their work overlaps on the device.
+Completion is detected by polling each slot's event; a request's latency is
+its completion time minus its arrival time.
+
+The paper answers queries one at a time and lists parallel queries as future
+work (Section 5, Conclusion); ``OneAtATime`` is that mode, kept as the
+comparator.  The scheduling logic only talks to an executor
+(``submit / done / result``), so it is tested on the CPU with a fake one.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BYTES_PER_PAIR = 12  # v1, v2, out as int32
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds since the stream start
+    v1: np.ndarray
+    v2: np.ndarray
+    result: np.ndarray | None = None
+    done_at: float | None = None
+    launches: list = field(default_factory=list)
+
+    @property
+    def size(self):
+        return len(self.v1)
+
+
+def poisson_stream(rng, rate_pairs: float, nreq: int, n: int, max_log2: float = 16.0,
+                   lo: int = 0, hi: int | None = None):
+    """Open-loop arrivals: batch sizes floor(2**U(0, max_log2)) (1 .. 65,536),
+    uniform random pairs, exponential gaps at rate_pairs / E[batch] requests/s."""
+    hi = n if hi is None else hi
+    sizes = np.floor(2.0 ** rng.uniform(0.0, max_log2, nreq)).astype(np.int64)
+    mean_b = (2.0 ** max_log2 - 1.0) / (max_log2 * np.log(2.0))  # E[2^U]
+    gaps = rng.exponential(mean_b / rate_pairs, nreq)
+    t = np.cumsum(gaps) - gaps[0]
+    reqs = []
+    for i in range(nreq):
+        b = int(sizes[i])
+        v1 = rng.integers(lo, hi, b).astype(np.int32)
+        v2 = rng.integers(0, n, b).astype(np.int32)
+        reqs.append(Request(i, float(t[i]), v1, v2))
+    return reqs
+
+
+class Scheduler:
+    """Admission, coalescing and completion on top of an executor."""
+
+    def __init__(self, executor, slots: int, slot_pairs: int, mem_budget: int):
+        if slots < 1 or slot_pairs < 1:
+            raise ValueError("need at least one slot of at least one pair")
+        self.ex = executor
+        self.nslots = slots
+        self.slot_pairs = slot_pairs
+        self.mem_budget = mem_budget
+        self.mem_used = 0
+        self.free = list(range(slots))
+        self.inflight = {}  # slot -> (handle, [(req, lo, hi)], bytes)
+        self.queue = collections.deque()
+        self.launches = 0
+        self.launch_sizes = []
+
+    def enqueue(self, req: Request):
+        if req.size > self.slot_pairs or req.size * BYTES_PER_PAIR > self.mem_budget:
+            raise ValueError("request %d (%d pairs) exceeds a slot or the memory budget"
+                             % (req.rid, req.size))
+        req.result = np.empty(req.size, np.int32)
+        req._issued = 0   # pairs handed to launches
+        req._filled = 0   # pairs whose results came back
+        if req.size == 0:
+            req.done_at = req.arrival
+            return
+        self.queue.append(req)
+
+    def _admit_one(self):
+        """Coalesces queue-head requests into one launch on a free slot.  A
+        request is cut only when the memory left cannot hold it whole."""
+        if not self.free or not self.queue:
+            return False
+        room = min(self.slot_pairs, (self.mem_budget - self.mem_used) // BYTES_PER_PAIR)
+        if room <= 0:
+            return False
+        parts, take = [], 0
+        while self.queue and take < room:
+            req = self.queue[0]
+            left = req.size - req._issued
+            if take > 0 and left > room - take:
+                break
+            cnt = min(left, room - take)
+            parts.append((req, req._issued, req._issued + cnt))
+            req._issued += cnt
+            take += cnt
+            if req._issued == req.size:
+                self.queue.popleft()
+            else:
+                break
+        slot = self.free.pop()
+        v1 = np.concatenate([r.v1[l:h] for r, l, h in parts])
+        v2 = np.concatenate([r.v2[l:h] for r, l, h in parts])
+        handle = self.ex.submit(slot, v1, v2)
+        nbytes = take * BYTES_PER_PAIR
+        self.mem_used += nbytes
+        self.inflight[slot] = (handle, parts, nbytes)
+        self.launches += 1
+        self.launch_sizes.append(take)
+        for r, l, h in parts:
+            r.launches.append(self.launches)
+        return True
+
+    def admit(self):
+        n = 0
+        while self._admit_one():
+            n += 1
+        return n
+
+    def complete(self, now_fn):
+        """Collects finished slots; returns the requests completed."""
+        finished = []
+        for slot in list(self.inflight):
+            handle, parts, nbytes = self.inflight[slot]
+            if not self.ex.done(handle):
+                continue
+            out = self.ex.result(handle)
+            t = now_fn()
+            pos = 0
+            for r, l, h in parts:
+                r.result[l:h] = out[pos:pos + (h - l)]
+                pos += h - l
+                r._filled += h - l
+                if r._filled == r.size:
+                    r.done_at = t
+                    finished.append(r)
+            del self.inflight[slot]
+            self.mem_used -= nbytes
+            self.free.append(slot)
+        return finished
+
+    def busy(self):
+        return bool(self.inflight) or bool(self.queue)
+
+
+def run_stream(sched: Scheduler, reqs, clock=None, spin=True):
+    """Replays the arrival times in real time (or on the given clock)."""
+    clock = clock or time.perf_counter
+    t0 = clock()
+    now = lambda: clock() - t0
+    i, done = 0, []
+    while i < len(reqs) or sched.busy():
+        t = now()
+        while i < len(reqs) and reqs[i].arrival <= t:
+            sched.enqueue(reqs[i])
+            i += 1
+        done += sched.complete(now)
+        sched.admit()
+        if not spin and i < len(reqs) and not sched.busy():
+            time.sleep(max(0.0, reqs[i].arrival - now()))
+    return done
+
+
+def summarize(reqs, sched=None):
+    lat = np.array([r.done_at - r.arrival for r in reqs])
+    pairs = sum(r.size for r in reqs)
+    span = max(r.done_at for r in reqs) - min(r.arrival for r in reqs)
+    out = {"requests": len(reqs), "pairs": int(pairs), "span_s": span,
+           "queries_per_s": pairs / span if span > 0 else float("inf"),
+           "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+           "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+           "latency_ms_mean": float(lat.mean() * 1e3)}
+    if sched is not None:
+        out["launches"] = sched.launches
+        out["pairs_per_launch"] = float(np.mean(sched.launch_sizes)) if sched.launch_sizes else 0.0
+    return out
+
+
+# ------------------------------------------------------------- executors
+class GpuExecutor:
+    """One HIP stream per slot, pinned host staging, device in/out buffers."""
+
+    def __init__(self, index, slots: int, slot_pairs: int):
+        import torch
+        from . import spq
+        self.torch, self.spq, self.index = torch, spq, index
+        self.cap = slot_pairs
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]  # default priority
+        self.h_in = [torch.empty(2 * slot_pairs, dtype=torch.int32, pin_memory=True)
+                     for _ in range(slots)]
+        self.h_out = [torch.empty(slot_pairs, dtype=torch.int32, pin_memory=True)
+                      for _ in range(slots)]
+        self.d_in = [torch.empty(2 * slot_pairs, dtype=torch.int32, device="cuda")
+                     for _ in range(slots)]
+        self.d_out = [torch.empty(slot_pairs, dtype=torch.int32, device="cuda")
+                      for _ in range(slots)]
+        self.events = [torch.cuda.Event() for _ in range(slots)]
+
+    def submit(self, slot, v1, v2):
+        torch, q, cap = self.torch, len(v1), self.cap
+        hin = self.h_in[slot].numpy()
+        hin[:q] = v1
+        hin[cap:cap + q] = v2
+        s = self.streams[slot]
+        with torch.cuda.stream(s):
+            din, dout = self.d_in[slot], self.d_out[slot]
+            din[:q].copy_(self.h_in[slot][:q], non_blocking=True)
+            din[cap:cap + q].copy_(self.h_in[slot][cap:cap + q], non_blocking=True)
+            self.spq.query_batch(self.index, din[:q], din[cap:cap + q], dout[:q], stream=s)
+            self.h_out[slot][:q].copy_(dout[:q], non_blocking=True)
+            self.events[slot].record(s)
+        return (slot, q)
+
+    def done(self, handle):
+        return self.events[handle[0]].query()
+
+    def result(self, handle):
+        slot, q = handle
+        return self.h_out[slot][:q].numpy().copy()
+
+
+class OneAtATime:
+    """The paper's mode: every pair is its own launch, one after another."""
+
+    def __init__(self, index):
+        import torch
+        from . import spq
+        self.torch, self.spq, self.index = torch, spq, index
+        self.h = torch.empty(3, dtype=torch.int32, pin_memory=True)
+        self.d = torch.empty(3, dtype=torch.int32, device="cuda")
+
+    def run(self, reqs, clock=time.perf_counter):
+        torch = self.torch
+        s = torch.cuda.current_stream()
+        t0 = clock()
+        for r in reqs:
+            while clock() - t0 < r.arrival:
+                pass
+            r.result = np.empty(r.size, np.int32)
+            for i in range(r.size):
+                self.h[0], self.h[1] = int(r.v1[i]), int(r.v2[i])
+                self.d.copy_(self.h, non_blocking=True)
+                self.spq.query_batch(self.index, self.d[0:1], self.d[1:2], self.d[2:3], stream=s)
+                self.h.copy_(self.d, non_blocking=True)
+                s.synchronize()
+                r.result[i] = int(self.h[2])
+            r.done_at = clock() - t0
+        return reqs
+
+
+# ------------------------------------------------------------------ main
+def main(argv=None):
+    """Serving measurement on the Delaunay index (1M points, 4,096 parts)."""
+    import argparse
+    import json
+    import torch
+    from . import spq, workloads as W
+
+    p = argparse.ArgumentParser()
+    p.add_argument("--rates", default="1e5,1e6,1e7")
+    p.add_argument("--requests", type=int, default=2000)
+    p.add_argument("--low-rate-requests", type=int, default=300,
+                   help="requests at rates below 1e6 pairs/s (their arrivals are slow)")
+    p.add_argument("--slots", type=int, default=4)
+    p.add_argument("--slot-pairs", type=int, default=65536)
+    p.add_argument("--mem-mib", type=float, default=64.0)
+    p.add_argument("--one-at-a-time-requests", type=int, default=20)
+    p.add_argument("--workload", default="delaunay1m", choices=["delaunay1m", "grid256d"])
+    args = p.parse_args(argv)
+    torch.cuda.set_device(0)
+    g = W.delaunay1m() if args.workload == "delaunay1m" else W.grid256d(queries=0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+    idx = spq.build_index(g["n"], dev(g["eu"]), dev(g["ev"]), dev(g["w"]), dev(g["part"]), g["k"])
+    torch.cuda.synchronize()
+    st = spq.index_stats(idx)
+    print("index built: n=%d V_BG=%d method=%d groups=%d bg_bytes=%.1f GB" % (
+        g["n"], st["v_bg"], st["bg_method"], st["ngroups"], st["bg_bytes"] / 1e9), flush=True)
+    rng = np.random.default_rng(W.SEED_BASE + 5)
+    report = {"workload": args.workload, "n": g["n"], "k": g["k"], "v_bg": st["v_bg"],
+              "slots": args.slots, "slot_pairs": args.slot_pairs, "mem_mib": args.mem_mib,
+              "rates": {}}
+    ex = GpuExecutor(idx, args.slots, args.slot_pairs)
+    for rate in [float(x) for x in args.rates.split(",")]:
+        nreq = args.requests if rate >= 1e6 else args.low_rate_requests
+        reqs = poisson_stream(rng, rate, nreq, g["n"])
+        sched = Scheduler(ex, args.slots, args.slot_pairs, int(args.mem_mib * 2**20))
+        done = run_stream(sched, reqs)
+        res = summarize(done, sched)
+        # each request alone must give the same answers as inside the mix
+        same = 0
+        for r in reqs:
+            alone = spq.query_batch(idx, dev(r.v1), dev(r.v2)).cpu().numpy()
+            same += int(np.array_equal(alone, r.result))
+        res["alone_equals_mix"] = "%d/%d" % (same, len(reqs))
+        res["offered_pairs_per_s"] = rate
+        report["rates"]["%g" % rate] = res
+        print(json.dumps({"rate": rate, **res}), flush=True)
+    one = poisson_stream(rng, 1e5, args.one_at_a_time_requests, g["n"], max_log2=10.0)
+    OneAtATime(idx).run(one)
+    report["one_at_a_time"] = summarize(one)
+    report["one_at_a_time"]["batch_sizes"] = "floor(2^U(0,10)) at 1e5 pairs/s offered"
+    print(json.dumps({"one_at_a_time": report["one_at_a_time"]}), flush=True)
+    print(json.dumps(report), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,120 @@
+"""The serving scheduler on the CPU with a fake executor: results, admission
+by memory and slots, coalescing, splitting, and the arrival generator."""
+import numpy as np
+import pytest
+
+from paper_1503_07192_amd import serve
+
+
+class FakeClock:
+    def __init__(self, dt=1e-4):
+        self.t, self.dt = 0.0, dt
+
+    def __call__(self):
+        self.t += self.dt
+        return self.t
+
+
+class FakeExecutor:
+    """Answers f(v1, v2) = 7*v1 + v2 after a delay proportional to the size."""
+
+    def __init__(self, clock, slots, per_pair=1e-6, fixed=5e-4):
+        self.clock, self.per_pair, self.fixed = clock, per_pair, fixed
+        self.active = set()
+        self.max_active = 0
+        self.sched = None
+        self.max_mem = 0
+
+    def submit(self, slot, v1, v2):
+        assert slot not in self.active
+        self.active.add(slot)
+        self.max_active = max(self.max_active, len(self.active))
+        if self.sched is not None:
+            self.max_mem = max(self.max_mem, self.sched.mem_used + 12 * len(v1))
+        ready = self.clock.t + self.fixed + self.per_pair * len(v1)
+        return [slot, ready, (7 * v1.astype(np.int64) + v2).astype(np.int32)]
+
+    def done(self, h):
+        if self.clock.t >= h[1]:
+            self.active.discard(h[0])
+            return True
+        return False
+
+    def result(self, h):
+        return h[2]
+
+
+def make(nreq=300, rate=2e6, seed=0, n=1000, max_log2=12.0):
+    rng = np.random.default_rng(seed)
+    return serve.poisson_stream(rng, rate, nreq, n, max_log2=max_log2)
+
+
+def run(reqs, slots=3, slot_pairs=4096, mem=10**6):
+    clock = FakeClock()
+    ex = FakeExecutor(clock, slots)
+    sched = serve.Scheduler(ex, slots, slot_pairs, mem)
+    ex.sched = sched
+    done = serve.run_stream(sched, reqs, clock=clock)
+    return sched, ex, done
+
+
+def test_every_request_gets_its_own_answers():
+    reqs = make()
+    sched, ex, done = run(reqs)
+    assert len(done) == len(reqs)
+    for r in reqs:
+        assert np.array_equal(r.result, 7 * r.v1 + r.v2)
+        assert r.done_at >= r.arrival
+    assert ex.max_active <= 3
+
+
+def test_memory_budget_and_slots_respected_with_splitting():
+    reqs = make(nreq=200, max_log2=12.0)
+    budget = 12 * 1500          # smaller than many requests: they get cut
+    reqs = [r for r in reqs if r.size <= 1500]
+    sched, ex, done = run(reqs, slots=2, slot_pairs=2048, mem=budget)
+    assert ex.max_mem <= budget
+    assert ex.max_active <= 2
+    for r in reqs:
+        assert np.array_equal(r.result, 7 * r.v1 + r.v2)
+
+
+def test_requests_split_when_memory_is_short():
+    rng = np.random.default_rng(1)
+    reqs = [serve.Request(i, 0.0, rng.integers(0, 50, 1000).astype(np.int32),
+                          rng.integers(0, 50, 1000).astype(np.int32)) for i in range(4)]
+    sched, ex, done = run(reqs, slots=4, slot_pairs=1000, mem=12 * 1600)
+    assert any(len(r.launches) > 1 for r in reqs)
+    for r in reqs:
+        assert np.array_equal(r.result, 7 * r.v1 + r.v2)
+
+
+def test_small_requests_are_coalesced():
+    rng = np.random.default_rng(2)
+    reqs = [serve.Request(i, 0.0, rng.integers(0, 9, 10).astype(np.int32),
+                          rng.integers(0, 9, 10).astype(np.int32)) for i in range(50)]
+    sched, ex, done = run(reqs, slots=1, slot_pairs=4096)
+    assert sched.launches < 50
+    assert max(sched.launch_sizes) > 10
+    for r in reqs:
+        assert np.array_equal(r.result, 7 * r.v1 + r.v2)
+
+
+def test_oversized_request_is_refused():
+    r = serve.Request(0, 0.0, np.zeros(5000, np.int32), np.zeros(5000, np.int32))
+    sched = serve.Scheduler(FakeExecutor(FakeClock(), 1), 1, 4096, 10**6)
+    with pytest.raises(ValueError):
+        sched.enqueue(r)
+
+
+def test_poisson_stream_shape():
+    rng = np.random.default_rng(3)
+    reqs = serve.poisson_stream(rng, 1e6, 4000, 100)
+    sizes = np.array([r.size for r in reqs])
+    assert sizes.min() >= 1 and sizes.max() <= 65536
+    mean_b = (2.0**16 - 1) / (16 * np.log(2))
+    assert abs(sizes.mean() / mean_b - 1) < 0.1
+    t = np.array([r.arrival for r in reqs])
+    assert (np.diff(t) >= 0).all()
+    rate_req = len(reqs) / t[-1]
+    assert abs(rate_req / (1e6 / mean_b) - 1) < 0.1
