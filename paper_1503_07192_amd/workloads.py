@@ -47,14 +47,22 @@ def grid_edges(rows: int, cols: int):
     return eu, ev
 
 
-def block_partition(rows: int, cols: int, br: int, bc: int):
-    """Component of (r, c) = (r // br) * ceil(cols / bc) + c // bc."""
+def block_partition(rows: int, cols: int, br: int, bc: int, sb: int = 1):
+    """Blocks of br x bc vertices.  With sb == 1 the component of (r, c) is
+    (r // br) * ceil(cols / bc) + c // bc (blocks row by row).  With sb > 1 the
+    blocks are numbered super-block by super-block, each super-block being
+    sb x sb blocks numbered row by row inside it, so that runs of sb*sb
+    consecutive ids are square regions."""
     r = np.arange(rows)[:, None] // br
     c = np.arange(cols)[None, :] // bc
-    nbc = -(-cols // bc)
-    part = (r * nbc + c).ravel().astype(np.int32)
-    k = int(-(-rows // br) * nbc)
-    return part, k
+    nbr, nbc = -(-rows // br), -(-cols // bc)
+    if sb == 1:
+        part = (r * nbc + c).ravel().astype(np.int32)
+    else:
+        assert nbr % sb == 0 and nbc % sb == 0
+        sr, sc = r // sb, c // sb
+        part = (((sr * (nbc // sb) + sc) * sb + r % sb) * sb + c % sb).ravel().astype(np.int32)
+    return part, int(nbr * nbc)
 
 
 def uniform_pairs(rng, n: int, q: int, lo: int = 0, hi: int | None = None):
@@ -153,7 +161,7 @@ def delaunay1m(queries: int = 0):
 
 
 def grid2048(queries: int = 10_000_000, side: int = 2048, blk: int = 16,
-             share_den: int = 32):
+             share_den: int = 32, sb: int = 8):
     """Grid with 10% of the edges deleted off a random spanning tree."""
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import minimum_spanning_tree
@@ -162,11 +170,14 @@ def grid2048(queries: int = 10_000_000, side: int = 2048, blk: int = 16,
     eu, ev = grid_edges(side, side)
     m0 = len(eu)
     # Kruskal with a uniformly shuffled edge order == MST under distinct random keys
-    key = rs.permutation(m0).astype(np.float64) + 1.0
+    perm = rs.permutation(m0)
+    key = perm.astype(np.float64) + 1.0          # edge i gets key perm[i] + 1
     mst = minimum_spanning_tree(coo_matrix((key, (eu, ev)), shape=(n, n)).tocsr())
     tk = mst.tocoo()
+    edge_of_key = np.argsort(perm)               # key - 1 -> edge index
     in_tree = np.zeros(m0, bool)
-    in_tree[(tk.data - 1.0).astype(np.int64)] = True
+    in_tree[edge_of_key[(tk.data - 1.0).astype(np.int64)]] = True
+    assert in_tree.sum() == n - 1
     non_tree = np.flatnonzero(~in_tree)
     ndel = int(round(0.1 * m0))
     drop = rs.choice(non_tree, size=ndel, replace=False)
@@ -174,13 +185,18 @@ def grid2048(queries: int = 10_000_000, side: int = 2048, blk: int = 16,
     keep[drop] = False
     eu, ev = eu[keep], ev[keep]
     w = np.clip(np.rint(np.exp(4.0 + rw.standard_normal(len(eu)))), 1, 1e5).astype(np.int64)
-    part, k = block_partition(side, side, blk, blk)
+    # blocks numbered by super-blocks of sb x sb blocks: consecutive ids are
+    # square regions, and the share (the first k / share_den components) is a
+    # run of whole super-blocks
+    part, k = block_partition(side, side, blk, blk, sb)
     share_k = k // share_den
-    share_rows = (share_k // (side // blk)) * blk   # share = first block-rows
+    share_v = np.flatnonzero(part < share_k).astype(np.int32)
     d = _pack("grid%d" % side, n, eu, ev, w, part, k, share_k=share_k,
-              share_vertices=share_rows * side)
+              share_vertices=len(share_v))
     if queries:
-        d["v1"], d["v2"] = uniform_pairs(rq, n, queries, 0, share_rows * side)
+        v1 = share_v[rq.integers(0, len(share_v), size=queries)]
+        v2 = rq.integers(0, n, size=queries, dtype=np.int64).astype(np.int32)
+        d["v1"], d["v2"] = np.ascontiguousarray(v1, np.int32), v2
     return d
 
 

@@ -31,3 +31,23 @@ def test_rcb_partition_balanced():
     part, k = W.rcb_partition(pts, 5, rng)
     sizes = np.bincount(part, minlength=k)
     assert k == 32 and sizes.sum() == 5000 and sizes.min() > 100
+
+
+def test_superblock_numbering():
+    part, k = W.block_partition(32, 32, 4, 4, sb=2)
+    assert k == 64 and np.array_equal(np.bincount(part), [16] * 64)
+    # ids 0..3 are the 2x2 blocks of the top-left 8x8 vertex square
+    grid = part.reshape(32, 32)
+    assert set(np.unique(grid[:8, :8])) == {0, 1, 2, 3}
+    assert grid[0, 4] == 1 and grid[4, 0] == 2 and grid[0, 8] == 4
+
+
+def test_grid2048_small_share():
+    g = W.grid2048(queries=1000, side=256, blk=16, sb=4)
+    assert g["k"] == 256 and g["share_k"] == 8
+    assert (g["part"][g["v1"]] < g["share_k"]).all()
+    # connected: a spanning tree is kept
+    import oracle
+    d = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], [0])
+    assert (d < oracle.O_INF).all()
+    assert g["m"] == 2 * 256 * 255 - round(0.1 * 2 * 256 * 255)
