@@ -64,8 +64,8 @@ class Scheduler:
     """Admission, coalescing and completion on top of an executor."""
 
     def __init__(self, executor, slots: int, slot_pairs: int, mem_budget: int):
-        if slots < 1 or slot_pairs < 1:
-            raise ValueError("need at least one slot of at least one pair")
+        if slots < 1 or slot_pairs < 1 or mem_budget < BYTES_PER_PAIR:
+            raise ValueError("need at least one slot and memory for one pair")
         self.ex = executor
         self.nslots = slots
         self.slot_pairs = slot_pairs
@@ -78,9 +78,8 @@ class Scheduler:
         self.launch_sizes = []
 
     def enqueue(self, req: Request):
-        if req.size > self.slot_pairs or req.size * BYTES_PER_PAIR > self.mem_budget:
-            raise ValueError("request %d (%d pairs) exceeds a slot or the memory budget"
-                             % (req.rid, req.size))
+        """Queues a request; one larger than a slot or than the memory budget
+        is served in pieces, in order."""
         req.result = np.empty(req.size, np.int32)
         req._issued = 0   # pairs handed to launches
         req._filled = 0   # pairs whose results came back
@@ -91,7 +90,8 @@ class Scheduler:
 
     def _admit_one(self):
         """Coalesces queue-head requests into one launch on a free slot.  A
-        request is cut only when the memory left cannot hold it whole."""
+        request is cut only when the room left in the launch (slot capacity,
+        memory budget) cannot hold it whole."""
         if not self.free or not self.queue:
             return False
         room = min(self.slot_pairs, (self.mem_budget - self.mem_used) // BYTES_PER_PAIR)

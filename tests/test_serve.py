@@ -100,11 +100,15 @@ def test_small_requests_are_coalesced():
         assert np.array_equal(r.result, 7 * r.v1 + r.v2)
 
 
-def test_oversized_request_is_refused():
-    r = serve.Request(0, 0.0, np.zeros(5000, np.int32), np.zeros(5000, np.int32))
-    sched = serve.Scheduler(FakeExecutor(FakeClock(), 1), 1, 4096, 10**6)
+def test_request_larger_than_a_slot_is_served_in_pieces():
+    rng = np.random.default_rng(4)
+    r = serve.Request(0, 0.0, rng.integers(0, 99, 5000).astype(np.int32),
+                      rng.integers(0, 99, 5000).astype(np.int32))
+    sched, ex, done = run([r], slots=2, slot_pairs=1024, mem=10**6)
+    assert len(r.launches) == 5 and done == [r]
+    assert np.array_equal(r.result, 7 * r.v1 + r.v2)
     with pytest.raises(ValueError):
-        sched.enqueue(r)
+        serve.Scheduler(ex, 1, 16, 4)
 
 
 def test_poisson_stream_shape():
