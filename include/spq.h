@@ -58,7 +58,14 @@ typedef struct {
                           Floyd-Warshall on all of BG, 2 two-level */
   int32_t group_comps; /* two-level: consecutive components per group
                           (0 = auto: about 4,096 BG vertices per group) */
-  int32_t reserved[3]; /* must be 0 */
+  int32_t share_comps; /* 0: the whole index.  s > 0: one GPU's share, the
+                          paper's APSP_BG(C) for C in [0, s) only (Alg. 1,
+                          Phase 3, done at the nodes owning those C): BG
+                          rows from the share's boundary vertices to all of
+                          BG; queries then need v1 in a share component.
+                          Two-level method; the share is rounded up to whole
+                          groups; needs the total edge weight below SPQ_INF */
+  int32_t reserved[2]; /* must be 0 */
 } spq_build_opts;
 
 typedef struct {
@@ -81,7 +88,9 @@ typedef struct {
   int32_t bg_method;       /* 1 flat, 2 two-level */
   int32_t ngroups;         /* groups of the two-level method (1 when flat) */
   int32_t v_bg2;           /* level-2 boundary vertices (two-level) */
-  int32_t pad0;
+  int32_t share_comps;     /* share mode: components [0, share_comps) (0 = all) */
+  int32_t share_groups;    /* share mode: groups holding them */
+  int32_t bf_rounds;       /* share mode: Bellman-Ford rounds over groups */
   float ms_partition;      /* device time: boundary, renumbering (through the host plan) */
   float ms_components;     /* device time: APSP(C) initialisation + Floyd-Warshall */
   float ms_bg_assembly;    /* device time: BG matrix assembly */
@@ -121,8 +130,9 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
  * Queries, Algorithm 2: out[i] = dist(v1[i], v2[i]) for i < q.
  *   v1, v2, out   DEVICE arrays of q int32, owned by the caller
  *   stream        hipStream_t (NULL = default stream); the call is asynchronous
- * A pair with an id outside [0, n) yields SPQ_BAD_PAIR in its slot; other
- * slots are unaffected.  Read-only on the index: calls may run concurrently
+ * A pair with an id outside [0, n), or (share mode) with v1 outside the
+ * share's components, yields SPQ_BAD_PAIR in its slot; other slots are
+ * unaffected.  Read-only on the index: calls may run concurrently
  * on different streams.  Errors: SPQ_EINVAL (null index, q < 0), SPQ_EDEVICE.
  */
 spq_status spq_query_batch(const spq_index* idx, int64_t q, const int32_t* v1,
@@ -150,7 +160,8 @@ spq_status spq_index_layout(const spq_index* idx, int32_t* comp, int32_t* local,
 spq_status spq_index_component(const spq_index* idx, int32_t c, int32_t* out);
 
 /* Rows [row0, row0+nrows) of the BG distance matrix (v_bg columns each),
- * copied to the HOST array out.  Synchronous. */
+ * copied to the HOST array out.  In share mode only rows of the share's
+ * groups exist (SPQ_EINVAL otherwise).  Synchronous. */
 spq_status spq_index_bg_rows(const spq_index* idx, int32_t row0, int32_t nrows,
                              int32_t* out);
 

@@ -59,7 +59,7 @@ struct spq_index {
   u32 *err = nullptr, *members = nullptr, *M = nullptr, *BG = nullptr;
   uint4* vrec = nullptr;
   // groups (all components in group 0 for the flat store)
-  int32_t method = 1, ngroups = 1, Vgp = 0, V2 = 0, m2pmax = 0;
+  int32_t method = 1, ngroups = 1, cpg = 1, Vgp = 0, V2 = 0, m2pmax = 0;
   int64_t V2p = 0, h_elems = 0;
   std::vector<int32_t> h_grp, h_gbg0, h_gV, h_m2, h_b2off;
   std::vector<int64_t> h_pairbase;
@@ -68,6 +68,12 @@ struct spq_index {
   uint8_t* flag2 = nullptr;
   u32 *Mg = nullptr, *R = nullptr, *XT = nullptr, *BG2 = nullptr, *H = nullptr;
   int64_t* pairbase = nullptr;
+  // share mode
+  int32_t share_comps = 0, share_groups = 0, S2 = 0, bf_rounds = 0;
+  int64_t S2p = 0;
+  u32 *A = nullptr, *DT = nullptr, *DT2 = nullptr, *bfflag = nullptr;
+  int4* xe = nullptr;
+  int32_t* xcount = nullptr;
   // exactness certificate (total weight >= INF)
   bool certify = false;
   int32_t *bgvert = nullptr, *label = nullptr, *bglabel = nullptr;
@@ -89,11 +95,82 @@ struct spq_index {
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
                     vrec, grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
-                    bgvert, label, bglabel, cert};
+                    bgvert, label, bglabel, cert, A,    DT,    DT2,   bfflag,  xe, xcount};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
 };
+
+// Share mode (after level 1): Bellman-Ford over groups from the share's
+// level-2 vertices, then the composition for the share's groups against all
+// groups.  Synchronous (one small readback per round).
+static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, hipStream_t s) {
+  const int32_t G = X->ngroups, Vgp = X->Vgp;
+  X->share_groups = std::min(G, (X->share_comps + X->cpg - 1) / X->cpg);
+  X->S2 = X->h_b2off[X->share_groups];
+  X->S2p = round_up(std::max<int32_t>(X->S2, 1), 128);
+  X->h_pairbase.assign((size_t)G * G, -1);
+  X->h_elems = 0;
+  for (int32_t a1 = 0; a1 < X->share_groups; a1++)
+    for (int32_t a2 = 0; a2 < G; a2++) {
+      X->h_pairbase[(size_t)a1 * G + a2] = X->h_elems;
+      X->h_elems += (int64_t)X->h_gV[a1] * X->h_gV[a2];
+    }
+  const int64_t V2p = std::max<int64_t>(X->V2p, 128);
+  X->V2p = V2p;
+  HIP_TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
+  HIP_TRY(dalloc(&X->XT, (int64_t)G * X->m2pmax * Vgp));
+  HIP_TRY(dalloc(&X->A, (int64_t)G * X->m2pmax * X->m2pmax));
+  // Bellman-Ford buffers carry 128 spare rows: a row tile may start at the
+  // last group's last level-2 id
+  HIP_TRY(dalloc(&X->DT, (V2p + 128) * X->S2p));
+  HIP_TRY(dalloc(&X->DT2, (V2p + 128) * X->S2p));
+  HIP_TRY(dalloc(&X->BG2, X->S2p * V2p));
+  HIP_TRY(dalloc(&X->H, X->h_elems));
+  HIP_TRY(dalloc(&X->pairbase, (int64_t)G * G));
+  HIP_TRY(dalloc(&X->xe, 2 * std::max<int64_t>(m, 1)));
+  HIP_TRY(dalloc(&X->xcount, 1));
+  HIP_TRY(dalloc(&X->bfflag, 1));
+  HIP_TRY(hipMemsetAsync(X->xcount, 0, sizeof(int32_t), s));
+  HIP_TRY(hipMemsetAsync(X->DT + V2p * X->S2p, 0xff, 128 * X->S2p * sizeof(u32), s));
+  HIP_TRY(hipMemcpyAsync(X->pairbase, X->h_pairbase.data(), sizeof(int64_t) * G * G,
+                         hipMemcpyHostToDevice, s));
+  ha.m2pmax = X->m2pmax; ha.V2 = X->V2; ha.V2p = V2p; ha.b2off = X->b2off; ha.R = X->R;
+  ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
+  ha.share_groups = X->share_groups; ha.S2 = X->S2; ha.S2p = X->S2p; ha.A = X->A; ha.DT = X->DT;
+  ha.DT2 = X->DT2; ha.xe = X->xe; ha.xcount = X->xcount;
+  HIP_TRY(spq::launch_share_prepare(ha, s));
+  int32_t nxe = 0;
+  HIP_TRY(hipMemcpyAsync(&nxe, X->xcount, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  u32* bufs[2] = {X->DT, X->DT2};
+  int cur = 0;
+  double intra = 0;
+  for (int32_t g = 0; g < G; g++)
+    intra += (double)((X->h_m2[g] + 127) / 128) * (double)(X->S2p / 128) * 128.0 * 128.0 *
+             (double)round_up(X->h_m2[g], 16);
+  for (;;) {
+    if (++X->bf_rounds > 100000) return fail(SPQ_EDEVICE, "Bellman-Ford over groups did not settle");
+    u32 changed = 0;
+    HIP_TRY(hipMemsetAsync(X->bfflag, 0, sizeof(u32), s));
+    HIP_TRY(spq::launch_share_round(ha, bufs[cur], bufs[cur ^ 1], nxe, X->bfflag, s));
+    HIP_TRY(hipMemcpyAsync(&changed, X->bfflag, sizeof(u32), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    cur ^= 1;
+    X->relax_bg_exec += intra + (double)nxe * X->S2;
+    if (!changed) break;
+  }
+  for (int32_t a1 = 0; a1 < X->share_groups; a1++)
+    for (int32_t a2 = 0; a2 < G; a2++) {
+      X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * (Vgp / 128) * 128.0 * 128.0 *
+                          (double)round_up(X->h_m2[a1], 16);
+      X->relax_bg_exec += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) *
+                          128.0 * 128.0 * (double)round_up(X->h_m2[a2], 16);
+    }
+  HIP_TRY(spq::launch_share_compose(ha, bufs[cur], s));
+  return SPQ_OK;
+}
 
 // Runs the exactness certificate when the build asked for it (total edge
 // weight >= SPQ_INF): connected components of G, then the checks of
@@ -150,7 +227,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   if (n > 0x7fffffff - 1) return fail(SPQ_EINVAL, "n too large");
   int tile = 128;
   bool profile = false, plain = false;
-  int32_t method_opt = 0, group_comps = 0;
+  int32_t method_opt = 0, group_comps = 0, share_comps = 0;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
@@ -161,7 +238,12 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     group_comps = opts->group_comps;
     if (method_opt < 0 || method_opt > 2) return fail(SPQ_EINVAL, "bg_method must be 0, 1 or 2");
     if (group_comps < 0) return fail(SPQ_EINVAL, "group_comps < 0");
-    for (int i = 0; i < 3; i++)
+    share_comps = opts->share_comps;
+    if (share_comps < 0 || share_comps > k) return fail(SPQ_EINVAL, "share_comps outside [0, k]");
+    if (share_comps == k) share_comps = 0;
+    if (share_comps > 0 && method_opt == 1)
+      return fail(SPQ_EINVAL, "a share needs the two-level method");
+    for (int i = 0; i < 2; i++)
       if (opts->reserved[i]) return fail(SPQ_EINVAL, "reserved options must be 0");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -231,6 +313,9 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   // which needs every component's own weight below SPQ_INF.
   if (htotal >= (unsigned long long)SPQ_INF) {
     X->certify = true;
+    if (share_comps > 0)
+      return guard(fail(SPQ_ERANGE, "total edge weight " + std::to_string(htotal) +
+                                        " reaches SPQ_INF; a share build needs it below"));
     for (int32_t c = 0; c < k; c++)
       if (X->h_sumc[c] >= (unsigned long long)SPQ_INF)
         return guard(fail(SPQ_ERANGE, "edge weights inside component " + std::to_string(c) +
@@ -257,7 +342,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   }
   X->V = X->h_bgoff[k];
   X->relax_bg = (double)X->V * X->V * X->V;
-  X->method = method_opt ? method_opt : (X->V > 32768 ? 2 : 1);
+  X->method = method_opt ? method_opt : (X->V > 32768 || share_comps > 0 ? 2 : 1);
+  X->share_comps = share_comps;
   int32_t cpg = k;
   if (X->method == 2) {
     if (group_comps > 0) {
@@ -270,6 +356,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     }
   }
   X->ngroups = (k + cpg - 1) / cpg;
+  X->cpg = cpg;
   X->h_grp.resize(k);
   X->h_gbg0.resize(X->ngroups);
   X->h_gV.resize(X->ngroups);
@@ -379,6 +466,13 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     X->V2 = X->h_b2off[G];
     X->V2p = round_up(X->V2, 128);
     X->m2pmax = (int32_t)std::max<int64_t>(128, round_up(m2max, 128));
+    if (X->share_comps > 0) {
+      spq_status ss = build_share(X, ha, m, s);
+      if (ss != SPQ_OK) return guard(ss);
+      TRY(hipEventRecord(X->ev[4], s));
+      *out = X;
+      return SPQ_OK;
+    }
     X->h_pairbase.assign((size_t)G * G, 0);
     for (int32_t a1 = 0; a1 < G; a1++)
       for (int32_t a2 = a1; a2 < G; a2++) {
@@ -443,7 +537,7 @@ spq_status spq_query_batch(const spq_index* X, int64_t q, const int32_t* v1, con
   a.q = q; a.v1 = v1; a.v2 = v2; a.out = out; a.n = X->n;
   a.vrec = X->vrec; a.M = X->M; a.BG = X->BG; a.ldbg = X->Vp;
   a.H = X->method == 2 ? X->H : nullptr; a.pairbase = X->pairbase; a.gV = X->gV;
-  a.ngroups = X->ngroups;
+  a.ngroups = X->ngroups; a.share_comps = X->share_comps;
   HIP_TRY(spq::launch_query(a, reinterpret_cast<hipStream_t>(stream)));
   return SPQ_OK;
 }
@@ -464,6 +558,9 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   st->bg_method = X->method;
   st->ngroups = X->ngroups;
   st->v_bg2 = X->V2;
+  st->share_comps = X->share_comps;
+  st->share_groups = X->share_groups;
+  st->bf_rounds = X->bf_rounds;
   if (X->method == 2) {
     st->v_bg_padded = X->Vgp;
     st->bg_bytes = (int64_t)X->h_elems * 4;
@@ -510,9 +607,13 @@ spq_status spq_index_bg_rows(const spq_index* X, int32_t row0, int32_t nrows, in
   if (nrows == 0) return SPQ_OK;
   HIP_TRY(hipEventSynchronize(X->ev[4]));
   if (X->method == 2) {
+    if (X->share_comps > 0 &&
+        (int64_t)row0 + nrows > X->h_gbg0[X->share_groups - 1] + X->h_gV[X->share_groups - 1])
+      return fail(SPQ_EINVAL, "BG rows outside the share");
     u32* tmp = nullptr;
     HIP_TRY(dalloc(&tmp, X->V));
     spq::HierArgs ha{};
+    ha.share_groups = X->share_groups;
     ha.V = X->V; ha.ngroups = X->ngroups; ha.bggrp = X->bggrp; ha.bgrow = X->bgrow; ha.bgnb = X->bgnb;
     ha.bglocal = X->bglocal; ha.gV = X->gV; ha.pairbase = X->pairbase; ha.H = X->H;
     hipError_t e = hipSuccess;

@@ -277,16 +277,17 @@ __device__ __forceinline__ void fill_inf(u32 (&c)[8][8]) {
 }
 
 // XT[S2] (m2pmax x Vgp, rows b in B2(S2), columns x of S1) =
-//   min over a in B2(S1) of D2[a][b] + R_S1[a][x],   for S2 = S1 + blockIdx.y.
+//   min over a in B2(S1) of D2[a][b] + R_S1[a][x],   for S2 = s2base + blockIdx.y.
+// D2 rows are level-2 ids of the sources (all of BG2, or the share's rows).
 // Rows b >= m2[S2] are stored as INF.
-__global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t Vgp, int32_t m2pmax,
+__global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t s2base, int32_t Vgp, int32_t m2pmax,
                                                const int32_t* __restrict__ m2,
                                                const int32_t* __restrict__ b2off,
                                                const u32* __restrict__ BG2, int64_t V2p,
                                                const u32* __restrict__ R, u32* __restrict__ XT) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
-  const int32_t s2 = s1 + (int32_t)blockIdx.y;
+  const int32_t s2 = s2base + (int32_t)blockIdx.y;
   const int ntx = Vgp / 128;
   const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
   const int32_t ka = m2[s1], mb = m2[s2];
@@ -315,10 +316,11 @@ __global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t Vgp, int32_t 
     }
 }
 
-// D(S1,S2) tile (rows x of S1, columns y of S2) for S2 = S1 + blockIdx.y:
+// D(S1,S2) tile (rows x of S1, columns y of S2) for S2 = s2base + blockIdx.y:
 //   min over b in B2(S2) of XT[S2][b][x] + R_S2[b][y], and d_S1 when S1 = S2;
 // stored in the component-pair layout described at the top of the file.
-__global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t ngroups, int32_t Vgp, int32_t m2pmax,
+__global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t s2base, int32_t ngroups, int32_t Vgp,
+                                              int32_t m2pmax,
                                               const int32_t* __restrict__ m2,
                                               const int32_t* __restrict__ gV,
                                               const int32_t* __restrict__ gbg0,
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t ngroups, int32
                                               const int32_t* __restrict__ bglocal, u32* __restrict__ H) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
-  const int32_t s2 = s1 + (int32_t)blockIdx.y;
+  const int32_t s2 = s2base + (int32_t)blockIdx.y;
   const int ntx = Vgp / 128;
   const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
   const int32_t V1 = gV[s1], V2 = gV[s2];
@@ -382,7 +384,8 @@ __global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t ngroups, int32
 }
 
 // One BG row (BG id x) gathered from the two-level store, for inspection.
-__global__ void k_hier_row(int32_t x, int32_t V, int32_t ngroups, const int32_t* __restrict__ bggrp,
+__global__ void k_hier_row(int32_t x, int32_t swap, int32_t V, int32_t ngroups,
+                           const int32_t* __restrict__ bggrp,
                            const int32_t* __restrict__ bgrow, const int32_t* __restrict__ bgnb,
                            const int32_t* __restrict__ bglocal, const int32_t* __restrict__ gV,
                            const int64_t* __restrict__ pairbase, const u32* __restrict__ H,
@@ -390,7 +393,7 @@ __global__ void k_hier_row(int32_t x, int32_t V, int32_t ngroups, const int32_t*
   const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (y >= V) return;
   int32_t a = x, b = (int32_t)y;
-  if (bggrp[a] > bggrp[b]) {
+  if (swap && bggrp[a] > bggrp[b]) {
     a = (int32_t)y;
     b = x;
   }
@@ -398,6 +401,154 @@ __global__ void k_hier_row(int32_t x, int32_t V, int32_t ngroups, const int32_t*
   const int64_t off = pairbase[(int64_t)sa * ngroups + sb] + (int64_t)bgrow[a] * gV[sb] +
                       (int64_t)bgnb[a] * bgrow[b] + (int64_t)bglocal[a] * bgnb[b] + bglocal[b];
   out[y] = H[off];
+}
+
+
+// ------------------------------------------------------------ share mode --
+// Distances from the level-2 boundary vertices of the share groups (the
+// first share_groups groups; their level-2 ids are 0 .. S2-1) to all level-2
+// vertices, by Bellman-Ford over groups on BG2 without building it: DT[b][i]
+// (row b = any level-2 id, column i = share source) alternates
+//   intra-group:  DT[B2(S)] = min(DT[B2(S)], A_S (x) DT[B2(S)])   (A_S = d_S on B2(S),
+//                 closed, so one product covers any path inside S)
+//   cross edges:  DT[b] = min(DT[b], DT[a] + w(a,b))  for each G edge between groups
+// until nothing changes; the fixed point is d_BG2 from every share source.
+
+// A_S: d_S between the B2 vertices of S (m2pmax x m2pmax per group, INF padding).
+__global__ void k_b2_block(int32_t Vgp, int32_t m2pmax, const int32_t* __restrict__ m2,
+                           const int32_t* __restrict__ b2list, const u32* __restrict__ Mg,
+                           u32* __restrict__ A) {
+  const int s = blockIdx.y;
+  const int32_t i = blockIdx.x, ms = m2[s];
+  u32* out = A + ((int64_t)s * m2pmax + i) * m2pmax;
+  const int32_t* list = b2list + (int64_t)s * Vgp;
+  const u32* prow = i < ms ? Mg + ((int64_t)s * Vgp + list[i]) * Vgp : nullptr;
+  for (int32_t j = threadIdx.x; j < m2pmax; j += blockDim.x)
+    out[j] = (i < ms && j < ms) ? prow[list[j]] : INF;
+}
+
+// DT init: row b (level-2 id), column i (share source): d_S(b, i) inside one
+// group, 0 for b = i, INF otherwise.
+__global__ void k_dt_init(int32_t V2, int32_t S2, int64_t S2p, int32_t ngroups,
+                          const int32_t* __restrict__ b2off, const int32_t* __restrict__ b2list,
+                          int32_t Vgp, const u32* __restrict__ Mg, u32* __restrict__ DT) {
+  const int64_t b = blockIdx.x;
+  u32* out = DT + b * S2p;
+  int64_t lo = 0, hi = 0;
+  const u32* prow = nullptr;
+  const int32_t* list = nullptr;
+  if (b < V2) {
+    int32_t a = 0, z = ngroups - 1;
+    while (a < z) {
+      const int32_t mid = (a + z + 1) >> 1;
+      if (b2off[mid] <= b) a = mid; else z = mid - 1;
+    }
+    lo = b2off[a];
+    hi = min((int64_t)b2off[a + 1], (int64_t)S2);
+    list = b2list + (int64_t)a * Vgp;
+    prow = Mg + ((int64_t)a * Vgp + list[b - lo]) * Vgp;
+  }
+  for (int64_t i = threadIdx.x; i < S2p; i += blockDim.x)
+    out[i] = (i == b) ? 0u : (i >= lo && i < hi) ? prow[list[i - lo]] : INF;
+}
+
+// Intra-group step, out of place: rows B2(S) of DTn = min(DTo, A_S (x) DTo).
+__global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
+                                                  const int32_t* __restrict__ m2,
+                                                  const int32_t* __restrict__ b2off,
+                                                  const u32* __restrict__ A, const u32* __restrict__ DTo,
+                                                  u32* __restrict__ DTn, u32* __restrict__ changed) {
+  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
+  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
+  const int s = blockIdx.y;
+  const int32_t ms = m2[s];
+  const int ntc = (int)(S2p / 128);
+  const int ti = (int)blockIdx.x / ntc, tj = (int)blockIdx.x % ntc;
+  if (ti * 128 >= ms) return;
+  const int64_t r0 = b2off[s];
+  u32 c[8][8];
+  tile_load<128>(c, DTo + (r0 + ti * 128) * S2p + tj * 128, S2p);  // rows past ms: unused
+  u32 old[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+#pragma unroll
+    for (int j = 0; j < 8; j++) old[i][j] = c[i][j];
+  const u32* At = A + (int64_t)s * m2pmax * m2pmax + ti * 128;  // A_S symmetric: At[k][i] = A[i][k]
+  const u32* B = DTo + r0 * S2p + tj * 128;
+  mp_stream128<true>(c, At, m2pmax, B, S2p, (ms + 15) / 16 * 16, ms, ms - ti * 128, sA, sB);
+  const int tx = tid_x(), ty = tid_y();
+  u32 diff = 0;
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int row = ti * 128 + h * 64 + ty * 4 + a;
+      if (row >= ms) continue;
+      u32* dst = DTn + (r0 + row) * S2p + tj * 128;
+#pragma unroll
+      for (int h2 = 0; h2 < 2; h2++) {
+        const int i = h * 4 + a, j = h2 * 4;
+        diff |= (c[i][j] != old[i][j]) | (c[i][j + 1] != old[i][j + 1]) |
+                (c[i][j + 2] != old[i][j + 2]) | (c[i][j + 3] != old[i][j + 3]);
+        *reinterpret_cast<uint4*>(dst + h2 * 64 + tx * 4) =
+            make_uint4(c[i][j], c[i][j + 1], c[i][j + 2], c[i][j + 3]);
+      }
+    }
+  if (diff) atomicOr(changed, 1u);
+}
+
+// Cross edges between groups, as directed level-2 pairs (a -> b, w).
+__global__ void k_cross_collect(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                                const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
+                                const int32_t* __restrict__ local, const int32_t* __restrict__ bgoff,
+                                const int32_t* __restrict__ grp, const int32_t* __restrict__ b2off,
+                                const int32_t* __restrict__ b2rank, int32_t* __restrict__ count,
+                                int4* __restrict__ xe) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = eu[e], v = ev[e];
+    const int32_t cu = comp[u], cv = comp[v];
+    if (cu == cv) continue;
+    const int32_t su = grp[cu], sv = grp[cv];
+    if (su == sv) continue;
+    const int32_t a = b2off[su] + b2rank[bgoff[cu] + local[u]];
+    const int32_t b = b2off[sv] + b2rank[bgoff[cv] + local[v]];
+    const int32_t slot = atomicAdd(count, 2);
+    xe[slot] = make_int4(a, b, w[e], 0);
+    xe[slot + 1] = make_int4(b, a, w[e], 0);
+  }
+}
+
+// DT[b][i] = min(DT[b][i], DT[a][i] + w) for every directed cross edge.
+__global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2, int64_t S2p, u32* DT,
+                           u32* __restrict__ changed) {
+  const int32_t e = blockIdx.x;
+  if (e >= nxe) return;
+  const int4 t = xe[e];
+  const u32* src = DT + (int64_t)t.x * S2p;
+  u32* dst = DT + (int64_t)t.y * S2p;
+  u32 diff = 0;
+  for (int32_t i = threadIdx.x; i < S2; i += blockDim.x) {
+    const u32 v = min(src[i] + (u32)t.z, INF);
+    if (v < dst[i]) {
+      atomicMin(dst + i, v);
+      diff = 1;
+    }
+  }
+  if (diff) atomicOr(changed, 1u);
+}
+
+// D2s (S2p x V2p) = DT^T, 32 x 32 tiles through LDS.
+__global__ void k_transpose(const u32* __restrict__ src, int64_t rows, int64_t cols, int64_t lds_,
+                            u32* __restrict__ dst, int64_t ldd) {
+  __shared__ u32 t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int k = ty; k < 32; k += 8)
+    if (r0 + k < rows && c0 + tx < cols) t[k][tx] = src[(r0 + k) * lds_ + c0 + tx];
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8)
+    if (c0 + k < cols && r0 + tx < rows) dst[(c0 + k) * ldd + r0 + tx] = t[tx][k];
 }
 
 // ---------------------------------------------------------------- launch --
@@ -439,18 +590,62 @@ hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s) {
   for (int32_t s1 = 0; s1 < a.ngroups; s1++) {
     const unsigned pairs = (unsigned)(a.ngroups - s1);
     if (a.V2p > 0)
-      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(s1, a.Vgp, a.m2pmax, a.m2, a.b2off,
+      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(s1, s1, a.Vgp, a.m2pmax, a.m2, a.b2off,
                                                                  a.BG2, a.V2p, a.R, a.XT);
     k_mp_y<<<dim3((unsigned)(ntx * ntx), pairs), 256, 0, s>>>(
-        s1, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
+        s1, s1, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
         a.bgnb, a.bglocal, a.H);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s) {
-  k_hier_row<<<(unsigned)((a.V + 255) / 256 > 0 ? (a.V + 255) / 256 : 1), 256, 0, s>>>(x, a.V, a.ngroups, a.bggrp, a.bgrow, a.bgnb,
-                                                          a.bglocal, a.gV, a.pairbase, a.H, out);
+  k_hier_row<<<(unsigned)((a.V + 255) / 256 > 0 ? (a.V + 255) / 256 : 1), 256, 0, s>>>(
+      x, a.share_groups > 0 ? 0 : 1, a.V, a.ngroups, a.bggrp, a.bgrow, a.bgnb, a.bglocal, a.gV,
+      a.pairbase, a.H, out);
+  return hipGetLastError();
+}
+
+}  // namespace spq
+
+namespace spq {
+
+hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s) {
+  k_r_gather<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(a.Vgp, a.m2pmax, a.m2,
+                                                                           a.b2list, a.Mg, a.R);
+  k_b2_block<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(a.Vgp, a.m2pmax, a.m2,
+                                                                           a.b2list, a.Mg, a.A);
+  k_dt_init<<<(unsigned)a.V2p, 256, 0, s>>>(a.V2, a.S2, a.S2p, a.ngroups, a.b2off, a.b2list, a.Vgp,
+                                            a.Mg, a.DT);
+  hipError_t e = hipMemcpyAsync(a.DT2, a.DT, sizeof(u32) * a.V2p * a.S2p, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  if (a.m > 0)
+    k_cross_collect<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
+                                                 a.b2off, a.b2rank, a.xcount, a.xe);
+  return hipGetLastError();
+}
+
+// One Bellman-Ford round: DT (in) -> DT2 (intra) -> cross edges on DT2.
+hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, u32* changed,
+                              hipStream_t s) {
+  const int ntm = a.m2pmax / 128, ntc = (int)(a.S2p / 128);
+  k_bf_intra<<<dim3((unsigned)(ntm * ntc), (unsigned)a.ngroups), 256, 0, s>>>(
+      a.m2pmax, a.S2p, a.m2, a.b2off, a.A, DTin, DTout, changed);
+  if (nxe > 0) k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, DTout, changed);
+  return hipGetLastError();
+}
+
+hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s) {
+  dim3 tg((unsigned)((a.S2p + 31) / 32), (unsigned)((a.V2p + 31) / 32));
+  k_transpose<<<tg, 256, 0, s>>>(DT, a.V2p, a.S2p, a.S2p, a.BG2, a.V2p);
+  const int ntx = a.Vgp / 128, ntm = a.m2pmax / 128;
+  for (int32_t s1 = 0; s1 < a.share_groups; s1++) {
+    k_mp_xt<<<dim3((unsigned)(ntm * ntx), (unsigned)a.ngroups), 256, 0, s>>>(
+        s1, 0, a.Vgp, a.m2pmax, a.m2, a.b2off, a.BG2, a.V2p, a.R, a.XT);
+    k_mp_y<<<dim3((unsigned)(ntx * ntx), (unsigned)a.ngroups), 256, 0, s>>>(
+        s1, 0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
+        a.bgnb, a.bglocal, a.H);
+  }
   return hipGetLastError();
 }
 

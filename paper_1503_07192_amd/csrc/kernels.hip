@@ -426,7 +426,8 @@ __global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restr
                                                const u32* __restrict__ M, const u32* __restrict__ BG,
                                                int64_t ldbg, const u32* __restrict__ H,
                                                const int64_t* __restrict__ pairbase,
-                                               const int32_t* __restrict__ gV, int32_t ngroups) {
+                                               const int32_t* __restrict__ gV, int32_t ngroups,
+                                               int32_t share_comps) {
   const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (qi >= q) return;
@@ -437,11 +438,15 @@ __global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restr
   }
   uint4 ra = vrec[2 * (int64_t)a], ra2 = vrec[2 * (int64_t)a + 1];
   uint4 rb = vrec[2 * (int64_t)b], rb2 = vrec[2 * (int64_t)b + 1];
+  if (share_comps > 0 && (int32_t)ra.z >= share_comps) {  // v1 outside the share
+    if (lane == 0) out[qi] = -1;
+    return;
+  }
   const u32* blk;
   if (H) {
-    // two-level store keeps group pairs S1 <= S2 only; dist is symmetric, so
-    // swap the endpoints when needed
-    if (ra2.z > rb2.z) {
+    // the full two-level store keeps group pairs S1 <= S2 only; dist is
+    // symmetric, so swap the endpoints when needed (a share keeps all S2)
+    if (share_comps == 0 && ra2.z > rb2.z) {
       const uint4 t = ra, t2 = ra2;
       ra = rb; ra2 = rb2; rb = t; rb2 = t2;
     }
@@ -592,7 +597,7 @@ hipError_t launch_query(const QueryArgs& a, hipStream_t s) {
   if (a.q <= 0) return hipSuccess;
   int64_t blocks = (a.q + 3) / 4;
   k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.vrec, a.M, a.BG, a.ldbg,
-                                           a.H, a.pairbase, a.gV, a.ngroups);
+                                           a.H, a.pairbase, a.gV, a.ngroups, a.share_comps);
   LAUNCH_CHECK();
 }
 

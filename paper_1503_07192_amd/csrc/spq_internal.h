@@ -66,6 +66,7 @@ struct QueryArgs {
   const int64_t* pairbase;
   const int32_t* gV;
   int32_t ngroups;
+  int32_t share_comps;  // > 0: only sources v1 in components [0, share_comps)
 };
 
 // Two-level BG (hier.hip).
@@ -83,7 +84,17 @@ struct HierArgs {
   const int32_t* b2off;            // [ngroups+1]
   u32 *R, *XT, *BG2, *H;
   const int64_t* pairbase;         // ngroups x ngroups
+  // share mode: rows of BG only from the first share_groups groups
+  int32_t share_groups, S2;        // groups, level-2 sources (ids 0 .. S2-1)
+  int64_t S2p;                     // S2 rounded up to 128
+  u32 *A, *DT, *DT2;               // A_S blocks; Bellman-Ford buffers (V2p x S2p)
+  int4* xe;                        // directed cross edges
+  int32_t* xcount;
 };
+hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s);
+hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, u32* changed,
+                              hipStream_t s);
+hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s);
 hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
 hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s);
 hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s);

@@ -34,7 +34,8 @@ class SpqError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("bg_tile", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("plain", ctypes.c_int32), ("bg_method", ctypes.c_int32),
-                ("group_comps", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("group_comps", ctypes.c_int32), ("share_comps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -47,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("relax_fw_inner", ctypes.c_double), ("fw_inner_launches", ctypes.c_int64),
                 ("ms_fw_inner", ctypes.c_float),
                 ("bg_method", ctypes.c_int32), ("ngroups", ctypes.c_int32),
-                ("v_bg2", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("v_bg2", ctypes.c_int32), ("share_comps", ctypes.c_int32),
+                ("share_groups", ctypes.c_int32), ("bf_rounds", ctypes.c_int32),
                 ("ms_partition", ctypes.c_float), ("ms_components", ctypes.c_float),
                 ("ms_bg_assembly", ctypes.c_float), ("ms_bg_apsp", ctypes.c_float)]
 
@@ -145,11 +147,12 @@ class Index:
 
 
 def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg_method=0,
-                group_comps=0, stream=None) -> Index:
+                group_comps=0, share_comps=0, stream=None) -> Index:
     """Algorithm 1 on device tensors; see spq_build_index."""
     L = load()
     opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)), plain=int(bool(plain)),
-                     bg_method=int(bg_method), group_comps=int(group_comps))
+                     bg_method=int(bg_method), group_comps=int(group_comps),
+                     share_comps=int(share_comps))
     h = ctypes.c_void_p()
     m = int(eu.numel())
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),

@@ -456,3 +456,96 @@ def test_delaunay1m_two_level():
     D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], src)
     want = clamp32(D[np.repeat(np.arange(100), 20), v2])
     assert np.array_equal(got, want)
+
+
+# --------------------------------------------------- share (one GPU's rows)
+def share_vertices(g, share_comps):
+    return np.flatnonzero(g["part"] < share_comps).astype(np.int32)
+
+
+def check_share(g, idx, share_comps, nsrc=None, rng=None):
+    lay = spq.index_layout(idx)
+    st = spq.index_stats(idx)
+    verts = bg_vertices(lay)
+    bgend = int(lay["bgoff"][min(g["k"], st["share_groups"] * (-(-g["k"] // st["ngroups"])))])
+    rows = np.arange(bgend) if nsrc is None else rng.choice(bgend, min(nsrc, bgend), replace=False)
+    if len(rows):
+        check_bg_rows(g, idx, lay, rows)
+    sv = share_vertices(g, share_comps)
+    if nsrc is None:
+        v1 = np.repeat(sv, g["n"]).astype(np.int32)
+        v2 = np.tile(np.arange(g["n"]), len(sv)).astype(np.int32)
+    else:
+        src = rng.choice(sv, nsrc)
+        v1 = np.repeat(src, 20).astype(np.int32)
+        v2 = rng.integers(0, g["n"], v1.size).astype(np.int32)
+    check_queries(g, idx, v1, v2)
+    outside = np.flatnonzero(g["part"] >= share_comps)
+    if len(outside):
+        got = run_queries(idx, outside[:5].astype(np.int32), np.zeros(min(5, len(outside)), np.int32))
+        assert (got == spq.SPQ_BAD_PAIR).all()
+
+
+@pytest.mark.parametrize("share_comps,gc", [(1, 1), (2, 2), (3, 2), (8, 4)])
+def test_share_small_grid(share_comps, gc):
+    rng = np.random.default_rng(40 + share_comps)
+    eu, ev, w = W.random_grid(rng, 16, 16, keep=0.9, diag=0.2, wlo=0, whi=50)
+    part, k = W.block_partition(16, 16, 4, 4, sb=2)
+    g = dict(name="sharegrid", n=256, eu=eu, ev=ev, w=w, part=part, k=k)
+    idx = build(g, share_comps=share_comps, group_comps=gc)
+    st = spq.index_stats(idx)
+    assert st["share_comps"] == share_comps and st["bf_rounds"] >= 1
+    lay = spq.index_layout(idx)
+    check_layout(g, lay)
+    check_components(g, idx, lay)
+    check_share(g, idx, share_comps)
+
+
+def test_share_random_partition():
+    rng = np.random.default_rng(77)
+    eu, ev, w = W.random_grid(rng, 12, 14, keep=0.8, diag=0.3, wlo=0, whi=20)
+    n, k = 168, 9
+    g = dict(name="sharerand", n=n, eu=eu, ev=ev, w=w, part=W.random_partition(rng, n, k), k=k)
+    idx = build(g, share_comps=4, group_comps=2)
+    check_share(g, idx, 4)
+
+
+def test_share_grid2048_small_equals_full_two_level():
+    g = W.grid2048(queries=2000, side=256, blk=16, sb=4)
+    full = build(g, bg_method=2, group_comps=16)
+    share = build(g, share_comps=g["share_k"], group_comps=16)
+    st = spq.index_stats(share)
+    assert st["share_groups"] == 1
+    lay = spq.index_layout(share)
+    nrows = int(lay["bgoff"][16])
+    V = st["v_bg"]
+    assert np.array_equal(spq.index_bg_rows(share, 0, nrows, V), spq.index_bg_rows(full, 0, nrows, V))
+    assert np.array_equal(run_queries(share, g["v1"], g["v2"]), run_queries(full, g["v1"], g["v2"]))
+    check_queries(g, share, g["v1"][:500], g["v2"][:500])
+
+
+def test_grid2048_share_full_size():
+    g = W.grid2048(queries=10_000_000)
+    print("grid2048: n=%d m=%d k=%d share=%d" % (g["n"], g["m"], g["k"], g["share_k"]), flush=True)
+    idx = build(g, share_comps=g["share_k"])
+    st = spq.index_stats(idx)
+    print({k: st[k] for k in ("v_bg", "ngroups", "v_bg2", "share_groups", "bf_rounds", "bg_bytes",
+                              "ms_components", "ms_bg_apsp")}, flush=True)
+    assert st["v_bg"] == 883_500 and st["share_groups"] == 8
+    rng = np.random.default_rng(44)
+    lay = spq.index_layout(idx)
+    flag = oracle.boundary(g["n"], g["eu"], g["ev"], g["part"])
+    check_layout_fast(g, lay, flag)
+    comps = np.concatenate([[0, 511, 512, g["k"] - 1], rng.choice(g["k"], 30, replace=False)])
+    check_components(g, idx, lay, np.unique(comps))
+    bgend = int(lay["bgoff"][512])
+    check_bg_rows(g, idx, lay, np.concatenate([[0, bgend - 1], rng.integers(0, bgend, 20)]))
+    out = run_queries(idx, g["v1"], g["v2"])
+    assert (out >= 0).all()
+    src = g["v1"][:60]
+    D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], src)
+    tgt = g["v2"][np.arange(60 * 20).reshape(60, 20) % len(g["v2"])]
+    sub = run_queries(idx, np.repeat(src, 20), tgt.ravel())
+    assert np.array_equal(sub, clamp32(D[np.repeat(np.arange(60), 20), tgt.ravel()]))
+    # the batch's own first pairs
+    assert np.array_equal(out[:60], clamp32(D[np.arange(60), g["v2"][:60]]))
