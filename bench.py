@@ -34,50 +34,77 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--queries", type=int, default=100_000)
+    p.add_argument("--workload", default="grid256d", choices=sorted(WORKLOADS))
+    p.add_argument("--queries", type=int, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     return p.parse_args()
 
 
+WORKLOADS = {
+    "grid256d": dict(
+        queries=100_000,
+        desc="grid256d: 256x256 grid + random cell diagonals, weights U[1,1000], 1,024 blocks "
+             "of 8x8, %d uniform query pairs"),
+    "delaunay1m": dict(
+        queries=100_000,
+        desc="delaunay1m: Delaunay triangulation of 1M uniform points, weight rint(length*1e6), "
+             "4,096 recursive-bisection parts, two-level BG, %d uniform query pairs"),
+    "grid2048": dict(
+        queries=10_000_000,
+        desc="grid2048: 2048x2048 grid minus 10%% of edges (connected), lognormal weights, 16,384 "
+             "blocks of 16x16; one GPU's share = BG rows of components [0,512); %d pairs with v1 "
+             "in the share"),
+}
+
+
+def make_workload(name, queries):
+    from paper_1503_07192_amd import workloads as W
+    if name == "grid256d":
+        return W.grid256d(queries=queries), {}
+    if name == "delaunay1m":
+        return W.delaunay1m(queries=queries), {}
+    g = W.grid2048(queries=queries)
+    return g, {"share_comps": g["share_k"]}
+
+
 def cpu_baseline(g, st, budget_s):
-    """The oracle on a bounded sample of the same workload, scaled up."""
+    """The oracle as it stands, timed on a bounded sample of the same workload."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     n, k = g["n"], g["k"]
+    rng = np.random.default_rng(0)
+    comps = np.arange(k) if k <= 1024 else np.sort(rng.choice(k, 1024, replace=False))
     t0 = time.perf_counter()
-    members, apsp = oracle.component_apsp(n, g["eu"], g["ev"], g["w"], g["part"], k,
+    members, apsp = oracle.component_apsp(n, g["eu"], g["ev"], g["w"], g["part"], k, comps=comps,
                                           nthreads=threads)
     t_comp = time.perf_counter() - t0
-    bg_ids, bverts, bu, bv, bw = oracle.boundary_graph(n, g["eu"], g["ev"], g["w"], g["part"], k,
-                                                       members, apsp)
-    V = len(bg_ids)
-    # time a few sources first, then size the sample to the budget
-    t0 = time.perf_counter()
-    oracle.bg_apsp(bg_ids, bu, bv, bw, sources=np.arange(64), nthreads=threads)
-    per_src = (time.perf_counter() - t0) / 64
-    nsrc = int(min(V, max(64, budget_s * 0.6 / max(per_src, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.bg_apsp(bg_ids, bu, bv, bw, sources=np.arange(nsrc), nthreads=threads)
-    t_bg_sample = time.perf_counter() - t0
-    t_bg = t_bg_sample * V / nsrc
-    relax = st["relax_comp"] + st["relax_bg"]
-    build_s = t_comp + t_bg
-    # the paper's baseline for queries: one Dijkstra per query on G
-    nq = 64
+    relax_sample = float(sum(len(m) ** 3 for m in members))
+    res = {"value": relax_sample / t_comp, "unit": "relax/s", "cores": threads, "kind": "oracle",
+           "sample": "Floyd-Warshall of %d of %d components (%.3g relaxations, %.2f s)"
+                     % (len(comps), k, relax_sample, t_comp)}
+    if k <= 1024:
+        # the paper's Phase 3: Dijkstra in BG from a budgeted number of sources
+        bg_ids, bverts, bu, bv, bw = oracle.boundary_graph(n, g["eu"], g["ev"], g["w"], g["part"],
+                                                           k, members, apsp)
+        V = len(bg_ids)
+        t0 = time.perf_counter()
+        oracle.bg_apsp(bg_ids, bu, bv, bw, sources=np.arange(min(64, V)), nthreads=threads)
+        per_src = (time.perf_counter() - t0) / min(64, V)
+        nsrc = int(min(V, max(64, budget_s * 0.6 / max(per_src, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.bg_apsp(bg_ids, bu, bv, bw, sources=np.arange(nsrc), nthreads=threads)
+        t_bg = (time.perf_counter() - t0) * V / nsrc
+        res["index_build_s"] = t_comp + t_bg
+        res["sample"] += ("; Dijkstra in BG from %d of %d sources, scaled: whole index in %.1f s"
+                          % (nsrc, V, t_comp + t_bg))
+    # the paper's comparison for queries: one Dijkstra per query on G
+    nq = 16
     t0 = time.perf_counter()
     oracle.dijkstra(n, g["eu"], g["ev"], g["w"], g["v1"][:nq], nthreads=threads)
-    q_s = (time.perf_counter() - t0) / nq
-    return {
-        "value": relax / build_s, "unit": "relax/s (Floyd-Warshall equivalent)",
-        "cores": threads, "kind": "oracle",
-        "sample": ("all %d component Floyd-Warshalls (%.2f s) + Dijkstra in BG from %d of %d "
-                   "sources (%.2f s, scaled x%.1f); index build extrapolated to %.1f s"
-                   % (k, t_comp, nsrc, V, t_bg_sample, V / nsrc, build_s)),
-        "build_s": build_s,
-        "queries_per_s": 1.0 / q_s,
-        "query_sample": "Dijkstra on G from the first %d query sources" % nq,
-    }
+    res["queries_per_s"] = nq / (time.perf_counter() - t0)
+    res["query_sample"] = "Dijkstra on G from %d query sources, %d threads" % (nq, threads)
+    return res
 
 
 def main():
@@ -90,7 +117,9 @@ def main():
     from paper_1503_07192_amd import spq, workloads as W
 
     torch.cuda.set_device(0)
-    g = W.grid256d(queries=args.queries)
+    wl = WORKLOADS[args.workload]
+    nq = args.queries or wl["queries"]
+    g, build_kw = make_workload(args.workload, nq)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
     eu, ev, w, part = dev(g["eu"]), dev(g["ev"]), dev(g["w"]), dev(g["part"])
     v1, v2 = dev(g["v1"]), dev(g["v2"])
@@ -99,7 +128,8 @@ def main():
     torch.cuda.synchronize()
 
     def step(record):
-        idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], profile=True, stream=stream)
+        idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], profile=True, stream=stream,
+                              **build_kw)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         spq.query_batch(idx, v1, v2, out, stream=stream)
@@ -129,15 +159,17 @@ def main():
     mq = np.array([r["ms_query"] for r in recs])
     # dominant kernel: the BG interior-tile launches, timed with HIP events on
     # the build stream inside the timed steps
-    inner_ms = np.array([r["ms_fw_inner"] for r in recs])
-    launches = st["fw_inner_launches"]
+    inner_ms = np.array([r["ms_dominant"] for r in recs])
+    launches = st["dominant_launches"]
     avg_launch_ms = float(np.median(inner_ms)) / launches
-    per_launch = st["relax_fw_inner"] / launches
+    per_launch = st["relax_dominant"] / launches
     inner_rate = per_launch / (avg_launch_ms * 1e-3)
+    kernel = ("k_fw_inner (BG interior tiles, 128x128, K chunk 16)" if st["bg_method"] == 1 else
+              "k_mp_y (two-level composition product, 128x128 tiles, K chunk 16)")
 
     # the plain comparators, after the timed region: one launch per component
     # for APSP(C), and one query per launch
-    idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], plain=True, stream=stream)
+    idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], plain=True, stream=stream, **build_kw)
     plain_st = spq.index_stats(idx)
     lat = []
     for i in range(200):
@@ -163,9 +195,11 @@ def main():
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "grid256d: 256x256 grid + random cell diagonals, weights U[1,1000], "
-                               "1,024 blocks of 8x8, %d uniform query pairs" % q,
-                   "n": g["n"], "m": g["m"], "k": g["k"], "v_bg": st["v_bg"], "queries": q},
+        "config": {"workload": wl["desc"] % q, "name": args.workload,
+                   "n": g["n"], "m": g["m"], "k": g["k"], "v_bg": st["v_bg"], "queries": q,
+                   "bg_method": "flat" if st["bg_method"] == 1 else "two-level",
+                   "groups": st["ngroups"], "v_bg2": st["v_bg2"],
+                   "share_comps": st["share_comps"], "bg_bytes": st["bg_bytes"]},
         "phase_ms": {key: float(np.median([r[key] for r in recs]))
                      for key in ("ms_partition", "ms_components", "ms_bg_assembly",
                                  "ms_bg_apsp", "ms_query")},
@@ -178,7 +212,7 @@ def main():
         "batched_components_ms": float(np.median([r["ms_components"] for r in recs])),
         "single_query_us_p50": float(np.percentile(lat, 50)),
         "single_query_us_p99": float(np.percentile(lat, 99)),
-        "roofline": {"bound": "alu", "kernel": "k_fw_inner (BG interior tiles, 128x128, K chunk 16)",
+        "roofline": {"bound": "alu", "kernel": kernel,
                      "achieved": inner_rate / 1e12, "peak": RELAX_PEAK / 1e12,
                      "unit": "Trelax/s", "frac": inner_rate / RELAX_PEAK, "traffic": None,
                      "launches_per_step": launches, "avg_launch_ms": avg_launch_ms,

@@ -50,8 +50,8 @@ typedef struct spq_index spq_index; /* opaque; owns all its device memory */
 
 typedef struct {
   int32_t bg_tile;     /* tile of the BG Floyd-Warshall: 0 (default 128), 64, 128 */
-  int32_t profile;     /* 1: time every interior-tile launch of the BG
-                          Floyd-Warshall with HIP events (see spq_stats) */
+  int32_t profile;     /* 1: time every launch of the dominant BG kernel with
+                          HIP events (see spq_stats) */
   int32_t plain;       /* 1: one kernel launch per component for APSP(C)
                           instead of one launch for all (comparison path) */
   int32_t bg_method;   /* 0 auto (flat up to 32,768 BG vertices), 1 flat
@@ -82,9 +82,11 @@ typedef struct {
   double relax_comp_exec;  /* relaxations the kernels execute for Phase 2 (padded
                               tiles; symmetric tiles computed once) */
   double relax_bg_exec;    /* same for BG */
-  double relax_fw_inner;   /* executed by the BG interior-tile launches */
-  int64_t fw_inner_launches; /* number of BG interior-tile launches */
-  float ms_fw_inner;       /* their summed device time (only with opts.profile) */
+  double relax_dominant;   /* executed by the launches of the dominant BG kernel:
+                              interior tiles (flat) or the composition product
+                              (two-level, share) */
+  int64_t dominant_launches; /* number of those launches */
+  float ms_dominant;       /* their summed device time (only with opts.profile) */
   int32_t bg_method;       /* 1 flat, 2 two-level */
   int32_t ngroups;         /* groups of the two-level method (1 when flat) */
   int32_t v_bg2;           /* level-2 boundary vertices (two-level) */

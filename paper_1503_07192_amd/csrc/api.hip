@@ -104,7 +104,8 @@ struct spq_index {
 // Share mode (after level 1): Bellman-Ford over groups from the share's
 // level-2 vertices, then the composition for the share's groups against all
 // groups.  Synchronous (one small readback per round).
-static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, hipStream_t s) {
+static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool profile,
+                              hipStream_t s) {
   const int32_t G = X->ngroups, Vgp = X->Vgp;
   X->share_groups = std::min(G, (X->share_comps + X->cpg - 1) / X->cpg);
   X->S2 = X->h_b2off[X->share_groups];
@@ -165,9 +166,17 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, hipStr
     for (int32_t a2 = 0; a2 < G; a2++) {
       X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * (Vgp / 128) * 128.0 * 128.0 *
                           (double)round_up(X->h_m2[a1], 16);
-      X->relax_bg_exec += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) *
-                          128.0 * 128.0 * (double)round_up(X->h_m2[a2], 16);
+      const double y = (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
+                       128.0 * (double)round_up(X->h_m2[a2], 16);
+      X->relax_bg_exec += y;
+      X->relax_inner += y;
     }
+  X->inner_launches = X->share_groups;
+  if (profile) {
+    X->prof.resize(2 * X->share_groups);
+    for (auto& e : X->prof) HIP_TRY(hipEventCreate(&e));
+    ha.evt = X->prof.data();
+  }
   HIP_TRY(spq::launch_share_compose(ha, bufs[cur], s));
   return SPQ_OK;
 }
@@ -467,7 +476,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     X->V2p = round_up(X->V2, 128);
     X->m2pmax = (int32_t)std::max<int64_t>(128, round_up(m2max, 128));
     if (X->share_comps > 0) {
-      spq_status ss = build_share(X, ha, m, s);
+      spq_status ss = build_share(X, ha, m, profile, s);
       if (ss != SPQ_OK) return guard(ss);
       TRY(hipEventRecord(X->ev[4], s));
       *out = X;
@@ -489,6 +498,16 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
         X->relax_bg_exec += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) *
                             128.0 * 128.0 * (double)round_up(X->h_m2[a2], 16);
       }
+    for (int32_t a1 = 0; a1 < G; a1++)
+      for (int32_t a2 = a1; a2 < G; a2++)
+        X->relax_inner += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
+                          128.0 * (double)round_up(X->h_m2[a2], 16);
+    X->inner_launches = G;
+    if (profile) {
+      X->prof.resize(2 * G);
+      for (auto& e : X->prof) TRY(hipEventCreate(&e));
+      ha.evt = X->prof.data();
+    }
     TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
     TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
     TRY(dalloc(&X->XT, (int64_t)G * X->m2pmax * Vgp));
@@ -553,8 +572,8 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   st->relax_bg = X->relax_bg;
   st->relax_comp_exec = X->relax_comp_exec;
   st->relax_bg_exec = X->relax_bg_exec;
-  st->relax_fw_inner = X->relax_inner;
-  st->fw_inner_launches = X->inner_launches;
+  st->relax_dominant = X->relax_inner;
+  st->dominant_launches = X->inner_launches;
   st->bg_method = X->method;
   st->ngroups = X->ngroups;
   st->v_bg2 = X->V2;
@@ -569,7 +588,7 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   for (size_t i = 0; i + 1 < X->prof.size(); i += 2) {
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, X->prof[i], X->prof[i + 1]));
-    st->ms_fw_inner += ms;
+    st->ms_dominant += ms;
   }
   HIP_TRY(hipEventElapsedTime(&st->ms_partition, X->ev[0], X->ev[1]));
   HIP_TRY(hipEventElapsedTime(&st->ms_components, X->ev[1], X->ev[2]));

@@ -592,9 +592,17 @@ hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s) {
     if (a.V2p > 0)
       k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(s1, s1, a.Vgp, a.m2pmax, a.m2, a.b2off,
                                                                  a.BG2, a.V2p, a.R, a.XT);
+    if (a.evt) {
+      hipError_t e = hipEventRecord(a.evt[2 * s1], s);
+      if (e != hipSuccess) return e;
+    }
     k_mp_y<<<dim3((unsigned)(ntx * ntx), pairs), 256, 0, s>>>(
         s1, s1, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
         a.bgnb, a.bglocal, a.H);
+    if (a.evt) {
+      hipError_t e = hipEventRecord(a.evt[2 * s1 + 1], s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipGetLastError();
 }
@@ -642,9 +650,17 @@ hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s)
   for (int32_t s1 = 0; s1 < a.share_groups; s1++) {
     k_mp_xt<<<dim3((unsigned)(ntm * ntx), (unsigned)a.ngroups), 256, 0, s>>>(
         s1, 0, a.Vgp, a.m2pmax, a.m2, a.b2off, a.BG2, a.V2p, a.R, a.XT);
+    if (a.evt) {
+      hipError_t e = hipEventRecord(a.evt[2 * s1], s);
+      if (e != hipSuccess) return e;
+    }
     k_mp_y<<<dim3((unsigned)(ntx * ntx), (unsigned)a.ngroups), 256, 0, s>>>(
         s1, 0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
         a.bgnb, a.bglocal, a.H);
+    if (a.evt) {
+      hipError_t e = hipEventRecord(a.evt[2 * s1 + 1], s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipGetLastError();
 }

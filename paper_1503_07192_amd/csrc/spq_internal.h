@@ -90,6 +90,7 @@ struct HierArgs {
   u32 *A, *DT, *DT2;               // A_S blocks; Bellman-Ford buffers (V2p x S2p)
   int4* xe;                        // directed cross edges
   int32_t* xcount;
+  hipEvent_t* evt;                 // NULL, or 2 per composition launch (k_mp_y)
 };
 hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s);
 hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, u32* changed,

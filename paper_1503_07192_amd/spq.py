@@ -45,8 +45,8 @@ class Stats(ctypes.Structure):
                 ("comp_bytes", ctypes.c_int64), ("bg_bytes", ctypes.c_int64),
                 ("relax_comp", ctypes.c_double), ("relax_bg", ctypes.c_double),
                 ("relax_comp_exec", ctypes.c_double), ("relax_bg_exec", ctypes.c_double),
-                ("relax_fw_inner", ctypes.c_double), ("fw_inner_launches", ctypes.c_int64),
-                ("ms_fw_inner", ctypes.c_float),
+                ("relax_dominant", ctypes.c_double), ("dominant_launches", ctypes.c_int64),
+                ("ms_dominant", ctypes.c_float),
                 ("bg_method", ctypes.c_int32), ("ngroups", ctypes.c_int32),
                 ("v_bg2", ctypes.c_int32), ("share_comps", ctypes.c_int32),
                 ("share_groups", ctypes.c_int32), ("bf_rounds", ctypes.c_int32),
