@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--queries", type=int, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     return p.parse_args()
 
 
@@ -125,6 +127,11 @@ def main():
     v1, v2 = dev(g["v1"]), dev(g["v2"])
     out = torch.empty_like(v1)
     stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        del src, dst
     torch.cuda.synchronize()
 
     def step(record):
