@@ -174,6 +174,26 @@ def main():
     kernel = ("k_fw_inner (BG interior tiles, 128x128, K chunk 16)" if st["bg_method"] == 1 else
               "k_mp_y (two-level composition product, 128x128 tiles, K chunk 16)")
 
+    # the other BG method on the same workload, after the timed region: same
+    # answers (checked on the whole query batch), different work
+    alt = None
+    if args.workload == "grid256d":
+        ref = out.clone()
+        for method, gc in ((2, 32),):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], bg_method=method, group_comps=gc,
+                                  stream=stream)
+            spq.query_batch(idx, v1, v2, out, stream=stream)
+            torch.cuda.synchronize()
+            t_alt = time.perf_counter() - t1
+            ast = spq.index_stats(idx)
+            alt = {"bg_method": "two-level", "groups": ast["ngroups"], "v_bg2": ast["v_bg2"],
+                   "step_ms": t_alt * 1e3, "ms_bg": ast["ms_bg_apsp"],
+                   "relax_executed": ast["relax_comp_exec"] + ast["relax_bg_exec"],
+                   "answers_identical": bool(torch.equal(ref, out))}
+            idx.free()
+
     # the plain comparators, after the timed region: one launch per component
     # for APSP(C), and one query per launch
     idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], plain=True, stream=stream, **build_kw)
@@ -215,6 +235,7 @@ def main():
         "queries_per_s": q / (np.median(mq) * 1e-3),
         "query_batch_ms_p50": float(np.percentile(mq, 50)),
         "query_batch_ms_p99": float(np.percentile(mq, 99)),
+        "other_bg_method": alt,
         "plain_components_ms": plain_st["ms_components"],
         "batched_components_ms": float(np.median([r["ms_components"] for r in recs])),
         "single_query_us_p50": float(np.percentile(lat, 50)),

@@ -107,6 +107,7 @@ struct spq_index {
 static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool profile,
                               hipStream_t s) {
   const int32_t G = X->ngroups, Vgp = X->Vgp;
+  if (G > 65535) return fail(SPQ_EINVAL, "share mode supports at most 65,535 groups");
   X->share_groups = std::min(G, (X->share_comps + X->cpg - 1) / X->cpg);
   X->S2 = X->h_b2off[X->share_groups];
   X->S2p = round_up(std::max<int32_t>(X->S2, 1), 128);
@@ -132,7 +133,7 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   HIP_TRY(dalloc(&X->pairbase, (int64_t)G * G));
   HIP_TRY(dalloc(&X->xe, 2 * std::max<int64_t>(m, 1)));
   HIP_TRY(dalloc(&X->xcount, 1));
-  HIP_TRY(dalloc(&X->bfflag, 1));
+  HIP_TRY(dalloc(&X->bfflag, 2 * (int64_t)G));
   HIP_TRY(hipMemsetAsync(X->xcount, 0, sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(X->DT + V2p * X->S2p, 0xff, 128 * X->S2p * sizeof(u32), s));
   HIP_TRY(hipMemcpyAsync(X->pairbase, X->h_pairbase.data(), sizeof(int64_t) * G * G,
@@ -147,20 +148,27 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   HIP_TRY(hipStreamSynchronize(s));
   u32* bufs[2] = {X->DT, X->DT2};
   int cur = 0;
-  double intra = 0;
-  for (int32_t g = 0; g < G; g++)
-    intra += (double)((X->h_m2[g] + 127) / 128) * (double)(X->S2p / 128) * 128.0 * 128.0 *
-             (double)round_up(X->h_m2[g], 16);
+  // dirty flags per group, two rounds' worth; the share's groups start dirty
+  std::vector<u32> hd(G, 0);
+  for (int32_t g = 0; g < X->share_groups; g++) hd[g] = 1;
+  HIP_TRY(hipMemcpyAsync(X->bfflag, hd.data(), sizeof(u32) * G, hipMemcpyHostToDevice, s));
+  u32* dcur = X->bfflag;
+  u32* dnext = X->bfflag + G;
   for (;;) {
     if (++X->bf_rounds > 100000) return fail(SPQ_EDEVICE, "Bellman-Ford over groups did not settle");
-    u32 changed = 0;
-    HIP_TRY(hipMemsetAsync(X->bfflag, 0, sizeof(u32), s));
-    HIP_TRY(spq::launch_share_round(ha, bufs[cur], bufs[cur ^ 1], nxe, X->bfflag, s));
-    HIP_TRY(hipMemcpyAsync(&changed, X->bfflag, sizeof(u32), hipMemcpyDeviceToHost, s));
+    for (int32_t g = 0; g < G; g++)
+      if (hd[g])
+        X->relax_bg_exec += (double)((X->h_m2[g] + 127) / 128) * (double)(X->S2p / 128) * 128.0 *
+                            128.0 * (double)round_up(X->h_m2[g], 16);
+    HIP_TRY(hipMemsetAsync(dnext, 0, sizeof(u32) * G, s));
+    HIP_TRY(spq::launch_share_round(ha, bufs[cur], bufs[cur ^ 1], nxe, dcur, dnext, s));
+    HIP_TRY(hipMemcpyAsync(hd.data(), dnext, sizeof(u32) * G, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     cur ^= 1;
-    X->relax_bg_exec += intra + (double)nxe * X->S2;
-    if (!changed) break;
+    std::swap(dcur, dnext);
+    bool any = false;
+    for (int32_t g = 0; g < G; g++) any |= hd[g] != 0;
+    if (!any) break;
   }
   for (int32_t a1 = 0; a1 < X->share_groups; a1++)
     for (int32_t a2 = 0; a2 < G; a2++) {

@@ -452,12 +452,16 @@ __global__ void k_dt_init(int32_t V2, int32_t S2, int64_t S2p, int32_t ngroups,
     out[i] = (i == b) ? 0u : (i >= lo && i < hi) ? prow[list[i - lo]] : INF;
 }
 
-// Intra-group step, out of place: rows B2(S) of DTn = min(DTo, A_S (x) DTo).
+// Intra-group step, out of place: rows B2(S) of DTn = min(DTo, A_S (x) DTo)
+// for the groups whose rows changed in the previous round (dirty); the rows of
+// the other groups are carried over unchanged.  One product with the closed
+// A_S leaves the group's rows closed, so the step is exact.
 __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
                                                   const int32_t* __restrict__ m2,
                                                   const int32_t* __restrict__ b2off,
                                                   const u32* __restrict__ A, const u32* __restrict__ DTo,
-                                                  u32* __restrict__ DTn, u32* __restrict__ changed) {
+                                                  u32* __restrict__ DTn,
+                                                  const u32* __restrict__ dirty) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
   const int s = blockIdx.y;
@@ -468,16 +472,12 @@ __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
   const int64_t r0 = b2off[s];
   u32 c[8][8];
   tile_load<128>(c, DTo + (r0 + ti * 128) * S2p + tj * 128, S2p);  // rows past ms: unused
-  u32 old[8][8];
-#pragma unroll
-  for (int i = 0; i < 8; i++)
-#pragma unroll
-    for (int j = 0; j < 8; j++) old[i][j] = c[i][j];
-  const u32* At = A + (int64_t)s * m2pmax * m2pmax + ti * 128;  // A_S symmetric: At[k][i] = A[i][k]
-  const u32* B = DTo + r0 * S2p + tj * 128;
-  mp_stream128<true>(c, At, m2pmax, B, S2p, (ms + 15) / 16 * 16, ms, ms - ti * 128, sA, sB);
+  if (dirty[s]) {
+    const u32* At = A + (int64_t)s * m2pmax * m2pmax + ti * 128;  // A_S symmetric: At[k][i] = A[i][k]
+    const u32* B = DTo + r0 * S2p + tj * 128;
+    mp_stream128<true>(c, At, m2pmax, B, S2p, (ms + 15) / 16 * 16, ms, ms - ti * 128, sA, sB);
+  }
   const int tx = tid_x(), ty = tid_y();
-  u32 diff = 0;
 #pragma unroll
   for (int h = 0; h < 2; h++)
 #pragma unroll
@@ -488,13 +488,10 @@ __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
 #pragma unroll
       for (int h2 = 0; h2 < 2; h2++) {
         const int i = h * 4 + a, j = h2 * 4;
-        diff |= (c[i][j] != old[i][j]) | (c[i][j + 1] != old[i][j + 1]) |
-                (c[i][j + 2] != old[i][j + 2]) | (c[i][j + 3] != old[i][j + 3]);
         *reinterpret_cast<uint4*>(dst + h2 * 64 + tx * 4) =
             make_uint4(c[i][j], c[i][j + 1], c[i][j + 2], c[i][j + 3]);
       }
     }
-  if (diff) atomicOr(changed, 1u);
 }
 
 // Cross edges between groups, as directed level-2 pairs (a -> b, w).
@@ -514,17 +511,21 @@ __global__ void k_cross_collect(int64_t m, const int32_t* __restrict__ eu, const
     const int32_t a = b2off[su] + b2rank[bgoff[cu] + local[u]];
     const int32_t b = b2off[sv] + b2rank[bgoff[cv] + local[v]];
     const int32_t slot = atomicAdd(count, 2);
-    xe[slot] = make_int4(a, b, w[e], 0);
-    xe[slot + 1] = make_int4(b, a, w[e], 0);
+    xe[slot] = make_int4(a, b, w[e], (su << 16) | sv);
+    xe[slot + 1] = make_int4(b, a, w[e], (sv << 16) | su);
   }
 }
 
-// DT[b][i] = min(DT[b][i], DT[a][i] + w) for every directed cross edge.
+// DT[b][i] = min(DT[b][i], DT[a][i] + w) for every directed cross edge whose
+// source group is dirty (a row that has not changed since it was last
+// propagated needs no new pass); a lowered row marks its group dirty for the
+// next round.
 __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2, int64_t S2p, u32* DT,
-                           u32* __restrict__ changed) {
+                           const u32* __restrict__ dirty, u32* __restrict__ dirty_next) {
   const int32_t e = blockIdx.x;
   if (e >= nxe) return;
   const int4 t = xe[e];
+  if (!dirty[t.w >> 16]) return;
   const u32* src = DT + (int64_t)t.x * S2p;
   u32* dst = DT + (int64_t)t.y * S2p;
   u32 diff = 0;
@@ -535,7 +536,7 @@ __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2,
       diff = 1;
     }
   }
-  if (diff) atomicOr(changed, 1u);
+  if (diff) dirty_next[t.w & 0xffff] = 1u;
 }
 
 // D2s (S2p x V2p) = DT^T, 32 x 32 tiles through LDS.
@@ -634,12 +635,13 @@ hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s) {
 }
 
 // One Bellman-Ford round: DT (in) -> DT2 (intra) -> cross edges on DT2.
-hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, u32* changed,
-                              hipStream_t s) {
+hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, const u32* dirty,
+                              u32* dirty_next, hipStream_t s) {
   const int ntm = a.m2pmax / 128, ntc = (int)(a.S2p / 128);
   k_bf_intra<<<dim3((unsigned)(ntm * ntc), (unsigned)a.ngroups), 256, 0, s>>>(
-      a.m2pmax, a.S2p, a.m2, a.b2off, a.A, DTin, DTout, changed);
-  if (nxe > 0) k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, DTout, changed);
+      a.m2pmax, a.S2p, a.m2, a.b2off, a.A, DTin, DTout, dirty);
+  if (nxe > 0)
+    k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, DTout, dirty, dirty_next);
   return hipGetLastError();
 }
 

@@ -93,8 +93,8 @@ struct HierArgs {
   hipEvent_t* evt;                 // NULL, or 2 per composition launch (k_mp_y)
 };
 hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s);
-hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, u32* changed,
-                              hipStream_t s);
+hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, const u32* dirty,
+                              u32* dirty_next, hipStream_t s);
 hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s);
 hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
 hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s);
