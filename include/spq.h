@@ -65,7 +65,9 @@ typedef struct {
                           BG; queries then need v1 in a share component.
                           Two-level method; the share is rounded up to whole
                           groups; needs the total edge weight below SPQ_INF */
-  int32_t reserved[2]; /* must be 0 */
+  int32_t inner_kc;    /* K chunk of the Floyd-Warshall interior-tile kernel:
+                          0 (default 16), 16 or 32 (see the autotuner) */
+  int32_t reserved[1]; /* must be 0 */
 } spq_build_opts;
 
 typedef struct {
@@ -185,14 +187,16 @@ const char* spq_last_error(void);
  *   and 0 on it.  One workgroup closes one whole matrix (the APSP(C) kernel).
  * spq_fw_dense: one v x v matrix with leading dimension ld (a multiple of
  *   tile, padded like above); blocked Floyd-Warshall in rounds of three
- *   kernels (the BG kernel).  tile is 64 or 128.
+ *   kernels (the BG kernel).  tile is 64 or 128; kc (K chunk of the interior
+ *   kernel) is 0 (default), 16 or 32.
  * spq_fw_components stages its size tables on the device and returns when
  * the work is done; spq_fw_dense is asynchronous on `stream`.
  * Errors: SPQ_EINVAL, SPQ_ENOMEM, SPQ_EDEVICE.
  */
 spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* off,
                              const int32_t* ld, int32_t* data, void* stream);
-spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t* data, void* stream);
+spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t kc, int32_t* data,
+                        void* stream);
 
 #ifdef __cplusplus
 }

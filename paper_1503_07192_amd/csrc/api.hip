@@ -244,7 +244,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   if (n > 0x7fffffff - 1) return fail(SPQ_EINVAL, "n too large");
   int tile = 128;
   bool profile = false, plain = false;
-  int32_t method_opt = 0, group_comps = 0, share_comps = 0;
+  int32_t method_opt = 0, group_comps = 0, share_comps = 0, inner_kc = 0;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
@@ -260,7 +260,10 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     if (share_comps == k) share_comps = 0;
     if (share_comps > 0 && method_opt == 1)
       return fail(SPQ_EINVAL, "a share needs the two-level method");
-    for (int i = 0; i < 2; i++)
+    inner_kc = opts->inner_kc;
+    if (inner_kc != 0 && inner_kc != 16 && inner_kc != 32)
+      return fail(SPQ_EINVAL, "inner_kc must be 0, 16 or 32");
+    for (int i = 0; i < 1; i++)
       if (opts->reserved[i]) return fail(SPQ_EINVAL, "reserved options must be 0");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -463,7 +466,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     TRY(dalloc(&X->bgnb, V));
     TRY(dalloc(&X->bggrp, V));
     if (V > 0) TRY(hipMemsetAsync(X->flag2, 0, V, s));
-    ha.V = V; ha.ngroups = G; ha.Vgp = Vgp; ha.m = m;
+    ha.V = V; ha.ngroups = G; ha.Vgp = Vgp; ha.m = m; ha.kc = inner_kc;
     ha.eu = eu; ha.ev = ev; ha.w = w; ha.comp = X->comp; ha.local = X->local; ha.bgoff = X->bgoff;
     ha.nb = X->nb; ha.bgcomp = X->bgcomp; ha.bglocal = X->bglocal; ha.P = X->P; ha.moff = X->moff;
     ha.M = X->M; ha.grp = X->grp; ha.gbg0 = X->gbg0; ha.gV = X->gV; ha.bgrow = X->bgrow;
@@ -545,7 +548,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     for (auto& e : X->prof) TRY(hipEventCreate(&e));
   }
   TRY(spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, s,
-                           X->prof.empty() ? nullptr : X->prof.data()));
+                           X->prof.empty() ? nullptr : X->prof.data(), inner_kc));
   TRY(hipEventRecord(X->ev[4], s));
 #undef TRY
   spq_status cs = certify(X, m, eu, ev, s);
@@ -688,12 +691,14 @@ spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* 
   return SPQ_OK;
 }
 
-spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t* data, void* stream) {
+spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t kc, int32_t* data,
+                        void* stream) {
   if (tile != 64 && tile != 128) return fail(SPQ_EINVAL, "tile must be 64 or 128");
+  if (kc != 0 && kc != 16 && kc != 32) return fail(SPQ_EINVAL, "kc must be 0, 16 or 32");
   if (v < 0 || ld < v || ld % tile || (v > 0 && !data)) return fail(SPQ_EINVAL, "bad v or ld");
   if (v == 0) return SPQ_OK;
   HIP_TRY(spq::launch_dense_fw(reinterpret_cast<u32*>(data), ld, tile, ld / tile,
-                               reinterpret_cast<hipStream_t>(stream), nullptr));
+                               reinterpret_cast<hipStream_t>(stream), nullptr, kc));
   return SPQ_OK;
 }
 

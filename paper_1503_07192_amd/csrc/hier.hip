@@ -569,7 +569,7 @@ hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s) {
     k_grp_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
                                              a.gbg0, a.Vgp, a.Mg, a.flag2);
   hipError_t e = launch_dense_fw_batch(a.Mg, a.Vgp, 128, a.Vgp / 128, a.ngroups,
-                                       (int64_t)a.Vgp * a.Vgp, s, nullptr);
+                                       (int64_t)a.Vgp * a.Vgp, s, nullptr, a.kc);
   if (e != hipSuccess) return e;
   k_b2_scan<<<(unsigned)a.ngroups, 256, 0, s>>>(a.gbg0, a.gV, a.flag2, a.Vgp, a.b2list, a.b2rank, a.m2);
   return hipGetLastError();
@@ -584,7 +584,7 @@ hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s) {
     if (a.m > 0)
       k_bg2_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
                                                a.b2off, a.b2rank, a.V2p, a.BG2);
-    hipError_t e = launch_dense_fw(a.BG2, a.V2p, 128, (int)(a.V2p / 128), s, nullptr);
+    hipError_t e = launch_dense_fw(a.BG2, a.V2p, 128, (int)(a.V2p / 128), s, nullptr, a.kc);
     if (e != hipSuccess) return e;
   }
   const int ntx = a.Vgp / 128, ntm = a.m2pmax / 128;

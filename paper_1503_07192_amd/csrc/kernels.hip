@@ -555,7 +555,7 @@ hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s) {
 #define SPQ_INNER_KC 16
 #endif
 
-template <int T>
+template <int T, int KC>
 static hipError_t fw_rounds(u32* A, int64_t ld, int nt, int batch, int64_t gstride, hipStream_t s,
                            hipEvent_t* ev) {
   for (int r = 0; r < nt; r++) {
@@ -566,7 +566,7 @@ static hipError_t fw_rounds(u32* A, int64_t ld, int nt, int batch, int64_t gstri
         hipError_t e = hipEventRecord(ev[2 * r], s);
         if (e != hipSuccess) return e;
       }
-      k_fw_inner<T, SPQ_INNER_KC><<<dim3((unsigned)((nt - 1) * nt / 2), batch), 256, 0, s>>>(
+      k_fw_inner<T, KC><<<dim3((unsigned)((nt - 1) * nt / 2), batch), 256, 0, s>>>(
           A, ld, r, nt, gstride);
       if (ev) {
         hipError_t e = hipEventRecord(ev[2 * r + 1], s);
@@ -577,15 +577,21 @@ static hipError_t fw_rounds(u32* A, int64_t ld, int nt, int batch, int64_t gstri
   LAUNCH_CHECK();
 }
 
-hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev) {
-  return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev);
+hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev,
+                           int kc) {
+  return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev, kc);
 }
 
+// kc: K chunk of the interior-tile kernel (16 or 32; 0 = SPQ_INNER_KC)
 hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
-                                 hipStream_t s, hipEvent_t* ev) {
+                                 hipStream_t s, hipEvent_t* ev, int kc) {
   if (nt <= 0 || batch <= 0) return hipSuccess;
-  if (tile == 64) return fw_rounds<64>(A, ld, nt, batch, gstride, s, ev);
-  return fw_rounds<128>(A, ld, nt, batch, gstride, s, ev);
+  if (kc == 0) kc = SPQ_INNER_KC;
+  if (tile == 64)
+    return kc == 32 ? fw_rounds<64, 32>(A, ld, nt, batch, gstride, s, ev)
+                    : fw_rounds<64, 16>(A, ld, nt, batch, gstride, s, ev);
+  return kc == 32 ? fw_rounds<128, 32>(A, ld, nt, batch, gstride, s, ev)
+                  : fw_rounds<128, 16>(A, ld, nt, batch, gstride, s, ev);
 }
 
 double dense_fw_exec_relax(int64_t nt, int tile) {

@@ -71,7 +71,7 @@ struct QueryArgs {
 
 // Two-level BG (hier.hip).
 struct HierArgs {
-  int32_t V, ngroups, Vgp, m2pmax, V2;
+  int32_t V, ngroups, Vgp, m2pmax, V2, kc;
   int64_t m, V2p;
   const int32_t *eu, *ev, *w, *comp, *local, *bgoff, *nb, *bgcomp, *bglocal, *P;
   const int64_t* moff;
@@ -121,11 +121,13 @@ hipError_t launch_components(const CompArgs& a, hipStream_t s);
 hipError_t launch_comp_fw(int32_t count, const int32_t* order, const int32_t* P, const int64_t* moff,
                           u32* M, hipStream_t s);
 hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s);
-// ev: NULL, or 2*nt events recorded around each interior-tile launch
-hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev);
+// ev: NULL, or 2*nt events recorded around each interior-tile launch;
+// kc: K chunk of the interior-tile kernel, 16 or 32 (0 = default)
+hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev,
+                           int kc = 0);
 // `batch` matrices of the same shape, gstride elements apart
 hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
-                                 hipStream_t s, hipEvent_t* ev);
+                                 hipStream_t s, hipEvent_t* ev, int kc = 0);
 // relaxations executed by launch_dense_fw (diagonal, panel and upper-triangle
 // interior tiles of every round)
 double dense_fw_exec_relax(int64_t nt, int tile);

@@ -35,7 +35,7 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("bg_tile", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("plain", ctypes.c_int32), ("bg_method", ctypes.c_int32),
                 ("group_comps", ctypes.c_int32), ("share_comps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("inner_kc", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -68,7 +68,7 @@ _SIGS = {
     "spq_free_index": (None, [P]),
     "spq_last_error": (ctypes.c_char_p, []),
     "spq_fw_components": (I32, [I32, P, P, P, P, P]),
-    "spq_fw_dense": (I32, [I32, I32, I32, P, P]),
+    "spq_fw_dense": (I32, [I32, I32, I32, I32, P, P]),
 }
 
 
@@ -147,12 +147,23 @@ class Index:
 
 
 def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg_method=0,
-                group_comps=0, share_comps=0, stream=None) -> Index:
-    """Algorithm 1 on device tensors; see spq_build_index."""
+                group_comps=0, share_comps=0, inner_kc=0, tune_cache=None, stream=None) -> Index:
+    """Algorithm 1 on device tensors; see spq_build_index.
+
+    tune_cache: path of an autotuner cache (paper_1503_07192_amd.autotune);
+    options it holds for this device and problem size fill in the ones left
+    at 0 here."""
     L = load()
+    if tune_cache:
+        from . import autotune
+        tuned = autotune.lookup(tune_cache, n, int(eu.numel()), k, share_comps)
+        bg_tile = bg_tile or tuned.get("bg_tile", 0)
+        inner_kc = inner_kc or tuned.get("inner_kc", 0)
+        bg_method = bg_method or tuned.get("bg_method", 0)
+        group_comps = group_comps or tuned.get("group_comps", 0)
     opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)), plain=int(bool(plain)),
                      bg_method=int(bg_method), group_comps=int(group_comps),
-                     share_comps=int(share_comps))
+                     share_comps=int(share_comps), inner_kc=int(inner_kc))
     h = ctypes.c_void_p()
     m = int(eu.numel())
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),
@@ -216,7 +227,7 @@ def fw_components(size, off, ld, data, stream=None):
     return data
 
 
-def fw_dense(v, ld, tile, data, stream=None):
-    _check(load().spq_fw_dense(int(v), int(ld), int(tile), _dev_i32(data, "data"),
+def fw_dense(v, ld, tile, data, stream=None, kc=0):
+    _check(load().spq_fw_dense(int(v), int(ld), int(tile), int(kc), _dev_i32(data, "data"),
                                _stream(stream)))
     return data

@@ -30,9 +30,10 @@ def test_argument_errors_without_device():
     assert "bg_tile" in spq.last_error()
     assert L.spq_build_index(5, 0, None, None, None, None, 2, None, None, None) == 1
     assert L.spq_query_batch(None, 3, None, None, None, None) == 1
-    assert L.spq_fw_dense(10, 10, 3, None, None) == 1
-    assert L.spq_fw_dense(10, 8, 64, None, None) == 1
-    assert L.spq_fw_dense(0, 0, 64, None, None) == 0
+    assert L.spq_fw_dense(10, 10, 3, 0, None, None) == 1
+    assert L.spq_fw_dense(10, 8, 64, 0, None, None) == 1
+    assert L.spq_fw_dense(10, 64, 64, 8, None, None) == 1
+    assert L.spq_fw_dense(0, 0, 64, 0, None, None) == 0
     assert L.spq_fw_components(-1, None, None, None, None, None) == 1
     assert L.spq_index_stats(None, None) == 1
     L.spq_free_index(None)

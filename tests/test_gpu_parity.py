@@ -152,15 +152,16 @@ def test_fw_components_kernel(wname, wlo, whi):
         assert np.array_equal(g[:N, :N], oracle_closure(m, N)), "N=%d" % N
 
 
+@pytest.mark.parametrize("kc", [16, 32])
 @pytest.mark.parametrize("tile", [64, 128])
 @pytest.mark.parametrize("v", [1, 5, 64, 100, 129, 300, 520])
-def test_fw_dense_kernel(tile, v):
+def test_fw_dense_kernel(tile, v, kc):
     rng = np.random.default_rng(1000 + v + tile)
     ld = -(-v // tile) * tile
     for wlo, whi in [(0, 3), (1, 10**6), (2**30, INF32 - 1)]:
         A = random_symmetric(rng, v, ld, min(1.0, 3.0 / max(v, 1)), wlo, whi)
         d = dev(A.ravel())
-        spq.fw_dense(v, ld, tile, d)
+        spq.fw_dense(v, ld, tile, d, kc=kc)
         torch.cuda.synchronize()
         got = d.cpu().numpy().reshape(ld, ld)
         assert np.array_equal(got[:v, :v], oracle_closure(A, v)), (wlo, whi)

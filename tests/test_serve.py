@@ -122,3 +122,17 @@ def test_poisson_stream_shape():
     assert (np.diff(t) >= 0).all()
     rate_req = len(reqs) / t[-1]
     assert abs(rate_req / (1e6 / mean_b) - 1) < 0.1
+
+
+def test_autotune_cache_lookup(tmp_path, monkeypatch):
+    from paper_1503_07192_amd import autotune
+    monkeypatch.setattr(autotune, "device_key", lambda: "gfx950")
+    path = tmp_path / "tune.json"
+    key = autotune.size_key(65536, 163066, 1024, 0)
+    path.write_text('{"gfx950": {"%s": {"best": {"bg_method": 2, "group_comps": 32}}}}' % key)
+    assert autotune.lookup(str(path), 65536, 163066, 1024, 0) == {"bg_method": 2, "group_comps": 32}
+    assert autotune.lookup(str(path), 1024, 1984, 16, 0) == {}
+    assert autotune.lookup(str(tmp_path / "missing.json"), 1, 1, 1) == {}
+    c = autotune.candidates(27900, 1024, 0)
+    assert {"bg_method": 1, "bg_tile": 128, "inner_kc": 16} in c
+    assert all(o["bg_method"] == 2 for o in autotune.candidates(255422, 4096, 0))
