@@ -67,8 +67,11 @@ typedef struct {
                           groups; needs the total edge weight below SPQ_INF */
   int32_t inner_kc;    /* K chunk of the Floyd-Warshall interior-tile kernel:
                           0 (default 16), 16 or 32 (see the autotuner) */
-  int32_t reserved[1]; /* must be 0 */
+  int32_t flags;       /* SPQ_NO_LOOKAHEAD: flat BG rounds without the overlap
+                          of the next round's diagonal and panel work */
 } spq_build_opts;
+
+#define SPQ_NO_LOOKAHEAD 1
 
 typedef struct {
   int32_t n, k;            /* vertices, components */

@@ -79,6 +79,9 @@ struct spq_index {
   int32_t *bgvert = nullptr, *label = nullptr, *bglabel = nullptr;
   u32* cert = nullptr;  // [4]: changed, bad, max APSP(C), max BG
   u32 cert_mc = 0, cert_mbg = 0;
+  // lookahead of the flat rounds: side stream and its two sync events
+  hipStream_t side = nullptr;
+  hipEvent_t la_sync[2] = {};
   hipEvent_t ev[5] = {};
   bool events = false;
   std::vector<hipEvent_t> prof;  // pairs around the BG interior-tile launches
@@ -91,6 +94,9 @@ struct spq_index {
       for (auto& e : ev) (void)hipEventDestroy(e);
     }
     for (auto& e : prof) (void)hipEventDestroy(e);
+    for (auto& e : la_sync)
+      if (e) (void)hipEventDestroy(e);
+    if (side) (void)hipStreamDestroy(side);
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
                     vrec, grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
@@ -245,6 +251,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   int tile = 128;
   bool profile = false, plain = false;
   int32_t method_opt = 0, group_comps = 0, share_comps = 0, inner_kc = 0;
+  bool lookahead = true;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
@@ -263,8 +270,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     inner_kc = opts->inner_kc;
     if (inner_kc != 0 && inner_kc != 16 && inner_kc != 32)
       return fail(SPQ_EINVAL, "inner_kc must be 0, 16 or 32");
-    for (int i = 0; i < 1; i++)
-      if (opts->reserved[i]) return fail(SPQ_EINVAL, "reserved options must be 0");
+    if (opts->flags & ~SPQ_NO_LOOKAHEAD) return fail(SPQ_EINVAL, "unknown flags");
+    lookahead = !(opts->flags & SPQ_NO_LOOKAHEAD);
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   spq_index* X = new spq_index();
@@ -547,8 +554,15 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     X->prof.resize(2 * X->inner_launches);
     for (auto& e : X->prof) TRY(hipEventCreate(&e));
   }
-  TRY(spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, s,
-                           X->prof.empty() ? nullptr : X->prof.data(), inner_kc));
+  if (lookahead && X->Vp / tile > 1) {
+    TRY(hipStreamCreateWithFlags(&X->side, hipStreamNonBlocking));  // default priority
+    for (auto& e : X->la_sync) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    TRY(spq::launch_dense_fw_lookahead(X->BG, X->Vp, tile, X->Vp / tile, s, X->side, X->la_sync,
+                                       X->prof.empty() ? nullptr : X->prof.data(), inner_kc));
+  } else {
+    TRY(spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, s,
+                             X->prof.empty() ? nullptr : X->prof.data(), inner_kc));
+  }
   TRY(hipEventRecord(X->ev[4], s));
 #undef TRY
   spq_status cs = certify(X, m, eu, ev, s);

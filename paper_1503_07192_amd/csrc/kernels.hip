@@ -332,17 +332,42 @@ __device__ __forceinline__ void tri_index(int b, int m, int& bi, int& bj) {
 #else
 #define SPQ_INNER_ATTR
 #endif
+//
+// part selects the tiles of the launch:
+//   0  every interior tile (i <= j, both != r)
+//   1  the tiles of row/column r+1 only: (i, r+1) for i <= r+1, i != r, and
+//      (r+1, j) for j > r+1 (what the next round's pivot row needs)
+//   2  every interior tile not in part 1
 template <int T, int KC>
 __global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict__ A, int64_t ld, int r, int nt,
-                                                                int64_t gstride) {
+                                                                int64_t gstride, int part) {
   constexpr int Q = KC * T / 4 / 256;  // uint4 per thread per operand chunk
   static_assert(Q >= 1 && KC * T / 4 % 256 == 0, "chunk must split evenly");
   __shared__ __attribute__((aligned(16))) u32 sA[2][KC * T];
   __shared__ __attribute__((aligned(16))) u32 sB[2][KC * T];
   A += (int64_t)blockIdx.y * gstride;
-  int bi, bj;
-  tri_index((int)blockIdx.x, nt - 1, bi, bj);
-  const int i = bi + (bi >= r), j = bj + (bj >= r);
+  int i, j;
+  const int b = (int)blockIdx.x;
+  if (part == 0) {
+    int bi, bj;
+    tri_index(b, nt - 1, bi, bj);
+    i = bi + (bi >= r);
+    j = bj + (bj >= r);
+  } else if (part == 1) {
+    const int p = r + 1;  // nt - 1 tiles
+    if (b <= r) {         // (i, p) for i in [0, p], i != r; b == r gives (p, p)
+      i = b + (b >= r ? 1 : 0);
+      j = p;
+    } else {              // (p, j) for j in (p, nt)
+      i = p;
+      j = b + 1;
+    }
+  } else {
+    int bi, bj;           // triangle over indices other than r and r+1
+    tri_index(b, nt - 2, bi, bj);
+    i = bi + (bi >= r ? 2 : 0);
+    j = bj + (bj >= r ? 2 : 0);
+  }
   const u32* Ar = A + (int64_t)r * T * ld + (int64_t)i * T;  // tile (r, i)
   const u32* Br = A + (int64_t)r * T * ld + (int64_t)j * T;  // tile (r, j)
   u32* Cij = A + (int64_t)i * T * ld + (int64_t)j * T;
@@ -567,7 +592,7 @@ static hipError_t fw_rounds(u32* A, int64_t ld, int nt, int batch, int64_t gstri
         if (e != hipSuccess) return e;
       }
       k_fw_inner<T, KC><<<dim3((unsigned)((nt - 1) * nt / 2), batch), 256, 0, s>>>(
-          A, ld, r, nt, gstride);
+          A, ld, r, nt, gstride, 0);
       if (ev) {
         hipError_t e = hipEventRecord(ev[2 * r + 1], s);
         if (e != hipSuccess) return e;
@@ -577,9 +602,64 @@ static hipError_t fw_rounds(u32* A, int64_t ld, int nt, int batch, int64_t gstri
   LAUNCH_CHECK();
 }
 
+// The same rounds with a lookahead: the interior tiles of row/column r+1 go
+// first (part 1); as soon as they are done, round r+1's diagonal and panel
+// run on the side stream while the rest of round r's interior (part 2) runs
+// on the main stream.  Part 2 neither reads nor writes a tile that round
+// r+1's diagonal or panel touches (row/column r+1 and the tiles (r, r+1),
+// (r+1, r)), so the two overlap safely.  ev (optional) gets one pair per
+// round around parts 1 + 2.
+template <int T, int KC>
+static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, hipStream_t s, hipStream_t side,
+                                      hipEvent_t* sync, hipEvent_t* ev) {
+#define CHK(x)                              \
+  do {                                      \
+    hipError_t e_ = (x);                    \
+    if (e_ != hipSuccess) return e_;        \
+  } while (0)
+  // sync[0] = side stream may start round r+1 (part 1 of round r done);
+  // sync[1] = main stream may start round r+1's interior (its panel done)
+  CHK(hipEventRecord(sync[0], s));
+  CHK(hipStreamWaitEvent(side, sync[0], 0));
+  k_fw_diag<T><<<1, 256, 0, side>>>(A, ld, 0, 0);
+  k_fw_panel<T><<<nt - 1, 256, 0, side>>>(A, ld, 0, 0);
+  CHK(hipEventRecord(sync[1], side));
+  for (int r = 0; r < nt; r++) {
+    CHK(hipStreamWaitEvent(s, sync[1], 0));
+    if (ev) CHK(hipEventRecord(ev[2 * r], s));
+    if (r + 1 < nt) {
+      k_fw_inner<T, KC><<<(unsigned)nt - 1, 256, 0, s>>>(A, ld, r, nt, 0, 1);
+      CHK(hipEventRecord(sync[0], s));
+      CHK(hipStreamWaitEvent(side, sync[0], 0));
+      k_fw_diag<T><<<1, 256, 0, side>>>(A, ld, r + 1, 0);
+      k_fw_panel<T><<<nt - 1, 256, 0, side>>>(A, ld, r + 1, 0);
+      if (nt > 2)
+        k_fw_inner<T, KC><<<(unsigned)((nt - 2) * (nt - 1) / 2), 256, 0, s>>>(A, ld, r, nt, 0, 2);
+      CHK(hipEventRecord(sync[1], side));
+    } else {
+      // last round: nothing to look ahead to
+      k_fw_inner<T, KC><<<(unsigned)((nt - 1) * nt / 2), 256, 0, s>>>(A, ld, r, nt, 0, 0);
+    }
+    if (ev) CHK(hipEventRecord(ev[2 * r + 1], s));
+  }
+#undef CHK
+  LAUNCH_CHECK();
+}
+
 hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev,
                            int kc) {
   return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev, kc);
+}
+
+hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
+                                     hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc) {
+  if (nt <= 1) return launch_dense_fw(A, ld, tile, nt, s, ev, kc);
+  if (kc == 0) kc = SPQ_INNER_KC;
+  if (tile == 64)
+    return kc == 32 ? fw_rounds_lookahead<64, 32>(A, ld, nt, s, side, sync, ev)
+                    : fw_rounds_lookahead<64, 16>(A, ld, nt, s, side, sync, ev);
+  return kc == 32 ? fw_rounds_lookahead<128, 32>(A, ld, nt, s, side, sync, ev)
+                  : fw_rounds_lookahead<128, 16>(A, ld, nt, s, side, sync, ev);
 }
 
 // kc: K chunk of the interior-tile kernel (16 or 32; 0 = SPQ_INNER_KC)

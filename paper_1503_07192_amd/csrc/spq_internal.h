@@ -128,6 +128,11 @@ hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, 
 // `batch` matrices of the same shape, gstride elements apart
 hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
                                  hipStream_t s, hipEvent_t* ev, int kc = 0);
+// Same closure with a lookahead over two streams (side: created by the caller,
+// default priority; sync: two events).  ev: NULL or 2*nt events, one pair
+// per round around its interior.
+hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
+                                     hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc);
 // relaxations executed by launch_dense_fw (diagonal, panel and upper-triangle
 // interior tiles of every round)
 double dense_fw_exec_relax(int64_t nt, int tile);

@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "spq.h")
 
 SPQ_INF = 2147483647
 SPQ_BAD_PAIR = -1
+SPQ_NO_LOOKAHEAD = 1
 STATUS = {0: "SPQ_OK", 1: "SPQ_EINVAL", 2: "SPQ_ENOMEM", 3: "SPQ_EDEVICE", 4: "SPQ_ERANGE"}
 
 
@@ -35,7 +36,7 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("bg_tile", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("plain", ctypes.c_int32), ("bg_method", ctypes.c_int32),
                 ("group_comps", ctypes.c_int32), ("share_comps", ctypes.c_int32),
-                ("inner_kc", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("inner_kc", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -147,7 +148,8 @@ class Index:
 
 
 def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg_method=0,
-                group_comps=0, share_comps=0, inner_kc=0, tune_cache=None, stream=None) -> Index:
+                group_comps=0, share_comps=0, inner_kc=0, lookahead=True, tune_cache=None,
+                stream=None) -> Index:
     """Algorithm 1 on device tensors; see spq_build_index.
 
     tune_cache: path of an autotuner cache (paper_1503_07192_amd.autotune);
@@ -163,7 +165,8 @@ def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg
         group_comps = group_comps or tuned.get("group_comps", 0)
     opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)), plain=int(bool(plain)),
                      bg_method=int(bg_method), group_comps=int(group_comps),
-                     share_comps=int(share_comps), inner_kc=int(inner_kc))
+                     share_comps=int(share_comps), inner_kc=int(inner_kc),
+                     flags=0 if lookahead else SPQ_NO_LOOKAHEAD)
     h = ctypes.c_void_p()
     m = int(eu.numel())
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),

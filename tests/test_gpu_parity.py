@@ -257,8 +257,11 @@ def test_grid32_bg_tile_plain_and_repeat_are_bitwise_identical():
     b = build(g, bg_tile=128)
     c = build(g, bg_tile=128)
     d = build(g, plain=True)
-    ra, rb, rc, rd = (spq.index_bg_rows(x, 0, 348, 348) for x in (a, b, c, d))
+    e = build(g, bg_tile=64, lookahead=False)
+    f = build(g, bg_tile=64, inner_kc=32)
+    ra, rb, rc, rd, re, rf = (spq.index_bg_rows(x, 0, 348, 348) for x in (a, b, c, d, e, f))
     assert np.array_equal(ra, rb) and np.array_equal(rb, rc) and np.array_equal(rb, rd)
+    assert np.array_equal(ra, re) and np.array_equal(ra, rf)
     for comp in range(16):
         assert np.array_equal(spq.index_component(b, comp, 64), spq.index_component(d, comp, 64))
     v1, v2 = all_pairs(g["n"])
@@ -370,6 +373,12 @@ def test_grid256d_two_level_equals_flat():
     rows = np.random.default_rng(8).integers(0, 27_900, 40)
     rf = [spq.index_bg_rows(flat, int(r), 1, 27_900) for r in rows]
     flat.free()
+    # flat rounds without the lookahead overlap: the same matrix
+    plain = build(g, bg_method=1, lookahead=False)
+    assert np.array_equal(run_queries(plain, g["v1"], g["v2"]), qf)
+    for r, want in zip(rows, rf):
+        assert np.array_equal(spq.index_bg_rows(plain, int(r), 1, 27_900), want)
+    plain.free()
     two = build(g, bg_method=2, group_comps=32)
     st = spq.index_stats(two)
     assert st["ngroups"] == 32 and st["v_bg2"] > 0
