@@ -172,8 +172,12 @@ spq_status spq_index_component(const spq_index* idx, int32_t c, int32_t* out);
 spq_status spq_index_bg_rows(const spq_index* idx, int32_t row0, int32_t nrows,
                              int32_t* out);
 
-/* Releases the index and its device memory (waits for its work). NULL is ok. */
+/* Releases the index (waits for the device).  Its device memory goes to the
+ * library's cache and is reused by later builds; NULL is ok. */
 void spq_free_index(spq_index* idx);
+
+/* Frees the device memory cached from released indexes (all devices). */
+void spq_release_cached_memory(void);
 
 /* Message of the last error on this thread ("" if none). */
 const char* spq_last_error(void);

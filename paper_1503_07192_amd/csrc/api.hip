@@ -4,8 +4,11 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/spq.h"
@@ -31,11 +34,80 @@ spq_status fail(spq_status s, const std::string& msg) {
     }                                                                                  \
   } while (0)
 
+// Device memory pool.  Index buffers are large (up to ~130 GB) and a fresh
+// hipMalloc of memory freed a moment earlier costs about a second per 100 GB
+// on this device, so a freed index hands its blocks back to this cache and
+// the next build reuses them.  spq_release_cached_memory() returns them.
+struct Pool {
+  std::mutex mu;
+  std::unordered_map<void*, std::pair<int, size_t>> live;  // ptr -> (device, bytes)
+  std::multimap<std::pair<int, size_t>, void*> idle;       // (device, bytes) -> ptr
+};
+
+Pool& pool() {
+  static Pool* p = new Pool();  // lives until the process ends
+  return *p;
+}
+
+size_t pool_round(size_t b) {
+  const size_t big = size_t(1) << 21;
+  return b < big ? (b + 255) & ~size_t(255) : (b + big - 1) & ~(big - 1);
+}
+
+void pool_drop_idle(int dev) {  // caller holds the lock
+  Pool& P = pool();
+  for (auto it = P.idle.begin(); it != P.idle.end();) {
+    if (dev < 0 || it->first.first == dev) {
+      (void)hipFree(it->second);
+      it = P.idle.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+hipError_t pool_alloc(void** out, size_t bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  bytes = pool_round(bytes);
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lock(P.mu);
+  auto it = P.idle.lower_bound({dev, bytes});
+  if (it != P.idle.end() && it->first.first == dev && it->first.second <= bytes + bytes / 4) {
+    *out = it->second;
+    P.live[*out] = it->first;
+    P.idle.erase(it);
+    return hipSuccess;
+  }
+  e = hipMalloc(out, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    pool_drop_idle(dev);
+    e = hipMalloc(out, bytes);
+  }
+  if (e == hipSuccess) P.live[*out] = {dev, bytes};
+  return e;
+}
+
+void pool_release(void* p) {
+  if (!p) return;
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lock(P.mu);
+  auto it = P.live.find(p);
+  if (it == P.live.end()) {
+    (void)hipFree(p);
+    return;
+  }
+  P.idle.insert({it->second, p});
+  P.live.erase(it);
+}
+
 template <typename T>
 hipError_t dalloc(T** p, int64_t count) {
   *p = nullptr;
   if (count <= 0) count = 1;
-  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)count);
+  return pool_alloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)count);
 }
 
 int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
@@ -97,13 +169,14 @@ struct spq_index {
     for (auto& e : la_sync)
       if (e) (void)hipEventDestroy(e);
     if (side) (void)hipStreamDestroy(side);
+    // no queued work of this index may still use its memory once it is cached
+    (void)hipDeviceSynchronize();
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
                     vrec, grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
                     bgvert, label, bglabel, cert, A,    DT,    DT2,   bfflag,  xe, xcount};
-    for (void* p : ptrs)
-      if (p) (void)hipFree(p);
+    for (void* p : ptrs) pool_release(p);
   }
 };
 
@@ -195,34 +268,43 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   return SPQ_OK;
 }
 
-// Runs the exactness certificate when the build asked for it (total edge
-// weight >= SPQ_INF): connected components of G, then the checks of
-// range.hip.  Synchronous.
-static spq_status certify(spq_index* X, int64_t m, const int32_t* eu, const int32_t* ev,
-                          hipStream_t s) {
-  if (!X->certify) return SPQ_OK;
+// Connected components of G and their label on every BG vertex (needed by the
+// exactness certificate).  Synchronous: one small readback per round.
+static spq_status cc_labels(spq_index* X, int64_t m, const int32_t* eu, const int32_t* ev,
+                            hipStream_t s) {
   const int32_t n = X->n;
   HIP_TRY(dalloc(&X->label, n));
   HIP_TRY(dalloc(&X->bglabel, X->V));
   HIP_TRY(dalloc(&X->cert, 4));
+  HIP_TRY(hipMemsetAsync(X->cert, 0, 4 * sizeof(u32), s));
   HIP_TRY(spq::launch_cc_init(n, X->label, s));
-  u32 h[4] = {1, 0, 0, 0};
+  u32 changed = 1;
   int rounds = 0;
-  while (h[0]) {
+  while (changed) {
     if (++rounds > 256) return fail(SPQ_ERANGE, "connected components did not settle");
     HIP_TRY(hipMemsetAsync(X->cert, 0, sizeof(u32), s));
     HIP_TRY(spq::launch_cc_round(m, eu, ev, n, X->label, X->cert, s));
-    HIP_TRY(hipMemcpyAsync(h, X->cert, sizeof(u32), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&changed, X->cert, sizeof(u32), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
-  HIP_TRY(hipMemsetAsync(X->cert, 0, 4 * sizeof(u32), s));
+  HIP_TRY(spq::launch_bg_label(X->V, X->bgvert, X->label, X->bglabel, s));
+  return SPQ_OK;
+}
+
+// The exactness certificate (range.hip) when the total edge weight reaches
+// SPQ_INF; cc_labels must have run.  For the two-level store the BG check ran
+// inside the composition kernel.  Synchronous.
+static spq_status certify(spq_index* X, hipStream_t s) {
+  if (!X->certify) return SPQ_OK;
   spq::CertArgs c{};
+  c.bg_checked = X->method == 2;
   c.V = X->V; c.ngroups = X->ngroups; c.Vgp = X->Vgp; c.Vp = X->Vp; c.comp_elems = X->comp_elems;
   c.M = X->M; c.BG = X->BG; c.H = X->method == 2 ? X->H : nullptr; c.bgvert = X->bgvert;
   c.label = X->label; c.gV = X->gV; c.gbg0 = X->gbg0; c.bgrow = X->bgrow; c.bgnb = X->bgnb;
   c.bglocal = X->bglocal; c.pairbase = X->pairbase; c.bglabel = X->bglabel;
   c.bad = X->cert + 1; c.mc = X->cert + 2; c.mbg = X->cert + 3;
   HIP_TRY(spq::launch_certificate(c, s));
+  u32 h[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(h, X->cert, sizeof(h), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (h[1]) return fail(SPQ_ERANGE, "a BG distance between connected vertices reaches SPQ_INF");
@@ -445,6 +527,10 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   pa.moff = X->moff; pa.P = X->P; pa.vrec = X->vrec; pa.grp = X->grp; pa.gbg0 = X->gbg0;
   pa.bgvert = X->bgvert;
   TRY(spq::launch_renumber(pa, s));
+  if (X->certify) {
+    spq_status cs = cc_labels(X, m, eu, ev, s);
+    if (cs != SPQ_OK) return guard(cs);
+  }
   TRY(hipEventRecord(X->ev[1], s));
 
   // ---- Phase 2: APSP(C) for every component
@@ -536,9 +622,14 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
                        hipMemcpyHostToDevice, s));
     ha.m2pmax = X->m2pmax; ha.V2 = X->V2; ha.V2p = X->V2p; ha.b2off = X->b2off; ha.R = X->R;
     ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
+    if (X->certify) {
+      ha.bglabel = X->bglabel;
+      ha.cert_bad = X->cert + 1;
+      ha.cert_mbg = X->cert + 3;
+    }
     TRY(spq::launch_hier_level2(ha, s));
     TRY(hipEventRecord(X->ev[4], s));
-    spq_status cs = certify(X, m, eu, ev, s);
+    spq_status cs = certify(X, s);
     if (cs != SPQ_OK) return guard(cs);
     *out = X;
     return SPQ_OK;
@@ -565,7 +656,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   }
   TRY(hipEventRecord(X->ev[4], s));
 #undef TRY
-  spq_status cs = certify(X, m, eu, ev, s);
+  spq_status cs = certify(X, s);
   if (cs != SPQ_OK) return guard(cs);
   *out = X;
   return SPQ_OK;
@@ -666,7 +757,7 @@ spq_status spq_index_bg_rows(const spq_index* X, int32_t row0, int32_t nrows, in
       if (e == hipSuccess)
         e = hipMemcpy(out + (int64_t)r * X->V, tmp, sizeof(int32_t) * X->V, hipMemcpyDeviceToHost);
     }
-    (void)hipFree(tmp);
+    pool_release(tmp);
     HIP_TRY(e);
     return SPQ_OK;
   }
@@ -677,6 +768,12 @@ spq_status spq_index_bg_rows(const spq_index* X, int32_t row0, int32_t nrows, in
 }
 
 void spq_free_index(spq_index* X) { delete X; }
+
+void spq_release_cached_memory(void) {
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lock(P.mu);
+  pool_drop_idle(-1);
+}
 
 spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* off,
                              const int32_t* ld, int32_t* data, void* stream) {
@@ -699,9 +796,9 @@ spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* 
   HIP_TRY(hipMemcpyAsync(d_off, off, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
   HIP_TRY(spq::launch_comp_fw(count, d_order, d_P, d_off, reinterpret_cast<u32*>(data), s));
   HIP_TRY(hipStreamSynchronize(s));
-  (void)hipFree(d_order);
-  (void)hipFree(d_P);
-  (void)hipFree(d_off);
+  pool_release(d_order);
+  pool_release(d_P);
+  pool_release(d_off);
   return SPQ_OK;
 }
 

@@ -329,7 +329,9 @@ __global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t s2base, int32_
                                               const int64_t* __restrict__ pairbase,
                                               const int32_t* __restrict__ bgrow,
                                               const int32_t* __restrict__ bgnb,
-                                              const int32_t* __restrict__ bglocal, u32* __restrict__ H) {
+                                              const int32_t* __restrict__ bglocal, u32* __restrict__ H,
+                                              const int32_t* __restrict__ bglabel,
+                                              u32* __restrict__ cert_bad, u32* __restrict__ cert_mbg) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
   const int32_t s2 = s2base + (int32_t)blockIdx.y;
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t s2base, int32_
   const int tx = tid_x(), ty = tid_y();
   const int32_t g1 = gbg0[s1], g2 = gbg0[s2];
   int64_t colpart[8];
-  int32_t colnb[8];
+  int32_t colnb[8], collab[8];
   bool colok[8];
 #pragma unroll
   for (int h2 = 0; h2 < 2; h2++)
@@ -363,7 +365,11 @@ __global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t s2base, int32_
       colpart[j] = bgrow[yg];   // times nb(x) below
       colnb[j] = bgnb[yg];
       colpart[j] = (colpart[j] << 32) | (uint32_t)bglocal[yg];
+      collab[j] = bglabel ? bglabel[yg] : 0;
     }
+  // exactness certificate, fused into the store: largest finite value, and
+  // whether any INF joins two vertices connected in G
+  u32 best = 0, wrong = 0;
 #pragma unroll
   for (int h = 0; h < 2; h++)
 #pragma unroll
@@ -373,14 +379,27 @@ __global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t s2base, int32_
       const int32_t xg = g1 + x;
       const int64_t rbase = (int64_t)bgrow[xg] * V2;
       const int64_t nbx = bgnb[xg], locx = bglocal[xg];
+      const int32_t labx = bglabel ? bglabel[xg] : 0;
       const int i = h * 4 + a;
 #pragma unroll
       for (int j = 0; j < 8; j++) {
         if (!colok[j]) continue;
         const int64_t rowy = colpart[j] >> 32, locy = colpart[j] & 0xffffffffll;
         base[rbase + nbx * rowy + locx * colnb[j] + locy] = c[i][j];
+        if (c[i][j] < INF) best = max(best, c[i][j]);
+        else wrong |= (u32)(collab[j] == labx);
       }
     }
+  if (bglabel) {
+    for (int o = 32; o > 0; o >>= 1) {
+      best = max(best, (u32)__shfl_xor((int)best, o));
+      wrong |= (u32)__shfl_xor((int)wrong, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      if (best) atomicMax(cert_mbg, best);
+      if (wrong) atomicOr(cert_bad, 1u);
+    }
+  }
 }
 
 // One BG row (BG id x) gathered from the two-level store, for inspection.
@@ -599,7 +618,7 @@ hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s) {
     }
     k_mp_y<<<dim3((unsigned)(ntx * ntx), pairs), 256, 0, s>>>(
         s1, s1, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
-        a.bgnb, a.bglocal, a.H);
+        a.bgnb, a.bglocal, a.H, a.bglabel, a.cert_bad, a.cert_mbg);
     if (a.evt) {
       hipError_t e = hipEventRecord(a.evt[2 * s1 + 1], s);
       if (e != hipSuccess) return e;
@@ -658,7 +677,7 @@ hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s)
     }
     k_mp_y<<<dim3((unsigned)(ntx * ntx), (unsigned)a.ngroups), 256, 0, s>>>(
         s1, 0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
-        a.bgnb, a.bglocal, a.H);
+        a.bgnb, a.bglocal, a.H, nullptr, nullptr, nullptr);
     if (a.evt) {
       hipError_t e = hipEventRecord(a.evt[2 * s1 + 1], s);
       if (e != hipSuccess) return e;

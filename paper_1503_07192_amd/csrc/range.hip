@@ -147,10 +147,15 @@ hipError_t launch_cc_round(int64_t m, const int32_t* eu, const int32_t* ev, int3
   return hipGetLastError();
 }
 
+hipError_t launch_bg_label(int32_t V, const int32_t* bgvert, const int32_t* label, int32_t* bglabel,
+                           hipStream_t s) {
+  if (V > 0) k_bg_label<<<rblocks(V), 256, 0, s>>>(V, bgvert, label, bglabel);
+  return hipGetLastError();
+}
+
 hipError_t launch_certificate(const CertArgs& a, hipStream_t s) {
   if (a.comp_elems > 0) k_max_finite<<<rblocks(a.comp_elems), 256, 0, s>>>(a.comp_elems, a.M, a.mc);
-  if (a.V > 0) {
-    k_bg_label<<<rblocks(a.V), 256, 0, s>>>(a.V, a.bgvert, a.label, a.bglabel);
+  if (a.V > 0 && !a.bg_checked) {
     if (a.H) {
       dim3 grid((unsigned)((int64_t)a.ngroups * a.ngroups), (unsigned)((a.Vgp + 15) / 16));
       k_check_hier<<<grid, 256, 0, s>>>(a.ngroups, a.gV, a.gbg0, a.pairbase, a.bgrow, a.bgnb,

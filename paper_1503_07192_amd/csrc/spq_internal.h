@@ -91,6 +91,9 @@ struct HierArgs {
   int4* xe;                        // directed cross edges
   int32_t* xcount;
   hipEvent_t* evt;                 // NULL, or 2 per composition launch (k_mp_y)
+  // exactness certificate fused into the composition (NULL: off)
+  const int32_t* bglabel;
+  u32 *cert_bad, *cert_mbg;
 };
 hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s);
 hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, const u32* dirty,
@@ -102,6 +105,7 @@ hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s
 
 // Exactness certificate (range.hip).
 struct CertArgs {
+  bool bg_checked;  // BG entries already checked (fused into the two-level store)
   int32_t V, ngroups, Vgp;
   int64_t Vp, comp_elems;
   const u32 *M, *BG, *H;
@@ -114,6 +118,8 @@ hipError_t launch_cc_init(int32_t n, int32_t* label, hipStream_t s);
 hipError_t launch_cc_round(int64_t m, const int32_t* eu, const int32_t* ev, int32_t n, int32_t* label,
                            u32* changed, hipStream_t s);
 hipError_t launch_certificate(const CertArgs& a, hipStream_t s);
+hipError_t launch_bg_label(int32_t V, const int32_t* bgvert, const int32_t* label, int32_t* bglabel,
+                           hipStream_t s);
 
 hipError_t launch_partition_scan(const PartArgs& a, hipStream_t s);
 hipError_t launch_renumber(const PartArgs& a, hipStream_t s);

@@ -67,6 +67,7 @@ _SIGS = {
     "spq_index_component": (I32, [P, I32, P]),
     "spq_index_bg_rows": (I32, [P, I32, I32, P]),
     "spq_free_index": (None, [P]),
+    "spq_release_cached_memory": (None, []),
     "spq_last_error": (ctypes.c_char_p, []),
     "spq_fw_components": (I32, [I32, P, P, P, P, P]),
     "spq_fw_dense": (I32, [I32, I32, I32, I32, P, P]),
@@ -93,6 +94,11 @@ def load():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def release_cached_memory():
+    """Frees device memory cached from released indexes."""
+    load().spq_release_cached_memory()
 
 
 def last_error() -> str:

@@ -559,3 +559,16 @@ def test_grid2048_share_full_size():
     assert np.array_equal(sub, clamp32(D[np.repeat(np.arange(60), 20), tgt.ravel()]))
     # the batch's own first pairs
     assert np.array_equal(out[:60], clamp32(D[np.arange(60), g["v2"][:60]]))
+
+
+def test_cached_memory_release_and_rebuild():
+    g = W.grid32()
+    a = build(g)
+    ra = spq.index_bg_rows(a, 0, 348, 348)
+    a.free()
+    b = build(g)                      # reuses the cached blocks
+    assert np.array_equal(spq.index_bg_rows(b, 0, 348, 348), ra)
+    b.free()
+    spq.release_cached_memory()
+    c = build(g)                      # fresh allocations
+    assert np.array_equal(spq.index_bg_rows(c, 0, 348, 348), ra)
