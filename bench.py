@@ -60,6 +60,26 @@ WORKLOADS = {
 }
 
 
+def recorded_traffic():
+    """HBM bytes per round of the interior kernel, from the committed counter
+    summary, if the kernel sources are still the ones it was measured on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_k_fw_inner_grid256d.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_round", "source_sha256"):
+            k, v = line.split(":", 1)
+            rec[k] = v.strip()
+    csrc = os.path.join(ROOT, "paper_1503_07192_amd", "csrc")
+    src = open(os.path.join(csrc, "tiles.h"), "rb").read() + \
+        open(os.path.join(csrc, "kernels.hip"), "rb").read()
+    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return float(rec["traffic_bytes_per_round"])
+
+
 def make_workload(name, queries):
     from paper_1503_07192_amd import workloads as W
     if name == "grid256d":
@@ -242,7 +262,11 @@ def main():
         "single_query_us_p99": float(np.percentile(lat, 99)),
         "roofline": {"bound": "alu", "kernel": kernel,
                      "achieved": inner_rate / 1e12, "peak": RELAX_PEAK / 1e12,
-                     "unit": "Trelax/s", "frac": inner_rate / RELAX_PEAK, "traffic": None,
+                     "unit": "Trelax/s", "frac": inner_rate / RELAX_PEAK,
+                     "traffic": recorded_traffic() if (args.workload == "grid256d"
+                                                       and st["bg_method"] == 1) else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "scaled by a 256 MiB copy)",
                      "launches_per_step": launches, "avg_launch_ms": avg_launch_ms,
                      "relax_per_launch": per_launch},
         "query_roofline": {"bound": "hbm", "achieved": q * qbytes / (np.median(mq) * 1e-3) / 1e9,
