@@ -199,7 +199,7 @@ def main():
     alt = None
     if args.workload == "grid256d":
         ref = out.clone()
-        for method, gc in ((2, 32),):
+        for method, gc in ((2, 128),):   # the autotuner's pick for this workload
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], bg_method=method, group_comps=gc,

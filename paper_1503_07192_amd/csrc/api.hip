@@ -131,7 +131,7 @@ struct spq_index {
   u32 *err = nullptr, *members = nullptr, *M = nullptr, *BG = nullptr;
   uint4* vrec = nullptr;
   // groups (all components in group 0 for the flat store)
-  int32_t method = 1, ngroups = 1, cpg = 1, Vgp = 0, V2 = 0, m2pmax = 0;
+  int32_t method = 1, ngroups = 1, cpg = 1, Vgp = 0, V2 = 0, m2pmax = 0, nbig = 0;
   int64_t V2p = 0, h_elems = 0;
   std::vector<int32_t> h_grp, h_gbg0, h_gV, h_m2, h_b2off;
   std::vector<int64_t> h_pairbase;
@@ -438,16 +438,24 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   for (int32_t c = 0; c < k; c++) {
     X->h_off[c + 1] = X->h_off[c] + X->h_cnt[c];
     X->h_bgoff[c + 1] = X->h_bgoff[c] + X->h_nb[c];
-    X->h_P[c] = (int32_t)round_up(X->h_cnt[c], spq::COMP_TILE);
+    // components above BIG_COMP vertices are closed by the multi-workgroup
+    // blocked rounds (128-tiles); the rest one workgroup each
+    const bool big = X->h_cnt[c] > spq::BIG_COMP;
+    X->h_P[c] = (int32_t)round_up(X->h_cnt[c], big ? 128 : spq::COMP_TILE);
     X->h_moff[c] = X->comp_elems;
     X->comp_elems += (int64_t)X->h_P[c] * X->h_P[c];
     X->max_comp = std::max(X->max_comp, X->h_cnt[c]);
     X->max_nb = std::max(X->max_nb, X->h_nb[c]);
     X->relax_comp += (double)X->h_cnt[c] * X->h_cnt[c] * X->h_cnt[c];
-    // one workgroup runs the blocked rounds on 64-tiles, i <= j interior tiles only
-    const int64_t ntc = X->h_P[c] / spq::COMP_TILE;
-    X->relax_comp_exec += (double)ntc * 64.0 * 64.0 * 64.0 *
-                          (1.0 + (ntc - 1) + (double)(ntc - 1) * ntc / 2.0);
+    if (big) {
+      X->relax_comp_exec += spq::dense_fw_exec_relax(X->h_P[c] / 128, 128);
+      X->nbig++;
+    } else {
+      // one workgroup runs the blocked rounds on 64-tiles, i <= j interior tiles only
+      const int64_t ntc = X->h_P[c] / spq::COMP_TILE;
+      X->relax_comp_exec += (double)ntc * 64.0 * 64.0 * 64.0 *
+                            (1.0 + (ntc - 1) + (double)(ntc - 1) * ntc / 2.0);
+    }
   }
   X->V = X->h_bgoff[k];
   X->relax_bg = (double)X->V * X->V * X->V;
@@ -538,10 +546,17 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   ca.k = k; ca.m = m; ca.eu = eu; ca.ev = ev; ca.w = w; ca.comp = X->comp; ca.local = X->local;
   ca.P = X->P; ca.moff = X->moff; ca.M = X->M;
   TRY(spq::launch_components(ca, s));
+  // order[] lists components largest first: the big ones lead
+  for (int32_t b = 0; b < X->nbig; b++) {
+    const int32_t c = X->h_order[b];
+    TRY(spq::launch_dense_fw(X->M + X->h_moff[c], X->h_P[c], 128, X->h_P[c] / 128, s, nullptr,
+                             inner_kc));
+  }
   if (plain) {
-    for (int32_t c = 0; c < k; c++) TRY(spq::launch_comp_fw(1, X->order + c, X->P, X->moff, X->M, s));
+    for (int32_t c = X->nbig; c < k; c++)
+      TRY(spq::launch_comp_fw(1, X->order + c, X->P, X->moff, X->M, s));
   } else {
-    TRY(spq::launch_comp_fw(k, X->order, X->P, X->moff, X->M, s));
+    TRY(spq::launch_comp_fw(k - X->nbig, X->order + X->nbig, X->P, X->moff, X->M, s));
   }
   TRY(hipEventRecord(X->ev[2], s));
 

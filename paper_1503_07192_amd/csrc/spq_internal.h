@@ -12,6 +12,9 @@ enum : u32 { ERR_PART = 1u, ERR_VERTEX = 2u, ERR_WEIGHT = 4u };
 
 // Component tables are padded to a multiple of this side.
 constexpr int COMP_TILE = 64;
+// Components with more vertices are closed by the multi-workgroup blocked
+// rounds (padded to 128) instead of one workgroup each.
+constexpr int BIG_COMP = 1024;
 
 struct PartArgs {
   int32_t n, k;

@@ -237,6 +237,23 @@ def test_index_small_graphs_all_pairs(g):
     check_queries(g, idx, v1, v2)
 
 
+def test_large_components_use_the_multi_workgroup_closure():
+    rng = np.random.default_rng(66)
+    eu, ev, w = W.random_grid(rng, 35, 40, keep=0.9, diag=0.2)
+    n = 1400
+    part = np.where(np.arange(n) < 1200, 0, 1 + (np.arange(n) % 3)).astype(np.int32)
+    g = dict(name="bigcomp", n=n, eu=eu, ev=ev, w=w, part=part, k=4)
+    for kw in ({}, {"plain": True}, {"bg_method": 2, "group_comps": 2}):
+        idx = build(g, **kw)
+        lay = spq.index_layout(idx)
+        check_layout(g, lay)
+        check_components(g, idx, lay)
+        rng2 = np.random.default_rng(1)
+        v1 = rng2.integers(0, n, 3000).astype(np.int32)
+        v2 = rng2.integers(0, n, 3000).astype(np.int32)
+        check_queries(g, idx, v1, v2)
+
+
 def test_grid32_everything():
     g = W.grid32()
     idx = build(g)
