@@ -589,3 +589,33 @@ def test_cached_memory_release_and_rebuild():
     spq.release_cached_memory()
     c = build(g)                      # fresh allocations
     assert np.array_equal(spq.index_bg_rows(c, 0, 348, 348), ra)
+
+
+def test_two_level_degenerate_groups():
+    """One group (no level-2 graph at all), groups cut off from every other
+    group (empty B2), and disconnected pieces, against Dijkstra."""
+    rng = np.random.default_rng(90)
+    # four disjoint 6x6 grids; components are 3x3 blocks, 4 per grid
+    parts_u, parts_v, parts_w, part = [], [], [], []
+    for piece in range(4):
+        eu, ev, w = W.random_grid(rng, 6, 6, keep=0.9, diag=0.3, wlo=0, whi=40)
+        parts_u.append(eu + 36 * piece)
+        parts_v.append(ev + 36 * piece)
+        parts_w.append(w)
+        pp, _ = W.block_partition(6, 6, 3, 3)
+        part.append(pp + 4 * piece)
+    g = dict(name="pieces", n=144, eu=np.concatenate(parts_u), ev=np.concatenate(parts_v),
+             w=np.concatenate(parts_w), part=np.concatenate(part).astype(np.int32), k=16)
+    v1, v2 = all_pairs(144)
+    for gc in (4, 8, 16, 3):
+        idx = build(g, bg_method=2, group_comps=gc)
+        st = spq.index_stats(idx)
+        if gc == 4:
+            assert st["v_bg2"] == 0          # each group is one piece
+        if gc == 16:
+            assert st["ngroups"] == 1 and st["v_bg2"] == 0
+        lay = spq.index_layout(idx)
+        check_bg_rows(g, idx, lay, np.arange(st["v_bg"]))
+        check_queries(g, idx, v1, v2)
+    share = build(g, share_comps=5, group_comps=4)
+    check_share(g, share, 5)
