@@ -68,10 +68,17 @@ typedef struct {
   int32_t inner_kc;    /* K chunk of the Floyd-Warshall interior-tile kernel:
                           0 (default 16), 16 or 32 (see the autotuner) */
   int32_t flags;       /* SPQ_NO_LOOKAHEAD: flat BG rounds without the overlap
-                          of the next round's diagonal and panel work */
+                          of the next round's diagonal and panel work.
+                          SPQ_GRAPH: the device work that depends on the
+                          weights (Phase 2, BG assembly and closure) is
+                          captured into HIP graphs, launched, and kept in the
+                          index for spq_reweight_index; the index keeps
+                          device copies of eu, ev, w (12 bytes per edge).
+                          Not with share_comps or profile */
 } spq_build_opts;
 
 #define SPQ_NO_LOOKAHEAD 1
+#define SPQ_GRAPH 2
 
 typedef struct {
   int32_t n, k;            /* vertices, components */
@@ -101,7 +108,13 @@ typedef struct {
   float ms_partition;      /* device time: boundary, renumbering (through the host plan) */
   float ms_components;     /* device time: APSP(C) initialisation + Floyd-Warshall */
   float ms_bg_assembly;    /* device time: BG matrix assembly */
-  float ms_bg_apsp;        /* device time: Floyd-Warshall in BG */
+  float ms_bg_apsp;        /* device time: Floyd-Warshall in BG.  With SPQ_GRAPH
+                              the phases run as one graph: ms_components and
+                              ms_bg_assembly are 0 and ms_bg_apsp covers
+                              Phases 2 and 3 */
+  int32_t graphs;          /* HIP graphs held for spq_reweight_index (0 without SPQ_GRAPH) */
+  int32_t reweights;       /* successful spq_reweight_index calls */
+  int64_t graph_nodes;     /* nodes (kernel launches, event waits) in those graphs */
 } spq_stats;
 
 /*
@@ -140,10 +153,34 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
  * A pair with an id outside [0, n), or (share mode) with v1 outside the
  * share's components, yields SPQ_BAD_PAIR in its slot; other slots are
  * unaffected.  Read-only on the index: calls may run concurrently
- * on different streams.  Errors: SPQ_EINVAL (null index, q < 0), SPQ_EDEVICE.
+ * on different streams.  Errors: SPQ_EINVAL (null index, q < 0), SPQ_ERANGE
+ * (index invalidated by a failed spq_reweight_index), SPQ_EDEVICE.
  */
 spq_status spq_query_batch(const spq_index* idx, int64_t q, const int32_t* v1,
                            const int32_t* v2, int32_t* out, void* stream);
+
+/*
+ * New edge weights for an index built with SPQ_GRAPH: same graph (eu, ev in
+ * the same order), same partition, so the boundary, the renumbering, the
+ * group plan and every launch shape stay; Phases 2 and 3 are recomputed by
+ * replaying the captured graphs on `stream`.
+ *   w       DEVICE array of m int32 (m as built), 0 <= w < SPQ_INF; read
+ *           during the call only
+ *   stream  hipStream_t (NULL = default stream); the call validates w (one
+ *           small device to host copy), queues the replay after the index's
+ *           last build or reweight, and returns (with the exactness
+ *           certificate, below, it waits for the replay)
+ * Queries queued later on `stream` see the new distances; queries still
+ * running on other streams must finish first (the caller orders them).
+ * When the total weight reaches SPQ_INF the result is certified as in the
+ * build (connected components are computed once, on first need).
+ * Errors: SPQ_EINVAL (NULL index, index built without SPQ_GRAPH, bad weight;
+ * the index is unchanged), SPQ_ERANGE (a component's weights reach SPQ_INF:
+ * index unchanged; or the certificate fails after the replay: the index is
+ * invalid and every later query or reweight on it returns SPQ_ERANGE),
+ * SPQ_EDEVICE.
+ */
+spq_status spq_reweight_index(spq_index* idx, const int32_t* w, void* stream);
 
 /* Sizes, work counts and per-phase device times (waits for the build). */
 spq_status spq_index_stats(const spq_index* idx, spq_stats* st);

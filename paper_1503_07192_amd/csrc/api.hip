@@ -159,6 +159,15 @@ struct spq_index {
   std::vector<hipEvent_t> prof;  // pairs around the BG interior-tile launches
   double relax_comp = 0, relax_bg = 0, relax_comp_exec = 0, relax_bg_exec = 0, relax_inner = 0;
   int64_t inner_launches = 0;
+  // SPQ_GRAPH: captured Phase 2-3 work, replayed by spq_reweight_index on
+  // the index's own copies of the edges
+  bool graph = false, fused_cert = false, valid = true;
+  hipStream_t cap = nullptr;
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs;
+  int64_t graph_nodes = 0;
+  int32_t reweights = 0;
+  int32_t *eu_own = nullptr, *ev_own = nullptr, *w_own = nullptr;
 
   ~spq_index() {
     if (events) {
@@ -171,14 +180,44 @@ struct spq_index {
     if (side) (void)hipStreamDestroy(side);
     // no queued work of this index may still use its memory once it is cached
     (void)hipDeviceSynchronize();
+    for (auto x : execs) (void)hipGraphExecDestroy(x);
+    for (auto g : graphs) (void)hipGraphDestroy(g);
+    if (cap) (void)hipStreamDestroy(cap);
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
                     vrec, grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
-                    bgvert, label, bglabel, cert, A,    DT,    DT2,   bfflag,  xe, xcount};
+                    bgvert, label, bglabel, cert, A,    DT,    DT2,   bfflag,  xe, xcount,
+                    eu_own, ev_own, w_own};
     for (void* p : ptrs) pool_release(p);
   }
 };
+
+// Queues body(stream): directly on s, or (SPQ_GRAPH) captured on the index's
+// capture stream into a HIP graph that is instantiated, launched on s and
+// kept for spq_reweight_index.  body must queue device work only (no
+// allocation, no host copy, no synchronization, no memset).
+template <typename F>
+static hipError_t graph_segment(spq_index* X, hipStream_t s, F&& body) {
+  if (!X->graph) return body(s);
+  hipError_t e = hipStreamBeginCapture(X->cap, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return e;
+  const hipError_t eb = body(X->cap);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(X->cap, &g);
+  if (g) X->graphs.push_back(g);
+  if (eb != hipSuccess) return eb;
+  if (e != hipSuccess) return e;
+  size_t nodes = 0;
+  e = hipGraphGetNodes(g, nullptr, &nodes);
+  if (e != hipSuccess) return e;
+  X->graph_nodes += (int64_t)nodes;
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) return e;
+  X->execs.push_back(x);
+  return hipGraphLaunch(x, s);
+}
 
 // Share mode (after level 1): Bellman-Ford over groups from the share's
 // level-2 vertices, then the composition for the share's groups against all
@@ -292,12 +331,13 @@ static spq_status cc_labels(spq_index* X, int64_t m, const int32_t* eu, const in
 }
 
 // The exactness certificate (range.hip) when the total edge weight reaches
-// SPQ_INF; cc_labels must have run.  For the two-level store the BG check ran
-// inside the composition kernel.  Synchronous.
+// SPQ_INF; cc_labels must have run.  For the two-level store the BG check
+// runs inside the composition kernel when that kernel was given the labels
+// (fused_cert); otherwise here.  Synchronous.
 static spq_status certify(spq_index* X, hipStream_t s) {
   if (!X->certify) return SPQ_OK;
   spq::CertArgs c{};
-  c.bg_checked = X->method == 2;
+  c.bg_checked = X->method == 2 && X->fused_cert;
   c.V = X->V; c.ngroups = X->ngroups; c.Vgp = X->Vgp; c.Vp = X->Vp; c.comp_elems = X->comp_elems;
   c.M = X->M; c.BG = X->BG; c.H = X->method == 2 ? X->H : nullptr; c.bgvert = X->bgvert;
   c.label = X->label; c.gV = X->gV; c.gbg0 = X->gbg0; c.bgrow = X->bgrow; c.bgnb = X->bgnb;
@@ -333,7 +373,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   int tile = 128;
   bool profile = false, plain = false;
   int32_t method_opt = 0, group_comps = 0, share_comps = 0, inner_kc = 0;
-  bool lookahead = true;
+  bool lookahead = true, use_graph = false;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
@@ -352,8 +392,11 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     inner_kc = opts->inner_kc;
     if (inner_kc != 0 && inner_kc != 16 && inner_kc != 32)
       return fail(SPQ_EINVAL, "inner_kc must be 0, 16 or 32");
-    if (opts->flags & ~SPQ_NO_LOOKAHEAD) return fail(SPQ_EINVAL, "unknown flags");
+    if (opts->flags & ~(SPQ_NO_LOOKAHEAD | SPQ_GRAPH)) return fail(SPQ_EINVAL, "unknown flags");
     lookahead = !(opts->flags & SPQ_NO_LOOKAHEAD);
+    use_graph = (opts->flags & SPQ_GRAPH) != 0;
+    if (use_graph && (share_comps > 0 || profile))
+      return fail(SPQ_EINVAL, "SPQ_GRAPH cannot be combined with share_comps or profile");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   spq_index* X = new spq_index();
@@ -365,6 +408,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   X->k = k;
   X->m = m;
   X->tile = tile;
+  X->graph = use_graph;
   {
     hipError_t e = hipGetDevice(&X->device);
     if (e != hipSuccess) return guard(fail(SPQ_EDEVICE, hipGetErrorString(e)));
@@ -528,6 +572,21 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   TRY(hipMemcpyAsync(X->order, X->h_order.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
   TRY(hipMemcpyAsync(X->moff, X->h_moff.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
   TRY(hipMemsetAsync(X->fill, 0, sizeof(int32_t) * k, s));
+  if (X->graph) {
+    // the captured kernels read the index's own copies of the edges
+    TRY(dalloc(&X->eu_own, m));
+    TRY(dalloc(&X->ev_own, m));
+    TRY(dalloc(&X->w_own, m));
+    if (m > 0) {
+      TRY(hipMemcpyAsync(X->eu_own, eu, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s));
+      TRY(hipMemcpyAsync(X->ev_own, ev, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s));
+      TRY(hipMemcpyAsync(X->w_own, w, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s));
+    }
+    eu = X->eu_own;
+    ev = X->ev_own;
+    w = X->w_own;
+    TRY(hipStreamCreateWithFlags(&X->cap, hipStreamNonBlocking));  // default priority
+  }
 
   // ---- renumbering (Section 4, Fig. 1)
   pa.off = X->off; pa.bgoff = X->bgoff; pa.fill = X->fill; pa.members = X->members;
@@ -545,20 +604,29 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   spq::CompArgs ca{};
   ca.k = k; ca.m = m; ca.eu = eu; ca.ev = ev; ca.w = w; ca.comp = X->comp; ca.local = X->local;
   ca.P = X->P; ca.moff = X->moff; ca.M = X->M;
-  TRY(spq::launch_components(ca, s));
-  // order[] lists components largest first: the big ones lead
-  for (int32_t b = 0; b < X->nbig; b++) {
-    const int32_t c = X->h_order[b];
-    TRY(spq::launch_dense_fw(X->M + X->h_moff[c], X->h_P[c], 128, X->h_P[c] / 128, s, nullptr,
-                             inner_kc));
+  auto phase2 = [&](hipStream_t st) -> hipError_t {
+    hipError_t e = spq::launch_components(ca, st);
+    // order[] lists components largest first: the big ones lead
+    for (int32_t b = 0; b < X->nbig && e == hipSuccess; b++) {
+      const int32_t c = X->h_order[b];
+      e = spq::launch_dense_fw(X->M + X->h_moff[c], X->h_P[c], 128, X->h_P[c] / 128, st, nullptr,
+                               inner_kc);
+    }
+    if (e != hipSuccess) return e;
+    if (plain) {
+      for (int32_t c = X->nbig; c < k && e == hipSuccess; c++)
+        e = spq::launch_comp_fw(1, X->order + c, X->P, X->moff, X->M, st);
+    } else {
+      e = spq::launch_comp_fw(k - X->nbig, X->order + X->nbig, X->P, X->moff, X->M, st);
+    }
+    if (e == hipSuccess && !X->graph) e = hipEventRecord(X->ev[2], st);
+    return e;
+  };
+  if (X->graph) {
+    // one graph covers the phases: no split of their device time
+    TRY(hipEventRecord(X->ev[2], s));
+    TRY(hipEventRecord(X->ev[3], s));
   }
-  if (plain) {
-    for (int32_t c = X->nbig; c < k; c++)
-      TRY(spq::launch_comp_fw(1, X->order + c, X->P, X->moff, X->M, s));
-  } else {
-    TRY(spq::launch_comp_fw(k - X->nbig, X->order + X->nbig, X->P, X->moff, X->M, s));
-  }
-  TRY(hipEventRecord(X->ev[2], s));
 
   // ---- Phase 3: BG and its all-pairs distances
   if (X->method == 2) {
@@ -573,6 +641,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     TRY(dalloc(&X->bgrow, V));
     TRY(dalloc(&X->bgnb, V));
     TRY(dalloc(&X->bggrp, V));
+    // level-2 boundary flags depend on the edges only and are only ever set
     if (V > 0) TRY(hipMemsetAsync(X->flag2, 0, V, s));
     ha.V = V; ha.ngroups = G; ha.Vgp = Vgp; ha.m = m; ha.kc = inner_kc;
     ha.eu = eu; ha.ev = ev; ha.w = w; ha.comp = X->comp; ha.local = X->local; ha.bgoff = X->bgoff;
@@ -580,8 +649,12 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     ha.M = X->M; ha.grp = X->grp; ha.gbg0 = X->gbg0; ha.gV = X->gV; ha.bgrow = X->bgrow;
     ha.bgnb = X->bgnb; ha.bggrp = X->bggrp; ha.Mg = X->Mg; ha.flag2 = X->flag2; ha.b2list = X->b2list;
     ha.b2rank = X->b2rank; ha.m2 = X->m2;
-    TRY(hipEventRecord(X->ev[3], s));
-    TRY(spq::launch_hier_level1(ha, s));
+    TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
+      hipError_t e = phase2(st);
+      if (e == hipSuccess && !X->graph) e = hipEventRecord(X->ev[3], st);
+      if (e == hipSuccess) e = spq::launch_hier_level1(ha, st);
+      return e;
+    }));
     X->h_m2.resize(G);
     TRY(hipMemcpyAsync(X->h_m2.data(), X->m2, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
@@ -641,8 +714,9 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       ha.bglabel = X->bglabel;
       ha.cert_bad = X->cert + 1;
       ha.cert_mbg = X->cert + 3;
+      X->fused_cert = true;
     }
-    TRY(spq::launch_hier_level2(ha, s));
+    TRY(graph_segment(X, s, [&](hipStream_t st) { return spq::launch_hier_level2(ha, st); }));
     TRY(hipEventRecord(X->ev[4], s));
     spq_status cs = certify(X, s);
     if (cs != SPQ_OK) return guard(cs);
@@ -654,21 +728,26 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   ba.comp = X->comp; ba.local = X->local; ba.bgoff = X->bgoff; ba.nb = X->nb;
   ba.bgcomp = X->bgcomp; ba.bglocal = X->bglocal; ba.P = X->P; ba.moff = X->moff;
   ba.M = X->M; ba.BG = X->BG;
-  TRY(spq::launch_bg_assembly(ba, s));
-  TRY(hipEventRecord(X->ev[3], s));
   if (profile && X->inner_launches > 0) {
     X->prof.resize(2 * X->inner_launches);
     for (auto& e : X->prof) TRY(hipEventCreate(&e));
   }
-  if (lookahead && X->Vp / tile > 1) {
+  const bool la = lookahead && X->Vp / tile > 1;
+  if (la) {
     TRY(hipStreamCreateWithFlags(&X->side, hipStreamNonBlocking));  // default priority
     for (auto& e : X->la_sync) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    TRY(spq::launch_dense_fw_lookahead(X->BG, X->Vp, tile, X->Vp / tile, s, X->side, X->la_sync,
-                                       X->prof.empty() ? nullptr : X->prof.data(), inner_kc));
-  } else {
-    TRY(spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, s,
-                             X->prof.empty() ? nullptr : X->prof.data(), inner_kc));
   }
+  hipEvent_t* pev = X->prof.empty() ? nullptr : X->prof.data();
+  TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
+    hipError_t e = phase2(st);
+    if (e == hipSuccess) e = spq::launch_bg_assembly(ba, st);
+    if (e == hipSuccess && !X->graph) e = hipEventRecord(X->ev[3], st);
+    if (e != hipSuccess) return e;
+    if (la)
+      return spq::launch_dense_fw_lookahead(X->BG, X->Vp, tile, X->Vp / tile, st, X->side,
+                                            X->la_sync, pev, inner_kc);
+    return spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, st, pev, inner_kc);
+  }));
   TRY(hipEventRecord(X->ev[4], s));
 #undef TRY
   spq_status cs = certify(X, s);
@@ -677,9 +756,72 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   return SPQ_OK;
 }
 
+// Replays the captured Phase 2-3 graphs with new weights (see spq.h).
+spq_status spq_reweight_index(spq_index* X, const int32_t* w, void* stream) {
+  g_err.clear();
+  if (!X) return fail(SPQ_EINVAL, "index is NULL");
+  if (!X->graph) return fail(SPQ_EINVAL, "index was built without SPQ_GRAPH");
+  if (!X->valid) return fail(SPQ_ERANGE, "index invalidated by a failed reweight");
+  if (X->m > 0 && !w) return fail(SPQ_EINVAL, "w is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int32_t k = X->k;
+  HIP_TRY(hipStreamWaitEvent(s, X->ev[4], 0));
+  HIP_TRY(hipEventRecord(X->ev[0], s));
+  // validate the new weights and sum them, per component and in total
+  HIP_TRY(hipMemsetAsync(X->sumc, 0, sizeof(unsigned long long) * k, s));
+  HIP_TRY(hipMemsetAsync(X->total, 0, sizeof(unsigned long long), s));
+  HIP_TRY(hipMemsetAsync(X->err, 0, sizeof(u32), s));
+  spq::PartArgs pa{};
+  pa.n = X->n; pa.k = k; pa.m = X->m; pa.eu = X->eu_own; pa.ev = X->ev_own; pa.w = w;
+  pa.part = X->comp; pa.flag = X->flag; pa.sumc = X->sumc; pa.total = X->total; pa.err = X->err;
+  HIP_TRY(spq::launch_edges_scan(pa, s));
+  u32 herr = 0;
+  unsigned long long htotal = 0;
+  HIP_TRY(hipMemcpyAsync(&herr, X->err, sizeof(u32), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&htotal, X->total, sizeof(htotal), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(X->h_sumc.data(), X->sumc, sizeof(unsigned long long) * k,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (herr & spq::ERR_WEIGHT) return fail(SPQ_EINVAL, "edge weight outside [0, SPQ_INF)");
+  if (herr) return fail(SPQ_EDEVICE, "edge scan reported an inconsistent index");
+  const bool cert = htotal >= (unsigned long long)SPQ_INF;
+  if (cert)
+    for (int32_t c = 0; c < k; c++)
+      if (X->h_sumc[c] >= (unsigned long long)SPQ_INF)
+        return fail(SPQ_ERANGE, "edge weights inside component " + std::to_string(c) +
+                                    " reach SPQ_INF; distances might not fit in int32");
+  // commit: from here on the index holds the new weights
+  if (X->m > 0)
+    HIP_TRY(hipMemcpyAsync(X->w_own, w, sizeof(int32_t) * X->m, hipMemcpyDeviceToDevice, s));
+  X->certify = cert;
+  if (cert) {
+    if (!X->label) {
+      spq_status cs = cc_labels(X, X->m, X->eu_own, X->ev_own, s);
+      if (cs != SPQ_OK) {
+        X->valid = false;
+        return cs;
+      }
+    }
+    HIP_TRY(hipMemsetAsync(X->cert, 0, 4 * sizeof(u32), s));
+  }
+  HIP_TRY(hipEventRecord(X->ev[1], s));
+  HIP_TRY(hipEventRecord(X->ev[2], s));
+  HIP_TRY(hipEventRecord(X->ev[3], s));
+  for (hipGraphExec_t x : X->execs) HIP_TRY(hipGraphLaunch(x, s));
+  HIP_TRY(hipEventRecord(X->ev[4], s));
+  spq_status cs = certify(X, s);
+  if (cs != SPQ_OK) {
+    X->valid = false;
+    return cs;
+  }
+  X->reweights++;
+  return SPQ_OK;
+}
+
 spq_status spq_query_batch(const spq_index* X, int64_t q, const int32_t* v1, const int32_t* v2,
                            int32_t* out, void* stream) {
   if (!X) return fail(SPQ_EINVAL, "index is NULL");
+  if (!X->valid) return fail(SPQ_ERANGE, "index invalidated by a failed reweight");
   if (q < 0) return fail(SPQ_EINVAL, "q < 0");
   if (q == 0) return SPQ_OK;
   if (!v1 || !v2 || !out) return fail(SPQ_EINVAL, "null query array");
@@ -711,6 +853,9 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   st->share_comps = X->share_comps;
   st->share_groups = X->share_groups;
   st->bf_rounds = X->bf_rounds;
+  st->graphs = (int32_t)X->execs.size();
+  st->reweights = X->reweights;
+  st->graph_nodes = X->graph_nodes;
   if (X->method == 2) {
     st->v_bg_padded = X->Vgp;
     st->bg_bytes = (int64_t)X->h_elems * 4;

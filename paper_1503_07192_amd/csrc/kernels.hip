@@ -539,6 +539,16 @@ hipError_t launch_partition_scan(const PartArgs& a, hipStream_t s) {
   LAUNCH_CHECK();
 }
 
+hipError_t launch_edges_scan(const PartArgs& a, hipStream_t s) {
+  if (a.m > 0) {
+    unsigned g = blocks_for(a.m);
+    if (g > 4096) g = 4096;
+    k_edges_scan<<<g, 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.n, a.part, a.k, a.flag, a.sumc, a.total,
+                                   a.err);
+  }
+  LAUNCH_CHECK();
+}
+
 hipError_t launch_renumber(const PartArgs& a, hipStream_t s) {
   k_members<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.part, a.flag, a.off, a.fill, a.members);
   k_rank<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.k, a.members, a.off, a.nb, a.bgoff, a.comp, a.local,

@@ -126,6 +126,8 @@ hipError_t launch_bg_label(int32_t V, const int32_t* bgvert, const int32_t* labe
 
 hipError_t launch_partition_scan(const PartArgs& a, hipStream_t s);
 hipError_t launch_renumber(const PartArgs& a, hipStream_t s);
+// Edge validation and weight sums only (a.part may be the renumbered comp[]).
+hipError_t launch_edges_scan(const PartArgs& a, hipStream_t s);
 hipError_t launch_components(const CompArgs& a, hipStream_t s);
 hipError_t launch_comp_fw(int32_t count, const int32_t* order, const int32_t* P, const int64_t* moff,
                           u32* M, hipStream_t s);

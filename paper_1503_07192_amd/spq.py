@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "spq.h")
 SPQ_INF = 2147483647
 SPQ_BAD_PAIR = -1
 SPQ_NO_LOOKAHEAD = 1
+SPQ_GRAPH = 2
 STATUS = {0: "SPQ_OK", 1: "SPQ_EINVAL", 2: "SPQ_ENOMEM", 3: "SPQ_EDEVICE", 4: "SPQ_ERANGE"}
 
 
@@ -52,7 +53,9 @@ class Stats(ctypes.Structure):
                 ("v_bg2", ctypes.c_int32), ("share_comps", ctypes.c_int32),
                 ("share_groups", ctypes.c_int32), ("bf_rounds", ctypes.c_int32),
                 ("ms_partition", ctypes.c_float), ("ms_components", ctypes.c_float),
-                ("ms_bg_assembly", ctypes.c_float), ("ms_bg_apsp", ctypes.c_float)]
+                ("ms_bg_assembly", ctypes.c_float), ("ms_bg_apsp", ctypes.c_float),
+                ("graphs", ctypes.c_int32), ("reweights", ctypes.c_int32),
+                ("graph_nodes", ctypes.c_int64)]
 
 
 _lib = None
@@ -62,6 +65,7 @@ _SIGS = {
     "spq_build_index": (I32, [I32, I64, P, P, P, P, I32, ctypes.POINTER(BuildOpts), P,
                               ctypes.POINTER(P)]),
     "spq_query_batch": (I32, [P, I64, P, P, P, P]),
+    "spq_reweight_index": (I32, [P, P, P]),
     "spq_index_stats": (I32, [P, ctypes.POINTER(Stats)]),
     "spq_index_layout": (I32, [P, P, P, P, P, P]),
     "spq_index_component": (I32, [P, I32, P]),
@@ -154,10 +158,11 @@ class Index:
 
 
 def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg_method=0,
-                group_comps=0, share_comps=0, inner_kc=0, lookahead=True, tune_cache=None,
-                stream=None) -> Index:
+                group_comps=0, share_comps=0, inner_kc=0, lookahead=True, graph=False,
+                tune_cache=None, stream=None) -> Index:
     """Algorithm 1 on device tensors; see spq_build_index.
 
+    graph: capture Phases 2-3 as HIP graphs kept for reweight().
     tune_cache: path of an autotuner cache (paper_1503_07192_amd.autotune);
     options it holds for this device and problem size fill in the ones left
     at 0 here."""
@@ -172,7 +177,7 @@ def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg
     opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)), plain=int(bool(plain)),
                      bg_method=int(bg_method), group_comps=int(group_comps),
                      share_comps=int(share_comps), inner_kc=int(inner_kc),
-                     flags=0 if lookahead else SPQ_NO_LOOKAHEAD)
+                     flags=(0 if lookahead else SPQ_NO_LOOKAHEAD) | (SPQ_GRAPH if graph else 0))
     h = ctypes.c_void_p()
     m = int(eu.numel())
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),
@@ -180,6 +185,13 @@ def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg
                            ctypes.byref(h))
     _check(st)
     return Index(h, int(n), int(k))
+
+
+def reweight(index: Index, w, stream=None):
+    """New edge weights (device int32, the build's edge order) for an index
+    built with graph=True; see spq_reweight_index."""
+    _check(load().spq_reweight_index(index.handle, _dev_i32(w, "w"), _stream(stream)))
+    return index
 
 
 def query_batch(index: Index, v1, v2, out=None, stream=None):

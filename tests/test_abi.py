@@ -36,6 +36,15 @@ def test_argument_errors_without_device():
     assert L.spq_fw_dense(0, 0, 64, 0, None, None) == 0
     assert L.spq_fw_components(-1, None, None, None, None, None) == 1
     assert L.spq_index_stats(None, None) == 1
+    assert L.spq_reweight_index(None, None, None) == 1
+    part = ctypes.c_void_p(8)
+    for flags, share, profile, msg in ((4, 0, 0, "unknown flags"),
+                                       (spq.SPQ_GRAPH, 1, 0, "SPQ_GRAPH"),
+                                       (spq.SPQ_GRAPH, 0, 1, "SPQ_GRAPH")):
+        opts = spq.BuildOpts(flags=flags, share_comps=share, profile=profile)
+        assert L.spq_build_index(5, 0, None, None, None, part, 2, ctypes.byref(opts), None,
+                                 ctypes.byref(h)) == 1
+        assert msg in spq.last_error()
     L.spq_free_index(None)
 
 
