@@ -214,6 +214,33 @@ def main():
                    "answers_identical": bool(torch.equal(ref, out))}
             idx.free()
 
+    # the build captured as HIP graphs, then replays of those graphs with other
+    # weights and back (spq_reweight_index); the last replay restores the
+    # workload's weights, so its answers must equal the timed steps'
+    graph = None
+    if not st["share_comps"]:
+        ref = out.clone()
+        w2 = torch.remainder(w, 997) + 1
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], graph=True, stream=stream,
+                              **build_kw)
+        torch.cuda.synchronize()
+        t_cap = time.perf_counter() - t1
+        reps = []
+        for wr in (w2, w, w2, w):
+            t1 = time.perf_counter()
+            spq.reweight(idx, wr, stream=stream)
+            torch.cuda.synchronize()
+            reps.append((time.perf_counter() - t1) * 1e3)
+        spq.query_batch(idx, v1, v2, out, stream=stream)
+        torch.cuda.synchronize()
+        gst = spq.index_stats(idx)
+        graph = {"build_ms": t_cap * 1e3, "reweight_ms_p50": float(np.median(reps)),
+                 "reweight_ms": reps, "graphs": gst["graphs"], "graph_nodes": gst["graph_nodes"],
+                 "answers_identical": bool(torch.equal(ref, out))}
+        idx.free()
+
     # the plain comparators, after the timed region: one launch per component
     # for APSP(C), and one query per launch
     idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], plain=True, stream=stream, **build_kw)
@@ -246,6 +273,7 @@ def main():
                    "n": g["n"], "m": g["m"], "k": g["k"], "v_bg": st["v_bg"], "queries": q,
                    "bg_method": "flat" if st["bg_method"] == 1 else "two-level",
                    "groups": st["ngroups"], "v_bg2": st["v_bg2"],
+                   "groups3": st["groups3"], "v_bg3": st["v_bg3"],
                    "share_comps": st["share_comps"], "bg_bytes": st["bg_bytes"]},
         "phase_ms": {key: float(np.median([r[key] for r in recs]))
                      for key in ("ms_partition", "ms_components", "ms_bg_assembly",
@@ -256,6 +284,7 @@ def main():
         "query_batch_ms_p50": float(np.percentile(mq, 50)),
         "query_batch_ms_p99": float(np.percentile(mq, 99)),
         "other_bg_method": alt,
+        "graph_build": graph,
         "plain_components_ms": plain_st["ms_components"],
         "batched_components_ms": float(np.median([r["ms_components"] for r in recs])),
         "single_query_us_p50": float(np.percentile(lat, 50)),

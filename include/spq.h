@@ -75,6 +75,12 @@ typedef struct {
                           index for spq_reweight_index; the index keeps
                           device copies of eu, ev, w (12 bytes per edge).
                           Not with share_comps or profile */
+  int32_t level3_groups; /* two-level: BG2 (the graph of the group boundaries)
+                          is closed by flat Floyd-Warshall, or, above 16,384
+                          BG2 vertices, by the same construction once more on
+                          super-groups of consecutive groups (level 3).
+                          0 auto (about 4,096 BG2 vertices per super-group),
+                          -1 never, g > 0 always, g groups per super-group */
 } spq_build_opts;
 
 #define SPQ_NO_LOOKAHEAD 1
@@ -115,6 +121,8 @@ typedef struct {
   int32_t graphs;          /* HIP graphs held for spq_reweight_index (0 without SPQ_GRAPH) */
   int32_t reweights;       /* successful spq_reweight_index calls */
   int64_t graph_nodes;     /* nodes (kernel launches, event waits) in those graphs */
+  int32_t groups3;         /* level-3 super-groups (0: BG2 closed flat) */
+  int32_t v_bg3;           /* level-3 boundary vertices */
 } spq_stats;
 
 /*

@@ -140,6 +140,14 @@ struct spq_index {
   uint8_t* flag2 = nullptr;
   u32 *Mg = nullptr, *R = nullptr, *XT = nullptr, *BG2 = nullptr, *H = nullptr;
   int64_t* pairbase = nullptr;
+  // level 3 (closure of BG2 by super-groups of gpt groups)
+  int32_t nT = 0, gpt = 0, V3gp = 0, V3 = 0, m3pmax = 0;
+  int64_t V3p = 0;
+  std::vector<int32_t> h_tbase, h_tsize, h_m3, h_b3off;
+  int32_t *tbase = nullptr, *tsize = nullptr, *b3list = nullptr, *b3rank = nullptr, *m3 = nullptr;
+  int32_t* b3off = nullptr;
+  uint8_t* flag3 = nullptr;
+  u32 *M3 = nullptr, *R3 = nullptr, *XT3 = nullptr, *BG3 = nullptr;
   // share mode
   int32_t share_comps = 0, share_groups = 0, S2 = 0, bf_rounds = 0;
   int64_t S2p = 0;
@@ -188,7 +196,8 @@ struct spq_index {
                     vrec, grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
                     bgvert, label, bglabel, cert, A,    DT,    DT2,   bfflag,  xe, xcount,
-                    eu_own, ev_own, w_own};
+                    eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
+                    M3, R3, XT3, BG3};
     for (void* p : ptrs) pool_release(p);
   }
 };
@@ -374,6 +383,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   bool profile = false, plain = false;
   int32_t method_opt = 0, group_comps = 0, share_comps = 0, inner_kc = 0;
   bool lookahead = true, use_graph = false;
+  int32_t level3_opt = 0;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
@@ -395,6 +405,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     if (opts->flags & ~(SPQ_NO_LOOKAHEAD | SPQ_GRAPH)) return fail(SPQ_EINVAL, "unknown flags");
     lookahead = !(opts->flags & SPQ_NO_LOOKAHEAD);
     use_graph = (opts->flags & SPQ_GRAPH) != 0;
+    level3_opt = opts->level3_groups;
+    if (level3_opt < -1) return fail(SPQ_EINVAL, "level3_groups must be -1, 0 or positive");
     if (use_graph && (share_comps > 0 || profile))
       return fail(SPQ_EINVAL, "SPQ_GRAPH cannot be combined with share_comps or profile");
   }
@@ -680,8 +692,34 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
         X->h_pairbase[(size_t)a1 * G + a2] = X->h_elems;
         X->h_elems += (int64_t)X->h_gV[a1] * X->h_gV[a2];
       }
-    // executed relaxations of level 2
-    if (X->V2p > 0) X->relax_bg_exec += spq::dense_fw_exec_relax(X->V2p / 128, 128);
+    // level 3: BG2 above 16,384 vertices (or as asked) is closed by super-groups
+    if (X->V2 > 0 && level3_opt >= 0) {
+      int32_t gpt = 0;
+      if (level3_opt > 0) {
+        gpt = std::min(level3_opt, G);
+      } else if (X->V2 > 16384) {
+        // about 4,096 BG2 vertices per super-group, a power of two of groups
+        const double avg = (double)X->V2 / G;
+        gpt = 1;
+        while (gpt * 2 <= G && gpt * 2 * avg <= 4096.0 * 1.41) gpt *= 2;
+        if (gpt >= G) gpt = 0;
+      }
+      if (gpt > 0) {
+        X->gpt = gpt;
+        X->nT = (G + gpt - 1) / gpt;
+        X->h_tbase.resize(X->nT);
+        X->h_tsize.resize(X->nT);
+        int32_t tmax = 0;
+        for (int32_t t = 0; t < X->nT; t++) {
+          X->h_tbase[t] = X->h_b2off[t * gpt];
+          X->h_tsize[t] = X->h_b2off[std::min((t + 1) * gpt, G)] - X->h_tbase[t];
+          tmax = std::max(tmax, X->h_tsize[t]);
+        }
+        X->V3gp = (int32_t)std::max<int64_t>(128, round_up(tmax, 128));
+      }
+    }
+    // executed relaxations of level 2 (its BG2 closure is counted with level 3)
+    if (X->V2p > 0 && X->nT == 0) X->relax_bg_exec += spq::dense_fw_exec_relax(X->V2p / 128, 128);
     for (int32_t a1 = 0; a1 < G; a1++)
       for (int32_t a2 = a1; a2 < G; a2++) {
         if (X->V2p > 0)
@@ -716,7 +754,75 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       ha.cert_mbg = X->cert + 3;
       X->fused_cert = true;
     }
-    TRY(graph_segment(X, s, [&](hipStream_t st) { return spq::launch_hier_level2(ha, st); }));
+    if (X->nT == 0) {
+      TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
+        hipError_t e = spq::launch_hier_level2_prep(ha, st);
+        if (e == hipSuccess) e = spq::launch_hier_level2_close(ha, st);
+        if (e == hipSuccess) e = spq::launch_hier_level2_compose(ha, st);
+        return e;
+      }));
+    } else {
+      const int32_t nT = X->nT, V3gp = X->V3gp;
+      TRY(dalloc(&X->tbase, nT));
+      TRY(dalloc(&X->tsize, nT));
+      TRY(dalloc(&X->M3, (int64_t)nT * V3gp * V3gp));
+      TRY(dalloc(&X->flag3, X->V2));
+      TRY(dalloc(&X->b3list, (int64_t)nT * V3gp));
+      TRY(dalloc(&X->b3rank, X->V2));
+      TRY(dalloc(&X->m3, nT));
+      TRY(dalloc(&X->b3off, nT + 1));
+      TRY(hipMemcpyAsync(X->tbase, X->h_tbase.data(), sizeof(int32_t) * nT, hipMemcpyHostToDevice, s));
+      TRY(hipMemcpyAsync(X->tsize, X->h_tsize.data(), sizeof(int32_t) * nT, hipMemcpyHostToDevice, s));
+      // level-3 boundary flags depend on the edges only and are only ever set
+      TRY(hipMemsetAsync(X->flag3, 0, X->V2, s));
+      spq::L3Args la{};
+      la.nT = nT; la.gpt = X->gpt; la.V3gp = V3gp; la.kc = inner_kc; la.m = m; la.V2p = X->V2p;
+      la.eu = eu; la.ev = ev; la.w = w; la.comp = X->comp; la.local = X->local; la.bgoff = X->bgoff;
+      la.grp = X->grp; la.b2off = X->b2off; la.b2rank = X->b2rank; la.BG2 = X->BG2;
+      la.tbase = X->tbase; la.tsize = X->tsize; la.M3 = X->M3; la.flag3 = X->flag3;
+      la.b3list = X->b3list; la.b3rank = X->b3rank; la.m3 = X->m3;
+      TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
+        hipError_t e = spq::launch_hier_level2_prep(ha, st);
+        if (e == hipSuccess) e = spq::launch_level3_a(la, st);
+        return e;
+      }));
+      X->h_m3.resize(nT);
+      TRY(hipMemcpyAsync(X->h_m3.data(), X->m3, sizeof(int32_t) * nT, hipMemcpyDeviceToHost, s));
+      TRY(hipStreamSynchronize(s));
+      X->h_b3off.assign(nT + 1, 0);
+      int32_t m3max = 0;
+      for (int32_t t = 0; t < nT; t++) {
+        X->h_b3off[t + 1] = X->h_b3off[t] + X->h_m3[t];
+        m3max = std::max(m3max, X->h_m3[t]);
+      }
+      X->V3 = X->h_b3off[nT];
+      X->V3p = round_up(X->V3, 128);
+      X->m3pmax = (int32_t)std::max<int64_t>(128, round_up(m3max, 128));
+      // executed relaxations of level 3
+      X->relax_bg_exec += nT * spq::dense_fw_exec_relax(V3gp / 128, 128);
+      if (X->V3p > 0) X->relax_bg_exec += spq::dense_fw_exec_relax(X->V3p / 128, 128);
+      for (int32_t t1 = 0; t1 < nT; t1++)
+        for (int32_t t2 = t1; t2 < nT; t2++) {
+          if (X->V3p > 0)
+            X->relax_bg_exec += (double)((X->h_m3[t2] + 127) / 128) * (V3gp / 128) * 128.0 * 128.0 *
+                                (double)round_up(X->h_m3[t1], 16);
+          X->relax_bg_exec += (double)((X->h_tsize[t1] + 127) / 128) *
+                              ((X->h_tsize[t2] + 127) / 128) * 128.0 * 128.0 *
+                              (double)round_up(X->h_m3[t2], 16);
+        }
+      TRY(hipMemcpyAsync(X->b3off, X->h_b3off.data(), sizeof(int32_t) * (nT + 1),
+                         hipMemcpyHostToDevice, s));
+      TRY(dalloc(&X->R3, (int64_t)nT * X->m3pmax * V3gp));
+      TRY(dalloc(&X->XT3, (int64_t)nT * X->m3pmax * V3gp));
+      if (X->V3p > 0) TRY(dalloc(&X->BG3, X->V3p * X->V3p));
+      la.V3 = X->V3; la.V3p = X->V3p; la.m3pmax = X->m3pmax; la.b3off = X->b3off; la.R3 = X->R3;
+      la.XT3 = X->XT3; la.BG3 = X->BG3;
+      TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
+        hipError_t e = spq::launch_level3_b(la, st);
+        if (e == hipSuccess) e = spq::launch_hier_level2_compose(ha, st);
+        return e;
+      }));
+    }
     TRY(hipEventRecord(X->ev[4], s));
     spq_status cs = certify(X, s);
     if (cs != SPQ_OK) return guard(cs);
@@ -856,6 +962,8 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   st->graphs = (int32_t)X->execs.size();
   st->reweights = X->reweights;
   st->graph_nodes = X->graph_nodes;
+  st->groups3 = X->nT;
+  st->v_bg3 = X->V3;
   if (X->method == 2) {
     st->v_bg_padded = X->Vgp;
     st->bg_bytes = (int64_t)X->h_elems * 4;

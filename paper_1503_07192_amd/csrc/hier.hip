@@ -402,6 +402,116 @@ __global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t s2base, int32_
   }
 }
 
+// ------------------------------------------------------------- level 3
+// The construction once more, on BG2, when BG2 itself is too large for one
+// flat Floyd-Warshall: super-groups T of consecutive groups; M3[T] = BG2
+// induced on T's vertices, closed (d_T); B3(T) = vertices of T with a G edge
+// to another super-group (the only BG2 edges that leave T); BG3 on the B3
+// vertices, closed by flat Floyd-Warshall (= d_BG2 on B3, Lemma 1 for the
+// super-group partition); then, by Lemma 3 at this level,
+//   d_BG2(x,y) = min over a in B3(T1), b in B3(T2) of
+//                d_T1(x,a) + d_BG3(a,b) + d_T2(b,y)   (and d_T1(x,y) if T1 = T2),
+// evaluated with the same two products and written straight into the dense
+// BG2 matrix for T1 <= T2: the block upper triangle the level-2 composition
+// reads (rows of a group S1, columns of a group S2 >= S1).
+
+// M3[T] (V3gp x V3gp): T's block of the unclosed BG2 matrix; 0 on the
+// padding's diagonal, INF elsewhere on the padding.
+__global__ void k_l3_gather(int64_t V2p, const u32* __restrict__ BG2, const int32_t* __restrict__ tbase,
+                            const int32_t* __restrict__ tsize, int32_t V3gp, u32* __restrict__ M3) {
+  const int t = blockIdx.y;
+  const int64_t p = blockIdx.x;
+  const int32_t nt = tsize[t];
+  u32* out = M3 + ((int64_t)t * V3gp + p) * V3gp;
+  const u32* src = BG2 + ((int64_t)tbase[t] + p) * V2p + tbase[t];
+  for (int64_t q0 = (int64_t)threadIdx.x * 4; q0 < V3gp; q0 += (int64_t)blockDim.x * 4) {
+    u32 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int64_t q = q0 + u;
+      v[u] = (p < nt && q < nt) ? src[q] : (q == p ? 0u : INF);
+    }
+    *reinterpret_cast<uint4*>(out + q0) = make_uint4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// G edges between super-groups (both ends are level-2 vertices).  BG3 ==
+// NULL: flags both ends as level-3 boundary vertices; otherwise enters the
+// edge into BG3 (ids b3off[T] + rank inside T).
+__global__ void k_l3_edges(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                           const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
+                           const int32_t* __restrict__ local, const int32_t* __restrict__ bgoff,
+                           const int32_t* __restrict__ grp, int32_t gpt, const int32_t* __restrict__ b2off,
+                           const int32_t* __restrict__ b2rank, uint8_t* __restrict__ flag3,
+                           const int32_t* __restrict__ b3off, const int32_t* __restrict__ b3rank,
+                           int64_t V3p, u32* __restrict__ BG3) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = eu[e], v = ev[e];
+    const int32_t cu = comp[u], cv = comp[v];
+    if (cu == cv) continue;
+    const int32_t su = grp[cu], sv = grp[cv];
+    const int32_t tu = su / gpt, tv = sv / gpt;
+    if (tu == tv) continue;
+    const int32_t xu = b2off[su] + b2rank[bgoff[cu] + local[u]];
+    const int32_t xv = b2off[sv] + b2rank[bgoff[cv] + local[v]];
+    if (!BG3) {
+      flag3[xu] = 1;
+      flag3[xv] = 1;
+      continue;
+    }
+    const int64_t a = b3off[tu] + b3rank[xu], b = b3off[tv] + b3rank[xv];
+    atomicMin(BG3 + a * V3p + b, (u32)w[e]);
+    atomicMin(BG3 + b * V3p + a, (u32)w[e]);
+  }
+}
+
+// d_BG2 tile for super-groups (T1, T2 = s2base + blockIdx.y), rows x of T1,
+// columns y of T2: min over b in B3(T2) of XT[T2][b][x] + R_T2[b][y], and d_T1
+// when T1 = T2; stored densely (row gbase[T1] + x, column gbase[T2] + y of
+// out, leading dimension ldo).
+__global__ __launch_bounds__(256) void k_mp_y_dense(int32_t s1, int32_t s2base, int32_t Vgp,
+                                                    int32_t m2pmax, const int32_t* __restrict__ m2,
+                                                    const int32_t* __restrict__ gV,
+                                                    const int32_t* __restrict__ gbase,
+                                                    const u32* __restrict__ XT, const u32* __restrict__ R,
+                                                    const u32* __restrict__ Mg, u32* __restrict__ out,
+                                                    int64_t ldo) {
+  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
+  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
+  const int32_t s2 = s2base + (int32_t)blockIdx.y;
+  const int ntx = Vgp / 128;
+  const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
+  const int32_t V1 = gV[s1], V2 = gV[s2];
+  if (ti * 128 >= V1 || tj * 128 >= V2) return;
+  u32 c[8][8];
+  if (s1 == s2)
+    tile_load<128>(c, Mg + (int64_t)s1 * Vgp * Vgp + (int64_t)ti * 128 * Vgp + tj * 128, Vgp);
+  else
+    fill_inf(c);
+  const int32_t kb = m2[s2];
+  const u32* At = XT + (int64_t)s2 * m2pmax * Vgp + ti * 128;
+  const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
+  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB);
+  const int tx = tid_x(), ty = tid_y();
+  const int64_t col0 = gbase[s2];
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int32_t x = ti * 128 + h * 64 + ty * 4 + a;
+      if (x >= V1) continue;
+      u32* row = out + ((int64_t)gbase[s1] + x) * ldo + col0;
+#pragma unroll
+      for (int h2 = 0; h2 < 2; h2++)
+#pragma unroll
+        for (int a2 = 0; a2 < 4; a2++) {
+          const int32_t y = tj * 128 + h2 * 64 + tx * 4 + a2;
+          if (y < V2) row[y] = c[h * 4 + a][h2 * 4 + a2];
+        }
+    }
+}
+
 // One BG row (BG id x) gathered from the two-level store, for inspection.
 __global__ void k_hier_row(int32_t x, int32_t swap, int32_t V, int32_t ngroups,
                            const int32_t* __restrict__ bggrp,
@@ -594,7 +704,7 @@ hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s) {
+hipError_t launch_hier_level2_prep(const HierArgs& a, hipStream_t s) {
   k_r_gather<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(a.Vgp, a.m2pmax, a.m2,
                                                                            a.b2list, a.Mg, a.R);
   if (a.V2p > 0) {
@@ -603,9 +713,16 @@ hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s) {
     if (a.m > 0)
       k_bg2_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
                                                a.b2off, a.b2rank, a.V2p, a.BG2);
-    hipError_t e = launch_dense_fw(a.BG2, a.V2p, 128, (int)(a.V2p / 128), s, nullptr, a.kc);
-    if (e != hipSuccess) return e;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_hier_level2_close(const HierArgs& a, hipStream_t s) {
+  if (a.V2p <= 0) return hipSuccess;
+  return launch_dense_fw(a.BG2, a.V2p, 128, (int)(a.V2p / 128), s, nullptr, a.kc);
+}
+
+hipError_t launch_hier_level2_compose(const HierArgs& a, hipStream_t s) {
   const int ntx = a.Vgp / 128, ntm = a.m2pmax / 128;
   for (int32_t s1 = 0; s1 < a.ngroups; s1++) {
     const unsigned pairs = (unsigned)(a.ngroups - s1);
@@ -623,6 +740,45 @@ hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s) {
       hipError_t e = hipEventRecord(a.evt[2 * s1 + 1], s);
       if (e != hipSuccess) return e;
     }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_level3_a(const L3Args& a, hipStream_t s) {
+  k_l3_gather<<<dim3((unsigned)a.V3gp, (unsigned)a.nT), 256, 0, s>>>(a.V2p, a.BG2, a.tbase, a.tsize,
+                                                                      a.V3gp, a.M3);
+  hipError_t e = launch_dense_fw_batch(a.M3, a.V3gp, 128, a.V3gp / 128, a.nT,
+                                       (int64_t)a.V3gp * a.V3gp, s, nullptr, a.kc);
+  if (e != hipSuccess) return e;
+  if (a.m > 0)
+    k_l3_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
+                                            a.gpt, a.b2off, a.b2rank, a.flag3, nullptr, nullptr, 0,
+                                            nullptr);
+  k_b2_scan<<<(unsigned)a.nT, 256, 0, s>>>(a.tbase, a.tsize, a.flag3, a.V3gp, a.b3list, a.b3rank, a.m3);
+  return hipGetLastError();
+}
+
+hipError_t launch_level3_b(const L3Args& a, hipStream_t s) {
+  k_r_gather<<<dim3((unsigned)a.m3pmax, (unsigned)a.nT), 256, 0, s>>>(a.V3gp, a.m3pmax, a.m3, a.b3list,
+                                                                       a.M3, a.R3);
+  if (a.V3p > 0) {
+    k_bg2_init<<<(unsigned)a.V3p, 256, 0, s>>>(a.V3, a.V3p, a.nT, a.b3off, a.b3list, a.V3gp, a.M3,
+                                               a.BG3);
+    if (a.m > 0)
+      k_l3_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
+                                              a.gpt, a.b2off, a.b2rank, nullptr, a.b3off, a.b3rank,
+                                              a.V3p, a.BG3);
+    hipError_t e = launch_dense_fw(a.BG3, a.V3p, 128, (int)(a.V3p / 128), s, nullptr, a.kc);
+    if (e != hipSuccess) return e;
+  }
+  const int ntx = a.V3gp / 128, ntm = a.m3pmax / 128;
+  for (int32_t t1 = 0; t1 < a.nT; t1++) {
+    const unsigned pairs = (unsigned)(a.nT - t1);
+    if (a.V3p > 0)
+      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(t1, t1, a.V3gp, a.m3pmax, a.m3, a.b3off,
+                                                                 a.BG3, a.V3p, a.R3, a.XT3);
+    k_mp_y_dense<<<dim3((unsigned)(ntx * ntx), pairs), 256, 0, s>>>(
+        t1, t1, a.V3gp, a.m3pmax, a.m3, a.tsize, a.tbase, a.XT3, a.R3, a.M3, a.BG2, a.V2p);
   }
   return hipGetLastError();
 }

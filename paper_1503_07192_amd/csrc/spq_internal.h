@@ -103,7 +103,31 @@ hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t 
                               u32* dirty_next, hipStream_t s);
 hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s);
 hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
-hipError_t launch_hier_level2(const HierArgs& a, hipStream_t s);
+// level 2 in three steps: R_S and the unclosed BG2 matrix; its closure by
+// flat Floyd-Warshall (or by level 3 below); the composition into H
+hipError_t launch_hier_level2_prep(const HierArgs& a, hipStream_t s);
+hipError_t launch_hier_level2_close(const HierArgs& a, hipStream_t s);
+hipError_t launch_hier_level2_compose(const HierArgs& a, hipStream_t s);
+
+// Level 3: the closure of BG2 by the same construction on super-groups of
+// gpt consecutive groups (hier.hip).
+struct L3Args {
+  int32_t nT, gpt, V3gp, V3, m3pmax, kc;
+  int64_t m, V2p, V3p;
+  const int32_t *eu, *ev, *w, *comp, *local, *bgoff, *grp;
+  const int32_t *b2off, *b2rank;       // level-2 ids
+  u32* BG2;                            // V2p x V2p, unclosed in, closed (upper block triangle) out
+  const int32_t *tbase, *tsize;        // [nT]: first BG2 id, BG2 vertices of each super-group
+  u32* M3;                             // nT x V3gp x V3gp
+  uint8_t* flag3;                      // [V2]
+  int32_t *b3list, *b3rank, *m3;       // nT x V3gp, [V2], [nT]
+  const int32_t* b3off;                // [nT+1]
+  u32 *R3, *XT3, *BG3;                 // nT x m3pmax x V3gp (twice), V3p x V3p
+};
+// super-group matrices, their closure, the level-3 boundary (m3)
+hipError_t launch_level3_a(const L3Args& a, hipStream_t s);
+// BG3 and its closure, then d_BG2 for super-group pairs T1 <= T2 into BG2
+hipError_t launch_level3_b(const L3Args& a, hipStream_t s);
 hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s);
 
 // Exactness certificate (range.hip).

@@ -37,7 +37,8 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("bg_tile", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("plain", ctypes.c_int32), ("bg_method", ctypes.c_int32),
                 ("group_comps", ctypes.c_int32), ("share_comps", ctypes.c_int32),
-                ("inner_kc", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("inner_kc", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("level3_groups", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -55,7 +56,8 @@ class Stats(ctypes.Structure):
                 ("ms_partition", ctypes.c_float), ("ms_components", ctypes.c_float),
                 ("ms_bg_assembly", ctypes.c_float), ("ms_bg_apsp", ctypes.c_float),
                 ("graphs", ctypes.c_int32), ("reweights", ctypes.c_int32),
-                ("graph_nodes", ctypes.c_int64)]
+                ("graph_nodes", ctypes.c_int64), ("groups3", ctypes.c_int32),
+                ("v_bg3", ctypes.c_int32)]
 
 
 _lib = None
@@ -159,7 +161,7 @@ class Index:
 
 def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg_method=0,
                 group_comps=0, share_comps=0, inner_kc=0, lookahead=True, graph=False,
-                tune_cache=None, stream=None) -> Index:
+                level3_groups=0, tune_cache=None, stream=None) -> Index:
     """Algorithm 1 on device tensors; see spq_build_index.
 
     graph: capture Phases 2-3 as HIP graphs kept for reweight().
@@ -174,10 +176,12 @@ def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg
         inner_kc = inner_kc or tuned.get("inner_kc", 0)
         bg_method = bg_method or tuned.get("bg_method", 0)
         group_comps = group_comps or tuned.get("group_comps", 0)
+        level3_groups = level3_groups or tuned.get("level3_groups", 0)
     opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)), plain=int(bool(plain)),
                      bg_method=int(bg_method), group_comps=int(group_comps),
                      share_comps=int(share_comps), inner_kc=int(inner_kc),
-                     flags=(0 if lookahead else SPQ_NO_LOOKAHEAD) | (SPQ_GRAPH if graph else 0))
+                     flags=(0 if lookahead else SPQ_NO_LOOKAHEAD) | (SPQ_GRAPH if graph else 0),
+                     level3_groups=int(level3_groups))
     h = ctypes.c_void_p()
     m = int(eu.numel())
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),

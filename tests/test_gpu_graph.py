@@ -60,6 +60,8 @@ GRAPH_CASES = [
     ("grid32_flat_tile64_plain", lambda: W.grid32(), {"bg_tile": 64, "plain": True}),
     ("grid32_two_level", lambda: W.grid32(), {"bg_method": 2, "group_comps": 4}),
     ("grid30_two_level_ragged", lambda: grid_case(3, 30, 27, 5), {"bg_method": 2, "group_comps": 3}),
+    ("grid30_level3", lambda: grid_case(3, 30, 27, 5),
+     {"bg_method": 2, "group_comps": 2, "level3_groups": 3}),
     ("bigcomp_flat", bigcomp_case, {}),
     ("bigcomp_two_level", bigcomp_case, {"bg_method": 2, "group_comps": 2}),
 ]
@@ -71,7 +73,7 @@ def test_graph_build_equals_eager(name, make, kw):
     eager = build(g, **kw)
     cap = build(g, graph=True, **kw)
     st = spq.index_stats(cap)
-    assert st["graphs"] == (2 if st["bg_method"] == 2 else 1)
+    assert st["graphs"] == (1 if st["bg_method"] == 1 else 3 if st["groups3"] else 2)
     assert st["graph_nodes"] > 0 and st["reweights"] == 0
     assert spq.index_stats(eager)["graphs"] == 0
     pairs = None
@@ -91,7 +93,9 @@ def reweighted(g, seed, lo, hi):
     return h
 
 
-@pytest.mark.parametrize("kw", [{}, {"bg_method": 2, "group_comps": 3}], ids=["flat", "two_level"])
+@pytest.mark.parametrize("kw", [{}, {"bg_method": 2, "group_comps": 3},
+                                {"bg_method": 2, "group_comps": 1, "level3_groups": 4}],
+                         ids=["flat", "two_level", "level3"])
 def test_reweight_replays_match_fresh_builds(kw):
     g = grid_case(11, 24, 26, 6)
     idx = build(g, graph=True, **kw)

@@ -383,6 +383,41 @@ def test_grid32_two_level_equals_flat(gc):
     assert np.array_equal(run_queries(flat, v1, v2), run_queries(two, v1, v2))
 
 
+@pytest.mark.parametrize("l3", [1, 2, 3, 5, 16])
+def test_grid32_level3_equals_flat(l3):
+    # 16 groups of one component; BG2 closed by super-groups of l3 groups
+    # (16: a single super-group, so no level-3 boundary at all)
+    g = W.grid32()
+    flat = build(g, bg_method=1)
+    three = build(g, bg_method=2, group_comps=1, level3_groups=l3)
+    st = spq.index_stats(three)
+    assert st["groups3"] == -(-16 // l3)
+    if l3 == 16:
+        assert st["v_bg3"] == 0
+    elif l3 == 1:   # super-groups of one group: every level-2 vertex is one of level 3
+        assert st["v_bg3"] == st["v_bg2"]
+    else:
+        assert 0 < st["v_bg3"] < st["v_bg2"]
+    assert np.array_equal(spq.index_bg_rows(flat, 0, 348, 348), spq.index_bg_rows(three, 0, 348, 348))
+    v1, v2 = all_pairs(g["n"])
+    assert np.array_equal(run_queries(flat, v1, v2), run_queries(three, v1, v2))
+
+
+LEVEL3 = [c for c in CASES if c["k"] >= 3]
+
+
+@pytest.mark.parametrize("g", LEVEL3, ids=[c["name"] for c in LEVEL3])
+def test_level3_small_graphs_all_pairs(g):
+    for gc, l3 in ((1, 1), (1, 2), (2, 1)):
+        idx = build(g, bg_method=2, group_comps=gc, level3_groups=l3)
+        st = spq.index_stats(idx)
+        assert st["groups3"] == (-(-st["ngroups"] // l3) if st["v_bg2"] else 0)
+        lay = spq.index_layout(idx)
+        check_bg_rows(g, idx, lay, np.arange(st["v_bg"]))
+        v1, v2 = all_pairs(g["n"])
+        check_queries(g, idx, v1, v2)
+
+
 def test_grid256d_two_level_equals_flat():
     g = W.grid256d()
     flat = build(g, bg_method=1)
@@ -396,6 +431,15 @@ def test_grid256d_two_level_equals_flat():
     for r, want in zip(rows, rf):
         assert np.array_equal(spq.index_bg_rows(plain, int(r), 1, 27_900), want)
     plain.free()
+    # 256 groups of 4 components, BG2 closed by 16 super-groups (level 3)
+    three = build(g, bg_method=2, group_comps=4, level3_groups=16)
+    st = spq.index_stats(three)
+    print({k: st[k] for k in ("ngroups", "v_bg2", "groups3", "v_bg3")}, flush=True)
+    assert st["ngroups"] == 256 and st["groups3"] == 16 and 0 < st["v_bg3"] < st["v_bg2"]
+    assert np.array_equal(run_queries(three, g["v1"], g["v2"]), qf)
+    for r, want in zip(rows, rf):
+        assert np.array_equal(spq.index_bg_rows(three, int(r), 1, 27_900), want)
+    three.free()
     two = build(g, bg_method=2, group_comps=32)
     st = spq.index_stats(two)
     assert st["ngroups"] == 32 and st["v_bg2"] > 0
@@ -462,9 +506,11 @@ def test_delaunay1m_two_level():
     print("delaunay1m: n=%d m=%d k=%d" % (g["n"], g["m"], g["k"]), flush=True)
     idx = build(g)
     st = spq.index_stats(idx)
-    print({k: st[k] for k in ("v_bg", "bg_method", "ngroups", "v_bg2", "max_comp", "max_boundary",
-                              "bg_bytes", "ms_components", "ms_bg_apsp")}, flush=True)
+    print({k: st[k] for k in ("v_bg", "bg_method", "ngroups", "v_bg2", "groups3", "v_bg3",
+                              "max_comp", "max_boundary", "bg_bytes", "ms_components",
+                              "ms_bg_apsp")}, flush=True)
     assert st["bg_method"] == 2 and st["ngroups"] == 64
+    assert st["groups3"] > 1 and 0 < st["v_bg3"] < st["v_bg2"]   # BG2 closed by level 3
     lay = spq.index_layout(idx)
     flag = oracle.boundary(g["n"], g["eu"], g["ev"], g["part"])
     assert st["v_bg"] == int(flag.sum())
