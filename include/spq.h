@@ -90,11 +90,14 @@ typedef struct {
   int32_t n, k;            /* vertices, components */
   int64_t m;               /* edges as given */
   int32_t v_bg;            /* boundary vertices = BG vertices */
-  int32_t v_bg_padded;     /* BG matrix side after padding to the tile */
+  int32_t v_bg_padded;     /* side of the padded Floyd-Warshall matrix: all of BG
+                              (flat) or one group (two-level) */
   int32_t max_comp;        /* largest component */
   int32_t max_boundary;    /* largest |B(C)| */
   int64_t comp_bytes;      /* bytes of all APSP(C) tables (padded) */
-  int64_t bg_bytes;        /* bytes of the BG distance matrix (padded) */
+  int64_t bg_bytes;        /* bytes of the blocked BG distance store the queries
+                              read (flat: V_BG^2 * 4; the Floyd-Warshall matrix
+                              is kept beside it) */
   double relax_comp;       /* sum over C of |C|^3: Floyd-Warshall relaxations, Phase 2 */
   double relax_bg;         /* v_bg^3: Floyd-Warshall relaxations in BG, Phase 3 */
   double relax_comp_exec;  /* relaxations the kernels execute for Phase 2 (padded
@@ -145,7 +148,8 @@ typedef struct {
  * (flat) or by the two-level method: BG split into groups of consecutive
  * components, each group closed, the graph of the group boundaries closed,
  * and the remaining distances composed as in Algorithm 2 one level up.  Both
- * give the same distances.
+ * give the same distances.  The distances are then kept in a blocked store
+ * where each B(C1) x B(C2) block is one contiguous run (what a query reads).
  * Errors: SPQ_EINVAL (bad id, weight or part, empty component, k < 1),
  * SPQ_ERANGE (the total edge weight reaches SPQ_INF, so a distance might not
  * fit), SPQ_ENOMEM, SPQ_EDEVICE.

@@ -227,7 +227,7 @@ void oracle_query_alg2(int64_t q, const int32_t* v1, const int32_t* v2,
     int32_t n1 = csize[C1], n2 = csize[C2];
     int32_t nb2 = bstart[C2 + 1] - bstart[C2];
     if (nb2 > tcap) { free(t); tcap = nb2; t = (int64_t*)malloc(sizeof(int64_t) * (size_t)tcap); }
-    /* lines 2-7: dist(v1, b2) through the best b1 */
+    /* first stage: dist(v1, b2) through the best b1 */
     for (int32_t j = 0; j < nb2; j++) {
       int32_t g2 = bstart[C2] + j;
       t[j] = O_INF;
@@ -237,15 +237,15 @@ void oracle_query_alg2(int64_t q, const int32_t* v1, const int32_t* v2,
         if (c < t[j]) t[j] = c;
       }
     }
-    /* line 8 moves a column between nodes; nothing to do in one memory */
-    /* lines 9-12: the best b2 */
+    /* the paper moves a column of APSP(C2) between nodes here; one memory needs nothing */
+    /* second stage: the best b2 */
     int64_t r = O_INF;
     for (int32_t j = 0; j < nb2; j++) {
       int64_t d2 = A2[(int64_t)blocal[bstart[C2] + j] * n2 + p2]; /* dist_C2(b2, v2) */
       int64_t c = sat_add(t[j], d2);
       if (c < r) r = c;
     }
-    /* line 13 */
+    /* same component: the path may stay inside C1 */
     if (C1 == C2) {
       int64_t d = A1[(int64_t)p1 * n1 + p2];
       if (d < r) r = d;

@@ -838,6 +838,15 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     X->prof.resize(2 * X->inner_launches);
     for (auto& e : X->prof) TRY(hipEventCreate(&e));
   }
+  // the blocked store the queries read (one group: the whole V x V matrix)
+  const int32_t V = X->V;
+  TRY(dalloc(&X->bgrow, V));
+  TRY(dalloc(&X->bgnb, V));
+  TRY(dalloc(&X->bggrp, V));
+  X->h_elems = (int64_t)V * V;
+  TRY(dalloc(&X->H, X->h_elems));
+  TRY(dalloc(&X->pairbase, 1));
+  TRY(hipMemsetAsync(X->pairbase, 0, sizeof(int64_t), s));
   const bool la = lookahead && X->Vp / tile > 1;
   if (la) {
     TRY(hipStreamCreateWithFlags(&X->side, hipStreamNonBlocking));  // default priority
@@ -850,9 +859,13 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     if (e == hipSuccess && !X->graph) e = hipEventRecord(X->ev[3], st);
     if (e != hipSuccess) return e;
     if (la)
-      return spq::launch_dense_fw_lookahead(X->BG, X->Vp, tile, X->Vp / tile, st, X->side,
-                                            X->la_sync, pev, inner_kc);
-    return spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, st, pev, inner_kc);
+      e = spq::launch_dense_fw_lookahead(X->BG, X->Vp, tile, X->Vp / tile, st, X->side, X->la_sync,
+                                         pev, inner_kc);
+    else
+      e = spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, st, pev, inner_kc);
+    if (e != hipSuccess) return e;
+    return spq::launch_flat_store(V, X->Vp, X->BG, X->bgcomp, X->bgoff, X->nb, X->grp, X->gbg0,
+                                  X->bgrow, X->bgnb, X->bggrp, X->bglocal, X->H, st);
   }));
   TRY(hipEventRecord(X->ev[4], s));
 #undef TRY
@@ -933,9 +946,9 @@ spq_status spq_query_batch(const spq_index* X, int64_t q, const int32_t* v1, con
   if (!v1 || !v2 || !out) return fail(SPQ_EINVAL, "null query array");
   spq::QueryArgs a{};
   a.q = q; a.v1 = v1; a.v2 = v2; a.out = out; a.n = X->n;
-  a.vrec = X->vrec; a.M = X->M; a.BG = X->BG; a.ldbg = X->Vp;
-  a.H = X->method == 2 ? X->H : nullptr; a.pairbase = X->pairbase; a.gV = X->gV;
-  a.ngroups = X->ngroups; a.share_comps = X->share_comps;
+  a.vrec = X->vrec; a.M = X->M;
+  a.H = X->H; a.pairbase = X->pairbase; a.gV = X->gV;
+  a.ngroups = X->ngroups; a.V = X->V; a.share_comps = X->share_comps;
   HIP_TRY(spq::launch_query(a, reinterpret_cast<hipStream_t>(stream)));
   return SPQ_OK;
 }
@@ -946,7 +959,7 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   st->n = X->n; st->k = X->k; st->m = X->m; st->v_bg = X->V; st->v_bg_padded = X->Vp;
   st->max_comp = X->max_comp; st->max_boundary = X->max_nb;
   st->comp_bytes = X->comp_elems * 4;
-  st->bg_bytes = (int64_t)X->Vp * X->Vp * 4;
+  st->bg_bytes = (int64_t)X->h_elems * 4;
   st->relax_comp = X->relax_comp;
   st->relax_bg = X->relax_bg;
   st->relax_comp_exec = X->relax_comp_exec;
@@ -964,10 +977,7 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   st->graph_nodes = X->graph_nodes;
   st->groups3 = X->nT;
   st->v_bg3 = X->V3;
-  if (X->method == 2) {
-    st->v_bg_padded = X->Vgp;
-    st->bg_bytes = (int64_t)X->h_elems * 4;
-  }
+  if (X->method == 2) st->v_bg_padded = X->Vgp;
   HIP_TRY(hipEventSynchronize(X->ev[4]));
   for (size_t i = 0; i + 1 < X->prof.size(); i += 2) {
     float ms = 0;
@@ -1009,29 +1019,24 @@ spq_status spq_index_bg_rows(const spq_index* X, int32_t row0, int32_t nrows, in
     return fail(SPQ_EINVAL, "BG rows out of range");
   if (nrows == 0) return SPQ_OK;
   HIP_TRY(hipEventSynchronize(X->ev[4]));
-  if (X->method == 2) {
-    if (X->share_comps > 0 &&
-        (int64_t)row0 + nrows > X->h_gbg0[X->share_groups - 1] + X->h_gV[X->share_groups - 1])
-      return fail(SPQ_EINVAL, "BG rows outside the share");
-    u32* tmp = nullptr;
-    HIP_TRY(dalloc(&tmp, X->V));
-    spq::HierArgs ha{};
-    ha.share_groups = X->share_groups;
-    ha.V = X->V; ha.ngroups = X->ngroups; ha.bggrp = X->bggrp; ha.bgrow = X->bgrow; ha.bgnb = X->bgnb;
-    ha.bglocal = X->bglocal; ha.gV = X->gV; ha.pairbase = X->pairbase; ha.H = X->H;
-    hipError_t e = hipSuccess;
-    for (int32_t r = 0; r < nrows && e == hipSuccess; r++) {
-      e = spq::launch_hier_row(ha, row0 + r, tmp, nullptr);
-      if (e == hipSuccess)
-        e = hipMemcpy(out + (int64_t)r * X->V, tmp, sizeof(int32_t) * X->V, hipMemcpyDeviceToHost);
-    }
-    pool_release(tmp);
-    HIP_TRY(e);
-    return SPQ_OK;
+  // rows are gathered from the blocked store the queries read
+  if (X->share_comps > 0 &&
+      (int64_t)row0 + nrows > X->h_gbg0[X->share_groups - 1] + X->h_gV[X->share_groups - 1])
+    return fail(SPQ_EINVAL, "BG rows outside the share");
+  u32* tmp = nullptr;
+  HIP_TRY(dalloc(&tmp, X->V));
+  spq::HierArgs ha{};
+  ha.share_groups = X->share_groups;
+  ha.V = X->V; ha.ngroups = X->ngroups; ha.bggrp = X->bggrp; ha.bgrow = X->bgrow; ha.bgnb = X->bgnb;
+  ha.bglocal = X->bglocal; ha.gV = X->gV; ha.pairbase = X->pairbase; ha.H = X->H;
+  hipError_t e = hipSuccess;
+  for (int32_t r = 0; r < nrows && e == hipSuccess; r++) {
+    e = spq::launch_hier_row(ha, row0 + r, tmp, nullptr);
+    if (e == hipSuccess)
+      e = hipMemcpy(out + (int64_t)r * X->V, tmp, sizeof(int32_t) * X->V, hipMemcpyDeviceToHost);
   }
-  HIP_TRY(hipMemcpy2D(out, sizeof(int32_t) * X->V, X->BG + (int64_t)row0 * X->Vp,
-                      sizeof(int32_t) * X->Vp, sizeof(int32_t) * X->V, nrows,
-                      hipMemcpyDeviceToHost));
+  pool_release(tmp);
+  HIP_TRY(e);
   return SPQ_OK;
 }
 

@@ -209,6 +209,18 @@ __global__ void k_hier_vmeta(int32_t V, const int32_t* __restrict__ bgcomp, cons
   bggrp[x] = s;
 }
 
+// Flat method: row x of the closed BG matrix into the blocked store of one
+// group (the layout above with S1 = S2 = the only group).
+__global__ void k_flat_store(int32_t V, int64_t Vp, const u32* __restrict__ BG,
+                             const int32_t* __restrict__ bgrow, const int32_t* __restrict__ bgnb,
+                             const int32_t* __restrict__ bglocal, u32* __restrict__ H) {
+  const int64_t x = blockIdx.x;
+  const u32* row = BG + x * Vp;
+  const int64_t rb = (int64_t)bgrow[x] * V, nbx = bgnb[x], locx = bglocal[x];
+  for (int32_t y = threadIdx.x; y < V; y += blockDim.x)
+    H[rb + nbx * bgrow[y] + locx * bgnb[y] + bglocal[y]] = row[y];
+}
+
 // ------------------------------------------------------- min-plus products --
 // c (128 x 128 in registers) = min(c, min over k < K of At[k][i] + B[k][j]).
 // Rows k of At and B are ldA / ldB apart; K is a multiple of 16 and is
@@ -741,6 +753,16 @@ hipError_t launch_hier_level2_compose(const HierArgs& a, hipStream_t s) {
       if (e != hipSuccess) return e;
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_flat_store(int32_t V, int64_t Vp, const u32* BG, const int32_t* bgcomp,
+                             const int32_t* bgoff, const int32_t* nb, const int32_t* grp,
+                             const int32_t* gbg0, int32_t* bgrow, int32_t* bgnb, int32_t* bggrp,
+                             const int32_t* bglocal, u32* H, hipStream_t s) {
+  if (V <= 0) return hipSuccess;
+  k_hier_vmeta<<<hblocks(V), 256, 0, s>>>(V, bgcomp, bgoff, nb, grp, gbg0, bgrow, bgnb, bggrp);
+  k_flat_store<<<(unsigned)V, 256, 0, s>>>(V, Vp, BG, bgrow, bgnb, bglocal, H);
   return hipGetLastError();
 }
 

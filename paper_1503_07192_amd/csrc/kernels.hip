@@ -435,85 +435,98 @@ __global__ void k_vrec(int32_t n, const int32_t* __restrict__ comp, const int32_
   vrec[2 * v + 1] = make_uint4((u32)bgoff[c], (u32)nb[c], (u32)s, (u32)(bgoff[c] - gbg0[s]));
 }
 
-// Algorithm 2, one wavefront per query:
-//   t(b2) = min over b1 of dist_C1(v1, b1) + dist_BG(b1, b2)     (lines 2-7)
-//   r     = min over b2 of t(b2) + dist_C2(b2, v2)                (lines 9-12)
-//   r     = min(r, dist_C1(v1, v2)) if C1 = C2                    (line 13)
-// dist_C1(v1, .) is the prefix of v1's row of APSP(C1) (boundary first), held
-// one value per lane and broadcast with ds_bpermute; dist_C2(b2, v2) is read
-// from v2's row (the matrix is symmetric); each row of the BG block is
-// contiguous.  When |B(C2)| <= 32 the wave splits into two half-waves that
-// take even and odd b1, so both halves stream BG rows.  Each lane keeps 8
-// row loads in flight.
-__global__ __launch_bounds__(256) void k_query(int64_t q, const int32_t* __restrict__ v1,
-                                               const int32_t* __restrict__ v2, int32_t* __restrict__ out,
-                                               int32_t n, const uint4* __restrict__ vrec,
-                                               const u32* __restrict__ M, const u32* __restrict__ BG,
-                                               int64_t ldbg, const u32* __restrict__ H,
-                                               const int64_t* __restrict__ pairbase,
-                                               const int32_t* __restrict__ gV, int32_t ngroups,
-                                               int32_t share_comps) {
-  const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (qi >= q) return;
+// Algorithm 2, one query per half-wave (32 lanes, 8 queries per workgroup):
+//   t(b2) = min over b1 of dist_C1(v1, b1) + dist_BG(b1, b2)     (first stage)
+//   r     = min over b2 of t(b2) + dist_C2(b2, v2)                (second stage)
+//   r     = min(r, dist_C1(v1, v2)) if C1 = C2                    (same component)
+// The B(C1) x B(C2) block of BG distances is read row by row in uint4
+// pieces: L = ceil(columns / 4) lanes per row, R = 32 / L rows per load, and
+// QU loads in flight per lane, each with its dist_C1(v1, b1) (the prefix of
+// v1's row of APSP(C1), boundary first).  A lane keeps the first-stage
+// minimum of its four columns over its rows and adds dist_C2(b2, v2) (v2's
+// row, the matrix being symmetric); the half-wave then takes the minimum.
+// The blocked BG store keeps each B(C1) x B(C2) block as one contiguous run
+// (rows |B(C2)| apart).  Block columns come in chunks of 128 when
+// |B(C2)| > 128.
+#ifndef SPQ_QUERY_UNROLL
+#define SPQ_QUERY_UNROLL 6
+#endif
+
+__device__ __forceinline__ uint4 load4_upto(const u32* p, int valid) {
+  if (valid >= 4) return *reinterpret_cast<const uint4*>(p);
+  return make_uint4(valid > 0 ? p[0] : INF, valid > 1 ? p[1] : INF, valid > 2 ? p[2] : INF, INF);
+}
+
+// 64 VGPRs: eight waves per SIMD keep enough block loads in flight
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_query(
+    int64_t q, const int32_t* __restrict__ v1, const int32_t* __restrict__ v2,
+    int32_t* __restrict__ out, int32_t n, const uint4* __restrict__ vrec, const u32* __restrict__ M,
+    const u32* __restrict__ H, const int64_t* __restrict__ pairbase, const int32_t* __restrict__ gV,
+    int32_t ngroups, int32_t V, int32_t share_comps) {
+  constexpr int QU = SPQ_QUERY_UNROLL;
+  const int64_t qi = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int l = threadIdx.x & 31;
+  if (qi >= q) return;  // whole half-waves only
   const int32_t a = v1[qi], b = v2[qi];
   if (a < 0 || a >= n || b < 0 || b >= n) {
-    if (lane == 0) out[qi] = -1;
+    if (l == 0) out[qi] = -1;
     return;
   }
   uint4 ra = vrec[2 * (int64_t)a], ra2 = vrec[2 * (int64_t)a + 1];
   uint4 rb = vrec[2 * (int64_t)b], rb2 = vrec[2 * (int64_t)b + 1];
   if (share_comps > 0 && (int32_t)ra.z >= share_comps) {  // v1 outside the share
-    if (lane == 0) out[qi] = -1;
+    if (l == 0) out[qi] = -1;
     return;
   }
-  const u32* blk;
-  if (H) {
-    // the full two-level store keeps group pairs S1 <= S2 only; dist is
-    // symmetric, so swap the endpoints when needed (a share keeps all S2)
-    if (share_comps == 0 && ra2.z > rb2.z) {
-      const uint4 t = ra, t2 = ra2;
-      ra = rb; ra2 = rb2; rb = t; rb2 = t2;
-    }
-    blk = H + pairbase[(int64_t)ra2.z * ngroups + rb2.z] + (int64_t)ra2.w * gV[rb2.z] +
-          (int64_t)ra2.y * rb2.w;
-    ldbg = rb2.y;
-  } else {
-    blk = BG + (int64_t)ra2.x * ldbg + rb2.x;
+  // the full two-level store keeps group pairs S1 <= S2 only; dist is
+  // symmetric, so swap the endpoints when needed (a share keeps all S2)
+  if (share_comps == 0 && ra2.z > rb2.z) {
+    const uint4 t = ra, t2 = ra2;
+    ra = rb; ra2 = rb2; rb = t; rb2 = t2;
   }
+  // one group (flat method): no table lookups on the critical path
+  const int64_t pb = ngroups == 1 ? 0 : pairbase[(int64_t)ra2.z * ngroups + rb2.z];
+  const int32_t vs2 = ngroups == 1 ? V : gV[rb2.z];
+  const u32* blk = H + pb + (int64_t)ra2.w * vs2 + (int64_t)ra2.y * rb2.w;
+  const int64_t ld = rb2.y;
   const u32* row1 = M + ((uint64_t)ra.x | ((uint64_t)ra.y << 32));
   const u32* row2 = M + ((uint64_t)rb.x | ((uint64_t)rb.y << 32));
   const int32_t nb1 = (int32_t)ra2.y, nb2 = (int32_t)rb2.y;
-  const int W = nb2 <= 32 ? 32 : 64;  // lanes per group
-  const int G = 64 / W;               // groups, each takes b1 = g (mod G)
-  const int g = lane / W, jj = lane % W;
   u32 best = INF;
-  for (int32_t b2base = 0; b2base < nb2; b2base += W) {
-    const int32_t b2 = b2base + jj;
-    const bool act = b2 < nb2;
-    const u32* col = blk + (act ? b2 : 0);
-    u32 t = INF;
-    for (int32_t b1base = 0; b1base < nb1; b1base += 64) {
-      const int32_t cnt = min(64, nb1 - b1base);
-      const u32 r1 = (lane < cnt) ? row1[b1base + lane] : INF;
-      const u32* cb = col + (int64_t)b1base * ldbg;
-      for (int32_t x0 = 0; x0 < cnt; x0 += 8 * G) {  // uniform over the wave
-        u32 d[8], xv[8];
+  for (int32_t c0 = 0; c0 < nb2; c0 += 128) {
+    const int32_t nbc = min(128, nb2 - c0);
+    const int L = (nbc + 3) >> 2, R = 32 / L;
+    const int r = l / L, col = c0 + (l - r * L) * 4;
+    const bool lane_on = r < R;
+    const int cvalid = c0 + nbc - col;  // columns of this lane's piece (>= 1 when on)
+    // second-stage terms first: independent of the block
+    u32 e[4];
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
-          const int idx = x0 + g + u * G;
-          xv[u] = (act && idx < cnt) ? cb[(int64_t)idx * ldbg] : INF;
-          d[u] = (u32)__shfl((int)r1, idx & 63);
-        }
+    for (int j = 0; j < 4; j++) e[j] = (lane_on && j < cvalid) ? row2[col + j] : INF;
+    u32 t[4] = {INF, INF, INF, INF};
+    for (int32_t r0 = 0; r0 < nb1; r0 += R * QU) {
+      uint4 v[QU];
+      u32 d[QU];
 #pragma unroll
-        for (int u = 0; u < 8; u++) t = min(t, d[u] + xv[u]);
+      for (int u = 0; u < QU; u++) {
+        const int32_t row = r0 + u * R + r;
+        const bool on = lane_on && row < nb1;
+        v[u] = on ? load4_upto(blk + (int64_t)row * ld + col, cvalid) : make_uint4(INF, INF, INF, INF);
+        d[u] = on ? row1[row] : INF;
+      }
+#pragma unroll
+      for (int u = 0; u < QU; u++) {
+        t[0] = min(t[0], d[u] + v[u].x);
+        t[1] = min(t[1], d[u] + v[u].y);
+        t[2] = min(t[2], d[u] + v[u].z);
+        t[3] = min(t[3], d[u] + v[u].w);
       }
     }
-    if (G == 2) t = min(t, (u32)__shfl_xor((int)t, 32));
-    if (act) best = min(best, min(t, INF) + row2[b2]);
+#pragma unroll
+    for (int j = 0; j < 4; j++) best = min(best, min(t[j], INF) + e[j]);
   }
-  for (int o = 32; o > 0; o >>= 1) best = min(best, (u32)__shfl_xor((int)best, o));
-  if (lane == 0) {
+  for (int o = 16; o > 0; o >>= 1) best = min(best, (u32)__shfl_xor((int)best, o));
+  if (l == 0) {
     if (ra.z == rb.z) best = min(best, row1[rb.w]);
     out[qi] = (int32_t)min(best, INF);
   }
@@ -691,9 +704,9 @@ double dense_fw_exec_relax(int64_t nt, int tile) {
 
 hipError_t launch_query(const QueryArgs& a, hipStream_t s) {
   if (a.q <= 0) return hipSuccess;
-  int64_t blocks = (a.q + 3) / 4;
-  k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.vrec, a.M, a.BG, a.ldbg,
-                                           a.H, a.pairbase, a.gV, a.ngroups, a.share_comps);
+  int64_t blocks = (a.q + 7) / 8;
+  k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.vrec, a.M, a.H,
+                                           a.pairbase, a.gV, a.ngroups, a.V, a.share_comps);
   LAUNCH_CHECK();
 }
 

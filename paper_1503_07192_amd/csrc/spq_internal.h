@@ -62,13 +62,13 @@ struct QueryArgs {
   int32_t* out;
   int32_t n;
   const uint4* vrec;
-  const u32 *M, *BG;
-  int64_t ldbg;
-  // two-level store (H != nullptr): pair offsets and group sizes
+  const u32* M;
+  // blocked BG store (both methods): pair offsets and group sizes; with one
+  // group (the flat method) pairbase[0] = 0 and gV[0] = V
   const u32* H;
   const int64_t* pairbase;
   const int32_t* gV;
-  int32_t ngroups;
+  int32_t ngroups, V;
   int32_t share_comps;  // > 0: only sources v1 in components [0, share_comps)
 };
 
@@ -103,6 +103,12 @@ hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t 
                               u32* dirty_next, hipStream_t s);
 hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s);
 hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
+// Flat method: per-BG-vertex layout terms, then the closed BG matrix (Vp x Vp)
+// copied into the blocked store of a single group.
+hipError_t launch_flat_store(int32_t V, int64_t Vp, const u32* BG, const int32_t* bgcomp,
+                             const int32_t* bgoff, const int32_t* nb, const int32_t* grp,
+                             const int32_t* gbg0, int32_t* bgrow, int32_t* bgnb, int32_t* bggrp,
+                             const int32_t* bglocal, u32* H, hipStream_t s);
 // level 2 in three steps: R_S and the unclosed BG2 matrix; its closure by
 // flat Floyd-Warshall (or by level 3 below); the composition into H
 hipError_t launch_hier_level2_prep(const HierArgs& a, hipStream_t s);

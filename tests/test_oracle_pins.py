@@ -198,7 +198,7 @@ def test_hand_example_tables_and_queries():
 
 # ----------------------------------------------------- special cases
 def test_k1_reduces_to_floyd_warshall():
-    """k = 1: no boundary, the query is line 13 alone = FW on G."""
+    """k = 1: no boundary, the query is its same-component term alone = FW on G."""
     rng = np.random.default_rng(2)
     eu, ev, w = W.random_grid(rng, 6, 7, keep=0.8, diag=0.2)
     n = 42
@@ -279,7 +279,7 @@ def test_planted_missing_line13_is_caught():
         for a, b, f in zip(v1, v2, full):
             same = any(a in m and b in m for m in T.members)
             if same:
-                # recompute lines 2-12 only
+                # recompute the two min stages only
                 c = [i for i, m in enumerate(T.members) if a in m][0]
                 m, A = T.members[c], T.apsp[c]
                 bl = np.searchsorted(m, T.bverts[c])
