@@ -74,20 +74,26 @@ def recorded_traffic():
             rec[k] = v.strip()
     csrc = os.path.join(ROOT, "paper_1503_07192_amd", "csrc")
     src = open(os.path.join(csrc, "tiles.h"), "rb").read() + \
-        open(os.path.join(csrc, "kernels.hip"), "rb").read()
+        open(os.path.join(csrc, "fw.hip"), "rb").read()
     if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return float(rec["traffic_bytes_per_round"])
 
 
+TUNE_CACHE = os.path.join(ROOT, "paper_1503_07192_amd", "tune_cache.json")
+
+
 def make_workload(name, queries):
+    """The graph and its build options.  grid256d closes BG by flat
+    Floyd-Warshall (the workload's definition; the two-level method is timed
+    beside it); the others take the autotuner's choice for this device."""
     from paper_1503_07192_amd import workloads as W
     if name == "grid256d":
         return W.grid256d(queries=queries), {}
     if name == "delaunay1m":
-        return W.delaunay1m(queries=queries), {}
+        return W.delaunay1m(queries=queries), {"tune_cache": TUNE_CACHE}
     g = W.grid2048(queries=queries)
-    return g, {"share_comps": g["share_k"]}
+    return g, {"share_comps": g["share_k"], "tune_cache": TUNE_CACHE}
 
 
 def cpu_baseline(g, st, budget_s):
@@ -142,6 +148,11 @@ def main():
     wl = WORKLOADS[args.workload]
     nq = args.queries or wl["queries"]
     g, build_kw = make_workload(args.workload, nq)
+    tuned = None
+    if build_kw.get("tune_cache"):
+        from paper_1503_07192_amd import autotune
+        tuned = autotune.lookup(build_kw["tune_cache"], g["n"], g["m"], g["k"],
+                                build_kw.get("share_comps", 0))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
     eu, ev, w, part = dev(g["eu"]), dev(g["ev"]), dev(g["w"]), dev(g["part"])
     v1, v2 = dev(g["v1"]), dev(g["v2"])
@@ -274,7 +285,8 @@ def main():
                    "bg_method": "flat" if st["bg_method"] == 1 else "two-level",
                    "groups": st["ngroups"], "v_bg2": st["v_bg2"],
                    "groups3": st["groups3"], "v_bg3": st["v_bg3"],
-                   "share_comps": st["share_comps"], "bg_bytes": st["bg_bytes"]},
+                   "share_comps": st["share_comps"], "bg_bytes": st["bg_bytes"],
+                   "tuned_options": tuned},
         "phase_ms": {key: float(np.median([r[key] for r in recs]))
                      for key in ("ms_partition", "ms_components", "ms_bg_assembly",
                                  "ms_bg_apsp", "ms_query")},
