@@ -283,7 +283,10 @@ def main(argv=None):
     torch.cuda.set_device(0)
     g = W.delaunay1m() if args.workload == "delaunay1m" else W.grid256d(queries=0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
-    idx = spq.build_index(g["n"], dev(g["eu"]), dev(g["ev"]), dev(g["w"]), dev(g["part"]), g["k"])
+    import os
+    cache = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+    idx = spq.build_index(g["n"], dev(g["eu"]), dev(g["ev"]), dev(g["w"]), dev(g["part"]), g["k"],
+                          tune_cache=cache)
     torch.cuda.synchronize()
     st = spq.index_stats(idx)
     print("index built: n=%d V_BG=%d method=%d groups=%d bg_bytes=%.1f GB" % (
