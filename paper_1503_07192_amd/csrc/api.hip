@@ -151,7 +151,7 @@ struct spq_index {
   // share mode
   int32_t share_comps = 0, share_groups = 0, S2 = 0, bf_rounds = 0;
   int64_t S2p = 0;
-  u32 *A = nullptr, *DT = nullptr, *DT2 = nullptr, *bfflag = nullptr;
+  u32 *A = nullptr, *DT = nullptr, *bfflag = nullptr;
   int4* xe = nullptr;
   int32_t* xcount = nullptr;
   // exactness certificate (total weight >= INF)
@@ -195,7 +195,7 @@ struct spq_index {
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
                     vrec, grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
-                    bgvert, label, bglabel, cert, A,    DT,    DT2,   bfflag,  xe, xcount,
+                    bgvert, label, bglabel, cert, A,    DT,    bfflag,  xe, xcount,
                     eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
                     M3, R3, XT3, BG3};
     for (void* p : ptrs) pool_release(p);
@@ -251,16 +251,18 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   HIP_TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
   HIP_TRY(dalloc(&X->XT, (int64_t)G * X->m2pmax * Vgp));
   HIP_TRY(dalloc(&X->A, (int64_t)G * X->m2pmax * X->m2pmax));
-  // Bellman-Ford buffers carry 128 spare rows: a row tile may start at the
-  // last group's last level-2 id
+  // the Bellman-Ford matrix carries 128 spare rows: a row tile may start at
+  // the last group's last level-2 id
   HIP_TRY(dalloc(&X->DT, (V2p + 128) * X->S2p));
-  HIP_TRY(dalloc(&X->DT2, (V2p + 128) * X->S2p));
   HIP_TRY(dalloc(&X->BG2, X->S2p * V2p));
   HIP_TRY(dalloc(&X->H, X->h_elems));
   HIP_TRY(dalloc(&X->pairbase, (int64_t)G * G));
   HIP_TRY(dalloc(&X->xe, 2 * std::max<int64_t>(m, 1)));
   HIP_TRY(dalloc(&X->xcount, 1));
-  HIP_TRY(dalloc(&X->bfflag, 2 * (int64_t)G));
+  // dirty flags, two rounds' worth: per group one word per column tile of
+  // 128 share sources and one "any" word
+  const int32_t ntc = (int32_t)(X->S2p / 128), fs = ntc + 1;
+  HIP_TRY(dalloc(&X->bfflag, 2 * (int64_t)G * fs));
   HIP_TRY(hipMemsetAsync(X->xcount, 0, sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(X->DT + V2p * X->S2p, 0xff, 128 * X->S2p * sizeof(u32), s));
   HIP_TRY(hipMemcpyAsync(X->pairbase, X->h_pairbase.data(), sizeof(int64_t) * G * G,
@@ -268,39 +270,39 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   ha.m2pmax = X->m2pmax; ha.V2 = X->V2; ha.V2p = V2p; ha.b2off = X->b2off; ha.R = X->R;
   ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
   ha.share_groups = X->share_groups; ha.S2 = X->S2; ha.S2p = X->S2p; ha.A = X->A; ha.DT = X->DT;
-  ha.DT2 = X->DT2; ha.xe = X->xe; ha.xcount = X->xcount;
+  ha.xe = X->xe; ha.xcount = X->xcount;
   HIP_TRY(spq::launch_share_prepare(ha, s));
   int32_t nxe = 0;
   HIP_TRY(hipMemcpyAsync(&nxe, X->xcount, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  u32* bufs[2] = {X->DT, X->DT2};
-  int cur = 0;
-  // dirty flags per group, two rounds' worth; the share's groups start dirty
-  std::vector<u32> hd(G, 0);
-  for (int32_t g = 0; g < X->share_groups; g++) hd[g] = 1;
-  HIP_TRY(hipMemcpyAsync(X->bfflag, hd.data(), sizeof(u32) * G, hipMemcpyHostToDevice, s));
+  // the share's groups start dirty on every column tile
+  std::vector<u32> hd((size_t)G * fs, 0);
+  for (int32_t g = 0; g < X->share_groups; g++)
+    for (int32_t t = 0; t < fs; t++) hd[(size_t)g * fs + t] = 1;
+  HIP_TRY(hipMemcpyAsync(X->bfflag, hd.data(), sizeof(u32) * G * fs, hipMemcpyHostToDevice, s));
   u32* dcur = X->bfflag;
-  u32* dnext = X->bfflag + G;
+  u32* dnext = X->bfflag + (int64_t)G * fs;
   for (;;) {
     if (++X->bf_rounds > 100000) return fail(SPQ_EDEVICE, "Bellman-Ford over groups did not settle");
-    for (int32_t g = 0; g < G; g++)
-      if (hd[g])
-        X->relax_bg_exec += (double)((X->h_m2[g] + 127) / 128) * (double)(X->S2p / 128) * 128.0 *
-                            128.0 * (double)round_up(X->h_m2[g], 16);
-    HIP_TRY(hipMemsetAsync(dnext, 0, sizeof(u32) * G, s));
-    HIP_TRY(spq::launch_share_round(ha, bufs[cur], bufs[cur ^ 1], nxe, dcur, dnext, s));
-    HIP_TRY(hipMemcpyAsync(hd.data(), dnext, sizeof(u32) * G, hipMemcpyDeviceToHost, s));
+    for (int32_t g = 0; g < G; g++) {
+      int32_t tiles = 0;
+      for (int32_t t = 0; t < ntc; t++) tiles += hd[(size_t)g * fs + t] != 0;
+      X->relax_bg_exec += (double)((X->h_m2[g] + 127) / 128) * tiles * 128.0 * 128.0 *
+                          (double)round_up(X->h_m2[g], 16);
+    }
+    HIP_TRY(hipMemsetAsync(dnext, 0, sizeof(u32) * G * fs, s));
+    HIP_TRY(spq::launch_share_round(ha, nxe, dcur, dnext, s));
+    HIP_TRY(hipMemcpyAsync(hd.data(), dnext, sizeof(u32) * G * fs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    cur ^= 1;
     std::swap(dcur, dnext);
     bool any = false;
-    for (int32_t g = 0; g < G; g++) any |= hd[g] != 0;
+    for (int32_t g = 0; g < G; g++) any |= hd[(size_t)g * fs + ntc] != 0;
     if (!any) break;
   }
   for (int32_t a1 = 0; a1 < X->share_groups; a1++)
     for (int32_t a2 = 0; a2 < G; a2++) {
-      X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * (Vgp / 128) * 128.0 * 128.0 *
-                          (double)round_up(X->h_m2[a1], 16);
+      X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * ((X->h_gV[a1] + 127) / 128) *
+                          128.0 * 128.0 * (double)round_up(X->h_m2[a1], 16);
       const double y = (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
                        128.0 * (double)round_up(X->h_m2[a2], 16);
       X->relax_bg_exec += y;
@@ -312,7 +314,7 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
     for (auto& e : X->prof) HIP_TRY(hipEventCreate(&e));
     ha.evt = X->prof.data();
   }
-  HIP_TRY(spq::launch_share_compose(ha, bufs[cur], s));
+  HIP_TRY(spq::launch_share_compose(ha, X->DT, s));
   return SPQ_OK;
 }
 
@@ -723,7 +725,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     for (int32_t a1 = 0; a1 < G; a1++)
       for (int32_t a2 = a1; a2 < G; a2++) {
         if (X->V2p > 0)
-          X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * (Vgp / 128) * 128.0 * 128.0 *
+          X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) *
+                              ((X->h_gV[a1] + 127) / 128) * 128.0 * 128.0 *
                               (double)round_up(X->h_m2[a1], 16);
         X->relax_bg_exec += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) *
                             128.0 * 128.0 * (double)round_up(X->h_m2[a2], 16);
@@ -804,7 +807,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       for (int32_t t1 = 0; t1 < nT; t1++)
         for (int32_t t2 = t1; t2 < nT; t2++) {
           if (X->V3p > 0)
-            X->relax_bg_exec += (double)((X->h_m3[t2] + 127) / 128) * (V3gp / 128) * 128.0 * 128.0 *
+            X->relax_bg_exec += (double)((X->h_m3[t2] + 127) / 128) *
+                                ((X->h_tsize[t1] + 127) / 128) * 128.0 * 128.0 *
                                 (double)round_up(X->h_m3[t1], 16);
           X->relax_bg_exec += (double)((X->h_tsize[t1] + 127) / 128) *
                               ((X->h_tsize[t2] + 127) / 128) * 128.0 * 128.0 *

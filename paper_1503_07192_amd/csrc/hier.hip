@@ -291,9 +291,12 @@ __device__ __forceinline__ void fill_inf(u32 (&c)[8][8]) {
 // XT[S2] (m2pmax x Vgp, rows b in B2(S2), columns x of S1) =
 //   min over a in B2(S1) of D2[a][b] + R_S1[a][x],   for S2 = s2base + blockIdx.y.
 // D2 rows are level-2 ids of the sources (all of BG2, or the share's rows).
-// Rows b >= m2[S2] are stored as INF.
+// Rows b in [m2[S2], round16(m2[S2])) are stored as INF.  The composition
+// reads rows below round16(m2[S2]) and column tiles below gV[S1] only, so
+// tiles past those are neither computed nor written.
 __global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t s2base, int32_t Vgp, int32_t m2pmax,
                                                const int32_t* __restrict__ m2,
+                                               const int32_t* __restrict__ gV,
                                                const int32_t* __restrict__ b2off,
                                                const u32* __restrict__ BG2, int64_t V2p,
                                                const u32* __restrict__ R, u32* __restrict__ XT) {
@@ -303,9 +306,10 @@ __global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t s2base, int32
   const int ntx = Vgp / 128;
   const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
   const int32_t ka = m2[s1], mb = m2[s2];
+  if (ti * 128 >= mb || tj * 128 >= gV[s1]) return;
   u32 c[8][8];
   fill_inf(c);
-  if (ti * 128 < mb) {
+  {
     const u32* At = BG2 + (int64_t)b2off[s1] * V2p + b2off[s2] + ti * 128;
     const u32* B = R + (int64_t)s1 * m2pmax * Vgp + tj * 128;
     mp_stream128<true>(c, At, V2p, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB);
@@ -593,15 +597,20 @@ __global__ void k_dt_init(int32_t V2, int32_t S2, int64_t S2p, int32_t ngroups,
     out[i] = (i == b) ? 0u : (i >= lo && i < hi) ? prow[list[i - lo]] : INF;
 }
 
-// Intra-group step, out of place: rows B2(S) of DTn = min(DTo, A_S (x) DTo)
-// for the groups whose rows changed in the previous round (dirty); the rows of
-// the other groups are carried over unchanged.  One product with the closed
-// A_S leaves the group's rows closed, so the step is exact.
+// Dirty flags of the Bellman-Ford rounds: per group, one word per column tile
+// of 128 share sources, then one word "any tile" (stride ntc + 1).
+//
+// Intra-group step, in place: rows B2(S) x column tile of DT = min(DT, A_S (x)
+// DT) for the (group, tile) pairs whose values changed in the previous round.
+// One product with the closed A_S leaves the rows closed.  Tiles of one group
+// read rows that other tiles of the group are lowering: every value read is
+// the old or the new one, both lengths of real walks and each at most the old
+// value, and A_S being closed, the old values already give the closed result,
+// so the step is exact in any interleaving.
 __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
                                                   const int32_t* __restrict__ m2,
                                                   const int32_t* __restrict__ b2off,
-                                                  const u32* __restrict__ A, const u32* __restrict__ DTo,
-                                                  u32* __restrict__ DTn,
+                                                  const u32* __restrict__ A, u32* DT,
                                                   const u32* __restrict__ dirty) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
@@ -609,15 +618,13 @@ __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
   const int32_t ms = m2[s];
   const int ntc = (int)(S2p / 128);
   const int ti = (int)blockIdx.x / ntc, tj = (int)blockIdx.x % ntc;
-  if (ti * 128 >= ms) return;
+  if (ti * 128 >= ms || !dirty[(int64_t)s * (ntc + 1) + tj]) return;
   const int64_t r0 = b2off[s];
   u32 c[8][8];
-  tile_load<128>(c, DTo + (r0 + ti * 128) * S2p + tj * 128, S2p);  // rows past ms: unused
-  if (dirty[s]) {
-    const u32* At = A + (int64_t)s * m2pmax * m2pmax + ti * 128;  // A_S symmetric: At[k][i] = A[i][k]
-    const u32* B = DTo + r0 * S2p + tj * 128;
-    mp_stream128<true>(c, At, m2pmax, B, S2p, (ms + 15) / 16 * 16, ms, ms - ti * 128, sA, sB);
-  }
+  tile_load<128>(c, DT + (r0 + ti * 128) * S2p + tj * 128, S2p);  // rows past ms: unused
+  const u32* At = A + (int64_t)s * m2pmax * m2pmax + ti * 128;  // A_S symmetric: At[k][i] = A[i][k]
+  const u32* B = DT + r0 * S2p + tj * 128;
+  mp_stream128<true>(c, At, m2pmax, B, S2p, (ms + 15) / 16 * 16, ms, ms - ti * 128, sA, sB);
   const int tx = tid_x(), ty = tid_y();
 #pragma unroll
   for (int h = 0; h < 2; h++)
@@ -625,7 +632,7 @@ __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
     for (int a = 0; a < 4; a++) {
       const int row = ti * 128 + h * 64 + ty * 4 + a;
       if (row >= ms) continue;
-      u32* dst = DTn + (r0 + row) * S2p + tj * 128;
+      u32* dst = DT + (r0 + row) * S2p + tj * 128;
 #pragma unroll
       for (int h2 = 0; h2 < 2; h2++) {
         const int i = h * 4 + a, j = h2 * 4;
@@ -657,27 +664,31 @@ __global__ void k_cross_collect(int64_t m, const int32_t* __restrict__ eu, const
   }
 }
 
-// DT[b][i] = min(DT[b][i], DT[a][i] + w) for every directed cross edge whose
-// source group is dirty (a row that has not changed since it was last
-// propagated needs no new pass); a lowered row marks its group dirty for the
-// next round.
+// DT[b][i] = min(DT[b][i], DT[a][i] + w) for every directed cross edge, on
+// the column tiles that are dirty for the source group (values that have not
+// changed since they were last propagated need no new pass); a lowered value
+// marks its (group, tile) dirty for the next round.
 __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2, int64_t S2p, u32* DT,
                            const u32* __restrict__ dirty, u32* __restrict__ dirty_next) {
   const int32_t e = blockIdx.x;
   if (e >= nxe) return;
   const int4 t = xe[e];
-  if (!dirty[t.w >> 16]) return;
+  const int ntc = (int)(S2p / 128);
+  const u32* dsrc = dirty + (int64_t)(t.w >> 16) * (ntc + 1);
+  if (!dsrc[ntc]) return;
+  u32* dnext = dirty_next + (int64_t)(t.w & 0xffff) * (ntc + 1);
   const u32* src = DT + (int64_t)t.x * S2p;
   u32* dst = DT + (int64_t)t.y * S2p;
-  u32 diff = 0;
   for (int32_t i = threadIdx.x; i < S2; i += blockDim.x) {
+    const int tile = i >> 7;
+    if (!dsrc[tile]) continue;
     const u32 v = min(src[i] + (u32)t.z, INF);
     if (v < dst[i]) {
       atomicMin(dst + i, v);
-      diff = 1;
+      dnext[tile] = 1u;
+      dnext[ntc] = 1u;
     }
   }
-  if (diff) dirty_next[t.w & 0xffff] = 1u;
 }
 
 // D2s (S2p x V2p) = DT^T, 32 x 32 tiles through LDS.
@@ -739,8 +750,8 @@ hipError_t launch_hier_level2_compose(const HierArgs& a, hipStream_t s) {
   for (int32_t s1 = 0; s1 < a.ngroups; s1++) {
     const unsigned pairs = (unsigned)(a.ngroups - s1);
     if (a.V2p > 0)
-      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(s1, s1, a.Vgp, a.m2pmax, a.m2, a.b2off,
-                                                                 a.BG2, a.V2p, a.R, a.XT);
+      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(s1, s1, a.Vgp, a.m2pmax, a.m2, a.gV,
+                                                                 a.b2off, a.BG2, a.V2p, a.R, a.XT);
     if (a.evt) {
       hipError_t e = hipEventRecord(a.evt[2 * s1], s);
       if (e != hipSuccess) return e;
@@ -797,8 +808,9 @@ hipError_t launch_level3_b(const L3Args& a, hipStream_t s) {
   for (int32_t t1 = 0; t1 < a.nT; t1++) {
     const unsigned pairs = (unsigned)(a.nT - t1);
     if (a.V3p > 0)
-      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(t1, t1, a.V3gp, a.m3pmax, a.m3, a.b3off,
-                                                                 a.BG3, a.V3p, a.R3, a.XT3);
+      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(t1, t1, a.V3gp, a.m3pmax, a.m3,
+                                                                 a.tsize, a.b3off, a.BG3, a.V3p, a.R3,
+                                                                 a.XT3);
     k_mp_y_dense<<<dim3((unsigned)(ntx * ntx), pairs), 256, 0, s>>>(
         t1, t1, a.V3gp, a.m3pmax, a.m3, a.tsize, a.tbase, a.XT3, a.R3, a.M3, a.BG2, a.V2p);
   }
@@ -823,22 +835,20 @@ hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s) {
                                                                            a.b2list, a.Mg, a.A);
   k_dt_init<<<(unsigned)a.V2p, 256, 0, s>>>(a.V2, a.S2, a.S2p, a.ngroups, a.b2off, a.b2list, a.Vgp,
                                             a.Mg, a.DT);
-  hipError_t e = hipMemcpyAsync(a.DT2, a.DT, sizeof(u32) * a.V2p * a.S2p, hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return e;
   if (a.m > 0)
     k_cross_collect<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
                                                  a.b2off, a.b2rank, a.xcount, a.xe);
   return hipGetLastError();
 }
 
-// One Bellman-Ford round: DT (in) -> DT2 (intra) -> cross edges on DT2.
-hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, const u32* dirty,
-                              u32* dirty_next, hipStream_t s) {
+// One Bellman-Ford round, in place on DT: intra-group step, then cross edges.
+hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const u32* dirty, u32* dirty_next,
+                              hipStream_t s) {
   const int ntm = a.m2pmax / 128, ntc = (int)(a.S2p / 128);
   k_bf_intra<<<dim3((unsigned)(ntm * ntc), (unsigned)a.ngroups), 256, 0, s>>>(
-      a.m2pmax, a.S2p, a.m2, a.b2off, a.A, DTin, DTout, dirty);
+      a.m2pmax, a.S2p, a.m2, a.b2off, a.A, a.DT, dirty);
   if (nxe > 0)
-    k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, DTout, dirty, dirty_next);
+    k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, a.DT, dirty, dirty_next);
   return hipGetLastError();
 }
 
@@ -848,7 +858,7 @@ hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s)
   const int ntx = a.Vgp / 128, ntm = a.m2pmax / 128;
   for (int32_t s1 = 0; s1 < a.share_groups; s1++) {
     k_mp_xt<<<dim3((unsigned)(ntm * ntx), (unsigned)a.ngroups), 256, 0, s>>>(
-        s1, 0, a.Vgp, a.m2pmax, a.m2, a.b2off, a.BG2, a.V2p, a.R, a.XT);
+        s1, 0, a.Vgp, a.m2pmax, a.m2, a.gV, a.b2off, a.BG2, a.V2p, a.R, a.XT);
     if (a.evt) {
       hipError_t e = hipEventRecord(a.evt[2 * s1], s);
       if (e != hipSuccess) return e;

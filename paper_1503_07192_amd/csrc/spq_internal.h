@@ -90,7 +90,7 @@ struct HierArgs {
   // share mode: rows of BG only from the first share_groups groups
   int32_t share_groups, S2;        // groups, level-2 sources (ids 0 .. S2-1)
   int64_t S2p;                     // S2 rounded up to 128
-  u32 *A, *DT, *DT2;               // A_S blocks; Bellman-Ford buffers (V2p x S2p)
+  u32 *A, *DT;                     // A_S blocks; Bellman-Ford distances (V2p + 128 rows x S2p)
   int4* xe;                        // directed cross edges
   int32_t* xcount;
   hipEvent_t* evt;                 // NULL, or 2 per composition launch (k_mp_y)
@@ -99,8 +99,9 @@ struct HierArgs {
   u32 *cert_bad, *cert_mbg;
 };
 hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s);
-hipError_t launch_share_round(const HierArgs& a, u32* DTin, u32* DTout, int32_t nxe, const u32* dirty,
-                              u32* dirty_next, hipStream_t s);
+// dirty flags: per group, ntc = S2p / 128 column tiles then one "any" word
+hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const u32* dirty, u32* dirty_next,
+                              hipStream_t s);
 hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s);
 hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
 // Flat method: per-BG-vertex layout terms, then the closed BG matrix (Vp x Vp)
