@@ -81,6 +81,11 @@ typedef struct {
                           super-groups of consecutive groups (level 3).
                           0 auto (about 4,096 BG2 vertices per super-group),
                           -1 never, g > 0 always, g groups per super-group */
+  int32_t group_bg;      /* two-level: > 0 forms the groups by size instead of
+                          by count: consecutive components join a group while
+                          it holds at most group_bg BG vertices (a larger
+                          component gets a group of its own); overrides
+                          group_comps */
 } spq_build_opts;
 
 #define SPQ_NO_LOOKAHEAD 1
@@ -170,6 +175,16 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
  */
 spq_status spq_query_batch(const spq_index* idx, int64_t q, const int32_t* v1,
                            const int32_t* v2, int32_t* out, void* stream);
+
+/*
+ * The same queries on HOST arrays (v1, v2, out: q int32 each, caller-owned),
+ * for callers without device memory of their own: the pairs are staged in
+ * device memory of the library (allocated per call), answered on a stream
+ * of the library's own, and copied back; returns when out is filled.
+ * Synchronous.  Errors: as spq_query_batch, plus SPQ_ENOMEM.
+ */
+spq_status spq_query_batch_host(const spq_index* idx, int64_t q, const int32_t* v1,
+                                const int32_t* v2, int32_t* out);
 
 /*
  * New edge weights for an index built with SPQ_GRAPH: same graph (eu, ev in

@@ -6,6 +6,9 @@ device architecture and a size class of the problem:
 
 * flat Floyd-Warshall on BG: tile side (64, 128) x interior K chunk (16, 32);
 * two-level BG: consecutive components per group (16 .. 256) x K chunk.
+  Groups formed by size (``group_bg``) are not tried: on partitions numbered
+  by recursive bisection or super-blocks they cut across the aligned runs of
+  2^j components that make a group compact, and measured 1.5-10x slower.
 
 Every candidate must give bit-identical answers on a query sample (checked),
 so picking one is purely a speed decision.  ``build_index(..., tune_cache=)``

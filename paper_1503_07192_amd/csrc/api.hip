@@ -235,7 +235,7 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
                               hipStream_t s) {
   const int32_t G = X->ngroups, Vgp = X->Vgp;
   if (G > 65535) return fail(SPQ_EINVAL, "share mode supports at most 65,535 groups");
-  X->share_groups = std::min(G, (X->share_comps + X->cpg - 1) / X->cpg);
+  X->share_groups = X->h_grp[X->share_comps - 1] + 1;
   X->S2 = X->h_b2off[X->share_groups];
   X->S2p = round_up(std::max<int32_t>(X->S2, 1), 128);
   X->h_pairbase.assign((size_t)G * G, -1);
@@ -385,7 +385,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   bool profile = false, plain = false;
   int32_t method_opt = 0, group_comps = 0, share_comps = 0, inner_kc = 0;
   bool lookahead = true, use_graph = false;
-  int32_t level3_opt = 0;
+  int32_t level3_opt = 0, group_bg = 0;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
@@ -408,6 +408,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     lookahead = !(opts->flags & SPQ_NO_LOOKAHEAD);
     use_graph = (opts->flags & SPQ_GRAPH) != 0;
     level3_opt = opts->level3_groups;
+    group_bg = opts->group_bg;
+    if (group_bg < 0) return fail(SPQ_EINVAL, "group_bg < 0");
     if (level3_opt < -1) return fail(SPQ_EINVAL, "level3_groups must be -1, 0 or positive");
     if (use_graph && (share_comps > 0 || profile))
       return fail(SPQ_EINVAL, "SPQ_GRAPH cannot be combined with share_comps or profile");
@@ -530,15 +532,31 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       while (cpg * 2 <= k && cpg * 2 * avg_nb <= 4096.0 * 1.41) cpg *= 2;
     }
   }
-  X->ngroups = (k + cpg - 1) / cpg;
+  // groups = runs of consecutive components: cpg each, or (group_bg) as many
+  // as keep the group within group_bg BG vertices
+  std::vector<int32_t> gstart;
+  if (X->method == 2 && group_bg > 0) {
+    int32_t held = 0;
+    for (int32_t c = 0; c < k; c++) {
+      if (gstart.empty() || (held > 0 && held + X->h_nb[c] > group_bg)) {
+        gstart.push_back(c);
+        held = 0;
+      }
+      held += X->h_nb[c];
+    }
+  } else {
+    for (int32_t c = 0; c < k; c += cpg) gstart.push_back(c);
+  }
+  X->ngroups = (int32_t)gstart.size();
+  gstart.push_back(k);
   X->cpg = cpg;
   X->h_grp.resize(k);
   X->h_gbg0.resize(X->ngroups);
   X->h_gV.resize(X->ngroups);
-  for (int32_t c = 0; c < k; c++) X->h_grp[c] = c / cpg;
   for (int32_t g = 0; g < X->ngroups; g++) {
-    X->h_gbg0[g] = X->h_bgoff[g * cpg];
-    X->h_gV[g] = X->h_bgoff[std::min((g + 1) * cpg, k)] - X->h_gbg0[g];
+    for (int32_t c = gstart[g]; c < gstart[g + 1]; c++) X->h_grp[c] = g;
+    X->h_gbg0[g] = X->h_bgoff[gstart[g]];
+    X->h_gV[g] = X->h_bgoff[gstart[g + 1]] - X->h_gbg0[g];
     X->Vgp = std::max<int32_t>(X->Vgp, (int32_t)round_up(X->h_gV[g], 128));
   }
   if (X->method == 1) {
@@ -954,6 +972,38 @@ spq_status spq_query_batch(const spq_index* X, int64_t q, const int32_t* v1, con
   a.H = X->H; a.pairbase = X->pairbase; a.gV = X->gV;
   a.ngroups = X->ngroups; a.V = X->V; a.share_comps = X->share_comps;
   HIP_TRY(spq::launch_query(a, reinterpret_cast<hipStream_t>(stream)));
+  return SPQ_OK;
+}
+
+spq_status spq_query_batch_host(const spq_index* X, int64_t q, const int32_t* v1, const int32_t* v2,
+                                int32_t* out) {
+  if (!X) return fail(SPQ_EINVAL, "index is NULL");
+  if (!X->valid) return fail(SPQ_ERANGE, "index invalidated by a failed reweight");
+  if (q < 0) return fail(SPQ_EINVAL, "q < 0");
+  if (q == 0) return SPQ_OK;
+  if (!v1 || !v2 || !out) return fail(SPQ_EINVAL, "null query array");
+  int32_t* d = nullptr;
+  HIP_TRY(dalloc(&d, 3 * q));
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);  // default priority
+  // the index may still be building on another stream
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, X->ev[4], 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(d, v1, sizeof(int32_t) * q, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d + q, v2, sizeof(int32_t) * q, hipMemcpyHostToDevice, s);
+  spq_status st = SPQ_OK;
+  if (e == hipSuccess) {
+    st = spq_query_batch(X, q, d, d + q, d + 2 * q, s);
+    if (st == SPQ_OK)
+      e = hipMemcpyAsync(out, d + 2 * q, sizeof(int32_t) * q, hipMemcpyDeviceToHost, s);
+  }
+  if (s) {
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
+    (void)hipStreamDestroy(s);
+  }
+  pool_release(d);  // the stream has drained: nothing queued uses d any more
+  if (st != SPQ_OK) return st;
+  HIP_TRY(e);
   return SPQ_OK;
 }
 

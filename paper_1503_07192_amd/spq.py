@@ -38,7 +38,7 @@ class BuildOpts(ctypes.Structure):
                 ("plain", ctypes.c_int32), ("bg_method", ctypes.c_int32),
                 ("group_comps", ctypes.c_int32), ("share_comps", ctypes.c_int32),
                 ("inner_kc", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("level3_groups", ctypes.c_int32)]
+                ("level3_groups", ctypes.c_int32), ("group_bg", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -67,6 +67,7 @@ _SIGS = {
     "spq_build_index": (I32, [I32, I64, P, P, P, P, I32, ctypes.POINTER(BuildOpts), P,
                               ctypes.POINTER(P)]),
     "spq_query_batch": (I32, [P, I64, P, P, P, P]),
+    "spq_query_batch_host": (I32, [P, I64, P, P, P]),
     "spq_reweight_index": (I32, [P, P, P]),
     "spq_index_stats": (I32, [P, ctypes.POINTER(Stats)]),
     "spq_index_layout": (I32, [P, P, P, P, P, P]),
@@ -161,7 +162,7 @@ class Index:
 
 def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg_method=0,
                 group_comps=0, share_comps=0, inner_kc=0, lookahead=True, graph=False,
-                level3_groups=0, tune_cache=None, stream=None) -> Index:
+                level3_groups=0, group_bg=0, tune_cache=None, stream=None) -> Index:
     """Algorithm 1 on device tensors; see spq_build_index.
 
     graph: capture Phases 2-3 as HIP graphs kept for reweight().
@@ -177,11 +178,12 @@ def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg
         bg_method = bg_method or tuned.get("bg_method", 0)
         group_comps = group_comps or tuned.get("group_comps", 0)
         level3_groups = level3_groups or tuned.get("level3_groups", 0)
+        group_bg = group_bg or tuned.get("group_bg", 0)
     opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)), plain=int(bool(plain)),
                      bg_method=int(bg_method), group_comps=int(group_comps),
                      share_comps=int(share_comps), inner_kc=int(inner_kc),
                      flags=(0 if lookahead else SPQ_NO_LOOKAHEAD) | (SPQ_GRAPH if graph else 0),
-                     level3_groups=int(level3_groups))
+                     level3_groups=int(level3_groups), group_bg=int(group_bg))
     h = ctypes.c_void_p()
     m = int(eu.numel())
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),
@@ -210,6 +212,18 @@ def query_batch(index: Index, v1, v2, out=None, stream=None):
         raise ValueError("out has the wrong length")
     _check(load().spq_query_batch(index.handle, q, _dev_i32(v1, "v1"), _dev_i32(v2, "v2"),
                                   _dev_i32(out, "out"), _stream(stream)))
+    return out
+
+
+def query_batch_host(index: Index, v1, v2):
+    """Algorithm 2 on host (numpy) pairs; returns a numpy int32 array."""
+    v1 = np.ascontiguousarray(v1, np.int32)
+    v2 = np.ascontiguousarray(v2, np.int32)
+    if v1.shape != v2.shape or v1.ndim != 1:
+        raise ValueError("v1 and v2 must be 1-d and equally long")
+    out = np.empty_like(v1)
+    _check(load().spq_query_batch_host(index.handle, len(v1), v1.ctypes.data, v2.ctypes.data,
+                                       out.ctypes.data))
     return out
 
 

@@ -30,6 +30,7 @@ def test_argument_errors_without_device():
     assert "bg_tile" in spq.last_error()
     assert L.spq_build_index(5, 0, None, None, None, None, 2, None, None, None) == 1
     assert L.spq_query_batch(None, 3, None, None, None, None) == 1
+    assert L.spq_query_batch_host(None, 3, None, None, None) == 1
     assert L.spq_fw_dense(10, 10, 3, 0, None, None) == 1
     assert L.spq_fw_dense(10, 8, 64, 0, None, None) == 1
     assert L.spq_fw_dense(10, 64, 64, 8, None, None) == 1

@@ -324,6 +324,11 @@ def test_query_invalid_ids_and_empty_batch():
     assert out[0] == D[0, 1]
     e = torch.empty(0, dtype=torch.int32, device="cuda")
     assert spq.query_batch(idx, e, e).numel() == 0
+    # the host-array entry point gives the same answers, bad pairs included
+    assert np.array_equal(spq.query_batch_host(idx, v1, v2), out)
+    assert spq.query_batch_host(idx, v1[:0], v2[:0]).size == 0
+    a, b = all_pairs(g["n"])
+    assert np.array_equal(spq.query_batch_host(idx, a, b), run_queries(idx, a, b))
 
 
 def test_build_errors():
@@ -536,11 +541,14 @@ def share_vertices(g, share_comps):
     return np.flatnonzero(g["part"] < share_comps).astype(np.int32)
 
 
-def check_share(g, idx, share_comps, nsrc=None, rng=None):
+def check_share(g, idx, share_comps, nsrc=None, rng=None, uniform=True):
     lay = spq.index_layout(idx)
     st = spq.index_stats(idx)
     verts = bg_vertices(lay)
-    bgend = int(lay["bgoff"][min(g["k"], st["share_groups"] * (-(-g["k"] // st["ngroups"])))])
+    if uniform:   # rows of the whole share groups
+        bgend = int(lay["bgoff"][min(g["k"], st["share_groups"] * (-(-g["k"] // st["ngroups"])))])
+    else:         # rows of the share's components
+        bgend = int(lay["bgoff"][share_comps])
     rows = np.arange(bgend) if nsrc is None else rng.choice(bgend, min(nsrc, bgend), replace=False)
     if len(rows):
         check_bg_rows(g, idx, lay, rows)
@@ -572,6 +580,41 @@ def test_share_small_grid(share_comps, gc):
     check_layout(g, lay)
     check_components(g, idx, lay)
     check_share(g, idx, share_comps)
+
+
+def size_groups(nb, budget):
+    """Group count of the size rule: consecutive components join a group
+    while it holds at most `budget` BG vertices."""
+    groups, held = 0, 0
+    for x in nb:
+        if groups == 0 or (held > 0 and held + x > budget):
+            groups, held = groups + 1, 0
+        held += int(x)
+    return groups
+
+
+@pytest.mark.parametrize("gb", [1, 40, 64, 100, 200, 1000])
+def test_grid32_size_groups_equal_flat(gb):
+    g = W.grid32()
+    flat = build(g, bg_method=1)
+    two = build(g, bg_method=2, group_bg=gb)
+    st = spq.index_stats(two)
+    assert st["ngroups"] == size_groups(spq.index_layout(two)["nb"], gb)
+    assert np.array_equal(spq.index_bg_rows(flat, 0, 348, 348), spq.index_bg_rows(two, 0, 348, 348))
+    v1, v2 = all_pairs(g["n"])
+    assert np.array_equal(run_queries(flat, v1, v2), run_queries(two, v1, v2))
+
+
+@pytest.mark.parametrize("share_comps,gb", [(1, 10), (3, 25), (5, 60)])
+def test_share_size_groups(share_comps, gb):
+    rng = np.random.default_rng(60 + share_comps)
+    eu, ev, w = W.random_grid(rng, 16, 16, keep=0.9, diag=0.2, wlo=0, whi=50)
+    part, k = W.block_partition(16, 16, 4, 4, sb=2)
+    g = dict(name="sharegrid", n=256, eu=eu, ev=ev, w=w, part=part, k=k)
+    idx = build(g, share_comps=share_comps, group_bg=gb)
+    st = spq.index_stats(idx)
+    assert st["ngroups"] == size_groups(spq.index_layout(idx)["nb"], gb)
+    check_share(g, idx, share_comps, uniform=False)
 
 
 def test_share_random_partition():
