@@ -129,7 +129,9 @@ struct spq_index {
   uint8_t* flag = nullptr;
   unsigned long long *sumc = nullptr, *total = nullptr;
   u32 *err = nullptr, *members = nullptr, *M = nullptr, *BG = nullptr;
-  uint4* vrec = nullptr;
+  u32* vrec = nullptr;
+  int64_t* gT = nullptr;           // [groups] first element of each group's band in H
+  std::vector<int64_t> h_gT;
   // groups (all components in group 0 for the flat store)
   int32_t method = 1, ngroups = 1, cpg = 1, Vgp = 0, V2 = 0, m2pmax = 0, nbig = 0;
   int64_t V2p = 0, h_elems = 0;
@@ -193,7 +195,7 @@ struct spq_index {
     if (cap) (void)hipStreamDestroy(cap);
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
-                    vrec, grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
+                    vrec, gT,    grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
                     bgvert, label, bglabel, cert, A,    DT,    bfflag,  xe, xcount,
                     eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
@@ -228,6 +230,19 @@ static hipError_t graph_segment(spq_index* X, hipStream_t s, F&& body) {
   return hipGraphLaunch(x, s);
 }
 
+// The query kernel locates a pair block from the two vertex records alone:
+// band of S1 + |S1| * (first BG id of S2, minus that of S1 in the full store).
+// The pair table built for the composition must agree with it.
+static bool bands_match(const spq_index* X, int32_t row_groups, bool share) {
+  const int32_t G = X->ngroups;
+  for (int32_t a1 = 0; a1 < row_groups; a1++)
+    for (int32_t a2 = share ? 0 : a1; a2 < G; a2++)
+      if (X->h_pairbase[(size_t)a1 * G + a2] !=
+          X->h_gT[a1] + (int64_t)X->h_gV[a1] * (X->h_gbg0[a2] - (share ? 0 : X->h_gbg0[a1])))
+        return false;
+  return true;
+}
+
 // Share mode (after level 1): Bellman-Ford over groups from the share's
 // level-2 vertices, then the composition for the share's groups against all
 // groups.  Synchronous (one small readback per round).
@@ -245,6 +260,7 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
       X->h_pairbase[(size_t)a1 * G + a2] = X->h_elems;
       X->h_elems += (int64_t)X->h_gV[a1] * X->h_gV[a2];
     }
+  if (!bands_match(X, X->share_groups, true)) return fail(SPQ_EDEVICE, "internal: band layout");
   const int64_t V2p = std::max<int64_t>(X->V2p, 128);
   X->V2p = V2p;
   HIP_TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
@@ -589,7 +605,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   TRY(dalloc(&X->bgvert, X->V));
   TRY(dalloc(&X->fill, k));
   TRY(dalloc(&X->members, n));
-  TRY(dalloc(&X->vrec, 2 * (int64_t)n));
+  TRY(dalloc(&X->vrec, spq::VREC_WORDS * (int64_t)n));
   TRY(dalloc(&X->M, X->comp_elems));
   if (X->method == 1 && X->Vp > 0) TRY(dalloc(&X->BG, (int64_t)X->Vp * X->Vp));
   TRY(dalloc(&X->grp, k));
@@ -598,6 +614,20 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   TRY(hipMemcpyAsync(X->grp, X->h_grp.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
   TRY(hipMemcpyAsync(X->gbg0, X->h_gbg0.data(), sizeof(int32_t) * X->ngroups, hipMemcpyHostToDevice, s));
   TRY(hipMemcpyAsync(X->gV, X->h_gV.data(), sizeof(int32_t) * X->ngroups, hipMemcpyHostToDevice, s));
+  // band of each group in the blocked store: the full store keeps group pairs
+  // S1 <= S2 (rows of S1 against S1 .. last), a share keeps share groups
+  // against all groups, the flat method one group
+  X->h_gT.assign(X->ngroups, 0);
+  {
+    const int32_t sg = share_comps > 0 ? X->h_grp[share_comps - 1] + 1 : X->ngroups;
+    int64_t t = 0;
+    for (int32_t g = 0; g < sg; g++) {
+      X->h_gT[g] = t;
+      t += (int64_t)X->h_gV[g] * (share_comps > 0 ? X->V : X->V - X->h_gbg0[g]);
+    }
+  }
+  TRY(dalloc(&X->gT, X->ngroups));
+  TRY(hipMemcpyAsync(X->gT, X->h_gT.data(), sizeof(int64_t) * X->ngroups, hipMemcpyHostToDevice, s));
   TRY(hipMemcpyAsync(X->off, X->h_off.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
   TRY(hipMemcpyAsync(X->bgoff, X->h_bgoff.data(), sizeof(int32_t) * (k + 1), hipMemcpyHostToDevice, s));
   TRY(hipMemcpyAsync(X->P, X->h_P.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
@@ -624,7 +654,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   pa.off = X->off; pa.bgoff = X->bgoff; pa.fill = X->fill; pa.members = X->members;
   pa.comp = X->comp; pa.local = X->local; pa.bgcomp = X->bgcomp; pa.bglocal = X->bglocal;
   pa.moff = X->moff; pa.P = X->P; pa.vrec = X->vrec; pa.grp = X->grp; pa.gbg0 = X->gbg0;
-  pa.bgvert = X->bgvert;
+  pa.gV = X->gV; pa.gT = X->gT; pa.bgvert = X->bgvert;
   TRY(spq::launch_renumber(pa, s));
   if (X->certify) {
     spq_status cs = cc_labels(X, m, eu, ev, s);
@@ -712,6 +742,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
         X->h_pairbase[(size_t)a1 * G + a2] = X->h_elems;
         X->h_elems += (int64_t)X->h_gV[a1] * X->h_gV[a2];
       }
+    if (!bands_match(X, G, false)) return guard(fail(SPQ_EDEVICE, "internal: band layout"));
     // level 3: BG2 above 16,384 vertices (or as asked) is closed by super-groups
     if (X->V2 > 0 && level3_opt >= 0) {
       int32_t gpt = 0;
@@ -968,9 +999,7 @@ spq_status spq_query_batch(const spq_index* X, int64_t q, const int32_t* v1, con
   if (!v1 || !v2 || !out) return fail(SPQ_EINVAL, "null query array");
   spq::QueryArgs a{};
   a.q = q; a.v1 = v1; a.v2 = v2; a.out = out; a.n = X->n;
-  a.vrec = X->vrec; a.M = X->M;
-  a.H = X->H; a.pairbase = X->pairbase; a.gV = X->gV;
-  a.ngroups = X->ngroups; a.V = X->V; a.share_comps = X->share_comps;
+  a.vrec = X->vrec; a.M = X->M; a.H = X->H; a.share_comps = X->share_comps;
   HIP_TRY(spq::launch_query(a, reinterpret_cast<hipStream_t>(stream)));
   return SPQ_OK;
 }

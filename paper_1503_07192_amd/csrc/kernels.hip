@@ -271,23 +271,28 @@ __global__ void k_bg_edges(int64_t m, const int32_t* __restrict__ eu, const int3
 }
 
 // ----------------------------------------------------------------- query --
-// Per-vertex record read by the query kernel in one 32-byte load: where the
-// vertex's row of APSP(C) starts, its component, its local index, and the
-// component's first BG id and boundary count.
+// Per-vertex query record (layout in spq_internal.h): where the vertex's row
+// of APSP(C) starts, its component and local index, its component's |B(C)|
+// and place in its group, and its group's size and band in the blocked store,
+// so a query needs no other table.
 __global__ void k_vrec(int32_t n, const int32_t* __restrict__ comp, const int32_t* __restrict__ local,
                        const int64_t* __restrict__ moff, const int32_t* __restrict__ P,
                        const int32_t* __restrict__ bgoff, const int32_t* __restrict__ nb,
                        const int32_t* __restrict__ grp, const int32_t* __restrict__ gbg0,
-                       uint4* __restrict__ vrec) {
+                       const int32_t* __restrict__ gV, const int64_t* __restrict__ gT,
+                       u32* __restrict__ vrec) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int32_t c = comp[v], l = local[v], s = grp[c];
   const uint64_t row = (uint64_t)(moff[c] + (int64_t)l * P[c]);
-  vrec[2 * v] = make_uint4((u32)row, (u32)(row >> 32), (u32)c, (u32)l);
-  vrec[2 * v + 1] = make_uint4((u32)bgoff[c], (u32)nb[c], (u32)s, (u32)(bgoff[c] - gbg0[s]));
+  const uint64_t t = (uint64_t)gT[s];
+  uint4* r = reinterpret_cast<uint4*>(vrec + v * VREC_WORDS);
+  r[0] = make_uint4((u32)row, (u32)(row >> 32), (u32)c, (u32)l);
+  r[1] = make_uint4((u32)gbg0[s], (u32)nb[c], (u32)s, (u32)(bgoff[c] - gbg0[s]));
+  r[2] = make_uint4((u32)gV[s], 0u, (u32)t, (u32)(t >> 32));
 }
 
-// Algorithm 2, one query per half-wave (32 lanes, 8 queries per workgroup):
+// Algorithm 2, one query at a time per half-wave (32 lanes, 8 per workgroup):
 //   t(b2) = min over b1 of dist_C1(v1, b1) + dist_BG(b1, b2)     (first stage)
 //   r     = min over b2 of t(b2) + dist_C2(b2, v2)                (second stage)
 //   r     = min(r, dist_C1(v1, v2)) if C1 = C2                    (same component)
@@ -300,6 +305,9 @@ __global__ void k_vrec(int32_t n, const int32_t* __restrict__ comp, const int32_
 // The blocked BG store keeps each B(C1) x B(C2) block as one contiguous run
 // (rows |B(C2)| apart).  Block columns come in chunks of 128 when
 // |B(C2)| > 128.
+// The two vertex records (24 words) are spread one word per lane over lanes
+// 0-23 and read with ds_bpermute; they locate the block without any other
+// table.
 #ifndef SPQ_QUERY_UNROLL
 #define SPQ_QUERY_UNROLL 6
 #endif
@@ -309,78 +317,100 @@ __device__ __forceinline__ uint4 load4_upto(const u32* p, int valid) {
   return make_uint4(valid > 0 ? p[0] : INF, valid > 1 ? p[1] : INF, valid > 2 ? p[2] : INF, INF);
 }
 
+__device__ __forceinline__ u32 hw_word(u32 x, int lane) { return (u32)__shfl((int)x, lane, 32); }
+
+// ids (lanes 0, 1) of pair i, or 0 past the end
+__device__ __forceinline__ u32 load_ids(int64_t i, int64_t q, const int32_t* v1, const int32_t* v2,
+                                        int l) {
+  if (i >= q || l > 1) return 0u;
+  return (u32)(l == 0 ? v1[i] : v2[i]);
+}
+
+// records of both endpoints (lanes 0-23), if both ids are valid
+__device__ __forceinline__ u32 load_recs(u32 ids, int32_t n, const u32* vrec, int l, bool& ok) {
+  const int32_t a = (int32_t)hw_word(ids, 0), b = (int32_t)hw_word(ids, 1);
+  ok = a >= 0 && a < n && b >= 0 && b < n;
+  if (!ok || l >= 2 * VREC_WORDS) return 0u;
+  const int32_t v = l < VREC_WORDS ? a : b;
+  return vrec[(int64_t)v * VREC_WORDS + (l < VREC_WORDS ? l : l - VREC_WORDS)];
+}
+
 // 64 VGPRs: eight waves per SIMD keep enough block loads in flight
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_query(
     int64_t q, const int32_t* __restrict__ v1, const int32_t* __restrict__ v2,
-    int32_t* __restrict__ out, int32_t n, const uint4* __restrict__ vrec, const u32* __restrict__ M,
-    const u32* __restrict__ H, const int64_t* __restrict__ pairbase, const int32_t* __restrict__ gV,
-    int32_t ngroups, int32_t V, int32_t share_comps) {
+    int32_t* __restrict__ out, int32_t n, const u32* __restrict__ vrec, const u32* __restrict__ M,
+    const u32* __restrict__ H, int32_t share_comps) {
   constexpr int QU = SPQ_QUERY_UNROLL;
   const int64_t qi = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
   const int l = threadIdx.x & 31;
   if (qi >= q) return;  // whole half-waves only
-  const int32_t a = v1[qi], b = v2[qi];
-  if (a < 0 || a >= n || b < 0 || b >= n) {
-    if (l == 0) out[qi] = -1;
-    return;
-  }
-  uint4 ra = vrec[2 * (int64_t)a], ra2 = vrec[2 * (int64_t)a + 1];
-  uint4 rb = vrec[2 * (int64_t)b], rb2 = vrec[2 * (int64_t)b + 1];
-  if (share_comps > 0 && (int32_t)ra.z >= share_comps) {  // v1 outside the share
-    if (l == 0) out[qi] = -1;
-    return;
-  }
-  // the full two-level store keeps group pairs S1 <= S2 only; dist is
-  // symmetric, so swap the endpoints when needed (a share keeps all S2)
-  if (share_comps == 0 && ra2.z > rb2.z) {
-    const uint4 t = ra, t2 = ra2;
-    ra = rb; ra2 = rb2; rb = t; rb2 = t2;
-  }
-  // one group (flat method): no table lookups on the critical path
-  const int64_t pb = ngroups == 1 ? 0 : pairbase[(int64_t)ra2.z * ngroups + rb2.z];
-  const int32_t vs2 = ngroups == 1 ? V : gV[rb2.z];
-  const u32* blk = H + pb + (int64_t)ra2.w * vs2 + (int64_t)ra2.y * rb2.w;
-  const int64_t ld = rb2.y;
-  const u32* row1 = M + ((uint64_t)ra.x | ((uint64_t)ra.y << 32));
-  const u32* row2 = M + ((uint64_t)rb.x | ((uint64_t)rb.y << 32));
-  const int32_t nb1 = (int32_t)ra2.y, nb2 = (int32_t)rb2.y;
-  u32 best = INF;
-  for (int32_t c0 = 0; c0 < nb2; c0 += 128) {
-    const int32_t nbc = min(128, nb2 - c0);
-    const int L = (nbc + 3) >> 2, R = 32 / L;
-    const int r = l / L, col = c0 + (l - r * L) * 4;
-    const bool lane_on = r < R;
-    const int cvalid = c0 + nbc - col;  // columns of this lane's piece (>= 1 when on)
-    // second-stage terms first: independent of the block
-    u32 e[4];
+  bool ok;
+  const u32 rec = load_recs(load_ids(qi, q, v1, v2, l), n, vrec, l, ok);
+  {
+    u32 res = 0xffffffffu;  // SPQ_BAD_PAIR
+    if (ok && (share_comps == 0 || (int32_t)hw_word(rec, 2) < share_comps)) {
+      {
+        // the full two-level store keeps group pairs S1 <= S2 only; dist is
+        // symmetric, so take the endpoints in group order when needed (a
+        // share keeps all S2): words o1 + j describe the first, o2 + j the
+        // second
+        const bool sw = share_comps == 0 && hw_word(rec, 6) > hw_word(rec, VREC_WORDS + 6);
+        const int o1 = sw ? VREC_WORDS : 0, o2 = sw ? 0 : VREC_WORDS;
+        const u32* row1 = M + ((uint64_t)hw_word(rec, o1) | ((uint64_t)hw_word(rec, o1 + 1) << 32));
+        const u32* row2 = M + ((uint64_t)hw_word(rec, o2) | ((uint64_t)hw_word(rec, o2 + 1) << 32));
+        const int32_t nb1 = (int32_t)hw_word(rec, o1 + 5), nb2 = (int32_t)hw_word(rec, o2 + 5);
+        // band of group S1, then the pair block: S1's rows against the
+        // groups before S2 in the band (from S1 itself in the full store)
+        const int64_t band = (int64_t)((uint64_t)hw_word(rec, o1 + 10) |
+                                       ((uint64_t)hw_word(rec, o1 + 11) << 32));
+        const int64_t gv1 = hw_word(rec, o1 + 8);
+        const int64_t pb = band + gv1 * ((int64_t)hw_word(rec, o2 + 4) -
+                                         (share_comps ? 0 : (int64_t)hw_word(rec, o1 + 4)));
+        const u32* blk = H + pb + (int64_t)hw_word(rec, o1 + 7) * hw_word(rec, o2 + 8) +
+                         (int64_t)nb1 * hw_word(rec, o2 + 7);
+        const int64_t ld = nb2;
+        const bool same = hw_word(rec, 2) == hw_word(rec, VREC_WORDS + 2);
+        const u32 loc2 = hw_word(rec, o2 + 3);
+        u32 best = INF;
+        for (int32_t c0 = 0; c0 < nb2; c0 += 128) {
+          const int32_t nbc = min(128, nb2 - c0);
+          const int L = (nbc + 3) >> 2, R = 32 / L;
+          const int r = l / L, col = c0 + (l - r * L) * 4;
+          const bool lane_on = r < R;
+          const int cvalid = c0 + nbc - col;  // columns of this lane's piece (>= 1 when on)
+          // second-stage terms first: independent of the block
+          u32 e[4];
 #pragma unroll
-    for (int j = 0; j < 4; j++) e[j] = (lane_on && j < cvalid) ? row2[col + j] : INF;
-    u32 t[4] = {INF, INF, INF, INF};
-    for (int32_t r0 = 0; r0 < nb1; r0 += R * QU) {
-      uint4 v[QU];
-      u32 d[QU];
+          for (int j = 0; j < 4; j++) e[j] = (lane_on && j < cvalid) ? row2[col + j] : INF;
+          u32 t[4] = {INF, INF, INF, INF};
+          for (int32_t r0 = 0; r0 < nb1; r0 += R * QU) {
+            uint4 v[QU];
+            u32 d[QU];
 #pragma unroll
-      for (int u = 0; u < QU; u++) {
-        const int32_t row = r0 + u * R + r;
-        const bool on = lane_on && row < nb1;
-        v[u] = on ? load4_upto(blk + (int64_t)row * ld + col, cvalid) : make_uint4(INF, INF, INF, INF);
-        d[u] = on ? row1[row] : INF;
-      }
+            for (int u = 0; u < QU; u++) {
+              const int32_t row = r0 + u * R + r;
+              const bool on = lane_on && row < nb1;
+              v[u] = on ? load4_upto(blk + (int64_t)row * ld + col, cvalid)
+                        : make_uint4(INF, INF, INF, INF);
+              d[u] = on ? row1[row] : INF;
+            }
 #pragma unroll
-      for (int u = 0; u < QU; u++) {
-        t[0] = min(t[0], d[u] + v[u].x);
-        t[1] = min(t[1], d[u] + v[u].y);
-        t[2] = min(t[2], d[u] + v[u].z);
-        t[3] = min(t[3], d[u] + v[u].w);
+            for (int u = 0; u < QU; u++) {
+              t[0] = min(t[0], d[u] + v[u].x);
+              t[1] = min(t[1], d[u] + v[u].y);
+              t[2] = min(t[2], d[u] + v[u].z);
+              t[3] = min(t[3], d[u] + v[u].w);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 4; j++) best = min(best, min(t[j], INF) + e[j]);
+        }
+        for (int o = 16; o > 0; o >>= 1) best = min(best, (u32)__shfl_xor((int)best, o));
+        if (same) best = min(best, row1[loc2]);
+        res = min(best, INF);
       }
     }
-#pragma unroll
-    for (int j = 0; j < 4; j++) best = min(best, min(t[j], INF) + e[j]);
-  }
-  for (int o = 16; o > 0; o >>= 1) best = min(best, (u32)__shfl_xor((int)best, o));
-  if (l == 0) {
-    if (ra.z == rb.z) best = min(best, row1[rb.w]);
-    out[qi] = (int32_t)min(best, INF);
+    if (l == 0) out[qi] = (int32_t)res;
   }
 }
 
@@ -419,7 +449,7 @@ hipError_t launch_renumber(const PartArgs& a, hipStream_t s) {
   k_rank<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.k, a.members, a.off, a.nb, a.bgoff, a.comp, a.local,
                                          a.bgcomp, a.bglocal, a.bgvert);
   k_vrec<<<blocks_for(a.n), 256, 0, s>>>(a.n, a.comp, a.local, a.moff, a.P, a.bgoff, a.nb, a.grp,
-                                         a.gbg0, a.vrec);
+                                         a.gbg0, a.gV, a.gT, a.vrec);
   LAUNCH_CHECK();
 }
 
@@ -453,9 +483,9 @@ hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s) {
 
 hipError_t launch_query(const QueryArgs& a, hipStream_t s) {
   if (a.q <= 0) return hipSuccess;
-  int64_t blocks = (a.q + 7) / 8;
+  const int64_t blocks = (a.q + 7) / 8;  // 8 pairs per workgroup
   k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.vrec, a.M, a.H,
-                                           a.pairbase, a.gV, a.ngroups, a.V, a.share_comps);
+                                           a.share_comps);
   LAUNCH_CHECK();
 }
 

@@ -36,8 +36,16 @@ struct PartArgs {
   const int64_t* moff;        // [k] first element of each APSP(C)
   const int32_t* P;           // [k] padded side of each APSP(C)
   const int32_t *grp, *gbg0;  // [k] group of each component, [groups] its first BG id
-  uint4* vrec;                // [2n] per-vertex query records
+  const int32_t* gV;          // [groups] BG vertices of each group
+  const int64_t* gT;          // [groups] first element of the group's band in the blocked store
+  u32* vrec;                  // [VREC_WORDS n] per-vertex query records
 };
+// Per-vertex query record (48 bytes):
+//   0 1  first element of the vertex's APSP(C) row    2 component   3 local index
+//   4    first BG id of the group                     5 |B(C)|      6 group
+//   7    first BG id of the component inside its group
+//   8    BG vertices of the group   9 unused   10 11 first element of the group's band
+constexpr int VREC_WORDS = 12;
 
 struct CompArgs {
   int32_t k;
@@ -61,14 +69,9 @@ struct QueryArgs {
   const int32_t *v1, *v2;
   int32_t* out;
   int32_t n;
-  const uint4* vrec;
+  const u32* vrec;
   const u32* M;
-  // blocked BG store (both methods): pair offsets and group sizes; with one
-  // group (the flat method) pairbase[0] = 0 and gV[0] = V
-  const u32* H;
-  const int64_t* pairbase;
-  const int32_t* gV;
-  int32_t ngroups, V;
+  const u32* H;  // blocked BG store (both methods)
   int32_t share_comps;  // > 0: only sources v1 in components [0, share_comps)
 };
 
