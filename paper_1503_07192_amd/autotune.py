@@ -5,7 +5,7 @@ workload itself and the fastest set is stored in a JSON cache keyed by the
 device architecture and a size class of the problem:
 
 * flat Floyd-Warshall on BG: tile side (64, 128) x interior K chunk (16, 32);
-* two-level BG: consecutive components per group (16 .. 256) x K chunk.
+* two-level BG: consecutive components per group (8 .. 256) x K chunk.
   Groups formed by size (``group_bg``) are not tried: on partitions numbered
   by recursive bisection or super-blocks they cut across the aligned runs of
   2^j components that make a group compact, and measured 1.5-10x slower.
@@ -52,7 +52,7 @@ def candidates(v_bg: int, k: int, share_comps: int):
         for tile in (128, 64):
             for kc in (16, 32):
                 out.append({"bg_method": 1, "bg_tile": tile, "inner_kc": kc})
-    cpg = 16
+    cpg = 8
     while cpg <= min(256, k):
         for kc in (16, 32):
             out.append({"bg_method": 2, "group_comps": cpg, "inner_kc": kc})

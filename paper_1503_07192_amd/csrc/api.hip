@@ -149,6 +149,9 @@ struct spq_index {
   int32_t *tbase = nullptr, *tsize = nullptr, *b3list = nullptr, *b3rank = nullptr, *m3 = nullptr;
   int32_t* b3off = nullptr;
   uint8_t* flag3 = nullptr;
+  // composition pair lists (level 2 or share, level 3)
+  int2 *plist = nullptr, *plist3 = nullptr;
+  int32_t npairs = 0, chunk = 0;
   u32 *M3 = nullptr, *R3 = nullptr, *XT3 = nullptr, *BG3 = nullptr;
   // share mode
   int32_t share_comps = 0, share_groups = 0, S2 = 0, bf_rounds = 0;
@@ -199,7 +202,7 @@ struct spq_index {
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
                     bgvert, label, bglabel, cert, A,    DT,    bfflag,  xe, xcount,
                     eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
-                    M3, R3, XT3, BG3};
+                    M3, R3, XT3, BG3, plist, plist3};
     for (void* p : ptrs) pool_release(p);
   }
 };
@@ -228,6 +231,23 @@ static hipError_t graph_segment(spq_index* X, hipStream_t s, F&& body) {
   if (e != hipSuccess) return e;
   X->execs.push_back(x);
   return hipGraphLaunch(x, s);
+}
+
+// Pair list of a composition (rows groups [0, rows) against groups [first,
+// G), first = the row group itself when `upper`), uploaded to *dev, and the
+// pairs per launch: the XT buffer holds one m x Vgp slot per pair of a
+// launch, at most 4 GiB, at least one slot.
+static hipError_t make_pairs(int32_t rows, int32_t G, bool upper, int64_t slot_elems, int2** dev,
+                             int32_t* npairs, int32_t* chunk, hipStream_t s) {
+  std::vector<int2> h;
+  for (int32_t a1 = 0; a1 < rows; a1++)
+    for (int32_t a2 = upper ? a1 : 0; a2 < G; a2++) h.push_back(make_int2(a1, a2));
+  *npairs = (int32_t)h.size();
+  const int64_t fit = ((int64_t)1 << 30) / std::max<int64_t>(slot_elems, 1);
+  *chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(*npairs, fit));
+  hipError_t e = dalloc(dev, std::max<int64_t>(*npairs, 1));
+  if (e != hipSuccess || h.empty()) return e;
+  return hipMemcpyAsync(*dev, h.data(), sizeof(int2) * h.size(), hipMemcpyHostToDevice, s);
 }
 
 // The query kernel locates a pair block from the two vertex records alone:
@@ -265,7 +285,9 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   X->V2p = V2p;
   HIP_TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
   HIP_TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
-  HIP_TRY(dalloc(&X->XT, (int64_t)G * X->m2pmax * Vgp));
+  HIP_TRY(make_pairs(X->share_groups, G, false, (int64_t)X->m2pmax * Vgp, &X->plist, &X->npairs,
+                     &X->chunk, s));
+  HIP_TRY(dalloc(&X->XT, (int64_t)X->chunk * X->m2pmax * Vgp));
   HIP_TRY(dalloc(&X->A, (int64_t)G * X->m2pmax * X->m2pmax));
   // the Bellman-Ford matrix carries 128 spare rows: a row tile may start at
   // the last group's last level-2 id
@@ -285,6 +307,7 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
                          hipMemcpyHostToDevice, s));
   ha.m2pmax = X->m2pmax; ha.V2 = X->V2; ha.V2p = V2p; ha.b2off = X->b2off; ha.R = X->R;
   ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
+  ha.plist = X->plist; ha.npairs = X->npairs; ha.chunk = X->chunk;
   ha.share_groups = X->share_groups; ha.S2 = X->S2; ha.S2p = X->S2p; ha.A = X->A; ha.DT = X->DT;
   ha.xe = X->xe; ha.xcount = X->xcount;
   HIP_TRY(spq::launch_share_prepare(ha, s));
@@ -324,9 +347,9 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
       X->relax_bg_exec += y;
       X->relax_inner += y;
     }
-  X->inner_launches = X->share_groups;
+  X->inner_launches = (X->npairs + X->chunk - 1) / X->chunk;
   if (profile) {
-    X->prof.resize(2 * X->share_groups);
+    X->prof.resize(2 * X->inner_launches);
     for (auto& e : X->prof) HIP_TRY(hipEventCreate(&e));
     ha.evt = X->prof.data();
   }
@@ -784,15 +807,16 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       for (int32_t a2 = a1; a2 < G; a2++)
         X->relax_inner += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
                           128.0 * (double)round_up(X->h_m2[a2], 16);
-    X->inner_launches = G;
+    TRY(make_pairs(G, G, true, (int64_t)X->m2pmax * Vgp, &X->plist, &X->npairs, &X->chunk, s));
+    X->inner_launches = (X->npairs + X->chunk - 1) / X->chunk;
     if (profile) {
-      X->prof.resize(2 * G);
+      X->prof.resize(2 * X->inner_launches);
       for (auto& e : X->prof) TRY(hipEventCreate(&e));
       ha.evt = X->prof.data();
     }
     TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
     TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
-    TRY(dalloc(&X->XT, (int64_t)G * X->m2pmax * Vgp));
+    TRY(dalloc(&X->XT, (int64_t)X->chunk * X->m2pmax * Vgp));
     if (X->V2p > 0) TRY(dalloc(&X->BG2, X->V2p * X->V2p));
     TRY(dalloc(&X->H, X->h_elems));
     TRY(dalloc(&X->pairbase, (int64_t)G * G));
@@ -800,6 +824,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
                        hipMemcpyHostToDevice, s));
     ha.m2pmax = X->m2pmax; ha.V2 = X->V2; ha.V2p = X->V2p; ha.b2off = X->b2off; ha.R = X->R;
     ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
+    ha.plist = X->plist; ha.npairs = X->npairs; ha.chunk = X->chunk;
     if (X->certify) {
       ha.bglabel = X->bglabel;
       ha.cert_bad = X->cert + 1;
@@ -866,7 +891,10 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       TRY(hipMemcpyAsync(X->b3off, X->h_b3off.data(), sizeof(int32_t) * (nT + 1),
                          hipMemcpyHostToDevice, s));
       TRY(dalloc(&X->R3, (int64_t)nT * X->m3pmax * V3gp));
-      TRY(dalloc(&X->XT3, (int64_t)nT * X->m3pmax * V3gp));
+      int32_t np3 = 0, ch3 = 0;
+      TRY(make_pairs(nT, nT, true, (int64_t)X->m3pmax * V3gp, &X->plist3, &np3, &ch3, s));
+      TRY(dalloc(&X->XT3, (int64_t)ch3 * X->m3pmax * V3gp));
+      la.plist = X->plist3; la.npairs = np3; la.chunk = ch3;
       if (X->V3p > 0) TRY(dalloc(&X->BG3, X->V3p * X->V3p));
       la.V3 = X->V3; la.V3p = X->V3p; la.m3pmax = X->m3pmax; la.b3off = X->b3off; la.R3 = X->R3;
       la.XT3 = X->XT3; la.BG3 = X->BG3;

@@ -288,13 +288,18 @@ __device__ __forceinline__ void fill_inf(u32 (&c)[8][8]) {
     for (int j = 0; j < 8; j++) c[i][j] = INF;
 }
 
-// XT[S2] (m2pmax x Vgp, rows b in B2(S2), columns x of S1) =
-//   min over a in B2(S1) of D2[a][b] + R_S1[a][x],   for S2 = s2base + blockIdx.y.
+// The composition runs over a list of group pairs (S1, S2), a chunk of it per
+// launch: blockIdx.y = pair plist[pbase + blockIdx.y], whose XT takes slot
+// blockIdx.y of the XT buffer (one slot per pair of the chunk).
+//
+// XT (m2pmax x Vgp, rows b in B2(S2), columns x of S1) =
+//   min over a in B2(S1) of D2[a][b] + R_S1[a][x].
 // D2 rows are level-2 ids of the sources (all of BG2, or the share's rows).
 // Rows b in [m2[S2], round16(m2[S2])) are stored as INF.  The composition
 // reads rows below round16(m2[S2]) and column tiles below gV[S1] only, so
 // tiles past those are neither computed nor written.
-__global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t s2base, int32_t Vgp, int32_t m2pmax,
+__global__ __launch_bounds__(256) void k_mp_xt(const int2* __restrict__ plist, int32_t pbase,
+                                               int32_t Vgp, int32_t m2pmax,
                                                const int32_t* __restrict__ m2,
                                                const int32_t* __restrict__ gV,
                                                const int32_t* __restrict__ b2off,
@@ -302,7 +307,9 @@ __global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t s2base, int32
                                                const u32* __restrict__ R, u32* __restrict__ XT) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
-  const int32_t s2 = s2base + (int32_t)blockIdx.y;
+  const int2 pr = plist[pbase + (int32_t)blockIdx.y];
+  const int32_t s1 = pr.x, s2 = pr.y;
+  const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
   const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
   const int32_t ka = m2[s1], mb = m2[s2];
@@ -314,7 +321,7 @@ __global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t s2base, int32
     const u32* B = R + (int64_t)s1 * m2pmax * Vgp + tj * 128;
     mp_stream128<true>(c, At, V2p, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB);
   }
-  u32* out = XT + ((int64_t)s2 * m2pmax + ti * 128) * Vgp + tj * 128;
+  u32* out = XT + (slot * m2pmax + ti * 128) * Vgp + tj * 128;
   const int tx = tid_x(), ty = tid_y();
 #pragma unroll
   for (int h = 0; h < 2; h++)
@@ -332,10 +339,11 @@ __global__ __launch_bounds__(256) void k_mp_xt(int32_t s1, int32_t s2base, int32
     }
 }
 
-// D(S1,S2) tile (rows x of S1, columns y of S2) for S2 = s2base + blockIdx.y:
-//   min over b in B2(S2) of XT[S2][b][x] + R_S2[b][y], and d_S1 when S1 = S2;
+// D(S1,S2) tile (rows x of S1, columns y of S2) for the pair of blockIdx.y:
+//   min over b in B2(S2) of XT[b][x] + R_S2[b][y], and d_S1 when S1 = S2;
 // stored in the component-pair layout described at the top of the file.
-__global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t s2base, int32_t ngroups, int32_t Vgp,
+__global__ __launch_bounds__(256) void k_mp_y(const int2* __restrict__ plist, int32_t pbase,
+                                              int32_t ngroups, int32_t Vgp,
                                               int32_t m2pmax,
                                               const int32_t* __restrict__ m2,
                                               const int32_t* __restrict__ gV,
@@ -350,7 +358,9 @@ __global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t s2base, int32_
                                               u32* __restrict__ cert_bad, u32* __restrict__ cert_mbg) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
-  const int32_t s2 = s2base + (int32_t)blockIdx.y;
+  const int2 pr = plist[pbase + (int32_t)blockIdx.y];
+  const int32_t s1 = pr.x, s2 = pr.y;
+  const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
   const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
   const int32_t V1 = gV[s1], V2 = gV[s2];
@@ -361,7 +371,7 @@ __global__ __launch_bounds__(256) void k_mp_y(int32_t s1, int32_t s2base, int32_
   else
     fill_inf(c);
   const int32_t kb = m2[s2];
-  const u32* At = XT + (int64_t)s2 * m2pmax * Vgp + ti * 128;
+  const u32* At = XT + slot * m2pmax * Vgp + ti * 128;
   const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
   mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB);
   u32* base = H + pairbase[(int64_t)s1 * ngroups + s2];
@@ -482,11 +492,12 @@ __global__ void k_l3_edges(int64_t m, const int32_t* __restrict__ eu, const int3
   }
 }
 
-// d_BG2 tile for super-groups (T1, T2 = s2base + blockIdx.y), rows x of T1,
-// columns y of T2: min over b in B3(T2) of XT[T2][b][x] + R_T2[b][y], and d_T1
+// d_BG2 tile for the super-group pair (T1, T2) of blockIdx.y, rows x of T1,
+// columns y of T2: min over b in B3(T2) of XT[b][x] + R_T2[b][y], and d_T1
 // when T1 = T2; stored densely (row gbase[T1] + x, column gbase[T2] + y of
 // out, leading dimension ldo).
-__global__ __launch_bounds__(256) void k_mp_y_dense(int32_t s1, int32_t s2base, int32_t Vgp,
+__global__ __launch_bounds__(256) void k_mp_y_dense(const int2* __restrict__ plist, int32_t pbase,
+                                                    int32_t Vgp,
                                                     int32_t m2pmax, const int32_t* __restrict__ m2,
                                                     const int32_t* __restrict__ gV,
                                                     const int32_t* __restrict__ gbase,
@@ -495,7 +506,9 @@ __global__ __launch_bounds__(256) void k_mp_y_dense(int32_t s1, int32_t s2base, 
                                                     int64_t ldo) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
-  const int32_t s2 = s2base + (int32_t)blockIdx.y;
+  const int2 pr = plist[pbase + (int32_t)blockIdx.y];
+  const int32_t s1 = pr.x, s2 = pr.y;
+  const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
   const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
   const int32_t V1 = gV[s1], V2 = gV[s2];
@@ -506,7 +519,7 @@ __global__ __launch_bounds__(256) void k_mp_y_dense(int32_t s1, int32_t s2base, 
   else
     fill_inf(c);
   const int32_t kb = m2[s2];
-  const u32* At = XT + (int64_t)s2 * m2pmax * Vgp + ti * 128;
+  const u32* At = XT + slot * m2pmax * Vgp + ti * 128;
   const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
   mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB);
   const int tx = tid_x(), ty = tid_y();
@@ -745,26 +758,34 @@ hipError_t launch_hier_level2_close(const HierArgs& a, hipStream_t s) {
   return launch_dense_fw(a.BG2, a.V2p, 128, (int)(a.V2p / 128), s, nullptr, a.kc);
 }
 
-hipError_t launch_hier_level2_compose(const HierArgs& a, hipStream_t s) {
+// Composition over the pair list a.plist (a.npairs pairs), a.chunk pairs per
+// launch of each product.  evt (optional) gets a pair of events around every
+// k_mp_y launch.  The share's BG2 rows come from its Bellman-Ford (DT^T).
+static hipError_t compose_level2(const HierArgs& a, const int32_t* bglabel, u32* cert_bad,
+                                 u32* cert_mbg, hipStream_t s) {
   const int ntx = a.Vgp / 128, ntm = a.m2pmax / 128;
-  for (int32_t s1 = 0; s1 < a.ngroups; s1++) {
-    const unsigned pairs = (unsigned)(a.ngroups - s1);
+  for (int32_t p0 = 0, c = 0; p0 < a.npairs; p0 += a.chunk, c++) {
+    const unsigned np = (unsigned)min(a.chunk, a.npairs - p0);
     if (a.V2p > 0)
-      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(s1, s1, a.Vgp, a.m2pmax, a.m2, a.gV,
-                                                                 a.b2off, a.BG2, a.V2p, a.R, a.XT);
+      k_mp_xt<<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(a.plist, p0, a.Vgp, a.m2pmax, a.m2, a.gV,
+                                                              a.b2off, a.BG2, a.V2p, a.R, a.XT);
     if (a.evt) {
-      hipError_t e = hipEventRecord(a.evt[2 * s1], s);
+      hipError_t e = hipEventRecord(a.evt[2 * c], s);
       if (e != hipSuccess) return e;
     }
-    k_mp_y<<<dim3((unsigned)(ntx * ntx), pairs), 256, 0, s>>>(
-        s1, s1, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
-        a.bgnb, a.bglocal, a.H, a.bglabel, a.cert_bad, a.cert_mbg);
+    k_mp_y<<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
+        a.plist, p0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase,
+        a.bgrow, a.bgnb, a.bglocal, a.H, bglabel, cert_bad, cert_mbg);
     if (a.evt) {
-      hipError_t e = hipEventRecord(a.evt[2 * s1 + 1], s);
+      hipError_t e = hipEventRecord(a.evt[2 * c + 1], s);
       if (e != hipSuccess) return e;
     }
   }
   return hipGetLastError();
+}
+
+hipError_t launch_hier_level2_compose(const HierArgs& a, hipStream_t s) {
+  return compose_level2(a, a.bglabel, a.cert_bad, a.cert_mbg, s);
 }
 
 hipError_t launch_flat_store(int32_t V, int64_t Vp, const u32* BG, const int32_t* bgcomp,
@@ -805,14 +826,14 @@ hipError_t launch_level3_b(const L3Args& a, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   const int ntx = a.V3gp / 128, ntm = a.m3pmax / 128;
-  for (int32_t t1 = 0; t1 < a.nT; t1++) {
-    const unsigned pairs = (unsigned)(a.nT - t1);
+  for (int32_t p0 = 0; p0 < a.npairs; p0 += a.chunk) {
+    const unsigned np = (unsigned)min(a.chunk, a.npairs - p0);
     if (a.V3p > 0)
-      k_mp_xt<<<dim3((unsigned)(ntm * ntx), pairs), 256, 0, s>>>(t1, t1, a.V3gp, a.m3pmax, a.m3,
-                                                                 a.tsize, a.b3off, a.BG3, a.V3p, a.R3,
-                                                                 a.XT3);
-    k_mp_y_dense<<<dim3((unsigned)(ntx * ntx), pairs), 256, 0, s>>>(
-        t1, t1, a.V3gp, a.m3pmax, a.m3, a.tsize, a.tbase, a.XT3, a.R3, a.M3, a.BG2, a.V2p);
+      k_mp_xt<<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(a.plist, p0, a.V3gp, a.m3pmax, a.m3,
+                                                              a.tsize, a.b3off, a.BG3, a.V3p, a.R3,
+                                                              a.XT3);
+    k_mp_y_dense<<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
+        a.plist, p0, a.V3gp, a.m3pmax, a.m3, a.tsize, a.tbase, a.XT3, a.R3, a.M3, a.BG2, a.V2p);
   }
   return hipGetLastError();
 }
@@ -855,23 +876,9 @@ hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const u32* dirty, 
 hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s) {
   dim3 tg((unsigned)((a.S2p + 31) / 32), (unsigned)((a.V2p + 31) / 32));
   k_transpose<<<tg, 256, 0, s>>>(DT, a.V2p, a.S2p, a.S2p, a.BG2, a.V2p);
-  const int ntx = a.Vgp / 128, ntm = a.m2pmax / 128;
-  for (int32_t s1 = 0; s1 < a.share_groups; s1++) {
-    k_mp_xt<<<dim3((unsigned)(ntm * ntx), (unsigned)a.ngroups), 256, 0, s>>>(
-        s1, 0, a.Vgp, a.m2pmax, a.m2, a.gV, a.b2off, a.BG2, a.V2p, a.R, a.XT);
-    if (a.evt) {
-      hipError_t e = hipEventRecord(a.evt[2 * s1], s);
-      if (e != hipSuccess) return e;
-    }
-    k_mp_y<<<dim3((unsigned)(ntx * ntx), (unsigned)a.ngroups), 256, 0, s>>>(
-        s1, 0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase, a.bgrow,
-        a.bgnb, a.bglocal, a.H, nullptr, nullptr, nullptr);
-    if (a.evt) {
-      hipError_t e = hipEventRecord(a.evt[2 * s1 + 1], s);
-      if (e != hipSuccess) return e;
-    }
-  }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return compose_level2(a, nullptr, nullptr, nullptr, s);
 }
 
 }  // namespace spq

@@ -96,6 +96,8 @@ struct HierArgs {
   u32 *A, *DT;                     // A_S blocks; Bellman-Ford distances (V2p + 128 rows x S2p)
   int4* xe;                        // directed cross edges
   int32_t* xcount;
+  const int2* plist;               // composition: group pairs (S1, S2)
+  int32_t npairs, chunk;           //   their count, pairs per launch (XT slots)
   hipEvent_t* evt;                 // NULL, or 2 per composition launch (k_mp_y)
   // exactness certificate fused into the composition (NULL: off)
   const int32_t* bglabel;
@@ -132,7 +134,10 @@ struct L3Args {
   uint8_t* flag3;                      // [V2]
   int32_t *b3list, *b3rank, *m3;       // nT x V3gp, [V2], [nT]
   const int32_t* b3off;                // [nT+1]
-  u32 *R3, *XT3, *BG3;                 // nT x m3pmax x V3gp (twice), V3p x V3p
+  u32 *R3, *BG3;                       // nT x m3pmax x V3gp, V3p x V3p
+  u32* XT3;                            // chunk x m3pmax x V3gp
+  const int2* plist;                   // super-group pairs T1 <= T2
+  int32_t npairs, chunk;               //   their count, pairs per launch
 };
 // super-group matrices, their closure, the level-3 boundary (m3)
 hipError_t launch_level3_a(const L3Args& a, hipStream_t s);
