@@ -111,6 +111,14 @@ def cpu_baseline(g, st, budget_s):
     res = {"value": relax_sample / t_comp, "unit": "relax/s", "cores": threads, "kind": "oracle",
            "sample": "Floyd-Warshall of %d of %d components (%.3g relaxations, %.2f s)"
                      % (len(comps), k, relax_sample, t_comp)}
+    # the same on one thread, an eighth of the sample
+    comps1 = comps[:max(1, len(comps) // 8)]
+    t0 = time.perf_counter()
+    members1, _ = oracle.component_apsp(n, g["eu"], g["ev"], g["w"], g["part"], k, comps=comps1,
+                                        nthreads=1)
+    t1 = time.perf_counter() - t0
+    res["value_1thread"] = float(sum(len(m) ** 3 for m in members1)) / t1
+    res["sample"] += "; one thread: %d components in %.2f s" % (len(comps1), t1)
     if k <= 1024:
         # the paper's Phase 3: Dijkstra in BG from a budgeted number of sources
         bg_ids, bverts, bu, bv, bw = oracle.boundary_graph(n, g["eu"], g["ev"], g["w"], g["part"],
