@@ -80,7 +80,8 @@ typedef struct {
                           BG2 vertices, by the same construction once more on
                           super-groups of consecutive groups (level 3).
                           0 auto (about 4,096 BG2 vertices per super-group),
-                          -1 never, g > 0 always, g groups per super-group */
+                          -1 never, g > 0 always, g groups per super-group.
+                          Share mode never builds BG2 and ignores it */
   int32_t group_bg;      /* two-level: > 0 forms the groups by size instead of
                           by count: consecutive components join a group while
                           it holds at most group_bg BG vertices (a larger
