@@ -281,6 +281,26 @@ __device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int6
   }
 }
 
+// c = min(c, the 128 x 128 tile at g), in the register layout of tile_load.
+__device__ __forceinline__ void tile_min128(u32 (&c)[8][8], const u32* __restrict__ g, int64_t ld) {
+  const int tx = tid_x(), ty = tid_y();
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const u32* row = g + (int64_t)(h * 64 + ty * 4 + a) * ld + tx * 4;
+#pragma unroll
+      for (int h2 = 0; h2 < 2; h2++) {
+        const uint4 v = *reinterpret_cast<const uint4*>(row + h2 * 64);
+        u32* r = c[h * 4 + a] + h2 * 4;
+        r[0] = min(r[0], v.x);
+        r[1] = min(r[1], v.y);
+        r[2] = min(r[2], v.z);
+        r[3] = min(r[3], v.w);
+      }
+    }
+}
+
 __device__ __forceinline__ void fill_inf(u32 (&c)[8][8]) {
 #pragma unroll
   for (int i = 0; i < 8; i++)
@@ -366,14 +386,15 @@ __global__ __launch_bounds__(256) void k_mp_y(const int2* __restrict__ plist, in
   const int32_t V1 = gV[s1], V2 = gV[s2];
   if (ti * 128 >= V1 || tj * 128 >= V2) return;
   u32 c[8][8];
-  if (s1 == s2)
-    tile_load<128>(c, Mg + (int64_t)s1 * Vgp * Vgp + (int64_t)ti * 128 * Vgp + tj * 128, Vgp);
-  else
-    fill_inf(c);
+  fill_inf(c);
   const int32_t kb = m2[s2];
   const u32* At = XT + slot * m2pmax * Vgp + ti * 128;
   const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
   mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB);
+  // the group's own closure when S1 = S2, folded in after the product: taken
+  // in first, it kept a second copy of the tile live through the K loop
+  if (s1 == s2)
+    tile_min128(c, Mg + (int64_t)s1 * Vgp * Vgp + (int64_t)ti * 128 * Vgp + tj * 128, Vgp);
   u32* base = H + pairbase[(int64_t)s1 * ngroups + s2];
   const int tx = tid_x(), ty = tid_y();
   const int32_t g1 = gbg0[s1], g2 = gbg0[s2];
@@ -514,14 +535,15 @@ __global__ __launch_bounds__(256) void k_mp_y_dense(const int2* __restrict__ pli
   const int32_t V1 = gV[s1], V2 = gV[s2];
   if (ti * 128 >= V1 || tj * 128 >= V2) return;
   u32 c[8][8];
-  if (s1 == s2)
-    tile_load<128>(c, Mg + (int64_t)s1 * Vgp * Vgp + (int64_t)ti * 128 * Vgp + tj * 128, Vgp);
-  else
-    fill_inf(c);
+  fill_inf(c);
   const int32_t kb = m2[s2];
   const u32* At = XT + slot * m2pmax * Vgp + ti * 128;
   const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
   mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB);
+  // the group's own closure when S1 = S2, folded in after the product: taken
+  // in first, it kept a second copy of the tile live through the K loop
+  if (s1 == s2)
+    tile_min128(c, Mg + (int64_t)s1 * Vgp * Vgp + (int64_t)ti * 128 * Vgp + tj * 128, Vgp);
   const int tx = tid_x(), ty = tid_y();
   const int64_t col0 = gbase[s2];
 #pragma unroll
