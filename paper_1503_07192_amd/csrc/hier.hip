@@ -281,6 +281,10 @@ __device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int6
   }
 }
 
+// The composition kernels fit in 128 VGPRs without spilling: four waves per
+// SIMD (four workgroups per CU) instead of two or three.
+#define SPQ_MP_ATTR __attribute__((amdgpu_waves_per_eu(4, 4)))
+
 // c = min(c, the 128 x 128 tile at g), in the register layout of tile_load.
 __device__ __forceinline__ void tile_min128(u32 (&c)[8][8], const u32* __restrict__ g, int64_t ld) {
   const int tx = tid_x(), ty = tid_y();
@@ -318,7 +322,7 @@ __device__ __forceinline__ void fill_inf(u32 (&c)[8][8]) {
 // Rows b in [m2[S2], round16(m2[S2])) are stored as INF.  The composition
 // reads rows below round16(m2[S2]) and column tiles below gV[S1] only, so
 // tiles past those are neither computed nor written.
-__global__ __launch_bounds__(256) void k_mp_xt(const int2* __restrict__ plist, int32_t pbase,
+__global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restrict__ plist, int32_t pbase,
                                                int32_t Vgp, int32_t m2pmax,
                                                const int32_t* __restrict__ m2,
                                                const int32_t* __restrict__ gV,
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(256) void k_mp_xt(const int2* __restrict__ plist, i
 // D(S1,S2) tile (rows x of S1, columns y of S2) for the pair of blockIdx.y:
 //   min over b in B2(S2) of XT[b][x] + R_S2[b][y], and d_S1 when S1 = S2;
 // stored in the component-pair layout described at the top of the file.
-__global__ __launch_bounds__(256) void k_mp_y(const int2* __restrict__ plist, int32_t pbase,
+__global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict__ plist, int32_t pbase,
                                               int32_t ngroups, int32_t Vgp,
                                               int32_t m2pmax,
                                               const int32_t* __restrict__ m2,
@@ -517,7 +521,7 @@ __global__ void k_l3_edges(int64_t m, const int32_t* __restrict__ eu, const int3
 // columns y of T2: min over b in B3(T2) of XT[b][x] + R_T2[b][y], and d_T1
 // when T1 = T2; stored densely (row gbase[T1] + x, column gbase[T2] + y of
 // out, leading dimension ldo).
-__global__ __launch_bounds__(256) void k_mp_y_dense(const int2* __restrict__ plist, int32_t pbase,
+__global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y_dense(const int2* __restrict__ plist, int32_t pbase,
                                                     int32_t Vgp,
                                                     int32_t m2pmax, const int32_t* __restrict__ m2,
                                                     const int32_t* __restrict__ gV,
