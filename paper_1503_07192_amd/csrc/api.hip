@@ -236,15 +236,23 @@ static hipError_t graph_segment(spq_index* X, hipStream_t s, F&& body) {
 // Pair list of a composition (rows groups [0, rows) against groups [first,
 // G), first = the row group itself when `upper`), uploaded to *dev, and the
 // pairs per launch: the XT buffer holds one m x Vgp slot per pair of a
-// launch, at most 4 GiB, at least one slot.
-static hipError_t make_pairs(int32_t rows, int32_t G, bool upper, int64_t slot_elems, int2** dev,
-                             int32_t* npairs, int32_t* chunk, hipStream_t s) {
+// launch, within 1/32 of the composition's output clamped to [256 MiB,
+// 4 GiB], at least one slot.
+static hipError_t make_pairs(int32_t rows, int32_t G, bool upper, int64_t slot_elems,
+                             int64_t out_elems, int2** dev, int32_t* npairs, int32_t* chunk,
+                             hipStream_t s) {
+  const int64_t count = upper ? (int64_t)rows * (2 * (int64_t)G - rows + 1) / 2 : (int64_t)rows * G;
+  if (count > 0x7fffffff) return hipErrorOutOfMemory;  // pair list beyond int32 indexing
   std::vector<int2> h;
+  h.reserve((size_t)count);
   for (int32_t a1 = 0; a1 < rows; a1++)
     for (int32_t a2 = upper ? a1 : 0; a2 < G; a2++) h.push_back(make_int2(a1, a2));
   *npairs = (int32_t)h.size();
-  const int64_t fit = ((int64_t)1 << 30) / std::max<int64_t>(slot_elems, 1);
-  *chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(*npairs, fit));
+  // pairs per launch: XT slots within 4 GiB, and the grid's y dimension
+  const int64_t budget = std::min<int64_t>((int64_t)1 << 30,
+                                           std::max<int64_t>((int64_t)1 << 26, out_elems / 32));
+  const int64_t fit = budget / std::max<int64_t>(slot_elems, 1);
+  *chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)*npairs, fit, 65535}));
   hipError_t e = dalloc(dev, std::max<int64_t>(*npairs, 1));
   if (e != hipSuccess || h.empty()) return e;
   return hipMemcpyAsync(*dev, h.data(), sizeof(int2) * h.size(), hipMemcpyHostToDevice, s);
@@ -285,7 +293,8 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   X->V2p = V2p;
   HIP_TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
   HIP_TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
-  HIP_TRY(make_pairs(X->share_groups, G, false, (int64_t)X->m2pmax * Vgp, &X->plist, &X->npairs,
+  HIP_TRY(make_pairs(X->share_groups, G, false, (int64_t)X->m2pmax * Vgp, X->h_elems, &X->plist,
+                     &X->npairs,
                      &X->chunk, s));
   HIP_TRY(dalloc(&X->XT, (int64_t)X->chunk * X->m2pmax * Vgp));
   HIP_TRY(dalloc(&X->A, (int64_t)G * X->m2pmax * X->m2pmax));
@@ -807,7 +816,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       for (int32_t a2 = a1; a2 < G; a2++)
         X->relax_inner += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
                           128.0 * (double)round_up(X->h_m2[a2], 16);
-    TRY(make_pairs(G, G, true, (int64_t)X->m2pmax * Vgp, &X->plist, &X->npairs, &X->chunk, s));
+    TRY(make_pairs(G, G, true, (int64_t)X->m2pmax * Vgp, X->h_elems, &X->plist, &X->npairs,
+                   &X->chunk, s));
     X->inner_launches = (X->npairs + X->chunk - 1) / X->chunk;
     if (profile) {
       X->prof.resize(2 * X->inner_launches);
@@ -892,7 +902,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
                          hipMemcpyHostToDevice, s));
       TRY(dalloc(&X->R3, (int64_t)nT * X->m3pmax * V3gp));
       int32_t np3 = 0, ch3 = 0;
-      TRY(make_pairs(nT, nT, true, (int64_t)X->m3pmax * V3gp, &X->plist3, &np3, &ch3, s));
+      TRY(make_pairs(nT, nT, true, (int64_t)X->m3pmax * V3gp, X->V2p * X->V2p / 2, &X->plist3,
+                     &np3, &ch3, s));
       TRY(dalloc(&X->XT3, (int64_t)ch3 * X->m3pmax * V3gp));
       la.plist = X->plist3; la.npairs = np3; la.chunk = ch3;
       if (X->V3p > 0) TRY(dalloc(&X->BG3, X->V3p * X->V3p));

@@ -423,6 +423,27 @@ def test_level3_small_graphs_all_pairs(g):
         check_queries(g, idx, v1, v2)
 
 
+def test_two_level_pair_list_in_several_launches():
+    # 400 groups of one component: 80,200 group pairs, so the composition
+    # runs over its pair list in several launches
+    rng = np.random.default_rng(12)
+    eu, ev, w = W.random_grid(rng, 40, 40, keep=0.9, diag=0.2)
+    part, k = W.block_partition(40, 40, 2, 2)
+    g = dict(name="pairs80k", n=1600, eu=eu, ev=ev, w=w, part=part, k=k)
+    flat = build(g, bg_method=1)
+    two = build(g, bg_method=2, group_comps=1, level3_groups=-1)
+    st = spq.index_stats(two)
+    assert st["ngroups"] == 400 and st["dominant_launches"] >= 2
+    V = st["v_bg"]
+    rows = np.random.default_rng(3).integers(0, V, 25)
+    for r in rows:
+        assert np.array_equal(spq.index_bg_rows(flat, int(r), 1, V), spq.index_bg_rows(two, int(r), 1, V))
+    v1, v2 = all_pairs(g["n"])
+    sel = np.random.default_rng(4).integers(0, len(v1), 200_000)
+    assert np.array_equal(run_queries(flat, v1[sel], v2[sel]), run_queries(two, v1[sel], v2[sel]))
+    check_queries(g, two, v1[sel[:3000]], v2[sel[:3000]])
+
+
 def test_grid256d_two_level_equals_flat():
     g = W.grid256d()
     flat = build(g, bg_method=1)
