@@ -277,7 +277,8 @@ static bool bands_match(const spq_index* X, int32_t row_groups, bool share) {
 static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool profile,
                               hipStream_t s) {
   const int32_t G = X->ngroups, Vgp = X->Vgp;
-  if (G > 65535) return fail(SPQ_EINVAL, "share mode supports at most 65,535 groups");
+  if (((int64_t)std::max<int64_t>(X->V2p, 128) + 31) / 32 > 65535)
+    return fail(SPQ_EINVAL, "share mode supports at most 2,097,120 level-2 vertices");
   X->share_groups = X->h_grp[X->share_comps - 1] + 1;
   X->S2 = X->h_b2off[X->share_groups];
   X->S2p = round_up(std::max<int32_t>(X->S2, 1), 128);
@@ -597,6 +598,10 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   }
   X->ngroups = (int32_t)gstart.size();
   gstart.push_back(k);
+  // group pairs index launch grids (up to ngroups^2 workgroups per launch of
+  // the certificate check, ngroups along a grid's y dimension elsewhere)
+  if (X->ngroups > 32768)
+    return guard(fail(SPQ_EINVAL, "more than 32,768 groups: raise group_comps or group_bg"));
   X->cpg = cpg;
   X->h_grp.resize(k);
   X->h_gbg0.resize(X->ngroups);
