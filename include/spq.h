@@ -123,7 +123,8 @@ typedef struct {
   float ms_partition;      /* device time: boundary, renumbering (through the host plan) */
   float ms_components;     /* device time: APSP(C) initialisation + Floyd-Warshall */
   float ms_bg_assembly;    /* device time: BG matrix assembly */
-  float ms_bg_apsp;        /* device time: Floyd-Warshall in BG.  With SPQ_GRAPH
+  float ms_bg_apsp;        /* device time: the BG closure (flat rounds, or every
+                              level of the two-level method).  With SPQ_GRAPH
                               the phases run as one graph: ms_components and
                               ms_bg_assembly are 0 and ms_bg_apsp covers
                               Phases 2 and 3 */
@@ -156,7 +157,8 @@ typedef struct {
  * and the remaining distances composed as in Algorithm 2 one level up.  Both
  * give the same distances.  The distances are then kept in a blocked store
  * where each B(C1) x B(C2) block is one contiguous run (what a query reads).
- * Errors: SPQ_EINVAL (bad id, weight or part, empty component, k < 1),
+ * Errors: SPQ_EINVAL (bad id, weight or part, empty component, k < 1, bad
+ * option, more than 32,768 groups),
  * SPQ_ERANGE (the total edge weight reaches SPQ_INF, so a distance might not
  * fit), SPQ_ENOMEM, SPQ_EDEVICE.
  */
