@@ -159,8 +159,11 @@ typedef struct {
  * where each B(C1) x B(C2) block is one contiguous run (what a query reads).
  * Errors: SPQ_EINVAL (bad id, weight or part, empty component, k < 1, bad
  * option, more than 32,768 groups),
- * SPQ_ERANGE (the total edge weight reaches SPQ_INF, so a distance might not
- * fit), SPQ_ENOMEM, SPQ_EDEVICE.
+ * SPQ_ERANGE (a distance might not fit below SPQ_INF: when the total edge
+ * weight reaches SPQ_INF the build proves its result instead of assuming it
+ * (every component's weight below SPQ_INF, no BG distance lost between
+ * connected vertices, no query sum reaching SPQ_INF) and fails if it cannot;
+ * a share build needs the total below SPQ_INF), SPQ_ENOMEM, SPQ_EDEVICE.
  */
 spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
                            const int32_t* w, const int32_t* part, int32_t k,
