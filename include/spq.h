@@ -74,7 +74,9 @@ typedef struct {
                           captured into HIP graphs, launched, and kept in the
                           index for spq_reweight_index; the index keeps
                           device copies of eu, ev, w (12 bytes per edge).
-                          Not with share_comps or profile */
+                          Not with share_comps or profile.
+                          SPQ_PATHS: keep the graph's adjacency (20 bytes per
+                          edge) for spq_query_paths */
   int32_t level3_groups; /* two-level: BG2 (the graph of the group boundaries)
                           is closed by flat Floyd-Warshall, or, above 16,384
                           BG2 vertices, by the same construction once more on
@@ -91,6 +93,7 @@ typedef struct {
 
 #define SPQ_NO_LOOKAHEAD 1
 #define SPQ_GRAPH 2
+#define SPQ_PATHS 4
 
 typedef struct {
   int32_t n, k;            /* vertices, components */
@@ -214,6 +217,29 @@ spq_status spq_query_batch_host(const spq_index* idx, int64_t q, const int32_t* 
  * SPQ_EDEVICE.
  */
 spq_status spq_reweight_index(spq_index* idx, const int32_t* w, void* stream);
+
+/*
+ * Shortest paths (index built with SPQ_PATHS): for pair i, the vertices of one
+ * shortest path from v1[i] to v2[i], found by walking back from v2[i] over
+ * neighbours u with dist(v1, u) + w(u, c) = dist(v1, c), each distance an
+ * Algorithm 2 query on the index (no extra table per distance).
+ *   v1, v2     DEVICE arrays of q int32
+ *   max_len    room per path (>= 1)
+ *   paths      DEVICE array of q * max_len int32: path i in
+ *              paths[i * max_len .. i * max_len + lens[i]), from v1[i] to v2[i]
+ *   lens       DEVICE array of q int32: vertices on the path (>= 1; 1 when
+ *              v1 = v2), 0 no path, -1 bad pair (id outside [0, n), or v1
+ *              outside a share), -2 the walk needed more than max_len
+ *              vertices, -3 it found no way off a plateau of zero-weight edges
+ *              (it backs out of dead ends but remembers only the last 16; with
+ *              positive weights it never backs out)
+ * Where several shortest paths exist any one may be returned.  Asynchronous
+ * on `stream`.  Errors: SPQ_EINVAL (NULL index or array, q < 0, max_len < 1,
+ * index built without SPQ_PATHS), SPQ_ERANGE (invalidated index),
+ * SPQ_EDEVICE.
+ */
+spq_status spq_query_paths(const spq_index* idx, int64_t q, const int32_t* v1, const int32_t* v2,
+                           int32_t max_len, int32_t* paths, int32_t* lens, void* stream);
 
 /* Sizes, work counts and per-phase device times (waits for the build). */
 spq_status spq_index_stats(const spq_index* idx, spq_stats* st);

@@ -181,6 +181,13 @@ struct spq_index {
   int64_t graph_nodes = 0;
   int32_t reweights = 0;
   int32_t *eu_own = nullptr, *ev_own = nullptr, *w_own = nullptr;
+  // SPQ_PATHS: adjacency (rowptr[n+1], (neighbour, edge) pairs) and weights
+  bool paths = false;
+  int64_t* rowptr = nullptr;
+  int2* adj = nullptr;
+  unsigned long long* adeg = nullptr;
+  int32_t* w_copy = nullptr;        // own copy of the weights (without SPQ_GRAPH)
+  const int32_t* w_path = nullptr;  // the weights the walk reads (w_copy or w_own)
 
   ~spq_index() {
     if (events) {
@@ -202,7 +209,7 @@ struct spq_index {
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
                     bgvert, label, bglabel, cert, A,    DT,    bfflag,  xe, xcount,
                     eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
-                    M3, R3, XT3, BG3, plist, plist3};
+                    M3, R3, XT3, BG3, plist, plist3, rowptr, adj, adeg, w_copy};
     for (void* p : ptrs) pool_release(p);
   }
 };
@@ -433,7 +440,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   int tile = 128;
   bool profile = false, plain = false;
   int32_t method_opt = 0, group_comps = 0, share_comps = 0, inner_kc = 0;
-  bool lookahead = true, use_graph = false;
+  bool lookahead = true, use_graph = false, use_paths = false;
   int32_t level3_opt = 0, group_bg = 0;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
@@ -453,7 +460,9 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     inner_kc = opts->inner_kc;
     if (inner_kc != 0 && inner_kc != 16 && inner_kc != 32)
       return fail(SPQ_EINVAL, "inner_kc must be 0, 16 or 32");
-    if (opts->flags & ~(SPQ_NO_LOOKAHEAD | SPQ_GRAPH)) return fail(SPQ_EINVAL, "unknown flags");
+    if (opts->flags & ~(SPQ_NO_LOOKAHEAD | SPQ_GRAPH | SPQ_PATHS))
+      return fail(SPQ_EINVAL, "unknown flags");
+    use_paths = (opts->flags & SPQ_PATHS) != 0;
     lookahead = !(opts->flags & SPQ_NO_LOOKAHEAD);
     use_graph = (opts->flags & SPQ_GRAPH) != 0;
     level3_opt = opts->level3_groups;
@@ -685,6 +694,24 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     ev = X->ev_own;
     w = X->w_own;
     TRY(hipStreamCreateWithFlags(&X->cap, hipStreamNonBlocking));  // default priority
+  }
+
+  if (use_paths) {
+    // adjacency for the path walk; the weights it reads follow reweighting
+    if (m > 0x7fffffff) return guard(fail(SPQ_EINVAL, "SPQ_PATHS needs m < 2^31"));
+    X->paths = true;
+    TRY(dalloc(&X->rowptr, (int64_t)n + 1));
+    TRY(dalloc(&X->adj, 2 * m));
+    TRY(dalloc(&X->adeg, n));
+    TRY(hipMemsetAsync(X->adeg, 0, sizeof(unsigned long long) * n, s));
+    TRY(spq::launch_adjacency(n, m, eu, ev, X->adeg, X->rowptr, X->adj, s));
+    if (X->graph) {
+      X->w_path = X->w_own;
+    } else {
+      TRY(dalloc(&X->w_copy, m));
+      if (m > 0) TRY(hipMemcpyAsync(X->w_copy, w, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s));
+      X->w_path = X->w_copy;
+    }
   }
 
   // ---- renumbering (Section 4, Fig. 1)
@@ -1045,6 +1072,22 @@ spq_status spq_query_batch(const spq_index* X, int64_t q, const int32_t* v1, con
   a.q = q; a.v1 = v1; a.v2 = v2; a.out = out; a.n = X->n;
   a.vrec = X->vrec; a.M = X->M; a.H = X->H; a.share_comps = X->share_comps;
   HIP_TRY(spq::launch_query(a, reinterpret_cast<hipStream_t>(stream)));
+  return SPQ_OK;
+}
+
+spq_status spq_query_paths(const spq_index* X, int64_t q, const int32_t* v1, const int32_t* v2,
+                           int32_t max_len, int32_t* paths, int32_t* lens, void* stream) {
+  if (!X) return fail(SPQ_EINVAL, "index is NULL");
+  if (!X->paths) return fail(SPQ_EINVAL, "index was built without SPQ_PATHS");
+  if (!X->valid) return fail(SPQ_ERANGE, "index invalidated by a failed reweight");
+  if (q < 0 || max_len < 1) return fail(SPQ_EINVAL, "need q >= 0 and max_len >= 1");
+  if (q == 0) return SPQ_OK;
+  if (!v1 || !v2 || !paths || !lens) return fail(SPQ_EINVAL, "null array");
+  spq::QueryArgs a{};
+  a.q = q; a.v1 = v1; a.v2 = v2; a.n = X->n;
+  a.vrec = X->vrec; a.M = X->M; a.H = X->H; a.share_comps = X->share_comps;
+  HIP_TRY(spq::launch_paths(a, max_len, X->rowptr, X->adj, X->w_path, paths, lens,
+                            reinterpret_cast<hipStream_t>(stream)));
   return SPQ_OK;
 }
 

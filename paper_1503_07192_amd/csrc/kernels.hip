@@ -335,82 +335,252 @@ __device__ __forceinline__ u32 load_recs(u32 ids, int32_t n, const u32* vrec, in
   return vrec[(int64_t)v * VREC_WORDS + (l < VREC_WORDS ? l : l - VREC_WORDS)];
 }
 
+// dist(v1, v2) by one half-wave from the two records spread over lanes 0-23
+// (load_recs); every lane of the half-wave calls it with the same records and
+// gets the result.  0xffffffff (SPQ_BAD_PAIR) when v1 lies outside a share.
+__device__ __forceinline__ u32 hw_pair_dist(u32 rec, int l, const u32* __restrict__ M,
+                                            const u32* __restrict__ H, int32_t share_comps) {
+  constexpr int QU = SPQ_QUERY_UNROLL;
+  if (share_comps > 0 && (int32_t)hw_word(rec, 2) >= share_comps) return 0xffffffffu;
+  // the full two-level store keeps group pairs S1 <= S2 only; dist is
+  // symmetric, so take the endpoints in group order when needed (a share
+  // keeps all S2): words o1 + j describe the first, o2 + j the second
+  const bool sw = share_comps == 0 && hw_word(rec, 6) > hw_word(rec, VREC_WORDS + 6);
+  const int o1 = sw ? VREC_WORDS : 0, o2 = sw ? 0 : VREC_WORDS;
+  const u32* row1 = M + ((uint64_t)hw_word(rec, o1) | ((uint64_t)hw_word(rec, o1 + 1) << 32));
+  const u32* row2 = M + ((uint64_t)hw_word(rec, o2) | ((uint64_t)hw_word(rec, o2 + 1) << 32));
+  const int32_t nb1 = (int32_t)hw_word(rec, o1 + 5), nb2 = (int32_t)hw_word(rec, o2 + 5);
+  // band of group S1, then the pair block: S1's rows against the groups
+  // before S2 in the band (from S1 itself in the full store)
+  const int64_t band = (int64_t)((uint64_t)hw_word(rec, o1 + 10) |
+                                 ((uint64_t)hw_word(rec, o1 + 11) << 32));
+  const int64_t gv1 = hw_word(rec, o1 + 8);
+  const int64_t pb = band + gv1 * ((int64_t)hw_word(rec, o2 + 4) -
+                                   (share_comps ? 0 : (int64_t)hw_word(rec, o1 + 4)));
+  const u32* blk = H + pb + (int64_t)hw_word(rec, o1 + 7) * hw_word(rec, o2 + 8) +
+                   (int64_t)nb1 * hw_word(rec, o2 + 7);
+  const int64_t ld = nb2;
+  const bool same = hw_word(rec, 2) == hw_word(rec, VREC_WORDS + 2);
+  const u32 loc2 = hw_word(rec, o2 + 3);
+  u32 best = INF;
+  for (int32_t c0 = 0; c0 < nb2; c0 += 128) {
+    const int32_t nbc = min(128, nb2 - c0);
+    const int L = (nbc + 3) >> 2, R = 32 / L;
+    const int r = l / L, col = c0 + (l - r * L) * 4;
+    const bool lane_on = r < R;
+    const int cvalid = c0 + nbc - col;  // columns of this lane's piece (>= 1 when on)
+    // second-stage terms first: independent of the block
+    u32 e[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) e[j] = (lane_on && j < cvalid) ? row2[col + j] : INF;
+    u32 t[4] = {INF, INF, INF, INF};
+    for (int32_t r0 = 0; r0 < nb1; r0 += R * QU) {
+      uint4 v[QU];
+      u32 d[QU];
+#pragma unroll
+      for (int u = 0; u < QU; u++) {
+        const int32_t row = r0 + u * R + r;
+        const bool on = lane_on && row < nb1;
+        v[u] = on ? load4_upto(blk + (int64_t)row * ld + col, cvalid) : make_uint4(INF, INF, INF, INF);
+        d[u] = on ? row1[row] : INF;
+      }
+#pragma unroll
+      for (int u = 0; u < QU; u++) {
+        t[0] = min(t[0], d[u] + v[u].x);
+        t[1] = min(t[1], d[u] + v[u].y);
+        t[2] = min(t[2], d[u] + v[u].z);
+        t[3] = min(t[3], d[u] + v[u].w);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) best = min(best, min(t[j], INF) + e[j]);
+  }
+  for (int o = 16; o > 0; o >>= 1) best = min(best, (u32)__shfl_xor((int)best, o));
+  if (same) best = min(best, row1[loc2]);
+  return min(best, INF);
+}
+
 // 64 VGPRs: eight waves per SIMD keep enough block loads in flight
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_query(
     int64_t q, const int32_t* __restrict__ v1, const int32_t* __restrict__ v2,
     int32_t* __restrict__ out, int32_t n, const u32* __restrict__ vrec, const u32* __restrict__ M,
     const u32* __restrict__ H, int32_t share_comps) {
-  constexpr int QU = SPQ_QUERY_UNROLL;
   const int64_t qi = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
   const int l = threadIdx.x & 31;
   if (qi >= q) return;  // whole half-waves only
   bool ok;
   const u32 rec = load_recs(load_ids(qi, q, v1, v2, l), n, vrec, l, ok);
-  {
-    u32 res = 0xffffffffu;  // SPQ_BAD_PAIR
-    if (ok && (share_comps == 0 || (int32_t)hw_word(rec, 2) < share_comps)) {
-      {
-        // the full two-level store keeps group pairs S1 <= S2 only; dist is
-        // symmetric, so take the endpoints in group order when needed (a
-        // share keeps all S2): words o1 + j describe the first, o2 + j the
-        // second
-        const bool sw = share_comps == 0 && hw_word(rec, 6) > hw_word(rec, VREC_WORDS + 6);
-        const int o1 = sw ? VREC_WORDS : 0, o2 = sw ? 0 : VREC_WORDS;
-        const u32* row1 = M + ((uint64_t)hw_word(rec, o1) | ((uint64_t)hw_word(rec, o1 + 1) << 32));
-        const u32* row2 = M + ((uint64_t)hw_word(rec, o2) | ((uint64_t)hw_word(rec, o2 + 1) << 32));
-        const int32_t nb1 = (int32_t)hw_word(rec, o1 + 5), nb2 = (int32_t)hw_word(rec, o2 + 5);
-        // band of group S1, then the pair block: S1's rows against the
-        // groups before S2 in the band (from S1 itself in the full store)
-        const int64_t band = (int64_t)((uint64_t)hw_word(rec, o1 + 10) |
-                                       ((uint64_t)hw_word(rec, o1 + 11) << 32));
-        const int64_t gv1 = hw_word(rec, o1 + 8);
-        const int64_t pb = band + gv1 * ((int64_t)hw_word(rec, o2 + 4) -
-                                         (share_comps ? 0 : (int64_t)hw_word(rec, o1 + 4)));
-        const u32* blk = H + pb + (int64_t)hw_word(rec, o1 + 7) * hw_word(rec, o2 + 8) +
-                         (int64_t)nb1 * hw_word(rec, o2 + 7);
-        const int64_t ld = nb2;
-        const bool same = hw_word(rec, 2) == hw_word(rec, VREC_WORDS + 2);
-        const u32 loc2 = hw_word(rec, o2 + 3);
-        u32 best = INF;
-        for (int32_t c0 = 0; c0 < nb2; c0 += 128) {
-          const int32_t nbc = min(128, nb2 - c0);
-          const int L = (nbc + 3) >> 2, R = 32 / L;
-          const int r = l / L, col = c0 + (l - r * L) * 4;
-          const bool lane_on = r < R;
-          const int cvalid = c0 + nbc - col;  // columns of this lane's piece (>= 1 when on)
-          // second-stage terms first: independent of the block
-          u32 e[4];
-#pragma unroll
-          for (int j = 0; j < 4; j++) e[j] = (lane_on && j < cvalid) ? row2[col + j] : INF;
-          u32 t[4] = {INF, INF, INF, INF};
-          for (int32_t r0 = 0; r0 < nb1; r0 += R * QU) {
-            uint4 v[QU];
-            u32 d[QU];
-#pragma unroll
-            for (int u = 0; u < QU; u++) {
-              const int32_t row = r0 + u * R + r;
-              const bool on = lane_on && row < nb1;
-              v[u] = on ? load4_upto(blk + (int64_t)row * ld + col, cvalid)
-                        : make_uint4(INF, INF, INF, INF);
-              d[u] = on ? row1[row] : INF;
-            }
-#pragma unroll
-            for (int u = 0; u < QU; u++) {
-              t[0] = min(t[0], d[u] + v[u].x);
-              t[1] = min(t[1], d[u] + v[u].y);
-              t[2] = min(t[2], d[u] + v[u].z);
-              t[3] = min(t[3], d[u] + v[u].w);
-            }
-          }
-#pragma unroll
-          for (int j = 0; j < 4; j++) best = min(best, min(t[j], INF) + e[j]);
+  const u32 res = ok ? hw_pair_dist(rec, l, M, H, share_comps) : 0xffffffffu;  // SPQ_BAD_PAIR
+  if (l == 0) out[qi] = (int32_t)res;
+}
+
+// ------------------------------------------------------------------ paths --
+// One shortest path per half-wave, walked back from t to s on the graph's
+// adjacency: at vertex c (dist(s, c) = D), any neighbour u over an edge of
+// weight w with dist(s, u) + w = D lies on a shortest s-c path, so the walk
+// steps to it, preferring dist(s, u) < D; every dist(s, u) is an Algorithm 2
+// query on the index.  With positive weights dist falls at every step and the
+// walk reaches s.  A zero-weight edge allows a step at equal distance; such a
+// step avoids the last 8 vertices of the walk and its last 16 dead ends, and
+// a vertex with no step at all is a dead end the walk backs out of.  A walk
+// that backs out past t, or runs 4 max_len + 1,024 steps, is reported (-3).
+// Lane 0 writes the vertices (t first) and reverses them at the end, so the
+// path reads s .. t.
+//   lens[i]: vertices on the path (>= 1), 0 no path, -1 bad pair (an id
+//   outside [0, n), or v1 outside a share), -2 the walk needed more than
+//   max_len vertices, -3 it found no way off a zero-weight plateau
+__device__ __forceinline__ u32 hw_dist_to(int32_t s, int32_t u, int32_t n, const u32* vrec,
+                                          const u32* M, const u32* H, int32_t share_comps, int l) {
+  bool ok;
+  const u32 ids = l == 0 ? (u32)s : (l == 1 ? (u32)u : 0u);
+  const u32 rec = load_recs(ids, n, vrec, l, ok);
+  return ok ? hw_pair_dist(rec, l, M, H, share_comps) : 0xffffffffu;
+}
+
+__global__ __launch_bounds__(256) void k_paths(
+    int64_t q, const int32_t* __restrict__ v1, const int32_t* __restrict__ v2, int32_t max_len,
+    int32_t n, const u32* __restrict__ vrec, const u32* __restrict__ M, const u32* __restrict__ H,
+    int32_t share_comps, const int64_t* __restrict__ rowptr, const int2* __restrict__ adj,
+    const int32_t* __restrict__ wts, int32_t* __restrict__ paths, int32_t* __restrict__ lens) {
+  const int64_t qi = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int l = threadIdx.x & 31;
+  if (qi >= q) return;  // whole half-waves only
+  const int32_t s = v1[qi], t = v2[qi];
+  int32_t* out = paths + qi * (int64_t)max_len;
+  int32_t code = 0;
+  u32 dcur = 0xffffffffu;
+  if (s >= 0 && s < n && t >= 0 && t < n) dcur = hw_dist_to(s, t, n, vrec, M, H, share_comps, l);
+  if (dcur == 0xffffffffu) code = -1;
+  int32_t len = 0;
+  if (code == 0 && dcur < INF) {
+    // lanes 0-7: the vertices at path positions p (slot p mod 8) of the last
+    // 8 pushed; lanes 0-15: the last 16 dead ends
+    int32_t cur = t, recent = l == 0 ? t : -1, dead = -1, ndead = 0;
+    if (l == 0) out[0] = t;
+    len = 1;
+    const int64_t iter_cap = 4 * (int64_t)max_len + 1024;
+    for (int64_t iter = 0; cur != s; iter++) {
+      if (iter > iter_cap) {
+        code = -3;
+        break;
+      }
+      int32_t next = -1;
+      u32 dnext = INF;
+      const int64_t e1 = rowptr[cur + 1];
+      for (int64_t e = rowptr[cur]; e < e1; e++) {
+        const int2 a = adj[e];
+        const u32 w = (u32)wts[a.y];
+        if (w > dcur || a.x == cur) continue;
+        const u32 du = hw_dist_to(s, a.x, n, vrec, M, H, share_comps, l);
+        if (du >= INF || du + w != dcur) continue;
+        if (du < dcur) {
+          next = a.x;
+          dnext = du;
+          break;
         }
-        for (int o = 16; o > 0; o >>= 1) best = min(best, (u32)__shfl_xor((int)best, o));
-        if (same) best = min(best, row1[loc2]);
-        res = min(best, INF);
+        if (next < 0) {  // a zero-weight step: not to a recent vertex or a dead end
+          const uint64_t seen = __ballot((l < 8 && recent == a.x) || (l < 16 && dead == a.x));
+          if (((seen >> (threadIdx.x & 32)) & 0xffffu) == 0) {
+            next = a.x;
+            dnext = du;
+          }
+        }
+      }
+      if (next >= 0) {
+        if (len >= max_len) {
+          code = -2;
+          break;
+        }
+        if (l == (len & 7)) recent = next;
+        cur = next;
+        dcur = dnext;
+        if (l == 0) out[len] = cur;
+        len++;
+      } else {
+        // a dead end (only on zero-weight plateaus): mark it, step back
+        if (l == (ndead & 15)) dead = cur;
+        ndead++;
+        if (--len == 0) {
+          code = -3;
+          break;
+        }
+        int32_t prev = 0;
+        if (l == 0) prev = out[len - 1];  // written by this lane
+        cur = __shfl(prev, 0, 32);
+        dcur = hw_dist_to(s, cur, n, vrec, M, H, share_comps, l);
       }
     }
-    if (l == 0) out[qi] = (int32_t)res;
+  }
+  if (l == 0) {
+    if (code == 0 && len > 0) {
+      for (int32_t i = 0, j = len - 1; i < j; i++, j--) {
+        const int32_t x = out[i];
+        out[i] = out[j];
+        out[j] = x;
+      }
+      lens[qi] = len;
+    } else {
+      lens[qi] = code;
+    }
+  }
+}
+
+// Adjacency of G for the path walk: both directions of every edge that is not
+// a self-loop, as (neighbour, edge index).
+__global__ void k_adj_count(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                            unsigned long long* __restrict__ deg) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = eu[e], v = ev[e];
+    if (u == v) continue;
+    atomicAdd(deg + u, 1ull);
+    atomicAdd(deg + v, 1ull);
+  }
+}
+
+// Exclusive prefix sum of deg[0, n) into rowptr[0, n] by one workgroup, in
+// chunks of 1,024 (n is at most a few million: microseconds).
+__global__ __launch_bounds__(256) void k_adj_scan(int32_t n, const unsigned long long* __restrict__ deg,
+                                                  int64_t* __restrict__ rowptr) {
+  __shared__ unsigned long long part[256];
+  unsigned long long carry = 0;
+  for (int64_t base = 0; base < n; base += 1024) {
+    unsigned long long x[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t i = base + threadIdx.x * 4 + j;
+      x[j] = i < n ? deg[i] : 0ull;
+      sum += x[j];
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {  // inclusive scan of the 256 partial sums
+      const unsigned long long y = threadIdx.x >= o ? part[threadIdx.x - o] : 0ull;
+      __syncthreads();
+      part[threadIdx.x] += y;
+      __syncthreads();
+    }
+    unsigned long long run = carry + (threadIdx.x ? part[threadIdx.x - 1] : 0ull);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t i = base + threadIdx.x * 4 + j;
+      if (i < n) rowptr[i] = (int64_t)run;
+      run += x[j];
+    }
+    carry += part[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rowptr[n] = (int64_t)carry;
+}
+
+__global__ void k_adj_fill(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                           unsigned long long* __restrict__ cursor, int2* __restrict__ adj) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = eu[e], v = ev[e];
+    if (u == v) continue;
+    adj[atomicAdd(cursor + u, 1ull)] = make_int2(v, (int32_t)e);
+    adj[atomicAdd(cursor + v, 1ull)] = make_int2(u, (int32_t)e);
   }
 }
 
@@ -486,6 +656,34 @@ hipError_t launch_query(const QueryArgs& a, hipStream_t s) {
   const int64_t blocks = (a.q + 7) / 8;  // 8 pairs per workgroup
   k_query<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, a.out, a.n, a.vrec, a.M, a.H,
                                            a.share_comps);
+  LAUNCH_CHECK();
+}
+
+hipError_t launch_adjacency(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
+                            unsigned long long* deg, int64_t* rowptr, int2* adj, hipStream_t s) {
+  // deg: n counters (zeroed by the caller), then reused as the fill cursors
+  if (m > 0) {
+    unsigned g = blocks_for(m);
+    if (g > 8192) g = 8192;
+    k_adj_count<<<g, 256, 0, s>>>(m, eu, ev, deg);
+  }
+  k_adj_scan<<<1, 256, 0, s>>>(n, deg, rowptr);
+  hipError_t e = hipMemcpyAsync(deg, rowptr, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  if (m > 0) {
+    unsigned g = blocks_for(m);
+    if (g > 8192) g = 8192;
+    k_adj_fill<<<g, 256, 0, s>>>(m, eu, ev, deg, adj);
+  }
+  LAUNCH_CHECK();
+}
+
+hipError_t launch_paths(const QueryArgs& a, int32_t max_len, const int64_t* rowptr, const int2* adj,
+                        const int32_t* wts, int32_t* paths, int32_t* lens, hipStream_t s) {
+  if (a.q <= 0) return hipSuccess;
+  const int64_t blocks = (a.q + 7) / 8;  // 8 paths per workgroup
+  k_paths<<<(unsigned)blocks, 256, 0, s>>>(a.q, a.v1, a.v2, max_len, a.n, a.vrec, a.M, a.H,
+                                           a.share_comps, rowptr, adj, wts, paths, lens);
   LAUNCH_CHECK();
 }
 

@@ -187,5 +187,12 @@ hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipSt
 // interior tiles of every round)
 double dense_fw_exec_relax(int64_t nt, int tile);
 hipError_t launch_query(const QueryArgs& a, hipStream_t s);
+// Adjacency of G (both directions, self-loops dropped) as rowptr[n+1] and
+// (neighbour, edge index) pairs; deg[n] zeroed scratch.
+hipError_t launch_adjacency(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
+                            unsigned long long* deg, int64_t* rowptr, int2* adj, hipStream_t s);
+// One shortest path per pair by a walk on the adjacency (kernels.hip).
+hipError_t launch_paths(const QueryArgs& a, int32_t max_len, const int64_t* rowptr, const int2* adj,
+                        const int32_t* wts, int32_t* paths, int32_t* lens, hipStream_t s);
 
 }  // namespace spq

@@ -23,6 +23,7 @@ SPQ_INF = 2147483647
 SPQ_BAD_PAIR = -1
 SPQ_NO_LOOKAHEAD = 1
 SPQ_GRAPH = 2
+SPQ_PATHS = 4
 STATUS = {0: "SPQ_OK", 1: "SPQ_EINVAL", 2: "SPQ_ENOMEM", 3: "SPQ_EDEVICE", 4: "SPQ_ERANGE"}
 
 
@@ -69,6 +70,7 @@ _SIGS = {
     "spq_query_batch": (I32, [P, I64, P, P, P, P]),
     "spq_query_batch_host": (I32, [P, I64, P, P, P]),
     "spq_reweight_index": (I32, [P, P, P]),
+    "spq_query_paths": (I32, [P, I64, P, P, I32, P, P, P]),
     "spq_index_stats": (I32, [P, ctypes.POINTER(Stats)]),
     "spq_index_layout": (I32, [P, P, P, P, P, P]),
     "spq_index_component": (I32, [P, I32, P]),
@@ -162,10 +164,11 @@ class Index:
 
 def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg_method=0,
                 group_comps=0, share_comps=0, inner_kc=0, lookahead=True, graph=False,
-                level3_groups=0, group_bg=0, tune_cache=None, stream=None) -> Index:
+                level3_groups=0, group_bg=0, paths=False, tune_cache=None, stream=None) -> Index:
     """Algorithm 1 on device tensors; see spq_build_index.
 
     graph: capture Phases 2-3 as HIP graphs kept for reweight().
+    paths: keep the graph's adjacency for query_paths().
     tune_cache: path of an autotuner cache (paper_1503_07192_amd.autotune);
     options it holds for this device and problem size fill in the ones left
     at 0 here."""
@@ -182,7 +185,8 @@ def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg
     opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)), plain=int(bool(plain)),
                      bg_method=int(bg_method), group_comps=int(group_comps),
                      share_comps=int(share_comps), inner_kc=int(inner_kc),
-                     flags=(0 if lookahead else SPQ_NO_LOOKAHEAD) | (SPQ_GRAPH if graph else 0),
+                     flags=(0 if lookahead else SPQ_NO_LOOKAHEAD) | (SPQ_GRAPH if graph else 0) |
+                     (SPQ_PATHS if paths else 0),
                      level3_groups=int(level3_groups), group_bg=int(group_bg))
     h = ctypes.c_void_p()
     m = int(eu.numel())
@@ -213,6 +217,21 @@ def query_batch(index: Index, v1, v2, out=None, stream=None):
     _check(load().spq_query_batch(index.handle, q, _dev_i32(v1, "v1"), _dev_i32(v2, "v2"),
                                   _dev_i32(out, "out"), _stream(stream)))
     return out
+
+
+def query_paths(index: Index, v1, v2, max_len, stream=None):
+    """One shortest path per pair (index built with paths=True); returns the
+    device tensors (paths [q, max_len], lens [q]), see spq_query_paths."""
+    import torch
+    q = int(v1.numel())
+    if int(v2.numel()) != q:
+        raise ValueError("v1 and v2 differ in length")
+    paths = torch.full((q, int(max_len)), -1, dtype=torch.int32, device=v1.device)
+    lens = torch.empty(q, dtype=torch.int32, device=v1.device)
+    _check(load().spq_query_paths(index.handle, q, _dev_i32(v1, "v1"), _dev_i32(v2, "v2"),
+                                  int(max_len), _dev_i32(paths, "paths"), _dev_i32(lens, "lens"),
+                                  _stream(stream)))
+    return paths, lens
 
 
 def query_batch_host(index: Index, v1, v2):

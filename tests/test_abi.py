@@ -31,6 +31,7 @@ def test_argument_errors_without_device():
     assert L.spq_build_index(5, 0, None, None, None, None, 2, None, None, None) == 1
     assert L.spq_query_batch(None, 3, None, None, None, None) == 1
     assert L.spq_query_batch_host(None, 3, None, None, None) == 1
+    assert L.spq_query_paths(None, 3, None, None, 8, None, None, None) == 1
     assert L.spq_fw_dense(10, 10, 3, 0, None, None) == 1
     assert L.spq_fw_dense(10, 8, 64, 0, None, None) == 1
     assert L.spq_fw_dense(10, 64, 64, 8, None, None) == 1
@@ -39,7 +40,7 @@ def test_argument_errors_without_device():
     assert L.spq_index_stats(None, None) == 1
     assert L.spq_reweight_index(None, None, None) == 1
     part = ctypes.c_void_p(8)
-    for flags, share, profile, msg in ((4, 0, 0, "unknown flags"),
+    for flags, share, profile, msg in ((8, 0, 0, "unknown flags"),
                                        (spq.SPQ_GRAPH, 1, 0, "SPQ_GRAPH"),
                                        (spq.SPQ_GRAPH, 0, 1, "SPQ_GRAPH")):
         opts = spq.BuildOpts(flags=flags, share_comps=share, profile=profile)
