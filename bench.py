@@ -262,8 +262,21 @@ def main():
 
     # the plain comparators, after the timed region: one launch per component
     # for APSP(C), and one query per launch
-    idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], plain=True, stream=stream, **build_kw)
+    idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], plain=True, paths=True, stream=stream,
+                          **build_kw)
     plain_st = spq.index_stats(idx)
+    # shortest paths (vertex sequences) for the first 1,000 pairs
+    npath = min(1000, q)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    _, plens = spq.query_paths(idx, v1[:npath], v2[:npath], 16384, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    plens = plens.cpu().numpy()
+    paths_res = {"pairs": npath, "ms": e0.elapsed_time(e1),
+                 "paths_per_s": npath / (e0.elapsed_time(e1) * 1e-3),
+                 "mean_vertices": float(plens[plens > 0].mean()) if (plens > 0).any() else 0.0,
+                 "found": int((plens > 0).sum()), "unreachable": int((plens == 0).sum())}
     # the same batch again on this (warm) index: caches and TLB hold its tables
     warm = []
     for _ in range(5):
@@ -314,6 +327,7 @@ def main():
         "query_batch_ms_p50": float(np.percentile(mq, 50)),
         "query_batch_ms_p99": float(np.percentile(mq, 99)),
         "other_bg_method": alt,
+        "paths": paths_res,
         "graph_build": graph,
         "plain_components_ms": plain_st["ms_components"],
         "batched_components_ms": float(np.median([r["ms_components"] for r in recs])),
