@@ -8,6 +8,8 @@ adversarial matrices.  A value the kernels report is min(exact distance,
 2^31-1): stored sums never wrap, so an exact distance at or above the
 sentinel shows as the sentinel.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -20,6 +22,8 @@ spq = pytest.importorskip("paper_1503_07192_amd.spq")
 
 pytestmark = pytest.mark.gpu
 INF32 = 2**31 - 1
+# the options bench.py builds delaunay1m and grid2048 with (the autotuner's)
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(spq.__file__)), "tune_cache.json")
 
 
 def clamp32(d):
@@ -530,13 +534,14 @@ def check_layout_fast(g, lay, flag):
 def test_delaunay1m_two_level():
     g = W.delaunay1m()
     print("delaunay1m: n=%d m=%d k=%d" % (g["n"], g["m"], g["k"]), flush=True)
-    idx = build(g)
+    idx = build(g, tune_cache=TUNE_CACHE)   # the benchmark's configuration
     st = spq.index_stats(idx)
     print({k: st[k] for k in ("v_bg", "bg_method", "ngroups", "v_bg2", "groups3", "v_bg3",
                               "max_comp", "max_boundary", "bg_bytes", "ms_components",
                               "ms_bg_apsp")}, flush=True)
-    assert st["bg_method"] == 2 and st["ngroups"] == 64
-    assert st["groups3"] > 1 and 0 < st["v_bg3"] < st["v_bg2"]   # BG2 closed by level 3
+    assert st["bg_method"] == 2
+    if st["v_bg2"] > 16384:   # BG2 closed by level 3
+        assert st["groups3"] > 1 and 0 < st["v_bg3"] < st["v_bg2"]
     lay = spq.index_layout(idx)
     flag = oracle.boundary(g["n"], g["eu"], g["ev"], g["part"])
     assert st["v_bg"] == int(flag.sum())
@@ -555,6 +560,12 @@ def test_delaunay1m_two_level():
     D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], src)
     want = clamp32(D[np.repeat(np.arange(100), 20), v2])
     assert np.array_equal(got, want)
+    # the default group size (64 groups, level 3 on 30,021 level-2 vertices)
+    idx.free()
+    dflt = build(g)
+    sd = spq.index_stats(dflt)
+    assert sd["ngroups"] == 64 and sd["groups3"] > 1
+    assert np.array_equal(run_queries(dflt, v1, v2), want)
 
 
 # --------------------------------------------------- share (one GPU's rows)
@@ -664,11 +675,11 @@ def test_share_grid2048_small_equals_full_two_level():
 def test_grid2048_share_full_size():
     g = W.grid2048(queries=10_000_000)
     print("grid2048: n=%d m=%d k=%d share=%d" % (g["n"], g["m"], g["k"], g["share_k"]), flush=True)
-    idx = build(g, share_comps=g["share_k"])
+    idx = build(g, share_comps=g["share_k"], tune_cache=TUNE_CACHE)   # the benchmark's configuration
     st = spq.index_stats(idx)
     print({k: st[k] for k in ("v_bg", "ngroups", "v_bg2", "share_groups", "bf_rounds", "bg_bytes",
                               "ms_components", "ms_bg_apsp")}, flush=True)
-    assert st["v_bg"] == 883_500 and st["share_groups"] == 8
+    assert st["v_bg"] == 883_500 and st["share_groups"] == 512 // (g["k"] // st["ngroups"])
     rng = np.random.default_rng(44)
     lay = spq.index_layout(idx)
     flag = oracle.boundary(g["n"], g["eu"], g["ev"], g["part"])
