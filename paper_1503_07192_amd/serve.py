@@ -178,8 +178,11 @@ def summarize(reqs, sched=None):
     lat = np.array([r.done_at - r.arrival for r in reqs])
     pairs = sum(r.size for r in reqs)
     span = max(r.done_at for r in reqs) - min(r.arrival for r in reqs)
+    # the offered load this sample of sizes and gaps actually carried
+    arr = max(r.arrival for r in reqs) - min(r.arrival for r in reqs)
     out = {"requests": len(reqs), "pairs": int(pairs), "span_s": span,
            "queries_per_s": pairs / span if span > 0 else float("inf"),
+           "offered_realized_pairs_per_s": pairs / arr if arr > 0 else float("inf"),
            "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
            "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
            "latency_ms_mean": float(lat.mean() * 1e3)}
