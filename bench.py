@@ -60,24 +60,29 @@ WORKLOADS = {
 }
 
 
-def recorded_traffic():
-    """HBM bytes per round of the interior kernel, from the committed counter
-    summary, if the kernel sources are still the ones it was measured on."""
+def recorded_traffic(name, work):
+    """HBM bytes per launch of a kernel, from the committed counter summary
+    profiles/pmc_<name>.md, if the sources it names still hash to the ones it
+    was measured on and a launch does the same work (relaxations or queries)
+    as in that run."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pmc_k_fw_inner_grid256d.md")
+    path = os.path.join(ROOT, "profiles", "pmc_%s.md" % name)
     if not os.path.exists(path):
         return None
     rec = {}
     for line in open(path):
-        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_round", "source_sha256"):
-            k, v = line.split(":", 1)
+        k, _, v = line.partition(":")
+        if k in ("traffic_bytes_per_launch", "work_per_launch", "sources", "source_sha256"):
             rec[k] = v.strip()
-    csrc = os.path.join(ROOT, "paper_1503_07192_amd", "csrc")
-    src = open(os.path.join(csrc, "tiles.h"), "rb").read() + \
-        open(os.path.join(csrc, "fw.hip"), "rb").read()
-    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+    if len(rec) < 4:
         return None
-    return float(rec["traffic_bytes_per_round"])
+    csrc = os.path.join(ROOT, "paper_1503_07192_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in rec["sources"].split())
+    if rec["source_sha256"] != hashlib.sha256(src).hexdigest():
+        return None
+    if abs(float(rec["work_per_launch"]) - work) > 1e-9 * max(1.0, work):
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 TUNE_CACHE = os.path.join(ROOT, "paper_1503_07192_amd", "tune_cache.json")
@@ -336,8 +341,8 @@ def main():
         "roofline": {"bound": "alu", "kernel": kernel,
                      "achieved": inner_rate / 1e12, "peak": RELAX_PEAK / 1e12,
                      "unit": "Trelax/s", "frac": inner_rate / RELAX_PEAK,
-                     "traffic": recorded_traffic() if (args.workload == "grid256d"
-                                                       and st["bg_method"] == 1) else None,
+                     "traffic": recorded_traffic(("k_fw_inner_" if st["bg_method"] == 1 else "k_mp_y_")
+                                                 + args.workload, per_launch),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "scaled by a 256 MiB copy)",
                      "launches_per_step": launches, "avg_launch_ms": avg_launch_ms,
@@ -345,7 +350,10 @@ def main():
         "query_roofline": {"bound": "hbm", "achieved": q * qbytes / (np.median(mq) * 1e-3) / 1e9,
                            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                            "frac": q * qbytes / (np.median(mq) * 1e-3) / HBM_PEAK,
-                           "bytes_per_query": qbytes},
+                           "bytes_per_query": qbytes,
+                           "traffic": recorded_traffic("k_query_" + args.workload, float(q)),
+                           "traffic_unit": "HBM bytes per launch of the step's batch (rocprofv3 "
+                                           "FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy)"},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, st, args.cpu_seconds)
