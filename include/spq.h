@@ -89,6 +89,11 @@ typedef struct {
                           it holds at most group_bg BG vertices (a larger
                           component gets a group of its own); overrides
                           group_comps */
+  int32_t bg_pivot;      /* rows per pivot block of the flat BG Floyd-Warshall
+                          (each round closes one block, then updates every
+                          other tile through it): 0 default (two tiles: 256
+                          with 128-tiles, 64 with 64-tiles), the tile, or
+                          twice the tile.  The answers do not depend on it */
 } spq_build_opts;
 
 #define SPQ_NO_LOOKAHEAD 1
@@ -289,16 +294,17 @@ const char* spq_last_error(void);
  *   Rows and columns in [size[i], ld[i]) must hold SPQ_INF off the diagonal
  *   and 0 on it.  One workgroup closes one whole matrix (the APSP(C) kernel).
  * spq_fw_dense: one v x v matrix with leading dimension ld (a multiple of
- *   tile, padded like above); blocked Floyd-Warshall in rounds of three
- *   kernels (the BG kernel).  tile is 64 or 128; kc (K chunk of the interior
- *   kernel) is 0 (default), 16 or 32.
+ *   tile, padded like above); blocked Floyd-Warshall in rounds over pivot
+ *   blocks of `pivot` rows (the BG kernels).  tile is 64 or 128; pivot is the
+ *   tile or twice the tile (0: the tile); kc (K chunk of the interior kernel)
+ *   is 0 (default), 16 or 32.
  * spq_fw_components stages its size tables on the device and returns when
  * the work is done; spq_fw_dense is asynchronous on `stream`.
  * Errors: SPQ_EINVAL, SPQ_ENOMEM, SPQ_EDEVICE.
  */
 spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* off,
                              const int32_t* ld, int32_t* data, void* stream);
-spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t kc, int32_t* data,
+spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int32_t kc, int32_t* data,
                         void* stream);
 
 #ifdef __cplusplus

@@ -116,7 +116,7 @@ int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
 
 struct spq_index {
   int device = 0;
-  int32_t n = 0, k = 0, V = 0, Vp = 0, tile = 128, max_comp = 0, max_nb = 0;
+  int32_t n = 0, k = 0, V = 0, Vp = 0, tile = 128, pivot = 256, max_comp = 0, max_nb = 0;
   int64_t m = 0, comp_elems = 0;
   std::vector<int32_t> h_cnt, h_nb, h_off, h_bgoff, h_P, h_order;
   std::vector<int64_t> h_moff;
@@ -441,11 +441,14 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   bool profile = false, plain = false;
   int32_t method_opt = 0, group_comps = 0, share_comps = 0, inner_kc = 0;
   bool lookahead = true, use_graph = false, use_paths = false;
-  int32_t level3_opt = 0, group_bg = 0;
+  int32_t level3_opt = 0, group_bg = 0, pivot = 0;
   if (opts) {
     if (opts->bg_tile != 0 && opts->bg_tile != 64 && opts->bg_tile != 128)
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
     if (opts->bg_tile) tile = opts->bg_tile;
+    pivot = opts->bg_pivot;
+    if (pivot != 0 && pivot != tile && pivot != 2 * tile)
+      return fail(SPQ_EINVAL, "bg_pivot must be 0, the tile or twice the tile");
     profile = opts->profile != 0;
     plain = opts->plain != 0;
     method_opt = opts->bg_method;
@@ -482,6 +485,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   X->k = k;
   X->m = m;
   X->tile = tile;
+  X->pivot = pivot ? pivot : 2 * tile;
   X->graph = use_graph;
   {
     hipError_t e = hipGetDevice(&X->device);
@@ -624,10 +628,9 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   if (X->method == 1) {
     X->Vp = (int32_t)round_up(X->V, tile);
     const int64_t nt = X->Vp / tile;
-    X->relax_bg_exec = spq::dense_fw_exec_relax(nt, tile);
-    if (nt > 1) {
-      X->inner_launches = nt;
-      X->relax_inner = (double)nt * (double)(nt - 1) * nt / 2.0 * tile * tile * (double)tile;
+    X->relax_bg_exec = spq::dense_fw_exec_relax(nt, tile, X->pivot, &X->relax_inner);
+    if (X->relax_inner > 0) {
+      X->inner_launches = spq::fw_rounds_count((int)nt, tile, X->pivot);
     }
   } else {
     X->Vgp = std::max<int32_t>(X->Vgp, 128);
@@ -984,9 +987,9 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     if (e != hipSuccess) return e;
     if (la)
       e = spq::launch_dense_fw_lookahead(X->BG, X->Vp, tile, X->Vp / tile, st, X->side, X->la_sync,
-                                         pev, inner_kc);
+                                         pev, inner_kc, X->pivot);
     else
-      e = spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, st, pev, inner_kc);
+      e = spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, st, pev, inner_kc, X->pivot);
     if (e != hipSuccess) return e;
     return spq::launch_flat_store(V, X->Vp, X->BG, X->bgcomp, X->bgoff, X->nb, X->grp, X->gbg0,
                                   X->bgrow, X->bgnb, X->bggrp, X->bglocal, X->H, st);
@@ -1245,14 +1248,16 @@ spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* 
   return SPQ_OK;
 }
 
-spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t kc, int32_t* data,
-                        void* stream) {
+spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int32_t kc,
+                        int32_t* data, void* stream) {
   if (tile != 64 && tile != 128) return fail(SPQ_EINVAL, "tile must be 64 or 128");
+  if (pivot != 0 && pivot != tile && pivot != 2 * tile)
+    return fail(SPQ_EINVAL, "pivot must be 0, the tile or twice the tile");
   if (kc != 0 && kc != 16 && kc != 32) return fail(SPQ_EINVAL, "kc must be 0, 16 or 32");
   if (v < 0 || ld < v || ld % tile || (v > 0 && !data)) return fail(SPQ_EINVAL, "bad v or ld");
   if (v == 0) return SPQ_OK;
   HIP_TRY(spq::launch_dense_fw(reinterpret_cast<u32*>(data), ld, tile, ld / tile,
-                               reinterpret_cast<hipStream_t>(stream), nullptr, kc));
+                               reinterpret_cast<hipStream_t>(stream), nullptr, kc, pivot));
   return SPQ_OK;
 }
 

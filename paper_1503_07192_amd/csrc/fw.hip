@@ -5,18 +5,29 @@
 #include "spq_internal.h"
 #include "tiles.h"
 
+#include <vector>
+
 namespace spq {
 
 #define LAUNCH_CHECK() return hipGetLastError()
 
-// Blocked Floyd-Warshall on one symmetric matrix, round r of nt:
-//   k_fw_diag   closes the diagonal tile (r, r)
-//   k_fw_panel  tile (r, j) = D (x) tile (r, j) for j != r, stored twice
-//               (as (r, j) and transposed as (j, r))
-//   k_fw_inner  tile (i, j) = min(tile (i, j), tile (r, i)^T (x) tile (r, j))
+// Blocked Floyd-Warshall on one symmetric matrix of nt x nt tiles, in rounds
+// over pivot blocks of one tile (c0 = r) or two tiles (c0 = 2r; the last
+// block is one tile when nt is odd):
+//   k_fw_diag / k_fw_diag2  close the pivot block (a 2 x 2-tile block by a
+//                            blocked Floyd-Warshall inside one workgroup)
+//   panel                    tile (a, j), a in the block, j outside it:
+//                            tile (a, j) = D (x) tile (a, j), stored twice (as
+//                            (a, j) and transposed as (j, a)); k_fw_panel for
+//                            one-tile blocks, k_fw_inner part 3 for two
+//   k_fw_inner               tile (i, j) = min(tile (i, j),
+//                            (block rows, tile i)^T (x) (block rows, tile j))
+// A two-tile block doubles the K of every interior product (256 instead of
+// 128 for 128-tiles): the fixed cost of a tile (loading and storing C) is
+// spread over twice the relaxations, and there are half as many rounds.
 //
-// A batch of equally sized matrices is handled by blockIdx.y: matrix y starts
-// gstride elements after matrix y-1.
+// A batch of equally sized matrices (one-tile blocks only) is handled by
+// blockIdx.y: matrix y starts gstride elements after matrix y-1.
 template <int T>
 __global__ __launch_bounds__(256) void k_fw_diag(u32* __restrict__ A, int64_t ld, int r,
                                                  int64_t gstride) {
@@ -62,53 +73,66 @@ __device__ __forceinline__ void tri_index(int b, int m, int& bi, int& bj) {
 }
 
 // Interior tiles.  The matrix is symmetric, so only tiles (i, j) with i <= j
-// are computed; tile (j, i) receives the transpose.  The k dimension is
-// streamed through LDS in chunks of KC rows of the two operand tiles (double
-// buffered, next chunk prefetched into registers while the current one is
-// consumed).
+// are computed; tile (j, i) receives the transpose.  The k dimension (the
+// PT * T rows of the pivot block) is streamed through LDS in chunks of KC rows
+// of the two operand tiles (double buffered, next chunk prefetched into
+// registers while the current one is consumed).
 #ifdef SPQ_INNER_WPE
 #define SPQ_INNER_ATTR __attribute__((amdgpu_waves_per_eu(SPQ_INNER_WPE, SPQ_INNER_WPE)))
 #else
 #define SPQ_INNER_ATTR
 #endif
 //
-// part selects the tiles of the launch:
-//   0  every interior tile (i <= j, both != r)
-//   1  the tiles of row/column r+1 only: (i, r+1) for i <= r+1, i != r, and
-//      (r+1, j) for j > r+1 (what the next round's pivot row needs)
-//   2  every interior tile not in part 1
-template <int T, int KC>
+// The pivot block is tiles [c0, c0 + PT), c0 = r * PT; nn = tiles of the next
+// block (parts 1 and 2).  part selects the tiles of the launch:
+//   0  every tile outside the pivot block (i <= j)
+//   1  the tiles with a row or column in the next block (what the next
+//      round's diagonal and panel read)
+//   2  every tile outside both blocks
+//   3  the panel: (a, j) for a in the pivot block, j outside it (PT = 2)
+template <int PT>
+__device__ __forceinline__ void inner_tile(int part, int b, int c0, int nt, int nn, int& i, int& j) {
+  int bi, bj;
+  if (part == 0) {
+    tri_index(b, nt - PT, bi, bj);
+    i = bi + (bi >= c0 ? PT : 0);
+    j = bj + (bj >= c0 ? PT : 0);
+  } else if (part == 1) {
+    const int no = nt - PT - nn;  // tiles outside both blocks
+    if (b < nn * no) {
+      const int x = c0 + PT + b / no, o = b % no;
+      const int y = o + (o >= c0 ? PT + nn : 0);
+      i = min(x, y);
+      j = max(x, y);
+    } else {
+      tri_index(b - nn * no, nn, bi, bj);
+      i = c0 + PT + bi;
+      j = c0 + PT + bj;
+    }
+  } else if (part == 2) {
+    tri_index(b, nt - PT - nn, bi, bj);
+    i = bi + (bi >= c0 ? PT + nn : 0);
+    j = bj + (bj >= c0 ? PT + nn : 0);
+  } else {
+    const int m = nt - PT, o = b % m;
+    i = c0 + b / m;
+    j = o + (o >= c0 ? PT : 0);
+  }
+}
+
+template <int T, int KC, int PT>
 __global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict__ A, int64_t ld, int r, int nt,
-                                                                int64_t gstride, int part) {
+                                                                int64_t gstride, int part, int nn) {
   constexpr int Q = KC * T / 4 / 256;  // uint4 per thread per operand chunk
   static_assert(Q >= 1 && KC * T / 4 % 256 == 0, "chunk must split evenly");
   __shared__ __attribute__((aligned(16))) u32 sA[2][KC * T];
   __shared__ __attribute__((aligned(16))) u32 sB[2][KC * T];
   A += (int64_t)blockIdx.y * gstride;
+  const int c0 = r * PT;
   int i, j;
-  const int b = (int)blockIdx.x;
-  if (part == 0) {
-    int bi, bj;
-    tri_index(b, nt - 1, bi, bj);
-    i = bi + (bi >= r);
-    j = bj + (bj >= r);
-  } else if (part == 1) {
-    const int p = r + 1;  // nt - 1 tiles
-    if (b <= r) {         // (i, p) for i in [0, p], i != r; b == r gives (p, p)
-      i = b + (b >= r ? 1 : 0);
-      j = p;
-    } else {              // (p, j) for j in (p, nt)
-      i = p;
-      j = b + 1;
-    }
-  } else {
-    int bi, bj;           // triangle over indices other than r and r+1
-    tri_index(b, nt - 2, bi, bj);
-    i = bi + (bi >= r ? 2 : 0);
-    j = bj + (bj >= r ? 2 : 0);
-  }
-  const u32* Ar = A + (int64_t)r * T * ld + (int64_t)i * T;  // tile (r, i)
-  const u32* Br = A + (int64_t)r * T * ld + (int64_t)j * T;  // tile (r, j)
+  inner_tile<PT>(part, (int)blockIdx.x, c0, nt, nn, i, j);
+  const u32* Ar = A + (int64_t)c0 * T * ld + (int64_t)i * T;  // block rows, tile column i
+  const u32* Br = A + (int64_t)c0 * T * ld + (int64_t)j * T;  // block rows, tile column j
   u32* Cij = A + (int64_t)i * T * ld + (int64_t)j * T;
   u32 t[T / 16][T / 16];
   tile_load<T>(t, Cij, ld);
@@ -132,7 +156,7 @@ __global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict
   // per SIMD); rolled it fits 128 (four waves, 3.5% faster on a 27,904-wide
   // matrix).  The last chunk reloads itself into the idle buffer (unused), so
   // the prefetch needs no branch.
-  constexpr int NCH = T / KC;
+  constexpr int NCH = PT * T / KC;
 #pragma unroll 1
   for (int ch = 0; ch < NCH; ch++) {
     const int kc = (ch + 1 < NCH ? ch + 1 : ch) * KC;
@@ -156,6 +180,56 @@ __global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict
   if (i != j) tile_store_t<T>(t, A + (int64_t)j * T * ld + (int64_t)i * T, ld);
 }
 
+// Closes the 2T x 2T diagonal block whose first tile is (c0, c0): blocked
+// Floyd-Warshall over its 2 x 2 tiles in one workgroup.  Round 0: close T00,
+// panel T01 = T00 (x) T01, interior T11 = min(T11, T10 (x) T01); round 1:
+// close T11, panel T01 = T01 (x) T11, interior T00 = min(T00, T01 (x) T10).
+// Each panel is computed in place from the old tile; with the diagonal tile
+// closed (zero diagonal) that is the exact panel.  LDS: two T x T tiles.
+template <int T>
+__global__ __launch_bounds__(256) void k_fw_diag2(u32* __restrict__ A, int64_t ld, int c0) {
+  __shared__ __attribute__((aligned(16))) u32 X[T * T];
+  __shared__ __attribute__((aligned(16))) u32 Y[T * T];
+  __shared__ __attribute__((aligned(16))) u32 rb[4 * T];
+  u32* T00 = A + (int64_t)c0 * T * ld + (int64_t)c0 * T;
+  u32* T01 = T00 + T;
+  u32* T10 = T00 + (int64_t)T * ld;
+  u32* T11 = T10 + T;
+  u32 t[T / 16][T / 16];
+  // round 0
+  tile_load<T>(t, T00, ld);
+  fw_tile<T>(t, rb);
+  tile_store<T>(t, T00, ld);
+  tile_to_lds<T>(t, X);                 // X = T00
+  tile_load<T>(t, T01, ld);
+  tile_to_lds<T>(t, Y);                 // Y = T01
+  __syncthreads();
+  minplus_lds<T>(t, X, Y, T);           // T01 = T00 (x) T01
+  __syncthreads();
+  tile_to_lds<T>(t, Y);                 // Y = T01
+  __syncthreads();
+  tile_load<T>(t, T11, ld);
+  minplus_lds<T>(t, Y, Y, T);           // T11 = min(T11, T10 (x) T01)
+  // round 1
+  fw_tile<T>(t, rb);
+  tile_store<T>(t, T11, ld);
+  tile_to_lds<T>(t, X);                 // X = T11 (X is no longer read)
+  __syncthreads();
+  tile_load<T>(t, Y, T);                // t = T01 (round 0)
+  __syncthreads();
+  tile_store_t<T>(t, Y, T);             // Y = T10
+  __syncthreads();
+  minplus_lds<T>(t, Y, X, T);           // T01 = T01 (x) T11
+  tile_store<T>(t, T01, ld);
+  tile_store_t<T>(t, T10, ld);
+  __syncthreads();
+  tile_store_t<T>(t, Y, T);             // Y = T10
+  __syncthreads();
+  tile_load<T>(t, T00, ld);             // closed in round 0, stored above
+  minplus_lds<T>(t, Y, Y, T);           // T00 = min(T00, T01 (x) T10)
+  tile_store<T>(t, T00, ld);
+}
+
 #ifndef SPQ_INNER_KC
 #define SPQ_INNER_KC 16
 #endif
@@ -171,8 +245,8 @@ static hipError_t fw_rounds(u32* A, int64_t ld, int nt, int batch, int64_t gstri
         hipError_t e = hipEventRecord(ev[2 * r], s);
         if (e != hipSuccess) return e;
       }
-      k_fw_inner<T, KC><<<dim3((unsigned)((nt - 1) * nt / 2), batch), 256, 0, s>>>(
-          A, ld, r, nt, gstride, 0);
+      k_fw_inner<T, KC, 1><<<dim3((unsigned)((nt - 1) * nt / 2), batch), 256, 0, s>>>(
+          A, ld, r, nt, gstride, 0, 1);
       if (ev) {
         hipError_t e = hipEventRecord(ev[2 * r + 1], s);
         if (e != hipSuccess) return e;
@@ -182,65 +256,156 @@ static hipError_t fw_rounds(u32* A, int64_t ld, int nt, int batch, int64_t gstri
   LAUNCH_CHECK();
 }
 
-// The same rounds with a lookahead: the interior tiles of row/column r+1 go
-// first (part 1); as soon as they are done, round r+1's diagonal and panel
-// run on the side stream while the rest of round r's interior (part 2) runs
-// on the main stream.  Part 2 neither reads nor writes a tile that round
-// r+1's diagonal or panel touches (row/column r+1 and the tiles (r, r+1),
-// (r+1, r)), so the two overlap safely.  ev (optional) gets one pair per
-// round around parts 1 + 2.
+// Pivot blocks of a single matrix: two tiles each (the last one a single tile
+// when nt is odd) or one tile each.
+struct FwBlock {
+  int c0, pt;
+};
+
+static int fw_blocks(int nt, int pivot_tiles, FwBlock* out) {
+  int nb = 0;
+  for (int c0 = 0; c0 < nt; nb++) {
+    const int pt = (pivot_tiles == 2 && c0 + 1 < nt) ? 2 : 1;
+    if (out) out[nb] = FwBlock{c0, pt};
+    c0 += pt;
+  }
+  return nb;
+}
+
+static int64_t tri_count(int64_t m) { return m > 0 ? m * (m + 1) / 2 : 0; }
+
+// tiles of an interior launch of block b (parts 0-2; nn = next block's tiles)
+static int64_t inner_count(int nt, FwBlock b, int part, int nn) {
+  if (part == 0) return tri_count(nt - b.pt);
+  if (part == 1) return (int64_t)nn * (nt - b.pt - nn) + tri_count(nn);
+  return tri_count(nt - b.pt - nn);
+}
+
 template <int T, int KC>
-static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, hipStream_t s, hipStream_t side,
-                                      hipEvent_t* sync, hipEvent_t* ev) {
+static hipError_t fw_close(u32* A, int64_t ld, FwBlock b, hipStream_t s) {
+  if (b.pt == 1)
+    k_fw_diag<T><<<1, 256, 0, s>>>(A, ld, b.c0, 0);
+  else
+    k_fw_diag2<T><<<1, 256, 0, s>>>(A, ld, b.c0);
+  return hipGetLastError();
+}
+
+template <int T, int KC>
+static hipError_t fw_panel(u32* A, int64_t ld, int nt, FwBlock b, hipStream_t s) {
+  if (nt <= b.pt) return hipSuccess;
+  if (b.pt == 1)
+    k_fw_panel<T><<<nt - 1, 256, 0, s>>>(A, ld, b.c0, 0);
+  else
+    k_fw_inner<T, KC, 2><<<(unsigned)(2 * (nt - 2)), 256, 0, s>>>(A, ld, b.c0 / 2, nt, 0, 3, 0);
+  return hipGetLastError();
+}
+
+template <int T, int KC>
+static hipError_t fw_inner(u32* A, int64_t ld, int nt, FwBlock b, int part, int nn, hipStream_t s) {
+  const int64_t count = inner_count(nt, b, part, nn);
+  if (count <= 0) return hipSuccess;
+  if (b.pt == 1)
+    k_fw_inner<T, KC, 1><<<(unsigned)count, 256, 0, s>>>(A, ld, b.c0, nt, 0, part, nn);
+  else
+    k_fw_inner<T, KC, 2><<<(unsigned)count, 256, 0, s>>>(A, ld, b.c0 / 2, nt, 0, part, nn);
+  return hipGetLastError();
+}
+
 #define CHK(x)                              \
   do {                                      \
     hipError_t e_ = (x);                    \
     if (e_ != hipSuccess) return e_;        \
   } while (0)
-  // sync[0] = side stream may start round r+1 (part 1 of round r done);
-  // sync[1] = main stream may start round r+1's interior (its panel done)
+
+// One matrix, rounds over its pivot blocks on one stream.  ev (optional) gets
+// one pair per round around its interior launch.
+template <int T, int KC>
+static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, hipStream_t s,
+                                   hipEvent_t* ev) {
+  std::vector<FwBlock> blk(fw_blocks(nt, pivot_tiles, nullptr));
+  fw_blocks(nt, pivot_tiles, blk.data());
+  for (size_t q = 0; q < blk.size(); q++) {
+    CHK((fw_close<T, KC>(A, ld, blk[q], s)));
+    if (nt <= blk[q].pt) continue;
+    CHK((fw_panel<T, KC>(A, ld, nt, blk[q], s)));
+    if (ev) CHK(hipEventRecord(ev[2 * q], s));
+    CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 0, 0, s)));
+    if (ev) CHK(hipEventRecord(ev[2 * q + 1], s));
+  }
+  return hipSuccess;
+}
+
+// The same rounds with a lookahead: the interior tiles with a row or column
+// in the next pivot block go first (part 1); as soon as they are done, the
+// next round's diagonal block and panel run on the side stream while the rest
+// of this round's interior (part 2) runs on the main stream.  Part 2 neither
+// reads nor writes a tile that the next round's diagonal or panel touches
+// (rows and columns of the next block: the panel also writes the tiles of the
+// current block's rows in those columns, which part 2 does not read), so the
+// two overlap safely.  ev (optional) gets one pair per round around parts 1 + 2.
+template <int T, int KC>
+static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, int pivot_tiles, hipStream_t s,
+                                      hipStream_t side, hipEvent_t* sync, hipEvent_t* ev) {
+  std::vector<FwBlock> blk(fw_blocks(nt, pivot_tiles, nullptr));
+  fw_blocks(nt, pivot_tiles, blk.data());
+  // sync[0] = side stream may start the next round (part 1 of this one done);
+  // sync[1] = main stream may start the next round's interior (its panel done)
   CHK(hipEventRecord(sync[0], s));
   CHK(hipStreamWaitEvent(side, sync[0], 0));
-  k_fw_diag<T><<<1, 256, 0, side>>>(A, ld, 0, 0);
-  k_fw_panel<T><<<nt - 1, 256, 0, side>>>(A, ld, 0, 0);
+  CHK((fw_close<T, KC>(A, ld, blk[0], side)));
+  CHK((fw_panel<T, KC>(A, ld, nt, blk[0], side)));
   CHK(hipEventRecord(sync[1], side));
-  for (int r = 0; r < nt; r++) {
+  for (size_t q = 0; q < blk.size(); q++) {
     CHK(hipStreamWaitEvent(s, sync[1], 0));
-    if (ev) CHK(hipEventRecord(ev[2 * r], s));
-    if (r + 1 < nt) {
-      k_fw_inner<T, KC><<<(unsigned)nt - 1, 256, 0, s>>>(A, ld, r, nt, 0, 1);
+    if (nt <= blk[q].pt) continue;  // a single block: closed, nothing else
+    if (ev) CHK(hipEventRecord(ev[2 * q], s));
+    if (q + 1 < blk.size()) {
+      const int nn = blk[q + 1].pt;
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 1, nn, s)));
       CHK(hipEventRecord(sync[0], s));
       CHK(hipStreamWaitEvent(side, sync[0], 0));
-      k_fw_diag<T><<<1, 256, 0, side>>>(A, ld, r + 1, 0);
-      k_fw_panel<T><<<nt - 1, 256, 0, side>>>(A, ld, r + 1, 0);
-      if (nt > 2)
-        k_fw_inner<T, KC><<<(unsigned)((nt - 2) * (nt - 1) / 2), 256, 0, s>>>(A, ld, r, nt, 0, 2);
+      CHK((fw_close<T, KC>(A, ld, blk[q + 1], side)));
+      CHK((fw_panel<T, KC>(A, ld, nt, blk[q + 1], side)));
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 2, nn, s)));
       CHK(hipEventRecord(sync[1], side));
     } else {
       // last round: nothing to look ahead to
-      k_fw_inner<T, KC><<<(unsigned)((nt - 1) * nt / 2), 256, 0, s>>>(A, ld, r, nt, 0, 0);
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 0, 0, s)));
     }
-    if (ev) CHK(hipEventRecord(ev[2 * r + 1], s));
+    if (ev) CHK(hipEventRecord(ev[2 * q + 1], s));
   }
-#undef CHK
-  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+int fw_rounds_count(int nt, int tile, int pivot) {
+  return fw_blocks(nt, pivot / tile, nullptr);
 }
 
 hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev,
-                           int kc) {
-  return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev, kc);
+                           int kc, int pivot) {
+  if (pivot == 0 || pivot == tile) return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev, kc);
+  if (nt <= 0) return hipSuccess;
+  if (kc == 0) kc = SPQ_INNER_KC;
+  if (tile == 64)
+    return kc == 32 ? fw_rounds_blocks<64, 32>(A, ld, nt, 2, s, ev)
+                    : fw_rounds_blocks<64, 16>(A, ld, nt, 2, s, ev);
+  return kc == 32 ? fw_rounds_blocks<128, 32>(A, ld, nt, 2, s, ev)
+                  : fw_rounds_blocks<128, 16>(A, ld, nt, 2, s, ev);
 }
 
 hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
-                                     hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc) {
-  if (nt <= 1) return launch_dense_fw(A, ld, tile, nt, s, ev, kc);
+                                     hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc,
+                                     int pivot) {
+  if (nt <= 0) return hipSuccess;
+  const int pt = (pivot == 0 || pivot == tile) ? 1 : 2;
   if (kc == 0) kc = SPQ_INNER_KC;
   if (tile == 64)
-    return kc == 32 ? fw_rounds_lookahead<64, 32>(A, ld, nt, s, side, sync, ev)
-                    : fw_rounds_lookahead<64, 16>(A, ld, nt, s, side, sync, ev);
-  return kc == 32 ? fw_rounds_lookahead<128, 32>(A, ld, nt, s, side, sync, ev)
-                  : fw_rounds_lookahead<128, 16>(A, ld, nt, s, side, sync, ev);
+    return kc == 32 ? fw_rounds_lookahead<64, 32>(A, ld, nt, pt, s, side, sync, ev)
+                    : fw_rounds_lookahead<64, 16>(A, ld, nt, pt, s, side, sync, ev);
+  return kc == 32 ? fw_rounds_lookahead<128, 32>(A, ld, nt, pt, s, side, sync, ev)
+                  : fw_rounds_lookahead<128, 16>(A, ld, nt, pt, s, side, sync, ev);
 }
+#undef CHK
 
 // kc: K chunk of the interior-tile kernel (16 or 32; 0 = SPQ_INNER_KC)
 hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
@@ -254,9 +419,24 @@ hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch
                   : fw_rounds<128, 16>(A, ld, nt, batch, gstride, s, ev);
 }
 
-double dense_fw_exec_relax(int64_t nt, int tile) {
+// Executed relaxations: per round the diagonal block (one tile: T^3; two:
+// six T^3 products and closures), the panel (each of its tiles K = block
+// rows) and the upper-triangle interior tiles; `inner` gets the interior part.
+double dense_fw_exec_relax(int64_t nt, int tile, int pivot, double* inner) {
   const double t3 = (double)tile * tile * tile;
-  return (double)nt * t3 * (1.0 + (nt - 1) + (double)(nt - 1) * nt / 2.0);
+  std::vector<FwBlock> blk(fw_blocks((int)nt, (pivot == 0 || pivot == tile) ? 1 : 2, nullptr));
+  fw_blocks((int)nt, (pivot == 0 || pivot == tile) ? 1 : 2, blk.data());
+  double all = 0, in = 0;
+  for (const FwBlock& b : blk) {
+    all += (b.pt == 1 ? 1.0 : 6.0) * t3;
+    if (nt <= b.pt) continue;
+    all += (double)b.pt * (nt - b.pt) * b.pt * t3;
+    const double x = (double)tri_count(nt - b.pt) * b.pt * t3;
+    all += x;
+    in += x;
+  }
+  if (inner) *inner = in;
+  return all;
 }
 
 }  // namespace spq

@@ -171,21 +171,24 @@ hipError_t launch_components(const CompArgs& a, hipStream_t s);
 hipError_t launch_comp_fw(int32_t count, const int32_t* order, const int32_t* P, const int64_t* moff,
                           u32* M, hipStream_t s);
 hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s);
-// ev: NULL, or 2*nt events recorded around each interior-tile launch;
-// kc: K chunk of the interior-tile kernel, 16 or 32 (0 = default)
+// ev: NULL, or two events per round recorded around its interior-tile
+// launch(es); kc: K chunk of the interior-tile kernel, 16 or 32 (0 = default);
+// pivot: rows per pivot block, the tile (or 0) or twice the tile (see fw.hip)
 hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev,
-                           int kc = 0);
-// `batch` matrices of the same shape, gstride elements apart
+                           int kc = 0, int pivot = 0);
+// `batch` matrices of the same shape, gstride elements apart (one-tile pivots)
 hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
                                  hipStream_t s, hipEvent_t* ev, int kc = 0);
 // Same closure with a lookahead over two streams (side: created by the caller,
-// default priority; sync: two events).  ev: NULL or 2*nt events, one pair
-// per round around its interior.
+// default priority; sync: two events).
 hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
-                                     hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc);
+                                     hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc,
+                                     int pivot = 0);
+// rounds of a single-matrix closure (pivot blocks)
+int fw_rounds_count(int nt, int tile, int pivot);
 // relaxations executed by launch_dense_fw (diagonal, panel and upper-triangle
-// interior tiles of every round)
-double dense_fw_exec_relax(int64_t nt, int tile);
+// interior tiles of every round); *inner (optional) = the interior part
+double dense_fw_exec_relax(int64_t nt, int tile, int pivot = 0, double* inner = nullptr);
 hipError_t launch_query(const QueryArgs& a, hipStream_t s);
 // Adjacency of G (both directions, self-loops dropped) as rowptr[n+1] and
 // (neighbour, edge index) pairs; deg[n] zeroed scratch.

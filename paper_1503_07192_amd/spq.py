@@ -39,7 +39,8 @@ class BuildOpts(ctypes.Structure):
                 ("plain", ctypes.c_int32), ("bg_method", ctypes.c_int32),
                 ("group_comps", ctypes.c_int32), ("share_comps", ctypes.c_int32),
                 ("inner_kc", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("level3_groups", ctypes.c_int32), ("group_bg", ctypes.c_int32)]
+                ("level3_groups", ctypes.c_int32), ("group_bg", ctypes.c_int32),
+                ("bg_pivot", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -79,7 +80,7 @@ _SIGS = {
     "spq_release_cached_memory": (None, []),
     "spq_last_error": (ctypes.c_char_p, []),
     "spq_fw_components": (I32, [I32, P, P, P, P, P]),
-    "spq_fw_dense": (I32, [I32, I32, I32, I32, P, P]),
+    "spq_fw_dense": (I32, [I32, I32, I32, I32, I32, P, P]),
 }
 
 
@@ -164,7 +165,8 @@ class Index:
 
 def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg_method=0,
                 group_comps=0, share_comps=0, inner_kc=0, lookahead=True, graph=False,
-                level3_groups=0, group_bg=0, paths=False, tune_cache=None, stream=None) -> Index:
+                level3_groups=0, group_bg=0, paths=False, bg_pivot=0, tune_cache=None,
+                stream=None) -> Index:
     """Algorithm 1 on device tensors; see spq_build_index.
 
     graph: capture Phases 2-3 as HIP graphs kept for reweight().
@@ -182,12 +184,14 @@ def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg
         group_comps = group_comps or tuned.get("group_comps", 0)
         level3_groups = level3_groups or tuned.get("level3_groups", 0)
         group_bg = group_bg or tuned.get("group_bg", 0)
+        bg_pivot = bg_pivot or tuned.get("bg_pivot", 0)
     opts = BuildOpts(bg_tile=bg_tile, profile=int(bool(profile)), plain=int(bool(plain)),
                      bg_method=int(bg_method), group_comps=int(group_comps),
                      share_comps=int(share_comps), inner_kc=int(inner_kc),
                      flags=(0 if lookahead else SPQ_NO_LOOKAHEAD) | (SPQ_GRAPH if graph else 0) |
                      (SPQ_PATHS if paths else 0),
-                     level3_groups=int(level3_groups), group_bg=int(group_bg))
+                     level3_groups=int(level3_groups), group_bg=int(group_bg),
+                     bg_pivot=int(bg_pivot))
     h = ctypes.c_void_p()
     m = int(eu.numel())
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),
@@ -285,7 +289,7 @@ def fw_components(size, off, ld, data, stream=None):
     return data
 
 
-def fw_dense(v, ld, tile, data, stream=None, kc=0):
-    _check(load().spq_fw_dense(int(v), int(ld), int(tile), int(kc), _dev_i32(data, "data"),
-                               _stream(stream)))
+def fw_dense(v, ld, tile, data, stream=None, kc=0, pivot=0):
+    _check(load().spq_fw_dense(int(v), int(ld), int(tile), int(pivot), int(kc),
+                               _dev_i32(data, "data"), _stream(stream)))
     return data

@@ -28,14 +28,20 @@ def test_argument_errors_without_device():
     assert L.spq_build_index(5, 0, None, None, None, ctypes.c_void_p(8), 2, ctypes.byref(opts),
                              None, ctypes.byref(h)) == 1
     assert "bg_tile" in spq.last_error()
+    opts = spq.BuildOpts(bg_pivot=192)
+    assert L.spq_build_index(5, 0, None, None, None, ctypes.c_void_p(8), 2, ctypes.byref(opts),
+                             None, ctypes.byref(h)) == 1
+    assert "bg_pivot" in spq.last_error()
     assert L.spq_build_index(5, 0, None, None, None, None, 2, None, None, None) == 1
     assert L.spq_query_batch(None, 3, None, None, None, None) == 1
     assert L.spq_query_batch_host(None, 3, None, None, None) == 1
     assert L.spq_query_paths(None, 3, None, None, 8, None, None, None) == 1
-    assert L.spq_fw_dense(10, 10, 3, 0, None, None) == 1
-    assert L.spq_fw_dense(10, 8, 64, 0, None, None) == 1
-    assert L.spq_fw_dense(10, 64, 64, 8, None, None) == 1
-    assert L.spq_fw_dense(0, 0, 64, 0, None, None) == 0
+    assert L.spq_fw_dense(10, 10, 3, 0, 0, None, None) == 1
+    assert L.spq_fw_dense(10, 8, 64, 0, 0, None, None) == 1
+    assert L.spq_fw_dense(10, 64, 64, 0, 8, None, None) == 1
+    assert L.spq_fw_dense(10, 128, 64, 256, 0, None, None) == 1
+    assert "pivot" in spq.last_error()
+    assert L.spq_fw_dense(0, 0, 64, 128, 0, None, None) == 0
     assert L.spq_fw_components(-1, None, None, None, None, None) == 1
     assert L.spq_index_stats(None, None) == 1
     assert L.spq_reweight_index(None, None, None) == 1
