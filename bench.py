@@ -22,10 +22,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz; a relaxation costs one
-# add and half of a three-input min (1.5 VALU operations) in the kernels.
-VALU_OPS_PER_S = 256 * 64 * 2.4e9
-RELAX_PEAK = VALU_OPS_PER_S / 1.5
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-cycles/s.  A relaxation
+# is one v_add_u32 and half a v_min3_u32 (two candidates per min3).  gfx950
+# issues v_add_u32 at two lane-operations per lane-cycle and v_min3_u32 at one
+# (measured every run by spq_valu_rates, reported as valu_rates), so a
+# relaxation costs 1/2 + 1/2 lane-cycle: 3.93e13 relaxations/s.  (Counting
+# every instruction at one per lane-cycle would give 2.62e13, which the
+# kernels exceed.)
+LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
+RELAX_PEAK = LANE_CYCLES_PER_S * 1.0
 HBM_PEAK = 8.0e12
 
 
@@ -355,6 +360,13 @@ def main():
                            "traffic_unit": "HBM bytes per launch of the step's batch (rocprofv3 "
                                            "FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy)"},
     }
+    # instruction issue rates behind the peak, measured after the timed region
+    vr = spq.valu_rates(stream)
+    line["valu_rates"] = {
+        "v_add_u32_lane_ops_per_s": vr["v_add_u32"], "v_min3_u32_lane_ops_per_s": vr["v_min3_u32"],
+        "per_lane_cycle": {"v_add_u32": vr["v_add_u32"] / LANE_CYCLES_PER_S,
+                           "v_min3_u32": vr["v_min3_u32"] / LANE_CYCLES_PER_S},
+        "relax_loop_per_s": vr["relax_loop"], "relax_loop_frac": vr["relax_loop"] / RELAX_PEAK}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, st, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -92,8 +92,9 @@ typedef struct {
   int32_t bg_pivot;      /* rows per pivot block of the flat BG Floyd-Warshall
                           (each round closes one block, then updates every
                           other tile through it): 0 default (two tiles: 256
-                          with 128-tiles, 64 with 64-tiles), the tile, or
-                          twice the tile.  The answers do not depend on it */
+                          with 128-tiles), or 1, 2 or 4 tiles (the last blocks
+                          of a matrix may be smaller).  The answers do not
+                          depend on it */
 } spq_build_opts;
 
 #define SPQ_NO_LOOKAHEAD 1
@@ -295,13 +296,26 @@ const char* spq_last_error(void);
  *   and 0 on it.  One workgroup closes one whole matrix (the APSP(C) kernel).
  * spq_fw_dense: one v x v matrix with leading dimension ld (a multiple of
  *   tile, padded like above); blocked Floyd-Warshall in rounds over pivot
- *   blocks of `pivot` rows (the BG kernels).  tile is 64 or 128; pivot is the
- *   tile or twice the tile (0: the tile); kc (K chunk of the interior kernel)
- *   is 0 (default), 16 or 32.
+ *   blocks of `pivot` rows (the BG kernels).  tile is 64 or 128; pivot is 1,
+ *   2 or 4 tiles (0: one tile); kc (K chunk of the interior kernel) is 0
+ *   (default), 16 or 32.
  * spq_fw_components stages its size tables on the device and returns when
  * the work is done; spq_fw_dense is asynchronous on `stream`.
  * Errors: SPQ_EINVAL, SPQ_ENOMEM, SPQ_EDEVICE.
  */
+/*
+ * Measurement hook: issue rates of the VALU instructions the min-plus kernels
+ * are built from, on the current device (8 workgroups of 256 lanes per CU,
+ * timed with HIP events on `stream`; about 0.1 s; synchronous).
+ *   out[0]  v_add_u32 lane-operations per second (independent chains)
+ *   out[1]  v_min3_u32 lane-operations per second (independent chains)
+ *   out[2]  relaxations per second of the kernels' inner loop on LDS
+ *           operands (no global memory in the loop)
+ * A relaxation is one add and half a min3, so out[0] and out[1] give the
+ * relaxation peak.  Errors: SPQ_EINVAL (out NULL), SPQ_ENOMEM, SPQ_EDEVICE.
+ */
+spq_status spq_valu_rates(double* out, void* stream);
+
 spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* off,
                              const int32_t* ld, int32_t* data, void* stream);
 spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int32_t kc, int32_t* data,

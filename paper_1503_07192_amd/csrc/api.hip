@@ -447,8 +447,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       return fail(SPQ_EINVAL, "bg_tile must be 0, 64 or 128");
     if (opts->bg_tile) tile = opts->bg_tile;
     pivot = opts->bg_pivot;
-    if (pivot != 0 && pivot != tile && pivot != 2 * tile)
-      return fail(SPQ_EINVAL, "bg_pivot must be 0, the tile or twice the tile");
+    if (pivot != 0 && pivot != tile && pivot != 2 * tile && pivot != 4 * tile)
+      return fail(SPQ_EINVAL, "bg_pivot must be 0 or 1, 2 or 4 tiles");
     profile = opts->profile != 0;
     plain = opts->plain != 0;
     method_opt = opts->bg_method;
@@ -1251,13 +1251,46 @@ spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* 
 spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int32_t kc,
                         int32_t* data, void* stream) {
   if (tile != 64 && tile != 128) return fail(SPQ_EINVAL, "tile must be 64 or 128");
-  if (pivot != 0 && pivot != tile && pivot != 2 * tile)
-    return fail(SPQ_EINVAL, "pivot must be 0, the tile or twice the tile");
+  if (pivot != 0 && pivot != tile && pivot != 2 * tile && pivot != 4 * tile)
+    return fail(SPQ_EINVAL, "pivot must be 0 or 1, 2 or 4 tiles");
   if (kc != 0 && kc != 16 && kc != 32) return fail(SPQ_EINVAL, "kc must be 0, 16 or 32");
   if (v < 0 || ld < v || ld % tile || (v > 0 && !data)) return fail(SPQ_EINVAL, "bad v or ld");
   if (v == 0) return SPQ_OK;
   HIP_TRY(spq::launch_dense_fw(reinterpret_cast<u32*>(data), ld, tile, ld / tile,
                                reinterpret_cast<hipStream_t>(stream), nullptr, kc, pivot));
+  return SPQ_OK;
+}
+
+// Measured VALU issue rates (see spq.h).
+spq_status spq_valu_rates(double* out, void* stream) {
+  if (!out) return fail(SPQ_EINVAL, "out is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int blocks = 8 * std::max(cus, 1);
+  u32* buf = nullptr;
+  HIP_TRY(dalloc(&buf, (int64_t)blocks * 256));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const int iters[3] = {4000, 4000, 1000};
+  for (int kind = 0; kind < 3 && e == hipSuccess; kind++) {
+    e = spq::launch_valu_probe(kind, blocks, iters[kind] / 10, buf, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = spq::launch_valu_probe(kind, blocks, iters[kind], buf, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    const double lanes = (double)blocks * 256.0;
+    const double work = kind < 2 ? lanes * iters[kind] * 32.0 : lanes * 64.0 * 16.0 * iters[kind];
+    if (e == hipSuccess) out[kind] = ms > 0 ? work / (ms * 1e-3) : 0.0;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  pool_release(buf);
+  HIP_TRY(e);
   return SPQ_OK;
 }
 

@@ -83,8 +83,8 @@ __device__ __forceinline__ void tri_index(int b, int m, int& bi, int& bj) {
 #define SPQ_INNER_ATTR
 #endif
 //
-// The pivot block is tiles [c0, c0 + PT), c0 = r * PT; nn = tiles of the next
-// block (parts 1 and 2).  part selects the tiles of the launch:
+// The pivot block is tiles [c0, c0 + PT); nn = tiles of the next block
+// (parts 1 and 2).  part selects the tiles of the launch:
 //   0  every tile outside the pivot block (i <= j)
 //   1  the tiles with a row or column in the next block (what the next
 //      round's diagonal and panel read)
@@ -121,14 +121,13 @@ __device__ __forceinline__ void inner_tile(int part, int b, int c0, int nt, int 
 }
 
 template <int T, int KC, int PT>
-__global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict__ A, int64_t ld, int r, int nt,
+__global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict__ A, int64_t ld, int c0, int nt,
                                                                 int64_t gstride, int part, int nn) {
   constexpr int Q = KC * T / 4 / 256;  // uint4 per thread per operand chunk
   static_assert(Q >= 1 && KC * T / 4 % 256 == 0, "chunk must split evenly");
   __shared__ __attribute__((aligned(16))) u32 sA[2][KC * T];
   __shared__ __attribute__((aligned(16))) u32 sB[2][KC * T];
   A += (int64_t)blockIdx.y * gstride;
-  const int c0 = r * PT;
   int i, j;
   inner_tile<PT>(part, (int)blockIdx.x, c0, nt, nn, i, j);
   const u32* Ar = A + (int64_t)c0 * T * ld + (int64_t)i * T;  // block rows, tile column i
@@ -256,8 +255,8 @@ static hipError_t fw_rounds(u32* A, int64_t ld, int nt, int batch, int64_t gstri
   LAUNCH_CHECK();
 }
 
-// Pivot blocks of a single matrix: two tiles each (the last one a single tile
-// when nt is odd) or one tile each.
+// Pivot blocks of a single matrix: pivot_tiles (1, 2 or 4) tiles each; the
+// tiles left at the end form blocks of two and one.
 struct FwBlock {
   int c0, pt;
 };
@@ -265,7 +264,8 @@ struct FwBlock {
 static int fw_blocks(int nt, int pivot_tiles, FwBlock* out) {
   int nb = 0;
   for (int c0 = 0; c0 < nt; nb++) {
-    const int pt = (pivot_tiles == 2 && c0 + 1 < nt) ? 2 : 1;
+    int pt = pivot_tiles;
+    while (pt > nt - c0) pt >>= 1;
     if (out) out[nb] = FwBlock{c0, pt};
     c0 += pt;
   }
@@ -282,21 +282,33 @@ static int64_t inner_count(int nt, FwBlock b, int part, int nn) {
 }
 
 template <int T, int KC>
+static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, hipStream_t s,
+                                   hipEvent_t* ev);
+
+// Closes the diagonal block: one tile, two tiles in one workgroup, or four
+// tiles by the rounds of this file over two-tile blocks (on the sub-matrix).
+template <int T, int KC>
 static hipError_t fw_close(u32* A, int64_t ld, FwBlock b, hipStream_t s) {
   if (b.pt == 1)
     k_fw_diag<T><<<1, 256, 0, s>>>(A, ld, b.c0, 0);
-  else
+  else if (b.pt == 2)
     k_fw_diag2<T><<<1, 256, 0, s>>>(A, ld, b.c0);
+  else
+    return fw_rounds_blocks<T, KC>(A + (int64_t)b.c0 * T * ld + (int64_t)b.c0 * T, ld, b.pt, 2, s,
+                                   nullptr);
   return hipGetLastError();
 }
 
 template <int T, int KC>
 static hipError_t fw_panel(u32* A, int64_t ld, int nt, FwBlock b, hipStream_t s) {
   if (nt <= b.pt) return hipSuccess;
+  const unsigned count = (unsigned)(b.pt * (nt - b.pt));
   if (b.pt == 1)
     k_fw_panel<T><<<nt - 1, 256, 0, s>>>(A, ld, b.c0, 0);
+  else if (b.pt == 2)
+    k_fw_inner<T, KC, 2><<<count, 256, 0, s>>>(A, ld, b.c0, nt, 0, 3, 0);
   else
-    k_fw_inner<T, KC, 2><<<(unsigned)(2 * (nt - 2)), 256, 0, s>>>(A, ld, b.c0 / 2, nt, 0, 3, 0);
+    k_fw_inner<T, KC, 4><<<count, 256, 0, s>>>(A, ld, b.c0, nt, 0, 3, 0);
   return hipGetLastError();
 }
 
@@ -306,8 +318,10 @@ static hipError_t fw_inner(u32* A, int64_t ld, int nt, FwBlock b, int part, int 
   if (count <= 0) return hipSuccess;
   if (b.pt == 1)
     k_fw_inner<T, KC, 1><<<(unsigned)count, 256, 0, s>>>(A, ld, b.c0, nt, 0, part, nn);
+  else if (b.pt == 2)
+    k_fw_inner<T, KC, 2><<<(unsigned)count, 256, 0, s>>>(A, ld, b.c0, nt, 0, part, nn);
   else
-    k_fw_inner<T, KC, 2><<<(unsigned)count, 256, 0, s>>>(A, ld, b.c0 / 2, nt, 0, part, nn);
+    k_fw_inner<T, KC, 4><<<(unsigned)count, 256, 0, s>>>(A, ld, b.c0, nt, 0, part, nn);
   return hipGetLastError();
 }
 
@@ -377,27 +391,30 @@ static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, int pivot_tile
   return hipSuccess;
 }
 
+static int pivot_tiles_of(int tile, int pivot) { return pivot <= tile ? 1 : pivot / tile; }
+
 int fw_rounds_count(int nt, int tile, int pivot) {
-  return fw_blocks(nt, pivot / tile, nullptr);
+  return fw_blocks(nt, pivot_tiles_of(tile, pivot), nullptr);
 }
 
 hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev,
                            int kc, int pivot) {
-  if (pivot == 0 || pivot == tile) return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev, kc);
+  const int pt = pivot_tiles_of(tile, pivot);
+  if (pt == 1) return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev, kc);
   if (nt <= 0) return hipSuccess;
   if (kc == 0) kc = SPQ_INNER_KC;
   if (tile == 64)
-    return kc == 32 ? fw_rounds_blocks<64, 32>(A, ld, nt, 2, s, ev)
-                    : fw_rounds_blocks<64, 16>(A, ld, nt, 2, s, ev);
-  return kc == 32 ? fw_rounds_blocks<128, 32>(A, ld, nt, 2, s, ev)
-                  : fw_rounds_blocks<128, 16>(A, ld, nt, 2, s, ev);
+    return kc == 32 ? fw_rounds_blocks<64, 32>(A, ld, nt, pt, s, ev)
+                    : fw_rounds_blocks<64, 16>(A, ld, nt, pt, s, ev);
+  return kc == 32 ? fw_rounds_blocks<128, 32>(A, ld, nt, pt, s, ev)
+                  : fw_rounds_blocks<128, 16>(A, ld, nt, pt, s, ev);
 }
 
 hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
                                      hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc,
                                      int pivot) {
   if (nt <= 0) return hipSuccess;
-  const int pt = (pivot == 0 || pivot == tile) ? 1 : 2;
+  const int pt = pivot_tiles_of(tile, pivot);
   if (kc == 0) kc = SPQ_INNER_KC;
   if (tile == 64)
     return kc == 32 ? fw_rounds_lookahead<64, 32>(A, ld, nt, pt, s, side, sync, ev)
@@ -420,15 +437,17 @@ hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch
 }
 
 // Executed relaxations: per round the diagonal block (one tile: T^3; two:
-// six T^3 products and closures), the panel (each of its tiles K = block
-// rows) and the upper-triangle interior tiles; `inner` gets the interior part.
+// six T^3 products and closures; four: the rounds over two-tile blocks on
+// it), the panel (each of its tiles K = block rows) and the upper-triangle
+// interior tiles; `inner` gets the interior part.
 double dense_fw_exec_relax(int64_t nt, int tile, int pivot, double* inner) {
   const double t3 = (double)tile * tile * tile;
-  std::vector<FwBlock> blk(fw_blocks((int)nt, (pivot == 0 || pivot == tile) ? 1 : 2, nullptr));
-  fw_blocks((int)nt, (pivot == 0 || pivot == tile) ? 1 : 2, blk.data());
+  const int ptiles = pivot_tiles_of(tile, pivot);
+  std::vector<FwBlock> blk(fw_blocks((int)nt, ptiles, nullptr));
+  fw_blocks((int)nt, ptiles, blk.data());
   double all = 0, in = 0;
   for (const FwBlock& b : blk) {
-    all += (b.pt == 1 ? 1.0 : 6.0) * t3;
+    all += b.pt == 1 ? t3 : b.pt == 2 ? 6.0 * t3 : dense_fw_exec_relax(b.pt, tile, 2 * tile, nullptr);
     if (nt <= b.pt) continue;
     all += (double)b.pt * (nt - b.pt) * b.pt * t3;
     const double x = (double)tri_count(nt - b.pt) * b.pt * t3;

@@ -81,6 +81,7 @@ _SIGS = {
     "spq_last_error": (ctypes.c_char_p, []),
     "spq_fw_components": (I32, [I32, P, P, P, P, P]),
     "spq_fw_dense": (I32, [I32, I32, I32, I32, I32, P, P]),
+    "spq_valu_rates": (I32, [P, P]),
 }
 
 
@@ -293,3 +294,11 @@ def fw_dense(v, ld, tile, data, stream=None, kc=0, pivot=0):
     _check(load().spq_fw_dense(int(v), int(ld), int(tile), int(pivot), int(kc),
                                _dev_i32(data, "data"), _stream(stream)))
     return data
+
+
+def valu_rates(stream=None):
+    """Measured issue rates on the current device, see spq_valu_rates:
+    {"v_add_u32": lane-ops/s, "v_min3_u32": lane-ops/s, "relax_loop": relax/s}."""
+    out = (ctypes.c_double * 3)()
+    _check(load().spq_valu_rates(out, _stream(stream)))
+    return {"v_add_u32": out[0], "v_min3_u32": out[1], "relax_loop": out[2]}

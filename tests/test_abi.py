@@ -39,10 +39,11 @@ def test_argument_errors_without_device():
     assert L.spq_fw_dense(10, 10, 3, 0, 0, None, None) == 1
     assert L.spq_fw_dense(10, 8, 64, 0, 0, None, None) == 1
     assert L.spq_fw_dense(10, 64, 64, 0, 8, None, None) == 1
-    assert L.spq_fw_dense(10, 128, 64, 256, 0, None, None) == 1
+    assert L.spq_fw_dense(10, 128, 64, 192, 0, None, None) == 1
     assert "pivot" in spq.last_error()
     assert L.spq_fw_dense(0, 0, 64, 128, 0, None, None) == 0
     assert L.spq_fw_components(-1, None, None, None, None, None) == 1
+    assert L.spq_valu_rates(None, None) == 1
     assert L.spq_index_stats(None, None) == 1
     assert L.spq_reweight_index(None, None, None) == 1
     part = ctypes.c_void_p(8)

@@ -156,13 +156,14 @@ def test_fw_components_kernel(wname, wlo, whi):
         assert np.array_equal(g[:N, :N], oracle_closure(m, N)), "N=%d" % N
 
 
-@pytest.mark.parametrize("pivot", [1, 2])
+@pytest.mark.parametrize("pivot", [1, 2, 4])
 @pytest.mark.parametrize("kc", [16, 32])
 @pytest.mark.parametrize("tile", [64, 128])
 @pytest.mark.parametrize("v", [1, 5, 64, 100, 129, 300, 520, 700])
 def test_fw_dense_kernel(tile, v, kc, pivot):
-    # pivot blocks of one or two tiles; with two, odd tile counts end on a
-    # one-tile block (128-tiles: 3, 5 and 6 tiles; 64-tiles: up to 11)
+    # pivot blocks of one, two or four tiles; the tiles left at the end form
+    # smaller blocks (128-tiles: 1-6 tiles, e.g. 4 + 2; 64-tiles: up to 11,
+    # 4 + 4 + 2 + 1)
     rng = np.random.default_rng(1000 + v + tile)
     ld = -(-v // tile) * tile
     for wlo, whi in [(0, 3), (1, 10**6), (2**30, INF32 - 1)]:
@@ -288,9 +289,10 @@ def test_grid32_bg_tile_plain_and_repeat_are_bitwise_identical():
     assert np.array_equal(ra, re) and np.array_equal(ra, rf)
     # pivot blocks of one tile, and of two without the lookahead (3 tiles of
     # 128: a two-tile block, then a one-tile block; 6 tiles of 64: three blocks)
-    for kw in ({"bg_pivot": 128}, {"bg_pivot": 256, "lookahead": False},
+    for kw in ({"bg_pivot": 128}, {"bg_pivot": 256, "lookahead": False}, {"bg_pivot": 256},
                {"bg_tile": 64, "bg_pivot": 64}, {"bg_tile": 64, "bg_pivot": 128, "lookahead": False},
-               {"bg_pivot": 256, "inner_kc": 32}):
+               {"bg_tile": 64, "bg_pivot": 256}, {"bg_tile": 64, "bg_pivot": 256, "lookahead": False},
+               {"bg_pivot": 512, "inner_kc": 32}):
         x = build(g, **kw)
         assert np.array_equal(spq.index_bg_rows(x, 0, 348, 348), ra), kw
     for comp in range(16):
@@ -471,12 +473,13 @@ def test_grid256d_two_level_equals_flat():
     for r, want in zip(rows, rf):
         assert np.array_equal(spq.index_bg_rows(plain, int(r), 1, 27_900), want)
     plain.free()
-    # pivot blocks of one tile (218 rounds) instead of two (109)
-    one = build(g, bg_method=1, bg_pivot=128)
-    assert np.array_equal(run_queries(one, g["v1"], g["v2"]), qf)
-    for r, want in zip(rows, rf):
-        assert np.array_equal(spq.index_bg_rows(one, int(r), 1, 27_900), want)
-    one.free()
+    # pivot blocks of one tile (218 rounds) and four (55) instead of two (109)
+    for pivot in (128, 512):
+        one = build(g, bg_method=1, bg_pivot=pivot)
+        assert np.array_equal(run_queries(one, g["v1"], g["v2"]), qf)
+        for r, want in zip(rows, rf):
+            assert np.array_equal(spq.index_bg_rows(one, int(r), 1, 27_900), want)
+        one.free()
     # 256 groups of 4 components, BG2 closed by 16 super-groups (level 3)
     three = build(g, bg_method=2, group_comps=4, level3_groups=16)
     st = spq.index_stats(three)
