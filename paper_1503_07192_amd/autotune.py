@@ -51,7 +51,8 @@ def candidates(v_bg: int, k: int, share_comps: int):
     if v_bg <= 32768 and not share_comps:
         for tile in (128, 64):
             for kc in (16, 32):
-                out.append({"bg_method": 1, "bg_tile": tile, "inner_kc": kc})
+                for pt in (2, 4):
+                    out.append({"bg_method": 1, "bg_tile": tile, "inner_kc": kc, "bg_pivot": pt * tile})
     cpg = 8
     while cpg <= min(256, k):
         for kc in (16, 32):
