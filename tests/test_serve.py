@@ -134,5 +134,6 @@ def test_autotune_cache_lookup(tmp_path, monkeypatch):
     assert autotune.lookup(str(path), 1024, 1984, 16, 0) == {}
     assert autotune.lookup(str(tmp_path / "missing.json"), 1, 1, 1) == {}
     c = autotune.candidates(27900, 1024, 0)
-    assert {"bg_method": 1, "bg_tile": 128, "inner_kc": 16} in c
+    assert {"bg_method": 1, "bg_tile": 128, "inner_kc": 16, "bg_pivot": 256} in c
+    assert {"bg_method": 1, "bg_tile": 64, "inner_kc": 32, "bg_pivot": 256} in c
     assert all(o["bg_method"] == 2 for o in autotune.candidates(255422, 4096, 0))
