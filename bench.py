@@ -362,8 +362,11 @@ def main():
     }
     # instruction issue rates behind the peak, measured after the timed region
     vr = spq.valu_rates(stream)
-    line["valu_rates"] = {k: dict(v) for k, v in vr.items()}
-    line["valu_rates"]["relax_loop"]["frac_of_peak"] = vr["relax_loop"]["per_s"] / RELAX_PEAK
+    line["valu_rates"] = {
+        "v_add_u32_lane_ops_per_s": vr["v_add_u32"], "v_min3_u32_lane_ops_per_s": vr["v_min3_u32"],
+        "per_nominal_lane_cycle": {"v_add_u32": vr["v_add_u32"] / LANE_CYCLES_PER_S,
+                                   "v_min3_u32": vr["v_min3_u32"] / LANE_CYCLES_PER_S},
+        "relax_loop_per_s": vr["relax_loop"], "relax_loop_frac": vr["relax_loop"] / RELAX_PEAK}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, st, args.cpu_seconds)
     print(json.dumps(line), flush=True)

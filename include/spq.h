@@ -306,18 +306,13 @@ const char* spq_last_error(void);
 /*
  * Measurement hook: issue rates of the VALU instructions the min-plus kernels
  * are built from, on the current device (8 workgroups of 256 lanes per CU,
- * timed with HIP events on `stream`; about 0.1 s; synchronous).  out holds 9
- * doubles:
+ * timed with HIP events on `stream`; about 0.1 s; synchronous).
  *   out[0]  v_add_u32 lane-operations per second (independent chains)
  *   out[1]  v_min3_u32 lane-operations per second (independent chains)
  *   out[2]  relaxations per second of the kernels' inner loop on LDS
  *           operands (no global memory in the loop)
- *   out[3..5]  the shader clock (Hz) while each of the three ran, from the
- *           shader-clock and 100 MHz real-time counters of the workgroups
- *   out[6..8]  out[0..2] per lane per clock (CUs x 64 lanes x out[3..5])
- * A relaxation is one add and half a min3, so the per-clock rates of the two
- * instructions give the relaxation peak.  Errors: SPQ_EINVAL (out NULL),
- * SPQ_ENOMEM, SPQ_EDEVICE.
+ * A relaxation is one add and half a min3, so out[0] and out[1] bound the
+ * relaxation peak.  Errors: SPQ_EINVAL (out NULL), SPQ_ENOMEM, SPQ_EDEVICE.
  */
 spq_status spq_valu_rates(double* out, void* stream);
 

@@ -1268,45 +1268,28 @@ spq_status spq_valu_rates(double* out, void* stream) {
   int dev = 0, cus = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  cus = std::max(cus, 1);
-  const int blocks = 8 * cus;
+  const int blocks = 8 * std::max(cus, 1);
   u32* buf = nullptr;
-  unsigned long long* clk = nullptr;
   HIP_TRY(dalloc(&buf, (int64_t)blocks * 256));
-  HIP_TRY(dalloc(&clk, 2 * (int64_t)blocks));
-  std::vector<unsigned long long> h(2 * (size_t)blocks);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   const int iters[3] = {4000, 4000, 1000};
   for (int kind = 0; kind < 3 && e == hipSuccess; kind++) {
-    e = spq::launch_valu_probe(kind, blocks, iters[kind] / 4, buf, clk, s);  // warm-up
+    e = spq::launch_valu_probe(kind, blocks, iters[kind] / 4, buf, s);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, s);
-    if (e == hipSuccess) e = spq::launch_valu_probe(kind, blocks, iters[kind], buf, clk, s);
+    if (e == hipSuccess) e = spq::launch_valu_probe(kind, blocks, iters[kind], buf, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e == hipSuccess)
-      e = hipMemcpy(h.data(), clk, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) break;
-    double ticks = 0, real = 0;
-    for (int b = 0; b < blocks; b++) {
-      ticks += (double)h[2 * b];
-      real += (double)h[2 * b + 1];
-    }
-    const double hz = real > 0 ? 1e8 * ticks / real : 0.0;  // real-time counter: 100 MHz
     const double lanes = (double)blocks * 256.0;
     const double work = kind < 2 ? lanes * iters[kind] * 32.0 : lanes * 64.0 * 16.0 * iters[kind];
-    const double rate = ms > 0 ? work / (ms * 1e-3) : 0.0;
-    out[kind] = rate;
-    out[3 + kind] = hz;
-    out[6 + kind] = hz > 0 ? rate / ((double)cus * 64.0 * hz) : 0.0;
+    if (e == hipSuccess) out[kind] = ms > 0 ? work / (ms * 1e-3) : 0.0;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   pool_release(buf);
-  pool_release(clk);
   HIP_TRY(e);
   return SPQ_OK;
 }

@@ -8,27 +8,13 @@
 //   iteration, so nothing waits on a result)
 //   kind 2: the production relaxation loop (minplus_lds of tiles.h) on LDS
 //   operands, no global memory inside the loop
-// Thread 0 of every workgroup records how far the shader clock (s_memtime)
-// and the 100 MHz real-time counter (s_memrealtime) advanced while it ran,
-// so the host can state the rates per clock, whatever clock the device ran.
 #include "spq_internal.h"
 #include "tiles.h"
 
 namespace spq {
 
-__device__ __forceinline__ void clock_mark(unsigned long long* clk, unsigned long long t0,
-                                           unsigned long long r0) {
-  if (threadIdx.x == 0) {
-    const unsigned long long t1 = __builtin_amdgcn_s_memtime(), r1 = __builtin_amdgcn_s_memrealtime();
-    clk[2 * blockIdx.x] = t1 - t0;
-    clk[2 * blockIdx.x + 1] = r1 - r0;
-  }
-}
-
 template <int OP>
-__global__ __launch_bounds__(256) void k_rate(u32* __restrict__ out, unsigned long long* __restrict__ clk,
-                                              int iters, u32 seed) {
-  const unsigned long long t0 = __builtin_amdgcn_s_memtime(), r0 = __builtin_amdgcn_s_memrealtime();
+__global__ __launch_bounds__(256) void k_rate(u32* __restrict__ out, int iters, u32 seed) {
   u32 x[8], y = seed ^ threadIdx.x, z = seed + blockIdx.x;
 #pragma unroll
   for (int i = 0; i < 8; i++) x[i] = threadIdx.x * 7u + i;
@@ -52,12 +38,10 @@ __global__ __launch_bounds__(256) void k_rate(u32* __restrict__ out, unsigned lo
 #pragma unroll
   for (int i = 0; i < 8; i++) s += x[i];
   out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
-  clock_mark(clk, t0, r0);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
-void k_rate_relax(u32* __restrict__ out, unsigned long long* __restrict__ clk, int iters, u32 seed) {
-  const unsigned long long t0 = __builtin_amdgcn_s_memtime(), r0 = __builtin_amdgcn_s_memrealtime();
+void k_rate_relax(u32* __restrict__ out, int iters, u32 seed) {
   __shared__ __attribute__((aligned(16))) u32 sA[16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[16 * 128];
   for (int e = threadIdx.x; e < 16 * 128; e += 256) {
@@ -77,20 +61,17 @@ void k_rate_relax(u32* __restrict__ out, unsigned long long* __restrict__ clk, i
 #pragma unroll
     for (int j = 0; j < 8; j++) s ^= c[i][j];
   out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
-  clock_mark(clk, t0, r0);
 }
 
-// out: blocks * 256 words; clk: 2 * blocks.  Work per launch: kinds 0/1:
-// blocks * 256 lanes * iters * 32 instructions; kind 2: blocks * 256 * 64 *
-// 16 * iters relaxations.
-hipError_t launch_valu_probe(int kind, int blocks, int iters, u32* out, unsigned long long* clk,
-                             hipStream_t s) {
+// out: blocks * 256 words.  Work per launch: kinds 0/1: blocks * 256 lanes *
+// iters * 32 instructions; kind 2: blocks * 256 * 64 * 16 * iters relaxations.
+hipError_t launch_valu_probe(int kind, int blocks, int iters, u32* out, hipStream_t s) {
   if (kind == 0)
-    k_rate<0><<<blocks, 256, 0, s>>>(out, clk, iters, 2u);
+    k_rate<0><<<blocks, 256, 0, s>>>(out, iters, 2u);
   else if (kind == 1)
-    k_rate<1><<<blocks, 256, 0, s>>>(out, clk, iters, 2u);
+    k_rate<1><<<blocks, 256, 0, s>>>(out, iters, 2u);
   else
-    k_rate_relax<<<blocks, 256, 0, s>>>(out, clk, iters, 2u);
+    k_rate_relax<<<blocks, 256, 0, s>>>(out, iters, 2u);
   return hipGetLastError();
 }
 

@@ -191,10 +191,8 @@ int fw_rounds_count(int nt, int tile, int pivot);
 double dense_fw_exec_relax(int64_t nt, int tile, int pivot = 0, double* inner = nullptr);
 hipError_t launch_query(const QueryArgs& a, hipStream_t s);
 // VALU rate probes (probe.hip): kind 0 v_add_u32, 1 v_min3_u32, 2 the
-// relaxation loop on LDS operands; out: blocks * 256 words; clk: 2 * blocks
-// (shader-clock and 100 MHz real-time ticks per workgroup)
-hipError_t launch_valu_probe(int kind, int blocks, int iters, u32* out, unsigned long long* clk,
-                             hipStream_t s);
+// relaxation loop on LDS operands; out: blocks * 256 words
+hipError_t launch_valu_probe(int kind, int blocks, int iters, u32* out, hipStream_t s);
 // Adjacency of G (both directions, self-loops dropped) as rowptr[n+1] and
 // (neighbour, edge index) pairs; deg[n] zeroed scratch.
 hipError_t launch_adjacency(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,

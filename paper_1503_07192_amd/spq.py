@@ -298,10 +298,7 @@ def fw_dense(v, ld, tile, data, stream=None, kc=0, pivot=0):
 
 def valu_rates(stream=None):
     """Measured issue rates on the current device, see spq_valu_rates:
-    per instruction kind ("v_add_u32", "v_min3_u32": lane-ops; "relax_loop":
-    relaxations) the rate per second, the shader clock it ran at and the rate
-    per lane per clock."""
-    out = (ctypes.c_double * 9)()
+    {"v_add_u32": lane-ops/s, "v_min3_u32": lane-ops/s, "relax_loop": relax/s}."""
+    out = (ctypes.c_double * 3)()
     _check(load().spq_valu_rates(out, _stream(stream)))
-    return {k: {"per_s": out[i], "clock_hz": out[3 + i], "per_lane_clock": out[6 + i]}
-            for i, k in enumerate(("v_add_u32", "v_min3_u32", "relax_loop"))}
+    return {"v_add_u32": out[0], "v_min3_u32": out[1], "relax_loop": out[2]}

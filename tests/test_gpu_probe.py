@@ -8,10 +8,8 @@ pytestmark = pytest.mark.gpu
 
 def test_valu_rates_are_measured():
     r = spq.valu_rates()
+    print(r, flush=True)
+    lane_cycles = 256 * 64 * 2.4e9   # MI355X: 256 CUs x 64 lanes x 2.4 GHz
     for kind in ("v_add_u32", "v_min3_u32", "relax_loop"):
-        v = r[kind]
-        print(kind, v, flush=True)
-        assert v["per_s"] > 0
-        assert 0.3e9 < v["clock_hz"] < 4.0e9
-        # at most two lane-operations (relaxations) per lane per clock
-        assert 0 < v["per_lane_clock"] < 2.5
+        # at most two operations (relaxations) per lane and clock
+        assert 0 < r[kind] < 2.2 * lane_cycles
