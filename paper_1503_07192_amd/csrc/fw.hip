@@ -12,16 +12,15 @@ namespace spq {
 #define LAUNCH_CHECK() return hipGetLastError()
 
 // Blocked Floyd-Warshall on one symmetric matrix of nt x nt tiles, in rounds
-// over pivot blocks of one tile (c0 = r) or two tiles (c0 = 2r; the last
-// block is one tile when nt is odd):
-//   k_fw_diag / k_fw_diag2  close the pivot block (a 2 x 2-tile block by a
-//                            blocked Floyd-Warshall inside one workgroup)
-//   panel                    tile (a, j), a in the block, j outside it:
-//                            tile (a, j) = D (x) tile (a, j), stored twice (as
-//                            (a, j) and transposed as (j, a)); k_fw_panel for
-//                            one-tile blocks, k_fw_inner part 3 for two
-//   k_fw_inner               tile (i, j) = min(tile (i, j),
-//                            (block rows, tile i)^T (x) (block rows, tile j))
+// over pivot blocks of one, two or four tiles (the tiles left at the end form
+// smaller blocks):
+//   close    the pivot block: k_fw_diag for one tile; a larger block by the
+//            same rounds on the sub-matrix, over blocks of half its size
+//   panel    tile (a, j), a in the block, j outside it: tile (a, j) =
+//            D (x) tile (a, j), stored twice (as (a, j) and transposed as
+//            (j, a)); k_fw_inner part 3 (the batched closures use k_fw_panel)
+//   interior tile (i, j) = min(tile (i, j),
+//            (block rows, tile i)^T (x) (block rows, tile j)), k_fw_inner
 // A two-tile block doubles the K of every interior product (256 instead of
 // 128 for 128-tiles): the fixed cost of a tile (loading and storing C) is
 // spread over twice the relaxations, and there are half as many rounds.
@@ -179,56 +178,6 @@ __global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict
   if (i != j) tile_store_t<T>(t, A + (int64_t)j * T * ld + (int64_t)i * T, ld);
 }
 
-// Closes the 2T x 2T diagonal block whose first tile is (c0, c0): blocked
-// Floyd-Warshall over its 2 x 2 tiles in one workgroup.  Round 0: close T00,
-// panel T01 = T00 (x) T01, interior T11 = min(T11, T10 (x) T01); round 1:
-// close T11, panel T01 = T01 (x) T11, interior T00 = min(T00, T01 (x) T10).
-// Each panel is computed in place from the old tile; with the diagonal tile
-// closed (zero diagonal) that is the exact panel.  LDS: two T x T tiles.
-template <int T>
-__global__ __launch_bounds__(256) void k_fw_diag2(u32* __restrict__ A, int64_t ld, int c0) {
-  __shared__ __attribute__((aligned(16))) u32 X[T * T];
-  __shared__ __attribute__((aligned(16))) u32 Y[T * T];
-  __shared__ __attribute__((aligned(16))) u32 rb[4 * T];
-  u32* T00 = A + (int64_t)c0 * T * ld + (int64_t)c0 * T;
-  u32* T01 = T00 + T;
-  u32* T10 = T00 + (int64_t)T * ld;
-  u32* T11 = T10 + T;
-  u32 t[T / 16][T / 16];
-  // round 0
-  tile_load<T>(t, T00, ld);
-  fw_tile<T>(t, rb);
-  tile_store<T>(t, T00, ld);
-  tile_to_lds<T>(t, X);                 // X = T00
-  tile_load<T>(t, T01, ld);
-  tile_to_lds<T>(t, Y);                 // Y = T01
-  __syncthreads();
-  minplus_lds<T>(t, X, Y, T);           // T01 = T00 (x) T01
-  __syncthreads();
-  tile_to_lds<T>(t, Y);                 // Y = T01
-  __syncthreads();
-  tile_load<T>(t, T11, ld);
-  minplus_lds<T>(t, Y, Y, T);           // T11 = min(T11, T10 (x) T01)
-  // round 1
-  fw_tile<T>(t, rb);
-  tile_store<T>(t, T11, ld);
-  tile_to_lds<T>(t, X);                 // X = T11 (X is no longer read)
-  __syncthreads();
-  tile_load<T>(t, Y, T);                // t = T01 (round 0)
-  __syncthreads();
-  tile_store_t<T>(t, Y, T);             // Y = T10
-  __syncthreads();
-  minplus_lds<T>(t, Y, X, T);           // T01 = T01 (x) T11
-  tile_store<T>(t, T01, ld);
-  tile_store_t<T>(t, T10, ld);
-  __syncthreads();
-  tile_store_t<T>(t, Y, T);             // Y = T10
-  __syncthreads();
-  tile_load<T>(t, T00, ld);             // closed in round 0, stored above
-  minplus_lds<T>(t, Y, Y, T);           // T00 = min(T00, T01 (x) T10)
-  tile_store<T>(t, T00, ld);
-}
-
 #ifndef SPQ_INNER_KC
 #define SPQ_INNER_KC 16
 #endif
@@ -285,26 +234,31 @@ template <int T, int KC>
 static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, hipStream_t s,
                                    hipEvent_t* ev);
 
-// Closes the diagonal block: one tile, two tiles in one workgroup, or four
-// tiles by the rounds of this file over two-tile blocks (on the sub-matrix).
+// Closes the diagonal block: one tile in one workgroup (k_fw_diag); a block
+// of two or four tiles by the rounds of this file on the sub-matrix, over
+// blocks of half its size.  Every launch of a block closure is small (one to
+// six workgroups of 32 KB LDS at most), so beside a running interior launch
+// it finds room on a CU at once; one workgroup holding two tiles in LDS
+// (130 KB) waited for a whole CU to drain, about as long as the interior.
 template <int T, int KC>
 static hipError_t fw_close(u32* A, int64_t ld, FwBlock b, hipStream_t s) {
-  if (b.pt == 1)
+  if (b.pt == 1) {
     k_fw_diag<T><<<1, 256, 0, s>>>(A, ld, b.c0, 0);
-  else if (b.pt == 2)
-    k_fw_diag2<T><<<1, 256, 0, s>>>(A, ld, b.c0);
-  else
-    return fw_rounds_blocks<T, KC>(A + (int64_t)b.c0 * T * ld + (int64_t)b.c0 * T, ld, b.pt, 2, s,
-                                   nullptr);
-  return hipGetLastError();
+    return hipGetLastError();
+  }
+  return fw_rounds_blocks<T, KC>(A + (int64_t)b.c0 * T * ld + (int64_t)b.c0 * T, ld, b.pt, b.pt / 2,
+                                 s, nullptr);
 }
 
+// The panel of block b: tiles (a, j), a in the block, j outside it, by the
+// interior kernel (part 3; 32 KB LDS, not k_fw_panel's 128 KB, for the same
+// reason as above).
 template <int T, int KC>
 static hipError_t fw_panel(u32* A, int64_t ld, int nt, FwBlock b, hipStream_t s) {
   if (nt <= b.pt) return hipSuccess;
   const unsigned count = (unsigned)(b.pt * (nt - b.pt));
   if (b.pt == 1)
-    k_fw_panel<T><<<nt - 1, 256, 0, s>>>(A, ld, b.c0, 0);
+    k_fw_inner<T, KC, 1><<<count, 256, 0, s>>>(A, ld, b.c0, nt, 0, 3, 0);
   else if (b.pt == 2)
     k_fw_inner<T, KC, 2><<<count, 256, 0, s>>>(A, ld, b.c0, nt, 0, 3, 0);
   else
@@ -436,10 +390,10 @@ hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch
                   : fw_rounds<128, 16>(A, ld, nt, batch, gstride, s, ev);
 }
 
-// Executed relaxations: per round the diagonal block (one tile: T^3; two:
-// six T^3 products and closures; four: the rounds over two-tile blocks on
-// it), the panel (each of its tiles K = block rows) and the upper-triangle
-// interior tiles; `inner` gets the interior part.
+// Executed relaxations: per round the diagonal block (one tile: T^3; more:
+// the rounds over half-size blocks on it), the panel (each of its tiles K =
+// block rows) and the upper-triangle interior tiles; `inner` gets the
+// interior part.
 double dense_fw_exec_relax(int64_t nt, int tile, int pivot, double* inner) {
   const double t3 = (double)tile * tile * tile;
   const int ptiles = pivot_tiles_of(tile, pivot);
@@ -447,7 +401,7 @@ double dense_fw_exec_relax(int64_t nt, int tile, int pivot, double* inner) {
   fw_blocks((int)nt, ptiles, blk.data());
   double all = 0, in = 0;
   for (const FwBlock& b : blk) {
-    all += b.pt == 1 ? t3 : b.pt == 2 ? 6.0 * t3 : dense_fw_exec_relax(b.pt, tile, 2 * tile, nullptr);
+    all += b.pt == 1 ? t3 : dense_fw_exec_relax(b.pt, tile, b.pt / 2 * tile, nullptr);
     if (nt <= b.pt) continue;
     all += (double)b.pt * (nt - b.pt) * b.pt * t3;
     const double x = (double)tri_count(nt - b.pt) * b.pt * t3;
