@@ -93,8 +93,10 @@ typedef struct {
                           (each round closes one block, then updates every
                           other tile through it): 0 default (two tiles: 256
                           with 128-tiles), or 1, 2 or 4 tiles (the last blocks
-                          of a matrix may be smaller).  The answers do not
-                          depend on it */
+                          of a matrix may be smaller).  The other closures
+                          (large components, groups, BG2, super-groups, BG3;
+                          128-tiles) use blocks of as many tiles.  The answers
+                          do not depend on it */
 } spq_build_opts;
 
 #define SPQ_NO_LOOKAHEAD 1

@@ -117,6 +117,7 @@ int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
 struct spq_index {
   int device = 0;
   int32_t n = 0, k = 0, V = 0, Vp = 0, tile = 128, pivot = 256, max_comp = 0, max_nb = 0;
+  int32_t cpivot = 256;  // pivot rows of the 128-tile closures (components, groups, BG2, BG3)
   int64_t m = 0, comp_elems = 0;
   std::vector<int32_t> h_cnt, h_nb, h_off, h_bgoff, h_P, h_order;
   std::vector<int64_t> h_moff;
@@ -486,6 +487,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   X->m = m;
   X->tile = tile;
   X->pivot = pivot ? pivot : 2 * tile;
+  X->cpivot = X->pivot / tile * 128;
   X->graph = use_graph;
   {
     hipError_t e = hipGetDevice(&X->device);
@@ -570,7 +572,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     X->max_nb = std::max(X->max_nb, X->h_nb[c]);
     X->relax_comp += (double)X->h_cnt[c] * X->h_cnt[c] * X->h_cnt[c];
     if (big) {
-      X->relax_comp_exec += spq::dense_fw_exec_relax(X->h_P[c] / 128, 128);
+      X->relax_comp_exec += spq::dense_fw_exec_relax(X->h_P[c] / 128, 128, X->cpivot);
       X->nbig++;
     } else {
       // one workgroup runs the blocked rounds on 64-tiles, i <= j interior tiles only
@@ -634,7 +636,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     }
   } else {
     X->Vgp = std::max<int32_t>(X->Vgp, 128);
-    X->relax_bg_exec = X->ngroups * spq::dense_fw_exec_relax(X->Vgp / 128, 128);
+    X->relax_bg_exec = X->ngroups * spq::dense_fw_exec_relax(X->Vgp / 128, 128, X->cpivot);
   }
   X->h_order.resize(k);
   std::iota(X->h_order.begin(), X->h_order.end(), 0);
@@ -739,7 +741,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     for (int32_t b = 0; b < X->nbig && e == hipSuccess; b++) {
       const int32_t c = X->h_order[b];
       e = spq::launch_dense_fw(X->M + X->h_moff[c], X->h_P[c], 128, X->h_P[c] / 128, st, nullptr,
-                               inner_kc);
+                               inner_kc, X->cpivot);
     }
     if (e != hipSuccess) return e;
     if (plain) {
@@ -772,7 +774,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     TRY(dalloc(&X->bggrp, V));
     // level-2 boundary flags depend on the edges only and are only ever set
     if (V > 0) TRY(hipMemsetAsync(X->flag2, 0, V, s));
-    ha.V = V; ha.ngroups = G; ha.Vgp = Vgp; ha.m = m; ha.kc = inner_kc;
+    ha.V = V; ha.ngroups = G; ha.Vgp = Vgp; ha.m = m; ha.kc = inner_kc; ha.pivot = X->cpivot;
     ha.eu = eu; ha.ev = ev; ha.w = w; ha.comp = X->comp; ha.local = X->local; ha.bgoff = X->bgoff;
     ha.nb = X->nb; ha.bgcomp = X->bgcomp; ha.bglocal = X->bglocal; ha.P = X->P; ha.moff = X->moff;
     ha.M = X->M; ha.grp = X->grp; ha.gbg0 = X->gbg0; ha.gV = X->gV; ha.bgrow = X->bgrow;
@@ -837,7 +839,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       }
     }
     // executed relaxations of level 2 (its BG2 closure is counted with level 3)
-    if (X->V2p > 0 && X->nT == 0) X->relax_bg_exec += spq::dense_fw_exec_relax(X->V2p / 128, 128);
+    if (X->V2p > 0 && X->nT == 0)
+      X->relax_bg_exec += spq::dense_fw_exec_relax(X->V2p / 128, 128, X->cpivot);
     for (int32_t a1 = 0; a1 < G; a1++)
       for (int32_t a2 = a1; a2 < G; a2++) {
         if (X->V2p > 0)
@@ -898,7 +901,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       // level-3 boundary flags depend on the edges only and are only ever set
       TRY(hipMemsetAsync(X->flag3, 0, X->V2, s));
       spq::L3Args la{};
-      la.nT = nT; la.gpt = X->gpt; la.V3gp = V3gp; la.kc = inner_kc; la.m = m; la.V2p = X->V2p;
+      la.nT = nT; la.gpt = X->gpt; la.V3gp = V3gp; la.kc = inner_kc; la.pivot = X->cpivot; la.m = m; la.V2p = X->V2p;
       la.eu = eu; la.ev = ev; la.w = w; la.comp = X->comp; la.local = X->local; la.bgoff = X->bgoff;
       la.grp = X->grp; la.b2off = X->b2off; la.b2rank = X->b2rank; la.BG2 = X->BG2;
       la.tbase = X->tbase; la.tsize = X->tsize; la.M3 = X->M3; la.flag3 = X->flag3;
@@ -921,8 +924,8 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       X->V3p = round_up(X->V3, 128);
       X->m3pmax = (int32_t)std::max<int64_t>(128, round_up(m3max, 128));
       // executed relaxations of level 3
-      X->relax_bg_exec += nT * spq::dense_fw_exec_relax(V3gp / 128, 128);
-      if (X->V3p > 0) X->relax_bg_exec += spq::dense_fw_exec_relax(X->V3p / 128, 128);
+      X->relax_bg_exec += nT * spq::dense_fw_exec_relax(V3gp / 128, 128, X->cpivot);
+      if (X->V3p > 0) X->relax_bg_exec += spq::dense_fw_exec_relax(X->V3p / 128, 128, X->cpivot);
       for (int32_t t1 = 0; t1 < nT; t1++)
         for (int32_t t2 = t1; t2 < nT; t2++) {
           if (X->V3p > 0)

@@ -230,9 +230,15 @@ static int64_t inner_count(int nt, FwBlock b, int part, int nn) {
   return tri_count(nt - b.pt - nn);
 }
 
+// `batch` equally sized matrices, gstride elements apart (blockIdx.y)
+struct FwBatch {
+  int batch;
+  int64_t gstride;
+};
+
 template <int T, int KC>
-static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, hipStream_t s,
-                                   hipEvent_t* ev);
+static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, FwBatch bt,
+                                   hipStream_t s, hipEvent_t* ev);
 
 // Closes the diagonal block: one tile in one workgroup (k_fw_diag); a block
 // of two or four tiles by the rounds of this file on the sub-matrix, over
@@ -241,41 +247,43 @@ static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, 
 // it finds room on a CU at once; one workgroup holding two tiles in LDS
 // (130 KB) waited for a whole CU to drain, about as long as the interior.
 template <int T, int KC>
-static hipError_t fw_close(u32* A, int64_t ld, FwBlock b, hipStream_t s) {
+static hipError_t fw_close(u32* A, int64_t ld, FwBlock b, FwBatch bt, hipStream_t s) {
   if (b.pt == 1) {
-    k_fw_diag<T><<<1, 256, 0, s>>>(A, ld, b.c0, 0);
+    k_fw_diag<T><<<dim3(1, bt.batch), 256, 0, s>>>(A, ld, b.c0, bt.gstride);
     return hipGetLastError();
   }
   return fw_rounds_blocks<T, KC>(A + (int64_t)b.c0 * T * ld + (int64_t)b.c0 * T, ld, b.pt, b.pt / 2,
-                                 s, nullptr);
+                                 bt, s, nullptr);
 }
 
 // The panel of block b: tiles (a, j), a in the block, j outside it, by the
 // interior kernel (part 3; 32 KB LDS, not k_fw_panel's 128 KB, for the same
 // reason as above).
 template <int T, int KC>
-static hipError_t fw_panel(u32* A, int64_t ld, int nt, FwBlock b, hipStream_t s) {
+static hipError_t fw_panel(u32* A, int64_t ld, int nt, FwBlock b, FwBatch bt, hipStream_t s) {
   if (nt <= b.pt) return hipSuccess;
-  const unsigned count = (unsigned)(b.pt * (nt - b.pt));
+  const dim3 grid((unsigned)(b.pt * (nt - b.pt)), (unsigned)bt.batch);
   if (b.pt == 1)
-    k_fw_inner<T, KC, 1><<<count, 256, 0, s>>>(A, ld, b.c0, nt, 0, 3, 0);
+    k_fw_inner<T, KC, 1><<<grid, 256, 0, s>>>(A, ld, b.c0, nt, bt.gstride, 3, 0);
   else if (b.pt == 2)
-    k_fw_inner<T, KC, 2><<<count, 256, 0, s>>>(A, ld, b.c0, nt, 0, 3, 0);
+    k_fw_inner<T, KC, 2><<<grid, 256, 0, s>>>(A, ld, b.c0, nt, bt.gstride, 3, 0);
   else
-    k_fw_inner<T, KC, 4><<<count, 256, 0, s>>>(A, ld, b.c0, nt, 0, 3, 0);
+    k_fw_inner<T, KC, 4><<<grid, 256, 0, s>>>(A, ld, b.c0, nt, bt.gstride, 3, 0);
   return hipGetLastError();
 }
 
 template <int T, int KC>
-static hipError_t fw_inner(u32* A, int64_t ld, int nt, FwBlock b, int part, int nn, hipStream_t s) {
+static hipError_t fw_inner(u32* A, int64_t ld, int nt, FwBlock b, int part, int nn, FwBatch bt,
+                           hipStream_t s) {
   const int64_t count = inner_count(nt, b, part, nn);
   if (count <= 0) return hipSuccess;
+  const dim3 grid((unsigned)count, (unsigned)bt.batch);
   if (b.pt == 1)
-    k_fw_inner<T, KC, 1><<<(unsigned)count, 256, 0, s>>>(A, ld, b.c0, nt, 0, part, nn);
+    k_fw_inner<T, KC, 1><<<grid, 256, 0, s>>>(A, ld, b.c0, nt, bt.gstride, part, nn);
   else if (b.pt == 2)
-    k_fw_inner<T, KC, 2><<<(unsigned)count, 256, 0, s>>>(A, ld, b.c0, nt, 0, part, nn);
+    k_fw_inner<T, KC, 2><<<grid, 256, 0, s>>>(A, ld, b.c0, nt, bt.gstride, part, nn);
   else
-    k_fw_inner<T, KC, 4><<<(unsigned)count, 256, 0, s>>>(A, ld, b.c0, nt, 0, part, nn);
+    k_fw_inner<T, KC, 4><<<grid, 256, 0, s>>>(A, ld, b.c0, nt, bt.gstride, part, nn);
   return hipGetLastError();
 }
 
@@ -285,19 +293,19 @@ static hipError_t fw_inner(u32* A, int64_t ld, int nt, FwBlock b, int part, int 
     if (e_ != hipSuccess) return e_;        \
   } while (0)
 
-// One matrix, rounds over its pivot blocks on one stream.  ev (optional) gets
-// one pair per round around its interior launch.
+// Rounds over the pivot blocks on one stream (a batch of matrices at once).
+// ev (optional) gets one pair per round around its interior launch.
 template <int T, int KC>
-static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, hipStream_t s,
-                                   hipEvent_t* ev) {
+static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, FwBatch bt,
+                                   hipStream_t s, hipEvent_t* ev) {
   std::vector<FwBlock> blk(fw_blocks(nt, pivot_tiles, nullptr));
   fw_blocks(nt, pivot_tiles, blk.data());
   for (size_t q = 0; q < blk.size(); q++) {
-    CHK((fw_close<T, KC>(A, ld, blk[q], s)));
+    CHK((fw_close<T, KC>(A, ld, blk[q], bt, s)));
     if (nt <= blk[q].pt) continue;
-    CHK((fw_panel<T, KC>(A, ld, nt, blk[q], s)));
+    CHK((fw_panel<T, KC>(A, ld, nt, blk[q], bt, s)));
     if (ev) CHK(hipEventRecord(ev[2 * q], s));
-    CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 0, 0, s)));
+    CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 0, 0, bt, s)));
     if (ev) CHK(hipEventRecord(ev[2 * q + 1], s));
   }
   return hipSuccess;
@@ -316,12 +324,13 @@ static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, int pivot_tile
                                       hipStream_t side, hipEvent_t* sync, hipEvent_t* ev) {
   std::vector<FwBlock> blk(fw_blocks(nt, pivot_tiles, nullptr));
   fw_blocks(nt, pivot_tiles, blk.data());
+  const FwBatch one{1, 0};
   // sync[0] = side stream may start the next round (part 1 of this one done);
   // sync[1] = main stream may start the next round's interior (its panel done)
   CHK(hipEventRecord(sync[0], s));
   CHK(hipStreamWaitEvent(side, sync[0], 0));
-  CHK((fw_close<T, KC>(A, ld, blk[0], side)));
-  CHK((fw_panel<T, KC>(A, ld, nt, blk[0], side)));
+  CHK((fw_close<T, KC>(A, ld, blk[0], one, side)));
+  CHK((fw_panel<T, KC>(A, ld, nt, blk[0], one, side)));
   CHK(hipEventRecord(sync[1], side));
   for (size_t q = 0; q < blk.size(); q++) {
     CHK(hipStreamWaitEvent(s, sync[1], 0));
@@ -329,16 +338,16 @@ static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, int pivot_tile
     if (ev) CHK(hipEventRecord(ev[2 * q], s));
     if (q + 1 < blk.size()) {
       const int nn = blk[q + 1].pt;
-      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 1, nn, s)));
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 1, nn, one, s)));
       CHK(hipEventRecord(sync[0], s));
       CHK(hipStreamWaitEvent(side, sync[0], 0));
-      CHK((fw_close<T, KC>(A, ld, blk[q + 1], side)));
-      CHK((fw_panel<T, KC>(A, ld, nt, blk[q + 1], side)));
-      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 2, nn, s)));
+      CHK((fw_close<T, KC>(A, ld, blk[q + 1], one, side)));
+      CHK((fw_panel<T, KC>(A, ld, nt, blk[q + 1], one, side)));
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 2, nn, one, s)));
       CHK(hipEventRecord(sync[1], side));
     } else {
       // last round: nothing to look ahead to
-      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 0, 0, s)));
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 0, 0, one, s)));
     }
     if (ev) CHK(hipEventRecord(ev[2 * q + 1], s));
   }
@@ -353,15 +362,7 @@ int fw_rounds_count(int nt, int tile, int pivot) {
 
 hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev,
                            int kc, int pivot) {
-  const int pt = pivot_tiles_of(tile, pivot);
-  if (pt == 1) return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev, kc);
-  if (nt <= 0) return hipSuccess;
-  if (kc == 0) kc = SPQ_INNER_KC;
-  if (tile == 64)
-    return kc == 32 ? fw_rounds_blocks<64, 32>(A, ld, nt, pt, s, ev)
-                    : fw_rounds_blocks<64, 16>(A, ld, nt, pt, s, ev);
-  return kc == 32 ? fw_rounds_blocks<128, 32>(A, ld, nt, pt, s, ev)
-                  : fw_rounds_blocks<128, 16>(A, ld, nt, pt, s, ev);
+  return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev, kc, pivot);
 }
 
 hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
@@ -380,9 +381,18 @@ hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipSt
 
 // kc: K chunk of the interior-tile kernel (16 or 32; 0 = SPQ_INNER_KC)
 hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
-                                 hipStream_t s, hipEvent_t* ev, int kc) {
+                                 hipStream_t s, hipEvent_t* ev, int kc, int pivot) {
   if (nt <= 0 || batch <= 0) return hipSuccess;
   if (kc == 0) kc = SPQ_INNER_KC;
+  const int pt = pivot_tiles_of(tile, pivot);
+  if (pt > 1) {
+    const FwBatch bt{batch, gstride};
+    if (tile == 64)
+      return kc == 32 ? fw_rounds_blocks<64, 32>(A, ld, nt, pt, bt, s, ev)
+                      : fw_rounds_blocks<64, 16>(A, ld, nt, pt, bt, s, ev);
+    return kc == 32 ? fw_rounds_blocks<128, 32>(A, ld, nt, pt, bt, s, ev)
+                    : fw_rounds_blocks<128, 16>(A, ld, nt, pt, bt, s, ev);
+  }
   if (tile == 64)
     return kc == 32 ? fw_rounds<64, 32>(A, ld, nt, batch, gstride, s, ev)
                     : fw_rounds<64, 16>(A, ld, nt, batch, gstride, s, ev);

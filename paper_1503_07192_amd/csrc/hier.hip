@@ -760,7 +760,7 @@ hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s) {
     k_grp_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
                                              a.gbg0, a.Vgp, a.Mg, a.flag2);
   hipError_t e = launch_dense_fw_batch(a.Mg, a.Vgp, 128, a.Vgp / 128, a.ngroups,
-                                       (int64_t)a.Vgp * a.Vgp, s, nullptr, a.kc);
+                                       (int64_t)a.Vgp * a.Vgp, s, nullptr, a.kc, a.pivot);
   if (e != hipSuccess) return e;
   k_b2_scan<<<(unsigned)a.ngroups, 256, 0, s>>>(a.gbg0, a.gV, a.flag2, a.Vgp, a.b2list, a.b2rank, a.m2);
   return hipGetLastError();
@@ -781,7 +781,7 @@ hipError_t launch_hier_level2_prep(const HierArgs& a, hipStream_t s) {
 
 hipError_t launch_hier_level2_close(const HierArgs& a, hipStream_t s) {
   if (a.V2p <= 0) return hipSuccess;
-  return launch_dense_fw(a.BG2, a.V2p, 128, (int)(a.V2p / 128), s, nullptr, a.kc);
+  return launch_dense_fw(a.BG2, a.V2p, 128, (int)(a.V2p / 128), s, nullptr, a.kc, a.pivot);
 }
 
 // Composition over the pair list a.plist (a.npairs pairs), a.chunk pairs per
@@ -828,7 +828,7 @@ hipError_t launch_level3_a(const L3Args& a, hipStream_t s) {
   k_l3_gather<<<dim3((unsigned)a.V3gp, (unsigned)a.nT), 256, 0, s>>>(a.V2p, a.BG2, a.tbase, a.tsize,
                                                                       a.V3gp, a.M3);
   hipError_t e = launch_dense_fw_batch(a.M3, a.V3gp, 128, a.V3gp / 128, a.nT,
-                                       (int64_t)a.V3gp * a.V3gp, s, nullptr, a.kc);
+                                       (int64_t)a.V3gp * a.V3gp, s, nullptr, a.kc, a.pivot);
   if (e != hipSuccess) return e;
   if (a.m > 0)
     k_l3_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
@@ -848,7 +848,7 @@ hipError_t launch_level3_b(const L3Args& a, hipStream_t s) {
       k_l3_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
                                               a.gpt, a.b2off, a.b2rank, nullptr, a.b3off, a.b3rank,
                                               a.V3p, a.BG3);
-    hipError_t e = launch_dense_fw(a.BG3, a.V3p, 128, (int)(a.V3p / 128), s, nullptr, a.kc);
+    hipError_t e = launch_dense_fw(a.BG3, a.V3p, 128, (int)(a.V3p / 128), s, nullptr, a.kc, a.pivot);
     if (e != hipSuccess) return e;
   }
   const int ntx = a.V3gp / 128, ntm = a.m3pmax / 128;

@@ -78,6 +78,7 @@ struct QueryArgs {
 // Two-level BG (hier.hip).
 struct HierArgs {
   int32_t V, ngroups, Vgp, m2pmax, V2, kc;
+  int32_t pivot;  // rows per pivot block of the dense closures (128 or 256)
   int64_t m, V2p;
   const int32_t *eu, *ev, *w, *comp, *local, *bgoff, *nb, *bgcomp, *bglocal, *P;
   const int64_t* moff;
@@ -125,6 +126,7 @@ hipError_t launch_hier_level2_compose(const HierArgs& a, hipStream_t s);
 // gpt consecutive groups (hier.hip).
 struct L3Args {
   int32_t nT, gpt, V3gp, V3, m3pmax, kc;
+  int32_t pivot;  // rows per pivot block of the dense closures
   int64_t m, V2p, V3p;
   const int32_t *eu, *ev, *w, *comp, *local, *bgoff, *grp;
   const int32_t *b2off, *b2rank;       // level-2 ids
@@ -176,9 +178,9 @@ hipError_t launch_bg_assembly(const BgArgs& a, hipStream_t s);
 // pivot: rows per pivot block, the tile (or 0) or twice the tile (see fw.hip)
 hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, hipEvent_t* ev,
                            int kc = 0, int pivot = 0);
-// `batch` matrices of the same shape, gstride elements apart (one-tile pivots)
+// `batch` matrices of the same shape, gstride elements apart
 hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
-                                 hipStream_t s, hipEvent_t* ev, int kc = 0);
+                                 hipStream_t s, hipEvent_t* ev, int kc = 0, int pivot = 0);
 // Same closure with a lookahead over two streams (side: created by the caller,
 // default priority; sync: two events).
 hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,

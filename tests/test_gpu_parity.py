@@ -489,6 +489,13 @@ def test_grid256d_two_level_equals_flat():
     for r, want in zip(rows, rf):
         assert np.array_equal(spq.index_bg_rows(three, int(r), 1, 27_900), want)
     three.free()
+    # the same with one-tile pivot blocks in the group, super-group and BG3
+    # closures (two-tile blocks are the default)
+    three = build(g, bg_method=2, group_comps=4, level3_groups=16, bg_pivot=128)
+    assert np.array_equal(run_queries(three, g["v1"], g["v2"]), qf)
+    for r, want in zip(rows[:10], rf[:10]):
+        assert np.array_equal(spq.index_bg_rows(three, int(r), 1, 27_900), want)
+    three.free()
     two = build(g, bg_method=2, group_comps=32)
     st = spq.index_stats(two)
     assert st["ngroups"] == 32 and st["v_bg2"] > 0
