@@ -64,6 +64,10 @@ GRAPH_CASES = [
      {"bg_method": 2, "group_comps": 2, "level3_groups": 3}),
     ("bigcomp_flat", bigcomp_case, {}),
     ("bigcomp_two_level", bigcomp_case, {"bg_method": 2, "group_comps": 2}),
+    # four-tile pivot blocks: the 1,280-wide component closure runs 4 + 4 + 2
+    ("bigcomp_pivot512", bigcomp_case, {"bg_pivot": 512}),
+    ("grid30_level3_pivot512", lambda: grid_case(3, 30, 27, 5),
+     {"bg_method": 2, "group_comps": 2, "level3_groups": 3, "bg_pivot": 512}),
 ]
 
 
