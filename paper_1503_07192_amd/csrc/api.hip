@@ -879,6 +879,14 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       ha.cert_mbg = X->cert + 3;
       X->fused_cert = true;
     }
+    // the single-matrix closure (BG2, or BG3 at level 3) runs with the
+    // lookahead of the flat method
+    if (lookahead) {
+      TRY(hipStreamCreateWithFlags(&X->side, hipStreamNonBlocking));  // default priority
+      for (auto& e : X->la_sync) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ha.side = X->side;
+      ha.sync = X->la_sync;
+    }
     if (X->nT == 0) {
       TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
         hipError_t e = spq::launch_hier_level2_prep(ha, st);
@@ -946,7 +954,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       la.plist = X->plist3; la.npairs = np3; la.chunk = ch3;
       if (X->V3p > 0) TRY(dalloc(&X->BG3, X->V3p * X->V3p));
       la.V3 = X->V3; la.V3p = X->V3p; la.m3pmax = X->m3pmax; la.b3off = X->b3off; la.R3 = X->R3;
-      la.XT3 = X->XT3; la.BG3 = X->BG3;
+      la.XT3 = X->XT3; la.BG3 = X->BG3; la.side = ha.side; la.sync = ha.sync;
       TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
         hipError_t e = spq::launch_level3_b(la, st);
         if (e == hipSuccess) e = spq::launch_hier_level2_compose(ha, st);

@@ -781,7 +781,10 @@ hipError_t launch_hier_level2_prep(const HierArgs& a, hipStream_t s) {
 
 hipError_t launch_hier_level2_close(const HierArgs& a, hipStream_t s) {
   if (a.V2p <= 0) return hipSuccess;
-  return launch_dense_fw(a.BG2, a.V2p, 128, (int)(a.V2p / 128), s, nullptr, a.kc, a.pivot);
+  const int nt = (int)(a.V2p / 128);
+  if (a.side && nt > 1)
+    return launch_dense_fw_lookahead(a.BG2, a.V2p, 128, nt, s, a.side, a.sync, nullptr, a.kc, a.pivot);
+  return launch_dense_fw(a.BG2, a.V2p, 128, nt, s, nullptr, a.kc, a.pivot);
 }
 
 // Composition over the pair list a.plist (a.npairs pairs), a.chunk pairs per
@@ -848,7 +851,11 @@ hipError_t launch_level3_b(const L3Args& a, hipStream_t s) {
       k_l3_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
                                               a.gpt, a.b2off, a.b2rank, nullptr, a.b3off, a.b3rank,
                                               a.V3p, a.BG3);
-    hipError_t e = launch_dense_fw(a.BG3, a.V3p, 128, (int)(a.V3p / 128), s, nullptr, a.kc, a.pivot);
+    const int nt = (int)(a.V3p / 128);
+    hipError_t e = (a.side && nt > 1)
+                       ? launch_dense_fw_lookahead(a.BG3, a.V3p, 128, nt, s, a.side, a.sync, nullptr,
+                                                   a.kc, a.pivot)
+                       : launch_dense_fw(a.BG3, a.V3p, 128, nt, s, nullptr, a.kc, a.pivot);
     if (e != hipSuccess) return e;
   }
   const int ntx = a.V3gp / 128, ntm = a.m3pmax / 128;

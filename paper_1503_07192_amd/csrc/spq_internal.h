@@ -79,6 +79,8 @@ struct QueryArgs {
 struct HierArgs {
   int32_t V, ngroups, Vgp, m2pmax, V2, kc;
   int32_t pivot;  // rows per pivot block of the dense closures (128 or 256)
+  hipStream_t side = nullptr;    // BG2 closure lookahead: side stream (default priority)
+  hipEvent_t* sync = nullptr;    // and its two events; null: no lookahead
   int64_t m, V2p;
   const int32_t *eu, *ev, *w, *comp, *local, *bgoff, *nb, *bgcomp, *bglocal, *P;
   const int64_t* moff;
@@ -127,6 +129,8 @@ hipError_t launch_hier_level2_compose(const HierArgs& a, hipStream_t s);
 struct L3Args {
   int32_t nT, gpt, V3gp, V3, m3pmax, kc;
   int32_t pivot;  // rows per pivot block of the dense closures
+  hipStream_t side = nullptr;    // BG3 closure lookahead (as for BG2)
+  hipEvent_t* sync = nullptr;
   int64_t m, V2p, V3p;
   const int32_t *eu, *ev, *w, *comp, *local, *bgoff, *grp;
   const int32_t *b2off, *b2rank;       // level-2 ids

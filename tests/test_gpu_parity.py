@@ -502,6 +502,14 @@ def test_grid256d_two_level_equals_flat():
     assert np.array_equal(run_queries(two, g["v1"], g["v2"]), qf)
     for r, want in zip(rows, rf):
         assert np.array_equal(spq.index_bg_rows(two, int(r), 1, 27_900), want)
+    two.free()
+    # BG2 (and, at level 3, BG3) closed without the lookahead: the same matrix
+    for kw in ({"group_comps": 32}, {"group_comps": 4, "level3_groups": 16}):
+        nl = build(g, bg_method=2, lookahead=False, **kw)
+        assert np.array_equal(run_queries(nl, g["v1"], g["v2"]), qf), kw
+        for r, want in zip(rows[:10], rf[:10]):
+            assert np.array_equal(spq.index_bg_rows(nl, int(r), 1, 27_900), want)
+        nl.free()
 
 
 # ------------------------------------------------ exactness certificate
