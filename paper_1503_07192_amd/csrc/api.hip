@@ -157,7 +157,8 @@ struct spq_index {
   // share mode
   int32_t share_comps = 0, share_groups = 0, S2 = 0, bf_rounds = 0;
   int64_t S2p = 0;
-  u32 *A = nullptr, *DT = nullptr, *bfflag = nullptr;
+  u32 *A = nullptr, *DT = nullptr, *bfflag = nullptr, *bfstamp = nullptr;
+  int32_t *bfcnt = nullptr, *bflist = nullptr;
   int4* xe = nullptr;
   int32_t* xcount = nullptr;
   // exactness certificate (total weight >= INF)
@@ -208,7 +209,8 @@ struct spq_index {
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
                     vrec, gT,    grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
-                    bgvert, label, bglabel, cert, A,    DT,    bfflag,  xe, xcount,
+                    bgvert, label, bglabel, cert, A,    DT,    bfflag,  bfstamp, bfcnt, bflist,
+                    xe, xcount,
                     eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
                     M3, R3, XT3, BG3, plist, plist3, rowptr, adj, adeg, w_copy};
     for (void* p : ptrs) pool_release(p);
@@ -319,6 +321,12 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   // 128 share sources and one "any" word
   const int32_t ntc = (int32_t)(X->S2p / 128), fs = ntc + 1;
   HIP_TRY(dalloc(&X->bfflag, 2 * (int64_t)G * fs));
+  // rows lowered per (group, column tile), two rounds' worth, and the round
+  // stamps that keep a row from being listed twice in one round
+  HIP_TRY(dalloc(&X->bfcnt, 2 * (int64_t)G * ntc));
+  HIP_TRY(dalloc(&X->bflist, 2 * (int64_t)G * ntc * X->m2pmax));
+  HIP_TRY(dalloc(&X->bfstamp, V2p * ntc));
+  HIP_TRY(hipMemsetAsync(X->bfstamp, 0xff, sizeof(u32) * V2p * ntc, s));
   HIP_TRY(hipMemsetAsync(X->xcount, 0, sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(X->DT + V2p * X->S2p, 0xff, 128 * X->S2p * sizeof(u32), s));
   HIP_TRY(hipMemcpyAsync(X->pairbase, X->h_pairbase.data(), sizeof(int64_t) * G * G,
@@ -332,26 +340,43 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   int32_t nxe = 0;
   HIP_TRY(hipMemcpyAsync(&nxe, X->xcount, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  // the share's groups start dirty on every column tile
+  // the share's groups start dirty on every column tile, with every row
   std::vector<u32> hd((size_t)G * fs, 0);
-  for (int32_t g = 0; g < X->share_groups; g++)
+  std::vector<int32_t> hc((size_t)G * ntc, 0);
+  for (int32_t g = 0; g < X->share_groups; g++) {
     for (int32_t t = 0; t < fs; t++) hd[(size_t)g * fs + t] = 1;
+    for (int32_t t = 0; t < ntc; t++) hc[(size_t)g * ntc + t] = spq::BF_ALL_ROWS;
+  }
   HIP_TRY(hipMemcpyAsync(X->bfflag, hd.data(), sizeof(u32) * G * fs, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(X->bfcnt, hc.data(), sizeof(int32_t) * G * ntc, hipMemcpyHostToDevice, s));
   u32* dcur = X->bfflag;
   u32* dnext = X->bfflag + (int64_t)G * fs;
+  int32_t* ccur = X->bfcnt;
+  int32_t* cnext = X->bfcnt + (int64_t)G * ntc;
+  int32_t* lcur = X->bflist;
+  int32_t* lnext = X->bflist + (int64_t)G * ntc * X->m2pmax;
   for (;;) {
     if (++X->bf_rounds > 100000) return fail(SPQ_EDEVICE, "Bellman-Ford over groups did not settle");
-    for (int32_t g = 0; g < G; g++) {
-      int32_t tiles = 0;
-      for (int32_t t = 0; t < ntc; t++) tiles += hd[(size_t)g * fs + t] != 0;
-      X->relax_bg_exec += (double)((X->h_m2[g] + 127) / 128) * tiles * 128.0 * 128.0 *
-                          (double)round_up(X->h_m2[g], 16);
-    }
+    // executed relaxations: a dirty (group, tile) multiplies its row tiles by
+    // the rows listed for it (all of them in the first round)
+    for (int32_t g = 0; g < G; g++)
+      for (int32_t t = 0; t < ntc; t++) {
+        const int32_t c = hc[(size_t)g * ntc + t];
+        if (c == 0 || !hd[(size_t)g * fs + t]) continue;
+        const int32_t kk = c == spq::BF_ALL_ROWS ? X->h_m2[g] : c;
+        X->relax_bg_exec += (double)((X->h_m2[g] + 127) / 128) * 128.0 * 128.0 *
+                            (double)round_up(kk, 16);
+      }
+    const spq::BfRound r{dcur, dnext, ccur, lcur, cnext, lnext, X->bfstamp, (u32)X->bf_rounds};
     HIP_TRY(hipMemsetAsync(dnext, 0, sizeof(u32) * G * fs, s));
-    HIP_TRY(spq::launch_share_round(ha, nxe, dcur, dnext, s));
+    HIP_TRY(hipMemsetAsync(cnext, 0, sizeof(int32_t) * G * ntc, s));
+    HIP_TRY(spq::launch_share_round(ha, nxe, r, s));
     HIP_TRY(hipMemcpyAsync(hd.data(), dnext, sizeof(u32) * G * fs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hc.data(), cnext, sizeof(int32_t) * G * ntc, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::swap(dcur, dnext);
+    std::swap(ccur, cnext);
+    std::swap(lcur, lnext);
     bool any = false;
     for (int32_t g = 0; g < G; g++) any |= hd[(size_t)g * fs + ntc] != 0;
     if (!any) break;

@@ -281,6 +281,46 @@ __device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int6
   }
 }
 
+// c = min(c, min over k < cnt of At[rows[k]][i] + B[rows[k]][j]): the K rows
+// are gathered through the list `rows` (cnt of them; streamed 16 at a time,
+// rows past cnt read as INF without touching memory).
+__device__ __forceinline__ void mp_stream128_rows(u32 (&c)[8][8], const u32* At, int64_t ldA,
+                                                  const u32* B, int64_t ldB,
+                                                  const int32_t* __restrict__ rows, int cnt,
+                                                  u32* sA, u32* sB) {
+  constexpr int T = 128, KC = 16;
+  const int nch = (cnt + KC - 1) / KC;
+  if (nch <= 0) return;
+  const int e0 = threadIdx.x, e1 = threadIdx.x + 256;
+  const int r0 = e0 >> 5, c0 = (e0 & 31) * 4, r1 = e1 >> 5, c1 = (e1 & 31) * 4;
+  const uint4 inf4 = make_uint4(INF, INF, INF, INF);
+  auto ld = [&](const u32* M, int64_t ldm, int k, int col) -> uint4 {
+    if (k >= cnt) return inf4;
+    return *reinterpret_cast<const uint4*>(M + (int64_t)rows[k] * ldm + col);
+  };
+  uint4 pa0 = ld(At, ldA, r0, c0), pa1 = ld(At, ldA, r1, c1);
+  uint4 pb0 = ld(B, ldB, r0, c0), pb1 = ld(B, ldB, r1, c1);
+  reinterpret_cast<uint4*>(sA)[e0] = pa0;
+  reinterpret_cast<uint4*>(sA)[e1] = pa1;
+  reinterpret_cast<uint4*>(sB)[e0] = pb0;
+  reinterpret_cast<uint4*>(sB)[e1] = pb1;
+  __syncthreads();
+  for (int ch = 0; ch < nch; ch++) {
+    const int kn = (ch + 1 < nch ? ch + 1 : ch) * KC;
+    pa0 = ld(At, ldA, kn + r0, c0);
+    pa1 = ld(At, ldA, kn + r1, c1);
+    pb0 = ld(B, ldB, kn + r0, c0);
+    pb1 = ld(B, ldB, kn + r1, c1);
+    const int cur = (ch & 1) * KC * T, nxt = ((ch + 1) & 1) * KC * T;
+    minplus_lds<T>(c, sA + cur, sB + cur, KC);
+    reinterpret_cast<uint4*>(sA + nxt)[e0] = pa0;
+    reinterpret_cast<uint4*>(sA + nxt)[e1] = pa1;
+    reinterpret_cast<uint4*>(sB + nxt)[e0] = pb0;
+    reinterpret_cast<uint4*>(sB + nxt)[e1] = pb1;
+    __syncthreads();
+  }
+}
+
 // The composition kernels fit in 128 VGPRs without spilling: four waves per
 // SIMD (four workgroups per CU) instead of two or three.
 #define SPQ_MP_ATTR __attribute__((amdgpu_waves_per_eu(4, 4)))
@@ -637,20 +677,28 @@ __global__ void k_dt_init(int32_t V2, int32_t S2, int64_t S2p, int32_t ngroups,
 }
 
 // Dirty flags of the Bellman-Ford rounds: per group, one word per column tile
-// of 128 share sources, then one word "any tile" (stride ntc + 1).
+// of 128 share sources, then one word "any tile" (stride ntc + 1).  Beside
+// them, per (group, column tile), the rows (local level-2 indices) that the
+// cross edges lowered since the group's last intra step: a count and a list
+// (count BF_ALL_ROWS: every row, the share's groups in the first round).
 //
 // Intra-group step, in place: rows B2(S) x column tile of DT = min(DT, A_S (x)
 // DT) for the (group, tile) pairs whose values changed in the previous round.
-// One product with the closed A_S leaves the rows closed.  Tiles of one group
-// read rows that other tiles of the group are lowering: every value read is
-// the old or the new one, both lengths of real walks and each at most the old
-// value, and A_S being closed, the old values already give the closed result,
-// so the step is exact in any interleaving.
+// One product with the closed A_S leaves the rows closed.  The rows were
+// closed before the cross edges lowered some of them, and for an unchanged
+// row k, A_S[x][k] + DT[k] >= DT[x] already; so only the lowered rows need to
+// be the K of the product.  Tiles of one group read rows that other tiles of
+// the group are lowering: every value read is the old or the new one, both
+// lengths of real walks and each at most the old value, and A_S being closed,
+// the old values already give the closed result, so the step is exact in any
+// interleaving.
 __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
                                                   const int32_t* __restrict__ m2,
                                                   const int32_t* __restrict__ b2off,
                                                   const u32* __restrict__ A, u32* DT,
-                                                  const u32* __restrict__ dirty) {
+                                                  const u32* __restrict__ dirty,
+                                                  const int32_t* __restrict__ rcnt,
+                                                  const int32_t* __restrict__ rlist) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
   const int s = blockIdx.y;
@@ -658,12 +706,18 @@ __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
   const int ntc = (int)(S2p / 128);
   const int ti = (int)blockIdx.x / ntc, tj = (int)blockIdx.x % ntc;
   if (ti * 128 >= ms || !dirty[(int64_t)s * (ntc + 1) + tj]) return;
+  const int64_t st = (int64_t)s * ntc + tj;
+  const int32_t cnt = rcnt[st];
+  if (cnt == 0) return;
   const int64_t r0 = b2off[s];
   u32 c[8][8];
   tile_load<128>(c, DT + (r0 + ti * 128) * S2p + tj * 128, S2p);  // rows past ms: unused
   const u32* At = A + (int64_t)s * m2pmax * m2pmax + ti * 128;  // A_S symmetric: At[k][i] = A[i][k]
   const u32* B = DT + r0 * S2p + tj * 128;
-  mp_stream128<true>(c, At, m2pmax, B, S2p, (ms + 15) / 16 * 16, ms, ms - ti * 128, sA, sB);
+  if (cnt == BF_ALL_ROWS)
+    mp_stream128<true>(c, At, m2pmax, B, S2p, (ms + 15) / 16 * 16, ms, ms - ti * 128, sA, sB);
+  else
+    mp_stream128_rows(c, At, m2pmax, B, S2p, rlist + st * m2pmax, cnt, sA, sB);
   const int tx = tid_x(), ty = tid_y();
 #pragma unroll
   for (int h = 0; h < 2; h++)
@@ -706,18 +760,32 @@ __global__ void k_cross_collect(int64_t m, const int32_t* __restrict__ eu, const
 // DT[b][i] = min(DT[b][i], DT[a][i] + w) for every directed cross edge, on
 // the column tiles that are dirty for the source group (values that have not
 // changed since they were last propagated need no new pass); a lowered value
-// marks its (group, tile) dirty for the next round.
+// marks its (group, tile) dirty for the next round and, once per round (the
+// stamp of (row, tile) holds the round that last listed it), adds its row to
+// that (group, tile)'s list.
 __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2, int64_t S2p, u32* DT,
-                           const u32* __restrict__ dirty, u32* __restrict__ dirty_next) {
+                           const u32* __restrict__ dirty, u32* __restrict__ dirty_next,
+                           const int32_t* __restrict__ b2off, int32_t m2pmax, u32 round,
+                           u32* __restrict__ stamp, int32_t* __restrict__ rcnt_next,
+                           int32_t* __restrict__ rlist_next) {
   const int32_t e = blockIdx.x;
   if (e >= nxe) return;
   const int4 t = xe[e];
   const int ntc = (int)(S2p / 128);
   const u32* dsrc = dirty + (int64_t)(t.w >> 16) * (ntc + 1);
   if (!dsrc[ntc]) return;
-  u32* dnext = dirty_next + (int64_t)(t.w & 0xffff) * (ntc + 1);
+  const int32_t sv = t.w & 0xffff;
+  u32* dnext = dirty_next + (int64_t)sv * (ntc + 1);
   const u32* src = DT + (int64_t)t.x * S2p;
   u32* dst = DT + (int64_t)t.y * S2p;
+  // tiles this workgroup has already listed its row for (LDS, when they fit):
+  // the global stamp is then touched once per tile, not once per element
+  __shared__ u32 listed[BF_LDS_TILES];
+  const bool local = ntc <= BF_LDS_TILES;
+  if (local) {
+    for (int q = threadIdx.x; q < ntc; q += blockDim.x) listed[q] = 0u;
+    __syncthreads();
+  }
   for (int32_t i = threadIdx.x; i < S2; i += blockDim.x) {
     const int tile = i >> 7;
     if (!dsrc[tile]) continue;
@@ -726,6 +794,12 @@ __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2,
       atomicMin(dst + i, v);
       dnext[tile] = 1u;
       dnext[ntc] = 1u;
+      if (local && atomicExch(listed + tile, 1u) != 0u) continue;
+      if (atomicExch(stamp + (int64_t)t.y * ntc + tile, round) != round) {
+        const int64_t st = (int64_t)sv * ntc + tile;
+        const int32_t slot = atomicAdd(rcnt_next + st, 1);
+        rlist_next[st * m2pmax + slot] = t.y - b2off[sv];
+      }
     }
   }
 }
@@ -896,13 +970,14 @@ hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s) {
 }
 
 // One Bellman-Ford round, in place on DT: intra-group step, then cross edges.
-hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const u32* dirty, u32* dirty_next,
-                              hipStream_t s) {
+hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const BfRound& r, hipStream_t s) {
   const int ntm = a.m2pmax / 128, ntc = (int)(a.S2p / 128);
   k_bf_intra<<<dim3((unsigned)(ntm * ntc), (unsigned)a.ngroups), 256, 0, s>>>(
-      a.m2pmax, a.S2p, a.m2, a.b2off, a.A, a.DT, dirty);
+      a.m2pmax, a.S2p, a.m2, a.b2off, a.A, a.DT, r.dirty, r.cnt, r.list);
   if (nxe > 0)
-    k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, a.DT, dirty, dirty_next);
+    k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, a.DT, r.dirty, r.dirty_next,
+                                             a.b2off, a.m2pmax, r.round, r.stamp, r.cnt_next,
+                                             r.list_next);
   return hipGetLastError();
 }
 

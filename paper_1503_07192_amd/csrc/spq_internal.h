@@ -107,9 +107,23 @@ struct HierArgs {
   u32 *cert_bad, *cert_mbg;
 };
 hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s);
-// dirty flags: per group, ntc = S2p / 128 column tiles then one "any" word
-hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const u32* dirty, u32* dirty_next,
-                              hipStream_t s);
+// One Bellman-Ford round of the share.  dirty flags: per group, ntc = S2p /
+// 128 column tiles then one "any" word; cnt / list: per (group, tile) the
+// number of rows lowered since the last intra step (BF_ALL_ROWS: all) and
+// their local indices (m2pmax slots each); stamp: V2p x ntc round stamps.
+constexpr int32_t BF_ALL_ROWS = 0x7fffffff;
+constexpr int BF_LDS_TILES = 2048;  // column tiles a cross-edge workgroup tracks in LDS
+struct BfRound {
+  const u32* dirty;
+  u32* dirty_next;
+  const int32_t* cnt;
+  const int32_t* list;
+  int32_t* cnt_next;
+  int32_t* list_next;
+  u32* stamp;
+  u32 round;
+};
+hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const BfRound& r, hipStream_t s);
 hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s);
 hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
 // Flat method: per-BG-vertex layout terms, then the closed BG matrix (Vp x Vp)
