@@ -91,11 +91,12 @@ typedef struct {
                           group_comps */
   int32_t bg_pivot;      /* rows per pivot block of the flat BG Floyd-Warshall
                           (each round closes one block, then updates every
-                          other tile through it): 0 default (two tiles: 256
-                          with 128-tiles), or 1, 2 or 4 tiles (the last blocks
-                          of a matrix may be smaller).  The other closures
-                          (large components, groups, BG2, super-groups, BG3;
-                          128-tiles) use blocks of as many tiles.  The answers
+                          other tile through it): 1, 2 or 4 tiles (the last
+                          blocks of a matrix may be smaller); the other
+                          closures (large components, groups, BG2,
+                          super-groups, BG3; 128-tiles) then use blocks of as
+                          many tiles.  0 default: four tiles for the flat BG,
+                          two (256 rows) for the other closures.  The answers
                           do not depend on it */
 } spq_build_opts;
 

@@ -511,8 +511,11 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   X->k = k;
   X->m = m;
   X->tile = tile;
-  X->pivot = pivot ? pivot : 2 * tile;
-  X->cpivot = X->pivot / tile * 128;
+  // default: four-tile blocks for the flat BG closure (measured 388 against
+  // 408 ms on a 27,904-wide matrix), two-tile blocks for the other closures
+  // (four measured 10 ms slower on the 256-group composition's closures)
+  X->pivot = pivot ? pivot : 4 * tile;
+  X->cpivot = pivot ? pivot / tile * 128 : 256;
   X->graph = use_graph;
   {
     hipError_t e = hipGetDevice(&X->device);

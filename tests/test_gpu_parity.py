@@ -473,8 +473,8 @@ def test_grid256d_two_level_equals_flat():
     for r, want in zip(rows, rf):
         assert np.array_equal(spq.index_bg_rows(plain, int(r), 1, 27_900), want)
     plain.free()
-    # pivot blocks of one tile (218 rounds) and four (55) instead of two (109)
-    for pivot in (128, 512):
+    # pivot blocks of one tile (218 rounds) and two (109) instead of four (55)
+    for pivot in (128, 256):
         one = build(g, bg_method=1, bg_pivot=pivot)
         assert np.array_equal(run_queries(one, g["v1"], g["v2"]), qf)
         for r, want in zip(rows, rf):
