@@ -134,44 +134,38 @@ __global__ __launch_bounds__(256) SPQ_INNER_ATTR void k_fw_inner(u32* __restrict
   u32* Cij = A + (int64_t)i * T * ld + (int64_t)j * T;
   u32 t[T / 16][T / 16];
   tile_load<T>(t, Cij, ld);
-  uint4 pa[Q], pb[Q];
-  // chunk 0 straight to LDS buffer 0
-#pragma unroll
-  for (int s = 0; s < Q; s++) {
-    const int e = threadIdx.x + s * 256;
-    const int row = e / (T / 4), c4 = e % (T / 4);
-    pa[s] = *reinterpret_cast<const uint4*>(Ar + (int64_t)row * ld + c4 * 4);
-    pb[s] = *reinterpret_cast<const uint4*>(Br + (int64_t)row * ld + c4 * 4);
-  }
-#pragma unroll
-  for (int s = 0; s < Q; s++) {
-    const int e = threadIdx.x + s * 256;
-    reinterpret_cast<uint4*>(sA[0])[e] = pa[s];
-    reinterpret_cast<uint4*>(sB[0])[e] = pb[s];
-  }
-  __syncthreads();
-  // The chunk loop stays rolled: unrolled, it needed 136 VGPRs (three waves
-  // per SIMD); rolled it fits 128 (four waves, 3.5% faster on a 27,904-wide
-  // matrix).  The last chunk reloads itself into the idle buffer (unused), so
-  // the prefetch needs no branch.
-  constexpr int NCH = PT * T / KC;
-#pragma unroll 1
-  for (int ch = 0; ch < NCH; ch++) {
-    const int kc = (ch + 1 < NCH ? ch + 1 : ch) * KC;
+  // The operand chunks go from global memory straight to LDS
+  // (global_load_lds_dwordx4, gfx950): no staging registers and no LDS
+  // stores.  Element e (in 16-byte units) of a chunk is row e / (T/4),
+  // column 4 (e % (T/4)); lane l of wave w loads e = s*256 + w*64 + l, and a
+  // wave's 64 lanes fill 1 KB of LDS in that order.  A chunk is complete once
+  // every wave's loads have arrived: vmcnt(0), then the barrier.
+  const int wv = (int)threadIdx.x >> 6;
+  auto load_chunk = [&](int kc, int buf) {
 #pragma unroll
     for (int s = 0; s < Q; s++) {
       const int e = threadIdx.x + s * 256;
       const int row = e / (T / 4), c4 = e % (T / 4);
-      pa[s] = *reinterpret_cast<const uint4*>(Ar + (int64_t)(kc + row) * ld + c4 * 4);
-      pb[s] = *reinterpret_cast<const uint4*>(Br + (int64_t)(kc + row) * ld + c4 * 4);
+      const int64_t off = (int64_t)(kc + row) * ld + c4 * 4;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(Ar + off),
+                                       (__attribute__((address_space(3))) void*)(&sA[buf][(s * 256 + wv * 64) * 4]),
+                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(Br + off),
+                                       (__attribute__((address_space(3))) void*)(&sB[buf][(s * 256 + wv * 64) * 4]),
+                                       16, 0, 0);
     }
+  };
+  load_chunk(0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  // The chunk loop stays rolled (unrolled, the staged version needed 136
+  // VGPRs and three waves per SIMD).
+  constexpr int NCH = PT * T / KC;
+#pragma unroll 1
+  for (int ch = 0; ch < NCH; ch++) {
+    if (ch + 1 < NCH) load_chunk((ch + 1) * KC, (ch + 1) & 1);
     minplus_lds<T>(t, sA[ch & 1], sB[ch & 1], KC);
-#pragma unroll
-    for (int s = 0; s < Q; s++) {
-      const int e = threadIdx.x + s * 256;
-      reinterpret_cast<uint4*>(sA[(ch + 1) & 1])[e] = pa[s];
-      reinterpret_cast<uint4*>(sB[(ch + 1) & 1])[e] = pb[s];
-    }
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
   tile_store<T>(t, Cij, ld);
