@@ -282,8 +282,9 @@ __device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int6
 }
 
 // c = min(c, min over k < cnt of At[rows[k]][i] + B[rows[k]][j]): the K rows
-// are gathered through the list `rows` (cnt of them; streamed 16 at a time,
-// rows past cnt read as INF without touching memory).
+// are gathered through the list `rows` (rows k themselves when it is null;
+// cnt of them, streamed 16 at a time, rows past cnt read as INF without
+// touching memory).
 __device__ __forceinline__ void mp_stream128_rows(u32 (&c)[8][8], const u32* At, int64_t ldA,
                                                   const u32* B, int64_t ldB,
                                                   const int32_t* __restrict__ rows, int cnt,
@@ -296,7 +297,7 @@ __device__ __forceinline__ void mp_stream128_rows(u32 (&c)[8][8], const u32* At,
   const uint4 inf4 = make_uint4(INF, INF, INF, INF);
   auto ld = [&](const u32* M, int64_t ldm, int k, int col) -> uint4 {
     if (k >= cnt) return inf4;
-    return *reinterpret_cast<const uint4*>(M + (int64_t)rows[k] * ldm + col);
+    return *reinterpret_cast<const uint4*>(M + (int64_t)(rows ? rows[k] : k) * ldm + col);
   };
   uint4 pa0 = ld(At, ldA, r0, c0), pa1 = ld(At, ldA, r1, c1);
   uint4 pb0 = ld(B, ldB, r0, c0), pb1 = ld(B, ldB, r1, c1);
@@ -714,10 +715,11 @@ __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
   tile_load<128>(c, DT + (r0 + ti * 128) * S2p + tj * 128, S2p);  // rows past ms: unused
   const u32* At = A + (int64_t)s * m2pmax * m2pmax + ti * 128;  // A_S symmetric: At[k][i] = A[i][k]
   const u32* B = DT + r0 * S2p + tj * 128;
-  if (cnt == BF_ALL_ROWS)
-    mp_stream128<true>(c, At, m2pmax, B, S2p, (ms + 15) / 16 * 16, ms, ms - ti * 128, sA, sB);
-  else
-    mp_stream128_rows(c, At, m2pmax, B, S2p, rlist + st * m2pmax, cnt, sA, sB);
+  // all rows (the share's groups, first round): rows 0 .. ms-1 in order; the
+  // block's columns past ms hold INF, so they need no mask
+  const bool all = cnt == BF_ALL_ROWS;
+  mp_stream128_rows(c, At, m2pmax, B, S2p, all ? nullptr : rlist + st * m2pmax, all ? ms : cnt, sA,
+                    sB);
   const int tx = tid_x(), ty = tid_y();
 #pragma unroll
   for (int h = 0; h < 2; h++)
