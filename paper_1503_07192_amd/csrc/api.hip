@@ -765,11 +765,28 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   ca.P = X->P; ca.moff = X->moff; ca.M = X->M;
   auto phase2 = [&](hipStream_t st) -> hipError_t {
     hipError_t e = spq::launch_components(ca, st);
-    // order[] lists components largest first: the big ones lead
-    for (int32_t b = 0; b < X->nbig && e == hipSuccess; b++) {
-      const int32_t c = X->h_order[b];
-      e = spq::launch_dense_fw(X->M + X->h_moff[c], X->h_P[c], 128, X->h_P[c] / 128, st, nullptr,
-                               inner_kc, X->cpivot);
+    if (plain) {
+      // order[] lists components largest first: the big ones lead
+      for (int32_t b = 0; b < X->nbig && e == hipSuccess; b++) {
+        const int32_t c = X->h_order[b];
+        e = spq::launch_dense_fw(X->M + X->h_moff[c], X->h_P[c], 128, X->h_P[c] / 128, st, nullptr,
+                                 inner_kc, X->cpivot);
+      }
+    } else {
+      // runs of consecutive big components of one padded size lie back to
+      // back in M (offsets follow the ids): one batched closure per run
+      for (int32_t c = 0; c < k && e == hipSuccess;) {
+        if (X->h_cnt[c] <= spq::BIG_COMP) {
+          c++;
+          continue;
+        }
+        const int32_t P = X->h_P[c];
+        int32_t c2 = c + 1;
+        while (c2 < k && c2 - c < 65535 && X->h_cnt[c2] > spq::BIG_COMP && X->h_P[c2] == P) c2++;
+        e = spq::launch_dense_fw_batch(X->M + X->h_moff[c], P, 128, P / 128, c2 - c, (int64_t)P * P, st,
+                                       nullptr, inner_kc, X->cpivot);
+        c = c2;
+      }
     }
     if (e != hipSuccess) return e;
     if (plain) {

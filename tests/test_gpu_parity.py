@@ -774,3 +774,27 @@ def test_two_level_degenerate_groups():
         check_queries(g, idx, v1, v2)
     share = build(g, share_comps=5, group_comps=4)
     check_share(g, share, 5)
+
+
+def test_big_components_closed_in_one_batch():
+    # three consecutive components of 1,200 vertices (padded to 1,280: above
+    # the one-workgroup limit) are closed by one batched launch sequence, a
+    # fourth of another size alone; every component against the oracle and
+    # the per-component (plain) build
+    rng = np.random.default_rng(77)
+    eu, ev, w = W.random_grid(rng, 40, 110, keep=0.9, diag=0.2, wlo=1, whi=500)
+    col = np.arange(40 * 110) % 110
+    part = np.where(col < 30, 0, np.where(col < 60, 1, np.where(col < 90, 2, 3))).astype(np.int32)
+    g = dict(name="bigbatch", n=40 * 110, eu=eu, ev=ev, w=w, part=part, k=4)
+    idx = build(g)
+    lay = spq.index_layout(idx)
+    assert spq.index_stats(idx)["max_comp"] == 1200
+    check_components(g, idx, lay)
+    plain = build(g, plain=True)
+    for c in range(4):
+        size = int(np.count_nonzero(lay["comp"] == c))
+        assert np.array_equal(spq.index_component(idx, c, size), spq.index_component(plain, c, size))
+    rng2 = np.random.default_rng(3)
+    v1 = rng2.integers(0, g["n"], 3000).astype(np.int32)
+    v2 = rng2.integers(0, g["n"], 3000).astype(np.int32)
+    check_queries(g, idx, v1, v2)
