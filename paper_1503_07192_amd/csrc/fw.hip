@@ -18,7 +18,8 @@ namespace spq {
 //            same rounds on the sub-matrix, over blocks of half its size
 //   panel    tile (a, j), a in the block, j outside it: tile (a, j) =
 //            D (x) tile (a, j), stored twice (as (a, j) and transposed as
-//            (j, a)); k_fw_inner part 3 (the batched closures use k_fw_panel)
+//            (j, a)); k_fw_inner part 3 (k_fw_panel in fw_rounds, the
+//            one-tile rounds of a batch)
 //   interior tile (i, j) = min(tile (i, j),
 //            (block rows, tile i)^T (x) (block rows, tile j)), k_fw_inner
 // A two-tile block doubles the K of every interior product (256 instead of
