@@ -281,7 +281,8 @@ spq_status spq_index_bg_rows(const spq_index* idx, int32_t row0, int32_t nrows,
  * library's cache and is reused by later builds; NULL is ok. */
 void spq_free_index(spq_index* idx);
 
-/* Frees the device memory cached from released indexes (all devices). */
+/* Frees the device memory and destroys the streams cached from released
+ * indexes (all devices). */
 void spq_release_cached_memory(void);
 
 /* Message of the last error on this thread ("" if none). */

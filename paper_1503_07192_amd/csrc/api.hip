@@ -103,6 +103,48 @@ void pool_release(void* p) {
   P.live.erase(it);
 }
 
+// Streams for the lookahead's side work, graph capture and host-array
+// queries.  Creating and destroying a stream costs about 56 us on this
+// device: nothing next to a build, but more than half of a one-pair
+// spq_query_batch_host call (about 71 us with a stream of its own, 30 us with
+// one from here).  A freed index hands its streams back (after its work has
+// finished), a host query as soon as its stream has drained, and later calls
+// on the same device take them again.
+struct StreamPool {
+  std::mutex mu;
+  std::multimap<int, hipStream_t> idle;  // device -> stream
+};
+
+StreamPool& stream_pool() {
+  static StreamPool* p = new StreamPool();  // lives until the process ends
+  return *p;
+}
+
+hipError_t stream_take(hipStream_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    StreamPool& P = stream_pool();
+    std::lock_guard<std::mutex> lock(P.mu);
+    auto it = P.idle.find(dev);
+    if (it != P.idle.end()) {
+      *out = it->second;
+      P.idle.erase(it);
+      return hipSuccess;
+    }
+  }
+  return hipStreamCreateWithFlags(out, hipStreamNonBlocking);  // default priority
+}
+
+// s must have no queued work left
+void stream_give(int dev, hipStream_t s) {
+  if (!s) return;
+  StreamPool& P = stream_pool();
+  std::lock_guard<std::mutex> lock(P.mu);
+  P.idle.insert({dev, s});
+}
+
 template <typename T>
 hipError_t dalloc(T** p, int64_t count) {
   *p = nullptr;
@@ -199,12 +241,13 @@ struct spq_index {
     for (auto& e : prof) (void)hipEventDestroy(e);
     for (auto& e : la_sync)
       if (e) (void)hipEventDestroy(e);
-    if (side) (void)hipStreamDestroy(side);
-    // no queued work of this index may still use its memory once it is cached
+    // no queued work of this index may still use its memory or its streams
+    // once they are cached
     (void)hipDeviceSynchronize();
+    stream_give(device, side);
     for (auto x : execs) (void)hipGraphExecDestroy(x);
     for (auto g : graphs) (void)hipGraphDestroy(g);
-    if (cap) (void)hipStreamDestroy(cap);
+    stream_give(device, cap);
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
                     vrec, gT,    grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
@@ -726,7 +769,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     eu = X->eu_own;
     ev = X->ev_own;
     w = X->w_own;
-    TRY(hipStreamCreateWithFlags(&X->cap, hipStreamNonBlocking));  // default priority
+    TRY(stream_take(&X->cap));
   }
 
   if (use_paths) {
@@ -927,7 +970,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     // the single-matrix closure (BG2, or BG3 at level 3) runs with the
     // lookahead of the flat method
     if (lookahead) {
-      TRY(hipStreamCreateWithFlags(&X->side, hipStreamNonBlocking));  // default priority
+      TRY(stream_take(&X->side));
       for (auto& e : X->la_sync) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       ha.side = X->side;
       ha.sync = X->la_sync;
@@ -1032,7 +1075,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   TRY(hipMemsetAsync(X->pairbase, 0, sizeof(int64_t), s));
   const bool la = lookahead && X->Vp / tile > 1;
   if (la) {
-    TRY(hipStreamCreateWithFlags(&X->side, hipStreamNonBlocking));  // default priority
+    TRY(stream_take(&X->side));
     for (auto& e : X->la_sync) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   hipEvent_t* pev = X->prof.empty() ? nullptr : X->prof.data();
@@ -1160,7 +1203,9 @@ spq_status spq_query_batch_host(const spq_index* X, int64_t q, const int32_t* v1
   int32_t* d = nullptr;
   HIP_TRY(dalloc(&d, 3 * q));
   hipStream_t s = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);  // default priority
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = stream_take(&s);
   // the index may still be building on another stream
   if (e == hipSuccess) e = hipStreamWaitEvent(s, X->ev[4], 0);
   if (e == hipSuccess) e = hipMemcpyAsync(d, v1, sizeof(int32_t) * q, hipMemcpyHostToDevice, s);
@@ -1174,7 +1219,10 @@ spq_status spq_query_batch_host(const spq_index* X, int64_t q, const int32_t* v1
   if (s) {
     const hipError_t es = hipStreamSynchronize(s);
     if (e == hipSuccess) e = es;
-    (void)hipStreamDestroy(s);
+    if (es == hipSuccess)
+      stream_give(dev, s);
+    else
+      (void)hipStreamDestroy(s);
   }
   pool_release(d);  // the stream has drained: nothing queued uses d any more
   if (st != SPQ_OK) return st;
@@ -1272,9 +1320,15 @@ spq_status spq_index_bg_rows(const spq_index* X, int32_t row0, int32_t nrows, in
 void spq_free_index(spq_index* X) { delete X; }
 
 void spq_release_cached_memory(void) {
-  Pool& P = pool();
-  std::lock_guard<std::mutex> lock(P.mu);
-  pool_drop_idle(-1);
+  {
+    Pool& P = pool();
+    std::lock_guard<std::mutex> lock(P.mu);
+    pool_drop_idle(-1);
+  }
+  StreamPool& S = stream_pool();
+  std::lock_guard<std::mutex> lock(S.mu);
+  for (auto& it : S.idle) (void)hipStreamDestroy(it.second);
+  S.idle.clear();
 }
 
 spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* off,

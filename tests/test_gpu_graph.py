@@ -211,3 +211,37 @@ def test_grid256d_graph_build_and_reweight():
     check_queries(h, idx, v1[:2000], v2[:2000])
     spq.reweight(idx, dev(g["w"]))
     assert np.array_equal(run_queries(idx, v1, v2), want)
+
+
+def test_streams_of_freed_indexes_are_reused():
+    """A freed index hands its side and capture streams back to the library
+    and later builds take them again.  Builds alive at the same time, builds
+    made after frees (on reused streams), a capture and replays on a reused
+    capture stream, and host-array queries (whose stream comes from the same
+    cache) all agree with a build that uses no side stream."""
+    g = W.grid32()
+    v1, v2 = all_pairs(g["n"])
+    base = build(g, bg_tile=64, lookahead=False)
+    ref_rows = spq.index_bg_rows(base, 0, 348, 348)
+    ref_q = run_queries(base, v1, v2)
+    for rep in range(3):
+        print("round %d" % rep, flush=True)
+        a = build(g, bg_tile=64)
+        b = build(g, bg_tile=64, graph=True)
+        c = build(g, bg_method=2, group_comps=1, level3_groups=2)
+        for x in (a, b, c):
+            assert np.array_equal(spq.index_bg_rows(x, 0, 348, 348), ref_rows)
+            assert np.array_equal(run_queries(x, v1, v2), ref_q)
+        assert np.array_equal(spq.query_batch_host(a, v1[::5], v2[::5]), ref_q[::5])
+        h = reweighted(g, 40 + rep, 1, 1000)
+        spq.reweight(b, dev(h["w"]))
+        fresh = build(h, bg_tile=64, lookahead=False)
+        assert np.array_equal(run_queries(b, v1, v2), run_queries(fresh, v1, v2))
+        for x in (a, b, c, fresh):
+            x.free()
+    check_queries(g, base, v1[::11], v2[::11])
+    base.free()
+    spq.release_cached_memory()
+    again = build(g, bg_tile=64, graph=True)
+    assert np.array_equal(run_queries(again, v1, v2), ref_q)
+
