@@ -868,6 +868,15 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     ha.M = X->M; ha.grp = X->grp; ha.gbg0 = X->gbg0; ha.gV = X->gV; ha.bgrow = X->bgrow;
     ha.bgnb = X->bgnb; ha.bggrp = X->bggrp; ha.Mg = X->Mg; ha.flag2 = X->flag2; ha.b2list = X->b2list;
     ha.b2rank = X->b2rank; ha.m2 = X->m2;
+    // the closures of this path (the groups' and super-groups' batches, BG2
+    // or BG3) run with the lookahead of the flat method; a share build keeps
+    // to one stream
+    if (lookahead && X->share_comps == 0) {
+      TRY(stream_take(&X->side));
+      for (auto& e : X->la_sync) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ha.side = X->side;
+      ha.sync = X->la_sync;
+    }
     TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
       hipError_t e = phase2(st);
       if (e == hipSuccess && !X->graph) e = hipEventRecord(X->ev[3], st);
@@ -967,14 +976,6 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       ha.cert_mbg = X->cert + 3;
       X->fused_cert = true;
     }
-    // the single-matrix closure (BG2, or BG3 at level 3) runs with the
-    // lookahead of the flat method
-    if (lookahead) {
-      TRY(stream_take(&X->side));
-      for (auto& e : X->la_sync) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      ha.side = X->side;
-      ha.sync = X->la_sync;
-    }
     if (X->nT == 0) {
       TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
         hipError_t e = spq::launch_hier_level2_prep(ha, st);
@@ -1002,6 +1003,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       la.grp = X->grp; la.b2off = X->b2off; la.b2rank = X->b2rank; la.BG2 = X->BG2;
       la.tbase = X->tbase; la.tsize = X->tsize; la.M3 = X->M3; la.flag3 = X->flag3;
       la.b3list = X->b3list; la.b3rank = X->b3rank; la.m3 = X->m3;
+      la.side = ha.side; la.sync = ha.sync;
       TRY(graph_segment(X, s, [&](hipStream_t st) -> hipError_t {
         hipError_t e = spq::launch_hier_level2_prep(ha, st);
         if (e == hipSuccess) e = spq::launch_level3_a(la, st);

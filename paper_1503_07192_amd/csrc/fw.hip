@@ -313,19 +313,21 @@ static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, 
 // reads nor writes a tile that the next round's diagonal or panel touches
 // (rows and columns of the next block: the panel also writes the tiles of the
 // current block's rows in those columns, which part 2 does not read), so the
-// two overlap safely.  ev (optional) gets one pair per round around parts 1 + 2.
+// two overlap safely.  A batch of matrices runs the same rounds side by side
+// (the argument holds for each).  ev (optional) gets one pair per round
+// around parts 1 + 2.
 template <int T, int KC>
-static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, int pivot_tiles, hipStream_t s,
-                                      hipStream_t side, hipEvent_t* sync, hipEvent_t* ev) {
+static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, int pivot_tiles, FwBatch bt,
+                                      hipStream_t s, hipStream_t side, hipEvent_t* sync,
+                                      hipEvent_t* ev) {
   std::vector<FwBlock> blk(fw_blocks(nt, pivot_tiles, nullptr));
   fw_blocks(nt, pivot_tiles, blk.data());
-  const FwBatch one{1, 0};
   // sync[0] = side stream may start the next round (part 1 of this one done);
   // sync[1] = main stream may start the next round's interior (its panel done)
   CHK(hipEventRecord(sync[0], s));
   CHK(hipStreamWaitEvent(side, sync[0], 0));
-  CHK((fw_close<T, KC>(A, ld, blk[0], one, side)));
-  CHK((fw_panel<T, KC>(A, ld, nt, blk[0], one, side)));
+  CHK((fw_close<T, KC>(A, ld, blk[0], bt, side)));
+  CHK((fw_panel<T, KC>(A, ld, nt, blk[0], bt, side)));
   CHK(hipEventRecord(sync[1], side));
   for (size_t q = 0; q < blk.size(); q++) {
     CHK(hipStreamWaitEvent(s, sync[1], 0));
@@ -333,16 +335,16 @@ static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, int pivot_tile
     if (ev) CHK(hipEventRecord(ev[2 * q], s));
     if (q + 1 < blk.size()) {
       const int nn = blk[q + 1].pt;
-      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 1, nn, one, s)));
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 1, nn, bt, s)));
       CHK(hipEventRecord(sync[0], s));
       CHK(hipStreamWaitEvent(side, sync[0], 0));
-      CHK((fw_close<T, KC>(A, ld, blk[q + 1], one, side)));
-      CHK((fw_panel<T, KC>(A, ld, nt, blk[q + 1], one, side)));
-      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 2, nn, one, s)));
+      CHK((fw_close<T, KC>(A, ld, blk[q + 1], bt, side)));
+      CHK((fw_panel<T, KC>(A, ld, nt, blk[q + 1], bt, side)));
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 2, nn, bt, s)));
       CHK(hipEventRecord(sync[1], side));
     } else {
       // last round: nothing to look ahead to
-      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 0, 0, one, s)));
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 0, 0, bt, s)));
     }
     if (ev) CHK(hipEventRecord(ev[2 * q + 1], s));
   }
@@ -363,14 +365,21 @@ hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, 
 hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
                                      hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc,
                                      int pivot) {
-  if (nt <= 0) return hipSuccess;
+  return launch_dense_fw_batch_lookahead(A, ld, tile, nt, 1, 0, s, side, sync, ev, kc, pivot);
+}
+
+hipError_t launch_dense_fw_batch_lookahead(u32* A, int64_t ld, int tile, int nt, int batch,
+                                           int64_t gstride, hipStream_t s, hipStream_t side,
+                                           hipEvent_t* sync, hipEvent_t* ev, int kc, int pivot) {
+  if (nt <= 0 || batch <= 0) return hipSuccess;
   const int pt = pivot_tiles_of(tile, pivot);
   if (kc == 0) kc = SPQ_INNER_KC;
+  const FwBatch bt{batch, gstride};
   if (tile == 64)
-    return kc == 32 ? fw_rounds_lookahead<64, 32>(A, ld, nt, pt, s, side, sync, ev)
-                    : fw_rounds_lookahead<64, 16>(A, ld, nt, pt, s, side, sync, ev);
-  return kc == 32 ? fw_rounds_lookahead<128, 32>(A, ld, nt, pt, s, side, sync, ev)
-                  : fw_rounds_lookahead<128, 16>(A, ld, nt, pt, s, side, sync, ev);
+    return kc == 32 ? fw_rounds_lookahead<64, 32>(A, ld, nt, pt, bt, s, side, sync, ev)
+                    : fw_rounds_lookahead<64, 16>(A, ld, nt, pt, bt, s, side, sync, ev);
+  return kc == 32 ? fw_rounds_lookahead<128, 32>(A, ld, nt, pt, bt, s, side, sync, ev)
+                  : fw_rounds_lookahead<128, 16>(A, ld, nt, pt, bt, s, side, sync, ev);
 }
 #undef CHK
 

@@ -835,8 +835,13 @@ hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s) {
   if (a.m > 0)
     k_grp_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
                                              a.gbg0, a.Vgp, a.Mg, a.flag2);
-  hipError_t e = launch_dense_fw_batch(a.Mg, a.Vgp, 128, a.Vgp / 128, a.ngroups,
-                                       (int64_t)a.Vgp * a.Vgp, s, nullptr, a.kc, a.pivot);
+  const int ntg = a.Vgp / 128;
+  hipError_t e = (a.side && ntg > 1)
+                     ? launch_dense_fw_batch_lookahead(a.Mg, a.Vgp, 128, ntg, a.ngroups,
+                                                       (int64_t)a.Vgp * a.Vgp, s, a.side, a.sync,
+                                                       nullptr, a.kc, a.pivot)
+                     : launch_dense_fw_batch(a.Mg, a.Vgp, 128, ntg, a.ngroups, (int64_t)a.Vgp * a.Vgp,
+                                             s, nullptr, a.kc, a.pivot);
   if (e != hipSuccess) return e;
   k_b2_scan<<<(unsigned)a.ngroups, 256, 0, s>>>(a.gbg0, a.gV, a.flag2, a.Vgp, a.b2list, a.b2rank, a.m2);
   return hipGetLastError();
@@ -906,8 +911,13 @@ hipError_t launch_flat_store(int32_t V, int64_t Vp, const u32* BG, const int32_t
 hipError_t launch_level3_a(const L3Args& a, hipStream_t s) {
   k_l3_gather<<<dim3((unsigned)a.V3gp, (unsigned)a.nT), 256, 0, s>>>(a.V2p, a.BG2, a.tbase, a.tsize,
                                                                       a.V3gp, a.M3);
-  hipError_t e = launch_dense_fw_batch(a.M3, a.V3gp, 128, a.V3gp / 128, a.nT,
-                                       (int64_t)a.V3gp * a.V3gp, s, nullptr, a.kc, a.pivot);
+  const int ntt = a.V3gp / 128;
+  hipError_t e = (a.side && ntt > 1)
+                     ? launch_dense_fw_batch_lookahead(a.M3, a.V3gp, 128, ntt, a.nT,
+                                                       (int64_t)a.V3gp * a.V3gp, s, a.side, a.sync,
+                                                       nullptr, a.kc, a.pivot)
+                     : launch_dense_fw_batch(a.M3, a.V3gp, 128, ntt, a.nT, (int64_t)a.V3gp * a.V3gp,
+                                             s, nullptr, a.kc, a.pivot);
   if (e != hipSuccess) return e;
   if (a.m > 0)
     k_l3_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,

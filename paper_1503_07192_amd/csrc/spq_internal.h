@@ -204,6 +204,10 @@ hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch
 hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
                                      hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc,
                                      int pivot = 0);
+// the lookahead closure of `batch` matrices, gstride elements apart
+hipError_t launch_dense_fw_batch_lookahead(u32* A, int64_t ld, int tile, int nt, int batch,
+                                           int64_t gstride, hipStream_t s, hipStream_t side,
+                                           hipEvent_t* sync, hipEvent_t* ev, int kc, int pivot);
 // rounds of a single-matrix closure (pivot blocks)
 int fw_rounds_count(int nt, int tile, int pivot);
 // relaxations executed by launch_dense_fw (diagonal, panel and upper-triangle
