@@ -68,6 +68,13 @@ GRAPH_CASES = [
     ("bigcomp_pivot512", bigcomp_case, {"bg_pivot": 512}),
     ("grid30_level3_pivot512", lambda: grid_case(3, 30, 27, 5),
      {"bg_method": 2, "group_comps": 2, "level3_groups": 3, "bg_pivot": 512}),
+    # group and super-group matrices of several tiles: their batched closures
+    # take the lookahead inside the capture (4 groups of 4 tiles; 4
+    # super-groups of 3 tiles)
+    ("grid64_two_level_batch_lookahead", lambda: grid_case(5, 64, 64, 8),
+     {"bg_method": 2, "group_comps": 16}),
+    ("grid64_level3_batch_lookahead", lambda: grid_case(5, 64, 64, 8),
+     {"bg_method": 2, "group_comps": 2, "level3_groups": 8}),
 ]
 
 
@@ -244,4 +251,33 @@ def test_streams_of_freed_indexes_are_reused():
     spq.release_cached_memory()
     again = build(g, bg_tile=64, graph=True)
     assert np.array_equal(run_queries(again, v1, v2), ref_q)
+
+
+def test_batched_closures_with_lookahead_equal_flat():
+    """The group closures (4 matrices of 512, 4 tiles each) and the
+    super-group closures (4 of 384) run their rounds with the lookahead, a
+    batch side by side: with two-tile and one-tile pivot blocks, and without
+    the lookahead, every BG row and query equals the flat build's."""
+    g = grid_case(5, 64, 64, 8)
+    flat = build(g, bg_method=1, lookahead=False)
+    V = spq.index_stats(flat)["v_bg"]
+    assert V == 1504
+    want_rows = spq.index_bg_rows(flat, 0, V, V)
+    rng = np.random.default_rng(9)
+    v1 = rng.integers(0, g["n"], 20000).astype(np.int32)
+    v2 = rng.integers(0, g["n"], 20000).astype(np.int32)
+    want_q = run_queries(flat, v1, v2)
+    check_queries(g, flat, v1[:3000], v2[:3000])
+    cases = [({"group_comps": 16}, 4, 0), ({"group_comps": 16, "bg_pivot": 128}, 4, 0),
+             ({"group_comps": 16, "lookahead": False}, 4, 0),
+             ({"group_comps": 2, "level3_groups": 8}, 32, 4),
+             ({"group_comps": 2, "level3_groups": 8, "bg_pivot": 128}, 32, 4),
+             ({"group_comps": 2, "level3_groups": 8, "lookahead": False}, 32, 4)]
+    for kw, ngroups, groups3 in cases:
+        x = build(g, bg_method=2, **kw)
+        st = spq.index_stats(x)
+        assert st["ngroups"] == ngroups and st["groups3"] == groups3, kw
+        assert np.array_equal(spq.index_bg_rows(x, 0, V, V), want_rows), kw
+        assert np.array_equal(run_queries(x, v1, v2), want_q), kw
+        x.free()
 
