@@ -210,7 +210,8 @@ struct spq_index {
   u32 cert_mc = 0, cert_mbg = 0;
   // lookahead of the flat rounds: side stream and its two sync events
   hipStream_t side = nullptr;
-  hipEvent_t la_sync[2] = {};
+  hipStream_t part1 = nullptr;  // flat rounds: part 1 of every round beside part 2
+  hipEvent_t la_sync[3] = {};
   hipEvent_t ev[5] = {};
   bool events = false;
   std::vector<hipEvent_t> prof;  // pairs around the BG interior-tile launches
@@ -245,6 +246,7 @@ struct spq_index {
     // once they are cached
     (void)hipDeviceSynchronize();
     stream_give(device, side);
+    stream_give(device, part1);
     for (auto x : execs) (void)hipGraphExecDestroy(x);
     for (auto g : graphs) (void)hipGraphDestroy(g);
     stream_give(device, cap);
@@ -1078,6 +1080,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
   const bool la = lookahead && X->Vp / tile > 1;
   if (la) {
     TRY(stream_take(&X->side));
+    TRY(stream_take(&X->part1));
     for (auto& e : X->la_sync) TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   hipEvent_t* pev = X->prof.empty() ? nullptr : X->prof.data();
@@ -1088,7 +1091,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     if (e != hipSuccess) return e;
     if (la)
       e = spq::launch_dense_fw_lookahead(X->BG, X->Vp, tile, X->Vp / tile, st, X->side, X->la_sync,
-                                         pev, inner_kc, X->pivot);
+                                         pev, inner_kc, X->pivot, X->part1);
     else
       e = spq::launch_dense_fw(X->BG, X->Vp, tile, X->Vp / tile, st, pev, inner_kc, X->pivot);
     if (e != hipSuccess) return e;

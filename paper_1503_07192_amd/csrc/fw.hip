@@ -314,16 +314,19 @@ static hipError_t fw_rounds_blocks(u32* A, int64_t ld, int nt, int pivot_tiles, 
 // (rows and columns of the next block: the panel also writes the tiles of the
 // current block's rows in those columns, which part 2 does not read), so the
 // two overlap safely.  A batch of matrices runs the same rounds side by side
-// (the argument holds for each).  ev (optional) gets one pair per round
-// around parts 1 + 2.
+// (the argument holds for each).  With a third stream p1, part 1 runs there
+// beside part 2 instead of before it (part 1 alone leaves workgroup slots
+// idle); the round still ends only when both are done.  ev (optional) gets
+// one pair per round around parts 1 + 2.
 template <int T, int KC>
 static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, int pivot_tiles, FwBatch bt,
-                                      hipStream_t s, hipStream_t side, hipEvent_t* sync,
-                                      hipEvent_t* ev) {
+                                      hipStream_t s, hipStream_t side, hipStream_t p1,
+                                      hipEvent_t* sync, hipEvent_t* ev) {
   std::vector<FwBlock> blk(fw_blocks(nt, pivot_tiles, nullptr));
   fw_blocks(nt, pivot_tiles, blk.data());
   // sync[0] = side stream may start the next round (part 1 of this one done);
-  // sync[1] = main stream may start the next round's interior (its panel done)
+  // sync[1] = main stream may start the next round's interior (its panel done);
+  // sync[2] (with p1) = p1 may start this round's part 1
   CHK(hipEventRecord(sync[0], s));
   CHK(hipStreamWaitEvent(side, sync[0], 0));
   CHK((fw_close<T, KC>(A, ld, blk[0], bt, side)));
@@ -335,13 +338,20 @@ static hipError_t fw_rounds_lookahead(u32* A, int64_t ld, int nt, int pivot_tile
     if (ev) CHK(hipEventRecord(ev[2 * q], s));
     if (q + 1 < blk.size()) {
       const int nn = blk[q + 1].pt;
-      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 1, nn, bt, s)));
-      CHK(hipEventRecord(sync[0], s));
+      hipStream_t s1 = s;
+      if (p1) {
+        CHK(hipEventRecord(sync[2], s));
+        CHK(hipStreamWaitEvent(p1, sync[2], 0));
+        s1 = p1;
+      }
+      CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 1, nn, bt, s1)));
+      CHK(hipEventRecord(sync[0], s1));
       CHK(hipStreamWaitEvent(side, sync[0], 0));
       CHK((fw_close<T, KC>(A, ld, blk[q + 1], bt, side)));
       CHK((fw_panel<T, KC>(A, ld, nt, blk[q + 1], bt, side)));
       CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 2, nn, bt, s)));
       CHK(hipEventRecord(sync[1], side));
+      if (p1) CHK(hipStreamWaitEvent(s, sync[0], 0));  // the round ends with part 1 too
     } else {
       // last round: nothing to look ahead to
       CHK((fw_inner<T, KC>(A, ld, nt, blk[q], 0, 0, bt, s)));
@@ -362,24 +372,30 @@ hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, 
   return launch_dense_fw_batch(A, ld, tile, nt, 1, 0, s, ev, kc, pivot);
 }
 
+static hipError_t dense_lookahead(u32* A, int64_t ld, int tile, int nt, FwBatch bt, hipStream_t s,
+                                  hipStream_t side, hipStream_t p1, hipEvent_t* sync,
+                                  hipEvent_t* ev, int kc, int pivot) {
+  if (nt <= 0 || bt.batch <= 0) return hipSuccess;
+  const int pt = pivot_tiles_of(tile, pivot);
+  if (kc == 0) kc = SPQ_INNER_KC;
+  if (tile == 64)
+    return kc == 32 ? fw_rounds_lookahead<64, 32>(A, ld, nt, pt, bt, s, side, p1, sync, ev)
+                    : fw_rounds_lookahead<64, 16>(A, ld, nt, pt, bt, s, side, p1, sync, ev);
+  return kc == 32 ? fw_rounds_lookahead<128, 32>(A, ld, nt, pt, bt, s, side, p1, sync, ev)
+                  : fw_rounds_lookahead<128, 16>(A, ld, nt, pt, bt, s, side, p1, sync, ev);
+}
+
 hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
                                      hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc,
-                                     int pivot) {
-  return launch_dense_fw_batch_lookahead(A, ld, tile, nt, 1, 0, s, side, sync, ev, kc, pivot);
+                                     int pivot, hipStream_t p1) {
+  return dense_lookahead(A, ld, tile, nt, FwBatch{1, 0}, s, side, p1, sync, ev, kc, pivot);
 }
 
 hipError_t launch_dense_fw_batch_lookahead(u32* A, int64_t ld, int tile, int nt, int batch,
                                            int64_t gstride, hipStream_t s, hipStream_t side,
                                            hipEvent_t* sync, hipEvent_t* ev, int kc, int pivot) {
-  if (nt <= 0 || batch <= 0) return hipSuccess;
-  const int pt = pivot_tiles_of(tile, pivot);
-  if (kc == 0) kc = SPQ_INNER_KC;
-  const FwBatch bt{batch, gstride};
-  if (tile == 64)
-    return kc == 32 ? fw_rounds_lookahead<64, 32>(A, ld, nt, pt, bt, s, side, sync, ev)
-                    : fw_rounds_lookahead<64, 16>(A, ld, nt, pt, bt, s, side, sync, ev);
-  return kc == 32 ? fw_rounds_lookahead<128, 32>(A, ld, nt, pt, bt, s, side, sync, ev)
-                  : fw_rounds_lookahead<128, 16>(A, ld, nt, pt, bt, s, side, sync, ev);
+  return dense_lookahead(A, ld, tile, nt, FwBatch{batch, gstride}, s, side, nullptr, sync, ev, kc,
+                         pivot);
 }
 #undef CHK
 

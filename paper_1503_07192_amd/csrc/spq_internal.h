@@ -200,10 +200,11 @@ hipError_t launch_dense_fw(u32* A, int64_t ld, int tile, int nt, hipStream_t s, 
 hipError_t launch_dense_fw_batch(u32* A, int64_t ld, int tile, int nt, int batch, int64_t gstride,
                                  hipStream_t s, hipEvent_t* ev, int kc = 0, int pivot = 0);
 // Same closure with a lookahead over two streams (side: created by the caller,
-// default priority; sync: two events).
+// default priority; sync: two events), or three with p1 (part 1 of every
+// round beside part 2; sync: three events).
 hipError_t launch_dense_fw_lookahead(u32* A, int64_t ld, int tile, int nt, hipStream_t s,
                                      hipStream_t side, hipEvent_t* sync, hipEvent_t* ev, int kc,
-                                     int pivot = 0);
+                                     int pivot = 0, hipStream_t p1 = nullptr);
 // the lookahead closure of `batch` matrices, gstride elements apart
 hipError_t launch_dense_fw_batch_lookahead(u32* A, int64_t ld, int tile, int nt, int batch,
                                            int64_t gstride, hipStream_t s, hipStream_t side,
