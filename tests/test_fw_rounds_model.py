@@ -1,7 +1,8 @@
 """A CPU model of the blocked Floyd-Warshall rounds of csrc/fw.hip: the tile
 sets of the interior launches (parts 0-3 of k_fw_inner over pivot blocks of
 one, two or four tiles, the last blocks smaller), the diagonal-block closure
-by rounds over half-size blocks, and the lookahead's split of a round.  The
+by rounds over half-size blocks, and the lookahead's split of a round (with
+part 1 on the build stream, or on a stream of its own beside part 2).  The
 model runs the rounds on small matrices (tiles of 4) and must give plain
 Floyd-Warshall; the tile sets must be in bounds, disjoint where the lookahead
 overlaps them, and cover each round's interior once.  This checks the host
@@ -108,6 +109,27 @@ def close(A, c0, pt, T):
         A[s, s] = sub
 
 
+def norm(i, j):
+    return (i, j) if i <= j else (j, i)
+
+
+def check_overlap(nt, cur, nxt, t1, t2):
+    """Part 2 may run at the same time as part 1 and as the side stream's
+    closure and panel of the next block (tiles as unordered pairs: every
+    launch writes a tile and its transpose).  Part 2 must neither read what
+    they write nor write what they read or write."""
+    def reads(tiles):  # own tile and the current block's panel at its columns
+        return {norm(i, j) for i, j in tiles} | {norm(a, x) for i, j in tiles for a in cur
+                                                 for x in (i, j)}
+    r1, w1 = reads(t1), {norm(i, j) for i, j in t1}
+    r2, w2 = reads(t2), {norm(i, j) for i, j in t2}
+    # side: the next block's diagonal closure, then its panel (a, j), a in it
+    ws = {norm(a, b) for a in nxt for b in nxt} | {norm(a, j) for a in nxt for j in range(nt)}
+    rs = set(ws)
+    assert not (w2 & (r1 | w1 | rs | ws))
+    assert not (r2 & (w1 | ws))
+
+
 def rounds(A, nt, T, ptiles, lookahead):
     blk = blocks(nt, ptiles)
     for q, (c0, pt) in enumerate(blk):
@@ -119,13 +141,22 @@ def rounds(A, nt, T, ptiles, lookahead):
             continue
         if lookahead and q + 1 < len(blk):
             n0, npt = blk[q + 1]
-            t1 = launch(A, nt, T, pt, c0, 1, npt)
-            close(A, n0, npt, T)               # side stream, beside part 2
-            launch(A, nt, T, npt, n0, 3, 0)
-            t2 = launch(A, nt, T, pt, c0, 2, npt)
+            if lookahead == "p1":
+                # part 1 on a stream of its own: part 2 may run before it and
+                # before the side stream's work, which waits for part 1 only
+                t2 = launch(A, nt, T, pt, c0, 2, npt)
+                t1 = launch(A, nt, T, pt, c0, 1, npt)
+                close(A, n0, npt, T)
+                launch(A, nt, T, npt, n0, 3, 0)
+            else:
+                t1 = launch(A, nt, T, pt, c0, 1, npt)
+                close(A, n0, npt, T)               # side stream, beside part 2
+                launch(A, nt, T, npt, n0, 3, 0)
+                t2 = launch(A, nt, T, pt, c0, 2, npt)
             nxt = set(range(n0, n0 + npt))
             assert all(i not in nxt and j not in nxt for i, j in t2)
             cur = set(range(c0, c0 + pt))
+            check_overlap(nt, cur, nxt, t1, t2)
             assert set(t1) | set(t2) == {(i, j) for i in range(nt) for j in range(i, nt)
                                          if i not in cur and j not in cur}
             assert not set(t1) & set(t2)
@@ -134,9 +165,9 @@ def rounds(A, nt, T, ptiles, lookahead):
 
 
 @pytest.mark.parametrize("ptiles", [1, 2, 4])
-@pytest.mark.parametrize("lookahead", [False, True])
+@pytest.mark.parametrize("lookahead", [False, True, "p1"])
 def test_rounds_equal_floyd_warshall(ptiles, lookahead):
-    rng = np.random.default_rng(ptiles * 10 + lookahead)
+    rng = np.random.default_rng(ptiles * 10 + {False: 0, True: 1, "p1": 2}[lookahead])
     T = 4
     for nt in range(1, 12):
         V = nt * T
