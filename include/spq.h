@@ -67,8 +67,11 @@ typedef struct {
                           groups; needs the total edge weight below SPQ_INF */
   int32_t inner_kc;    /* K chunk of the Floyd-Warshall interior-tile kernel:
                           0 (default 16), 16 or 32 (see the autotuner) */
-  int32_t flags;       /* SPQ_NO_LOOKAHEAD: flat BG rounds without the overlap
-                          of the next round's diagonal and panel work.
+  int32_t flags;       /* SPQ_NO_LOOKAHEAD: Floyd-Warshall rounds on one
+                          stream: without the overlap of the next round's
+                          diagonal and panel work (flat BG; the two-level
+                          group, super-group, BG2 and BG3 closures) and,
+                          flat, of a round's two interior parts.
                           SPQ_GRAPH: the device work that depends on the
                           weights (Phase 2, BG assembly and closure) is
                           captured into HIP graphs, launched, and kept in the
