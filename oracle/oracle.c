@@ -254,3 +254,24 @@ void oracle_query_alg2(int64_t q, const int32_t* v1, const int32_t* v2,
   }
   free(t);
 }
+
+/* ------------------------------------------------------ min-plus product -- */
+/* C = A (x) B over (min, +): C[i][j] = min over k of A[i][k] + B[k][j].
+ * This is how distance tables compose through a separating vertex set: a
+ * shortest path from i to j that meets the set splits at a vertex k of it
+ * into an i-k part and a k-j part (the two stages of Algorithm 2, and the
+ * same composition one level up in the two-level BG).  A is n x K, B is
+ * K x p, C is n x p, all row-major; O_INF means no path, and with K = 0 every
+ * entry of C is O_INF. */
+void oracle_minplus(int32_t n, int32_t K, int32_t p, const int64_t* A, const int64_t* B,
+                    int64_t* C) {
+  for (int32_t i = 0; i < n; i++)
+    for (int32_t j = 0; j < p; j++) {
+      int64_t best = O_INF;
+      for (int32_t k = 0; k < K; k++) {
+        int64_t c = sat_add(A[(int64_t)i * K + k], B[(int64_t)k * p + j]);
+        if (c < best) best = c;
+      }
+      C[(int64_t)i * p + j] = best;
+    }
+}

@@ -26,9 +26,15 @@ What it computes, each from its definition in the paper:
 * ``bg_apsp``         SSSP in BG from each requested BG vertex by Dijkstra
                       (Algorithm 1, Phase 3).
 * ``query_alg2``      Algorithm 2 evaluated literally on those tables.
+* ``minplus``         the (min, +) product of two distance tables: how
+                      distances compose through a separating vertex set (the
+                      two stages of Algorithm 2; the composition of the
+                      two-level BG applies it one level up).
 
 Pins (in tests/test_oracle_pins.py): brute force on tiny graphs; closed forms
-on grids and paths; Lemma 1 (BG distances equal G distances); Lemma 3 (the
+on grids and paths; for ``minplus``, its identity element, walks of at most
+two edges enumerated edge by edge, repeated squaring reaching the
+brute-force distances, a closed form and the transpose identity; Lemma 1 (BG distances equal G distances); Lemma 3 (the
 query equals the G distance); the k = 1 and k = n reductions; invariance under
 partition and boundary superset; metric invariants.
 """
@@ -72,6 +78,9 @@ def lib():
         L.oracle_fw.argtypes = [ctypes.c_int32, i64p]
         L.oracle_fw_many.restype = None
         L.oracle_fw_many.argtypes = [ctypes.c_int32, i32p, i64p, i64p, ctypes.c_int32]
+        L.oracle_minplus.restype = None
+        L.oracle_minplus.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i64p, i64p,
+                                     i64p]
         L.oracle_query_alg2.restype = None
         L.oracle_query_alg2.argtypes = [ctypes.c_int64, i32p, i32p, i32p, i32p, i32p, i64p,
                                         i64p, i32p, i32p, ctypes.c_int32, i64p, i64p]
@@ -282,6 +291,19 @@ def query_alg2(T, v1, v2):
     lib().oracle_query_alg2(len(v1), v1, v2, comp, pos, csize, moff, np.ascontiguousarray(apsp),
                             bstart, _i32(blocal), V, dbg.ravel(), out)
     return out
+
+
+def minplus(A, B):
+    """(min, +) product of int64 tables (O_INF = no path): C[i][j] = min over
+    k of A[i][k] + B[k][j]."""
+    A = np.ascontiguousarray(A, np.int64)
+    B = np.ascontiguousarray(B, np.int64)
+    if A.ndim != 2 or B.ndim != 2 or A.shape[1] != B.shape[0]:
+        raise ValueError("minplus: shapes %s and %s do not chain" % (A.shape, B.shape))
+    C = np.empty((A.shape[0], B.shape[1]), np.int64)
+    if C.size:
+        lib().oracle_minplus(A.shape[0], A.shape[1], B.shape[1], A, B, C)
+    return C
 
 
 def to_int32_distance(d):
