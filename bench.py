@@ -1,15 +1,16 @@
 """Benchmark: one step = the whole hot path on one batch of synthetic input.
 
 A step builds the index (boundary + renumbering, APSP of every component,
-BG assembly, all-pairs distances in BG) and answers one batch of query pairs,
-on the 256x256 grid with random diagonals (65,536 vertices, 1,024 blocks of
-8x8, 100,000 uniform pairs).  Inputs are resident in HBM before timing.
+BG assembly, distances in BG) and answers one batch of query pairs.  The
+default workload is the largest one that fits one GPU: the 2048x2048 grid
+with 10% of its edges deleted (4.19M vertices, 16,384 components of 16x16),
+built as one GPU's share (all APSP(C), BG rows of components [0, 512)),
+then 10M query pairs with v1 in the share.  Inputs are resident in HBM
+before timing.
 
 Prints ONE JSON line.  `value` is min-plus relaxations executed per second
-over the whole step (queries included in the time): the Floyd-Warshall
-relaxations the kernels perform for all components and for BG.  Symmetric
-tiles are computed once, so this count is about half of sum(|C|^3) + V_BG^3;
-`fw_equiv_relax_per_s` divides that full count by the same time.
+over the whole step (queries included in the time); `index_build_ms` is the
+build alone and `query_batch_ms_p50/p99` the batch, both from HIP events.
 """
 import argparse
 import json
@@ -22,15 +23,19 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 lane-cycles/s.  A relaxation
-# is one v_add_u32 and half a v_min3_u32 (two candidates per min3).  gfx950
-# issues v_add_u32 at two lane-operations per lane-cycle and v_min3_u32 at one
-# (measured every run by spq_valu_rates, reported as valu_rates), so a
-# relaxation costs 1/2 + 1/2 lane-cycle: 3.93e13 relaxations/s.  (Counting
-# every instruction at one per lane-cycle would give 2.62e13, which the
-# kernels exceed.)
+# MI355X: 256 CUs x 2.4 GHz.  A relaxation c = min(c, a+b) is one v_add_u32
+# and half a v_min3_u32 (two candidates folded per min3): 1.5 VALU
+# instructions.  The published fp32 vector peak, 157.3 TFLOP/s, is 128
+# lanes per CU per clock (an FMA counts two flops); at that rate for every
+# 32-bit instruction a relaxation costs 1.5 / 128 CU-clocks: 5.24e13
+# relaxations/s, the peak the roofline fraction is taken against.  At 64
+# lanes per CU per clock for v_min3_u32 and 128 for v_add_u32 (what
+# spq_valu_rates measures on the box: the add above 64 lanes per clock, the
+# min3 below it) the bound would be 3.93e13: reported beside it as the lower
+# end of the band.
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
-RELAX_PEAK = LANE_CYCLES_PER_S * 1.0
+RELAX_PEAK = 256 * 2.4e9 * 128 / 1.5
+RELAX_PEAK_LOW = LANE_CYCLES_PER_S * 1.0
 HBM_PEAK = 8.0e12
 
 
@@ -39,7 +44,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="grid256d", choices=sorted(WORKLOADS))
+    p.add_argument("--workload", default="grid2048", choices=sorted(WORKLOADS))
     p.add_argument("--queries", type=int, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -107,29 +112,44 @@ def make_workload(name, queries):
 
 
 def cpu_baseline(g, st, budget_s):
-    """The oracle as it stands, timed on a bounded sample of the same workload."""
+    """The oracle as it stands (built -O3 -march=native on this host), timed on
+    a bounded sample of the same workload: component Floyd-Warshalls on all
+    threads and on one, Dijkstra in BG from sampled sources where BG is small
+    enough for the oracle, and one Dijkstra on G per query."""
     import oracle
+    oracle.configure(native=True)
     threads = max(1, min(16, os.cpu_count() or 1))
     n, k = g["n"], g["k"]
     rng = np.random.default_rng(0)
-    comps = np.arange(k) if k <= 1024 else np.sort(rng.choice(k, 1024, replace=False))
-    t0 = time.perf_counter()
-    members, apsp = oracle.component_apsp(n, g["eu"], g["ev"], g["w"], g["part"], k, comps=comps,
-                                          nthreads=threads)
-    t_comp = time.perf_counter() - t0
+    order = rng.permutation(k)
+
+    def fw_sample(count, nthreads):
+        comps = np.sort(order[:count])
+        t0 = time.perf_counter()
+        members, apsp = oracle.component_apsp(n, g["eu"], g["ev"], g["w"], g["part"], k,
+                                              comps=comps, nthreads=nthreads)
+        return comps, members, apsp, time.perf_counter() - t0
+
+    def budgeted(nthreads, seconds):
+        # a first sample fixes the rate; the second fills the budget
+        c = min(k, 64 * nthreads)
+        comps, members, apsp, t = fw_sample(c, nthreads)
+        if t < seconds and c < k:
+            c = int(min(k, max(c + 1, c * seconds / max(t, 1e-3))))
+            comps, members, apsp, t = fw_sample(c, nthreads)
+        return comps, members, apsp, t
+
+    comps, members, apsp, t_comp = budgeted(threads, budget_s * 0.3)
     relax_sample = float(sum(len(m) ** 3 for m in members))
     res = {"value": relax_sample / t_comp, "unit": "relax/s", "cores": threads, "kind": "oracle",
-           "sample": "Floyd-Warshall of %d of %d components (%.3g relaxations, %.2f s)"
-                     % (len(comps), k, relax_sample, t_comp)}
-    # the same on one thread, an eighth of the sample
-    comps1 = comps[:max(1, len(comps) // 8)]
-    t0 = time.perf_counter()
-    members1, _ = oracle.component_apsp(n, g["eu"], g["ev"], g["w"], g["part"], k, comps=comps1,
-                                        nthreads=1)
-    t1 = time.perf_counter() - t0
+           "build": "gcc -O3 -march=native",
+           "sample": "Floyd-Warshall of %d of %d components (%.3g relaxations, %.2f s, %d threads)"
+                     % (len(comps), k, relax_sample, t_comp, threads)}
+    comps1, members1, _, t1 = budgeted(1, budget_s * 0.15)
     res["value_1thread"] = float(sum(len(m) ** 3 for m in members1)) / t1
     res["sample"] += "; one thread: %d components in %.2f s" % (len(comps1), t1)
-    if k <= 1024:
+    res["component_phase_s"] = float(st["relax_comp"]) / res["value"]
+    if k <= 1024 and len(comps) == k:
         # the paper's Phase 3: Dijkstra in BG from a budgeted number of sources
         bg_ids, bverts, bu, bv, bw = oracle.boundary_graph(n, g["eu"], g["ev"], g["w"], g["part"],
                                                            k, members, apsp)
@@ -137,7 +157,7 @@ def cpu_baseline(g, st, budget_s):
         t0 = time.perf_counter()
         oracle.bg_apsp(bg_ids, bu, bv, bw, sources=np.arange(min(64, V)), nthreads=threads)
         per_src = (time.perf_counter() - t0) / min(64, V)
-        nsrc = int(min(V, max(64, budget_s * 0.6 / max(per_src, 1e-6))))
+        nsrc = int(min(V, max(64, budget_s * 0.3 / max(per_src, 1e-6))))
         t0 = time.perf_counter()
         oracle.bg_apsp(bg_ids, bu, bv, bw, sources=np.arange(nsrc), nthreads=threads)
         t_bg = (time.perf_counter() - t0) * V / nsrc
@@ -145,11 +165,18 @@ def cpu_baseline(g, st, budget_s):
         res["sample"] += ("; Dijkstra in BG from %d of %d sources, scaled: whole index in %.1f s"
                           % (nsrc, V, t_comp + t_bg))
     # the paper's comparison for queries: one Dijkstra per query on G
-    nq = 16
+    nq = threads
     t0 = time.perf_counter()
     oracle.dijkstra(n, g["eu"], g["ev"], g["w"], g["v1"][:nq], nthreads=threads)
-    res["queries_per_s"] = nq / (time.perf_counter() - t0)
-    res["query_sample"] = "Dijkstra on G from %d query sources, %d threads" % (nq, threads)
+    t = time.perf_counter() - t0
+    if t < budget_s * 0.25:
+        nq = int(min(len(g["v1"]), max(nq + 1, nq * budget_s * 0.25 / max(t, 1e-3))))
+        t0 = time.perf_counter()
+        oracle.dijkstra(n, g["eu"], g["ev"], g["w"], g["v1"][:nq], nthreads=threads)
+        t = time.perf_counter() - t0
+    res["queries_per_s"] = nq / t
+    res["query_sample"] = "Dijkstra on G from %d query sources, %d threads, %.2f s" % (
+        nq, threads, t)
     return res
 
 
@@ -184,15 +211,17 @@ def main():
     torch.cuda.synchronize()
 
     def step(record):
+        eb, e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        eb.record(stream)
         idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], profile=True, stream=stream,
                               **build_kw)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         spq.query_batch(idx, v1, v2, out, stream=stream)
         e1.record(stream)
         st = spq.index_stats(idx)
         e1.synchronize()
         if record is not None:
+            st["ms_build"] = eb.elapsed_time(e0)
             st["ms_query"] = e0.elapsed_time(e1)
             record.append(st)
         idx.free()
@@ -209,10 +238,10 @@ def main():
 
     st = recs[-1]
     relax = st["relax_comp_exec"] + st["relax_bg_exec"]
-    relax_fw = st["relax_comp"] + st["relax_bg"]
     ms_step = elapsed * 1e3 / args.steps
     q = len(g["v1"])
     mq = np.array([r["ms_query"] for r in recs])
+    mb = np.array([r["ms_build"] for r in recs])
     # dominant kernel: the BG interior-tile launches, timed with HIP events on
     # the build stream inside the timed steps
     inner_ms = np.array([r["ms_dominant"] for r in recs])
@@ -275,6 +304,8 @@ def main():
     idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], plain=True, paths=True, stream=stream,
                           **build_kw)
     plain_st = spq.index_stats(idx)
+    lay = spq.index_layout(idx)
+    layout_tables = (lay["comp"], lay["nb"])
     # shortest paths (vertex sequences) for the first 1,000 pairs
     npath = min(1000, q)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -308,9 +339,14 @@ def main():
     idx.free()
     lat = np.array(lat)
 
-    # bytes the query kernel must move: both row prefixes, the BG block, ids, result
-    nbv = st["v_bg"] / st["k"]
-    qbytes = 4 * (nbv + nbv * nbv + nbv) + 12 + 16
+    # bytes the query kernel must move per pair: both row prefixes, the BG
+    # block, the ids and the result (12), the two 48-byte vertex records read
+    # as the 16 bytes a pair uses, and d_C1(v1, v2) when C1 = C2
+    comp_of, nb_of = layout_tables
+    c1, c2 = comp_of[g["v1"]], comp_of[g["v2"]]
+    nb1, nb2 = nb_of[c1].astype(np.float64), nb_of[c2].astype(np.float64)
+    qbytes_total = float(np.sum(4 * (nb1 + nb1 * nb2 + nb2) + 12 + 16 + 4 * (c1 == c2)))
+    qbytes = qbytes_total / q
 
     line = {
         "metric": "min-plus relaxations/s (index build); queries/s + p50/p99 query latency",
@@ -331,7 +367,9 @@ def main():
                      for key in ("ms_partition", "ms_components", "ms_bg_assembly",
                                  "ms_bg_apsp", "ms_query")},
         "relax_per_step": relax,
-        "fw_equiv_relax_per_s": relax_fw * args.steps / elapsed,
+        "index_build_ms": float(np.median(mb)),
+        "index_build_ms_p99": float(np.percentile(mb, 99)),
+        "index_build_relax_per_s": relax / (np.median(mb) * 1e-3),
         "queries_per_s": q / (np.median(mq) * 1e-3),
         "queries_per_s_warm": q / (np.median(warm) * 1e-3),
         "query_batch_ms_p50": float(np.percentile(mq, 50)),
@@ -346,15 +384,19 @@ def main():
         "roofline": {"bound": "alu", "kernel": kernel,
                      "achieved": inner_rate / 1e12, "peak": RELAX_PEAK / 1e12,
                      "unit": "Trelax/s", "frac": inner_rate / RELAX_PEAK,
+                     "peak_band": {"low": RELAX_PEAK_LOW / 1e12, "high": RELAX_PEAK / 1e12,
+                                   "frac_high_to_low": [inner_rate / RELAX_PEAK,
+                                                        inner_rate / RELAX_PEAK_LOW]},
                      "traffic": recorded_traffic(("k_fw_inner_" if st["bg_method"] == 1 else "k_mp_y_")
                                                  + args.workload, per_launch),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "scaled by a 256 MiB copy)",
                      "launches_per_step": launches, "avg_launch_ms": avg_launch_ms,
                      "relax_per_launch": per_launch},
-        "query_roofline": {"bound": "hbm", "achieved": q * qbytes / (np.median(mq) * 1e-3) / 1e9,
+        "query_roofline": {"bound": "hbm", "achieved": qbytes_total / (np.median(mq) * 1e-3) / 1e9,
                            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                           "frac": q * qbytes / (np.median(mq) * 1e-3) / HBM_PEAK,
+                           "frac": qbytes_total / (np.median(mq) * 1e-3) / HBM_PEAK,
+                           "frac_warm": qbytes_total / (np.median(warm) * 1e-3) / HBM_PEAK,
                            "bytes_per_query": qbytes,
                            "traffic": recorded_traffic("k_query_" + args.workload, float(q)),
                            "traffic_unit": "HBM bytes per launch of the step's batch (rocprofv3 "
@@ -366,7 +408,8 @@ def main():
         "v_add_u32_lane_ops_per_s": vr["v_add_u32"], "v_min3_u32_lane_ops_per_s": vr["v_min3_u32"],
         "per_nominal_lane_cycle": {"v_add_u32": vr["v_add_u32"] / LANE_CYCLES_PER_S,
                                    "v_min3_u32": vr["v_min3_u32"] / LANE_CYCLES_PER_S},
-        "relax_loop_per_s": vr["relax_loop"], "relax_loop_frac": vr["relax_loop"] / RELAX_PEAK}
+        "relax_loop_per_s": vr["relax_loop"], "relax_loop_frac": vr["relax_loop"] / RELAX_PEAK,
+        "relax_regs_per_s": vr["relax_regs"], "relax_regs_frac": vr["relax_regs"] / RELAX_PEAK}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, st, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -318,8 +318,11 @@ const char* spq_last_error(void);
  *   out[1]  v_min3_u32 lane-operations per second (independent chains)
  *   out[2]  relaxations per second of the kernels' inner loop on LDS
  *           operands (no global memory in the loop)
- * A relaxation is one add and half a min3, so out[0] and out[1] bound the
- * relaxation peak.  Errors: SPQ_EINVAL (out NULL), SPQ_ENOMEM, SPQ_EDEVICE.
+ *   out[3]  relaxations per second of the same relaxation instructions on
+ *           operands in registers (no LDS reads): the instruction sequence
+ *           alone
+ * out holds 4 doubles.  A relaxation is one add and half a min3, so out[0]
+ * and out[1] bound the relaxation peak.  Errors: SPQ_EINVAL (out NULL), SPQ_ENOMEM, SPQ_EDEVICE.
  */
 spq_status spq_valu_rates(double* out, void* stream);
 
@@ -327,6 +330,81 @@ spq_status spq_fw_components(int32_t count, const int32_t* size, const int64_t* 
                              const int32_t* ld, int32_t* data, void* stream);
 spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int32_t kc, int32_t* data,
                         void* stream);
+
+/*
+ * Test hook: the min-plus products of the two-level build's group-level
+ * composition, on caller-owned DEVICE buffers, by the kernels the build uses.
+ * The composition is Algorithm 2 applied one level up (Lemma 3 with groups of
+ * components in place of components): a shortest path from vertex x of group
+ * S1 to vertex y of group S2 leaves S1 through a boundary vertex a and enters
+ * S2 through a boundary vertex b, so
+ *   T(S1,S2)[x][y] = min over a < nk[S1], b < nk[S2] of
+ *                    R[S1][a][x] + D[koff[S1]+a][koff[S2]+b] + R[S2][b][y],
+ *   also min'd with M[S1][x][y] when S1 = S2,
+ * with every sum clamped at SPQ_INF (exact: outputs are min(exact, SPQ_INF)).
+ *   layout    SPQ_MP_BLOCKED: the first product into a scratch table, then
+ *             the product stored in the query layout (the two-level kernels);
+ *             SPQ_MP_DENSE: the same first product, then the product stored
+ *             densely (the level-3 kernels)
+ *   groups    G in [1, 4096]; nv[g] in [1, vp] vertices and nk[g] in [0, kp]
+ *             boundary rows per group (HOST arrays of G);
+ *             koff[g] = nk[0] + ... + nk[g-1], voff[g] likewise over nv
+ *   vp, kp    positive multiples of 128
+ *   R         G x kp x vp int32: R[g][a][x] at R[(g*kp + a)*vp + x]
+ *   D         rows and columns koff[G] at least, leading dimension ldd >=
+ *             koff[G] (may be NULL when koff[G] = 0)
+ *   M         G x vp x vp int32: M[g][x][y] at M[(g*vp + x)*vp + y]
+ *   pairs     HOST array of 2*npairs group ids (S1, S2), no pair twice
+ *   out       SPQ_MP_BLOCKED: pair p's nv[S1] x nv[S2] values start at element
+ *             obase[p] = sum over earlier pairs q of nv[S1_q]*nv[S2_q]; each
+ *             group is cut into consecutive runs ("components") of cb
+ *             vertices (the last may be shorter) and (x, y) sits at
+ *             r(x)*nv[S2] + n(x)*r(y) + l(x)*n(y) + l(y), where r(v) = v - v%cb
+ *             is the run's first vertex, n(v) its length and l(v) = v%cb
+ *             (ldo unused).
+ *             SPQ_MP_DENSE: (x, y) at out[(voff[S1]+x)*ldo + voff[S2]+y],
+ *             ldo >= voff[G] (cb unused).
+ * Every entry of R, D and M, padding included, must be in [0, SPQ_INF]
+ * (entries are not checked).  Reads R rows past nk[g] up to the next
+ * multiple of 16 and every column of R and M, never multiplying them into
+ * an output.  Synchronous on `stream`; scratch memory is the library's.
+ * Errors: SPQ_EINVAL, SPQ_ENOMEM, SPQ_EDEVICE.
+ */
+#define SPQ_MP_BLOCKED 0
+#define SPQ_MP_DENSE 1
+spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv, const int32_t* nk,
+                               int32_t vp, int32_t kp, const int32_t* R, const int32_t* D,
+                               int64_t ldd, const int32_t* M, int32_t npairs, const int32_t* pairs,
+                               int32_t cb, int32_t* out, int64_t ldo, void* stream);
+
+/*
+ * Test hook: the intra-group product of the share build's Bellman-Ford
+ * rounds (BG rows of one GPU's share, Algorithm 1 Phase 3, computed over the
+ * groups of the two-level method), in place on a caller-owned DEVICE table C.
+ * Group g owns rows koff[g] .. koff[g]+nk[g]-1 of C (koff as above); for
+ * each of them and every column j < ldc:
+ *   C[koff[g]+r][j] = min(C[koff[g]+r][j],
+ *                         min over listed k of A[g][r][k] + C[koff[g]+k][j]).
+ *   nk        HOST array of G (in [1, 65535]) row counts in [0, kp]
+ *   kp        positive multiple of 128
+ *   A         G x kp x kp int32, A[g][r][k] at A[(g*kp + r)*kp + k]; must be
+ *             symmetric on [0, nk[g])^2 (the kernel reads column r as row r)
+ *   C         at least koff[G] + 128 rows of ldc (a positive multiple of 128)
+ *             int32; rows past koff[G] are read, never written
+ *   cnt       HOST array of G: cnt[g] < 0 lists every row 0 .. nk[g]-1, else
+ *             the next cnt[g] entries of `rows` (HOST, local indices) are
+ *             the listed rows of group g
+ * Rows are updated in place while other workgroups read them as K, so the
+ * result is the formula above for any schedule only when every value read
+ * is no smaller than it: A[g] closed (its own all-pairs distances, 0 on the
+ * diagonal) and every row that is not listed already satisfying
+ * A[g][r][k] + C[k][j] >= C[r][j] (the state between two rounds).
+ * Entries in [0, SPQ_INF].  Synchronous on `stream`.
+ * Errors: SPQ_EINVAL, SPQ_ENOMEM, SPQ_EDEVICE.
+ */
+spq_status spq_minplus_rows(int32_t groups, const int32_t* nk, int32_t kp, const int32_t* A,
+                            int32_t* C, int64_t ldc, const int32_t* cnt, const int32_t* rows,
+                            void* stream);
 
 #ifdef __cplusplus
 }

@@ -51,24 +51,39 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
+LIB_NATIVE = os.path.join(HERE, "liboracle_native.so")
+
 _lib = None
+_native = False
 
 
-def build(force: bool = False) -> str:
-    """Compile oracle.c into oracle/liboracle.so with gcc."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-pthread",
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile oracle.c with gcc: oracle/liboracle.so (-O2, portable), or with
+    native=True oracle/liboracle_native.so (-O3 -march=native, for timing the
+    oracle on the host that runs it; built there, never shipped)."""
+    out = LIB_NATIVE if native else LIB
+    flags = ["-O3", "-march=native"] if native else ["-O2"]
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *flags, "-std=c11", "-shared", "-fPIC", "-pthread",
                                SRC, "-o", tmp])
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, out)
+    return out
+
+
+def configure(native: bool):
+    """Select the build the functions below call (before their first use):
+    the portable one (tests) or the -O3 -march=native one (CPU timing)."""
+    global _lib, _native
+    if _lib is not None and native != _native:
+        raise RuntimeError("oracle library already loaded")
+    _native = native
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(LIB)
+        L = ctypes.CDLL(build(force=_native, native=_native))
         i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
         i64p = np.ctypeslib.ndpointer(np.int64, flags="C")
         L.oracle_dijkstra.restype = ctypes.c_int

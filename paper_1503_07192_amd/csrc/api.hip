@@ -494,6 +494,24 @@ static spq_status certify(spq_index* X, hipStream_t s) {
   return SPQ_OK;
 }
 
+// Pool blocks of a hook, released when it returns, after its stream has
+// drained (also on an early error return, when copies may still be queued).
+struct Scratch {
+  hipStream_t s;
+  std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t st) : s(st) {}
+  template <typename T>
+  hipError_t get(T** p, int64_t count) {
+    hipError_t e = dalloc(p, count);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+  ~Scratch() {
+    if (!ptrs.empty()) (void)hipStreamSynchronize(s);
+    for (void* p : ptrs) pool_release(p);
+  }
+};
+
 extern "C" {
 
 const char* spq_last_error(void) { return g_err.c_str(); }
@@ -1376,6 +1394,165 @@ spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int3
   return SPQ_OK;
 }
 
+// Group-level composition products on caller buffers (see spq.h).
+spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv, const int32_t* nk,
+                               int32_t vp, int32_t kp, const int32_t* R, const int32_t* D,
+                               int64_t ldd, const int32_t* M, int32_t npairs, const int32_t* pairs,
+                               int32_t cb, int32_t* out, int64_t ldo, void* stream) {
+  if (layout != SPQ_MP_BLOCKED && layout != SPQ_MP_DENSE) return fail(SPQ_EINVAL, "bad layout");
+  if (groups < 1 || groups > 4096) return fail(SPQ_EINVAL, "groups must be in [1, 4096]");
+  if (vp < 128 || vp % 128 || kp < 128 || kp % 128)
+    return fail(SPQ_EINVAL, "vp and kp must be positive multiples of 128");
+  if (!nv || !nk || !R || !M || !out || npairs < 0 || (npairs > 0 && !pairs))
+    return fail(SPQ_EINVAL, "null argument or npairs < 0");
+  std::vector<int32_t> koff(groups + 1, 0), voff(groups + 1, 0);
+  for (int32_t g = 0; g < groups; g++) {
+    if (nv[g] < 1 || nv[g] > vp || nk[g] < 0 || nk[g] > kp)
+      return fail(SPQ_EINVAL, "group " + std::to_string(g) + ": nv outside [1, vp] or nk outside [0, kp]");
+    koff[g + 1] = koff[g] + nk[g];
+    voff[g + 1] = voff[g] + nv[g];
+  }
+  if (koff[groups] > 0 && (!D || ldd < koff[groups]))
+    return fail(SPQ_EINVAL, "D is NULL or ldd below the total boundary rows");
+  if (layout == SPQ_MP_BLOCKED && cb < 1) return fail(SPQ_EINVAL, "cb < 1");
+  if (layout == SPQ_MP_DENSE && ldo < voff[groups]) return fail(SPQ_EINVAL, "ldo below the total vertices");
+  std::vector<int2> plist(npairs);
+  std::vector<int64_t> pairbase((size_t)groups * groups, -1);
+  int64_t obase = 0;
+  for (int32_t p = 0; p < npairs; p++) {
+    const int32_t s1 = pairs[2 * p], s2 = pairs[2 * p + 1];
+    if (s1 < 0 || s1 >= groups || s2 < 0 || s2 >= groups)
+      return fail(SPQ_EINVAL, "pair " + std::to_string(p) + ": group outside [0, groups)");
+    if (pairbase[(size_t)s1 * groups + s2] >= 0)
+      return fail(SPQ_EINVAL, "pair " + std::to_string(p) + " repeats an earlier pair");
+    pairbase[(size_t)s1 * groups + s2] = obase;
+    obase += (int64_t)nv[s1] * nv[s2];
+    plist[p] = make_int2(s1, s2);
+  }
+  if (npairs == 0) return SPQ_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // pairs per launch: XT slots of kp x vp words within 256 MiB
+  const int64_t slot = (int64_t)kp * vp;
+  const int32_t chunk =
+      (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)npairs, 65535, ((int64_t)1 << 26) / slot}));
+  Scratch sc(s);
+  int2* d_plist = nullptr;
+  int32_t *d_nk = nullptr, *d_nv = nullptr, *d_koff = nullptr, *d_voff = nullptr;
+  u32* d_xt = nullptr;
+  HIP_TRY(sc.get(&d_plist, npairs));
+  HIP_TRY(sc.get(&d_nk, groups));
+  HIP_TRY(sc.get(&d_nv, groups));
+  HIP_TRY(sc.get(&d_koff, groups + 1));
+  HIP_TRY(sc.get(&d_voff, groups + 1));
+  HIP_TRY(sc.get(&d_xt, (int64_t)chunk * slot));
+  HIP_TRY(hipMemcpyAsync(d_plist, plist.data(), sizeof(int2) * npairs, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_nk, nk, sizeof(int32_t) * groups, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_nv, nv, sizeof(int32_t) * groups, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_koff, koff.data(), sizeof(int32_t) * (groups + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_voff, voff.data(), sizeof(int32_t) * (groups + 1), hipMemcpyHostToDevice, s));
+  // a D with no rows is never read; the kernels still take a valid pointer
+  const u32* dD = reinterpret_cast<const u32*>(koff[groups] > 0 ? D : R);
+  const int64_t ld = koff[groups] > 0 ? ldd : 1;
+  if (layout == SPQ_MP_DENSE) {
+    spq::L3Args a{};
+    a.V3gp = vp; a.m3pmax = kp; a.m3 = d_nk; a.tsize = d_nv; a.b3off = d_koff; a.tbase = d_voff;
+    a.BG3 = const_cast<u32*>(dD); a.V3p = ld;
+    a.R3 = const_cast<u32*>(reinterpret_cast<const u32*>(R));
+    a.M3 = const_cast<u32*>(reinterpret_cast<const u32*>(M));
+    a.XT3 = d_xt; a.BG2 = reinterpret_cast<u32*>(out); a.V2p = ldo;
+    a.plist = d_plist; a.npairs = npairs; a.chunk = chunk;
+    HIP_TRY(spq::launch_level3_compose(a, s));
+  } else {
+    // every group cut into consecutive components of cb vertices: per vertex
+    // its component's first index, size and its own index inside it
+    const int32_t V = voff[groups];
+    std::vector<int32_t> row(V), cnb(V), loc(V);
+    for (int32_t g = 0; g < groups; g++)
+      for (int32_t x = 0; x < nv[g]; x++) {
+        const int32_t r0 = x - x % cb;
+        row[voff[g] + x] = r0;
+        cnb[voff[g] + x] = std::min(cb, nv[g] - r0);
+        loc[voff[g] + x] = x % cb;
+      }
+    int32_t *d_row = nullptr, *d_cnb = nullptr, *d_loc = nullptr;
+    int64_t* d_pb = nullptr;
+    HIP_TRY(sc.get(&d_row, V));
+    HIP_TRY(sc.get(&d_cnb, V));
+    HIP_TRY(sc.get(&d_loc, V));
+    HIP_TRY(sc.get(&d_pb, (int64_t)groups * groups));
+    HIP_TRY(hipMemcpyAsync(d_row, row.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_cnb, cnb.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_loc, loc.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_pb, pairbase.data(), sizeof(int64_t) * groups * groups,
+                           hipMemcpyHostToDevice, s));
+    spq::HierArgs a{};
+    a.ngroups = groups; a.Vgp = vp; a.m2pmax = kp; a.m2 = d_nk; a.gV = d_nv; a.b2off = d_koff;
+    a.gbg0 = d_voff; a.BG2 = const_cast<u32*>(dD); a.V2p = ld;
+    a.R = const_cast<u32*>(reinterpret_cast<const u32*>(R));
+    a.Mg = const_cast<u32*>(reinterpret_cast<const u32*>(M));
+    a.XT = d_xt; a.H = reinterpret_cast<u32*>(out); a.pairbase = d_pb;
+    a.bgrow = d_row; a.bgnb = d_cnb; a.bglocal = d_loc;
+    a.plist = d_plist; a.npairs = npairs; a.chunk = chunk;
+    HIP_TRY(spq::launch_hier_level2_compose(a, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return SPQ_OK;
+}
+
+// The in-place product of the share's Bellman-Ford rounds on caller buffers
+// (see spq.h).
+spq_status spq_minplus_rows(int32_t groups, const int32_t* nk, int32_t kp, const int32_t* A,
+                            int32_t* C, int64_t ldc, const int32_t* cnt, const int32_t* rows,
+                            void* stream) {
+  if (groups < 1 || groups > 65535) return fail(SPQ_EINVAL, "groups must be in [1, 65535]");
+  if (kp < 128 || kp % 128) return fail(SPQ_EINVAL, "kp must be a positive multiple of 128");
+  if (ldc < 128 || ldc % 128) return fail(SPQ_EINVAL, "ldc must be a positive multiple of 128");
+  if (!nk || !A || !C || !cnt) return fail(SPQ_EINVAL, "null argument");
+  std::vector<int32_t> koff(groups + 1, 0);
+  int64_t listed = 0;
+  for (int32_t g = 0; g < groups; g++) {
+    if (nk[g] < 0 || nk[g] > kp) return fail(SPQ_EINVAL, "nk outside [0, kp]");
+    if (cnt[g] > nk[g]) return fail(SPQ_EINVAL, "more listed rows than rows in a group");
+    koff[g + 1] = koff[g] + nk[g];
+    if (cnt[g] > 0) listed += cnt[g];
+  }
+  if (listed > 0 && !rows) return fail(SPQ_EINVAL, "rows is NULL");
+  const int32_t ntc = (int32_t)(ldc / 128);
+  std::vector<u32> dirty((size_t)groups * (ntc + 1), 1u);
+  std::vector<int32_t> hc((size_t)groups * ntc);
+  std::vector<int32_t> hl((size_t)groups * ntc * kp, 0);
+  for (int32_t g = 0, at = 0; g < groups; g++) {
+    const int32_t c = cnt[g] < 0 ? spq::BF_ALL_ROWS : cnt[g];
+    for (int32_t t = 0; t < ntc; t++) {
+      hc[(size_t)g * ntc + t] = c;
+      for (int32_t i = 0; i < std::max(cnt[g], 0); i++) {
+        const int32_t r = rows[at + i];
+        if (r < 0 || r >= nk[g]) return fail(SPQ_EINVAL, "listed row outside its group");
+        hl[((size_t)g * ntc + t) * kp + i] = r;
+      }
+    }
+    at += std::max(cnt[g], 0);
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Scratch sc(s);
+  int32_t *d_nk = nullptr, *d_koff = nullptr, *d_cnt = nullptr, *d_list = nullptr;
+  u32* d_dirty = nullptr;
+  HIP_TRY(sc.get(&d_nk, groups));
+  HIP_TRY(sc.get(&d_koff, groups + 1));
+  HIP_TRY(sc.get(&d_cnt, (int64_t)groups * ntc));
+  HIP_TRY(sc.get(&d_list, (int64_t)groups * ntc * kp));
+  HIP_TRY(sc.get(&d_dirty, (int64_t)groups * (ntc + 1)));
+  HIP_TRY(hipMemcpyAsync(d_nk, nk, sizeof(int32_t) * groups, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_koff, koff.data(), sizeof(int32_t) * (groups + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_cnt, hc.data(), sizeof(int32_t) * hc.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_list, hl.data(), sizeof(int32_t) * hl.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_dirty, dirty.data(), sizeof(u32) * dirty.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(spq::launch_bf_intra(groups, kp, ldc, d_nk, d_koff, reinterpret_cast<const u32*>(A),
+                               reinterpret_cast<u32*>(C), d_dirty, d_cnt, d_list, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SPQ_OK;
+}
+
 // Measured VALU issue rates (see spq.h).
 spq_status spq_valu_rates(double* out, void* stream) {
   if (!out) return fail(SPQ_EINVAL, "out is NULL");
@@ -1389,8 +1566,8 @@ spq_status spq_valu_rates(double* out, void* stream) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  const int iters[3] = {4000, 4000, 1000};
-  for (int kind = 0; kind < 3 && e == hipSuccess; kind++) {
+  const int iters[4] = {4000, 4000, 1000, 1000};
+  for (int kind = 0; kind < 4 && e == hipSuccess; kind++) {
     e = spq::launch_valu_probe(kind, blocks, iters[kind] / 4, buf, s);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     if (e == hipSuccess) e = spq::launch_valu_probe(kind, blocks, iters[kind], buf, s);

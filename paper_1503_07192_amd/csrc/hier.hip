@@ -944,6 +944,10 @@ hipError_t launch_level3_b(const L3Args& a, hipStream_t s) {
                        : launch_dense_fw(a.BG3, a.V3p, 128, nt, s, nullptr, a.kc, a.pivot);
     if (e != hipSuccess) return e;
   }
+  return launch_level3_compose(a, s);
+}
+
+hipError_t launch_level3_compose(const L3Args& a, hipStream_t s) {
   const int ntx = a.V3gp / 128, ntm = a.m3pmax / 128;
   for (int32_t p0 = 0; p0 < a.npairs; p0 += a.chunk) {
     const unsigned np = (unsigned)min(a.chunk, a.npairs - p0);
@@ -990,6 +994,15 @@ hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const BfRound& r, 
     k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, a.DT, r.dirty, r.dirty_next,
                                              a.b2off, a.m2pmax, r.round, r.stamp, r.cnt_next,
                                              r.list_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf_intra(int32_t ngroups, int32_t m2pmax, int64_t S2p, const int32_t* m2,
+                           const int32_t* b2off, const u32* A, u32* DT, const u32* dirty,
+                           const int32_t* rcnt, const int32_t* rlist, hipStream_t s) {
+  const int ntm = m2pmax / 128, ntc = (int)(S2p / 128);
+  k_bf_intra<<<dim3((unsigned)(ntm * ntc), (unsigned)ngroups), 256, 0, s>>>(m2pmax, S2p, m2, b2off, A,
+                                                                            DT, dirty, rcnt, rlist);
   return hipGetLastError();
 }
 

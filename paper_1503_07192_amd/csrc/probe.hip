@@ -8,6 +8,8 @@
 //   iteration, so nothing waits on a result)
 //   kind 2: the production relaxation loop (minplus_lds of tiles.h) on LDS
 //   operands, no global memory inside the loop
+//   kind 3: the same relaxation pairs (relax2) on operands held in registers:
+//   no LDS reads either, so the loop is the instruction sequence alone
 #include "spq_internal.h"
 #include "tiles.h"
 
@@ -63,15 +65,47 @@ void k_rate_relax(u32* __restrict__ out, int iters, u32 seed) {
   out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
 }
 
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_rate_relax_regs(u32* __restrict__ out, int iters, u32 seed) {
+  u32 a0[8], b0[8], a1[8], b1[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    a0[i] = ((threadIdx.x + i) * 2654435761u + seed) >> 4;
+    b0[i] = ((threadIdx.x + 3 * i) * 40503u + seed) >> 4;
+    a1[i] = ((threadIdx.x + 5 * i) * 2246822519u + seed) >> 4;
+    b1[i] = ((threadIdx.x + 7 * i) * 3266489917u + seed) >> 4;
+  }
+  u32 c[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+#pragma unroll
+    for (int j = 0; j < 8; j++) c[i][j] = INF - (u32)(i + j) - threadIdx.x;
+  // eight pairs of k per iteration: the relaxations of one 16-row chunk
+  for (int it = 0; it < iters; it++)
+    for (int kk = 0; kk < 8; kk++)
+#pragma unroll
+      for (int i = 0; i < 8; i++)
+#pragma unroll
+        for (int j = 0; j < 8; j++) relax2(c[i][j], a0[i], b0[j], a1[i], b1[j]);
+  u32 s = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+#pragma unroll
+    for (int j = 0; j < 8; j++) s ^= c[i][j];
+  out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
 // out: blocks * 256 words.  Work per launch: kinds 0/1: blocks * 256 lanes *
-// iters * 32 instructions; kind 2: blocks * 256 * 64 * 16 * iters relaxations.
+// iters * 32 instructions; kinds 2/3: blocks * 256 * 64 * 16 * iters relaxations.
 hipError_t launch_valu_probe(int kind, int blocks, int iters, u32* out, hipStream_t s) {
   if (kind == 0)
     k_rate<0><<<blocks, 256, 0, s>>>(out, iters, 2u);
   else if (kind == 1)
     k_rate<1><<<blocks, 256, 0, s>>>(out, iters, 2u);
-  else
+  else if (kind == 2)
     k_rate_relax<<<blocks, 256, 0, s>>>(out, iters, 2u);
+  else
+    k_rate_relax_regs<<<blocks, 256, 0, s>>>(out, iters, 2u);
   return hipGetLastError();
 }
 

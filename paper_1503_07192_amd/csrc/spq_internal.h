@@ -163,6 +163,13 @@ struct L3Args {
 hipError_t launch_level3_a(const L3Args& a, hipStream_t s);
 // BG3 and its closure, then d_BG2 for super-group pairs T1 <= T2 into BG2
 hipError_t launch_level3_b(const L3Args& a, hipStream_t s);
+// the two products of the level-3 composition alone (pairs, XT3, R3, M3, BG3 ->
+// BG2), a.chunk pairs per launch
+hipError_t launch_level3_compose(const L3Args& a, hipStream_t s);
+// the intra-group product of one Bellman-Ford round of the share, on its own
+hipError_t launch_bf_intra(int32_t ngroups, int32_t m2pmax, int64_t S2p, const int32_t* m2,
+                           const int32_t* b2off, const u32* A, u32* DT, const u32* dirty,
+                           const int32_t* rcnt, const int32_t* rlist, hipStream_t s);
 hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s);
 
 // Exactness certificate (range.hip).

@@ -24,6 +24,8 @@ SPQ_BAD_PAIR = -1
 SPQ_NO_LOOKAHEAD = 1
 SPQ_GRAPH = 2
 SPQ_PATHS = 4
+SPQ_MP_BLOCKED = 0
+SPQ_MP_DENSE = 1
 STATUS = {0: "SPQ_OK", 1: "SPQ_EINVAL", 2: "SPQ_ENOMEM", 3: "SPQ_EDEVICE", 4: "SPQ_ERANGE"}
 
 
@@ -82,6 +84,8 @@ _SIGS = {
     "spq_fw_components": (I32, [I32, P, P, P, P, P]),
     "spq_fw_dense": (I32, [I32, I32, I32, I32, I32, P, P]),
     "spq_valu_rates": (I32, [P, P]),
+    "spq_minplus_batched": (I32, [I32, I32, P, P, I32, I32, P, P, I64, P, I32, P, I32, P, I64, P]),
+    "spq_minplus_rows": (I32, [I32, P, I32, P, P, I64, P, P, P]),
 }
 
 
@@ -298,7 +302,42 @@ def fw_dense(v, ld, tile, data, stream=None, kc=0, pivot=0):
 
 def valu_rates(stream=None):
     """Measured issue rates on the current device, see spq_valu_rates:
-    {"v_add_u32": lane-ops/s, "v_min3_u32": lane-ops/s, "relax_loop": relax/s}."""
-    out = (ctypes.c_double * 3)()
+    {"v_add_u32": lane-ops/s, "v_min3_u32": lane-ops/s, "relax_loop": relax/s (LDS
+    operands), "relax_regs": relax/s (register operands)}."""
+    out = (ctypes.c_double * 4)()
     _check(load().spq_valu_rates(out, _stream(stream)))
-    return {"v_add_u32": out[0], "v_min3_u32": out[1], "relax_loop": out[2]}
+    return {"v_add_u32": out[0], "v_min3_u32": out[1], "relax_loop": out[2],
+            "relax_regs": out[3]}
+
+
+def minplus_batched(layout, nv, nk, vp, kp, R, D, ldd, M, pairs, out, cb=1, ldo=0, stream=None):
+    """Group-level composition products on device tensors (see
+    spq_minplus_batched): nv, nk per group and pairs [(S1, S2), ...] on the
+    host; R, D, M, out int32 device tensors.  Synchronous."""
+    import torch
+    nv = np.ascontiguousarray(nv, np.int32)
+    nk = np.ascontiguousarray(nk, np.int32)
+    pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+    if nv.shape != nk.shape or nv.ndim != 1:
+        raise ValueError("nv and nk must be 1-d and equally long")
+    dptr = _dev_i32(D, "D") if D is not None else ctypes.c_void_p(0)
+    _check(load().spq_minplus_batched(int(layout), len(nv), nv.ctypes.data, nk.ctypes.data,
+                                      int(vp), int(kp), _dev_i32(R, "R"), dptr, int(ldd),
+                                      _dev_i32(M, "M"), len(pairs), pairs.ctypes.data, int(cb),
+                                      _dev_i32(out, "out"), int(ldo), _stream(stream)))
+    return out
+
+
+def minplus_rows(nk, kp, A, C, ldc, cnt, rows=None, stream=None):
+    """The in-place intra-group product of the share's Bellman-Ford rounds on
+    device tensors (see spq_minplus_rows): nk, cnt and rows on the host.
+    Synchronous."""
+    nk = np.ascontiguousarray(nk, np.int32)
+    cnt = np.ascontiguousarray(cnt, np.int32)
+    rows = np.ascontiguousarray(rows if rows is not None else np.zeros(0), np.int32)
+    if nk.shape != cnt.shape or nk.ndim != 1:
+        raise ValueError("nk and cnt must be 1-d and equally long")
+    _check(load().spq_minplus_rows(len(nk), nk.ctypes.data, int(kp), _dev_i32(A, "A"),
+                                   _dev_i32(C, "C"), int(ldc), cnt.ctypes.data, rows.ctypes.data,
+                                   _stream(stream)))
+    return C

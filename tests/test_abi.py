@@ -57,6 +57,43 @@ def test_argument_errors_without_device():
     L.spq_free_index(None)
 
 
+def test_minplus_hooks_reject_bad_arguments_without_device():
+    import numpy as np
+    L = spq.load()
+    dummy = ctypes.c_void_p(8)
+    nv = np.array([100, 128], np.int32)
+    nk = np.array([5, 0], np.int32)
+    pairs = np.array([0, 1, 1, 1], np.int32)
+
+    def call(layout=0, groups=2, nv=nv, nk=nk, vp=128, kp=128, ldd=5, npairs=2, pairs=pairs,
+             cb=8, ldo=0):
+        return L.spq_minplus_batched(layout, groups, nv.ctypes.data, nk.ctypes.data, vp, kp, dummy,
+                                     dummy, ldd, dummy, npairs, pairs.ctypes.data, cb, dummy, ldo,
+                                     None)
+    assert call(layout=2) == 1 and "layout" in spq.last_error()
+    assert call(vp=100) == 1 and "multiples of 128" in spq.last_error()
+    assert call(nv=np.array([129, 1], np.int32)) == 1 and "group 0" in spq.last_error()
+    assert call(ldd=4) == 1 and "ldd" in spq.last_error()
+    assert call(cb=0) == 1 and "cb" in spq.last_error()
+    assert call(layout=1, ldo=227) == 1 and "ldo" in spq.last_error()
+    assert call(pairs=np.array([0, 1, 0, 1], np.int32)) == 1 and "repeats" in spq.last_error()
+    assert call(pairs=np.array([0, 2, 0, 1], np.int32)) == 1 and "outside" in spq.last_error()
+    assert call(npairs=0) == 0
+    cnt = np.array([-1, 0], np.int32)
+    assert L.spq_minplus_rows(2, nk.ctypes.data, 100, dummy, dummy, 128, cnt.ctypes.data, None,
+                              None) == 1
+    assert L.spq_minplus_rows(2, nk.ctypes.data, 128, dummy, dummy, 128,
+                              np.array([6, 0], np.int32).ctypes.data, None, None) == 1
+    assert "listed rows" in spq.last_error()
+    assert L.spq_minplus_rows(2, nk.ctypes.data, 128, dummy, dummy, 128,
+                              np.array([2, 0], np.int32).ctypes.data, None, None) == 1
+    assert "rows is NULL" in spq.last_error()
+    rows = np.array([1, 5], np.int32)
+    assert L.spq_minplus_rows(2, nk.ctypes.data, 128, dummy, dummy, 128,
+                              np.array([2, 0], np.int32).ctypes.data, rows.ctypes.data, None) == 1
+    assert "outside its group" in spq.last_error()
+
+
 def test_python_binding_rejects_host_tensors():
     torch = pytest.importorskip("torch")
     x = torch.zeros(4, dtype=torch.int32)

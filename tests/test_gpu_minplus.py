@@ -1,0 +1,234 @@
+"""The min-plus kernels of the two-level build, driven directly through the
+C-ABI test hooks on adversarial operands, against the oracle's plain (min, +)
+product (bit-exact).
+
+spq_minplus_batched runs the group-level composition (Algorithm 2 one level
+up, Lemma 3): the first product into the scratch table and the second into
+the query layout (blocked) or densely (level 3).  spq_minplus_rows runs the
+in-place intra-group product of the share's Bellman-Ford rounds.  Operands
+are INF-heavy, near INF, with boundary counts that are not multiples of 16,
+ragged 128-tiles, empty groups and padding that holds arbitrary values in
+[0, INF].
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import O_INF
+from paper_1503_07192_amd import spq
+
+pytestmark = pytest.mark.gpu
+INF = spq.SPQ_INF
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+
+
+def to64(a):
+    a = np.asarray(a, np.int64)
+    return np.where(a >= INF, O_INF, a)
+
+
+def to32(a):
+    return np.minimum(a, INF).astype(np.int32)
+
+
+def values(rng, shape, kind):
+    """int32 entries in [0, INF] of one of the adversarial kinds."""
+    if kind == "plain":
+        v = rng.integers(0, 1000, shape)
+    elif kind == "inf_heavy":
+        v = rng.integers(0, 1000, shape)
+        v[rng.random(shape) < 0.7] = INF
+    elif kind == "near_inf":
+        # finite values just below INF, INF itself, halves of INF and zeros
+        u = rng.random(shape)
+        v = np.where(u < 0.2, INF, INF - rng.integers(1, 4, shape))
+        v = np.where((u >= 0.5) & (u < 0.7), (INF >> 1) + rng.integers(0, 3, shape), v)
+        v = np.where(u >= 0.7, rng.integers(0, 3, shape), v)
+    else:
+        raise ValueError(kind)
+    return v.astype(np.int64)
+
+
+def compose_case(seed, G, vp, kp, kind, nv=None, nk=None):
+    rng = np.random.default_rng(seed)
+    nv = np.array(nv if nv is not None else rng.integers(1, vp + 1, G), np.int32)
+    nk = np.array(nk if nk is not None else rng.integers(0, kp + 1, G), np.int32)
+    koff = np.concatenate([[0], np.cumsum(nk)]).astype(np.int64)
+    K = int(koff[-1])
+    ldd = K + 3  # not a multiple of four: unaligned row starts
+    # padding holds arbitrary values in [0, INF]: never multiplied into an output
+    R = rng.integers(0, INF, (G, kp, vp), dtype=np.int64)
+    M = rng.integers(0, INF, (G, vp, vp), dtype=np.int64)
+    D = rng.integers(0, INF, (max(K, 1), ldd), dtype=np.int64)
+    for g in range(G):
+        R[g, :nk[g], :nv[g]] = values(rng, (nk[g], nv[g]), kind)
+        M[g, :nv[g], :nv[g]] = values(rng, (nv[g], nv[g]), kind)
+    D[:K, :K] = values(rng, (K, K), kind)
+    return nv, nk, koff, R, D, ldd, M
+
+
+def expected_pair(nv, nk, koff, R, D, M, s1, s2):
+    R1 = to64(R[s1, :nk[s1], :nv[s1]])
+    R2 = to64(R[s2, :nk[s2], :nv[s2]])
+    Db = to64(D[koff[s1]:koff[s1] + nk[s1], koff[s2]:koff[s2] + nk[s2]])
+    T = oracle.minplus(oracle.minplus(R1.T.copy(), Db), R2)
+    if s1 == s2:
+        T = np.minimum(T, to64(M[s1, :nv[s1], :nv[s1]]))
+    return to32(T)
+
+
+def blocked_positions(n1, n2, cb):
+    """Element offsets of (x, y) in the query layout: runs of cb vertices."""
+    def parts(n):
+        v = np.arange(n)
+        r = v - v % cb
+        return r, np.minimum(cb, n - r), v % cb
+    r1, c1, l1 = parts(n1)
+    r2, c2, l2 = parts(n2)
+    return (r1[:, None] * n2 + c1[:, None] * r2[None, :] + l1[:, None] * c2[None, :]
+            + l2[None, :])
+
+
+CASES = [
+    # seed, groups, vp, kp, kind, nv, nk, cb
+    (1, 3, 128, 128, "plain", None, None, 7),
+    (2, 4, 256, 128, "inf_heavy", [256, 129, 1, 200], [17, 0, 1, 127], 16),
+    (3, 3, 256, 256, "near_inf", [250, 256, 131], [250, 33, 255], 40),
+    (4, 5, 128, 128, "plain", [128, 128, 128, 128, 128], [128, 128, 16, 15, 1], 64),
+    (5, 2, 384, 128, "inf_heavy", [300, 384], [100, 90], 53),
+    (6, 3, 128, 128, "plain", [5, 6, 7], [0, 0, 0], 3),
+]
+
+
+@pytest.mark.parametrize("layout", [spq.SPQ_MP_BLOCKED, spq.SPQ_MP_DENSE])
+@pytest.mark.parametrize("seed,G,vp,kp,kind,nv,nk,cb", CASES)
+def test_composition_products_equal_oracle(layout, seed, G, vp, kp, kind, nv, nk, cb):
+    import torch
+    nv, nk, koff, R, D, ldd, M = compose_case(seed, G, vp, kp, kind, nv, nk)
+    rng = np.random.default_rng(seed + 100)
+    allp = [(a, b) for a in range(G) for b in range(G)]
+    pairs = [allp[i] for i in rng.permutation(len(allp))[:max(1, len(allp) - 2)]]
+    pairs += [(g, g) for g in range(G) if (g, g) not in pairs]
+    V = int(nv.sum())
+    voff = np.concatenate([[0], np.cumsum(nv)]).astype(np.int64)
+    print("case", seed, "layout", layout, "G", G, "pairs", len(pairs), flush=True)
+    if layout == spq.SPQ_MP_BLOCKED:
+        total = sum(int(nv[a]) * int(nv[b]) for a, b in pairs)
+        out = torch.full((total + 64,), -7, dtype=torch.int32, device="cuda")
+        spq.minplus_batched(layout, nv, nk, vp, kp, dev(R), dev(D), ldd, dev(M), pairs, out, cb=cb)
+        got = out.cpu().numpy()
+        assert (got[total:] == -7).all(), "written past the last pair"
+        base = 0
+        for a, b in pairs:
+            want = expected_pair(nv, nk, koff, R, D, M, a, b)
+            pos = blocked_positions(int(nv[a]), int(nv[b]), cb)
+            assert np.array_equal(got[base + pos], want), (a, b)
+            base += int(nv[a]) * int(nv[b])
+    else:
+        ldo = V + 5
+        out = torch.full((V * ldo,), -7, dtype=torch.int32, device="cuda")
+        spq.minplus_batched(layout, nv, nk, vp, kp, dev(R), dev(D), ldd, dev(M), pairs, out,
+                            ldo=ldo)
+        got = out.cpu().numpy().reshape(V, ldo)
+        written = np.zeros((V, ldo), bool)
+        for a, b in pairs:
+            want = expected_pair(nv, nk, koff, R, D, M, a, b)
+            blk = got[voff[a]:voff[a + 1], voff[b]:voff[b + 1]]
+            assert np.array_equal(blk, want), (a, b)
+            written[voff[a]:voff[a + 1], voff[b]:voff[b + 1]] = True
+        assert (got[~written] == -7).all(), "written outside the listed pairs"
+
+
+def test_composition_many_pairs_in_chunks():
+    """More pairs than one launch holds (256 MiB of scratch slots): kp x vp =
+    384 x 1024 words per slot gives 170 pairs per launch."""
+    import torch
+    G, vp, kp = 14, 1024, 384
+    rng = np.random.default_rng(9)
+    nv = rng.integers(1, 40, G).astype(np.int32)
+    nk = rng.integers(0, 30, G).astype(np.int32)
+    nv, nk, koff, R, D, ldd, M = compose_case(9, G, vp, kp, "inf_heavy", nv, nk)
+    pairs = [(a, b) for a in range(G) for b in range(G)]  # 196 pairs, two launches
+    total = sum(int(nv[a]) * int(nv[b]) for a, b in pairs)
+    out = torch.full((total,), -7, dtype=torch.int32, device="cuda")
+    spq.minplus_batched(spq.SPQ_MP_BLOCKED, nv, nk, vp, kp, dev(R), dev(D), ldd, dev(M), pairs, out,
+                        cb=5)
+    got = out.cpu().numpy()
+    base = 0
+    for a, b in pairs:
+        want = expected_pair(nv, nk, koff, R, D, M, a, b)
+        assert np.array_equal(got[base + blocked_positions(int(nv[a]), int(nv[b]), 5)], want)
+        base += int(nv[a]) * int(nv[b])
+
+
+def closed_group_matrix(rng, n, kp, kind):
+    """A[g]: all-pairs distances of a random graph on n vertices (closed,
+    symmetric, 0 diagonal), in a kp x kp array whose padding is arbitrary."""
+    A = rng.integers(0, INF, (kp, kp), dtype=np.int64)
+    if n:
+        m = int(rng.integers(0, 3 * n + 1))
+        eu = rng.integers(0, n, m).astype(np.int32)
+        ev = rng.integers(0, n, m).astype(np.int32)
+        hi = 1000 if kind != "near_inf" else (INF >> 2)
+        w = rng.integers(0, hi, m).astype(np.int32)
+        d = oracle.fw(oracle.dense_init(n, eu, ev, w))
+        A[:n, :n] = to32(d)
+    return A
+
+
+@pytest.mark.parametrize("seed,nk,kp,kind", [
+    (1, [50, 0, 129, 17], 256, "plain"),
+    (2, [128, 1, 33], 128, "inf_heavy"),
+    (3, [200, 255, 3], 256, "near_inf"),
+])
+@pytest.mark.parametrize("listed", [False, True])
+def test_bellman_ford_intra_product_equals_oracle(seed, nk, kp, kind, listed):
+    import torch
+    rng = np.random.default_rng(seed)
+    nk = np.array(nk, np.int32)
+    G = len(nk)
+    koff = np.concatenate([[0], np.cumsum(nk)]).astype(np.int64)
+    ldc = 256  # two column tiles
+    rows_total = int(koff[-1]) + 128
+    A = np.stack([closed_group_matrix(rng, int(nk[g]), kp, kind) for g in range(G)])
+    C = values(rng, (rows_total, ldc), kind)
+    cnt = np.full(G, -1, np.int32)
+    rows = []
+    if listed:
+        # the state between two rounds: every group's rows already closed
+        # under A[g]; then the cross edges lower a few listed rows
+        for g in range(G):
+            sl = slice(koff[g], koff[g + 1])
+            Ag = to64(A[g, :nk[g], :nk[g]])
+            C[sl] = to32(np.minimum(to64(C[sl]), oracle.minplus(Ag, to64(C[sl]))))
+            lst = rng.permutation(int(nk[g]))[:int(rng.integers(0, nk[g] + 1))] if nk[g] else []
+            lst = np.array(lst, np.int64)
+            for r in lst:
+                C[koff[g] + r] = np.minimum(C[koff[g] + r], values(rng, (ldc,), "plain"))
+            cnt[g] = len(lst)
+            rows.extend(lst.tolist())
+    want = C.copy()
+    for g in range(G):
+        if not nk[g]:
+            continue
+        sl = slice(koff[g], koff[g + 1])
+        Ag = to64(A[g, :nk[g], :nk[g]])
+        Cg = to64(C[sl])
+        if listed:
+            lst = np.array(rows[int(sum(max(c, 0) for c in cnt[:g])):][:cnt[g]], np.int64)
+            prod = oracle.minplus(Ag[:, lst].copy(), Cg[lst].copy()) if len(lst) else \
+                np.full(Cg.shape, O_INF, np.int64)
+            # the listed rows alone give the full product on this state
+            assert np.array_equal(np.minimum(Cg, prod), np.minimum(Cg, oracle.minplus(Ag, Cg)))
+        else:
+            prod = oracle.minplus(Ag, Cg)
+        want[sl] = to32(np.minimum(Cg, prod))
+    print("case", seed, "listed", listed, "nk", nk.tolist(), flush=True)
+    dC = dev(C)
+    spq.minplus_rows(nk, kp, dev(A), dC, ldc, cnt, np.array(rows, np.int32))
+    got = dC.cpu().numpy()
+    assert np.array_equal(got, want.astype(np.int32))
