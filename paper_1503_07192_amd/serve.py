@@ -1,13 +1,17 @@
 """Continuous-batching query server on a resident index.
 
 Requests (batches of query pairs) arrive over time.  The scheduler keeps a
-FIFO admission queue and a fixed set of slots; each slot is one HIP stream
-with its own pinned staging buffers and device buffers.  Whenever a slot is
-free, the requests at the head of the queue are coalesced into one launch of
-``spq_query_batch`` on that slot, as many as fit in the slot's pair capacity
-and in the device memory budget (memory-based admission).  Several slots are
-in flight at once, so requests that arrive while others run are admitted as
-soon as a slot and memory free up, and their work overlaps on the device.
+FIFO admission queue and a fixed set of slots; each slot is one HIP stream.
+Every launch's device buffers (pairs in, distances out) and their pinned
+staging are carved out of one device pool and one pinned pool of the memory
+budget's size by a first-fit allocator (``Arena``): a launch is admitted only
+when its buffers can be allocated there (memory-based admission), and they
+return to the pool when it completes.  Whenever a slot is free, the requests
+at the head of the queue are coalesced into one launch of ``spq_query_batch``
+on that slot, as many as fit in the slot's pair capacity and in the largest
+free region.  Several slots are in flight at once, so requests that arrive
+while others run are admitted as soon as a slot and memory free up, and
+their work overlaps on the device.
 Completion is detected by polling each slot's event; a request's latency is
 its completion time minus its arrival time.
 
@@ -61,17 +65,68 @@ def poisson_stream(rng, rate_pairs: float, nreq: int, n: int, max_log2: float = 
     return reqs
 
 
+class Arena:
+    """First-fit allocator of byte ranges in [0, size), in ALIGN-byte units:
+    the admission gate of the server (a launch runs only once its buffers
+    are allocated here) over the executor's device and pinned pools."""
+
+    ALIGN = 256
+
+    def __init__(self, size: int):
+        self.size = size - size % self.ALIGN
+        self.holes = [(0, self.size)] if self.size > 0 else []   # (offset, length), sorted
+        self.live = {}   # offset -> length
+        self.used = 0
+
+    def largest(self) -> int:
+        return max((h[1] for h in self.holes), default=0)
+
+    def alloc(self, nbytes: int):
+        """Offset of a free range of at least nbytes, or None."""
+        n = -(-max(nbytes, 1) // self.ALIGN) * self.ALIGN
+        for i, (off, ln) in enumerate(self.holes):
+            if ln >= n:
+                if ln == n:
+                    del self.holes[i]
+                else:
+                    self.holes[i] = (off + n, ln - n)
+                self.live[off] = n
+                self.used += n
+                return off
+        return None
+
+    def free(self, off: int):
+        n = self.live.pop(off)
+        self.used -= n
+        holes = self.holes
+        i = 0
+        while i < len(holes) and holes[i][0] < off:
+            i += 1
+        holes.insert(i, (off, n))
+        # merge with the following and the preceding hole
+        if i + 1 < len(holes) and holes[i][0] + holes[i][1] == holes[i + 1][0]:
+            holes[i] = (holes[i][0], holes[i][1] + holes[i + 1][1])
+            del holes[i + 1]
+        if i > 0 and holes[i - 1][0] + holes[i - 1][1] == holes[i][0]:
+            holes[i - 1] = (holes[i - 1][0], holes[i - 1][1] + holes[i][1])
+            del holes[i]
+
+
 class Scheduler:
-    """Admission, coalescing and completion on top of an executor."""
+    """Admission, coalescing and completion on top of an executor.  The
+    executor's ``arena`` (its memory pools; a fresh Arena of mem_budget bytes
+    if it has none) decides admission."""
 
     def __init__(self, executor, slots: int, slot_pairs: int, mem_budget: int):
-        if slots < 1 or slot_pairs < 1 or mem_budget < BYTES_PER_PAIR:
+        if slots < 1 or slot_pairs < 1 or mem_budget < Arena.ALIGN:
             raise ValueError("need at least one slot and memory for one pair")
         self.ex = executor
         self.nslots = slots
         self.slot_pairs = slot_pairs
+        self.arena = getattr(executor, "arena", None) or Arena(mem_budget)
+        if self.arena.size > mem_budget:
+            raise ValueError("the executor's pool is larger than the memory budget")
         self.mem_budget = mem_budget
-        self.mem_used = 0
         self.free = list(range(slots))
         self.inflight = {}  # slot -> (handle, [(req, lo, hi)], bytes)
         self.queue = collections.deque()
@@ -95,7 +150,7 @@ class Scheduler:
         memory budget) cannot hold it whole."""
         if not self.free or not self.queue:
             return False
-        room = min(self.slot_pairs, (self.mem_budget - self.mem_used) // BYTES_PER_PAIR)
+        room = min(self.slot_pairs, self.arena.largest() // BYTES_PER_PAIR)
         if room <= 0:
             return False
         parts, take = [], 0
@@ -115,10 +170,9 @@ class Scheduler:
         slot = self.free.pop()
         v1 = np.concatenate([r.v1[l:h] for r, l, h in parts])
         v2 = np.concatenate([r.v2[l:h] for r, l, h in parts])
-        handle = self.ex.submit(slot, v1, v2)
-        nbytes = take * BYTES_PER_PAIR
-        self.mem_used += nbytes
-        self.inflight[slot] = (handle, parts, nbytes)
+        off = self.arena.alloc(take * BYTES_PER_PAIR)   # fits: take <= largest hole / 12
+        handle = self.ex.submit(slot, v1, v2, off)
+        self.inflight[slot] = (handle, parts, off)
         self.launches += 1
         self.launch_sizes.append(take)
         for r, l, h in parts:
@@ -135,7 +189,7 @@ class Scheduler:
         """Collects finished slots; returns the requests completed."""
         finished = []
         for slot in list(self.inflight):
-            handle, parts, nbytes = self.inflight[slot]
+            handle, parts, off = self.inflight[slot]
             if not self.ex.done(handle):
                 continue
             out = self.ex.result(handle)
@@ -149,9 +203,13 @@ class Scheduler:
                     r.done_at = t
                     finished.append(r)
             del self.inflight[slot]
-            self.mem_used -= nbytes
+            self.arena.free(off)
             self.free.append(slot)
         return finished
+
+    @property
+    def mem_used(self):
+        return self.arena.used
 
     def busy(self):
         return bool(self.inflight) or bool(self.queue)
@@ -205,45 +263,44 @@ def summarize(reqs, sched=None):
 
 # ------------------------------------------------------------- executors
 class GpuExecutor:
-    """One HIP stream per slot, pinned host staging, device in/out buffers."""
+    """One HIP stream per slot; the buffers of every launch come from one
+    device pool and one pinned host pool of mem_bytes each, allocated once,
+    through the executor's Arena: a launch at offset off keeps its pairs and
+    results at [off, off + 12 q) of both pools until it completes."""
 
-    def __init__(self, index, slots: int, slot_pairs: int):
+    def __init__(self, index, slots: int, mem_bytes: int):
         import torch
         from . import spq
         self.torch, self.spq, self.index = torch, spq, index
-        self.cap = slot_pairs
+        self.arena = Arena(mem_bytes)
+        words = self.arena.size // 4
         self.streams = [torch.cuda.Stream() for _ in range(slots)]  # default priority
-        self.h_in = [torch.empty(2 * slot_pairs, dtype=torch.int32, pin_memory=True)
-                     for _ in range(slots)]
-        self.h_out = [torch.empty(slot_pairs, dtype=torch.int32, pin_memory=True)
-                      for _ in range(slots)]
-        self.d_in = [torch.empty(2 * slot_pairs, dtype=torch.int32, device="cuda")
-                     for _ in range(slots)]
-        self.d_out = [torch.empty(slot_pairs, dtype=torch.int32, device="cuda")
-                      for _ in range(slots)]
+        self.d_pool = torch.empty(words, dtype=torch.int32, device="cuda")
+        self.h_pool = torch.empty(words, dtype=torch.int32, pin_memory=True)
         self.events = [torch.cuda.Event() for _ in range(slots)]
 
-    def submit(self, slot, v1, v2):
-        torch, q, cap = self.torch, len(v1), self.cap
-        hin = self.h_in[slot].numpy()
-        hin[:q] = v1
-        hin[cap:cap + q] = v2
+    def submit(self, slot, v1, v2, off):
+        torch, q = self.torch, len(v1)
+        b = off // 4
+        hin = self.h_pool[b:b + 2 * q]
+        hin.numpy()[:q] = v1
+        hin.numpy()[q:] = v2
+        din = self.d_pool[b:b + 2 * q]
+        dout = self.d_pool[b + 2 * q:b + 3 * q]
         s = self.streams[slot]
         with torch.cuda.stream(s):
-            din, dout = self.d_in[slot], self.d_out[slot]
-            din[:q].copy_(self.h_in[slot][:q], non_blocking=True)
-            din[cap:cap + q].copy_(self.h_in[slot][cap:cap + q], non_blocking=True)
-            self.spq.query_batch(self.index, din[:q], din[cap:cap + q], dout[:q], stream=s)
-            self.h_out[slot][:q].copy_(dout[:q], non_blocking=True)
+            din.copy_(hin, non_blocking=True)
+            self.spq.query_batch(self.index, din[:q], din[q:], dout, stream=s)
+            self.h_pool[b + 2 * q:b + 3 * q].copy_(dout, non_blocking=True)
             self.events[slot].record(s)
-        return (slot, q)
+        return (slot, b, q)
 
     def done(self, handle):
         return self.events[handle[0]].query()
 
     def result(self, handle):
-        slot, q = handle
-        return self.h_out[slot][:q].numpy().copy()
+        _, b, q = handle
+        return self.h_pool[b + 2 * q:b + 3 * q].numpy().copy()
 
 
 class OneAtATime:
@@ -309,11 +366,12 @@ def main(argv=None):
     report = {"workload": args.workload, "n": g["n"], "k": g["k"], "v_bg": st["v_bg"],
               "slots": args.slots, "slot_pairs": args.slot_pairs, "mem_mib": args.mem_mib,
               "rates": {}}
-    ex = GpuExecutor(idx, args.slots, args.slot_pairs)
+    mem = int(args.mem_mib * 2**20)
+    ex = GpuExecutor(idx, args.slots, mem)
     for rate in [float(x) for x in args.rates.split(",")]:
         nreq = args.requests if rate >= 1e6 else args.low_rate_requests
         reqs = poisson_stream(rng, rate, nreq, g["n"])
-        sched = Scheduler(ex, args.slots, args.slot_pairs, int(args.mem_mib * 2**20))
+        sched = Scheduler(ex, args.slots, args.slot_pairs, mem)
         done = run_stream(sched, reqs)
         res = summarize(done, sched)
         # each request alone must give the same answers as inside the mix

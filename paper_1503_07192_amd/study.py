@@ -23,7 +23,9 @@ import time
 import numpy as np
 
 
-def run(blocks=(64, 32, 16, 8, 4), queries=100_000, log=print):
+def run(blocks=(64, 32, 16, 8, 4), queries=100_000, log=print, answers=False):
+    """One row per block side; with answers=True each row also holds the
+    query batch (v1, v2) and that index's answers (numpy)."""
     import torch
     from . import spq, workloads as W
     g = W.grid256d(queries=queries)
@@ -61,8 +63,10 @@ def run(blocks=(64, 32, 16, 8, 4), queries=100_000, log=print):
                "ms_bg": st["ms_bg_apsp"], "relax_executed": st["relax_comp_exec"] + st["relax_bg_exec"],
                "query_ms_first": ts[0], "query_ms_again": float(np.median(ts[1:])),
                "queries": len(g["v1"]), "answers_identical": bool(np.array_equal(ans, ref))}
-        rows.append(row)
         log(json.dumps(row))
+        if answers:
+            row["v1"], row["v2"], row["answers"] = g["v1"], g["v2"], ans
+        rows.append(row)
         idx.free()
     return rows
 

@@ -75,6 +75,23 @@ def check_components(g, idx, lay, comps=None):
         assert np.array_equal(got, want), "component %d" % c
 
 
+def check_components_all(g, idx, lay, chunk=2048):
+    """Every APSP(C) against the oracle's Floyd-Warshall on the induced
+    component, in chunks of components (large graphs)."""
+    order = np.lexsort((lay["local"], lay["comp"]))   # vertices by (component, local index)
+    off = lay["off"]
+    for c0 in range(0, g["k"], chunk):
+        comps = np.arange(c0, min(g["k"], c0 + chunk))
+        members, apsp = oracle.component_apsp(g["n"], g["eu"], g["ev"], g["w"], g["part"], g["k"],
+                                              comps=comps)
+        for c, mem, A in zip(comps, members, apsp):
+            vs = order[off[c]:off[c + 1]]
+            p = np.searchsorted(mem, vs)
+            got = spq.index_component(idx, int(c), len(vs))
+            assert np.array_equal(got, clamp32(A[np.ix_(p, p)])), "component %d" % c
+        print("components %d..%d match" % (comps[0], comps[-1]), flush=True)
+
+
 def bg_vertices(lay):
     out = []
     for c in range(len(lay["nb"])):
@@ -326,6 +343,24 @@ def test_grid256d_full_size():
     assert np.array_equal(rev, out)
     same = run_queries(idx, g["v1"], g["v1"])
     assert (same == 0).all()
+
+
+def test_grid256d_every_bg_row_equals_dijkstra():
+    """All 27,900 BG rows of the benchmark workload's flat closure against
+    Dijkstra on G from each BG vertex (Lemma 1), in chunks of sources."""
+    g = W.grid256d(queries=0)
+    idx = build(g)
+    lay = spq.index_layout(idx)
+    verts = bg_vertices(lay)
+    V = len(verts)
+    assert V == 27_900
+    for r0 in range(0, V, 2048):
+        r1 = min(V, r0 + 2048)
+        D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], verts[r0:r1])
+        got = spq.index_bg_rows(idx, r0, r1 - r0, V)
+        bad = np.flatnonzero((got != clamp32(D[:, verts])).any(axis=1))
+        assert len(bad) == 0, "BG row %d" % (r0 + bad[0])
+        print("BG rows %d..%d match" % (r0, r1 - 1), flush=True)
 
 
 def test_query_invalid_ids_and_empty_batch():
@@ -581,9 +616,7 @@ def test_delaunay1m_two_level():
     assert st["v_bg"] == int(flag.sum())
     check_layout_fast(g, lay, flag)
     rng = np.random.default_rng(31)
-    comps = np.concatenate([[0, g["k"] - 1], rng.choice(g["k"], 40, replace=False)])
-    comps = np.concatenate([comps, [int(np.argmax(np.bincount(g["part"])))]])
-    check_components(g, idx, lay, np.unique(comps))
+    check_components_all(g, idx, lay)
     check_bg_rows(g, idx, lay, np.concatenate([[0, st["v_bg"] - 1], rng.integers(0, st["v_bg"], 30)]))
     # source-grouped query sample: 100 sources x 20 targets, plus same-vertex pairs
     src = rng.integers(0, g["n"], 100).astype(np.int32)
@@ -718,8 +751,7 @@ def test_grid2048_share_full_size():
     lay = spq.index_layout(idx)
     flag = oracle.boundary(g["n"], g["eu"], g["ev"], g["part"])
     check_layout_fast(g, lay, flag)
-    comps = np.concatenate([[0, 511, 512, g["k"] - 1], rng.choice(g["k"], 30, replace=False)])
-    check_components(g, idx, lay, np.unique(comps))
+    check_components_all(g, idx, lay)
     bgend = int(lay["bgoff"][512])
     check_bg_rows(g, idx, lay, np.concatenate([[0, bgend - 1], rng.integers(0, bgend, 20)]))
     out = run_queries(idx, g["v1"], g["v2"])

@@ -25,8 +25,8 @@ def test_served_mix_equals_alone(method):
     torch.cuda.synchronize()
     rng = np.random.default_rng(12)
     reqs = serve.poisson_stream(rng, 2e7, 150, g["n"], max_log2=12.0)
-    ex = serve.GpuExecutor(idx, 4, 2048)
-    sched = serve.Scheduler(ex, 4, 2048, 12 * 3000)   # small budget: requests get cut
+    ex = serve.GpuExecutor(idx, 4, 12 * 3000)
+    sched = serve.Scheduler(ex, 4, 2048, 12 * 3000)   # small pool: requests get cut
     done = serve.run_stream(sched, reqs)
     assert len(done) == len(reqs)
     assert sched.launches < sum(r.size for r in reqs)
@@ -45,3 +45,42 @@ def test_served_mix_equals_alone(method):
     for r in one:
         alone = spq.query_batch(idx, dev(r.v1), dev(r.v2)).cpu().numpy()
         assert np.array_equal(alone, r.result)
+
+
+def test_config5_serving_on_the_delaunay_index():
+    """Serving on the Delaunay index (1M points, 4,096 parts) built with the
+    autotuner's options, as the serving measurement runs it: a Poisson stream
+    at 1e7 pairs/s offered with batch sizes floor(2^U(0,14)), four slots over
+    a 16 MiB pool.  Every request is identical alone and in the mix, and the
+    first four pairs of every request match Dijkstra on G."""
+    import os
+    g = W.delaunay1m()
+    cache = os.path.join(os.path.dirname(os.path.abspath(spq.__file__)), "tune_cache.json")
+    print("serve test: build delaunay1m (tuned)", flush=True)
+    idx = spq.build_index(g["n"], dev(g["eu"]), dev(g["ev"]), dev(g["w"]), dev(g["part"]), g["k"],
+                          tune_cache=cache)
+    torch.cuda.synchronize()
+    st = spq.index_stats(idx)
+    assert st["bg_method"] == 2 and st["v_bg"] > 250_000
+    rng = np.random.default_rng(W.SEED_BASE + 5)
+    reqs = serve.poisson_stream(rng, 1e7, 200, g["n"], max_log2=14.0)
+    mem = 16 << 20
+    ex = serve.GpuExecutor(idx, 4, mem)
+    sched = serve.Scheduler(ex, 4, 65536, mem)
+    done = serve.run_stream(sched, reqs)
+    assert len(done) == len(reqs)
+    assert sched.launches < len(reqs)   # requests were coalesced
+    print(serve.summarize(done, sched), flush=True)
+    for r in reqs:
+        alone = spq.query_batch(idx, dev(r.v1), dev(r.v2)).cpu().numpy()
+        assert np.array_equal(alone, r.result), r.rid
+    # the first four pairs of every request against Dijkstra, 100 sources at a time
+    v1 = np.concatenate([r.v1[:4] for r in reqs])
+    v2 = np.concatenate([r.v2[:4] for r in reqs])
+    got = np.concatenate([r.result[:4] for r in reqs])
+    for a in range(0, len(v1), 100):
+        D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], v1[a:a + 100])
+        want = np.minimum(D[np.arange(len(D)), v2[a:a + 100]], 2**31 - 1)
+        assert np.array_equal(got[a:a + 100], want), a
+    print("config 5: %d requests, %d pairs checked against Dijkstra" % (len(reqs), len(v1)),
+          flush=True)

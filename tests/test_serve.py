@@ -24,19 +24,26 @@ class FakeExecutor:
         self.max_active = 0
         self.sched = None
         self.max_mem = 0
+        self.regions = {}   # slot -> (offset, bytes) of its launch's buffers
 
-    def submit(self, slot, v1, v2):
+    def submit(self, slot, v1, v2, off):
         assert slot not in self.active
+        # the launch's buffers lie inside the pool and overlap no running launch
+        lo, hi = off, off + 12 * len(v1)
+        assert 0 <= lo and hi <= self.sched.arena.size
+        for a, b in self.regions.values():
+            assert hi <= a or b <= lo
+        self.regions[slot] = (lo, hi)
         self.active.add(slot)
         self.max_active = max(self.max_active, len(self.active))
-        if self.sched is not None:
-            self.max_mem = max(self.max_mem, self.sched.mem_used + 12 * len(v1))
+        self.max_mem = max(self.max_mem, sum(b - a for a, b in self.regions.values()))
         ready = self.clock.t + self.fixed + self.per_pair * len(v1)
         return [slot, ready, (7 * v1.astype(np.int64) + v2).astype(np.int32)]
 
     def done(self, h):
         if self.clock.t >= h[1]:
             self.active.discard(h[0])
+            self.regions.pop(h[0], None)
             return True
         return False
 
@@ -109,6 +116,35 @@ def test_request_larger_than_a_slot_is_served_in_pieces():
     assert np.array_equal(r.result, 7 * r.v1 + r.v2)
     with pytest.raises(ValueError):
         serve.Scheduler(ex, 1, 16, 4)
+
+
+def test_arena_first_fit_free_and_merge():
+    a = serve.Arena(10 * 256 + 100)
+    assert a.size == 2560 and a.largest() == 2560
+    x = a.alloc(1)          # one 256-byte unit
+    y = a.alloc(600)        # three units
+    z = a.alloc(256)
+    assert (x, y, z) == (0, 256, 1024) and a.used == 5 * 256
+    assert a.alloc(6 * 256) is None and a.largest() == 5 * 256
+    a.free(y)
+    assert a.largest() == 5 * 256 and a.alloc(3 * 256) == 256   # first fit reuses the hole
+    a.free(256)
+    a.free(x)
+    a.free(z)
+    assert a.used == 0 and a.holes == [(0, 2560)]
+    assert a.alloc(2560) == 0 and a.alloc(1) is None
+
+
+def test_admission_waits_for_pool_memory():
+    """A launch is admitted only when its buffers fit in the pool: with room
+    for one 1,000-pair launch, four requests run one after another."""
+    rng = np.random.default_rng(5)
+    reqs = [serve.Request(i, 0.0, rng.integers(0, 50, 1000).astype(np.int32),
+                          rng.integers(0, 50, 1000).astype(np.int32)) for i in range(4)]
+    sched, ex, done = run(reqs, slots=4, slot_pairs=1000, mem=12 * 1000 + 255)
+    assert ex.max_active == 1 and ex.max_mem <= 12 * 1000
+    for r in reqs:
+        assert np.array_equal(r.result, 7 * r.v1 + r.v2)
 
 
 def test_poisson_stream_shape():
