@@ -185,6 +185,20 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
                            const spq_build_opts* opts, void* stream, spq_index** out);
 
 /*
+ * Preprocessing (Algorithm 1) from HOST arrays, for callers without device
+ * memory of their own: the same arguments, options and results as
+ * spq_build_index, but eu, ev, w (m int32 each) and part (n int32) are host
+ * arrays, caller-owned and read during the call only.  They are copied into
+ * device memory of the library, the build runs on a stream of the library's
+ * own, and the call returns when the index is complete (the staging copies
+ * are freed by then).  Use the index on any stream afterwards.
+ * Errors: as spq_build_index (SPQ_ENOMEM also for the staging copies).
+ */
+spq_status spq_build_index_host(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
+                                const int32_t* w, const int32_t* part, int32_t k,
+                                const spq_build_opts* opts, spq_index** out);
+
+/*
  * Queries, Algorithm 2: out[i] = dist(v1[i], v2[i]) for i < q.
  *   v1, v2, out   DEVICE arrays of q int32, owned by the caller
  *   stream        hipStream_t (NULL = default stream); the call is asynchronous

@@ -1253,6 +1253,49 @@ spq_status spq_query_batch_host(const spq_index* X, int64_t q, const int32_t* v1
   return SPQ_OK;
 }
 
+// The build from host arrays: staged in pool memory, built on a cached
+// stream of the library, waited for (see spq.h).
+spq_status spq_build_index_host(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
+                                const int32_t* w, const int32_t* part, int32_t k,
+                                const spq_build_opts* opts, spq_index** out) {
+  g_err.clear();
+  if (!out) return fail(SPQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || m < 0 || k < 1) return fail(SPQ_EINVAL, "need n >= 1, m >= 0, k >= 1");
+  if (!part || (m > 0 && (!eu || !ev || !w))) return fail(SPQ_EINVAL, "null input array");
+  int32_t* d = nullptr;
+  HIP_TRY(dalloc(&d, 3 * m + n));
+  hipStream_t s = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = stream_take(&s);
+  const size_t eb = sizeof(int32_t) * (size_t)m;
+  if (e == hipSuccess && m > 0) e = hipMemcpyAsync(d, eu, eb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && m > 0) e = hipMemcpyAsync(d + m, ev, eb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && m > 0) e = hipMemcpyAsync(d + 2 * m, w, eb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d + 3 * m, part, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s);
+  spq_status st = SPQ_OK;
+  if (e == hipSuccess) st = spq_build_index(n, m, d, d + m, d + 2 * m, d + 3 * m, k, opts, s, out);
+  if (s) {
+    // the build reads the staged arrays until its queued work is done
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
+    if (es == hipSuccess)
+      stream_give(dev, s);
+    else
+      (void)hipStreamDestroy(s);
+  }
+  pool_release(d);
+  if (st != SPQ_OK) return st;
+  if (e != hipSuccess) {
+    spq_free_index(*out);
+    *out = nullptr;
+  }
+  HIP_TRY(e);
+  return SPQ_OK;
+}
+
 spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   if (!X || !st) return fail(SPQ_EINVAL, "null argument");
   std::memset(st, 0, sizeof(*st));

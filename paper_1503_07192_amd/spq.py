@@ -70,6 +70,8 @@ I32, I64 = ctypes.c_int32, ctypes.c_int64
 _SIGS = {
     "spq_build_index": (I32, [I32, I64, P, P, P, P, I32, ctypes.POINTER(BuildOpts), P,
                               ctypes.POINTER(P)]),
+    "spq_build_index_host": (I32, [I32, I64, P, P, P, P, I32, ctypes.POINTER(BuildOpts),
+                                   ctypes.POINTER(P)]),
     "spq_query_batch": (I32, [P, I64, P, P, P, P]),
     "spq_query_batch_host": (I32, [P, I64, P, P, P]),
     "spq_reweight_index": (I32, [P, P, P]),
@@ -168,21 +170,12 @@ class Index:
             pass
 
 
-def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg_method=0,
-                group_comps=0, share_comps=0, inner_kc=0, lookahead=True, graph=False,
-                level3_groups=0, group_bg=0, paths=False, bg_pivot=0, tune_cache=None,
-                stream=None) -> Index:
-    """Algorithm 1 on device tensors; see spq_build_index.
-
-    graph: capture Phases 2-3 as HIP graphs kept for reweight().
-    paths: keep the graph's adjacency for query_paths().
-    tune_cache: path of an autotuner cache (paper_1503_07192_amd.autotune);
-    options it holds for this device and problem size fill in the ones left
-    at 0 here."""
-    L = load()
+def _opts(n, m, k, bg_tile=0, profile=False, plain=False, bg_method=0, group_comps=0,
+          share_comps=0, inner_kc=0, lookahead=True, graph=False, level3_groups=0, group_bg=0,
+          paths=False, bg_pivot=0, tune_cache=None):
     if tune_cache:
         from . import autotune
-        tuned = autotune.lookup(tune_cache, n, int(eu.numel()), k, share_comps)
+        tuned = autotune.lookup(tune_cache, n, m, k, share_comps)
         bg_tile = bg_tile or tuned.get("bg_tile", 0)
         inner_kc = inner_kc or tuned.get("inner_kc", 0)
         bg_method = bg_method or tuned.get("bg_method", 0)
@@ -197,12 +190,43 @@ def build_index(n, eu, ev, w, part, k, bg_tile=0, profile=False, plain=False, bg
                      (SPQ_PATHS if paths else 0),
                      level3_groups=int(level3_groups), group_bg=int(group_bg),
                      bg_pivot=int(bg_pivot))
-    h = ctypes.c_void_p()
+    return opts
+
+
+def build_index(n, eu, ev, w, part, k, stream=None, **kw) -> Index:
+    """Algorithm 1 on device tensors; see spq_build_index.
+
+    Options (keywords, see spq_build_opts): bg_tile, profile, plain,
+    bg_method, group_comps, share_comps, inner_kc, lookahead, level3_groups,
+    group_bg, bg_pivot;
+    graph: capture Phases 2-3 as HIP graphs kept for reweight();
+    paths: keep the graph's adjacency for query_paths();
+    tune_cache: path of an autotuner cache (paper_1503_07192_amd.autotune);
+    options it holds for this device and problem size fill in the ones left
+    at 0 here."""
+    L = load()
     m = int(eu.numel())
+    opts = _opts(int(n), m, int(k), **kw)
+    h = ctypes.c_void_p()
     st = L.spq_build_index(int(n), m, _dev_i32(eu, "eu"), _dev_i32(ev, "ev"), _dev_i32(w, "w"),
                            _dev_i32(part, "part"), int(k), ctypes.byref(opts), _stream(stream),
                            ctypes.byref(h))
     _check(st)
+    return Index(h, int(n), int(k))
+
+
+def build_index_host(n, eu, ev, w, part, k, **kw) -> Index:
+    """Algorithm 1 on host (numpy) arrays, synchronous; see
+    spq_build_index_host.  Options as build_index."""
+    eu, ev, w, part = (np.ascontiguousarray(a, np.int32) for a in (eu, ev, w, part))
+    m = len(eu)
+    if len(ev) != m or len(w) != m or len(part) != int(n):
+        raise ValueError("eu, ev, w need m entries and part n")
+    opts = _opts(int(n), m, int(k), **kw)
+    h = ctypes.c_void_p()
+    _check(load().spq_build_index_host(int(n), m, eu.ctypes.data, ev.ctypes.data, w.ctypes.data,
+                                       part.ctypes.data, int(k), ctypes.byref(opts),
+                                       ctypes.byref(h)))
     return Index(h, int(n), int(k))
 
 

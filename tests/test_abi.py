@@ -33,6 +33,12 @@ def test_argument_errors_without_device():
                              None, ctypes.byref(h)) == 1
     assert "bg_pivot" in spq.last_error()
     assert L.spq_build_index(5, 0, None, None, None, None, 2, None, None, None) == 1
+    assert L.spq_build_index_host(0, 0, None, None, None, None, 1, None, ctypes.byref(h)) == 1
+    assert "n >= 1" in spq.last_error()
+    assert L.spq_build_index_host(5, 3, None, None, None, ctypes.c_void_p(8), 2, None,
+                                  ctypes.byref(h)) == 1
+    assert "null input" in spq.last_error()
+    assert L.spq_build_index_host(5, 0, None, None, None, None, 2, None, None) == 1
     assert L.spq_query_batch(None, 3, None, None, None, None) == 1
     assert L.spq_query_batch_host(None, 3, None, None, None) == 1
     assert L.spq_query_paths(None, 3, None, None, 8, None, None, None) == 1
