@@ -43,7 +43,9 @@ typedef enum {
   SPQ_EINVAL = 1,  /* bad argument: id, weight, partition, empty component */
   SPQ_ENOMEM = 2,  /* device allocation failed */
   SPQ_EDEVICE = 3, /* a HIP call failed */
-  SPQ_ERANGE = 4   /* distances might not fit below SPQ_INF */
+  SPQ_ERANGE = 4,  /* distances might not fit below SPQ_INF */
+  SPQ_EBUSY = 5    /* the call's fixed device scratch is in use by an
+                      overlapping call on the same device */
 } spq_status;
 
 typedef struct spq_index spq_index; /* opaque; owns all its device memory */
@@ -220,6 +222,28 @@ spq_status spq_query_batch(const spq_index* idx, int64_t q, const int32_t* v1,
  */
 spq_status spq_query_batch_host(const spq_index* idx, int64_t q, const int32_t* v1,
                                 const int32_t* v2, int32_t* out);
+
+/*
+ * spq_query_batch_host without any allocation, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * allocation after set-up): the pairs and answers are staged in a fixed
+ * device array of the library, 3 x SPQ_STATIC_PAIRS int32 (12 MiB) per
+ * device, set up on the first call on each device and held until the
+ * process ends.  The call allocates nothing (no hipMalloc, no stream).
+ *   v1, v2, out   HOST arrays of q int32, caller-owned, q <= SPQ_STATIC_PAIRS
+ *   stream        hipStream_t the copies and the query kernel are queued on
+ *                 (NULL = default stream)
+ * Returns when out is filled (synchronous on `stream`).  Every call on a
+ * device shares that device's array: overlapping calls would race, so a
+ * call made while another one holds the array returns SPQ_EBUSY (nothing
+ * done).  Nothing in the array needs clearing: each call writes the pairs
+ * and answers it reads.
+ * Errors: as spq_query_batch, plus SPQ_EINVAL (q > SPQ_STATIC_PAIRS),
+ * SPQ_EBUSY.
+ */
+#define SPQ_STATIC_PAIRS (1 << 20)
+spq_status spq_query_batch_host_static(const spq_index* idx, int64_t q, const int32_t* v1,
+                                       const int32_t* v2, int32_t* out, void* stream);
 
 /*
  * New edge weights for an index built with SPQ_GRAPH: same graph (eu, ev in

@@ -2,6 +2,7 @@
 // batched queries (Algorithm 2), inspection and test hooks.  Declarations and
 // their contracts are in include/spq.h.
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -153,6 +154,28 @@ hipError_t dalloc(T** p, int64_t count) {
 }
 
 int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
+
+}  // namespace
+
+// Fixed staging of spq_query_batch_host_static: v1, v2 and the answers of one
+// call, SPQ_STATIC_PAIRS int32 each, on every device the library runs on.
+// Host code never passes this symbol to a kernel or a copy: it takes the
+// device address hipGetSymbolAddress gives for the current device (once per
+// device, kept in g_static).
+static __device__ __align__(256) int32_t scratch[3 * SPQ_STATIC_PAIRS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct StaticScratch {
+  std::once_flag once;
+  hipError_t init = hipSuccess;
+  int32_t* ptr = nullptr;         // scratch on this device
+  std::atomic<bool> busy{false};  // a call holds the array
+};
+
+StaticScratch g_static[kMaxDevices];
 
 }  // namespace
 
@@ -1248,6 +1271,54 @@ spq_status spq_query_batch_host(const spq_index* X, int64_t q, const int32_t* v1
       (void)hipStreamDestroy(s);
   }
   pool_release(d);  // the stream has drained: nothing queued uses d any more
+  if (st != SPQ_OK) return st;
+  HIP_TRY(e);
+  return SPQ_OK;
+}
+
+// spq_query_batch_host through the fixed staging array (see spq.h): no
+// allocation, caller's stream, SPQ_EBUSY while another call holds the array.
+spq_status spq_query_batch_host_static(const spq_index* X, int64_t q, const int32_t* v1,
+                                       const int32_t* v2, int32_t* out, void* stream) {
+  if (!X) return fail(SPQ_EINVAL, "index is NULL");
+  if (!X->valid) return fail(SPQ_ERANGE, "index invalidated by a failed reweight");
+  if (q < 0) return fail(SPQ_EINVAL, "q < 0");
+  if (q > SPQ_STATIC_PAIRS)
+    return fail(SPQ_EINVAL, "q = " + std::to_string(q) + " exceeds SPQ_STATIC_PAIRS (" +
+                                std::to_string(SPQ_STATIC_PAIRS) + ")");
+  if (q == 0) return SPQ_OK;
+  if (!v1 || !v2 || !out) return fail(SPQ_EINVAL, "null query array");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SPQ_EINVAL, "device id beyond the library's table");
+  StaticScratch& S = g_static[dev];
+  std::call_once(S.once, [&S] {
+    void* p = nullptr;
+    S.init = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (S.init == hipSuccess) S.ptr = static_cast<int32_t*>(p);
+  });
+  if (S.init != hipSuccess || !S.ptr)
+    return fail(SPQ_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                 hipGetErrorString(S.init != hipSuccess ? S.init : hipErrorUnknown));
+  if (S.busy.exchange(true)) return fail(SPQ_EBUSY, "the static query staging is in use on this device");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int32_t* d1 = S.ptr;
+  int32_t* d2 = S.ptr + SPQ_STATIC_PAIRS;
+  int32_t* dout = S.ptr + 2 * (int64_t)SPQ_STATIC_PAIRS;
+  const size_t bytes = sizeof(int32_t) * (size_t)q;
+  // the index may still be building on another stream
+  hipError_t e = hipStreamWaitEvent(s, X->ev[4], 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(d1, v1, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d2, v2, bytes, hipMemcpyHostToDevice, s);
+  spq_status st = SPQ_OK;
+  if (e == hipSuccess) {
+    st = spq_query_batch(X, q, d1, d2, dout, s);
+    if (st == SPQ_OK) e = hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, s);
+  }
+  // the array is free again only once nothing queued uses it
+  const hipError_t es = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = es;
+  S.busy.store(false);
   if (st != SPQ_OK) return st;
   HIP_TRY(e);
   return SPQ_OK;

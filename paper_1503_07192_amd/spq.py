@@ -26,7 +26,9 @@ SPQ_GRAPH = 2
 SPQ_PATHS = 4
 SPQ_MP_BLOCKED = 0
 SPQ_MP_DENSE = 1
-STATUS = {0: "SPQ_OK", 1: "SPQ_EINVAL", 2: "SPQ_ENOMEM", 3: "SPQ_EDEVICE", 4: "SPQ_ERANGE"}
+SPQ_STATIC_PAIRS = 1 << 20
+STATUS = {0: "SPQ_OK", 1: "SPQ_EINVAL", 2: "SPQ_ENOMEM", 3: "SPQ_EDEVICE", 4: "SPQ_ERANGE",
+          5: "SPQ_EBUSY"}
 
 
 class SpqError(RuntimeError):
@@ -74,6 +76,7 @@ _SIGS = {
                                    ctypes.POINTER(P)]),
     "spq_query_batch": (I32, [P, I64, P, P, P, P]),
     "spq_query_batch_host": (I32, [P, I64, P, P, P]),
+    "spq_query_batch_host_static": (I32, [P, I64, P, P, P, P]),
     "spq_reweight_index": (I32, [P, P, P]),
     "spq_query_paths": (I32, [P, I64, P, P, I32, P, P, P]),
     "spq_index_stats": (I32, [P, ctypes.POINTER(Stats)]),
@@ -276,6 +279,20 @@ def query_batch_host(index: Index, v1, v2):
     out = np.empty_like(v1)
     _check(load().spq_query_batch_host(index.handle, len(v1), v1.ctypes.data, v2.ctypes.data,
                                        out.ctypes.data))
+    return out
+
+
+def query_batch_host_static(index: Index, v1, v2, stream=None):
+    """Algorithm 2 on host (numpy) pairs through the library's fixed device
+    staging (no allocation; at most SPQ_STATIC_PAIRS pairs); returns a numpy
+    int32 array.  See spq_query_batch_host_static."""
+    v1 = np.ascontiguousarray(v1, np.int32)
+    v2 = np.ascontiguousarray(v2, np.int32)
+    if v1.shape != v2.shape or v1.ndim != 1:
+        raise ValueError("v1 and v2 must be 1-d and equally long")
+    out = np.empty_like(v1)
+    _check(load().spq_query_batch_host_static(index.handle, len(v1), v1.ctypes.data,
+                                              v2.ctypes.data, out.ctypes.data, _stream(stream)))
     return out
 
 
