@@ -88,7 +88,11 @@ typedef struct {
                           super-groups of consecutive groups (level 3).
                           0 auto (about 4,096 BG2 vertices per super-group),
                           -1 never, g > 0 always, g groups per super-group.
-                          Share mode never builds BG2 and ignores it */
+                          Share mode never builds BG2: there it sets the
+                          blocks of its Bellman-Ford over BG2, g consecutive
+                          groups per block (closed together, so a round
+                          crosses a block instead of a group); 0 auto (about
+                          1,024 level-2 vertices per block), -1 one group */
   int32_t group_bg;      /* two-level: > 0 forms the groups by size instead of
                           by count: consecutive components join a group while
                           it holds at most group_bg BG vertices (a larger
@@ -136,7 +140,7 @@ typedef struct {
   int32_t v_bg2;           /* level-2 boundary vertices (two-level) */
   int32_t share_comps;     /* share mode: components [0, share_comps) (0 = all) */
   int32_t share_groups;    /* share mode: groups holding them */
-  int32_t bf_rounds;       /* share mode: Bellman-Ford rounds over groups */
+  int32_t bf_rounds;       /* share mode: Bellman-Ford rounds over blocks of groups */
   float ms_partition;      /* device time: boundary, renumbering (through the host plan) */
   float ms_components;     /* device time: APSP(C) initialisation + Floyd-Warshall */
   float ms_bg_assembly;    /* device time: BG matrix assembly */
@@ -150,6 +154,7 @@ typedef struct {
   int64_t graph_nodes;     /* nodes (kernel launches, event waits) in those graphs */
   int32_t groups3;         /* level-3 super-groups (0: BG2 closed flat) */
   int32_t v_bg3;           /* level-3 boundary vertices */
+  int32_t bf_block_groups; /* share mode: groups per Bellman-Ford block */
 } spq_stats;
 
 /*
@@ -387,7 +392,7 @@ spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int3
  *   groups    G in [1, 4096]; nv[g] in [1, vp] vertices and nk[g] in [0, kp]
  *             boundary rows per group (HOST arrays of G);
  *             koff[g] = nk[0] + ... + nk[g-1], voff[g] likewise over nv
- *   vp, kp    positive multiples of 128
+ *   vp, kp    positive multiples of 128, vp <= 32,768
  *   R         G x kp x vp int32: R[g][a][x] at R[(g*kp + a)*vp + x]
  *   D         rows and columns koff[G] at least, leading dimension ldd >=
  *             koff[G] (may be NULL when koff[G] = 0)

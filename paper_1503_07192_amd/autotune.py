@@ -5,7 +5,9 @@ workload itself and the fastest set is stored in a JSON cache keyed by the
 device architecture and a size class of the problem:
 
 * flat Floyd-Warshall on BG: tile side (64, 128) x interior K chunk (16, 32);
-* two-level BG: consecutive components per group (8 .. 256) x K chunk.
+* two-level BG: consecutive components per group (8 .. 256) x K chunk;
+* share builds: consecutive components per group (8 .. 64) x groups per
+  block of the Bellman-Ford over BG2 (1, 2, 4, 8), K chunk 16.
   Groups formed by size (``group_bg``) are not tried: on partitions numbered
   by recursive bisection or super-blocks they cut across the aligned runs of
   2^j components that make a group compact, and measured 1.5-10x slower.
@@ -54,6 +56,13 @@ def candidates(v_bg: int, k: int, share_comps: int):
                 for pt in (2, 4):
                     out.append({"bg_method": 1, "bg_tile": tile, "inner_kc": kc, "bg_pivot": pt * tile})
     cpg = 8
+    if share_comps:
+        while cpg <= min(64, k):
+            for blk in (1, 2, 4, 8):
+                out.append({"bg_method": 2, "group_comps": cpg, "level3_groups": blk,
+                            "inner_kc": 16})
+            cpg *= 2
+        return out
     while cpg <= min(256, k):
         for kc in (16, 32):
             out.append({"bg_method": 2, "group_comps": cpg, "inner_kc": kc})

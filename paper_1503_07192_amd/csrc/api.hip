@@ -224,6 +224,10 @@ struct spq_index {
   int64_t S2p = 0;
   u32 *A = nullptr, *DT = nullptr, *bfflag = nullptr, *bfstamp = nullptr;
   int32_t *bfcnt = nullptr, *bflist = nullptr;
+  // Bellman-Ford blocks (runs of bgpt groups): first level-2 id, size
+  int32_t bgpt = 1, nblk = 0, bpmax = 0;
+  std::vector<int32_t> h_boff, h_bsize;
+  int32_t *boff = nullptr, *bsize = nullptr;
   int4* xe = nullptr;
   int32_t* xcount = nullptr;
   // exactness certificate (total weight >= INF)
@@ -278,7 +282,7 @@ struct spq_index {
                     vrec, gT,    grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
                     bgvert, label, bglabel, cert, A,    DT,    bfflag,  bfstamp, bfcnt, bflist,
-                    xe, xcount,
+                    xe, xcount, boff, bsize,
                     eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
                     M3, R3, XT3, BG3, plist, plist3, rowptr, adj, adeg, w_copy};
     for (void* p : ptrs) pool_release(p);
@@ -349,10 +353,11 @@ static bool bands_match(const spq_index* X, int32_t row_groups, bool share) {
   return true;
 }
 
-// Share mode (after level 1): Bellman-Ford over groups from the share's
-// level-2 vertices, then the composition for the share's groups against all
-// groups.  Synchronous (one small readback per round).
-static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool profile,
+// Share mode (after level 1): Bellman-Ford over blocks of groups from the
+// share's level-2 vertices, then the composition for the share's groups
+// against all groups.  blk_opt: groups per block (> 0), 0 auto, -1 one.
+// Synchronous (one small readback per round).
+static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool profile, int32_t blk_opt,
                               hipStream_t s) {
   const int32_t G = X->ngroups, Vgp = X->Vgp;
   if (((int64_t)std::max<int64_t>(X->V2p, 128) + 31) / 32 > 65535)
@@ -370,29 +375,59 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   if (!bands_match(X, X->share_groups, true)) return fail(SPQ_EDEVICE, "internal: band layout");
   const int64_t V2p = std::max<int64_t>(X->V2p, 128);
   X->V2p = V2p;
+  // Bellman-Ford blocks: runs of bgpt groups (auto: a power of two of groups,
+  // about 1,024 level-2 vertices per block)
+  int32_t bgpt = 1;
+  if (blk_opt > 0) {
+    bgpt = std::min(blk_opt, G);
+  } else if (blk_opt == 0) {
+    const double avg = std::max(1.0, (double)X->V2 / G);
+    while (bgpt * 2 <= G && bgpt * 2 * avg <= 1024.0 * 1.41) bgpt *= 2;
+  }
+  X->bgpt = bgpt;
+  X->nblk = (G + bgpt - 1) / bgpt;
+  if (X->nblk > 65535) return fail(SPQ_EINVAL, "more than 65,535 Bellman-Ford blocks");
+  const int32_t NB = X->nblk;
+  X->h_boff.assign(NB + 1, 0);
+  X->h_bsize.assign(NB, 0);
+  int32_t bmax = 0;
+  for (int32_t t = 0; t < NB; t++) {
+    X->h_boff[t] = X->h_b2off[t * bgpt];
+    X->h_bsize[t] = X->h_b2off[std::min((t + 1) * bgpt, G)] - X->h_boff[t];
+    bmax = std::max(bmax, X->h_bsize[t]);
+  }
+  X->h_boff[NB] = X->V2;
+  X->bpmax = (int32_t)std::max<int64_t>(128, round_up(bmax, 128));
+  const int32_t BP = X->bpmax;
+  if (bgpt > 1) X->relax_bg_exec += NB * spq::dense_fw_exec_relax(BP / 128, 128, X->cpivot);
   HIP_TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(dalloc(&X->boff, NB + 1));
+  HIP_TRY(dalloc(&X->bsize, NB));
+  HIP_TRY(hipMemcpyAsync(X->boff, X->h_boff.data(), sizeof(int32_t) * (NB + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(X->bsize, X->h_bsize.data(), sizeof(int32_t) * NB, hipMemcpyHostToDevice, s));
   HIP_TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
   HIP_TRY(make_pairs(X->share_groups, G, false, (int64_t)X->m2pmax * Vgp, X->h_elems, &X->plist,
                      &X->npairs,
                      &X->chunk, s));
   HIP_TRY(dalloc(&X->XT, (int64_t)X->chunk * X->m2pmax * Vgp));
-  HIP_TRY(dalloc(&X->A, (int64_t)G * X->m2pmax * X->m2pmax));
+  HIP_TRY(dalloc(&X->A, (int64_t)NB * BP * BP));
   // the Bellman-Ford matrix carries 128 spare rows: a row tile may start at
-  // the last group's last level-2 id
+  // the last block's last level-2 id
   HIP_TRY(dalloc(&X->DT, (V2p + 128) * X->S2p));
-  HIP_TRY(dalloc(&X->BG2, X->S2p * V2p));
+  // D2 = DT transposed, one column panel of S2p x m2pmax per group
+  HIP_TRY(dalloc(&X->BG2, (int64_t)G * X->S2p * X->m2pmax));
   HIP_TRY(dalloc(&X->H, X->h_elems));
   HIP_TRY(dalloc(&X->pairbase, (int64_t)G * G));
   HIP_TRY(dalloc(&X->xe, 2 * std::max<int64_t>(m, 1)));
   HIP_TRY(dalloc(&X->xcount, 1));
-  // dirty flags, two rounds' worth: per group one word per column tile of
+  // dirty flags, two rounds' worth: per block one word per column tile of
   // 128 share sources and one "any" word
   const int32_t ntc = (int32_t)(X->S2p / 128), fs = ntc + 1;
-  HIP_TRY(dalloc(&X->bfflag, 2 * (int64_t)G * fs));
-  // rows lowered per (group, column tile), two rounds' worth, and the round
+  HIP_TRY(dalloc(&X->bfflag, 2 * (int64_t)NB * fs));
+  // rows lowered per (block, column tile), two rounds' worth, and the round
   // stamps that keep a row from being listed twice in one round
-  HIP_TRY(dalloc(&X->bfcnt, 2 * (int64_t)G * ntc));
-  HIP_TRY(dalloc(&X->bflist, 2 * (int64_t)G * ntc * X->m2pmax));
+  HIP_TRY(dalloc(&X->bfcnt, 2 * (int64_t)NB * ntc));
+  HIP_TRY(dalloc(&X->bflist, 2 * (int64_t)NB * ntc * BP));
   HIP_TRY(dalloc(&X->bfstamp, V2p * ntc));
   HIP_TRY(hipMemsetAsync(X->bfstamp, 0xff, sizeof(u32) * V2p * ntc, s));
   HIP_TRY(hipMemsetAsync(X->xcount, 0, sizeof(int32_t), s));
@@ -402,51 +437,52 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   ha.m2pmax = X->m2pmax; ha.V2 = X->V2; ha.V2p = V2p; ha.b2off = X->b2off; ha.R = X->R;
   ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
   ha.plist = X->plist; ha.npairs = X->npairs; ha.chunk = X->chunk;
-  ha.share_groups = X->share_groups; ha.S2 = X->S2; ha.S2p = X->S2p; ha.A = X->A; ha.DT = X->DT;
+  ha.share_groups = X->share_groups; ha.S2 = X->S2; ha.S2p = X->S2p; ha.DT = X->DT;
   ha.xe = X->xe; ha.xcount = X->xcount;
-  HIP_TRY(spq::launch_share_prepare(ha, s));
+  const spq::ShareBlocks blk{bgpt, NB, BP, X->boff, X->bsize, X->A};
+  HIP_TRY(spq::launch_share_prepare(ha, blk, s));
   int32_t nxe = 0;
   HIP_TRY(hipMemcpyAsync(&nxe, X->xcount, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  // the share's groups start dirty on every column tile, with every row
-  std::vector<u32> hd((size_t)G * fs, 0);
-  std::vector<int32_t> hc((size_t)G * ntc, 0);
-  for (int32_t g = 0; g < X->share_groups; g++) {
-    for (int32_t t = 0; t < fs; t++) hd[(size_t)g * fs + t] = 1;
-    for (int32_t t = 0; t < ntc; t++) hc[(size_t)g * ntc + t] = spq::BF_ALL_ROWS;
-  }
-  HIP_TRY(hipMemcpyAsync(X->bfflag, hd.data(), sizeof(u32) * G * fs, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(X->bfcnt, hc.data(), sizeof(int32_t) * G * ntc, hipMemcpyHostToDevice, s));
+  // The blocks holding share sources start dirty on every column tile.  Their
+  // rows start closed (DT's initial rows are rows of the closed A), so the
+  // first intra step has no row to multiply: cross edges move first.
+  std::vector<u32> hd((size_t)NB * fs, 0);
+  std::vector<int32_t> hc((size_t)NB * ntc, 0);
+  for (int32_t t = 0; t < NB && X->h_boff[t] < X->S2; t++)
+    for (int32_t c = 0; c < fs; c++) hd[(size_t)t * fs + c] = 1;
+  HIP_TRY(hipMemcpyAsync(X->bfflag, hd.data(), sizeof(u32) * NB * fs, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(X->bfcnt, hc.data(), sizeof(int32_t) * NB * ntc, hipMemcpyHostToDevice, s));
   u32* dcur = X->bfflag;
-  u32* dnext = X->bfflag + (int64_t)G * fs;
+  u32* dnext = X->bfflag + (int64_t)NB * fs;
   int32_t* ccur = X->bfcnt;
-  int32_t* cnext = X->bfcnt + (int64_t)G * ntc;
+  int32_t* cnext = X->bfcnt + (int64_t)NB * ntc;
   int32_t* lcur = X->bflist;
-  int32_t* lnext = X->bflist + (int64_t)G * ntc * X->m2pmax;
+  int32_t* lnext = X->bflist + (int64_t)NB * ntc * BP;
   for (;;) {
-    if (++X->bf_rounds > 100000) return fail(SPQ_EDEVICE, "Bellman-Ford over groups did not settle");
-    // executed relaxations: a dirty (group, tile) multiplies its row tiles by
-    // the rows listed for it (all of them in the first round)
-    for (int32_t g = 0; g < G; g++)
-      for (int32_t t = 0; t < ntc; t++) {
-        const int32_t c = hc[(size_t)g * ntc + t];
-        if (c == 0 || !hd[(size_t)g * fs + t]) continue;
-        const int32_t kk = c == spq::BF_ALL_ROWS ? X->h_m2[g] : c;
-        X->relax_bg_exec += (double)((X->h_m2[g] + 127) / 128) * 128.0 * 128.0 *
+    if (++X->bf_rounds > 100000) return fail(SPQ_EDEVICE, "Bellman-Ford over blocks did not settle");
+    // executed relaxations: a dirty (block, tile) multiplies its row tiles by
+    // the rows listed for it
+    for (int32_t t = 0; t < NB; t++)
+      for (int32_t c = 0; c < ntc; c++) {
+        const int32_t cc = hc[(size_t)t * ntc + c];
+        if (cc == 0 || !hd[(size_t)t * fs + c]) continue;
+        const int32_t kk = cc == spq::BF_ALL_ROWS ? X->h_bsize[t] : cc;
+        X->relax_bg_exec += (double)((X->h_bsize[t] + 127) / 128) * 128.0 * 128.0 *
                             (double)round_up(kk, 16);
       }
     const spq::BfRound r{dcur, dnext, ccur, lcur, cnext, lnext, X->bfstamp, (u32)X->bf_rounds};
-    HIP_TRY(hipMemsetAsync(dnext, 0, sizeof(u32) * G * fs, s));
-    HIP_TRY(hipMemsetAsync(cnext, 0, sizeof(int32_t) * G * ntc, s));
-    HIP_TRY(spq::launch_share_round(ha, nxe, r, s));
-    HIP_TRY(hipMemcpyAsync(hd.data(), dnext, sizeof(u32) * G * fs, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hc.data(), cnext, sizeof(int32_t) * G * ntc, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemsetAsync(dnext, 0, sizeof(u32) * NB * fs, s));
+    HIP_TRY(hipMemsetAsync(cnext, 0, sizeof(int32_t) * NB * ntc, s));
+    HIP_TRY(spq::launch_share_round(ha, blk, nxe, r, s));
+    HIP_TRY(hipMemcpyAsync(hd.data(), dnext, sizeof(u32) * NB * fs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hc.data(), cnext, sizeof(int32_t) * NB * ntc, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::swap(dcur, dnext);
     std::swap(ccur, cnext);
     std::swap(lcur, lnext);
     bool any = false;
-    for (int32_t g = 0; g < G; g++) any |= hd[(size_t)g * fs + ntc] != 0;
+    for (int32_t t = 0; t < NB; t++) any |= hd[(size_t)t * fs + ntc] != 0;
     if (!any) break;
   }
   for (int32_t a1 = 0; a1 < X->share_groups; a1++)
@@ -750,6 +786,10 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     }
   } else {
     X->Vgp = std::max<int32_t>(X->Vgp, 128);
+    // the composition stores a group pair's block with 32-bit offsets
+    if (X->Vgp > 32768)
+      return guard(fail(SPQ_EINVAL, "a group holds more than 32,768 BG vertices: lower "
+                                    "group_comps or group_bg"));
     X->relax_bg_exec = X->ngroups * spq::dense_fw_exec_relax(X->Vgp / 128, 128, X->cpivot);
   }
   X->h_order.resize(k);
@@ -939,7 +979,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     X->V2p = round_up(X->V2, 128);
     X->m2pmax = (int32_t)std::max<int64_t>(128, round_up(m2max, 128));
     if (X->share_comps > 0) {
-      spq_status ss = build_share(X, ha, m, profile, s);
+      spq_status ss = build_share(X, ha, m, profile, level3_opt, s);
       if (ss != SPQ_OK) return guard(ss);
       TRY(hipEventRecord(X->ev[4], s));
       *out = X;
@@ -1386,6 +1426,7 @@ spq_status spq_index_stats(const spq_index* X, spq_stats* st) {
   st->share_comps = X->share_comps;
   st->share_groups = X->share_groups;
   st->bf_rounds = X->bf_rounds;
+  st->bf_block_groups = X->share_comps > 0 ? X->bgpt : 0;
   st->graphs = (int32_t)X->execs.size();
   st->reweights = X->reweights;
   st->graph_nodes = X->graph_nodes;
@@ -1517,6 +1558,7 @@ spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv
   if (groups < 1 || groups > 4096) return fail(SPQ_EINVAL, "groups must be in [1, 4096]");
   if (vp < 128 || vp % 128 || kp < 128 || kp % 128)
     return fail(SPQ_EINVAL, "vp and kp must be positive multiples of 128");
+  if (vp > 32768) return fail(SPQ_EINVAL, "vp above 32,768");
   if (!nv || !nk || !R || !M || !out || npairs < 0 || (npairs > 0 && !pairs))
     return fail(SPQ_EINVAL, "null argument or npairs < 0");
   std::vector<int32_t> koff(groups + 1, 0), voff(groups + 1, 0);

@@ -357,9 +357,22 @@ __device__ __forceinline__ void fill_inf(u32 (&c)[8][8]) {
 // launch: blockIdx.y = pair plist[pbase + blockIdx.y], whose XT takes slot
 // blockIdx.y of the XT buffer (one slot per pair of the chunk).
 //
+// Workgroups are dealt round-robin to the eight XCDs in order of their linear
+// id, so with gridDim.x a multiple of 8 an XCD would get the same tile column
+// of every pair; the tiles past a group's last vertex (the padded last
+// column, empty for most groups) would then leave one XCD idle.  The tile of
+// a workgroup is therefore rotated by its pair.
+__device__ __forceinline__ int comp_tile() {
+  return (int)((blockIdx.x + blockIdx.y) % gridDim.x);
+}
+//
 // XT (m2pmax x Vgp, rows b in B2(S2), columns x of S1) =
 //   min over a in B2(S1) of D2[a][b] + R_S1[a][x].
-// D2 rows are level-2 ids of the sources (all of BG2, or the share's rows).
+// D2 rows are level-2 ids of the sources (all of BG2, or the share's rows),
+// leading dimension ldd.  pstride = 0: D2 is dense (column = level-2 id);
+// pstride > 0: D2 is cut into one column panel per group S2, pstride
+// elements apart, whose column j is B2(S2)'s j-th vertex: the (S1, S2) block
+// a product reads is then one contiguous run instead of rows ldd apart.
 // Rows b in [m2[S2], round16(m2[S2])) are stored as INF.  The composition
 // reads rows below round16(m2[S2]) and column tiles below gV[S1] only, so
 // tiles past those are neither computed nor written.
@@ -368,7 +381,8 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
                                                const int32_t* __restrict__ m2,
                                                const int32_t* __restrict__ gV,
                                                const int32_t* __restrict__ b2off,
-                                               const u32* __restrict__ BG2, int64_t V2p,
+                                               const u32* __restrict__ BG2, int64_t ldd,
+                                               int64_t pstride,
                                                const u32* __restrict__ R, u32* __restrict__ XT) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
@@ -376,15 +390,17 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
   const int32_t s1 = pr.x, s2 = pr.y;
   const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
-  const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
+  const int tile = comp_tile();
+  const int ti = tile / ntx, tj = tile % ntx;
   const int32_t ka = m2[s1], mb = m2[s2];
   if (ti * 128 >= mb || tj * 128 >= gV[s1]) return;
   u32 c[8][8];
   fill_inf(c);
   {
-    const u32* At = BG2 + (int64_t)b2off[s1] * V2p + b2off[s2] + ti * 128;
+    const u32* At = BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd +
+                    (pstride ? 0 : b2off[s2]) + ti * 128;
     const u32* B = R + (int64_t)s1 * m2pmax * Vgp + tj * 128;
-    mp_stream128<true>(c, At, V2p, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB);
+    mp_stream128<true>(c, At, ldd, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB);
   }
   u32* out = XT + (slot * m2pmax + ti * 128) * Vgp + tj * 128;
   const int tx = tid_x(), ty = tid_y();
@@ -407,6 +423,12 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
 // D(S1,S2) tile (rows x of S1, columns y of S2) for the pair of blockIdx.y:
 //   min over b in B2(S2) of XT[b][x] + R_S2[b][y], and d_S1 when S1 = S2;
 // stored in the component-pair layout described at the top of the file.
+// The offset of (x, y) inside the pair's block, rowoff(x) V_S2 + nb(x)
+// rowoff(y) + loc(x) nb(y) + loc(y), is below V_S1 V_S2 < 2^30 (groups hold at
+// most 32,768 BG vertices): 32-bit arithmetic from the pair's base pointer.
+// CERT: the exactness certificate is fused into the store (largest finite
+// value, and whether an INF joins two vertices connected in G).
+template <bool CERT>
 __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict__ plist, int32_t pbase,
                                               int32_t ngroups, int32_t Vgp,
                                               int32_t m2pmax,
@@ -427,7 +449,8 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict
   const int32_t s1 = pr.x, s2 = pr.y;
   const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
-  const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
+  const int tile = comp_tile();
+  const int ti = tile / ntx, tj = tile % ntx;
   const int32_t V1 = gV[s1], V2 = gV[s2];
   if (ti * 128 >= V1 || tj * 128 >= V2) return;
   u32 c[8][8];
@@ -443,24 +466,21 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict
   u32* base = H + pairbase[(int64_t)s1 * ngroups + s2];
   const int tx = tid_x(), ty = tid_y();
   const int32_t g1 = gbg0[s1], g2 = gbg0[s2];
-  int64_t colpart[8];
-  int32_t colnb[8], collab[8];
-  bool colok[8];
+  // column terms: rowoff(y), nb(y), loc(y) (and the label for the certificate)
+  u32 ry[8], ny[8], ly[8];
+  int32_t collab[8];
 #pragma unroll
   for (int h2 = 0; h2 < 2; h2++)
 #pragma unroll
     for (int a2 = 0; a2 < 4; a2++) {
       const int32_t y = tj * 128 + h2 * 64 + tx * 4 + a2;
       const int j = h2 * 4 + a2;
-      colok[j] = y < V2;
-      const int32_t yg = g2 + (colok[j] ? y : 0);
-      colpart[j] = bgrow[yg];   // times nb(x) below
-      colnb[j] = bgnb[yg];
-      colpart[j] = (colpart[j] << 32) | (uint32_t)bglocal[yg];
-      collab[j] = bglabel ? bglabel[yg] : 0;
+      const int32_t yg = g2 + (y < V2 ? y : 0);
+      ry[j] = (u32)bgrow[yg];
+      ny[j] = (u32)bgnb[yg];
+      ly[j] = (u32)bglocal[yg];
+      if (CERT) collab[j] = bglabel[yg];
     }
-  // exactness certificate, fused into the store: largest finite value, and
-  // whether any INF joins two vertices connected in G
   u32 best = 0, wrong = 0;
 #pragma unroll
   for (int h = 0; h < 2; h++)
@@ -469,20 +489,22 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict
       const int32_t x = ti * 128 + h * 64 + ty * 4 + a;
       if (x >= V1) continue;
       const int32_t xg = g1 + x;
-      const int64_t rbase = (int64_t)bgrow[xg] * V2;
-      const int64_t nbx = bgnb[xg], locx = bglocal[xg];
-      const int32_t labx = bglabel ? bglabel[xg] : 0;
+      const u32 rbase = (u32)bgrow[xg] * (u32)V2;
+      const u32 nbx = (u32)bgnb[xg], locx = (u32)bglocal[xg];
+      const int32_t labx = CERT ? bglabel[xg] : 0;
       const int i = h * 4 + a;
 #pragma unroll
       for (int j = 0; j < 8; j++) {
-        if (!colok[j]) continue;
-        const int64_t rowy = colpart[j] >> 32, locy = colpart[j] & 0xffffffffll;
-        base[rbase + nbx * rowy + locx * colnb[j] + locy] = c[i][j];
-        if (c[i][j] < INF) best = max(best, c[i][j]);
-        else wrong |= (u32)(collab[j] == labx);
+        const int32_t y = tj * 128 + (j >> 2) * 64 + tx * 4 + (j & 3);
+        if (y >= V2) continue;
+        base[rbase + __umul24(nbx, ry[j]) + __umul24(locx, ny[j]) + ly[j]] = c[i][j];
+        if (CERT) {
+          if (c[i][j] < INF) best = max(best, c[i][j]);
+          else wrong |= (u32)(collab[j] == labx);
+        }
       }
     }
-  if (bglabel) {
+  if (CERT) {
     for (int o = 32; o > 0; o >>= 1) {
       best = max(best, (u32)__shfl_xor((int)best, o));
       wrong |= (u32)__shfl_xor((int)wrong, o);
@@ -576,7 +598,8 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y_dense(const int2* __re
   const int32_t s1 = pr.x, s2 = pr.y;
   const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
-  const int ti = (int)blockIdx.x / ntx, tj = (int)blockIdx.x % ntx;
+  const int tile = comp_tile();
+  const int ti = tile / ntx, tj = tile % ntx;
   const int32_t V1 = gV[s1], V2 = gV[s2];
   if (ti * 128 >= V1 || tj * 128 >= V2) return;
   u32 c[8][8];
@@ -632,65 +655,109 @@ __global__ void k_hier_row(int32_t x, int32_t swap, int32_t V, int32_t ngroups,
 // ------------------------------------------------------------ share mode --
 // Distances from the level-2 boundary vertices of the share groups (the
 // first share_groups groups; their level-2 ids are 0 .. S2-1) to all level-2
-// vertices, by Bellman-Ford over groups on BG2 without building it: DT[b][i]
+// vertices, by Bellman-Ford over blocks of consecutive groups on BG2, without
+// building BG2.  A block T is a run of gpt groups (gpt = 1: every group is a
+// block); A_T = BG2 induced on T's level-2 vertices (d_S between the B2
+// vertices of one group S, the G edges between groups of T), closed.  DT[b][i]
 // (row b = any level-2 id, column i = share source) alternates
-//   intra-group:  DT[B2(S)] = min(DT[B2(S)], A_S (x) DT[B2(S)])   (A_S = d_S on B2(S),
-//                 closed, so one product covers any path inside S)
-//   cross edges:  DT[b] = min(DT[b], DT[a] + w(a,b))  for each G edge between groups
-// until nothing changes; the fixed point is d_BG2 from every share source.
+//   intra-block:  DT[T] = min(DT[T], A_T (x) DT[T])   (A_T closed: one product
+//                 covers any walk that stays inside T)
+//   cross edges:  DT[b] = min(DT[b], DT[a] + w(a,b))  for each G edge between blocks
+// until nothing changes.  Every walk of BG2 is a sequence of pieces inside one
+// block joined by G edges between blocks, so the fixed point is d_BG2 from
+// every share source (Lemma 1 for the block partition of BG2).  Larger blocks
+// mean fewer rounds (a round crosses one block) and fewer cross edges, at the
+// price of larger products.
 
-// A_S: d_S between the B2 vertices of S (m2pmax x m2pmax per group, INF padding).
-__global__ void k_b2_block(int32_t Vgp, int32_t m2pmax, const int32_t* __restrict__ m2,
-                           const int32_t* __restrict__ b2list, const u32* __restrict__ Mg,
-                           u32* __restrict__ A) {
-  const int s = blockIdx.y;
-  const int32_t i = blockIdx.x, ms = m2[s];
-  u32* out = A + ((int64_t)s * m2pmax + i) * m2pmax;
-  const int32_t* list = b2list + (int64_t)s * Vgp;
-  const u32* prow = i < ms ? Mg + ((int64_t)s * Vgp + list[i]) * Vgp : nullptr;
-  for (int32_t j = threadIdx.x; j < m2pmax; j += blockDim.x)
-    out[j] = (i < ms && j < ms) ? prow[list[j]] : INF;
+// A_T before its closure (bpmax x bpmax per block, local level-2 indices):
+// d_S between the B2 vertices of one group, 0 on the diagonal, INF elsewhere
+// and on the padding.  gpt = 1: A_T = d_S on B2(S), already closed.
+__global__ void k_blk_init(int32_t Vgp, int32_t bpmax, int32_t gpt, int32_t ngroups,
+                           const int32_t* __restrict__ b2off, const int32_t* __restrict__ b2list,
+                           const u32* __restrict__ Mg, u32* __restrict__ A) {
+  const int t = blockIdx.y;
+  const int32_t p = blockIdx.x;
+  const int32_t g0 = t * gpt, g1 = min(g0 + gpt, ngroups);
+  const int32_t base = b2off[g0], size = b2off[g1] - base;
+  u32* out = A + ((int64_t)t * bpmax + p) * bpmax;
+  int32_t lo = 0, hi = 0;
+  const u32* prow = nullptr;
+  const int32_t* list = nullptr;
+  if (p < size) {
+    int32_t a = g0;  // the row's group (a block holds few groups)
+    while (a + 1 < g1 && b2off[a + 1] - base <= p) a++;
+    lo = b2off[a] - base;
+    hi = b2off[a + 1] - base;
+    list = b2list + (int64_t)a * Vgp;
+    prow = Mg + ((int64_t)a * Vgp + list[p - lo]) * Vgp;
+  }
+  for (int32_t q = threadIdx.x; q < bpmax; q += blockDim.x)
+    out[q] = (q == p) ? 0u : (q >= lo && q < hi) ? prow[list[q - lo]] : INF;
 }
 
-// DT init: row b (level-2 id), column i (share source): d_S(b, i) inside one
-// group, 0 for b = i, INF otherwise.
-__global__ void k_dt_init(int32_t V2, int32_t S2, int64_t S2p, int32_t ngroups,
-                          const int32_t* __restrict__ b2off, const int32_t* __restrict__ b2list,
-                          int32_t Vgp, const u32* __restrict__ Mg, u32* __restrict__ DT) {
+// G edges between groups of the same block, into A_T (both directions).
+__global__ void k_blk_edges(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                            const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
+                            const int32_t* __restrict__ local, const int32_t* __restrict__ bgoff,
+                            const int32_t* __restrict__ grp, int32_t gpt,
+                            const int32_t* __restrict__ b2off, const int32_t* __restrict__ b2rank,
+                            int32_t bpmax, u32* __restrict__ A) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = eu[e], v = ev[e];
+    const int32_t cu = comp[u], cv = comp[v];
+    if (cu == cv) continue;
+    const int32_t su = grp[cu], sv = grp[cv];
+    if (su == sv || su / gpt != sv / gpt) continue;
+    const int32_t t = su / gpt, base = b2off[t * gpt];
+    const int64_t a = b2off[su] + b2rank[bgoff[cu] + local[u]] - base;
+    const int64_t b = b2off[sv] + b2rank[bgoff[cv] + local[v]] - base;
+    u32* At = A + (int64_t)t * bpmax * bpmax;
+    atomicMin(At + a * bpmax + b, (u32)w[e]);
+    atomicMin(At + b * bpmax + a, (u32)w[e]);
+  }
+}
+
+// DT init: row b (level-2 id), column i (share source): the distance inside
+// b's block when i lies in it (row b of the closed A_T), 0 for b = i, INF
+// otherwise.  boff: first level-2 id of each block (nblk + 1 entries).
+__global__ void k_dt_init(int32_t V2, int32_t S2, int64_t S2p, int32_t nblk,
+                          const int32_t* __restrict__ boff, int32_t bpmax, const u32* __restrict__ A,
+                          u32* __restrict__ DT) {
   const int64_t b = blockIdx.x;
   u32* out = DT + b * S2p;
   int64_t lo = 0, hi = 0;
-  const u32* prow = nullptr;
-  const int32_t* list = nullptr;
+  const u32* arow = nullptr;
   if (b < V2) {
-    int32_t a = 0, z = ngroups - 1;
+    int32_t a = 0, z = nblk - 1;
     while (a < z) {
       const int32_t mid = (a + z + 1) >> 1;
-      if (b2off[mid] <= b) a = mid; else z = mid - 1;
+      if (boff[mid] <= b) a = mid; else z = mid - 1;
     }
-    lo = b2off[a];
-    hi = min((int64_t)b2off[a + 1], (int64_t)S2);
-    list = b2list + (int64_t)a * Vgp;
-    prow = Mg + ((int64_t)a * Vgp + list[b - lo]) * Vgp;
+    lo = boff[a];
+    hi = min((int64_t)boff[a + 1], (int64_t)S2);
+    arow = A + ((int64_t)a * bpmax + (b - lo)) * bpmax;
   }
   for (int64_t i = threadIdx.x; i < S2p; i += blockDim.x)
-    out[i] = (i == b) ? 0u : (i >= lo && i < hi) ? prow[list[i - lo]] : INF;
+    out[i] = (i == b) ? 0u : (i >= lo && i < hi) ? arow[i - lo] : INF;
 }
 
-// Dirty flags of the Bellman-Ford rounds: per group, one word per column tile
-// of 128 share sources, then one word "any tile" (stride ntc + 1).  Beside
-// them, per (group, column tile), the rows (local level-2 indices) that the
-// cross edges lowered since the group's last intra step: a count and a list
-// (count BF_ALL_ROWS: every row, the share's groups in the first round).
+// Dirty flags of the Bellman-Ford rounds: per block (a group or a run of
+// groups; m2 / b2off / A below are the block's level-2 count, first level-2
+// id and closed matrix), one word per column tile of 128 share sources, then
+// one word "any tile" (stride ntc + 1).  Beside them, per (block, column
+// tile), the rows (local level-2 indices) that the cross edges lowered since
+// the block's last intra step: a count and a list (count BF_ALL_ROWS: every
+// row).
 //
-// Intra-group step, in place: rows B2(S) x column tile of DT = min(DT, A_S (x)
-// DT) for the (group, tile) pairs whose values changed in the previous round.
-// One product with the closed A_S leaves the rows closed.  The rows were
+// Intra-block step, in place: the block's rows x column tile of DT = min(DT,
+// A (x) DT) for the (block, tile) pairs whose values changed in the previous
+// round.  One product with the closed A leaves the rows closed.  The rows were
 // closed before the cross edges lowered some of them, and for an unchanged
-// row k, A_S[x][k] + DT[k] >= DT[x] already; so only the lowered rows need to
-// be the K of the product.  Tiles of one group read rows that other tiles of
-// the group are lowering: every value read is the old or the new one, both
-// lengths of real walks and each at most the old value, and A_S being closed,
+// row k, A[x][k] + DT[k] >= DT[x] already; so only the lowered rows need to
+// be the K of the product.  Tiles of one block read rows that other tiles of
+// the block are lowering: every value read is the old or the new one, both
+// lengths of real walks and each at most the old value, and A being closed,
 // the old values already give the closed result, so the step is exact in any
 // interleaving.
 __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
@@ -737,11 +804,13 @@ __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
     }
 }
 
-// Cross edges between groups, as directed level-2 pairs (a -> b, w).
+// Cross edges between blocks, as directed level-2 pairs (a -> b, w), tagged
+// (source block << 16) | destination block.
 __global__ void k_cross_collect(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
                                 const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
                                 const int32_t* __restrict__ local, const int32_t* __restrict__ bgoff,
-                                const int32_t* __restrict__ grp, const int32_t* __restrict__ b2off,
+                                const int32_t* __restrict__ grp, int32_t gpt,
+                                const int32_t* __restrict__ b2off,
                                 const int32_t* __restrict__ b2rank, int32_t* __restrict__ count,
                                 int4* __restrict__ xe) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
@@ -750,21 +819,23 @@ __global__ void k_cross_collect(int64_t m, const int32_t* __restrict__ eu, const
     const int32_t cu = comp[u], cv = comp[v];
     if (cu == cv) continue;
     const int32_t su = grp[cu], sv = grp[cv];
-    if (su == sv) continue;
+    const int32_t tu = su / gpt, tv = sv / gpt;  // blocks
+    if (tu == tv) continue;
     const int32_t a = b2off[su] + b2rank[bgoff[cu] + local[u]];
     const int32_t b = b2off[sv] + b2rank[bgoff[cv] + local[v]];
     const int32_t slot = atomicAdd(count, 2);
-    xe[slot] = make_int4(a, b, w[e], (su << 16) | sv);
-    xe[slot + 1] = make_int4(b, a, w[e], (sv << 16) | su);
+    xe[slot] = make_int4(a, b, w[e], (tu << 16) | tv);
+    xe[slot + 1] = make_int4(b, a, w[e], (tv << 16) | tu);
   }
 }
 
 // DT[b][i] = min(DT[b][i], DT[a][i] + w) for every directed cross edge, on
-// the column tiles that are dirty for the source group (values that have not
+// the column tiles that are dirty for the source block (values that have not
 // changed since they were last propagated need no new pass); a lowered value
-// marks its (group, tile) dirty for the next round and, once per round (the
+// marks its (block, tile) dirty for the next round and, once per round (the
 // stamp of (row, tile) holds the round that last listed it), adds its row to
-// that (group, tile)'s list.
+// that (block, tile)'s list (b2off: first level-2 id of each block, m2pmax:
+// list slots per (block, tile)).
 __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2, int64_t S2p, u32* DT,
                            const u32* __restrict__ dirty, u32* __restrict__ dirty_next,
                            const int32_t* __restrict__ b2off, int32_t m2pmax, u32 round,
@@ -806,17 +877,25 @@ __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2,
   }
 }
 
-// D2s (S2p x V2p) = DT^T, 32 x 32 tiles through LDS.
-__global__ void k_transpose(const u32* __restrict__ src, int64_t rows, int64_t cols, int64_t lds_,
-                            u32* __restrict__ dst, int64_t ldd) {
+// The share's D2 in column panels: panel S (one per group, S2p x m2pmax
+// elements) holds D2[i][j] = DT[b2off[S] + j][i] for the share sources i and
+// the B2(S) vertices j < m2[S], INF in the columns past m2[S].  32 x 32 tiles
+// through LDS; blockIdx.z = the group.
+__global__ void k_panel_transpose(const u32* __restrict__ DT, int64_t S2p, int32_t m2pmax,
+                                  const int32_t* __restrict__ m2, const int32_t* __restrict__ b2off,
+                                  u32* __restrict__ D2) {
   __shared__ u32 t[32][33];
-  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  const int g = blockIdx.z;
+  const int32_t ms = m2[g], r0 = b2off[g];
+  const int64_t i0 = (int64_t)blockIdx.x * 32;  // share sources (panel rows)
+  const int32_t j0 = (int32_t)blockIdx.y * 32;  // B2(S) vertices (panel columns)
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int k = ty; k < 32; k += 8)
-    if (r0 + k < rows && c0 + tx < cols) t[k][tx] = src[(r0 + k) * lds_ + c0 + tx];
+    if (j0 + k < ms && i0 + tx < S2p) t[k][tx] = DT[(int64_t)(r0 + j0 + k) * S2p + i0 + tx];
   __syncthreads();
+  u32* panel = D2 + (int64_t)g * S2p * m2pmax;
   for (int k = ty; k < 32; k += 8)
-    if (c0 + k < cols && r0 + tx < rows) dst[(c0 + k) * ldd + r0 + tx] = t[tx][k];
+    if (i0 + k < S2p) panel[(i0 + k) * m2pmax + j0 + tx] = j0 + tx < ms ? t[tx][k] : INF;
 }
 
 // ---------------------------------------------------------------- launch --
@@ -877,15 +956,21 @@ static hipError_t compose_level2(const HierArgs& a, const int32_t* bglabel, u32*
   for (int32_t p0 = 0, c = 0; p0 < a.npairs; p0 += a.chunk, c++) {
     const unsigned np = (unsigned)min(a.chunk, a.npairs - p0);
     if (a.V2p > 0)
-      k_mp_xt<<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(a.plist, p0, a.Vgp, a.m2pmax, a.m2, a.gV,
-                                                              a.b2off, a.BG2, a.V2p, a.R, a.XT);
+      k_mp_xt<<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(
+          a.plist, p0, a.Vgp, a.m2pmax, a.m2, a.gV, a.b2off, a.BG2, a.d2pstride ? a.d2ld : a.V2p,
+          a.d2pstride, a.R, a.XT);
     if (a.evt) {
       hipError_t e = hipEventRecord(a.evt[2 * c], s);
       if (e != hipSuccess) return e;
     }
-    k_mp_y<<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
-        a.plist, p0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase,
-        a.bgrow, a.bgnb, a.bglocal, a.H, bglabel, cert_bad, cert_mbg);
+    if (bglabel)
+      k_mp_y<true><<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
+          a.plist, p0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase,
+          a.bgrow, a.bgnb, a.bglocal, a.H, bglabel, cert_bad, cert_mbg);
+    else
+      k_mp_y<false><<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
+          a.plist, p0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase,
+          a.bgrow, a.bgnb, a.bglocal, a.H, nullptr, nullptr, nullptr);
     if (a.evt) {
       hipError_t e = hipEventRecord(a.evt[2 * c + 1], s);
       if (e != hipSuccess) return e;
@@ -953,8 +1038,8 @@ hipError_t launch_level3_compose(const L3Args& a, hipStream_t s) {
     const unsigned np = (unsigned)min(a.chunk, a.npairs - p0);
     if (a.V3p > 0)
       k_mp_xt<<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(a.plist, p0, a.V3gp, a.m3pmax, a.m3,
-                                                              a.tsize, a.b3off, a.BG3, a.V3p, a.R3,
-                                                              a.XT3);
+                                                              a.tsize, a.b3off, a.BG3, a.V3p, 0,
+                                                              a.R3, a.XT3);
     k_mp_y_dense<<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
         a.plist, p0, a.V3gp, a.m3pmax, a.m3, a.tsize, a.tbase, a.XT3, a.R3, a.M3, a.BG2, a.V2p);
   }
@@ -972,27 +1057,36 @@ hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s
 
 namespace spq {
 
-hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s) {
+hipError_t launch_share_prepare(const HierArgs& a, const ShareBlocks& b, hipStream_t s) {
   k_r_gather<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(a.Vgp, a.m2pmax, a.m2,
                                                                            a.b2list, a.Mg, a.R);
-  k_b2_block<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(a.Vgp, a.m2pmax, a.m2,
-                                                                           a.b2list, a.Mg, a.A);
-  k_dt_init<<<(unsigned)a.V2p, 256, 0, s>>>(a.V2, a.S2, a.S2p, a.ngroups, a.b2off, a.b2list, a.Vgp,
-                                            a.Mg, a.DT);
+  k_blk_init<<<dim3((unsigned)b.bpmax, (unsigned)b.nblk), 256, 0, s>>>(a.Vgp, b.bpmax, b.gpt,
+                                                                       a.ngroups, a.b2off, a.b2list,
+                                                                       a.Mg, b.A);
+  if (b.gpt > 1) {
+    if (a.m > 0)
+      k_blk_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
+                                               b.gpt, a.b2off, a.b2rank, b.bpmax, b.A);
+    hipError_t e = launch_dense_fw_batch(b.A, b.bpmax, 128, b.bpmax / 128, b.nblk,
+                                         (int64_t)b.bpmax * b.bpmax, s, nullptr, a.kc, a.pivot);
+    if (e != hipSuccess) return e;
+  }
+  k_dt_init<<<(unsigned)a.V2p, 256, 0, s>>>(a.V2, a.S2, a.S2p, b.nblk, b.boff, b.bpmax, b.A, a.DT);
   if (a.m > 0)
     k_cross_collect<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
-                                                 a.b2off, a.b2rank, a.xcount, a.xe);
+                                                 b.gpt, a.b2off, a.b2rank, a.xcount, a.xe);
   return hipGetLastError();
 }
 
-// One Bellman-Ford round, in place on DT: intra-group step, then cross edges.
-hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const BfRound& r, hipStream_t s) {
-  const int ntm = a.m2pmax / 128, ntc = (int)(a.S2p / 128);
-  k_bf_intra<<<dim3((unsigned)(ntm * ntc), (unsigned)a.ngroups), 256, 0, s>>>(
-      a.m2pmax, a.S2p, a.m2, a.b2off, a.A, a.DT, r.dirty, r.cnt, r.list);
+// One Bellman-Ford round, in place on DT: intra-block step, then cross edges.
+hipError_t launch_share_round(const HierArgs& a, const ShareBlocks& b, int32_t nxe, const BfRound& r,
+                              hipStream_t s) {
+  const int ntm = b.bpmax / 128, ntc = (int)(a.S2p / 128);
+  k_bf_intra<<<dim3((unsigned)(ntm * ntc), (unsigned)b.nblk), 256, 0, s>>>(
+      b.bpmax, a.S2p, b.bsize, b.boff, b.A, a.DT, r.dirty, r.cnt, r.list);
   if (nxe > 0)
     k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, a.DT, r.dirty, r.dirty_next,
-                                             a.b2off, a.m2pmax, r.round, r.stamp, r.cnt_next,
+                                             b.boff, b.bpmax, r.round, r.stamp, r.cnt_next,
                                              r.list_next);
   return hipGetLastError();
 }
@@ -1007,11 +1101,14 @@ hipError_t launch_bf_intra(int32_t ngroups, int32_t m2pmax, int64_t S2p, const i
 }
 
 hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s) {
-  dim3 tg((unsigned)((a.S2p + 31) / 32), (unsigned)((a.V2p + 31) / 32));
-  k_transpose<<<tg, 256, 0, s>>>(DT, a.V2p, a.S2p, a.S2p, a.BG2, a.V2p);
+  dim3 tg((unsigned)((a.S2p + 31) / 32), (unsigned)(a.m2pmax / 32), (unsigned)a.ngroups);
+  k_panel_transpose<<<tg, 256, 0, s>>>(DT, a.S2p, a.m2pmax, a.m2, a.b2off, a.BG2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return compose_level2(a, nullptr, nullptr, nullptr, s);
+  HierArgs p = a;
+  p.d2ld = a.m2pmax;
+  p.d2pstride = a.S2p * a.m2pmax;
+  return compose_level2(p, nullptr, nullptr, nullptr, s);
 }
 
 }  // namespace spq

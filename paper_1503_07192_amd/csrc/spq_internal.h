@@ -92,11 +92,15 @@ struct HierArgs {
   int32_t *b2list, *b2rank, *m2;   // ngroups x Vgp, [V], [ngroups]
   const int32_t* b2off;            // [ngroups+1]
   u32 *R, *XT, *BG2, *H;
+  // BG2 as the first product reads it: dense (d2pstride = 0, leading
+  // dimension V2p), or one column panel per group (share: S2p x m2pmax,
+  // leading dimension d2ld = m2pmax, panels d2pstride apart)
+  int64_t d2ld = 0, d2pstride = 0;
   const int64_t* pairbase;         // ngroups x ngroups
   // share mode: rows of BG only from the first share_groups groups
   int32_t share_groups, S2;        // groups, level-2 sources (ids 0 .. S2-1)
   int64_t S2p;                     // S2 rounded up to 128
-  u32 *A, *DT;                     // A_S blocks; Bellman-Ford distances (V2p + 128 rows x S2p)
+  u32* DT;                         // Bellman-Ford distances (V2p + 128 rows x S2p)
   int4* xe;                        // directed cross edges
   int32_t* xcount;
   const int2* plist;               // composition: group pairs (S1, S2)
@@ -106,11 +110,19 @@ struct HierArgs {
   const int32_t* bglabel;
   u32 *cert_bad, *cert_mbg;
 };
-hipError_t launch_share_prepare(const HierArgs& a, hipStream_t s);
-// One Bellman-Ford round of the share.  dirty flags: per group, ntc = S2p /
-// 128 column tiles then one "any" word; cnt / list: per (group, tile) the
+// The share's Bellman-Ford blocks: runs of gpt consecutive groups, nblk of
+// them; boff[nblk+1] first level-2 id of each, bsize[nblk] level-2 vertices
+// of each; A: nblk x bpmax x bpmax (BG2 induced on each block, closed).
+struct ShareBlocks {
+  int32_t gpt, nblk, bpmax;
+  const int32_t *boff, *bsize;
+  u32* A;
+};
+hipError_t launch_share_prepare(const HierArgs& a, const ShareBlocks& b, hipStream_t s);
+// One Bellman-Ford round of the share.  dirty flags: per block, ntc = S2p /
+// 128 column tiles then one "any" word; cnt / list: per (block, tile) the
 // number of rows lowered since the last intra step (BF_ALL_ROWS: all) and
-// their local indices (m2pmax slots each); stamp: V2p x ntc round stamps.
+// their local indices (bpmax slots each); stamp: V2p x ntc round stamps.
 constexpr int32_t BF_ALL_ROWS = 0x7fffffff;
 constexpr int BF_LDS_TILES = 2048;  // column tiles a cross-edge workgroup tracks in LDS
 struct BfRound {
@@ -123,7 +135,8 @@ struct BfRound {
   u32* stamp;
   u32 round;
 };
-hipError_t launch_share_round(const HierArgs& a, int32_t nxe, const BfRound& r, hipStream_t s);
+hipError_t launch_share_round(const HierArgs& a, const ShareBlocks& b, int32_t nxe, const BfRound& r,
+                              hipStream_t s);
 hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s);
 hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
 // Flat method: per-BG-vertex layout terms, then the closed BG matrix (Vp x Vp)

@@ -63,7 +63,7 @@ class Stats(ctypes.Structure):
                 ("ms_bg_assembly", ctypes.c_float), ("ms_bg_apsp", ctypes.c_float),
                 ("graphs", ctypes.c_int32), ("reweights", ctypes.c_int32),
                 ("graph_nodes", ctypes.c_int64), ("groups3", ctypes.c_int32),
-                ("v_bg3", ctypes.c_int32)]
+                ("v_bg3", ctypes.c_int32), ("bf_block_groups", ctypes.c_int32)]
 
 
 _lib = None

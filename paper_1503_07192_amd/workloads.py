@@ -22,7 +22,8 @@ Workloads (random streams come from ``SeedSequence(150307192 + cfg)``):
                 to 4,096 components.
 * ``grid2048``  2048x2048 grid, 10% of the non-spanning-tree edges deleted,
                 lognormal(4,1) weights clipped to [1,1e5], 16,384 blocks of
-                16x16; the single-GPU share is components [0, 512).
+                16x16 numbered along a Z-order curve; the single-GPU share
+                is components [0, 512) (a 256 x 512-vertex region).
 """
 from __future__ import annotations
 
@@ -47,16 +48,37 @@ def grid_edges(rows: int, cols: int):
     return eu, ev
 
 
+def morton_code(r, c, bits: int = 16):
+    """Z-order (Morton) code of block (r, c): the bits of c and r interleaved,
+    c in the even bit positions."""
+    r = np.asarray(r, np.int64)
+    c = np.asarray(c, np.int64)
+    z = np.zeros(np.broadcast(r, c).shape, np.int64)
+    for b in range(bits):
+        z |= ((c >> b) & 1) << (2 * b)
+        z |= ((r >> b) & 1) << (2 * b + 1)
+    return z
+
+
 def block_partition(rows: int, cols: int, br: int, bc: int, sb: int = 1):
     """Blocks of br x bc vertices.  With sb == 1 the component of (r, c) is
     (r // br) * ceil(cols / bc) + c // bc (blocks row by row).  With sb > 1 the
     blocks are numbered super-block by super-block, each super-block being
     sb x sb blocks numbered row by row inside it, so that runs of sb*sb
-    consecutive ids are square regions."""
+    consecutive ids are square regions.  With sb == 0 the blocks are numbered
+    along a Z-order curve (ids = ranks of their Morton codes): every aligned
+    run of 4^j consecutive ids is a 2^j x 2^j square of blocks and every run
+    of 2 * 4^j a 2^j x 2^(j+1) rectangle, when the block grid is a power of
+    two on each side."""
     r = np.arange(rows)[:, None] // br
     c = np.arange(cols)[None, :] // bc
     nbr, nbc = -(-rows // br), -(-cols // bc)
-    if sb == 1:
+    if sb == 0:
+        br_, bc_ = np.meshgrid(np.arange(nbr), np.arange(nbc), indexing="ij")
+        rank = np.empty(nbr * nbc, np.int64)
+        rank[np.argsort(morton_code(br_.ravel(), bc_.ravel()), kind="stable")] = np.arange(nbr * nbc)
+        part = rank.reshape(nbr, nbc)[r, c].ravel().astype(np.int32)
+    elif sb == 1:
         part = (r * nbc + c).ravel().astype(np.int32)
     else:
         assert nbr % sb == 0 and nbc % sb == 0
@@ -161,7 +183,7 @@ def delaunay1m(queries: int = 0):
 
 
 def grid2048(queries: int = 10_000_000, side: int = 2048, blk: int = 16,
-             share_den: int = 32, sb: int = 8):
+             share_den: int = 32, sb: int = 0):
     """Grid with 10% of the edges deleted off a random spanning tree."""
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import minimum_spanning_tree
@@ -185,9 +207,9 @@ def grid2048(queries: int = 10_000_000, side: int = 2048, blk: int = 16,
     keep[drop] = False
     eu, ev = eu[keep], ev[keep]
     w = np.clip(np.rint(np.exp(4.0 + rw.standard_normal(len(eu)))), 1, 1e5).astype(np.int64)
-    # blocks numbered by super-blocks of sb x sb blocks: consecutive ids are
-    # square regions, and the share (the first k / share_den components) is a
-    # run of whole super-blocks
+    # blocks numbered along a Z-order curve (sb = 0; sb > 0: by super-blocks
+    # of sb x sb blocks): runs of consecutive ids are compact regions, and the
+    # share (the first k / share_den components) is one of them
     part, k = block_partition(side, side, blk, blk, sb)
     share_k = k // share_den
     share_v = np.flatnonzero(part < share_k).astype(np.int32)

@@ -666,15 +666,21 @@ def check_share(g, idx, share_comps, nsrc=None, rng=None, uniform=True):
         assert (got == spq.SPQ_BAD_PAIR).all()
 
 
+@pytest.mark.parametrize("blk", [-1, 0, 2, 3])
 @pytest.mark.parametrize("share_comps,gc", [(1, 1), (2, 2), (3, 2), (8, 4)])
-def test_share_small_grid(share_comps, gc):
+def test_share_small_grid(share_comps, gc, blk):
+    """Share builds with the Bellman-Ford over single groups (-1), blocks of
+    2 and 3 groups, and the automatic blocks (all 16 groups in one block at
+    gc = 1)."""
     rng = np.random.default_rng(40 + share_comps)
     eu, ev, w = W.random_grid(rng, 16, 16, keep=0.9, diag=0.2, wlo=0, whi=50)
     part, k = W.block_partition(16, 16, 4, 4, sb=2)
     g = dict(name="sharegrid", n=256, eu=eu, ev=ev, w=w, part=part, k=k)
-    idx = build(g, share_comps=share_comps, group_comps=gc)
+    idx = build(g, share_comps=share_comps, group_comps=gc, level3_groups=blk)
     st = spq.index_stats(idx)
     assert st["share_comps"] == share_comps and st["bf_rounds"] >= 1
+    if blk != 0:
+        assert st["bf_block_groups"] == min(max(blk, 1), st["ngroups"])
     lay = spq.index_layout(idx)
     check_layout(g, lay)
     check_components(g, idx, lay)
@@ -716,23 +722,29 @@ def test_share_size_groups(share_comps, gb):
     check_share(g, idx, share_comps, uniform=False)
 
 
-def test_share_random_partition():
+@pytest.mark.parametrize("blk", [-1, 2, 4])
+def test_share_random_partition(blk):
     rng = np.random.default_rng(77)
     eu, ev, w = W.random_grid(rng, 12, 14, keep=0.8, diag=0.3, wlo=0, whi=20)
     n, k = 168, 9
     g = dict(name="sharerand", n=n, eu=eu, ev=ev, w=w, part=W.random_partition(rng, n, k), k=k)
-    idx = build(g, share_comps=4, group_comps=2)
+    idx = build(g, share_comps=4, group_comps=2, level3_groups=blk)
     check_share(g, idx, 4)
 
 
-def test_share_grid2048_small_equals_full_two_level():
-    g = W.grid2048(queries=2000, side=256, blk=16, sb=4)
+@pytest.mark.parametrize("gc,blk", [(16, -1), (16, 0), (4, -1), (4, 2), (4, 4), (4, 5), (2, 8)])
+def test_share_grid2048_small_equals_full_two_level(gc, blk):
+    """The grid2048 recipe at 256x256 (256 components in Z-order, share =
+    components [0, 8)): the share's BG rows and answers equal the full
+    two-level index's, for groups of 16, 4 and 2 components and Bellman-Ford
+    blocks of 1 to 8 groups."""
+    g = W.grid2048(queries=2000, side=256, blk=16)
     full = build(g, bg_method=2, group_comps=16)
-    share = build(g, share_comps=g["share_k"], group_comps=16)
+    share = build(g, share_comps=g["share_k"], group_comps=gc, level3_groups=blk)
     st = spq.index_stats(share)
-    assert st["share_groups"] == 1
+    assert st["share_groups"] == -(-8 // gc)
     lay = spq.index_layout(share)
-    nrows = int(lay["bgoff"][16])
+    nrows = int(lay["bgoff"][st["share_groups"] * gc])
     V = st["v_bg"]
     assert np.array_equal(spq.index_bg_rows(share, 0, nrows, V), spq.index_bg_rows(full, 0, nrows, V))
     assert np.array_equal(run_queries(share, g["v1"], g["v2"]), run_queries(full, g["v1"], g["v2"]))

@@ -42,9 +42,26 @@ def test_superblock_numbering():
     assert grid[0, 4] == 1 and grid[4, 0] == 2 and grid[0, 8] == 4
 
 
+def test_morton_numbering():
+    part, k = W.block_partition(64, 64, 4, 4, sb=0)
+    assert k == 256 and np.array_equal(np.bincount(part), [16] * 256)
+    blocks = part.reshape(64, 64)[::4, ::4]
+    # aligned runs of 4^j ids are squares of 2^j x 2^j blocks, runs of 2 * 4^j
+    # are 2^j x 2^(j+1)
+    for run, (h, wd) in ((4, (2, 2)), (8, (2, 4)), (16, (4, 4)), (32, (4, 8)), (64, (8, 8))):
+        for j in range(0, k, run):
+            r, c = np.nonzero((blocks >= j) & (blocks < j + run))
+            assert (r.max() - r.min() + 1, c.max() - c.min() + 1) == (h, wd), (run, j)
+    assert np.array_equal(blocks[:2, :4], [[0, 1, 4, 5], [2, 3, 6, 7]])
+
+
 def test_grid2048_small_share():
-    g = W.grid2048(queries=1000, side=256, blk=16, sb=4)
+    g = W.grid2048(queries=1000, side=256, blk=16)
     assert g["k"] == 256 and g["share_k"] == 8
+    # the share: the first 8 components in Z-order, a 2 x 4 block region
+    sv = np.flatnonzero(g["part"] < 8)
+    assert len(sv) == 8 * 256
+    assert (sv // 256).max() < 32 and (sv % 256).max() < 64
     assert (g["part"][g["v1"]] < g["share_k"]).all()
     # connected: a spanning tree is kept
     import oracle
