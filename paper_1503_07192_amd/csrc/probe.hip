@@ -4,8 +4,9 @@
 // candidates per min3), so the peak is set by how many of each a CU issues
 // per clock.
 //   kind 0: v_add_u32 only    kind 1: v_min3_u32 only
-//   (eight independent chains per lane, four instructions per chain and
-//   iteration, so nothing waits on a result)
+//   (eight chains per lane, each four dependent instructions per iteration,
+//   emitted chain after chain: a wave waits on its own results and the
+//   other waves of the SIMD fill the gaps)
 //   kind 2: the production relaxation loop (minplus_lds of tiles.h) on LDS
 //   operands, no global memory inside the loop
 //   kind 3: the same relaxation pairs (relax2) on operands held in registers:

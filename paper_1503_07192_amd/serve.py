@@ -48,9 +48,11 @@ class Request:
 
 
 def poisson_stream(rng, rate_pairs: float, nreq: int, n: int, max_log2: float = 16.0,
-                   lo: int = 0, hi: int | None = None):
+                   lo: int = 0, hi: int | None = None, sources=None):
     """Open-loop arrivals: batch sizes floor(2**U(0, max_log2)) (1 .. 65,536),
-    uniform random pairs, exponential gaps at rate_pairs / E[batch] requests/s."""
+    uniform random pairs, exponential gaps at rate_pairs / E[batch] requests/s.
+    v1 is uniform in [lo, hi), or over the array `sources` when given (a
+    share's vertices); v2 uniform in [0, n)."""
     hi = n if hi is None else hi
     sizes = np.floor(2.0 ** rng.uniform(0.0, max_log2, nreq)).astype(np.int64)
     mean_b = (2.0 ** max_log2 - 1.0) / (max_log2 * np.log(2.0))  # E[2^U]
@@ -59,7 +61,10 @@ def poisson_stream(rng, rate_pairs: float, nreq: int, n: int, max_log2: float = 
     reqs = []
     for i in range(nreq):
         b = int(sizes[i])
-        v1 = rng.integers(lo, hi, b).astype(np.int32)
+        if sources is None:
+            v1 = rng.integers(lo, hi, b).astype(np.int32)
+        else:
+            v1 = np.asarray(sources)[rng.integers(0, len(sources), b)].astype(np.int32)
         v2 = rng.integers(0, n, b).astype(np.int32)
         reqs.append(Request(i, float(t[i]), v1, v2))
     return reqs
