@@ -5,7 +5,9 @@ workload itself and the fastest set is stored in a JSON cache keyed by the
 device architecture and a size class of the problem:
 
 * flat Floyd-Warshall on BG: tile side (64, 128) x interior K chunk (16, 32);
-* two-level BG: consecutive components per group (8 .. 256) x K chunk;
+* two-level BG: consecutive components per group (8 .. 256) x K chunk, and
+  on large BG (above 65,536 vertices) super-groups of 8 or 32 groups for the
+  level-3 closure of BG2 at 16 and 32 components per group;
 * share builds: consecutive components per group (8 .. 64) x groups per
   block of the Bellman-Ford over BG2 (1, 2, 4, 8), K chunk 16.
   Groups formed by size (``group_bg``) are not tried: on partitions numbered
@@ -66,6 +68,12 @@ def candidates(v_bg: int, k: int, share_comps: int):
     while cpg <= min(256, k):
         for kc in (16, 32):
             out.append({"bg_method": 2, "group_comps": cpg, "inner_kc": kc})
+        if v_bg > 65536 and cpg in (16, 32):
+            # BG2 closed by super-groups of fewer or more groups than the
+            # automatic choice (about 4,096 BG2 vertices each)
+            for l3 in (8, 32):
+                out.append({"bg_method": 2, "group_comps": cpg, "inner_kc": 16,
+                            "level3_groups": l3})
         cpg *= 2
     return out
 

@@ -453,38 +453,72 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
     for (int32_t c = 0; c < fs; c++) hd[(size_t)t * fs + c] = 1;
   HIP_TRY(hipMemcpyAsync(X->bfflag, hd.data(), sizeof(u32) * NB * fs, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(X->bfcnt, hc.data(), sizeof(int32_t) * NB * ntc, hipMemcpyHostToDevice, s));
-  u32* dcur = X->bfflag;
-  u32* dnext = X->bfflag + (int64_t)NB * fs;
-  int32_t* ccur = X->bfcnt;
-  int32_t* cnext = X->bfcnt + (int64_t)NB * ntc;
-  int32_t* lcur = X->bflist;
-  int32_t* lnext = X->bflist + (int64_t)NB * ntc * BP;
-  for (;;) {
-    if (++X->bf_rounds > 100000) return fail(SPQ_EDEVICE, "Bellman-Ford over blocks did not settle");
-    // executed relaxations: a dirty (block, tile) multiplies its row tiles by
-    // the rows listed for it
+  // Rounds are queued ahead of the host: a round needs only the flags the
+  // previous one left on the device, so up to BF_AHEAD rounds are in flight
+  // while the host reads back (pinned, behind an event) the flags of the
+  // oldest one, for the relaxation count and to see when nothing is dirty.
+  // The rounds queued after the one that leaves nothing dirty find no dirty
+  // tile and no cross edge to relax: they change nothing.
+  constexpr int BF_AHEAD = 3, SLOTS = BF_AHEAD + 1;
+  const size_t fwords = (size_t)NB * fs, cwords = (size_t)NB * ntc;
+  struct Readback {
+    u32* host = nullptr;
+    hipEvent_t ev[SLOTS] = {};
+    ~Readback() {
+      for (auto& e : ev)
+        if (e) {
+          (void)hipEventSynchronize(e);
+          (void)hipEventDestroy(e);
+        }
+      if (host) (void)hipHostFree(host);
+    }
+  } rb;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&rb.host), sizeof(u32) * SLOTS * (fwords + cwords)));
+  for (auto& e : rb.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  u32* dbuf[2] = {X->bfflag, X->bfflag + (int64_t)NB * fs};
+  int32_t* cbuf[2] = {X->bfcnt, X->bfcnt + (int64_t)NB * ntc};
+  int32_t* lbuf[2] = {X->bflist, X->bflist + (int64_t)NB * ntc * BP};
+  // executed relaxations of a round from the flags and counts it starts
+  // with: a dirty (block, tile) multiplies its row tiles by the rows listed
+  // for it
+  auto count = [&](const u32* fl, const int32_t* cn) {
     for (int32_t t = 0; t < NB; t++)
       for (int32_t c = 0; c < ntc; c++) {
-        const int32_t cc = hc[(size_t)t * ntc + c];
-        if (cc == 0 || !hd[(size_t)t * fs + c]) continue;
+        const int32_t cc = cn[(size_t)t * ntc + c];
+        if (cc == 0 || !fl[(size_t)t * fs + c]) continue;
         const int32_t kk = cc == spq::BF_ALL_ROWS ? X->h_bsize[t] : cc;
         X->relax_bg_exec += (double)((X->h_bsize[t] + 127) / 128) * 128.0 * 128.0 *
                             (double)round_up(kk, 16);
       }
-    const spq::BfRound r{dcur, dnext, ccur, lcur, cnext, lnext, X->bfstamp, (u32)X->bf_rounds};
-    HIP_TRY(hipMemsetAsync(dnext, 0, sizeof(u32) * NB * fs, s));
-    HIP_TRY(hipMemsetAsync(cnext, 0, sizeof(int32_t) * NB * ntc, s));
-    HIP_TRY(spq::launch_share_round(ha, blk, nxe, r, s));
-    HIP_TRY(hipMemcpyAsync(hd.data(), dnext, sizeof(u32) * NB * fs, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hc.data(), cnext, sizeof(int32_t) * NB * ntc, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::swap(dcur, dnext);
-    std::swap(ccur, cnext);
-    std::swap(lcur, lnext);
+  };
+  count(hd.data(), hc.data());
+  int64_t issued = 0, consumed = 0;
+  for (;;) {
+    while (issued - consumed < BF_AHEAD) {
+      if (issued >= 100000) return fail(SPQ_EDEVICE, "Bellman-Ford over blocks did not settle");
+      const int in = (int)(issued & 1), out = in ^ 1;
+      const spq::BfRound r{dbuf[in], dbuf[out], cbuf[in], lbuf[in], cbuf[out], lbuf[out],
+                           X->bfstamp, (u32)(issued + 1)};
+      HIP_TRY(hipMemsetAsync(dbuf[out], 0, sizeof(u32) * fwords, s));
+      HIP_TRY(hipMemsetAsync(cbuf[out], 0, sizeof(int32_t) * cwords, s));
+      HIP_TRY(spq::launch_share_round(ha, blk, nxe, r, s));
+      u32* slot = rb.host + (size_t)(issued % SLOTS) * (fwords + cwords);
+      HIP_TRY(hipMemcpyAsync(slot, dbuf[out], sizeof(u32) * fwords, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(slot + fwords, cbuf[out], sizeof(int32_t) * cwords, hipMemcpyDeviceToHost,
+                             s));
+      HIP_TRY(hipEventRecord(rb.ev[issued % SLOTS], s));
+      issued++;
+    }
+    HIP_TRY(hipEventSynchronize(rb.ev[consumed % SLOTS]));
+    const u32* fl = rb.host + (size_t)(consumed % SLOTS) * (fwords + cwords);
+    const int32_t* cn = reinterpret_cast<const int32_t*>(fl + fwords);
+    consumed++;
     bool any = false;
-    for (int32_t t = 0; t < NB; t++) any |= hd[(size_t)t * fs + ntc] != 0;
+    for (int32_t t = 0; t < NB; t++) any |= fl[(size_t)t * fs + ntc] != 0;
     if (!any) break;
+    count(fl, cn);  // the next round's work
   }
+  X->bf_rounds = (int32_t)consumed;
   for (int32_t a1 = 0; a1 < X->share_groups; a1++)
     for (int32_t a2 = 0; a2 < G; a2++) {
       X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * ((X->h_gV[a1] + 127) / 128) *

@@ -173,3 +173,17 @@ def test_autotune_cache_lookup(tmp_path, monkeypatch):
     assert {"bg_method": 1, "bg_tile": 128, "inner_kc": 16, "bg_pivot": 256} in c
     assert {"bg_method": 1, "bg_tile": 64, "inner_kc": 32, "bg_pivot": 256} in c
     assert all(o["bg_method"] == 2 for o in autotune.candidates(255422, 4096, 0))
+
+
+def test_poisson_stream_sources():
+    """v1 drawn from a share's vertex list when one is given, v2 from all."""
+    import numpy as np
+    from paper_1503_07192_amd import serve as SV
+    rng = np.random.default_rng(3)
+    src = np.array([5, 17, 40], np.int32)
+    reqs = SV.poisson_stream(rng, 1e6, 50, 100, max_log2=8.0, sources=src)
+    v1 = np.concatenate([r.v1 for r in reqs])
+    v2 = np.concatenate([r.v2 for r in reqs])
+    assert set(np.unique(v1)) <= set(src.tolist()) and len(np.unique(v1)) == 3
+    assert v2.min() >= 0 and v2.max() < 100 and len(np.unique(v2)) > 50
+    assert all(r.v1.dtype == np.int32 and len(r.v1) == len(r.v2) >= 1 for r in reqs)
