@@ -11,7 +11,7 @@ device architecture and a size class of the problem:
 * share builds: consecutive components per group (8 .. 64) x groups per
   block of the Bellman-Ford over BG2 (1, 2, 4, 8), K chunk 16.
   Groups formed by size (``group_bg``) are not tried: on partitions numbered
-  by recursive bisection or super-blocks they cut across the aligned runs of
+  by recursive bisection or along a Z-order curve they cut across the aligned runs of
   2^j components that make a group compact, and measured 1.5-10x slower.
 
 Every candidate must give bit-identical answers on a query sample (checked),

@@ -400,7 +400,9 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
     const u32* At = BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd +
                     (pstride ? 0 : b2off[s2]) + ti * 128;
     const u32* B = R + (int64_t)s1 * m2pmax * Vgp + tj * 128;
-    mp_stream128<true>(c, At, ldd, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB);
+    // a panel holds INF past its group's B2 vertices: no column mask there
+    mp_stream128<true>(c, At, ldd, B, Vgp, (ka + 15) / 16 * 16, ka, pstride ? 128 : mb - ti * 128,
+                       sA, sB);
   }
   u32* out = XT + (slot * m2pmax + ti * 128) * Vgp + tj * 128;
   const int tx = tid_x(), ty = tid_y();
