@@ -411,6 +411,16 @@ def main():
         "served": served,
         "single_query_us_p50": float(np.percentile(lat, 50)),
         "single_query_us_p99": float(np.percentile(lat, 99)),
+        # the batched forms against the plain GPU path (one launch per
+        # component; one pair per query launch, back to back)
+        "speedup_vs_plain": {
+            "components": plain_st["ms_components"] /
+                          max(1e-9, float(np.median([r["ms_components"] for r in recs]))),
+            "queries": (q / (np.median(mq) * 1e-3)) / (1e6 / float(np.percentile(lat, 50)))},
+        # context only: the paper's cluster (300 nodes, 2x Xeon E5-2670 + 2x
+        # Tesla M2090 each) answered one query at a time in 0.25-2 ms on an
+        # unspecified 256k-vertex planar graph, 500-4,000 queries/s
+        "paper_context_queries_per_s": [500, 4000],
         "roofline": {"bound": "alu", "kernel": kernel,
                      "achieved": inner_rate / 1e12, "peak": RELAX_PEAK / 1e12,
                      "unit": "Trelax/s", "frac": inner_rate / RELAX_PEAK,

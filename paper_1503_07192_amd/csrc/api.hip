@@ -224,10 +224,13 @@ struct spq_index {
   int64_t S2p = 0;
   u32 *A = nullptr, *DT = nullptr, *bfflag = nullptr, *bfstamp = nullptr;
   int32_t *bfcnt = nullptr, *bflist = nullptr;
-  // Bellman-Ford blocks (runs of bgpt groups): first level-2 id, size
+  // Bellman-Ford blocks (runs of groups): first level-2 id, size, first
+  // group, and the block of every group
   int32_t bgpt = 1, nblk = 0, bpmax = 0;
-  std::vector<int32_t> h_boff, h_bsize;
-  int32_t *boff = nullptr, *bsize = nullptr;
+  std::vector<int32_t> h_boff, h_bsize, h_bfirst, h_gblk;
+  int32_t *boff = nullptr, *bsize = nullptr, *bfirst = nullptr, *gblk = nullptr;
+  std::vector<int32_t> h_gfirst;  // first component of every group
+  bool group_bg = false;          // groups formed by size
   int4* xe = nullptr;
   int32_t* xcount = nullptr;
   // exactness certificate (total weight >= INF)
@@ -282,7 +285,7 @@ struct spq_index {
                     vrec, gT,    grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
                     bgvert, label, bglabel, cert, A,    DT,    bfflag,  bfstamp, bfcnt, bflist,
-                    xe, xcount, boff, bsize,
+                    xe, xcount, boff, bsize, bfirst, gblk,
                     eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
                     M3, R3, XT3, BG3, plist, plist3, rowptr, adj, adeg, w_copy};
     for (void* p : ptrs) pool_release(p);
@@ -385,26 +388,42 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
     while (bgpt * 2 <= G && bgpt * 2 * avg <= 1024.0 * 1.41) bgpt *= 2;
   }
   X->bgpt = bgpt;
-  X->nblk = (G + bgpt - 1) / bgpt;
+  // Blocks: the groups that start in each run of bgpt x (components per
+  // group) consecutive components, so that a group cut in halves does not
+  // shift the later blocks (groups formed by size: runs of bgpt groups).
+  X->h_gblk.resize(G);
+  for (int32_t g = 0; g < G; g++)
+    X->h_gblk[g] = X->group_bg ? g / bgpt : (int32_t)(X->h_gfirst[g] / ((int64_t)bgpt * X->cpg));
+  X->nblk = X->h_gblk[G - 1] + 1;
   if (X->nblk > 65535) return fail(SPQ_EINVAL, "more than 65,535 Bellman-Ford blocks");
   const int32_t NB = X->nblk;
+  X->h_bfirst.assign(NB + 1, G);
+  for (int32_t g = G - 1; g >= 0; g--) X->h_bfirst[X->h_gblk[g]] = g;
+  bool multi = false;
   X->h_boff.assign(NB + 1, 0);
   X->h_bsize.assign(NB, 0);
   int32_t bmax = 0;
   for (int32_t t = 0; t < NB; t++) {
-    X->h_boff[t] = X->h_b2off[t * bgpt];
-    X->h_bsize[t] = X->h_b2off[std::min((t + 1) * bgpt, G)] - X->h_boff[t];
+    if (X->h_bfirst[t] >= X->h_bfirst[t + 1]) return fail(SPQ_EDEVICE, "internal: empty block");
+    multi |= X->h_bfirst[t + 1] - X->h_bfirst[t] > 1;
+    X->h_boff[t] = X->h_b2off[X->h_bfirst[t]];
+    X->h_bsize[t] = X->h_b2off[X->h_bfirst[t + 1]] - X->h_boff[t];
     bmax = std::max(bmax, X->h_bsize[t]);
   }
   X->h_boff[NB] = X->V2;
   X->bpmax = (int32_t)std::max<int64_t>(128, round_up(bmax, 128));
   const int32_t BP = X->bpmax;
-  if (bgpt > 1) X->relax_bg_exec += NB * spq::dense_fw_exec_relax(BP / 128, 128, X->cpivot);
+  if (multi) X->relax_bg_exec += NB * spq::dense_fw_exec_relax(BP / 128, 128, X->cpivot);
   HIP_TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
   HIP_TRY(dalloc(&X->boff, NB + 1));
   HIP_TRY(dalloc(&X->bsize, NB));
   HIP_TRY(hipMemcpyAsync(X->boff, X->h_boff.data(), sizeof(int32_t) * (NB + 1), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(X->bsize, X->h_bsize.data(), sizeof(int32_t) * NB, hipMemcpyHostToDevice, s));
+  HIP_TRY(dalloc(&X->bfirst, NB + 1));
+  HIP_TRY(dalloc(&X->gblk, G));
+  HIP_TRY(hipMemcpyAsync(X->bfirst, X->h_bfirst.data(), sizeof(int32_t) * (NB + 1), hipMemcpyHostToDevice,
+                         s));
+  HIP_TRY(hipMemcpyAsync(X->gblk, X->h_gblk.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
   HIP_TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
   HIP_TRY(make_pairs(X->share_groups, G, false, (int64_t)X->m2pmax * Vgp, X->h_elems, &X->plist,
                      &X->npairs,
@@ -439,7 +458,7 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   ha.plist = X->plist; ha.npairs = X->npairs; ha.chunk = X->chunk;
   ha.share_groups = X->share_groups; ha.S2 = X->S2; ha.S2p = X->S2p; ha.DT = X->DT;
   ha.xe = X->xe; ha.xcount = X->xcount;
-  const spq::ShareBlocks blk{bgpt, NB, BP, X->boff, X->bsize, X->A};
+  const spq::ShareBlocks blk{NB, BP, multi, X->bfirst, X->gblk, X->boff, X->bsize, X->A};
   HIP_TRY(spq::launch_share_prepare(ha, blk, s));
   int32_t nxe = 0;
   HIP_TRY(hipMemcpyAsync(&nxe, X->xcount, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -794,7 +813,43 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     }
   } else {
     for (int32_t c = 0; c < k; c += cpg) gstart.push_back(c);
+    // Every group matrix is padded to the widest group (whole 128-tiles).
+    // In a share build, when a few groups reach one tile past almost all the
+    // others (grid2048, 16 components per group: 6 of 1,024 above 896 BG
+    // vertices), they are cut in halves of consecutive components until they
+    // fit the tile count of the 99th percentile, so the others are not
+    // padded for them.  (The Bellman-Ford blocks follow the component
+    // ranges, not the group count, so the cut shifts none of them.)
+    if (X->method == 2 && share_comps > 0 && gstart.size() >= 100) {
+      std::vector<int32_t> sorted;
+      for (size_t g = 0; g < gstart.size(); g++)
+        sorted.push_back(X->h_bgoff[g + 1 < gstart.size() ? gstart[g + 1] : k] -
+                         X->h_bgoff[gstart[g]]);
+      std::sort(sorted.begin(), sorted.end());
+      const int64_t cap = round_up(std::max<int32_t>(1, sorted[(sorted.size() * 99) / 100]), 128);
+      if (cap < round_up(sorted.back(), 128)) {
+        std::vector<int32_t> cut;
+        std::vector<std::pair<int32_t, int32_t>> todo;
+        for (size_t g = 0; g < gstart.size(); g++) {
+          todo.emplace_back(gstart[g], g + 1 < gstart.size() ? gstart[g + 1] : k);
+          while (!todo.empty()) {
+            const auto r = todo.back();
+            todo.pop_back();
+            if (r.second - r.first > 1 && X->h_bgoff[r.second] - X->h_bgoff[r.first] > cap) {
+              const int32_t mid = r.first + (r.second - r.first) / 2;
+              todo.emplace_back(mid, r.second);  // the lower half first
+              todo.emplace_back(r.first, mid);
+            } else {
+              cut.push_back(r.first);
+            }
+          }
+        }
+        gstart.swap(cut);
+      }
+    }
   }
+  X->group_bg = X->method == 2 && group_bg > 0;
+  X->h_gfirst = gstart;
   X->ngroups = (int32_t)gstart.size();
   gstart.push_back(k);
   // group pairs index launch grids (up to ngroups^2 workgroups per launch of

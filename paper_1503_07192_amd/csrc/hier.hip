@@ -658,8 +658,9 @@ __global__ void k_hier_row(int32_t x, int32_t swap, int32_t V, int32_t ngroups,
 // Distances from the level-2 boundary vertices of the share groups (the
 // first share_groups groups; their level-2 ids are 0 .. S2-1) to all level-2
 // vertices, by Bellman-Ford over blocks of consecutive groups on BG2, without
-// building BG2.  A block T is a run of gpt groups (gpt = 1: every group is a
-// block); A_T = BG2 induced on T's level-2 vertices (d_S between the B2
+// building BG2.  A block T is a run of consecutive groups (one group: the
+// Bellman-Ford over groups); A_T = BG2 induced on T's level-2 vertices (d_S
+// between the B2
 // vertices of one group S, the G edges between groups of T), closed.  DT[b][i]
 // (row b = any level-2 id, column i = share source) alternates
 //   intra-block:  DT[T] = min(DT[T], A_T (x) DT[T])   (A_T closed: one product
@@ -673,13 +674,14 @@ __global__ void k_hier_row(int32_t x, int32_t swap, int32_t V, int32_t ngroups,
 
 // A_T before its closure (bpmax x bpmax per block, local level-2 indices):
 // d_S between the B2 vertices of one group, 0 on the diagonal, INF elsewhere
-// and on the padding.  gpt = 1: A_T = d_S on B2(S), already closed.
-__global__ void k_blk_init(int32_t Vgp, int32_t bpmax, int32_t gpt, int32_t ngroups,
+// and on the padding.  Block t holds groups [bfirst[t], bfirst[t+1]); a block
+// of one group: A_T = d_S on B2(S), already closed.
+__global__ void k_blk_init(int32_t Vgp, int32_t bpmax, const int32_t* __restrict__ bfirst,
                            const int32_t* __restrict__ b2off, const int32_t* __restrict__ b2list,
                            const u32* __restrict__ Mg, u32* __restrict__ A) {
   const int t = blockIdx.y;
   const int32_t p = blockIdx.x;
-  const int32_t g0 = t * gpt, g1 = min(g0 + gpt, ngroups);
+  const int32_t g0 = bfirst[t], g1 = bfirst[t + 1];
   const int32_t base = b2off[g0], size = b2off[g1] - base;
   u32* out = A + ((int64_t)t * bpmax + p) * bpmax;
   int32_t lo = 0, hi = 0;
@@ -701,7 +703,8 @@ __global__ void k_blk_init(int32_t Vgp, int32_t bpmax, int32_t gpt, int32_t ngro
 __global__ void k_blk_edges(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
                             const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
                             const int32_t* __restrict__ local, const int32_t* __restrict__ bgoff,
-                            const int32_t* __restrict__ grp, int32_t gpt,
+                            const int32_t* __restrict__ grp, const int32_t* __restrict__ gblk,
+                            const int32_t* __restrict__ bfirst,
                             const int32_t* __restrict__ b2off, const int32_t* __restrict__ b2rank,
                             int32_t bpmax, u32* __restrict__ A) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
@@ -710,8 +713,8 @@ __global__ void k_blk_edges(int64_t m, const int32_t* __restrict__ eu, const int
     const int32_t cu = comp[u], cv = comp[v];
     if (cu == cv) continue;
     const int32_t su = grp[cu], sv = grp[cv];
-    if (su == sv || su / gpt != sv / gpt) continue;
-    const int32_t t = su / gpt, base = b2off[t * gpt];
+    if (su == sv || gblk[su] != gblk[sv]) continue;
+    const int32_t t = gblk[su], base = b2off[bfirst[t]];
     const int64_t a = b2off[su] + b2rank[bgoff[cu] + local[u]] - base;
     const int64_t b = b2off[sv] + b2rank[bgoff[cv] + local[v]] - base;
     u32* At = A + (int64_t)t * bpmax * bpmax;
@@ -811,7 +814,7 @@ __global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
 __global__ void k_cross_collect(int64_t m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
                                 const int32_t* __restrict__ w, const int32_t* __restrict__ comp,
                                 const int32_t* __restrict__ local, const int32_t* __restrict__ bgoff,
-                                const int32_t* __restrict__ grp, int32_t gpt,
+                                const int32_t* __restrict__ grp, const int32_t* __restrict__ gblk,
                                 const int32_t* __restrict__ b2off,
                                 const int32_t* __restrict__ b2rank, int32_t* __restrict__ count,
                                 int4* __restrict__ xe) {
@@ -821,7 +824,7 @@ __global__ void k_cross_collect(int64_t m, const int32_t* __restrict__ eu, const
     const int32_t cu = comp[u], cv = comp[v];
     if (cu == cv) continue;
     const int32_t su = grp[cu], sv = grp[cv];
-    const int32_t tu = su / gpt, tv = sv / gpt;  // blocks
+    const int32_t tu = gblk[su], tv = gblk[sv];  // blocks
     if (tu == tv) continue;
     const int32_t a = b2off[su] + b2rank[bgoff[cu] + local[u]];
     const int32_t b = b2off[sv] + b2rank[bgoff[cv] + local[v]];
@@ -1062,13 +1065,13 @@ namespace spq {
 hipError_t launch_share_prepare(const HierArgs& a, const ShareBlocks& b, hipStream_t s) {
   k_r_gather<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(a.Vgp, a.m2pmax, a.m2,
                                                                            a.b2list, a.Mg, a.R);
-  k_blk_init<<<dim3((unsigned)b.bpmax, (unsigned)b.nblk), 256, 0, s>>>(a.Vgp, b.bpmax, b.gpt,
-                                                                       a.ngroups, a.b2off, a.b2list,
-                                                                       a.Mg, b.A);
-  if (b.gpt > 1) {
+  k_blk_init<<<dim3((unsigned)b.bpmax, (unsigned)b.nblk), 256, 0, s>>>(a.Vgp, b.bpmax, b.bfirst,
+                                                                       a.b2off, a.b2list, a.Mg,
+                                                                       b.A);
+  if (b.multi) {
     if (a.m > 0)
       k_blk_edges<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
-                                               b.gpt, a.b2off, a.b2rank, b.bpmax, b.A);
+                                               b.gblk, b.bfirst, a.b2off, a.b2rank, b.bpmax, b.A);
     hipError_t e = launch_dense_fw_batch(b.A, b.bpmax, 128, b.bpmax / 128, b.nblk,
                                          (int64_t)b.bpmax * b.bpmax, s, nullptr, a.kc, a.pivot);
     if (e != hipSuccess) return e;
@@ -1076,7 +1079,7 @@ hipError_t launch_share_prepare(const HierArgs& a, const ShareBlocks& b, hipStre
   k_dt_init<<<(unsigned)a.V2p, 256, 0, s>>>(a.V2, a.S2, a.S2p, b.nblk, b.boff, b.bpmax, b.A, a.DT);
   if (a.m > 0)
     k_cross_collect<<<hblocks(a.m), 256, 0, s>>>(a.m, a.eu, a.ev, a.w, a.comp, a.local, a.bgoff, a.grp,
-                                                 b.gpt, a.b2off, a.b2rank, a.xcount, a.xe);
+                                                 b.gblk, a.b2off, a.b2rank, a.xcount, a.xe);
   return hipGetLastError();
 }
 

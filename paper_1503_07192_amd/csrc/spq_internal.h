@@ -110,12 +110,15 @@ struct HierArgs {
   const int32_t* bglabel;
   u32 *cert_bad, *cert_mbg;
 };
-// The share's Bellman-Ford blocks: runs of gpt consecutive groups, nblk of
-// them; boff[nblk+1] first level-2 id of each, bsize[nblk] level-2 vertices
-// of each; A: nblk x bpmax x bpmax (BG2 induced on each block, closed).
+// The share's Bellman-Ford blocks: runs of consecutive groups, nblk of them
+// (block t = groups [bfirst[t], bfirst[t+1]), gblk[group] = its block;
+// multi: some block holds more than one group); boff[nblk+1] first level-2
+// id of each, bsize[nblk] level-2 vertices of each; A: nblk x bpmax x bpmax
+// (BG2 induced on each block, closed).
 struct ShareBlocks {
-  int32_t gpt, nblk, bpmax;
-  const int32_t *boff, *bsize;
+  int32_t nblk, bpmax;
+  bool multi;
+  const int32_t *bfirst, *gblk, *boff, *bsize;
   u32* A;
 };
 hipError_t launch_share_prepare(const HierArgs& a, const ShareBlocks& b, hipStream_t s);

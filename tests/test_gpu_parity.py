@@ -127,6 +127,24 @@ def check_queries(g, idx, v1, v2):
         (v1[bad[0]], v2[bad[0]]), got[bad[0]], want[bad[0]])
 
 
+def check_pairs_by_source(g, idx, v1, v2, chunk=100):
+    """check_queries on a large sample: one Dijkstra per distinct source,
+    `chunk` sources at a time (the distance rows of a 4M-vertex graph are
+    32 MB each)."""
+    v1 = np.asarray(v1, np.int32)
+    v2 = np.asarray(v2, np.int32)
+    got = run_queries(idx, v1, v2)
+    src, inv = np.unique(v1, return_inverse=True)
+    for c0 in range(0, len(src), chunk):
+        D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], src[c0:c0 + chunk])
+        sel = np.flatnonzero((inv >= c0) & (inv < c0 + chunk))
+        want = clamp32(D[inv[sel] - c0, v2[sel]])
+        bad = np.flatnonzero(got[sel] != want)
+        assert len(bad) == 0, "first mismatch pair %s: got %d want %d" % (
+            (v1[sel[bad[0]]], v2[sel[bad[0]]]), got[sel[bad[0]]], want[bad[0]])
+    return len(src)
+
+
 def all_pairs(n):
     a, b = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     return a.ravel().astype(np.int32), b.ravel().astype(np.int32)
@@ -601,7 +619,7 @@ def check_layout_fast(g, lay, flag):
 
 
 def test_delaunay1m_two_level():
-    g = W.delaunay1m()
+    g = W.delaunay1m(queries=2000)
     print("delaunay1m: n=%d m=%d k=%d" % (g["n"], g["m"], g["k"]), flush=True)
     idx = build(g, tune_cache=TUNE_CACHE)   # the benchmark's configuration
     st = spq.index_stats(idx)
@@ -618,21 +636,24 @@ def test_delaunay1m_two_level():
     rng = np.random.default_rng(31)
     check_components_all(g, idx, lay)
     check_bg_rows(g, idx, lay, np.concatenate([[0, st["v_bg"] - 1], rng.integers(0, st["v_bg"], 30)]))
-    # source-grouped query sample: 100 sources x 20 targets, plus same-vertex pairs
-    src = rng.integers(0, g["n"], 100).astype(np.int32)
-    v1 = np.repeat(src, 20)
+    # source-grouped query sample: 1,000 sources x 16 targets (the first of
+    # each the source itself), then the workload's own first 2,000 pairs
+    src = rng.integers(0, g["n"], 1000).astype(np.int32)
+    v1 = np.repeat(src, 16)
     v2 = rng.integers(0, g["n"], v1.size).astype(np.int32)
-    v2[::20] = v1[::20]
-    got = run_queries(idx, v1, v2)
-    D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], src)
-    want = clamp32(D[np.repeat(np.arange(100), 20), v2])
+    v2[::16] = v1[::16]
+    check_pairs_by_source(g, idx, v1, v2)
+    check_pairs_by_source(g, idx, g["v1"], g["v2"])
+    got = run_queries(idx, v1[:2000], v2[:2000])
+    D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], src[:125])
+    want = clamp32(D[np.repeat(np.arange(125), 16), v2[:2000]])
     assert np.array_equal(got, want)
     # the default group size (64 groups, level 3 on 30,021 level-2 vertices)
     idx.free()
     dflt = build(g)
     sd = spq.index_stats(dflt)
     assert sd["ngroups"] == 64 and sd["groups3"] > 1
-    assert np.array_equal(run_queries(dflt, v1, v2), want)
+    assert np.array_equal(run_queries(dflt, v1[:2000], v2[:2000]), want)
 
 
 # --------------------------------------------------- share (one GPU's rows)
@@ -758,7 +779,9 @@ def test_grid2048_share_full_size():
     st = spq.index_stats(idx)
     print({k: st[k] for k in ("v_bg", "ngroups", "v_bg2", "share_groups", "bf_rounds", "bg_bytes",
                               "ms_components", "ms_bg_apsp")}, flush=True)
-    assert st["v_bg"] == 883_500 and st["share_groups"] == 512 // (g["k"] // st["ngroups"])
+    # groups of the tuned size, a few of them cut in halves (one 128-tile
+    # wider than the 99th percentile): at least k / 16 groups, 32 for the share
+    assert st["v_bg"] == 883_500 and st["ngroups"] >= g["k"] // 16 and st["share_groups"] >= 32
     rng = np.random.default_rng(44)
     lay = spq.index_layout(idx)
     flag = oracle.boundary(g["n"], g["eu"], g["ev"], g["part"])
@@ -768,13 +791,14 @@ def test_grid2048_share_full_size():
     check_bg_rows(g, idx, lay, np.concatenate([[0, bgend - 1], rng.integers(0, bgend, 20)]))
     out = run_queries(idx, g["v1"], g["v2"])
     assert (out >= 0).all()
-    src = g["v1"][:60]
-    D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], src)
-    tgt = g["v2"][np.arange(60 * 20).reshape(60, 20) % len(g["v2"])]
-    sub = run_queries(idx, np.repeat(src, 20), tgt.ravel())
-    assert np.array_equal(sub, clamp32(D[np.repeat(np.arange(60), 20), tgt.ravel()]))
-    # the batch's own first pairs
-    assert np.array_equal(out[:60], clamp32(D[np.arange(60), g["v2"][:60]]))
+    # 500 share sources x 16 targets, then the batch's own first 2,000 pairs
+    sv = np.flatnonzero(g["part"] < g["share_k"]).astype(np.int32)
+    src = sv[rng.integers(0, len(sv), 500)]
+    v1 = np.repeat(src, 16)
+    v2 = rng.integers(0, g["n"], v1.size).astype(np.int32)
+    check_pairs_by_source(g, idx, v1, v2)
+    check_pairs_by_source(g, idx, g["v1"][:2000], g["v2"][:2000])
+    assert np.array_equal(out[:2000], run_queries(idx, g["v1"][:2000], g["v2"][:2000]))
 
 
 def test_cached_memory_release_and_rebuild():
@@ -842,3 +866,50 @@ def test_big_components_closed_in_one_batch():
     v1 = rng2.integers(0, g["n"], 3000).astype(np.int32)
     v2 = rng2.integers(0, g["n"], 3000).astype(np.int32)
     check_queries(g, idx, v1, v2)
+
+
+def wide_group_graph():
+    """48x48 grid: components 0 and 1 interleave on a 12x12 corner as a
+    checkerboard (every vertex on the boundary, 72 each), the rest are 2x4
+    blocks: in groups of two components every group fits one 128-tile but
+    the first (144 BG vertices)."""
+    rng = np.random.default_rng(91)
+    R = C = 48
+    eu, ev, w = W.random_grid(rng, R, C, keep=0.95, diag=0.1, wlo=1, whi=60)
+    r, c = np.divmod(np.arange(R * C), C)
+    part = np.empty(R * C, np.int32)
+    corner = (r < 12) & (c < 12)
+    part[corner] = ((r + c) % 2)[corner]
+    top = ~corner & (r < 12)
+    part[top] = 2 + (r[top] // 2) * 9 + (c[top] - 12) // 4
+    low = r >= 12
+    part[low] = 2 + 54 + ((r[low] - 12) // 2) * 12 + c[low] // 4
+    k = int(part.max()) + 1
+    assert k == 272 and np.bincount(part).min() >= 8
+    return dict(name="widegroup", n=R * C, eu=eu, ev=ev, w=w, part=part, k=k)
+
+
+@pytest.mark.parametrize("blk", [1, 4])
+def test_share_cuts_the_wide_group(blk):
+    """A share build in groups of two components (136 groups): the one group
+    a tile wider than all others is cut into its two components, the
+    Bellman-Ford blocks still cover the same runs of components, and the
+    share's BG rows and answers equal the full two-level index's (which keeps
+    the wide group) and Dijkstra's."""
+    g = wide_group_graph()
+    full = build(g, bg_method=2, group_comps=2, level3_groups=-1)
+    fst = spq.index_stats(full)
+    assert fst["ngroups"] == 136 and fst["v_bg_padded"] == 256
+    share = build(g, share_comps=40, group_comps=2, level3_groups=blk)
+    st = spq.index_stats(share)
+    assert st["ngroups"] == 137 and st["v_bg_padded"] == 128 and st["share_groups"] == 21, st
+    lay = spq.index_layout(share)
+    nrows = int(lay["bgoff"][40])
+    V = st["v_bg"]
+    assert np.array_equal(spq.index_bg_rows(share, 0, nrows, V), spq.index_bg_rows(full, 0, nrows, V))
+    sv = share_vertices(g, 40)
+    rng = np.random.default_rng(6)
+    v1 = sv[rng.integers(0, len(sv), 20000)]
+    v2 = rng.integers(0, g["n"], 20000).astype(np.int32)
+    assert np.array_equal(run_queries(share, v1, v2), run_queries(full, v1, v2))
+    check_queries(g, share, v1[:2000], v2[:2000])
