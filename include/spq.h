@@ -59,7 +59,11 @@ typedef struct {
   int32_t bg_method;   /* 0 auto (flat up to 32,768 BG vertices), 1 flat
                           Floyd-Warshall on all of BG, 2 two-level */
   int32_t group_comps; /* two-level: consecutive components per group
-                          (0 = auto: about 4,096 BG vertices per group) */
+                          (0 = auto: about 4,096 BG vertices per group).  A
+                          share build with 100 groups or more cuts a group
+                          that is wider (in 128-tiles of BG vertices) than
+                          the 99th percentile into halves of consecutive
+                          components until it fits */
   int32_t share_comps; /* 0: the whole index.  s > 0: one GPU's share, the
                           paper's APSP_BG(C) for C in [0, s) only (Alg. 1,
                           Phase 3, done at the nodes owning those C): BG
