@@ -344,7 +344,7 @@ def main():
 
     # continuous batching on a resident index of the same workload, after the
     # timed region: open-loop Poisson arrivals of 1 .. 65,536 pairs, slots and
-    # memory-gated admission (serve.py); every checked request must give the
+    # memory-gated admission (the library's server); every checked request must give the
     # same answers alone as in the mix
     served = None
     if not args.no_serve:
@@ -355,13 +355,14 @@ def main():
                 if st["share_comps"] else None)
         rng = np.random.default_rng(W.SEED_BASE + 5)
         mem = 64 << 20
-        ex = SV.GpuExecutor(idx, 4, mem)
-        served = {"slots": 4, "slot_pairs": 65536, "mem_mib": 64, "rates": {}}
+        served = {"server": "spq_server (native worker thread)", "slots": 4,
+                  "slot_pairs": 65536, "mem_mib": 64, "rates": {}}
         for rate, nreq in ((1e6, 300), (1e7, 1000)):
             reqs = SV.poisson_stream(rng, rate, nreq, g["n"], sources=srcs)
-            sched = SV.Scheduler(ex, 4, 65536, mem)
-            done = SV.run_stream(sched, reqs)
-            res = SV.summarize(done, sched)
+            server = spq.Server(idx, 4, 65536, mem)
+            done = SV.run_native(server, reqs)
+            res = SV.summarize(done, server_stats=server.stats())
+            server.close()
             same = sum(int(np.array_equal(spq.query_batch(idx, dev(r.v1), dev(r.v2)).cpu().numpy(),
                                           r.result)) for r in reqs[:100])
             res["alone_equals_mix"] = "%d/%d" % (same, min(100, len(reqs)))

@@ -300,6 +300,57 @@ spq_status spq_reweight_index(spq_index* idx, const int32_t* w, void* stream);
 spq_status spq_query_paths(const spq_index* idx, int64_t q, const int32_t* v1, const int32_t* v2,
                            int32_t max_len, int32_t* paths, int32_t* lens, void* stream);
 
+/*
+ * Continuous-batching server on a built index.  Answering many queries at
+ * once is the extension the paper names as future work (Section 5); every
+ * launch runs Algorithm 2 (spq_query_batch) on a batch of pairs.
+ *
+ * Requests (HOST arrays of pairs) are queued in submission order.  A worker
+ * thread of the server coalesces the requests at the head of the queue into
+ * launches on `slots` HIP streams (at most slot_pairs pairs per launch) and
+ * writes each request's answers into its own output array.  The buffers of a
+ * launch (12 bytes per pair: v1, v2, answer) are taken from one device pool
+ * and one pinned host pool of mem_bytes each, both allocated at creation; a
+ * launch starts only when a slot is free and its buffers can be allocated in
+ * the pools (first fit), and returns them when it completes.  A request is
+ * cut into several launches only when the room left in a launch cannot hold
+ * it whole.  The answers are those of spq_query_batch on the same pairs.
+ *
+ *   spq_server_create   slots in [1, 64], slot_pairs >= 1, mem_bytes in
+ *                       [256 B, 64 GiB] (rounded down to 256 B); waits for
+ *                       the index build.  The index must outlive the
+ *                       server and must not be reweighted while it runs.
+ *                       Errors: SPQ_EINVAL, SPQ_ENOMEM, SPQ_EDEVICE.
+ *   spq_server_submit   queues q pairs (q >= 0; q = 0 completes at once);
+ *                       v1, v2 and out stay owned by the caller and must stay
+ *                       valid, and out unread, until the request completes.
+ *                       *ticket identifies the request.  Thread-safe.
+ *                       Errors: SPQ_EINVAL, or the server's first device
+ *                       error once one happened (nothing queued).
+ *   spq_server_poll     *done = 1 once every answer of the ticket's request is
+ *                       in its out array (wait != 0 blocks until then); then
+ *                       *latency_s (may be NULL) = completion time minus
+ *                       submission time, and the ticket is released (a later
+ *                       poll of it returns SPQ_EINVAL).  Thread-safe.
+ *                       Errors: SPQ_EINVAL (unknown ticket), the server's
+ *                       first device error for a request it did not finish.
+ *   spq_server_stats    launches made and pairs launched so far (either
+ *                       pointer may be NULL).
+ *   spq_server_destroy  answers every request submitted so far, then stops
+ *                       the worker and frees the pools; NULL is ok.
+ * After a device error the server answers nothing more: requests not yet
+ * complete report the error, and so does every later submission.
+ */
+typedef struct spq_server spq_server;
+spq_status spq_server_create(const spq_index* idx, int32_t slots, int64_t slot_pairs,
+                             int64_t mem_bytes, spq_server** out);
+spq_status spq_server_submit(spq_server* srv, int64_t q, const int32_t* v1, const int32_t* v2,
+                             int32_t* out, int64_t* ticket);
+spq_status spq_server_poll(spq_server* srv, int64_t ticket, int32_t wait, int32_t* done,
+                           double* latency_s);
+spq_status spq_server_stats(spq_server* srv, int64_t* launches, int64_t* pairs);
+void spq_server_destroy(spq_server* srv);
+
 /* Sizes, work counts and per-phase device times (waits for the build). */
 spq_status spq_index_stats(const spq_index* idx, spq_stats* st);
 

@@ -14,7 +14,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libspq.so")
-SOURCES = ["api.hip", "kernels.hip", "fw.hip", "hier.hip", "range.hip", "probe.hip"]
+SOURCES = ["api.hip", "kernels.hip", "fw.hip", "hier.hip", "range.hip", "probe.hip",
+           "server.hip"]
 ARCH = "gfx950"
 
 

@@ -179,6 +179,8 @@ StaticScratch g_static[kMaxDevices];
 
 }  // namespace
 
+int spq::set_error(int s, const char* msg) { return fail(static_cast<spq_status>(s), msg); }
+
 struct spq_index {
   int device = 0;
   int32_t n = 0, k = 0, V = 0, Vp = 0, tile = 128, pivot = 256, max_comp = 0, max_nb = 0;

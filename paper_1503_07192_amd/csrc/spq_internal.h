@@ -248,5 +248,7 @@ hipError_t launch_adjacency(int32_t n, int64_t m, const int32_t* eu, const int32
 // One shortest path per pair by a walk on the adjacency (kernels.hip).
 hipError_t launch_paths(const QueryArgs& a, int32_t max_len, const int64_t* rowptr, const int2* adj,
                         const int32_t* wts, int32_t* paths, int32_t* lens, hipStream_t s);
+// Sets this thread's spq_last_error message and returns s (api.hip).
+int set_error(int s, const char* msg);
 
 }  // namespace spq

@@ -1,24 +1,29 @@
-"""Continuous-batching query server on a resident index.
+"""Continuous-batching query serving on a resident index.
 
-Requests (batches of query pairs) arrive over time.  The scheduler keeps a
-FIFO admission queue and a fixed set of slots; each slot is one HIP stream.
-Every launch's device buffers (pairs in, distances out) and their pinned
-staging are carved out of one device pool and one pinned pool of the memory
-budget's size by a first-fit allocator (``Arena``): a launch is admitted only
-when its buffers can be allocated there (memory-based admission), and they
-return to the pool when it completes.  Whenever a slot is free, the requests
-at the head of the queue are coalesced into one launch of ``spq_query_batch``
-on that slot, as many as fit in the slot's pair capacity and in the largest
-free region.  Several slots are in flight at once, so requests that arrive
-while others run are admitted as soon as a slot and memory free up, and
-their work overlaps on the device.
-Completion is detected by polling each slot's event; a request's latency is
-its completion time minus its arrival time.
+Requests (batches of query pairs) arrive over time.  The server is the
+library's own (``spq.Server``, spq_server_* in the C ABI): a native worker
+thread keeps a FIFO admission queue and a fixed set of slots, each slot one
+HIP stream.  Every launch's device buffers (pairs in, distances out) and their
+pinned staging are carved out of one device pool and one pinned pool of the
+memory budget's size by a first-fit allocator: a launch is admitted only when
+its buffers can be allocated there (memory-based admission), and they return
+to the pools when it completes.  Whenever a slot is free, the requests at the
+head of the queue are coalesced into one launch of ``spq_query_batch`` on that
+slot, as many as fit in the slot's pair capacity and in the largest free
+region.  Several slots are in flight at once, so requests that arrive while
+others run are admitted as soon as a slot and memory free up, and their work
+overlaps on the device.  A request's latency is its completion time minus
+its arrival time.
+
+``Scheduler`` and ``Arena`` below are the same admission policy in Python,
+driven by an executor interface (``submit / done / result``): the tests run
+them on the CPU against a fake executor, where the policy's decisions can be
+checked step by step.  ``run_native`` replays an arrival stream against the
+library's server.
 
 The paper answers queries one at a time and lists parallel queries as future
 work (Section 5, Conclusion); ``OneAtATime`` is that mode, kept as the
-comparator.  The scheduling logic only talks to an executor
-(``submit / done / result``), so it is tested on the CPU with a fake one.
+comparator.
 """
 from __future__ import annotations
 
@@ -248,7 +253,7 @@ def run_stream(sched: Scheduler, reqs, clock=None, spin=True):
     return done
 
 
-def summarize(reqs, sched=None):
+def summarize(reqs, sched=None, server_stats=None):
     lat = np.array([r.done_at - r.arrival for r in reqs])
     pairs = sum(r.size for r in reqs)
     span = max(r.done_at for r in reqs) - min(r.arrival for r in reqs)
@@ -263,49 +268,38 @@ def summarize(reqs, sched=None):
     if sched is not None:
         out["launches"] = sched.launches
         out["pairs_per_launch"] = float(np.mean(sched.launch_sizes)) if sched.launch_sizes else 0.0
+    if server_stats is not None:
+        out["launches"] = server_stats["launches"]
+        out["pairs_per_launch"] = server_stats["pairs"] / max(1, server_stats["launches"])
     return out
 
 
-# ------------------------------------------------------------- executors
-class GpuExecutor:
-    """One HIP stream per slot; the buffers of every launch come from one
-    device pool and one pinned host pool of mem_bytes each, allocated once,
-    through the executor's Arena: a launch at offset off keeps its pairs and
-    results at [off, off + 12 q) of both pools until it completes."""
-
-    def __init__(self, index, slots: int, mem_bytes: int):
-        import torch
-        from . import spq
-        self.torch, self.spq, self.index = torch, spq, index
-        self.arena = Arena(mem_bytes)
-        words = self.arena.size // 4
-        self.streams = [torch.cuda.Stream() for _ in range(slots)]  # default priority
-        self.d_pool = torch.empty(words, dtype=torch.int32, device="cuda")
-        self.h_pool = torch.empty(words, dtype=torch.int32, pin_memory=True)
-        self.events = [torch.cuda.Event() for _ in range(slots)]
-
-    def submit(self, slot, v1, v2, off):
-        torch, q = self.torch, len(v1)
-        b = off // 4
-        hin = self.h_pool[b:b + 2 * q]
-        hin.numpy()[:q] = v1
-        hin.numpy()[q:] = v2
-        din = self.d_pool[b:b + 2 * q]
-        dout = self.d_pool[b + 2 * q:b + 3 * q]
-        s = self.streams[slot]
-        with torch.cuda.stream(s):
-            din.copy_(hin, non_blocking=True)
-            self.spq.query_batch(self.index, din[:q], din[q:], dout, stream=s)
-            self.h_pool[b + 2 * q:b + 3 * q].copy_(dout, non_blocking=True)
-            self.events[slot].record(s)
-        return (slot, b, q)
-
-    def done(self, handle):
-        return self.events[handle[0]].query()
-
-    def result(self, handle):
-        _, b, q = handle
-        return self.h_pool[b + 2 * q:b + 3 * q].numpy().copy()
+# ------------------------------------------------------------- native server
+def run_native(server, reqs, clock=time.perf_counter):
+    """Replays the arrival times in real time against ``server`` (an
+    ``spq.Server``): each request is submitted at its arrival time, then every
+    one is collected.  done_at = submission time + the server's own latency
+    (completion minus submission), so a submission that lags its arrival
+    time counts against the request.  The cyclic garbage collector is paused
+    meanwhile."""
+    t0 = clock()
+    sent = []
+    was_enabled = gc.isenabled()
+    gc.disable()
+    try:
+        for r in reqs:
+            while clock() - t0 < r.arrival:
+                pass
+            at = clock() - t0
+            sent.append((r, server.submit(r.v1, r.v2), at))
+        for r, ticket, at in sent:
+            r.result, lat = server.poll(ticket, wait=True)
+            r.done_at = at + lat
+    finally:
+        if was_enabled:
+            gc.enable()
+        gc.collect()
+    return reqs
 
 
 class OneAtATime:
@@ -372,13 +366,13 @@ def main(argv=None):
               "slots": args.slots, "slot_pairs": args.slot_pairs, "mem_mib": args.mem_mib,
               "rates": {}}
     mem = int(args.mem_mib * 2**20)
-    ex = GpuExecutor(idx, args.slots, mem)
     for rate in [float(x) for x in args.rates.split(",")]:
         nreq = args.requests if rate >= 1e6 else args.low_rate_requests
         reqs = poisson_stream(rng, rate, nreq, g["n"])
-        sched = Scheduler(ex, args.slots, args.slot_pairs, mem)
-        done = run_stream(sched, reqs)
-        res = summarize(done, sched)
+        server = spq.Server(idx, args.slots, args.slot_pairs, mem)
+        done = run_native(server, reqs)
+        res = summarize(done, server_stats=server.stats())
+        server.close()
         # each request alone must give the same answers as inside the mix
         same = 0
         for r in reqs:

@@ -91,6 +91,11 @@ _SIGS = {
     "spq_valu_rates": (I32, [P, P]),
     "spq_minplus_batched": (I32, [I32, I32, P, P, I32, I32, P, P, I64, P, I32, P, I32, P, I64, P]),
     "spq_minplus_rows": (I32, [I32, P, I32, P, P, I64, P, P, P]),
+    "spq_server_create": (I32, [P, I32, I64, I64, P]),
+    "spq_server_submit": (I32, [P, I64, P, P, P, P]),
+    "spq_server_poll": (I32, [P, I64, I32, P, P]),
+    "spq_server_stats": (I32, [P, P, P]),
+    "spq_server_destroy": (None, [P]),
 }
 
 
@@ -294,6 +299,64 @@ def query_batch_host_static(index: Index, v1, v2, stream=None):
     _check(load().spq_query_batch_host_static(index.handle, len(v1), v1.ctypes.data,
                                               v2.ctypes.data, out.ctypes.data, _stream(stream)))
     return out
+
+
+class Server:
+    """The library's continuous-batching server (spq_server_*) on a built
+    index: requests of host (numpy) pairs are queued, coalesced into launches
+    on `slots` streams by a native worker thread, and answered into numpy
+    arrays; `mem_bytes` is its device (and pinned) pool, 12 bytes per pair in
+    flight."""
+
+    def __init__(self, index: Index, slots: int = 4, slot_pairs: int = 65536,
+                 mem_bytes: int = 64 << 20):
+        h = ctypes.c_void_p()
+        _check(load().spq_server_create(index.handle, int(slots), int(slot_pairs), int(mem_bytes),
+                                        ctypes.byref(h)))
+        self.handle = h.value
+        self.index = index   # the index must outlive the server
+        self._held = {}      # ticket -> (v1, v2, out): alive until answered
+
+    def submit(self, v1, v2) -> int:
+        """Queues the pairs (v1[i], v2[i]); returns the request's ticket."""
+        v1 = np.ascontiguousarray(v1, np.int32)
+        v2 = np.ascontiguousarray(v2, np.int32)
+        if v1.shape != v2.shape or v1.ndim != 1:
+            raise ValueError("v1 and v2 must be 1-d and equally long")
+        out = np.empty_like(v1)
+        t = ctypes.c_int64()
+        _check(load().spq_server_submit(self.handle, len(v1), v1.ctypes.data, v2.ctypes.data,
+                                        out.ctypes.data, ctypes.byref(t)))
+        self._held[t.value] = (v1, v2, out)
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = False):
+        """(answers, latency in seconds) once the request is complete, else
+        None; wait=True blocks until it is.  A ticket is answered once."""
+        done = ctypes.c_int32()
+        lat = ctypes.c_double()
+        _check(load().spq_server_poll(self.handle, int(ticket), int(bool(wait)),
+                                      ctypes.byref(done), ctypes.byref(lat)))
+        if not done.value:
+            return None
+        return self._held.pop(ticket)[2], lat.value
+
+    def stats(self) -> dict:
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().spq_server_stats(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return {"launches": a.value, "pairs": b.value}
+
+    def close(self):
+        """Answers everything submitted, then frees the server."""
+        if self.handle:
+            load().spq_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def index_stats(index: Index) -> dict:

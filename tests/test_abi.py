@@ -124,3 +124,22 @@ def test_struct_layouts_match_header(tmp_path):
     assert int(out[1]) == ctypes.sizeof(spq.Stats)
     for f, off in zip(fields, out[2:]):
         assert int(off) == getattr(spq.Stats, f).offset, f
+
+
+def test_server_rejects_bad_arguments_without_device():
+    """spq_server_*: null server, index, ticket or output pointer, negative
+    sizes; destroy(NULL) is a no-op."""
+    L = spq.load()
+    h = ctypes.c_void_p()
+    assert L.spq_server_create(None, 4, 1024, 1 << 20, None) == 1
+    assert "out is NULL" in spq.last_error()
+    assert L.spq_server_create(None, 4, 1024, 1 << 20, ctypes.byref(h)) == 1
+    assert "index is NULL" in spq.last_error() and h.value is None
+    t = ctypes.c_int64()
+    assert L.spq_server_submit(None, 3, None, None, None, ctypes.byref(t)) == 1
+    assert L.spq_server_submit(ctypes.c_void_p(8), 3, None, None, None, None) == 1
+    assert "null argument" in spq.last_error()
+    d = ctypes.c_int32()
+    assert L.spq_server_poll(None, 1, 0, ctypes.byref(d), None) == 1
+    assert L.spq_server_stats(None, None, None) == 1
+    L.spq_server_destroy(None)

@@ -1,6 +1,7 @@
 """The C ABI from a plain C program (tests/c_client/spq_client.c, built with
 gcc against include/spq.h and libspq.so): host-array build, host-array
-queries with and without allocation, answers equal to Dijkstra on G
+queries with and without allocation and through the library's server,
+answers equal to Dijkstra on G
 (Algorithm 1 then Algorithm 2, Lemma 3)."""
 import os
 import subprocess
@@ -34,8 +35,9 @@ def test_c_client_grid32(tmp_path):
                          timeout=120)
     assert res.returncode == 0, res.stderr
     assert "v_bg=348" in res.stdout
-    out = np.fromfile(outp, "<i4").reshape(2, len(v1))
-    assert np.array_equal(out[0], out[1])
+    out = np.fromfile(outp, "<i4").reshape(3, len(v1))
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    assert "served: %d pairs" % len(v1) in res.stdout
     D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], np.maximum(v1, 0))
     want = D[np.arange(len(v1)), v2].astype(np.int32)
     want[5] = spq.SPQ_BAD_PAIR

@@ -1,5 +1,6 @@
-"""Serving on the GPU: every request's answers are the same alone and in the
-mix of concurrently served requests (tolerance 0), and match Dijkstra."""
+"""Serving on the GPU through the library's server (spq_server_*): every
+request's answers are the same alone and in the mix of concurrently served
+requests (tolerance 0), and match Dijkstra."""
 import numpy as np
 import pytest
 
@@ -25,21 +26,27 @@ def test_served_mix_equals_alone(method):
     torch.cuda.synchronize()
     rng = np.random.default_rng(12)
     reqs = serve.poisson_stream(rng, 2e7, 150, g["n"], max_log2=12.0)
-    ex = serve.GpuExecutor(idx, 4, 12 * 3000)
-    sched = serve.Scheduler(ex, 4, 2048, 12 * 3000)   # small pool: requests get cut
-    done = serve.run_stream(sched, reqs)
-    assert len(done) == len(reqs)
-    assert sched.launches < sum(r.size for r in reqs)
-    assert any(len(r.launches) > 1 for r in reqs)
+    reqs.append(serve.Request(len(reqs), reqs[-1].arrival, np.zeros(0, np.int32),
+                              np.zeros(0, np.int32)))    # an empty request
+    server = spq.Server(idx, 4, 2048, 12 * 3000)         # small pool: requests get cut
+    done = serve.run_native(server, reqs)
+    st = server.stats()
+    server.close()
+    total = sum(r.size for r in reqs)
+    assert len(done) == len(reqs) and st["pairs"] == total
+    assert st["launches"] < total                         # coalesced
+    # a launch holds at most 2,048 pairs and (12,000 B of pool) 1,000 pairs
+    assert st["launches"] >= -(-total // 1000)
+    assert any(r.size > 1000 for r in reqs)               # so some were cut
     for r in reqs:
-        alone = spq.query_batch(idx, dev(r.v1), dev(r.v2)).cpu().numpy()
+        alone = spq.query_batch(idx, dev(r.v1), dev(r.v2)).cpu().numpy() if r.size else r.result
         assert np.array_equal(alone, r.result), r.rid
     # a sample against Dijkstra on G
     for r in reqs[:5]:
         D = oracle.dijkstra(g["n"], g["eu"], g["ev"], g["w"], r.v1[:20])
         assert np.array_equal(r.result[:20], D[np.arange(min(20, r.size)), r.v2[:20]])
-    s = serve.summarize(done, sched)
-    assert s["latency_ms_p99"] >= s["latency_ms_p50"] > 0
+    s = serve.summarize(done, server_stats=st)
+    assert s["latency_ms_p99"] >= s["latency_ms_p50"] >= 0
     one = serve.poisson_stream(rng, 1e5, 3, g["n"], max_log2=6.0)
     serve.OneAtATime(idx).run(one)
     for r in one:
@@ -64,13 +71,13 @@ def test_config5_serving_on_the_delaunay_index():
     assert st["bg_method"] == 2 and st["v_bg"] > 250_000
     rng = np.random.default_rng(W.SEED_BASE + 5)
     reqs = serve.poisson_stream(rng, 1e7, 200, g["n"], max_log2=14.0)
-    mem = 16 << 20
-    ex = serve.GpuExecutor(idx, 4, mem)
-    sched = serve.Scheduler(ex, 4, 65536, mem)
-    done = serve.run_stream(sched, reqs)
+    server = spq.Server(idx, 4, 65536, 16 << 20)
+    done = serve.run_native(server, reqs)
+    st = server.stats()
+    server.close()
     assert len(done) == len(reqs)
-    assert sched.launches < len(reqs)   # requests were coalesced
-    print(serve.summarize(done, sched), flush=True)
+    assert st["launches"] < len(reqs)   # requests were coalesced
+    print(serve.summarize(done, server_stats=st), flush=True)
     for r in reqs:
         alone = spq.query_batch(idx, dev(r.v1), dev(r.v2)).cpu().numpy()
         assert np.array_equal(alone, r.result), r.rid
@@ -84,3 +91,43 @@ def test_config5_serving_on_the_delaunay_index():
         assert np.array_equal(got[a:a + 100], want), a
     print("config 5: %d requests, %d pairs checked against Dijkstra" % (len(reqs), len(v1)),
           flush=True)
+
+
+def test_server_threads_polling_and_close():
+    """Requests submitted from four threads at once, collected by polling
+    without waiting, and a close() with requests still uncollected: every
+    answer equals spq_query_batch's on the same pairs."""
+    import threading
+    g = W.grid256d(queries=0)
+    print("serve test: threads", flush=True)
+    idx = spq.build_index(g["n"], dev(g["eu"]), dev(g["ev"]), dev(g["w"]), dev(g["part"]), g["k"],
+                          bg_method=2, group_comps=64)
+    server = spq.Server(idx, 3, 5000, 1 << 20)
+    rng = np.random.default_rng(5)
+    batches = [(rng.integers(0, g["n"], s).astype(np.int32), rng.integers(0, g["n"], s).astype(np.int32))
+               for s in rng.integers(1, 9000, 64)]
+    tickets = [None] * len(batches)
+
+    def send(lo):
+        for i in range(lo, len(batches), 4):
+            tickets[i] = server.submit(*batches[i])
+
+    th = [threading.Thread(target=send, args=(j,)) for j in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    got = {}
+    while len(got) < 48:                      # collect the first 48 by polling
+        for i in range(48):
+            if i not in got:
+                r = server.poll(tickets[i])
+                if r is not None:
+                    got[i] = r[0]
+    late = [server._held[tickets[i]][2] for i in range(48, 64)]
+    server.close()                            # answers the other 16 first
+    for i, (v1, v2) in enumerate(batches):
+        want = spq.query_batch(idx, dev(v1), dev(v2)).cpu().numpy()
+        assert np.array_equal(got[i] if i < 48 else late[i - 48], want), i
+    with pytest.raises(spq.SpqError):
+        spq.Server(idx, 0, 10, 1 << 20)
