@@ -183,6 +183,14 @@ def cpu_baseline(g, st, budget_s):
     return res
 
 
+T_START = time.perf_counter()
+
+
+def progress(msg):
+    """One line per finished phase on stderr (stdout holds only the result)."""
+    print("bench: %s (%.1f s)" % (msg, time.perf_counter() - T_START), file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -196,6 +204,7 @@ def main():
     wl = WORKLOADS[args.workload]
     nq = args.queries or wl["queries"]
     g, build_kw = make_workload(args.workload, nq)
+    progress("workload %s generated" % args.workload)
     tuned = None
     if build_kw.get("tune_cache"):
         from paper_1503_07192_amd import autotune
@@ -229,8 +238,9 @@ def main():
             record.append(st)
         idx.free()
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step(None)
+        progress("warm-up step %d done" % (i + 1))
     recs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -238,6 +248,7 @@ def main():
         step(recs)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress("%d timed steps done" % args.steps)
 
     st = recs[-1]
     relax = st["relax_comp_exec"] + st["relax_bg_exec"]
@@ -307,6 +318,7 @@ def main():
     idx = spq.build_index(g["n"], eu, ev, w, part, g["k"], plain=True, paths=True, stream=stream,
                           **build_kw)
     plain_st = spq.index_stats(idx)
+    progress("comparison builds done")
     lay = spq.index_layout(idx)
     layout_tables = (lay["comp"], lay["nb"])
     # shortest paths (vertex sequences) for the first 1,000 pairs
@@ -444,6 +456,7 @@ def main():
                                            "FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy)"},
     }
     # instruction issue rates behind the peak, measured after the timed region
+    progress("query latencies and serving done")
     vr = spq.valu_rates(stream)
     line["valu_rates"] = {
         "v_add_u32_lane_ops_per_s": vr["v_add_u32"], "v_min3_u32_lane_ops_per_s": vr["v_min3_u32"],
