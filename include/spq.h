@@ -476,33 +476,57 @@ spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv
                                int32_t cb, int32_t* out, int64_t ldo, void* stream);
 
 /*
- * Test hook: the intra-group product of the share build's Bellman-Ford
- * rounds (BG rows of one GPU's share, Algorithm 1 Phase 3, computed over the
- * groups of the two-level method), in place on a caller-owned DEVICE table C.
- * Group g owns rows koff[g] .. koff[g]+nk[g]-1 of C (koff as above); for
- * each of them and every column j < ldc:
- *   C[koff[g]+r][j] = min(C[koff[g]+r][j],
- *                         min over listed k of A[g][r][k] + C[koff[g]+k][j]).
+ * Test hook: the intra-block product of the share build's Bellman-Ford
+ * rounds (BG rows of one GPU's share, Algorithm 1 Phase 3, computed over
+ * blocks of the two-level method's groups), in place on a caller-owned
+ * DEVICE table C.  Group g owns nk[g] rows of C: own_g[r] = own[koff[g] + r]
+ * (koff as above; own NULL: own_g[r] = koff[g] + r).  For each of them and
+ * every column j < ldc:
+ *   C[own_g[r]][j] = min(C[own_g[r]][j],
+ *                        min over listed k of A[g][r][k] + C[own_g[k]][j]).
  *   nk        HOST array of G (in [1, 65535]) row counts in [0, kp]
  *   kp        positive multiple of 128
  *   A         G x kp x kp int32, A[g][r][k] at A[(g*kp + r)*kp + k]; must be
  *             symmetric on [0, nk[g])^2 (the kernel reads column r as row r)
- *   C         at least koff[G] + 128 rows of ldc (a positive multiple of 128)
- *             int32; rows past koff[G] are read, never written
+ *   C         int32 rows of ldc (a positive multiple of 128) entries, at
+ *             least every row named by own_g
  *   cnt       HOST array of G: cnt[g] < 0 lists every row 0 .. nk[g]-1, else
- *             the next cnt[g] entries of `rows` (HOST, local indices) are
- *             the listed rows of group g
+ *             the next cnt[g] entries of `rows` (HOST, indices r < nk[g])
+ *             are the listed rows of group g
+ *   own       HOST array of koff[G] distinct rows of C, or NULL
  * Rows are updated in place while other workgroups read them as K, so the
  * result is the formula above for any schedule only when every value read
  * is no smaller than it: A[g] closed (its own all-pairs distances, 0 on the
  * diagonal) and every row that is not listed already satisfying
- * A[g][r][k] + C[k][j] >= C[r][j] (the state between two rounds).
- * Entries in [0, SPQ_INF].  Synchronous on `stream`.
+ * A[g][r][k] + C[own_g[k]][j] >= C[own_g[r]][j] (the state between two
+ * rounds).  Entries in [0, SPQ_INF].  Synchronous on `stream`.
  * Errors: SPQ_EINVAL, SPQ_ENOMEM, SPQ_EDEVICE.
  */
 spq_status spq_minplus_rows(int32_t groups, const int32_t* nk, int32_t kp, const int32_t* A,
                             int32_t* C, int64_t ldc, const int32_t* cnt, const int32_t* rows,
-                            void* stream);
+                            const int32_t* own, void* stream);
+
+/*
+ * Test hook: the last product of the share build's Bellman-Ford stage, which
+ * fills the rows of a block that no cross edge reaches from its boundary
+ * rows, in place on a caller-owned DEVICE table C.  Group g reads nk[g] rows
+ * own_g[k] = own[koff[g] + k] and writes nout[g] rows out_g[i] =
+ * out[ooff[g] + i] (koff, ooff: exclusive prefix sums of nk, nout); for
+ * every column j < ldc:
+ *   C[out_g[i]][j] = min(C[out_g[i]][j],
+ *                        min over k < nk[g] of Aout[g][k][i] + C[own_g[k]][j]).
+ *   nk, nout  HOST arrays of G (in [1, 65535]) counts in [0, kp], [0, np]
+ *   kp, np    positive multiples of 128
+ *   Aout      G x kp x np int32, Aout[g][k][i] at Aout[(g*kp + k)*np + i]
+ *   C         int32 rows of ldc (a positive multiple of 128) entries
+ *   own, out  HOST arrays of koff[G] and ooff[G] rows of C; no row may be
+ *             both read (own) and written (out)
+ * Entries in [0, SPQ_INF].  Synchronous on `stream`.
+ * Errors: SPQ_EINVAL, SPQ_ENOMEM, SPQ_EDEVICE.
+ */
+spq_status spq_minplus_gather(int32_t groups, const int32_t* nk, const int32_t* nout, int32_t kp,
+                              int32_t np, const int32_t* Aout, int32_t* C, int64_t ldc,
+                              const int32_t* own, const int32_t* out, void* stream);
 
 #ifdef __cplusplus
 }

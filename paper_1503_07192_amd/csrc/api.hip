@@ -226,6 +226,12 @@ struct spq_index {
   int64_t S2p = 0;
   u32 *A = nullptr, *DT = nullptr, *bfflag = nullptr, *bfstamp = nullptr;
   int32_t *bfcnt = nullptr, *bflist = nullptr;
+  // the blocks' boundary B3 (rows the rounds keep settled) and the rest
+  uint8_t *sb_flag = nullptr, *sb_flagn = nullptr;
+  int32_t *sb_list = nullptr, *sb_nlist = nullptr, *sb_rank = nullptr, *sb_nrank = nullptr;
+  int32_t *sb_m = nullptr, *sb_n = nullptr;
+  u32 *sb_A3 = nullptr, *sb_Aout = nullptr;
+  std::vector<int32_t> h_sbm, h_sbn;
   // Bellman-Ford blocks (runs of groups): first level-2 id, size, first
   // group, and the block of every group
   int32_t bgpt = 1, nblk = 0, bpmax = 0;
@@ -287,6 +293,7 @@ struct spq_index {
                     vrec, gT,    grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
                     b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
                     bgvert, label, bglabel, cert, A,    DT,    bfflag,  bfstamp, bfcnt, bflist,
+                    sb_flag, sb_flagn, sb_list, sb_nlist, sb_rank, sb_nrank, sb_m, sb_n, sb_A3, sb_Aout,
                     xe, xcount, boff, bsize, bfirst, gblk,
                     eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
                     M3, R3, XT3, BG3, plist, plist3, rowptr, adj, adeg, w_copy};
@@ -448,8 +455,15 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   // rows lowered per (block, column tile), two rounds' worth, and the round
   // stamps that keep a row from being listed twice in one round
   HIP_TRY(dalloc(&X->bfcnt, 2 * (int64_t)NB * ntc));
-  HIP_TRY(dalloc(&X->bflist, 2 * (int64_t)NB * ntc * BP));
   HIP_TRY(dalloc(&X->bfstamp, V2p * ntc));
+  HIP_TRY(dalloc(&X->sb_flag, V2p));
+  HIP_TRY(dalloc(&X->sb_flagn, V2p));
+  HIP_TRY(dalloc(&X->sb_list, (int64_t)NB * BP));
+  HIP_TRY(dalloc(&X->sb_nlist, (int64_t)NB * BP));
+  HIP_TRY(dalloc(&X->sb_rank, V2p));
+  HIP_TRY(dalloc(&X->sb_nrank, V2p));
+  HIP_TRY(dalloc(&X->sb_m, NB));
+  HIP_TRY(dalloc(&X->sb_n, NB));
   HIP_TRY(hipMemsetAsync(X->bfstamp, 0xff, sizeof(u32) * V2p * ntc, s));
   HIP_TRY(hipMemsetAsync(X->xcount, 0, sizeof(int32_t), s));
   HIP_TRY(hipMemsetAsync(X->DT + V2p * X->S2p, 0xff, 128 * X->S2p * sizeof(u32), s));
@@ -462,9 +476,28 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   ha.xe = X->xe; ha.xcount = X->xcount;
   const spq::ShareBlocks blk{NB, BP, multi, X->bfirst, X->gblk, X->boff, X->bsize, X->A};
   HIP_TRY(spq::launch_share_prepare(ha, blk, s));
+  HIP_TRY(spq::launch_share_b3_lists(ha, blk, X->sb_flag, X->sb_flagn, X->sb_list, X->sb_nlist,
+                                     X->sb_rank, X->sb_nrank, X->sb_m, X->sb_n, s));
   int32_t nxe = 0;
+  X->h_sbm.assign(NB, 0);
+  X->h_sbn.assign(NB, 0);
   HIP_TRY(hipMemcpyAsync(&nxe, X->xcount, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(X->h_sbm.data(), X->sb_m, sizeof(int32_t) * NB, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(X->h_sbn.data(), X->sb_n, sizeof(int32_t) * NB, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  int32_t m3max = 0, n3max = 0;
+  for (int32_t t = 0; t < NB; t++) {
+    m3max = std::max(m3max, X->h_sbm[t]);
+    n3max = std::max(n3max, X->h_sbn[t]);
+  }
+  const int32_t B3P = (int32_t)std::max<int64_t>(128, round_up(m3max, 128));
+  const int32_t N3P = (int32_t)std::max<int64_t>(128, round_up(n3max, 128));
+  HIP_TRY(dalloc(&X->bflist, 2 * (int64_t)NB * ntc * B3P));
+  HIP_TRY(dalloc(&X->sb_A3, (int64_t)NB * B3P * B3P));
+  HIP_TRY(dalloc(&X->sb_Aout, (int64_t)NB * B3P * N3P));
+  const spq::ShareB3 b3{B3P, N3P, X->sb_m, X->sb_n, X->sb_list, X->sb_nlist, X->sb_rank,
+                        X->sb_A3, X->sb_Aout};
+  HIP_TRY(spq::launch_share_b3_gather(blk, b3, s));
   // The blocks holding share sources start dirty on every column tile.  Their
   // rows start closed (DT's initial rows are rows of the closed A), so the
   // first intra step has no row to multiply: cross edges move first.
@@ -498,17 +531,17 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   for (auto& e : rb.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   u32* dbuf[2] = {X->bfflag, X->bfflag + (int64_t)NB * fs};
   int32_t* cbuf[2] = {X->bfcnt, X->bfcnt + (int64_t)NB * ntc};
-  int32_t* lbuf[2] = {X->bflist, X->bflist + (int64_t)NB * ntc * BP};
+  int32_t* lbuf[2] = {X->bflist, X->bflist + (int64_t)NB * ntc * B3P};
   // executed relaxations of a round from the flags and counts it starts
-  // with: a dirty (block, tile) multiplies its row tiles by the rows listed
-  // for it
+  // with: a dirty (block, tile) multiplies its B3 row tiles by the rows
+  // listed for it
   auto count = [&](const u32* fl, const int32_t* cn) {
     for (int32_t t = 0; t < NB; t++)
       for (int32_t c = 0; c < ntc; c++) {
         const int32_t cc = cn[(size_t)t * ntc + c];
         if (cc == 0 || !fl[(size_t)t * fs + c]) continue;
-        const int32_t kk = cc == spq::BF_ALL_ROWS ? X->h_bsize[t] : cc;
-        X->relax_bg_exec += (double)((X->h_bsize[t] + 127) / 128) * 128.0 * 128.0 *
+        const int32_t kk = cc == spq::BF_ALL_ROWS ? X->h_sbm[t] : cc;
+        X->relax_bg_exec += (double)((X->h_sbm[t] + 127) / 128) * 128.0 * 128.0 *
                             (double)round_up(kk, 16);
       }
   };
@@ -522,7 +555,7 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
                            X->bfstamp, (u32)(issued + 1)};
       HIP_TRY(hipMemsetAsync(dbuf[out], 0, sizeof(u32) * fwords, s));
       HIP_TRY(hipMemsetAsync(cbuf[out], 0, sizeof(int32_t) * cwords, s));
-      HIP_TRY(spq::launch_share_round(ha, blk, nxe, r, s));
+      HIP_TRY(spq::launch_share_round(ha, blk, b3, nxe, r, s));
       u32* slot = rb.host + (size_t)(issued % SLOTS) * (fwords + cwords);
       HIP_TRY(hipMemcpyAsync(slot, dbuf[out], sizeof(u32) * fwords, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipMemcpyAsync(slot + fwords, cbuf[out], sizeof(int32_t) * cwords, hipMemcpyDeviceToHost,
@@ -540,6 +573,12 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
     count(fl, cn);  // the next round's work
   }
   X->bf_rounds = (int32_t)consumed;
+  // the rows outside B3 from the settled B3 rows
+  HIP_TRY(spq::launch_share_final(ha, blk, b3, s));
+  for (int32_t t = 0; t < NB; t++)
+    if (X->h_sbm[t] > 0)
+      X->relax_bg_exec += (double)((X->h_sbn[t] + 127) / 128) * ntc * 128.0 * 128.0 *
+                          (double)round_up(X->h_sbm[t], 16);
   for (int32_t a1 = 0; a1 < X->share_groups; a1++)
     for (int32_t a2 = 0; a2 < G; a2++) {
       X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * ((X->h_gV[a1] + 127) / 128) *
@@ -1750,7 +1789,7 @@ spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv
 // (see spq.h).
 spq_status spq_minplus_rows(int32_t groups, const int32_t* nk, int32_t kp, const int32_t* A,
                             int32_t* C, int64_t ldc, const int32_t* cnt, const int32_t* rows,
-                            void* stream) {
+                            const int32_t* own, void* stream) {
   if (groups < 1 || groups > 65535) return fail(SPQ_EINVAL, "groups must be in [1, 65535]");
   if (kp < 128 || kp % 128) return fail(SPQ_EINVAL, "kp must be a positive multiple of 128");
   if (ldc < 128 || ldc % 128) return fail(SPQ_EINVAL, "ldc must be a positive multiple of 128");
@@ -1768,7 +1807,13 @@ spq_status spq_minplus_rows(int32_t groups, const int32_t* nk, int32_t kp, const
   std::vector<u32> dirty((size_t)groups * (ntc + 1), 1u);
   std::vector<int32_t> hc((size_t)groups * ntc);
   std::vector<int32_t> hl((size_t)groups * ntc * kp, 0);
+  std::vector<int32_t> ho((size_t)groups * kp, 0);
   for (int32_t g = 0, at = 0; g < groups; g++) {
+    for (int32_t r = 0; r < nk[g]; r++) {
+      const int32_t c = own ? own[koff[g] + r] : koff[g] + r;
+      if (c < 0) return fail(SPQ_EINVAL, "negative row in own");
+      ho[(size_t)g * kp + r] = c;
+    }
     const int32_t c = cnt[g] < 0 ? spq::BF_ALL_ROWS : cnt[g];
     for (int32_t t = 0; t < ntc; t++) {
       hc[(size_t)g * ntc + t] = c;
@@ -1782,20 +1827,70 @@ spq_status spq_minplus_rows(int32_t groups, const int32_t* nk, int32_t kp, const
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Scratch sc(s);
-  int32_t *d_nk = nullptr, *d_koff = nullptr, *d_cnt = nullptr, *d_list = nullptr;
+  int32_t *d_nk = nullptr, *d_zero = nullptr, *d_own = nullptr, *d_cnt = nullptr, *d_list = nullptr;
   u32* d_dirty = nullptr;
+  const std::vector<int32_t> zero(groups, 0);
   HIP_TRY(sc.get(&d_nk, groups));
-  HIP_TRY(sc.get(&d_koff, groups + 1));
+  HIP_TRY(sc.get(&d_zero, groups));
+  HIP_TRY(sc.get(&d_own, (int64_t)groups * kp));
   HIP_TRY(sc.get(&d_cnt, (int64_t)groups * ntc));
   HIP_TRY(sc.get(&d_list, (int64_t)groups * ntc * kp));
   HIP_TRY(sc.get(&d_dirty, (int64_t)groups * (ntc + 1)));
   HIP_TRY(hipMemcpyAsync(d_nk, nk, sizeof(int32_t) * groups, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_koff, koff.data(), sizeof(int32_t) * (groups + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_zero, zero.data(), sizeof(int32_t) * groups, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_own, ho.data(), sizeof(int32_t) * ho.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d_cnt, hc.data(), sizeof(int32_t) * hc.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d_list, hl.data(), sizeof(int32_t) * hl.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d_dirty, dirty.data(), sizeof(u32) * dirty.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(spq::launch_bf_intra(groups, kp, ldc, d_nk, d_koff, reinterpret_cast<const u32*>(A),
-                               reinterpret_cast<u32*>(C), d_dirty, d_cnt, d_list, s));
+  HIP_TRY(spq::launch_bf_rows(groups, kp, kp, ldc, d_nk, d_zero, d_own,
+                              reinterpret_cast<const u32*>(A), reinterpret_cast<u32*>(C), d_dirty,
+                              d_cnt, d_list, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SPQ_OK;
+}
+
+spq_status spq_minplus_gather(int32_t groups, const int32_t* nk, const int32_t* nout, int32_t kp,
+                              int32_t np, const int32_t* Aout, int32_t* C, int64_t ldc,
+                              const int32_t* own, const int32_t* out, void* stream) {
+  if (groups < 1 || groups > 65535) return fail(SPQ_EINVAL, "groups must be in [1, 65535]");
+  if (kp < 128 || kp % 128 || np < 128 || np % 128)
+    return fail(SPQ_EINVAL, "kp and np must be positive multiples of 128");
+  if (ldc < 128 || ldc % 128) return fail(SPQ_EINVAL, "ldc must be a positive multiple of 128");
+  if (!nk || !nout || !Aout || !C) return fail(SPQ_EINVAL, "null argument");
+  const int32_t L = std::max(kp, np);
+  std::vector<int32_t> ho((size_t)groups * L, 0), hq((size_t)groups * L, 0);
+  int64_t ak = 0, ao = 0;
+  for (int32_t g = 0; g < groups; g++) {
+    if (nk[g] < 0 || nk[g] > kp || nout[g] < 0 || nout[g] > np)
+      return fail(SPQ_EINVAL, "nk outside [0, kp] or nout outside [0, np]");
+    if ((nk[g] > 0 && !own) || (nout[g] > 0 && !out)) return fail(SPQ_EINVAL, "null row list");
+    for (int32_t k = 0; k < nk[g]; k++) {
+      if (own[ak + k] < 0) return fail(SPQ_EINVAL, "negative row in own");
+      ho[(size_t)g * L + k] = own[ak + k];
+    }
+    for (int32_t i = 0; i < nout[g]; i++) {
+      if (out[ao + i] < 0) return fail(SPQ_EINVAL, "negative row in out");
+      hq[(size_t)g * L + i] = out[ao + i];
+    }
+    ak += nk[g];
+    ao += nout[g];
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Scratch sc(s);
+  int32_t *d_nk = nullptr, *d_nout = nullptr, *d_zero = nullptr, *d_own = nullptr, *d_out = nullptr;
+  const std::vector<int32_t> zero(groups, 0);
+  HIP_TRY(sc.get(&d_nk, groups));
+  HIP_TRY(sc.get(&d_nout, groups));
+  HIP_TRY(sc.get(&d_zero, groups));
+  HIP_TRY(sc.get(&d_own, (int64_t)groups * L));
+  HIP_TRY(sc.get(&d_out, (int64_t)groups * L));
+  HIP_TRY(hipMemcpyAsync(d_nk, nk, sizeof(int32_t) * groups, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_nout, nout, sizeof(int32_t) * groups, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_zero, zero.data(), sizeof(int32_t) * groups, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_own, ho.data(), sizeof(int32_t) * ho.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_out, hq.data(), sizeof(int32_t) * hq.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(spq::launch_bf_gather(groups, L, kp, np, ldc, d_nk, d_nout, d_zero, d_own, d_out,
+                                reinterpret_cast<const u32*>(Aout), reinterpret_cast<u32*>(C), s));
   HIP_TRY(hipStreamSynchronize(s));
   return SPQ_OK;
 }

@@ -281,26 +281,32 @@ __device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int6
   }
 }
 
-// c = min(c, min over k < cnt of At[rows[k]][i] + B[rows[k]][j]): the K rows
-// are gathered through the list `rows` (rows k themselves when it is null;
-// cnt of them, streamed 16 at a time, rows past cnt read as INF without
-// touching memory).
+// c = min(c, min over k < cnt of At[rows[k]][i] + B[bmap[rows[k]]][j]): the K
+// rows are gathered through the list `rows` (rows k themselves when it is
+// null; cnt of them, streamed 16 at a time, rows past cnt read as INF without
+// touching memory), and B's rows once more through bmap when it is not null.
 __device__ __forceinline__ void mp_stream128_rows(u32 (&c)[8][8], const u32* At, int64_t ldA,
                                                   const u32* B, int64_t ldB,
                                                   const int32_t* __restrict__ rows, int cnt,
-                                                  u32* sA, u32* sB) {
+                                                  u32* sA, u32* sB,
+                                                  const int32_t* __restrict__ bmap = nullptr) {
   constexpr int T = 128, KC = 16;
   const int nch = (cnt + KC - 1) / KC;
   if (nch <= 0) return;
   const int e0 = threadIdx.x, e1 = threadIdx.x + 256;
   const int r0 = e0 >> 5, c0 = (e0 & 31) * 4, r1 = e1 >> 5, c1 = (e1 & 31) * 4;
   const uint4 inf4 = make_uint4(INF, INF, INF, INF);
-  auto ld = [&](const u32* M, int64_t ldm, int k, int col) -> uint4 {
+  auto lda = [&](int k, int col) -> uint4 {
     if (k >= cnt) return inf4;
-    return *reinterpret_cast<const uint4*>(M + (int64_t)(rows ? rows[k] : k) * ldm + col);
+    return *reinterpret_cast<const uint4*>(At + (int64_t)(rows ? rows[k] : k) * ldA + col);
   };
-  uint4 pa0 = ld(At, ldA, r0, c0), pa1 = ld(At, ldA, r1, c1);
-  uint4 pb0 = ld(B, ldB, r0, c0), pb1 = ld(B, ldB, r1, c1);
+  auto ldb = [&](int k, int col) -> uint4 {
+    if (k >= cnt) return inf4;
+    const int32_t r = rows ? rows[k] : k;
+    return *reinterpret_cast<const uint4*>(B + (int64_t)(bmap ? bmap[r] : r) * ldB + col);
+  };
+  uint4 pa0 = lda(r0, c0), pa1 = lda(r1, c1);
+  uint4 pb0 = ldb(r0, c0), pb1 = ldb(r1, c1);
   reinterpret_cast<uint4*>(sA)[e0] = pa0;
   reinterpret_cast<uint4*>(sA)[e1] = pa1;
   reinterpret_cast<uint4*>(sB)[e0] = pb0;
@@ -308,10 +314,10 @@ __device__ __forceinline__ void mp_stream128_rows(u32 (&c)[8][8], const u32* At,
   __syncthreads();
   for (int ch = 0; ch < nch; ch++) {
     const int kn = (ch + 1 < nch ? ch + 1 : ch) * KC;
-    pa0 = ld(At, ldA, kn + r0, c0);
-    pa1 = ld(At, ldA, kn + r1, c1);
-    pb0 = ld(B, ldB, kn + r0, c0);
-    pb1 = ld(B, ldB, kn + r1, c1);
+    pa0 = lda(kn + r0, c0);
+    pa1 = lda(kn + r1, c1);
+    pb0 = ldb(kn + r0, c0);
+    pb1 = ldb(kn + r1, c1);
     const int cur = (ch & 1) * KC * T, nxt = ((ch + 1) & 1) * KC * T;
     minplus_lds<T>(c, sA + cur, sB + cur, KC);
     reinterpret_cast<uint4*>(sA + nxt)[e0] = pa0;
@@ -748,12 +754,10 @@ __global__ void k_dt_init(int32_t V2, int32_t S2, int64_t S2p, int32_t nblk,
 }
 
 // Dirty flags of the Bellman-Ford rounds: per block (a group or a run of
-// groups; m2 / b2off / A below are the block's level-2 count, first level-2
-// id and closed matrix), one word per column tile of 128 share sources, then
-// one word "any tile" (stride ntc + 1).  Beside them, per (block, column
-// tile), the rows (local level-2 indices) that the cross edges lowered since
-// the block's last intra step: a count and a list (count BF_ALL_ROWS: every
-// row).
+// groups), one word per column tile of 128 share sources, then one word "any
+// tile" (stride ntc + 1).  Beside them, per (block, column tile), the B3 rows
+// (indices in the block's b3list) that the cross edges lowered since the
+// block's last intra step: a count and a list (count BF_ALL_ROWS: every row).
 //
 // Intra-block step, in place: the block's rows x column tile of DT = min(DT,
 // A (x) DT) for the (block, tile) pairs whose values changed in the previous
@@ -764,50 +768,9 @@ __global__ void k_dt_init(int32_t V2, int32_t S2, int64_t S2p, int32_t nblk,
 // the block are lowering: every value read is the old or the new one, both
 // lengths of real walks and each at most the old value, and A being closed,
 // the old values already give the closed result, so the step is exact in any
-// interleaving.
-__global__ __launch_bounds__(256) void k_bf_intra(int32_t m2pmax, int64_t S2p,
-                                                  const int32_t* __restrict__ m2,
-                                                  const int32_t* __restrict__ b2off,
-                                                  const u32* __restrict__ A, u32* DT,
-                                                  const u32* __restrict__ dirty,
-                                                  const int32_t* __restrict__ rcnt,
-                                                  const int32_t* __restrict__ rlist) {
-  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
-  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
-  const int s = blockIdx.y;
-  const int32_t ms = m2[s];
-  const int ntc = (int)(S2p / 128);
-  const int ti = (int)blockIdx.x / ntc, tj = (int)blockIdx.x % ntc;
-  if (ti * 128 >= ms || !dirty[(int64_t)s * (ntc + 1) + tj]) return;
-  const int64_t st = (int64_t)s * ntc + tj;
-  const int32_t cnt = rcnt[st];
-  if (cnt == 0) return;
-  const int64_t r0 = b2off[s];
-  u32 c[8][8];
-  tile_load<128>(c, DT + (r0 + ti * 128) * S2p + tj * 128, S2p);  // rows past ms: unused
-  const u32* At = A + (int64_t)s * m2pmax * m2pmax + ti * 128;  // A_S symmetric: At[k][i] = A[i][k]
-  const u32* B = DT + r0 * S2p + tj * 128;
-  // all rows (the share's groups, first round): rows 0 .. ms-1 in order; the
-  // block's columns past ms hold INF, so they need no mask
-  const bool all = cnt == BF_ALL_ROWS;
-  mp_stream128_rows(c, At, m2pmax, B, S2p, all ? nullptr : rlist + st * m2pmax, all ? ms : cnt, sA,
-                    sB);
-  const int tx = tid_x(), ty = tid_y();
-#pragma unroll
-  for (int h = 0; h < 2; h++)
-#pragma unroll
-    for (int a = 0; a < 4; a++) {
-      const int row = ti * 128 + h * 64 + ty * 4 + a;
-      if (row >= ms) continue;
-      u32* dst = DT + (r0 + row) * S2p + tj * 128;
-#pragma unroll
-      for (int h2 = 0; h2 < 2; h2++) {
-        const int i = h * 4 + a, j = h2 * 4;
-        *reinterpret_cast<uint4*>(dst + h2 * 64 + tx * 4) =
-            make_uint4(c[i][j], c[i][j + 1], c[i][j + 2], c[i][j + 3]);
-      }
-    }
-}
+// interleaving.  The rounds run this step on the B3 rows only (k_bf_intra3
+// below, with A restricted to B3 x B3, which is closed as well: a shortest
+// path inside the block between two B3 vertices needs no other row of DT).
 
 // Cross edges between blocks, as directed level-2 pairs (a -> b, w), tagged
 // (source block << 16) | destination block.
@@ -839,11 +802,12 @@ __global__ void k_cross_collect(int64_t m, const int32_t* __restrict__ eu, const
 // changed since they were last propagated need no new pass); a lowered value
 // marks its (block, tile) dirty for the next round and, once per round (the
 // stamp of (row, tile) holds the round that last listed it), adds its row to
-// that (block, tile)'s list (b2off: first level-2 id of each block, m2pmax:
-// list slots per (block, tile)).
+// that (block, tile)'s list as its index among the block's B3 rows (b3rank;
+// a cross edge ends in B3 by definition; lstride: list slots per (block,
+// tile)).
 __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2, int64_t S2p, u32* DT,
                            const u32* __restrict__ dirty, u32* __restrict__ dirty_next,
-                           const int32_t* __restrict__ b2off, int32_t m2pmax, u32 round,
+                           const int32_t* __restrict__ b3rank, int32_t lstride, u32 round,
                            u32* __restrict__ stamp, int32_t* __restrict__ rcnt_next,
                            int32_t* __restrict__ rlist_next) {
   const int32_t e = blockIdx.x;
@@ -876,10 +840,165 @@ __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2,
       if (atomicExch(stamp + (int64_t)t.y * ntc + tile, round) != round) {
         const int64_t st = (int64_t)sv * ntc + tile;
         const int32_t slot = atomicAdd(rcnt_next + st, 1);
-        rlist_next[st * m2pmax + slot] = t.y - b2off[sv];
+        rlist_next[st * lstride + slot] = b3rank[t.y];
       }
     }
   }
+}
+
+// ------------------------------------------------------------- block boundary
+// Only the B3 rows of a block (level-2 vertices with a G edge to another
+// block) are lowered by cross edges and read by them, so the rounds keep
+// just those rows settled; a path from a source to any other row v of block
+// T either stays in T (DT's initial row, from the closed A_T) or enters T
+// last through some b in B3(T), so once the B3 rows are exact
+//   DT[v] = min(DT[v], min over b in B3(T) of A_T[v][b] + DT[b])
+// gives the rest in one product per block.
+
+// flag3[a] = 1 for every source a of a directed cross edge (both directions
+// are listed, so every endpoint); the count is read on the device.
+__global__ void k_b3_mark(const int32_t* __restrict__ xcount, const int4* __restrict__ xe,
+                          uint8_t* __restrict__ flag3) {
+  const int32_t n = *xcount;
+  for (int32_t e = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); e < n;
+       e += (int32_t)(gridDim.x * blockDim.x))
+    flag3[xe[e].x] = 1;
+}
+
+__global__ void k_flag_not(int32_t n, const uint8_t* __restrict__ f, uint8_t* __restrict__ g) {
+  for (int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); i < n;
+       i += (int32_t)(gridDim.x * blockDim.x))
+    g[i] = f[i] ? 0 : 1;
+}
+
+// Row i of block t's A3: A_T[b3[i]][b3[j]] for i, j < m3[t]; INF elsewhere.
+__global__ void k_a3_gather(int32_t bpmax, int32_t b3pmax, const int32_t* __restrict__ m3,
+                            const int32_t* __restrict__ b3list, const u32* __restrict__ A,
+                            u32* __restrict__ A3) {
+  const int t = blockIdx.y;
+  const int32_t i = blockIdx.x, mt = m3[t];
+  const int32_t* bl = b3list + (int64_t)t * bpmax;
+  u32* out = A3 + ((int64_t)t * b3pmax + i) * b3pmax;
+  const u32* arow = i < mt ? A + ((int64_t)t * bpmax + bl[i]) * bpmax : nullptr;
+  for (int32_t j = threadIdx.x; j < b3pmax; j += blockDim.x) out[j] = (arow && j < mt) ? arow[bl[j]] : INF;
+}
+
+// Row k of block t's Aout: A_T[b3[k]][nb3[i]] for k < m3[t], i < n3[t]; INF
+// elsewhere (A_T is symmetric: row b3[k] holds column b3[k]).
+__global__ void k_aout_gather(int32_t bpmax, int32_t b3pmax, int32_t n3pmax,
+                              const int32_t* __restrict__ m3, const int32_t* __restrict__ n3,
+                              const int32_t* __restrict__ b3list, const int32_t* __restrict__ nb3list,
+                              const u32* __restrict__ A, u32* __restrict__ Aout) {
+  const int t = blockIdx.y;
+  const int32_t k = blockIdx.x, nt = n3[t];
+  const int32_t* bl = b3list + (int64_t)t * bpmax;
+  const int32_t* nl = nb3list + (int64_t)t * bpmax;
+  u32* out = Aout + ((int64_t)t * b3pmax + k) * n3pmax;
+  const u32* arow = k < m3[t] ? A + ((int64_t)t * bpmax + bl[k]) * bpmax : nullptr;
+  for (int32_t i = threadIdx.x; i < n3pmax; i += blockDim.x) out[i] = (arow && i < nt) ? arow[nl[i]] : INF;
+}
+
+// The 128 x 128 tile whose row r is g + rows[r] * ld, in the register layout
+// of tile_load; rows r >= nvalid read as INF and are not stored.
+__device__ __forceinline__ void tile_load_rows(u32 (&c)[8][8], const u32* g, int64_t ld,
+                                               const int32_t* __restrict__ rows, int nvalid) {
+  const int tx = tid_x(), ty = tid_y();
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int r = h * 64 + ty * 4 + a;
+      if (r < nvalid) {
+        const u32* row = g + (int64_t)rows[r] * ld + tx * 4;
+#pragma unroll
+        for (int h2 = 0; h2 < 2; h2++) {
+          const uint4 v = *reinterpret_cast<const uint4*>(row + h2 * 64);
+          u32* d = c[h * 4 + a] + h2 * 4;
+          d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; j++) c[h * 4 + a][j] = INF;
+      }
+    }
+}
+
+__device__ __forceinline__ void tile_store_rows(const u32 (&c)[8][8], u32* g, int64_t ld,
+                                                const int32_t* __restrict__ rows, int nvalid) {
+  const int tx = tid_x(), ty = tid_y();
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int r = h * 64 + ty * 4 + a;
+      if (r >= nvalid) continue;
+      u32* row = g + (int64_t)rows[r] * ld + tx * 4;
+#pragma unroll
+      for (int h2 = 0; h2 < 2; h2++) {
+        const u32* v = c[h * 4 + a] + h2 * 4;
+        *reinterpret_cast<uint4*>(row + h2 * 64) = make_uint4(v[0], v[1], v[2], v[3]);
+      }
+    }
+}
+
+// The intra-block step of a round on the B3 rows only (see the Intra-block
+// step above for why the listed rows suffice and why in place is exact): rows
+// b3[ti*128 ..] x column tile tj of block s = min(DT, A3 (x) DT) over the
+// listed B3 rows (their indices in b3list).
+__global__ __launch_bounds__(256) void k_bf_intra3(int32_t bpmax, int32_t b3pmax, int64_t S2p,
+                                                   const int32_t* __restrict__ m3,
+                                                   const int32_t* __restrict__ boff,
+                                                   const int32_t* __restrict__ b3list,
+                                                   const u32* __restrict__ A3, u32* DT,
+                                                   const u32* __restrict__ dirty,
+                                                   const int32_t* __restrict__ rcnt,
+                                                   const int32_t* __restrict__ rlist) {
+  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
+  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
+  const int s = blockIdx.y;
+  const int32_t ms = m3[s];
+  const int ntc = (int)(S2p / 128);
+  const int ti = (int)blockIdx.x / ntc, tj = (int)blockIdx.x % ntc;
+  if (ti * 128 >= ms || !dirty[(int64_t)s * (ntc + 1) + tj]) return;
+  const int64_t st = (int64_t)s * ntc + tj;
+  const int32_t cnt = rcnt[st];
+  if (cnt == 0) return;
+  const int32_t* bl = b3list + (int64_t)s * bpmax;
+  u32* D = DT + (int64_t)boff[s] * S2p + tj * 128;  // the block's rows, this column tile
+  const int nv = min(128, ms - ti * 128);
+  u32 c[8][8];
+  tile_load_rows(c, D, S2p, bl + ti * 128, nv);
+  const u32* At = A3 + (int64_t)s * b3pmax * b3pmax + ti * 128;  // symmetric: At[k][i] = A3[i][k]
+  const bool all = cnt == BF_ALL_ROWS;
+  mp_stream128_rows(c, At, b3pmax, D, S2p, all ? nullptr : rlist + st * b3pmax, all ? ms : cnt, sA, sB,
+                    bl);
+  tile_store_rows(c, D, S2p, bl + ti * 128, nv);
+}
+
+// The rows outside B3, once the rounds have settled: rows nb3[ti*128 ..] x
+// column tile tj of block s = min(DT, Aout^T (x) DT[B3 rows]).
+__global__ __launch_bounds__(256) void k_bf_final(int32_t bpmax, int32_t b3pmax, int32_t n3pmax,
+                                                  int64_t S2p, const int32_t* __restrict__ m3,
+                                                  const int32_t* __restrict__ n3,
+                                                  const int32_t* __restrict__ boff,
+                                                  const int32_t* __restrict__ b3list,
+                                                  const int32_t* __restrict__ nb3list,
+                                                  const u32* __restrict__ Aout, u32* DT) {
+  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
+  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
+  const int s = blockIdx.y;
+  const int32_t nn = n3[s], kk = m3[s];
+  const int ntc = (int)(S2p / 128);
+  const int ti = (int)blockIdx.x / ntc, tj = (int)blockIdx.x % ntc;
+  if (ti * 128 >= nn || kk == 0) return;
+  const int32_t* nl = nb3list + (int64_t)s * bpmax;
+  u32* D = DT + (int64_t)boff[s] * S2p + tj * 128;
+  const int nv = min(128, nn - ti * 128);
+  u32 c[8][8];
+  tile_load_rows(c, D, S2p, nl + ti * 128, nv);
+  const u32* At = Aout + (int64_t)s * b3pmax * n3pmax + ti * 128;  // At[k][i] = A_T[b3[k]][nb3[i]]
+  mp_stream128_rows(c, At, n3pmax, D, S2p, nullptr, kk, sA, sB, b3list + (int64_t)s * bpmax);
+  tile_store_rows(c, D, S2p, nl + ti * 128, nv);
 }
 
 // The share's D2 in column panels: panel S (one per group, S2p x m2pmax
@@ -1083,25 +1202,65 @@ hipError_t launch_share_prepare(const HierArgs& a, const ShareBlocks& b, hipStre
   return hipGetLastError();
 }
 
-// One Bellman-Ford round, in place on DT: intra-block step, then cross edges.
-hipError_t launch_share_round(const HierArgs& a, const ShareBlocks& b, int32_t nxe, const BfRound& r,
-                              hipStream_t s) {
-  const int ntm = b.bpmax / 128, ntc = (int)(a.S2p / 128);
-  k_bf_intra<<<dim3((unsigned)(ntm * ntc), (unsigned)b.nblk), 256, 0, s>>>(
-      b.bpmax, a.S2p, b.bsize, b.boff, b.A, a.DT, r.dirty, r.cnt, r.list);
+hipError_t launch_share_b3_lists(const HierArgs& a, const ShareBlocks& b, uint8_t* flag3,
+                                 uint8_t* flagn, int32_t* b3list, int32_t* nb3list, int32_t* b3rank,
+                                 int32_t* nrank, int32_t* m3, int32_t* n3, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(flag3, 0, (size_t)(a.V2 > 0 ? a.V2 : 1), s);
+  if (e != hipSuccess) return e;
+  if (a.m > 0) k_b3_mark<<<hblocks(2 * a.m), 256, 0, s>>>(a.xcount, a.xe, flag3);
+  if (a.V2 > 0) k_flag_not<<<hblocks(a.V2), 256, 0, s>>>(a.V2, flag3, flagn);
+  k_b2_scan<<<(unsigned)b.nblk, 256, 0, s>>>(b.boff, b.bsize, flag3, b.bpmax, b3list, b3rank, m3);
+  k_b2_scan<<<(unsigned)b.nblk, 256, 0, s>>>(b.boff, b.bsize, flagn, b.bpmax, nb3list, nrank, n3);
+  return hipGetLastError();
+}
+
+hipError_t launch_share_b3_gather(const ShareBlocks& b, const ShareB3& c, hipStream_t s) {
+  k_a3_gather<<<dim3((unsigned)c.b3pmax, (unsigned)b.nblk), 256, 0, s>>>(b.bpmax, c.b3pmax, c.m3,
+                                                                          c.b3list, b.A, c.A3);
+  k_aout_gather<<<dim3((unsigned)c.b3pmax, (unsigned)b.nblk), 256, 0, s>>>(
+      b.bpmax, c.b3pmax, c.n3pmax, c.m3, c.n3, c.b3list, c.nb3list, b.A, c.Aout);
+  return hipGetLastError();
+}
+
+// One Bellman-Ford round, in place on DT: intra-block step on the B3 rows,
+// then cross edges.
+hipError_t launch_share_round(const HierArgs& a, const ShareBlocks& b, const ShareB3& c, int32_t nxe,
+                              const BfRound& r, hipStream_t s) {
+  const int ntm = c.b3pmax / 128, ntc = (int)(a.S2p / 128);
+  k_bf_intra3<<<dim3((unsigned)(ntm * ntc), (unsigned)b.nblk), 256, 0, s>>>(
+      b.bpmax, c.b3pmax, a.S2p, c.m3, b.boff, c.b3list, c.A3, a.DT, r.dirty, r.cnt, r.list);
   if (nxe > 0)
     k_bf_cross<<<(unsigned)nxe, 256, 0, s>>>(nxe, a.xe, a.S2, a.S2p, a.DT, r.dirty, r.dirty_next,
-                                             b.boff, b.bpmax, r.round, r.stamp, r.cnt_next,
+                                             c.b3rank, c.b3pmax, r.round, r.stamp, r.cnt_next,
                                              r.list_next);
   return hipGetLastError();
 }
 
-hipError_t launch_bf_intra(int32_t ngroups, int32_t m2pmax, int64_t S2p, const int32_t* m2,
-                           const int32_t* b2off, const u32* A, u32* DT, const u32* dirty,
-                           const int32_t* rcnt, const int32_t* rlist, hipStream_t s) {
-  const int ntm = m2pmax / 128, ntc = (int)(S2p / 128);
-  k_bf_intra<<<dim3((unsigned)(ntm * ntc), (unsigned)ngroups), 256, 0, s>>>(m2pmax, S2p, m2, b2off, A,
-                                                                            DT, dirty, rcnt, rlist);
+hipError_t launch_share_final(const HierArgs& a, const ShareBlocks& b, const ShareB3& c,
+                              hipStream_t s) {
+  const int ntm = c.n3pmax / 128, ntc = (int)(a.S2p / 128);
+  k_bf_final<<<dim3((unsigned)(ntm * ntc), (unsigned)b.nblk), 256, 0, s>>>(
+      b.bpmax, c.b3pmax, c.n3pmax, a.S2p, c.m3, c.n3, b.boff, c.b3list, c.nb3list, c.Aout, a.DT);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf_rows(int32_t ngroups, int32_t lstride, int32_t kp, int64_t ldc,
+                          const int32_t* nk, const int32_t* zero, const int32_t* own, const u32* A,
+                          u32* C, const u32* dirty, const int32_t* rcnt, const int32_t* rlist,
+                          hipStream_t s) {
+  const int ntm = kp / 128, ntc = (int)(ldc / 128);
+  k_bf_intra3<<<dim3((unsigned)(ntm * ntc), (unsigned)ngroups), 256, 0, s>>>(
+      lstride, kp, ldc, nk, zero, own, A, C, dirty, rcnt, rlist);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf_gather(int32_t ngroups, int32_t lstride, int32_t kp, int32_t np, int64_t ldc,
+                            const int32_t* nk, const int32_t* nout, const int32_t* zero,
+                            const int32_t* own, const int32_t* out, const u32* Aout, u32* C,
+                            hipStream_t s) {
+  const int ntm = np / 128, ntc = (int)(ldc / 128);
+  k_bf_final<<<dim3((unsigned)(ntm * ntc), (unsigned)ngroups), 256, 0, s>>>(
+      lstride, kp, np, ldc, nk, nout, zero, own, out, Aout, C);
   return hipGetLastError();
 }
 

@@ -122,10 +122,33 @@ struct ShareBlocks {
   u32* A;
 };
 hipError_t launch_share_prepare(const HierArgs& a, const ShareBlocks& b, hipStream_t s);
-// One Bellman-Ford round of the share.  dirty flags: per block, ntc = S2p /
-// 128 column tiles then one "any" word; cnt / list: per (block, tile) the
-// number of rows lowered since the last intra step (BF_ALL_ROWS: all) and
-// their local indices (bpmax slots each); stamp: V2p x ntc round stamps.
+// The blocks' boundary B3: level-2 vertices with a G edge to another block,
+// the only rows a cross edge lowers.  Lists hold local indices into a
+// block's rows (bpmax slots per block): b3list the B3 rows, nb3list the
+// others, both ascending; b3rank[level-2 id] = index in b3list (-1: not B3);
+// m3 / n3 their counts.  A3: nblk x b3pmax x b3pmax, the closed block matrix
+// on B3 x B3; Aout: nblk x b3pmax x n3pmax, on B3 (rows) x the other rows.
+struct ShareB3 {
+  int32_t b3pmax, n3pmax;
+  const int32_t *m3, *n3, *b3list, *nb3list, *b3rank;
+  u32 *A3, *Aout;
+};
+// flags from the cross edges (after launch_share_prepare), then the lists;
+// flag3 / flagn: V2 bytes, nrank: V2 words of scratch
+hipError_t launch_share_b3_lists(const HierArgs& a, const ShareBlocks& b, uint8_t* flag3,
+                                 uint8_t* flagn, int32_t* b3list, int32_t* nb3list, int32_t* b3rank,
+                                 int32_t* nrank, int32_t* m3, int32_t* n3, hipStream_t s);
+// A3 and Aout gathered from the closed block matrices
+hipError_t launch_share_b3_gather(const ShareBlocks& b, const ShareB3& c, hipStream_t s);
+// After the rounds: rows outside B3 from the settled B3 rows,
+//   DT[v] = min(DT[v], min over b in B3(T) of A_T[v][b] + DT[b])
+hipError_t launch_share_final(const HierArgs& a, const ShareBlocks& b, const ShareB3& c,
+                              hipStream_t s);
+// One Bellman-Ford round of the share, on the B3 rows of every block.  dirty
+// flags: per block, ntc = S2p / 128 column tiles then one "any" word; cnt /
+// list: per (block, tile) the number of B3 rows lowered since the last intra
+// step (BF_ALL_ROWS: all) and their indices in b3list (b3pmax slots each);
+// stamp: V2p x ntc round stamps.
 constexpr int32_t BF_ALL_ROWS = 0x7fffffff;
 constexpr int BF_LDS_TILES = 2048;  // column tiles a cross-edge workgroup tracks in LDS
 struct BfRound {
@@ -138,8 +161,8 @@ struct BfRound {
   u32* stamp;
   u32 round;
 };
-hipError_t launch_share_round(const HierArgs& a, const ShareBlocks& b, int32_t nxe, const BfRound& r,
-                              hipStream_t s);
+hipError_t launch_share_round(const HierArgs& a, const ShareBlocks& b, const ShareB3& c, int32_t nxe,
+                              const BfRound& r, hipStream_t s);
 hipError_t launch_share_compose(const HierArgs& a, const u32* DT, hipStream_t s);
 hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s);
 // Flat method: per-BG-vertex layout terms, then the closed BG matrix (Vp x Vp)
@@ -183,9 +206,18 @@ hipError_t launch_level3_b(const L3Args& a, hipStream_t s);
 // BG2), a.chunk pairs per launch
 hipError_t launch_level3_compose(const L3Args& a, hipStream_t s);
 // the intra-group product of one Bellman-Ford round of the share, on its own
-hipError_t launch_bf_intra(int32_t ngroups, int32_t m2pmax, int64_t S2p, const int32_t* m2,
-                           const int32_t* b2off, const u32* A, u32* DT, const u32* dirty,
-                           const int32_t* rcnt, const int32_t* rlist, hipStream_t s);
+// The two Bellman-Ford products on caller buffers (test hooks): k_bf_intra3
+// with group g owning rows own[g*lstride ..] of C and A[g] kp x kp, every
+// tile dirty; k_bf_final with K rows own[g*lstride ..], output rows
+// out[g*lstride ..] and Aout[g] kp x np.  zero: ngroups zeros (row offsets).
+hipError_t launch_bf_rows(int32_t ngroups, int32_t lstride, int32_t kp, int64_t ldc,
+                          const int32_t* nk, const int32_t* zero, const int32_t* own, const u32* A,
+                          u32* C, const u32* dirty, const int32_t* rcnt, const int32_t* rlist,
+                          hipStream_t s);
+hipError_t launch_bf_gather(int32_t ngroups, int32_t lstride, int32_t kp, int32_t np, int64_t ldc,
+                            const int32_t* nk, const int32_t* nout, const int32_t* zero,
+                            const int32_t* own, const int32_t* out, const u32* Aout, u32* C,
+                            hipStream_t s);
 hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s);
 
 // Exactness certificate (range.hip).

@@ -90,7 +90,8 @@ _SIGS = {
     "spq_fw_dense": (I32, [I32, I32, I32, I32, I32, P, P]),
     "spq_valu_rates": (I32, [P, P]),
     "spq_minplus_batched": (I32, [I32, I32, P, P, I32, I32, P, P, I64, P, I32, P, I32, P, I64, P]),
-    "spq_minplus_rows": (I32, [I32, P, I32, P, P, I64, P, P, P]),
+    "spq_minplus_rows": (I32, [I32, P, I32, P, P, I64, P, P, P, P]),
+    "spq_minplus_gather": (I32, [I32, P, P, I32, I32, P, P, I64, P, P, P]),
     "spq_server_create": (I32, [P, I32, I64, I64, P]),
     "spq_server_submit": (I32, [P, I64, P, P, P, P]),
     "spq_server_poll": (I32, [P, I64, I32, P, P]),
@@ -432,16 +433,40 @@ def minplus_batched(layout, nv, nk, vp, kp, R, D, ldd, M, pairs, out, cb=1, ldo=
     return out
 
 
-def minplus_rows(nk, kp, A, C, ldc, cnt, rows=None, stream=None):
-    """The in-place intra-group product of the share's Bellman-Ford rounds on
-    device tensors (see spq_minplus_rows): nk, cnt and rows on the host.
-    Synchronous."""
+def minplus_rows(nk, kp, A, C, ldc, cnt, rows=None, own=None, stream=None):
+    """The in-place intra-block product of the share's Bellman-Ford rounds on
+    device tensors (see spq_minplus_rows): nk, cnt, rows and own on the
+    host.  Synchronous."""
     nk = np.ascontiguousarray(nk, np.int32)
     cnt = np.ascontiguousarray(cnt, np.int32)
     rows = np.ascontiguousarray(rows if rows is not None else np.zeros(0), np.int32)
     if nk.shape != cnt.shape or nk.ndim != 1:
         raise ValueError("nk and cnt must be 1-d and equally long")
+    own_p = None
+    if own is not None:
+        own = np.ascontiguousarray(own, np.int32)
+        if own.shape != (int(nk.sum()),):
+            raise ValueError("own must hold sum(nk) rows")
+        own_p = own.ctypes.data
     _check(load().spq_minplus_rows(len(nk), nk.ctypes.data, int(kp), _dev_i32(A, "A"),
                                    _dev_i32(C, "C"), int(ldc), cnt.ctypes.data, rows.ctypes.data,
-                                   _stream(stream)))
+                                   own_p, _stream(stream)))
+    return C
+
+
+def minplus_gather(nk, nout, kp, np_, Aout, C, ldc, own, out, stream=None):
+    """The last product of the share's Bellman-Ford stage on device tensors
+    (see spq_minplus_gather): nk, nout, own and out on the host.
+    Synchronous."""
+    nk = np.ascontiguousarray(nk, np.int32)
+    nout = np.ascontiguousarray(nout, np.int32)
+    own = np.ascontiguousarray(own, np.int32)
+    out = np.ascontiguousarray(out, np.int32)
+    if nk.shape != nout.shape or nk.ndim != 1:
+        raise ValueError("nk and nout must be 1-d and equally long")
+    if own.shape != (int(nk.sum()),) or out.shape != (int(nout.sum()),):
+        raise ValueError("own / out must hold sum(nk) / sum(nout) rows")
+    _check(load().spq_minplus_gather(len(nk), nk.ctypes.data, nout.ctypes.data, int(kp), int(np_),
+                                     _dev_i32(Aout, "Aout"), _dev_i32(C, "C"), int(ldc),
+                                     own.ctypes.data, out.ctypes.data, _stream(stream)))
     return C

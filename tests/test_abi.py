@@ -87,17 +87,35 @@ def test_minplus_hooks_reject_bad_arguments_without_device():
     assert call(npairs=0) == 0
     cnt = np.array([-1, 0], np.int32)
     assert L.spq_minplus_rows(2, nk.ctypes.data, 100, dummy, dummy, 128, cnt.ctypes.data, None,
-                              None) == 1
+                              None, None) == 1
     assert L.spq_minplus_rows(2, nk.ctypes.data, 128, dummy, dummy, 128,
-                              np.array([6, 0], np.int32).ctypes.data, None, None) == 1
+                              np.array([6, 0], np.int32).ctypes.data, None, None, None) == 1
     assert "listed rows" in spq.last_error()
     assert L.spq_minplus_rows(2, nk.ctypes.data, 128, dummy, dummy, 128,
-                              np.array([2, 0], np.int32).ctypes.data, None, None) == 1
+                              np.array([2, 0], np.int32).ctypes.data, None, None, None) == 1
     assert "rows is NULL" in spq.last_error()
     rows = np.array([1, 5], np.int32)
     assert L.spq_minplus_rows(2, nk.ctypes.data, 128, dummy, dummy, 128,
-                              np.array([2, 0], np.int32).ctypes.data, rows.ctypes.data, None) == 1
+                              np.array([2, 0], np.int32).ctypes.data, rows.ctypes.data, None,
+                              None) == 1
     assert "outside its group" in spq.last_error()
+    own = np.array([0, 1, 2, -3, 4], np.int32)
+    assert L.spq_minplus_rows(2, nk.ctypes.data, 128, dummy, dummy, 128, cnt.ctypes.data, None,
+                              own.ctypes.data, None) == 1
+    assert "negative row" in spq.last_error()
+    nout = np.array([3, 0], np.int32)
+    out = np.array([7, 8, 9], np.int32)
+    own = np.arange(5, dtype=np.int32)
+
+    def gather(nk=nk, nout=nout, kp=128, np_=128, ldc=128, own=own, out=out):
+        return L.spq_minplus_gather(2, nk.ctypes.data, nout.ctypes.data, kp, np_, dummy, dummy, ldc,
+                                    own.ctypes.data if own is not None else None,
+                                    out.ctypes.data if out is not None else None, None)
+    assert gather(np_=100) == 1 and "multiples of 128" in spq.last_error()
+    assert gather(ldc=64) == 1 and "ldc" in spq.last_error()
+    assert gather(nout=np.array([129, 0], np.int32)) == 1 and "nout" in spq.last_error()
+    assert gather(own=None) == 1 and "null row list" in spq.last_error()
+    assert gather(out=np.array([7, -8, 9], np.int32)) == 1 and "negative row" in spq.last_error()
 
 
 def test_python_binding_rejects_host_tensors():

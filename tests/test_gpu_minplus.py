@@ -5,7 +5,9 @@ product (bit-exact).
 spq_minplus_batched runs the group-level composition (Algorithm 2 one level
 up, Lemma 3): the first product into the scratch table and the second into
 the query layout (blocked) or densely (level 3).  spq_minplus_rows runs the
-in-place intra-group product of the share's Bellman-Ford rounds.  Operands
+in-place intra-block product of the share's Bellman-Ford rounds, on rows a
+block owns anywhere in the table; spq_minplus_gather the product that then
+fills the block's other rows from its boundary rows.  Operands
 are INF-heavy, near INF, with boundary counts that are not multiples of 16,
 ragged 128-tiles, empty groups and padding that holds arbitrary values in
 [0, INF].
@@ -186,16 +188,23 @@ def closed_group_matrix(rng, n, kp, kind):
     (3, [200, 255, 3], 256, "near_inf"),
 ])
 @pytest.mark.parametrize("listed", [False, True])
-def test_bellman_ford_intra_product_equals_oracle(seed, nk, kp, kind, listed):
+@pytest.mark.parametrize("scattered", [False, True])
+def test_bellman_ford_intra_product_equals_oracle(seed, nk, kp, kind, listed, scattered):
+    """Groups own consecutive rows of C, or (scattered) rows spread over a
+    larger C in random order, as a block's boundary rows are among its
+    rows; rows of C no group owns stay as they are."""
     import torch
     rng = np.random.default_rng(seed)
     nk = np.array(nk, np.int32)
     G = len(nk)
     koff = np.concatenate([[0], np.cumsum(nk)]).astype(np.int64)
     ldc = 256  # two column tiles
-    rows_total = int(koff[-1]) + 128
+    K = int(koff[-1])
+    rows_total = 2 * K + 77 if scattered else K + 128
+    own = (rng.permutation(rows_total)[:K] if scattered else np.arange(K)).astype(np.int64)
     A = np.stack([closed_group_matrix(rng, int(nk[g]), kp, kind) for g in range(G)])
-    C = values(rng, (rows_total, ldc), kind)
+    C0 = values(rng, (rows_total, ldc), kind)
+    C = C0[own].copy()   # the owned rows, group by group
     cnt = np.full(G, -1, np.int32)
     rows = []
     if listed:
@@ -230,8 +239,53 @@ def test_bellman_ford_intra_product_equals_oracle(seed, nk, kp, kind, listed):
         else:
             prod = oracle.minplus(Ag, Cg)
         want[sl] = to32(np.minimum(Cg, prod))
-    print("case", seed, "listed", listed, "nk", nk.tolist(), flush=True)
-    dC = dev(C)
-    spq.minplus_rows(nk, kp, dev(A), dC, ldc, cnt, np.array(rows, np.int32))
+    print("case", seed, "listed", listed, "scattered", scattered, "nk", nk.tolist(), flush=True)
+    C0[own] = C
+    full_want = C0.copy()
+    full_want[own] = want
+    dC = dev(C0)
+    spq.minplus_rows(nk, kp, dev(A), dC, ldc, cnt, np.array(rows, np.int32),
+                     own=own.astype(np.int32) if scattered else None)
     got = dC.cpu().numpy()
-    assert np.array_equal(got, want.astype(np.int32))
+    assert np.array_equal(got, full_want.astype(np.int32))
+
+
+@pytest.mark.parametrize("seed,nk,nout,kp,np_,kind", [
+    (1, [50, 0, 129, 17], [100, 7, 0, 128], 256, 128, "plain"),
+    (2, [128, 1, 33], [300, 1, 256], 128, 384, "inf_heavy"),
+    (3, [16, 255, 3], [5, 129, 250], 256, 256, "near_inf"),
+])
+def test_bellman_ford_final_product_equals_oracle(seed, nk, nout, kp, np_, kind):
+    """The product that fills a block's other rows from its settled boundary
+    rows: C[out_g[i]] = min(C[out_g[i]], min over k of Aout[g][k][i] +
+    C[own_g[k]]), with own and out disjoint rows of C in random order and
+    padding of Aout holding arbitrary values."""
+    import torch
+    rng = np.random.default_rng(seed)
+    nk = np.array(nk, np.int32)
+    nout = np.array(nout, np.int32)
+    G = len(nk)
+    ldc = 384  # three column tiles
+    K, O = int(nk.sum()), int(nout.sum())
+    rows_total = K + O + 50
+    perm = rng.permutation(rows_total)
+    own, out = perm[:K].astype(np.int64), perm[K:K + O].astype(np.int64)
+    Aout = rng.integers(0, INF, (G, kp, np_), dtype=np.int64)
+    koff = np.concatenate([[0], np.cumsum(nk)]).astype(np.int64)
+    ooff = np.concatenate([[0], np.cumsum(nout)]).astype(np.int64)
+    for g in range(G):
+        Aout[g, :nk[g], :nout[g]] = values(rng, (nk[g], nout[g]), kind)
+    C = values(rng, (rows_total, ldc), kind)
+    want = C.copy()
+    for g in range(G):
+        if not nout[g] or not nk[g]:
+            continue
+        og = own[koff[g]:koff[g + 1]]
+        qg = out[ooff[g]:ooff[g + 1]]
+        prod = oracle.minplus(to64(Aout[g, :nk[g], :nout[g]]).T.copy(), to64(C[og]))
+        want[qg] = to32(np.minimum(to64(C[qg]), prod))
+    print("case", seed, "nk", nk.tolist(), "nout", nout.tolist(), flush=True)
+    dC = dev(C)
+    spq.minplus_gather(nk, nout, kp, np_, dev(Aout), dC, ldc, own.astype(np.int32),
+                       out.astype(np.int32))
+    assert np.array_equal(dC.cpu().numpy(), want.astype(np.int32))
