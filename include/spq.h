@@ -451,8 +451,16 @@ spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int3
  *   R         G x kp x vp int32: R[g][a][x] at R[(g*kp + a)*vp + x]
  *   D         rows and columns koff[G] at least, leading dimension ldd >=
  *             koff[G] (may be NULL when koff[G] = 0)
+ *   Dt        D transposed, same leading dimension: read when assoc != 0
+ *             (NULL otherwise)
  *   M         G x vp x vp int32: M[g][x][y] at M[(g*vp + x)*vp + y]
  *   pairs     HOST array of 2*npairs group ids (S1, S2), no pair twice
+ *   assoc     0: every pair through B2(S2) (the first product over B2(S1));
+ *             2: every pair with S1 != S2 through B2(S1) instead (the
+ *             products' roles exchanged, the first one reading Dt, the tile
+ *             stored transposed); 1: per pair whichever costs fewer executed
+ *             relaxations, as a share build chooses (1 and 2 need
+ *             SPQ_MP_BLOCKED).  The result does not depend on it.
  *   out       SPQ_MP_BLOCKED: pair p's nv[S1] x nv[S2] values start at element
  *             obase[p] = sum over earlier pairs q of nv[S1_q]*nv[S2_q]; each
  *             group is cut into consecutive runs ("components") of cb
@@ -472,8 +480,9 @@ spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int3
 #define SPQ_MP_DENSE 1
 spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv, const int32_t* nk,
                                int32_t vp, int32_t kp, const int32_t* R, const int32_t* D,
-                               int64_t ldd, const int32_t* M, int32_t npairs, const int32_t* pairs,
-                               int32_t cb, int32_t* out, int64_t ldo, void* stream);
+                               const int32_t* Dt, int64_t ldd, const int32_t* M, int32_t npairs,
+                               const int32_t* pairs, int32_t assoc, int32_t cb, int32_t* out,
+                               int64_t ldo, void* stream);
 
 /*
  * Test hook: the intra-block product of the share build's Bellman-Ford

@@ -334,13 +334,16 @@ static hipError_t graph_segment(spq_index* X, hipStream_t s, F&& body) {
 // 4 GiB], at least one slot.
 static hipError_t make_pairs(int32_t rows, int32_t G, bool upper, int64_t slot_elems,
                              int64_t out_elems, int2** dev, int32_t* npairs, int32_t* chunk,
-                             hipStream_t s) {
+                             hipStream_t s, const std::vector<uint8_t>* swap = nullptr) {
   const int64_t count = upper ? (int64_t)rows * (2 * (int64_t)G - rows + 1) / 2 : (int64_t)rows * G;
   if (count > 0x7fffffff) return hipErrorOutOfMemory;  // pair list beyond int32 indexing
   std::vector<int2> h;
   h.reserve((size_t)count);
+  // swap (optional, rows x G flags in this order): pairs computed through
+  // the row group's boundary (PAIR_SWAP)
   for (int32_t a1 = 0; a1 < rows; a1++)
-    for (int32_t a2 = upper ? a1 : 0; a2 < G; a2++) h.push_back(make_int2(a1, a2));
+    for (int32_t a2 = upper ? a1 : 0; a2 < G; a2++)
+      h.push_back(swap && (*swap)[h.size()] ? make_int2(a2, a1 | spq::PAIR_SWAP) : make_int2(a1, a2));
   *npairs = (int32_t)h.size();
   // pairs per launch: XT slots within 4 GiB, and the grid's y dimension
   const int64_t budget = std::min<int64_t>((int64_t)1 << 30,
@@ -434,9 +437,21 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
                          s));
   HIP_TRY(hipMemcpyAsync(X->gblk, X->h_gblk.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
   HIP_TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
+  // each output block (S1, S2) through the cheaper boundary: the products
+  // cost tiles(m2[S2]) tiles(V_S1) m2[S1] + tiles(V_S1) tiles(V_S2) m2[S2]
+  // through B2(S2), the same with S1 and S2 exchanged through B2(S1) (its
+  // first product then reads D2 transposed, which is the Bellman-Ford table)
+  auto t128 = [](int32_t v) { return (double)((v + 127) / 128); };
+  auto cost = [&](int32_t a, int32_t b) {
+    return t128(X->h_m2[b]) * t128(X->h_gV[a]) * (double)round_up(X->h_m2[a], 16) +
+           t128(X->h_gV[a]) * t128(X->h_gV[b]) * (double)round_up(X->h_m2[b], 16);
+  };
+  std::vector<uint8_t> swap((size_t)X->share_groups * G, 0);
+  for (int32_t a1 = 0; a1 < X->share_groups; a1++)
+    for (int32_t a2 = 0; a2 < G; a2++)
+      swap[(size_t)a1 * G + a2] = a1 != a2 && cost(a2, a1) < cost(a1, a2);
   HIP_TRY(make_pairs(X->share_groups, G, false, (int64_t)X->m2pmax * Vgp, X->h_elems, &X->plist,
-                     &X->npairs,
-                     &X->chunk, s));
+                     &X->npairs, &X->chunk, s, &swap));
   HIP_TRY(dalloc(&X->XT, (int64_t)X->chunk * X->m2pmax * Vgp));
   HIP_TRY(dalloc(&X->A, (int64_t)NB * BP * BP));
   // the Bellman-Ford matrix carries 128 spare rows: a row tile may start at
@@ -473,6 +488,7 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
   ha.plist = X->plist; ha.npairs = X->npairs; ha.chunk = X->chunk;
   ha.share_groups = X->share_groups; ha.S2 = X->S2; ha.S2p = X->S2p; ha.DT = X->DT;
+  ha.D2t = X->DT; ha.d2tld = X->S2p;
   ha.xe = X->xe; ha.xcount = X->xcount;
   const spq::ShareBlocks blk{NB, BP, multi, X->bfirst, X->gblk, X->boff, X->bsize, X->A};
   HIP_TRY(spq::launch_share_prepare(ha, blk, s));
@@ -579,8 +595,10 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
     if (X->h_sbm[t] > 0)
       X->relax_bg_exec += (double)((X->h_sbn[t] + 127) / 128) * ntc * 128.0 * 128.0 *
                           (double)round_up(X->h_sbm[t], 16);
-  for (int32_t a1 = 0; a1 < X->share_groups; a1++)
-    for (int32_t a2 = 0; a2 < G; a2++) {
+  for (int32_t p1 = 0; p1 < X->share_groups; p1++)
+    for (int32_t p2 = 0; p2 < G; p2++) {
+      const bool sw = swap[(size_t)p1 * G + p2];
+      const int32_t a1 = sw ? p2 : p1, a2 = sw ? p1 : p2;  // the products' roles
       X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * ((X->h_gV[a1] + 127) / 128) *
                           128.0 * 128.0 * (double)round_up(X->h_m2[a1], 16);
       const double y = (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
@@ -1682,9 +1700,12 @@ spq_status spq_fw_dense(int32_t v, int32_t ld, int32_t tile, int32_t pivot, int3
 // Group-level composition products on caller buffers (see spq.h).
 spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv, const int32_t* nk,
                                int32_t vp, int32_t kp, const int32_t* R, const int32_t* D,
-                               int64_t ldd, const int32_t* M, int32_t npairs, const int32_t* pairs,
-                               int32_t cb, int32_t* out, int64_t ldo, void* stream) {
+                               const int32_t* Dt, int64_t ldd, const int32_t* M, int32_t npairs,
+                               const int32_t* pairs, int32_t assoc, int32_t cb, int32_t* out,
+                               int64_t ldo, void* stream) {
   if (layout != SPQ_MP_BLOCKED && layout != SPQ_MP_DENSE) return fail(SPQ_EINVAL, "bad layout");
+  if (assoc < 0 || assoc > 2 || (assoc && layout != SPQ_MP_BLOCKED))
+    return fail(SPQ_EINVAL, "assoc must be 0, or 1 or 2 with SPQ_MP_BLOCKED");
   if (groups < 1 || groups > 4096) return fail(SPQ_EINVAL, "groups must be in [1, 4096]");
   if (vp < 128 || vp % 128 || kp < 128 || kp % 128)
     return fail(SPQ_EINVAL, "vp and kp must be positive multiples of 128");
@@ -1698,8 +1719,8 @@ spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv
     koff[g + 1] = koff[g] + nk[g];
     voff[g + 1] = voff[g] + nv[g];
   }
-  if (koff[groups] > 0 && (!D || ldd < koff[groups]))
-    return fail(SPQ_EINVAL, "D is NULL or ldd below the total boundary rows");
+  if (koff[groups] > 0 && (!D || ldd < koff[groups] || (assoc && !Dt)))
+    return fail(SPQ_EINVAL, "D (or Dt) is NULL or ldd below the total boundary rows");
   if (layout == SPQ_MP_BLOCKED && cb < 1) return fail(SPQ_EINVAL, "cb < 1");
   if (layout == SPQ_MP_DENSE && ldo < voff[groups]) return fail(SPQ_EINVAL, "ldo below the total vertices");
   std::vector<int2> plist(npairs);
@@ -1713,7 +1734,14 @@ spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv
       return fail(SPQ_EINVAL, "pair " + std::to_string(p) + " repeats an earlier pair");
     pairbase[(size_t)s1 * groups + s2] = obase;
     obase += (int64_t)nv[s1] * nv[s2];
-    plist[p] = make_int2(s1, s2);
+    // through B2(S1) instead of B2(S2): the products' roles exchanged
+    auto t128 = [](int32_t v) { return (int64_t)((v + 127) / 128); };
+    auto cost = [&](int32_t a, int32_t b) {
+      return t128(nk[b]) * t128(nv[a]) * round_up(nk[a], 16) +
+             t128(nv[a]) * t128(nv[b]) * round_up(nk[b], 16);
+    };
+    const bool sw = s1 != s2 && (assoc == 2 || (assoc == 1 && cost(s2, s1) < cost(s1, s2)));
+    plist[p] = sw ? make_int2(s2, s1 | spq::PAIR_SWAP) : make_int2(s1, s2);
   }
   if (npairs == 0) return SPQ_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1778,6 +1806,7 @@ spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv
     a.Mg = const_cast<u32*>(reinterpret_cast<const u32*>(M));
     a.XT = d_xt; a.H = reinterpret_cast<u32*>(out); a.pairbase = d_pb;
     a.bgrow = d_row; a.bgnb = d_cnb; a.bglocal = d_loc;
+    a.D2t = koff[groups] > 0 && Dt ? reinterpret_cast<const u32*>(Dt) : dD; a.d2tld = ld;
     a.plist = d_plist; a.npairs = npairs; a.chunk = chunk;
     HIP_TRY(spq::launch_hier_level2_compose(a, s));
   }

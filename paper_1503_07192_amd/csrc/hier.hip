@@ -382,18 +382,23 @@ __device__ __forceinline__ int comp_tile() {
 // Rows b in [m2[S2], round16(m2[S2])) are stored as INF.  The composition
 // reads rows below round16(m2[S2]) and column tiles below gV[S1] only, so
 // tiles past those are neither computed nor written.
+// A pair flagged PAIR_SWAP reads D2[B2(s1)][B2(s2)] from the transposed
+// table D2t (rows: level-2 ids, leading dimension ldt; with a column mask,
+// as D2t's columns past B2(s2) belong to other groups).
 __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restrict__ plist, int32_t pbase,
                                                int32_t Vgp, int32_t m2pmax,
                                                const int32_t* __restrict__ m2,
                                                const int32_t* __restrict__ gV,
                                                const int32_t* __restrict__ b2off,
                                                const u32* __restrict__ BG2, int64_t ldd,
-                                               int64_t pstride,
+                                               int64_t pstride, const u32* __restrict__ D2t,
+                                               int64_t ldt,
                                                const u32* __restrict__ R, u32* __restrict__ XT) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
   const int2 pr = plist[pbase + (int32_t)blockIdx.y];
-  const int32_t s1 = pr.x, s2 = pr.y;
+  const bool sw = (pr.y & PAIR_SWAP) != 0;
+  const int32_t s1 = pr.x, s2 = pr.y & ~PAIR_SWAP;
   const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
   const int tile = comp_tile();
@@ -403,12 +408,17 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
   u32 c[8][8];
   fill_inf(c);
   {
-    const u32* At = BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd +
-                    (pstride ? 0 : b2off[s2]) + ti * 128;
     const u32* B = R + (int64_t)s1 * m2pmax * Vgp + tj * 128;
-    // a panel holds INF past its group's B2 vertices: no column mask there
-    mp_stream128<true>(c, At, ldd, B, Vgp, (ka + 15) / 16 * 16, ka, pstride ? 128 : mb - ti * 128,
-                       sA, sB);
+    if (sw) {
+      const u32* At = D2t + (int64_t)b2off[s1] * ldt + b2off[s2] + ti * 128;
+      mp_stream128<true>(c, At, ldt, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB);
+    } else {
+      const u32* At = BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd +
+                      (pstride ? 0 : b2off[s2]) + ti * 128;
+      // a panel holds INF past its group's B2 vertices: no column mask there
+      mp_stream128<true>(c, At, ldd, B, Vgp, (ka + 15) / 16 * 16, ka, pstride ? 128 : mb - ti * 128,
+                         sA, sB);
+    }
   }
   u32* out = XT + (slot * m2pmax + ti * 128) * Vgp + tj * 128;
   const int tx = tid_x(), ty = tid_y();
@@ -426,6 +436,19 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
         *reinterpret_cast<uint4*>(out + (int64_t)row * Vgp + h2 * 64 + tx * 4) = v;
       }
     }
+}
+
+// The certificate's per-wave reduction: largest finite value, and whether
+// an INF joins two vertices connected in G.
+__device__ __forceinline__ void cert_reduce(u32 best, u32 wrong, u32* cert_bad, u32* cert_mbg) {
+  for (int o = 32; o > 0; o >>= 1) {
+    best = max(best, (u32)__shfl_xor((int)best, o));
+    wrong |= (u32)__shfl_xor((int)wrong, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (best) atomicMax(cert_mbg, best);
+    if (wrong) atomicOr(cert_bad, 1u);
+  }
 }
 
 // D(S1,S2) tile (rows x of S1, columns y of S2) for the pair of blockIdx.y:
@@ -454,7 +477,8 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
   const int2 pr = plist[pbase + (int32_t)blockIdx.y];
-  const int32_t s1 = pr.x, s2 = pr.y;
+  const bool sw = (pr.y & PAIR_SWAP) != 0;
+  const int32_t s1 = pr.x, s2 = pr.y & ~PAIR_SWAP;
   const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
   const int tile = comp_tile();
@@ -471,9 +495,49 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict
   // in first, it kept a second copy of the tile live through the K loop
   if (s1 == s2)
     tile_min128(c, Mg + (int64_t)s1 * Vgp * Vgp + (int64_t)ti * 128 * Vgp + tj * 128, Vgp);
-  u32* base = H + pairbase[(int64_t)s1 * ngroups + s2];
   const int tx = tid_x(), ty = tid_y();
   const int32_t g1 = gbg0[s1], g2 = gbg0[s2];
+  if (sw) {
+    // the tile holds block (s2, s1) transposed: row x of s1 here is column x
+    // of the stored block (s2, s1), column y of s2 its row
+    u32* base = H + pairbase[(int64_t)s2 * ngroups + s1];
+    u32 rx[8], nx[8], lx[8];  // row terms of the stored block, from the columns
+    int32_t collab[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int32_t y = tj * 128 + (j >> 2) * 64 + tx * 4 + (j & 3);
+      const int32_t yg = g2 + (y < V2 ? y : 0);
+      rx[j] = (u32)bgrow[yg] * (u32)V1;
+      nx[j] = (u32)bgnb[yg];
+      lx[j] = (u32)bglocal[yg];
+      if (CERT) collab[j] = bglabel[yg];
+    }
+    u32 best = 0, wrong = 0;
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int a = 0; a < 4; a++) {
+        const int32_t x = ti * 128 + h * 64 + ty * 4 + a;
+        if (x >= V1) continue;
+        const int32_t xg = g1 + x;
+        const u32 ry = (u32)bgrow[xg], ny = (u32)bgnb[xg], ly = (u32)bglocal[xg];
+        const int32_t labx = CERT ? bglabel[xg] : 0;
+        const int i = h * 4 + a;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const int32_t y = tj * 128 + (j >> 2) * 64 + tx * 4 + (j & 3);
+          if (y >= V2) continue;
+          base[rx[j] + __umul24(nx[j], ry) + __umul24(lx[j], ny) + ly] = c[i][j];
+          if (CERT) {
+            if (c[i][j] < INF) best = max(best, c[i][j]);
+            else wrong |= (u32)(collab[j] == labx);
+          }
+        }
+      }
+    if (CERT) cert_reduce(best, wrong, cert_bad, cert_mbg);
+    return;
+  }
+  u32* base = H + pairbase[(int64_t)s1 * ngroups + s2];
   // column terms: rowoff(y), nb(y), loc(y) (and the label for the certificate)
   u32 ry[8], ny[8], ly[8];
   int32_t collab[8];
@@ -512,16 +576,7 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict
         }
       }
     }
-  if (CERT) {
-    for (int o = 32; o > 0; o >>= 1) {
-      best = max(best, (u32)__shfl_xor((int)best, o));
-      wrong |= (u32)__shfl_xor((int)wrong, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-      if (best) atomicMax(cert_mbg, best);
-      if (wrong) atomicOr(cert_bad, 1u);
-    }
-  }
+  if (CERT) cert_reduce(best, wrong, cert_bad, cert_mbg);
 }
 
 // ------------------------------------------------------------- level 3
@@ -603,7 +658,8 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y_dense(const int2* __re
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
   const int2 pr = plist[pbase + (int32_t)blockIdx.y];
-  const int32_t s1 = pr.x, s2 = pr.y;
+  const bool sw = (pr.y & PAIR_SWAP) != 0;
+  const int32_t s1 = pr.x, s2 = pr.y & ~PAIR_SWAP;
   const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
   const int tile = comp_tile();
@@ -1082,7 +1138,7 @@ static hipError_t compose_level2(const HierArgs& a, const int32_t* bglabel, u32*
     if (a.V2p > 0)
       k_mp_xt<<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(
           a.plist, p0, a.Vgp, a.m2pmax, a.m2, a.gV, a.b2off, a.BG2, a.d2pstride ? a.d2ld : a.V2p,
-          a.d2pstride, a.R, a.XT);
+          a.d2pstride, a.D2t, a.d2tld, a.R, a.XT);
     if (a.evt) {
       hipError_t e = hipEventRecord(a.evt[2 * c], s);
       if (e != hipSuccess) return e;
@@ -1163,7 +1219,7 @@ hipError_t launch_level3_compose(const L3Args& a, hipStream_t s) {
     if (a.V3p > 0)
       k_mp_xt<<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(a.plist, p0, a.V3gp, a.m3pmax, a.m3,
                                                               a.tsize, a.b3off, a.BG3, a.V3p, 0,
-                                                              a.R3, a.XT3);
+                                                              nullptr, 0, a.R3, a.XT3);
     k_mp_y_dense<<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
         a.plist, p0, a.V3gp, a.m3pmax, a.m3, a.tsize, a.tbase, a.XT3, a.R3, a.M3, a.BG2, a.V2p);
   }

@@ -103,7 +103,9 @@ struct HierArgs {
   u32* DT;                         // Bellman-Ford distances (V2p + 128 rows x S2p)
   int4* xe;                        // directed cross edges
   int32_t* xcount;
-  const int2* plist;               // composition: group pairs (S1, S2)
+  const int2* plist;               // composition: group pairs (S1, S2), see PAIR_SWAP
+  const u32* D2t = nullptr;        // D2 transposed (rows: level-2 ids; the share's DT)
+  int64_t d2tld = 0;               //   its leading dimension
   int32_t npairs, chunk;           //   their count, pairs per launch (XT slots)
   hipEvent_t* evt;                 // NULL, or 2 per composition launch (k_mp_y)
   // exactness certificate fused into the composition (NULL: off)
@@ -115,6 +117,11 @@ struct HierArgs {
 // multi: some block holds more than one group); boff[nblk+1] first level-2
 // id of each, bsize[nblk] level-2 vertices of each; A: nblk x bpmax x bpmax
 // (BG2 induced on each block, closed).
+// A pair of the level-2 composition whose y carries PAIR_SWAP is computed
+// through the other boundary: (x, y & ~PAIR_SWAP) = (S2, S1) for the output
+// block (S1, S2), so the large product runs over B2(S1) instead of B2(S2);
+// its first product reads the D2 block transposed (D2t).
+constexpr int32_t PAIR_SWAP = 0x40000000;
 struct ShareBlocks {
   int32_t nblk, bpmax;
   bool multi;

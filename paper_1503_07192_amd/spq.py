@@ -89,7 +89,8 @@ _SIGS = {
     "spq_fw_components": (I32, [I32, P, P, P, P, P]),
     "spq_fw_dense": (I32, [I32, I32, I32, I32, I32, P, P]),
     "spq_valu_rates": (I32, [P, P]),
-    "spq_minplus_batched": (I32, [I32, I32, P, P, I32, I32, P, P, I64, P, I32, P, I32, P, I64, P]),
+    "spq_minplus_batched": (I32, [I32, I32, P, P, I32, I32, P, P, P, I64, P, I32, P, I32, I32, P,
+                                  I64, P]),
     "spq_minplus_rows": (I32, [I32, P, I32, P, P, I64, P, P, P, P]),
     "spq_minplus_gather": (I32, [I32, P, P, I32, I32, P, P, I64, P, P, P]),
     "spq_server_create": (I32, [P, I32, I64, I64, P]),
@@ -415,10 +416,12 @@ def valu_rates(stream=None):
             "relax_regs": out[3]}
 
 
-def minplus_batched(layout, nv, nk, vp, kp, R, D, ldd, M, pairs, out, cb=1, ldo=0, stream=None):
+def minplus_batched(layout, nv, nk, vp, kp, R, D, ldd, M, pairs, out, cb=1, ldo=0, stream=None,
+                    assoc=0, Dt=None):
     """Group-level composition products on device tensors (see
     spq_minplus_batched): nv, nk per group and pairs [(S1, S2), ...] on the
-    host; R, D, M, out int32 device tensors.  Synchronous."""
+    host; R, D, Dt (D transposed, for assoc 1 and 2), M, out int32 device
+    tensors.  Synchronous."""
     import torch
     nv = np.ascontiguousarray(nv, np.int32)
     nk = np.ascontiguousarray(nk, np.int32)
@@ -426,10 +429,11 @@ def minplus_batched(layout, nv, nk, vp, kp, R, D, ldd, M, pairs, out, cb=1, ldo=
     if nv.shape != nk.shape or nv.ndim != 1:
         raise ValueError("nv and nk must be 1-d and equally long")
     dptr = _dev_i32(D, "D") if D is not None else ctypes.c_void_p(0)
+    dtptr = _dev_i32(Dt, "Dt") if Dt is not None else ctypes.c_void_p(0)
     _check(load().spq_minplus_batched(int(layout), len(nv), nv.ctypes.data, nk.ctypes.data,
-                                      int(vp), int(kp), _dev_i32(R, "R"), dptr, int(ldd),
-                                      _dev_i32(M, "M"), len(pairs), pairs.ctypes.data, int(cb),
-                                      _dev_i32(out, "out"), int(ldo), _stream(stream)))
+                                      int(vp), int(kp), _dev_i32(R, "R"), dptr, dtptr, int(ldd),
+                                      _dev_i32(M, "M"), len(pairs), pairs.ctypes.data, int(assoc),
+                                      int(cb), _dev_i32(out, "out"), int(ldo), _stream(stream)))
     return out
 
 

@@ -72,10 +72,10 @@ def test_minplus_hooks_reject_bad_arguments_without_device():
     pairs = np.array([0, 1, 1, 1], np.int32)
 
     def call(layout=0, groups=2, nv=nv, nk=nk, vp=128, kp=128, ldd=5, npairs=2, pairs=pairs,
-             cb=8, ldo=0):
+             cb=8, ldo=0, assoc=0, Dt=None):
         return L.spq_minplus_batched(layout, groups, nv.ctypes.data, nk.ctypes.data, vp, kp, dummy,
-                                     dummy, ldd, dummy, npairs, pairs.ctypes.data, cb, dummy, ldo,
-                                     None)
+                                     dummy, Dt, ldd, dummy, npairs, pairs.ctypes.data, assoc, cb,
+                                     dummy, ldo, None)
     assert call(layout=2) == 1 and "layout" in spq.last_error()
     assert call(vp=100) == 1 and "multiples of 128" in spq.last_error()
     assert call(nv=np.array([129, 1], np.int32)) == 1 and "group 0" in spq.last_error()
@@ -85,6 +85,9 @@ def test_minplus_hooks_reject_bad_arguments_without_device():
     assert call(pairs=np.array([0, 1, 0, 1], np.int32)) == 1 and "repeats" in spq.last_error()
     assert call(pairs=np.array([0, 2, 0, 1], np.int32)) == 1 and "outside" in spq.last_error()
     assert call(npairs=0) == 0
+    assert call(assoc=3) == 1 and "assoc" in spq.last_error()
+    assert call(layout=1, ldo=228, assoc=1) == 1 and "assoc" in spq.last_error()
+    assert call(assoc=1) == 1 and "Dt" in spq.last_error()
     cnt = np.array([-1, 0], np.int32)
     assert L.spq_minplus_rows(2, nk.ctypes.data, 100, dummy, dummy, 128, cnt.ctypes.data, None,
                               None, None) == 1

@@ -4,7 +4,8 @@ product (bit-exact).
 
 spq_minplus_batched runs the group-level composition (Algorithm 2 one level
 up, Lemma 3): the first product into the scratch table and the second into
-the query layout (blocked) or densely (level 3).  spq_minplus_rows runs the
+the query layout (blocked, through either group's boundary) or densely
+(level 3).  spq_minplus_rows runs the
 in-place intra-block product of the share's Bellman-Ford rounds, on rows a
 block owns anywhere in the table; spq_minplus_gather the product that then
 fills the block's other rows from its boundary rows.  Operands
@@ -106,9 +107,23 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("layout", [spq.SPQ_MP_BLOCKED, spq.SPQ_MP_DENSE])
+def transposed(D, ldd):
+    """D^T with the same leading dimension (the first K x K block transposed,
+    the rest arbitrary), as the association through B2(S1) reads it."""
+    K = D.shape[0]
+    Dt = np.random.default_rng(K).integers(0, INF, D.shape, dtype=np.int64)
+    k = min(K, ldd)
+    Dt[:k, :k] = D[:k, :k].T
+    return Dt
+
+
+@pytest.mark.parametrize("layout,assoc", [(spq.SPQ_MP_BLOCKED, 0), (spq.SPQ_MP_BLOCKED, 1),
+                                          (spq.SPQ_MP_BLOCKED, 2), (spq.SPQ_MP_DENSE, 0)])
 @pytest.mark.parametrize("seed,G,vp,kp,kind,nv,nk,cb", CASES)
-def test_composition_products_equal_oracle(layout, seed, G, vp, kp, kind, nv, nk, cb):
+def test_composition_products_equal_oracle(layout, assoc, seed, G, vp, kp, kind, nv, nk, cb):
+    """assoc 2 computes every pair with S1 != S2 through B2(S1) (roles
+    exchanged, the tile stored transposed), assoc 1 whichever is cheaper:
+    the results are the same products."""
     import torch
     nv, nk, koff, R, D, ldd, M = compose_case(seed, G, vp, kp, kind, nv, nk)
     rng = np.random.default_rng(seed + 100)
@@ -117,11 +132,12 @@ def test_composition_products_equal_oracle(layout, seed, G, vp, kp, kind, nv, nk
     pairs += [(g, g) for g in range(G) if (g, g) not in pairs]
     V = int(nv.sum())
     voff = np.concatenate([[0], np.cumsum(nv)]).astype(np.int64)
-    print("case", seed, "layout", layout, "G", G, "pairs", len(pairs), flush=True)
+    print("case", seed, "layout", layout, "assoc", assoc, "G", G, "pairs", len(pairs), flush=True)
     if layout == spq.SPQ_MP_BLOCKED:
         total = sum(int(nv[a]) * int(nv[b]) for a, b in pairs)
         out = torch.full((total + 64,), -7, dtype=torch.int32, device="cuda")
-        spq.minplus_batched(layout, nv, nk, vp, kp, dev(R), dev(D), ldd, dev(M), pairs, out, cb=cb)
+        spq.minplus_batched(layout, nv, nk, vp, kp, dev(R), dev(D), ldd, dev(M), pairs, out, cb=cb,
+                            assoc=assoc, Dt=dev(transposed(D, ldd)) if assoc else None)
         got = out.cpu().numpy()
         assert (got[total:] == -7).all(), "written past the last pair"
         base = 0
@@ -145,7 +161,8 @@ def test_composition_products_equal_oracle(layout, seed, G, vp, kp, kind, nv, nk
         assert (got[~written] == -7).all(), "written outside the listed pairs"
 
 
-def test_composition_many_pairs_in_chunks():
+@pytest.mark.parametrize("assoc", [0, 1])
+def test_composition_many_pairs_in_chunks(assoc):
     """More pairs than one launch holds (256 MiB of scratch slots): kp x vp =
     384 x 1024 words per slot gives 170 pairs per launch."""
     import torch
@@ -158,7 +175,7 @@ def test_composition_many_pairs_in_chunks():
     total = sum(int(nv[a]) * int(nv[b]) for a, b in pairs)
     out = torch.full((total,), -7, dtype=torch.int32, device="cuda")
     spq.minplus_batched(spq.SPQ_MP_BLOCKED, nv, nk, vp, kp, dev(R), dev(D), ldd, dev(M), pairs, out,
-                        cb=5)
+                        cb=5, assoc=assoc, Dt=dev(transposed(D, ldd)) if assoc else None)
     got = out.cpu().numpy()
     base = 0
     for a, b in pairs:
