@@ -155,6 +155,18 @@ hipError_t dalloc(T** p, int64_t count) {
 
 int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
 
+// Rows of v valid ones that the composition kernels relax: whole 128-tiles,
+// but in the last, partial tile a wave skips its 16 rows of a half when they
+// all lie past the valid ones (a wave holds rows 16w .. 16w+15 and
+// 64+16w .. 64+16w+15 of the tile).
+double mp_rows(int32_t v) {
+  const int32_t rem = v % 128;
+  double rows = (double)(v - rem);
+  if (rem)
+    for (int w = 0; w < 4; w++) rows += (16 * w < rem ? 16 : 0) + (64 + 16 * w < rem ? 16 : 0);
+  return rows;
+}
+
 }  // namespace
 
 // Fixed staging of spq_query_batch_host_static: v1, v2 and the answers of one
@@ -443,8 +455,8 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   // first product then reads D2 transposed, which is the Bellman-Ford table)
   auto t128 = [](int32_t v) { return (double)((v + 127) / 128); };
   auto cost = [&](int32_t a, int32_t b) {
-    return t128(X->h_m2[b]) * t128(X->h_gV[a]) * (double)round_up(X->h_m2[a], 16) +
-           t128(X->h_gV[a]) * t128(X->h_gV[b]) * (double)round_up(X->h_m2[b], 16);
+    return mp_rows(X->h_m2[b]) * t128(X->h_gV[a]) * (double)round_up(X->h_m2[a], 16) +
+           mp_rows(X->h_gV[a]) * t128(X->h_gV[b]) * (double)round_up(X->h_m2[b], 16);
   };
   std::vector<uint8_t> swap((size_t)X->share_groups * G, 0);
   for (int32_t a1 = 0; a1 < X->share_groups; a1++)
@@ -599,10 +611,10 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
     for (int32_t p2 = 0; p2 < G; p2++) {
       const bool sw = swap[(size_t)p1 * G + p2];
       const int32_t a1 = sw ? p2 : p1, a2 = sw ? p1 : p2;  // the products' roles
-      X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) * ((X->h_gV[a1] + 127) / 128) *
-                          128.0 * 128.0 * (double)round_up(X->h_m2[a1], 16);
-      const double y = (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
-                       128.0 * (double)round_up(X->h_m2[a2], 16);
+      X->relax_bg_exec += mp_rows(X->h_m2[a2]) * ((X->h_gV[a1] + 127) / 128) * 128.0 *
+                          (double)round_up(X->h_m2[a1], 16);
+      const double y = mp_rows(X->h_gV[a1]) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
+                       (double)round_up(X->h_m2[a2], 16);
       X->relax_bg_exec += y;
       X->relax_inner += y;
     }
@@ -1172,16 +1184,15 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     for (int32_t a1 = 0; a1 < G; a1++)
       for (int32_t a2 = a1; a2 < G; a2++) {
         if (X->V2p > 0)
-          X->relax_bg_exec += (double)((X->h_m2[a2] + 127) / 128) *
-                              ((X->h_gV[a1] + 127) / 128) * 128.0 * 128.0 *
+          X->relax_bg_exec += mp_rows(X->h_m2[a2]) * ((X->h_gV[a1] + 127) / 128) * 128.0 *
                               (double)round_up(X->h_m2[a1], 16);
-        X->relax_bg_exec += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) *
-                            128.0 * 128.0 * (double)round_up(X->h_m2[a2], 16);
+        X->relax_bg_exec += mp_rows(X->h_gV[a1]) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
+                            (double)round_up(X->h_m2[a2], 16);
       }
     for (int32_t a1 = 0; a1 < G; a1++)
       for (int32_t a2 = a1; a2 < G; a2++)
-        X->relax_inner += (double)((X->h_gV[a1] + 127) / 128) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
-                          128.0 * (double)round_up(X->h_m2[a2], 16);
+        X->relax_inner += mp_rows(X->h_gV[a1]) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
+                          (double)round_up(X->h_m2[a2], 16);
     TRY(make_pairs(G, G, true, (int64_t)X->m2pmax * Vgp, X->h_elems, &X->plist, &X->npairs,
                    &X->chunk, s));
     X->inner_launches = (X->npairs + X->chunk - 1) / X->chunk;
@@ -1258,11 +1269,9 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       for (int32_t t1 = 0; t1 < nT; t1++)
         for (int32_t t2 = t1; t2 < nT; t2++) {
           if (X->V3p > 0)
-            X->relax_bg_exec += (double)((X->h_m3[t2] + 127) / 128) *
-                                ((X->h_tsize[t1] + 127) / 128) * 128.0 * 128.0 *
+            X->relax_bg_exec += mp_rows(X->h_m3[t2]) * ((X->h_tsize[t1] + 127) / 128) * 128.0 *
                                 (double)round_up(X->h_m3[t1], 16);
-          X->relax_bg_exec += (double)((X->h_tsize[t1] + 127) / 128) *
-                              ((X->h_tsize[t2] + 127) / 128) * 128.0 * 128.0 *
+          X->relax_bg_exec += mp_rows(X->h_tsize[t1]) * ((X->h_tsize[t2] + 127) / 128) * 128.0 *
                               (double)round_up(X->h_m3[t2], 16);
         }
       TRY(hipMemcpyAsync(X->b3off, X->h_b3off.data(), sizeof(int32_t) * (nT + 1),
@@ -1735,10 +1744,10 @@ spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv
     pairbase[(size_t)s1 * groups + s2] = obase;
     obase += (int64_t)nv[s1] * nv[s2];
     // through B2(S1) instead of B2(S2): the products' roles exchanged
-    auto t128 = [](int32_t v) { return (int64_t)((v + 127) / 128); };
+    auto t128 = [](int32_t v) { return (double)((v + 127) / 128); };
     auto cost = [&](int32_t a, int32_t b) {
-      return t128(nk[b]) * t128(nv[a]) * round_up(nk[a], 16) +
-             t128(nv[a]) * t128(nv[b]) * round_up(nk[b], 16);
+      return mp_rows(nk[b]) * t128(nv[a]) * (double)round_up(nk[a], 16) +
+             mp_rows(nv[a]) * t128(nv[b]) * (double)round_up(nk[b], 16);
     };
     const bool sw = s1 != s2 && (assoc == 2 || (assoc == 1 && cost(s2, s1) < cost(s1, s2)));
     plist[p] = sw ? make_int2(s2, s1 | spq::PAIR_SWAP) : make_int2(s1, s2);

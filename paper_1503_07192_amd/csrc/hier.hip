@@ -227,7 +227,8 @@ __global__ void k_flat_store(int32_t V, int64_t Vp, const u32* __restrict__ BG,
 // streamed through LDS 16 rows at a time (double buffered, next chunk
 // prefetched into registers).  With MASKED, rows k >= kvalid and columns
 // i >= avalid of At read as INF without touching memory, and rows k >= kvalid
-// of B likewise.
+// of B likewise.  Rows of c at or past rv are left unfinished (never
+// stored by the caller).
 template <bool MASKED>
 __device__ __forceinline__ uint4 mp_load_a(const u32* At, int64_t ldA, int k, int col, int kvalid,
                                            int avalid) {
@@ -245,10 +246,29 @@ __device__ __forceinline__ uint4 mp_load_b(const u32* B, int64_t ldB, int k, int
   return *reinterpret_cast<const uint4*>(B + (int64_t)k * ldB + col);
 }
 
-template <bool MASKED>
-__device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int64_t ldA, const u32* B,
-                                             int64_t ldB, int K, int kvalid, int avalid, u32* sA,
-                                             u32* sB) {
+// The relaxations of one LDS chunk for a thread's first NR rows (8 all, 4
+// the first half of the tile, 0 none: the wave only stages chunks).
+template <int NR>
+__device__ __forceinline__ void mp_chunk(u32 (&c)[8][8], const u32* sA, const u32* sB, int K) {
+  if (NR == 8) minplus_lds<128>(c, sA, sB, K);
+  if (NR == 4) minplus_lds<128, 4>(c, sA, sB, K);
+}
+
+// The rows a wave relaxes when only rows below rv of the tile are ever
+// stored: a thread's rows are h*64 + ty*4 + a and a wave holds four
+// consecutive ty (16 rows of each half), so a wave whose rows of the second
+// half (or of both halves) all lie at or past rv skips them, and its VALU
+// slots go to the other waves of its SIMD.  Every wave still stages its
+// share of each chunk and meets every barrier.
+__device__ __forceinline__ int wave_rows(int rv) {
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  return (rv >= 128 || 64 + 16 * w < rv) ? 8 : (16 * w < rv) ? 4 : 0;
+}
+
+template <bool MASKED, int NR>
+__device__ __forceinline__ void mp_stream128_n(u32 (&c)[8][8], const u32* At, int64_t ldA, const u32* B,
+                                               int64_t ldB, int K, int kvalid, int avalid, u32* sA,
+                                               u32* sB) {
   constexpr int T = 128, KC = 16;
   const int nch = K / KC;
   if (nch <= 0) return;
@@ -272,7 +292,7 @@ __device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int6
     pb0 = mp_load_b<MASKED>(B, ldB, kn + r0, c0, kvalid);
     pb1 = mp_load_b<MASKED>(B, ldB, kn + r1, c1, kvalid);
     const int cur = (ch & 1) * KC * T, nxt = ((ch + 1) & 1) * KC * T;
-    minplus_lds<T>(c, sA + cur, sB + cur, KC);
+    mp_chunk<NR>(c, sA + cur, sB + cur, KC);
     reinterpret_cast<uint4*>(sA + nxt)[e0] = pa0;
     reinterpret_cast<uint4*>(sA + nxt)[e1] = pa1;
     reinterpret_cast<uint4*>(sB + nxt)[e0] = pb0;
@@ -281,15 +301,29 @@ __device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int6
   }
 }
 
+template <bool MASKED>
+__device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int64_t ldA, const u32* B,
+                                             int64_t ldB, int K, int kvalid, int avalid, u32* sA,
+                                             u32* sB, int rv = 128) {
+  const int nr = wave_rows(rv);
+  if (nr == 8)
+    mp_stream128_n<MASKED, 8>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
+  else if (nr == 4)
+    mp_stream128_n<MASKED, 4>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
+  else
+    mp_stream128_n<MASKED, 0>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
+}
+
 // c = min(c, min over k < cnt of At[rows[k]][i] + B[bmap[rows[k]]][j]): the K
 // rows are gathered through the list `rows` (rows k themselves when it is
 // null; cnt of them, streamed 16 at a time, rows past cnt read as INF without
 // touching memory), and B's rows once more through bmap when it is not null.
-__device__ __forceinline__ void mp_stream128_rows(u32 (&c)[8][8], const u32* At, int64_t ldA,
-                                                  const u32* B, int64_t ldB,
-                                                  const int32_t* __restrict__ rows, int cnt,
-                                                  u32* sA, u32* sB,
-                                                  const int32_t* __restrict__ bmap = nullptr) {
+template <int NR>
+__device__ __forceinline__ void mp_stream128_rows_n(u32 (&c)[8][8], const u32* At, int64_t ldA,
+                                                    const u32* B, int64_t ldB,
+                                                    const int32_t* __restrict__ rows, int cnt,
+                                                    u32* sA, u32* sB,
+                                                    const int32_t* __restrict__ bmap) {
   constexpr int T = 128, KC = 16;
   const int nch = (cnt + KC - 1) / KC;
   if (nch <= 0) return;
@@ -319,13 +353,23 @@ __device__ __forceinline__ void mp_stream128_rows(u32 (&c)[8][8], const u32* At,
     pb0 = ldb(kn + r0, c0);
     pb1 = ldb(kn + r1, c1);
     const int cur = (ch & 1) * KC * T, nxt = ((ch + 1) & 1) * KC * T;
-    minplus_lds<T>(c, sA + cur, sB + cur, KC);
+    mp_chunk<NR>(c, sA + cur, sB + cur, KC);
     reinterpret_cast<uint4*>(sA + nxt)[e0] = pa0;
     reinterpret_cast<uint4*>(sA + nxt)[e1] = pa1;
     reinterpret_cast<uint4*>(sB + nxt)[e0] = pb0;
     reinterpret_cast<uint4*>(sB + nxt)[e1] = pb1;
     __syncthreads();
   }
+}
+
+__device__ __forceinline__ void mp_stream128_rows(u32 (&c)[8][8], const u32* At, int64_t ldA,
+                                                  const u32* B, int64_t ldB,
+                                                  const int32_t* __restrict__ rows, int cnt,
+                                                  u32* sA, u32* sB,
+                                                  const int32_t* __restrict__ bmap = nullptr) {
+  // every row: the gathered operands leave no registers for a second copy
+  // of the loop (the kernels' last row tiles are a small share of them)
+  mp_stream128_rows_n<8>(c, At, ldA, B, ldB, rows, cnt, sA, sB, bmap);
 }
 
 // The composition kernels fit in 128 VGPRs without spilling: four waves per
@@ -411,13 +455,14 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
     const u32* B = R + (int64_t)s1 * m2pmax * Vgp + tj * 128;
     if (sw) {
       const u32* At = D2t + (int64_t)b2off[s1] * ldt + b2off[s2] + ti * 128;
-      mp_stream128<true>(c, At, ldt, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB);
+      mp_stream128<true>(c, At, ldt, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB,
+                         mb - ti * 128);
     } else {
       const u32* At = BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd +
                       (pstride ? 0 : b2off[s2]) + ti * 128;
       // a panel holds INF past its group's B2 vertices: no column mask there
       mp_stream128<true>(c, At, ldd, B, Vgp, (ka + 15) / 16 * 16, ka, pstride ? 128 : mb - ti * 128,
-                         sA, sB);
+                         sA, sB, mb - ti * 128);
     }
   }
   u32* out = XT + (slot * m2pmax + ti * 128) * Vgp + tj * 128;
@@ -490,7 +535,7 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict
   const int32_t kb = m2[s2];
   const u32* At = XT + slot * m2pmax * Vgp + ti * 128;
   const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
-  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB);
+  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB, V1 - ti * 128);
   // the group's own closure when S1 = S2, folded in after the product: taken
   // in first, it kept a second copy of the tile live through the K loop
   if (s1 == s2)
@@ -658,8 +703,7 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y_dense(const int2* __re
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
   const int2 pr = plist[pbase + (int32_t)blockIdx.y];
-  const bool sw = (pr.y & PAIR_SWAP) != 0;
-  const int32_t s1 = pr.x, s2 = pr.y & ~PAIR_SWAP;
+  const int32_t s1 = pr.x, s2 = pr.y;
   const int64_t slot = blockIdx.y;
   const int ntx = Vgp / 128;
   const int tile = comp_tile();
@@ -671,7 +715,7 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y_dense(const int2* __re
   const int32_t kb = m2[s2];
   const u32* At = XT + slot * m2pmax * Vgp + ti * 128;
   const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
-  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB);
+  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB, V1 - ti * 128);
   // the group's own closure when S1 = S2, folded in after the product: taken
   // in first, it kept a second copy of the tile live through the K loop
   if (s1 == s2)
