@@ -222,6 +222,11 @@ struct spq_index {
   uint8_t* flag2 = nullptr;
   u32 *Mg = nullptr, *R = nullptr, *XT = nullptr, *BG2 = nullptr, *H = nullptr;
   int64_t* pairbase = nullptr;
+  // the composition's positions: per group its width (B2 vertices padded to
+  // a multiple of 4, then the others), their bound Vrp and the table
+  int32_t Vrp = 0;
+  std::vector<int32_t> h_W;
+  int32_t* pos = nullptr;
   // level 3 (closure of BG2 by super-groups of gpt groups)
   int32_t nT = 0, gpt = 0, V3gp = 0, V3 = 0, m3pmax = 0;
   int64_t V3p = 0;
@@ -303,7 +308,7 @@ struct spq_index {
     void* ptrs[] = {comp, local, nb,   off,  bgoff, P,     order, bgcomp,  bglocal,
                     cnt,  fill,  moff, flag, sumc,  total, err,   members, M,      BG,
                     vrec, gT,    grp,   gbg0, gV,   bgrow, bgnb,  bggrp, b2list,  b2rank, m2,
-                    b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase,
+                    b2off, flag2, Mg,  R,    XT,    BG2,   H,     pairbase, pos,
                     bgvert, label, bglabel, cert, A,    DT,    bfflag,  bfstamp, bfcnt, bflist,
                     sb_flag, sb_flagn, sb_list, sb_nlist, sb_rank, sb_nrank, sb_m, sb_n, sb_A3, sb_Aout,
                     xe, xcount, boff, bsize, bfirst, gblk,
@@ -341,9 +346,9 @@ static hipError_t graph_segment(spq_index* X, hipStream_t s, F&& body) {
 
 // Pair list of a composition (rows groups [0, rows) against groups [first,
 // G), first = the row group itself when `upper`), uploaded to *dev, and the
-// pairs per launch: the XT buffer holds one m x Vgp slot per pair of a
-// launch, within 1/32 of the composition's output clamped to [256 MiB,
-// 4 GiB], at least one slot.
+// pairs per launch: the XT buffer holds one slot of slot_elems words per
+// pair of a launch, within 1/32 of the composition's output clamped to
+// [256 MiB, 4 GiB], at least one slot.
 static hipError_t make_pairs(int32_t rows, int32_t G, bool upper, int64_t slot_elems,
                              int64_t out_elems, int2** dev, int32_t* npairs, int32_t* chunk,
                              hipStream_t s, const std::vector<uint8_t>* swap = nullptr) {
@@ -365,6 +370,30 @@ static hipError_t make_pairs(int32_t rows, int32_t G, bool upper, int64_t slot_e
   hipError_t e = dalloc(dev, std::max<int64_t>(*npairs, 1));
   if (e != hipSuccess || h.empty()) return e;
   return hipMemcpyAsync(*dev, h.data(), sizeof(int2) * h.size(), hipMemcpyHostToDevice, s);
+}
+
+// The composition's positions from the level-2 boundary counts: widths and
+// their bound Vrp (a multiple of 128).
+static void set_positions(spq_index* X) {
+  X->h_W.resize(X->ngroups);
+  int64_t wmax = 0;
+  for (int32_t g = 0; g < X->ngroups; g++) {
+    X->h_W[g] = (int32_t)round_up(X->h_m2[g], 4) + X->h_gV[g] - X->h_m2[g];
+    wmax = std::max<int64_t>(wmax, X->h_W[g]);
+  }
+  X->Vrp = (int32_t)std::max<int64_t>(128, round_up(wmax, 128));
+}
+
+// Executed relaxations of a pair's two products, the first over B2(a1)
+// (columns: a1's positions, rows B2(a2)), the second over B2(a2) (rows: a1's
+// positions, columns: a2's vertices outside B2(a2)).
+static double xt_relax(const spq_index* X, int32_t a1, int32_t a2) {
+  return mp_rows(X->h_m2[a2]) * (double)((X->h_W[a1] + 127) / 128) * 128.0 *
+         (double)round_up(X->h_m2[a1], 16);
+}
+static double y_relax(const spq_index* X, int32_t a1, int32_t a2) {
+  return mp_rows(X->h_W[a1]) * (double)((X->h_gV[a2] - X->h_m2[a2] + 127) / 128) * 128.0 *
+         (double)round_up(X->h_m2[a2], 16);
 }
 
 // The query kernel locates a pair block from the two vertex records alone:
@@ -448,23 +477,23 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
   HIP_TRY(hipMemcpyAsync(X->bfirst, X->h_bfirst.data(), sizeof(int32_t) * (NB + 1), hipMemcpyHostToDevice,
                          s));
   HIP_TRY(hipMemcpyAsync(X->gblk, X->h_gblk.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
-  HIP_TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
-  // each output block (S1, S2) through the cheaper boundary: the products
-  // cost tiles(m2[S2]) tiles(V_S1) m2[S1] + tiles(V_S1) tiles(V_S2) m2[S2]
-  // through B2(S2), the same with S1 and S2 exchanged through B2(S1) (its
-  // first product then reads D2 transposed, which is the Bellman-Ford table)
-  auto t128 = [](int32_t v) { return (double)((v + 127) / 128); };
-  auto cost = [&](int32_t a, int32_t b) {
-    return mp_rows(X->h_m2[b]) * t128(X->h_gV[a]) * (double)round_up(X->h_m2[a], 16) +
-           mp_rows(X->h_gV[a]) * t128(X->h_gV[b]) * (double)round_up(X->h_m2[b], 16);
-  };
+  set_positions(X);
+  const int32_t Vrp = X->Vrp;
+  // R's last row is read up to 127 words past its end (the second product's
+  // column tiles start past the B2 positions)
+  HIP_TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vrp + 128));
+  HIP_TRY(dalloc(&X->pos, (int64_t)G * Vrp));
+  // each output block (S1, S2) through the cheaper boundary: through B2(S2)
+  // or, S1 and S2 exchanged, through B2(S1) (its first product then reads D2
+  // transposed, which is the Bellman-Ford table)
+  auto cost = [&](int32_t a, int32_t b) { return xt_relax(X, a, b) + y_relax(X, a, b); };
   std::vector<uint8_t> swap((size_t)X->share_groups * G, 0);
   for (int32_t a1 = 0; a1 < X->share_groups; a1++)
     for (int32_t a2 = 0; a2 < G; a2++)
       swap[(size_t)a1 * G + a2] = a1 != a2 && cost(a2, a1) < cost(a1, a2);
-  HIP_TRY(make_pairs(X->share_groups, G, false, (int64_t)X->m2pmax * Vgp, X->h_elems, &X->plist,
+  HIP_TRY(make_pairs(X->share_groups, G, false, (int64_t)X->m2pmax * Vrp, X->h_elems, &X->plist,
                      &X->npairs, &X->chunk, s, &swap));
-  HIP_TRY(dalloc(&X->XT, (int64_t)X->chunk * X->m2pmax * Vgp));
+  HIP_TRY(dalloc(&X->XT, (int64_t)X->chunk * X->m2pmax * Vrp));
   HIP_TRY(dalloc(&X->A, (int64_t)NB * BP * BP));
   // the Bellman-Ford matrix carries 128 spare rows: a row tile may start at
   // the last block's last level-2 id
@@ -498,6 +527,7 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
                          hipMemcpyHostToDevice, s));
   ha.m2pmax = X->m2pmax; ha.V2 = X->V2; ha.V2p = V2p; ha.b2off = X->b2off; ha.R = X->R;
   ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
+  ha.pos = X->pos; ha.Vrp = Vrp;
   ha.plist = X->plist; ha.npairs = X->npairs; ha.chunk = X->chunk;
   ha.share_groups = X->share_groups; ha.S2 = X->S2; ha.S2p = X->S2p; ha.DT = X->DT;
   ha.D2t = X->DT; ha.d2tld = X->S2p;
@@ -611,10 +641,8 @@ static spq_status build_share(spq_index* X, spq::HierArgs& ha, int64_t m, bool p
     for (int32_t p2 = 0; p2 < G; p2++) {
       const bool sw = swap[(size_t)p1 * G + p2];
       const int32_t a1 = sw ? p2 : p1, a2 = sw ? p1 : p2;  // the products' roles
-      X->relax_bg_exec += mp_rows(X->h_m2[a2]) * ((X->h_gV[a1] + 127) / 128) * 128.0 *
-                          (double)round_up(X->h_m2[a1], 16);
-      const double y = mp_rows(X->h_gV[a1]) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
-                       (double)round_up(X->h_m2[a2], 16);
+      X->relax_bg_exec += xt_relax(X, a1, a2);
+      const double y = y_relax(X, a1, a2);
       X->relax_bg_exec += y;
       X->relax_inner += y;
     }
@@ -1181,19 +1209,16 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
     // executed relaxations of level 2 (its BG2 closure is counted with level 3)
     if (X->V2p > 0 && X->nT == 0)
       X->relax_bg_exec += spq::dense_fw_exec_relax(X->V2p / 128, 128, X->cpivot);
+    set_positions(X);
+    const int32_t Vrp = X->Vrp;
     for (int32_t a1 = 0; a1 < G; a1++)
       for (int32_t a2 = a1; a2 < G; a2++) {
-        if (X->V2p > 0)
-          X->relax_bg_exec += mp_rows(X->h_m2[a2]) * ((X->h_gV[a1] + 127) / 128) * 128.0 *
-                              (double)round_up(X->h_m2[a1], 16);
-        X->relax_bg_exec += mp_rows(X->h_gV[a1]) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
-                            (double)round_up(X->h_m2[a2], 16);
+        if (X->V2p > 0) X->relax_bg_exec += xt_relax(X, a1, a2);
+        const double y = y_relax(X, a1, a2);
+        X->relax_bg_exec += y;
+        X->relax_inner += y;
       }
-    for (int32_t a1 = 0; a1 < G; a1++)
-      for (int32_t a2 = a1; a2 < G; a2++)
-        X->relax_inner += mp_rows(X->h_gV[a1]) * ((X->h_gV[a2] + 127) / 128) * 128.0 *
-                          (double)round_up(X->h_m2[a2], 16);
-    TRY(make_pairs(G, G, true, (int64_t)X->m2pmax * Vgp, X->h_elems, &X->plist, &X->npairs,
+    TRY(make_pairs(G, G, true, (int64_t)X->m2pmax * Vrp, X->h_elems, &X->plist, &X->npairs,
                    &X->chunk, s));
     X->inner_launches = (X->npairs + X->chunk - 1) / X->chunk;
     if (profile) {
@@ -1202,8 +1227,11 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       ha.evt = X->prof.data();
     }
     TRY(hipMemcpyAsync(X->b2off, X->h_b2off.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
-    TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vgp));
-    TRY(dalloc(&X->XT, (int64_t)X->chunk * X->m2pmax * Vgp));
+    // R's last row is read up to 127 words past its end (the second
+    // product's column tiles start past the B2 positions)
+    TRY(dalloc(&X->R, (int64_t)G * X->m2pmax * Vrp + 128));
+    TRY(dalloc(&X->pos, (int64_t)G * Vrp));
+    TRY(dalloc(&X->XT, (int64_t)X->chunk * X->m2pmax * Vrp));
     if (X->V2p > 0) TRY(dalloc(&X->BG2, X->V2p * X->V2p));
     TRY(dalloc(&X->H, X->h_elems));
     TRY(dalloc(&X->pairbase, (int64_t)G * G));
@@ -1211,6 +1239,7 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
                        hipMemcpyHostToDevice, s));
     ha.m2pmax = X->m2pmax; ha.V2 = X->V2; ha.V2p = X->V2p; ha.b2off = X->b2off; ha.R = X->R;
     ha.XT = X->XT; ha.BG2 = X->BG2; ha.H = X->H; ha.pairbase = X->pairbase;
+    ha.pos = X->pos; ha.Vrp = Vrp;
     ha.plist = X->plist; ha.npairs = X->npairs; ha.chunk = X->chunk;
     if (X->certify) {
       ha.bglabel = X->bglabel;

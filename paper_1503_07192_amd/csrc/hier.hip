@@ -144,6 +144,60 @@ __global__ void k_r_gather(int32_t Vgp, int32_t m2pmax, const int32_t* __restric
   }
 }
 
+// Positions of every group (one workgroup each; the layout is described with
+// the composition below): B2 vertices, padding to a multiple of 4, the other
+// vertices ascending (found by b2rank < 0), padding up to Vrp.
+__global__ __launch_bounds__(256) void k_pos_build(const int32_t* __restrict__ gbg0,
+                                                   const int32_t* __restrict__ gV,
+                                                   const int32_t* __restrict__ b2rank,
+                                                   const int32_t* __restrict__ b2list,
+                                                   const int32_t* __restrict__ m2, int32_t Vgp,
+                                                   int32_t Vrp, int32_t* __restrict__ pos) {
+  __shared__ int32_t wsum[4];
+  const int s = blockIdx.x;
+  const int32_t g0 = gbg0[s], V = gV[s], k = m2[s], P2 = (k + 3) & ~3, W = P2 + V - k;
+  int32_t* out = pos + (int64_t)s * Vrp;
+  for (int32_t p = threadIdx.x; p < Vrp; p += 256) {
+    if (p < k) out[p] = b2list[(int64_t)s * Vgp + p];
+    else if (p < P2 || p >= W) out[p] = -1;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int32_t base = 0;
+  for (int32_t c0 = 0; c0 < V; c0 += 256) {
+    const int32_t p = c0 + (int32_t)threadIdx.x;
+    const bool f = p < V && b2rank[g0 + p] < 0;
+    const unsigned long long bal = __ballot(f);
+    const int32_t before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wid] = __popcll(bal);
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+    for (int i = 0; i < 4; i++) {
+      if (i < wid) woff += wsum[i];
+      tot += wsum[i];
+    }
+    if (f) out[P2 + base + woff + before] = p;
+    base += tot;
+    __syncthreads();
+  }
+}
+
+// R_S by position: R[S][r][p] = d_S(r-th B2 vertex, vertex at position p) for
+// r < m2[S]; INF on the other rows and at padding positions.
+__global__ void k_rpos_gather(int32_t Vgp, int32_t Vrp, int32_t m2pmax, const int32_t* __restrict__ m2,
+                              const int32_t* __restrict__ b2list, const int32_t* __restrict__ pos,
+                              const u32* __restrict__ Mg, u32* __restrict__ R) {
+  const int s = blockIdx.y;
+  const int32_t i = blockIdx.x;
+  u32* dst = R + ((int64_t)s * m2pmax + i) * Vrp;
+  const bool live = i < m2[s];
+  const u32* src = Mg + ((int64_t)s * Vgp + (live ? b2list[(int64_t)s * Vgp + i] : 0)) * Vgp;
+  const int32_t* ps = pos + (int64_t)s * Vrp;
+  for (int32_t p = threadIdx.x; p < Vrp; p += blockDim.x) {
+    const int32_t x = live ? ps[p] : -1;
+    dst[p] = x >= 0 ? src[x] : INF;
+  }
+}
+
 // BG2 matrix init: d_S between B2 vertices of one group, 0 on the diagonal,
 // INF elsewhere and on the padding.
 __global__ void k_bg2_init(int32_t V2, int64_t V2p, int32_t ngroups, const int32_t* __restrict__ b2off,
@@ -415,72 +469,25 @@ __device__ __forceinline__ void fill_inf(u32 (&c)[8][8]) {
 __device__ __forceinline__ int comp_tile() {
   return (int)((blockIdx.x + blockIdx.y) % gridDim.x);
 }
-//
-// XT (m2pmax x Vgp, rows b in B2(S2), columns x of S1) =
-//   min over a in B2(S1) of D2[a][b] + R_S1[a][x].
-// D2 rows are level-2 ids of the sources (all of BG2, or the share's rows),
-// leading dimension ldd.  pstride = 0: D2 is dense (column = level-2 id);
-// pstride > 0: D2 is cut into one column panel per group S2, pstride
-// elements apart, whose column j is B2(S2)'s j-th vertex: the (S1, S2) block
-// a product reads is then one contiguous run instead of rows ldd apart.
-// Rows b in [m2[S2], round16(m2[S2])) are stored as INF.  The composition
-// reads rows below round16(m2[S2]) and column tiles below gV[S1] only, so
-// tiles past those are neither computed nor written.
-// A pair flagged PAIR_SWAP reads D2[B2(s1)][B2(s2)] from the transposed
-// table D2t (rows: level-2 ids, leading dimension ldt; with a column mask,
-// as D2t's columns past B2(s2) belong to other groups).
-__global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restrict__ plist, int32_t pbase,
-                                               int32_t Vgp, int32_t m2pmax,
-                                               const int32_t* __restrict__ m2,
-                                               const int32_t* __restrict__ gV,
-                                               const int32_t* __restrict__ b2off,
-                                               const u32* __restrict__ BG2, int64_t ldd,
-                                               int64_t pstride, const u32* __restrict__ D2t,
-                                               int64_t ldt,
-                                               const u32* __restrict__ R, u32* __restrict__ XT) {
-  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
-  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
-  const int2 pr = plist[pbase + (int32_t)blockIdx.y];
-  const bool sw = (pr.y & PAIR_SWAP) != 0;
-  const int32_t s1 = pr.x, s2 = pr.y & ~PAIR_SWAP;
-  const int64_t slot = blockIdx.y;
-  const int ntx = Vgp / 128;
-  const int tile = comp_tile();
-  const int ti = tile / ntx, tj = tile % ntx;
-  const int32_t ka = m2[s1], mb = m2[s2];
-  if (ti * 128 >= mb || tj * 128 >= gV[s1]) return;
-  u32 c[8][8];
-  fill_inf(c);
-  {
-    const u32* B = R + (int64_t)s1 * m2pmax * Vgp + tj * 128;
-    if (sw) {
-      const u32* At = D2t + (int64_t)b2off[s1] * ldt + b2off[s2] + ti * 128;
-      mp_stream128<true>(c, At, ldt, B, Vgp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB,
-                         mb - ti * 128);
-    } else {
-      const u32* At = BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd +
-                      (pstride ? 0 : b2off[s2]) + ti * 128;
-      // a panel holds INF past its group's B2 vertices: no column mask there
-      mp_stream128<true>(c, At, ldd, B, Vgp, (ka + 15) / 16 * 16, ka, pstride ? 128 : mb - ti * 128,
-                         sA, sB, mb - ti * 128);
-    }
-  }
-  u32* out = XT + (slot * m2pmax + ti * 128) * Vgp + tj * 128;
-  const int tx = tid_x(), ty = tid_y();
-#pragma unroll
-  for (int h = 0; h < 2; h++)
-#pragma unroll
-    for (int a = 0; a < 4; a++) {
-      const int row = h * 64 + ty * 4 + a;
-      const bool live = ti * 128 + row < mb;
-#pragma unroll
-      for (int h2 = 0; h2 < 2; h2++) {
-        const int i = h * 4 + a, j = h2 * 4;
-        uint4 v = live ? make_uint4(c[i][j], c[i][j + 1], c[i][j + 2], c[i][j + 3])
-                       : make_uint4(INF, INF, INF, INF);
-        *reinterpret_cast<uint4*>(out + (int64_t)row * Vgp + h2 * 64 + tx * 4) = v;
-      }
-    }
+
+// Positions.  The two-level builds lay each group's vertices out in R, XT
+// and the composition's tiles by position: its B2 vertices first (b2list
+// order), padding up to a multiple of 4, then its other vertices ascending
+// (pos[group * Vrp + p] = local index, -1 for padding).  For y in B2(S2),
+// D(S1,S2)[x][y] = XT[y][x]: the first product already holds it (the
+// minimum of the second one is reached at b = y, d_S2(y, y) = 0, and no other
+// b goes lower, d_S2 being closed), so the first product stores those
+// entries and the second one runs only over S2's other vertices.  pos NULL:
+// positions are local indices and every column takes the second product.
+__device__ __forceinline__ int32_t pos_first(int32_t m2, bool skip) { return skip ? (m2 + 3) & ~3 : 0; }
+__device__ __forceinline__ int32_t pos_width(int32_t V, int32_t m2, bool skip) {
+  return skip ? ((m2 + 3) & ~3) + V - m2 : V;
+}
+// local index at position p of a group (base = group * Vrp), -1 for none
+__device__ __forceinline__ int32_t pos_local(const int32_t* __restrict__ pos, int64_t base, int32_t p,
+                                             int32_t W, int32_t V) {
+  if (p >= W) return -1;
+  return pos ? pos[base + p] : (p < V ? p : -1);
 }
 
 // The certificate's per-wave reduction: largest finite value, and whether
@@ -496,132 +503,229 @@ __device__ __forceinline__ void cert_reduce(u32 best, u32 wrong, u32* cert_bad, 
   }
 }
 
-// D(S1,S2) tile (rows x of S1, columns y of S2) for the pair of blockIdx.y:
-//   min over b in B2(S2) of XT[b][x] + R_S2[b][y], and d_S1 when S1 = S2;
-// stored in the component-pair layout described at the top of the file.
-// The offset of (x, y) inside the pair's block, rowoff(x) V_S2 + nb(x)
-// rowoff(y) + loc(x) nb(y) + loc(y), is below V_S1 V_S2 < 2^30 (groups hold at
-// most 32,768 BG vertices): 32-bit arithmetic from the pair's base pointer.
-// CERT: the exactness certificate is fused into the store (largest finite
-// value, and whether an INF joins two vertices connected in G).
-template <bool CERT>
-__global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict__ plist, int32_t pbase,
-                                              int32_t ngroups, int32_t Vgp,
-                                              int32_t m2pmax,
-                                              const int32_t* __restrict__ m2,
-                                              const int32_t* __restrict__ gV,
-                                              const int32_t* __restrict__ gbg0,
-                                              const u32* __restrict__ XT, const u32* __restrict__ R,
-                                              const u32* __restrict__ Mg,
-                                              const int64_t* __restrict__ pairbase,
-                                              const int32_t* __restrict__ bgrow,
-                                              const int32_t* __restrict__ bgnb,
-                                              const int32_t* __restrict__ bglocal, u32* __restrict__ H,
-                                              const int32_t* __restrict__ bglabel,
-                                              u32* __restrict__ cert_bad, u32* __restrict__ cert_mbg) {
+// Stores tile c into its block of the query layout, whose element (x, y)
+// sits at rowoff(x) |Y| + nb(x) rowoff(y) + loc(x) nb(y) + loc(y) (below
+// |X| |Y| < 2^30: 32-bit offsets from the block's base).  Row i of the
+// thread is vertex lr[i] of the group whose first BG id is gr (-1: none),
+// column j vertex lc[j] of the group at gc.  ROWS_X: c's rows are the
+// block's rows x, else its columns y.  CERT: the certificate is folded in.
+template <bool CERT, bool ROWS_X>
+__device__ __forceinline__ void store_block(const u32 (&c)[8][8], u32* base, int32_t gr, int32_t gc,
+                                            const int32_t (&lr)[8], const int32_t (&lc)[8], u32 nY,
+                                            const int32_t* __restrict__ bgrow,
+                                            const int32_t* __restrict__ bgnb,
+                                            const int32_t* __restrict__ bglocal,
+                                            const int32_t* __restrict__ bglabel, u32* cert_bad,
+                                            u32* cert_mbg) {
+  // column terms: the block's y terms (rowoff, nb, loc), or with ROWS_X
+  // false its x terms (rowoff x |Y|, nb, loc)
+  u32 t0[8], t1[8], t2[8];
+  int32_t collab[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const int32_t qg = gc + (lc[j] >= 0 ? lc[j] : 0);
+    t0[j] = ROWS_X ? (u32)bgrow[qg] : (u32)bgrow[qg] * nY;
+    t1[j] = (u32)bgnb[qg];
+    t2[j] = (u32)bglocal[qg];
+    if (CERT) collab[j] = bglabel[qg];
+  }
+  u32 best = 0, wrong = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    if (lr[i] < 0) continue;
+    const int32_t rg = gr + lr[i];
+    const u32 u0 = ROWS_X ? (u32)bgrow[rg] * nY : (u32)bgrow[rg];
+    const u32 u1 = (u32)bgnb[rg], u2 = (u32)bglocal[rg];
+    const int32_t labr = CERT ? bglabel[rg] : 0;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      if (lc[j] < 0) continue;
+      // rowoff(x) |Y| + nb(x) rowoff(y) + loc(x) nb(y) + loc(y)
+      const u32 off = ROWS_X ? u0 + __umul24(u1, t0[j]) + __umul24(u2, t1[j]) + t2[j]
+                             : t0[j] + __umul24(t1[j], u0) + __umul24(t2[j], u1) + u2;
+      base[off] = c[i][j];
+      if (CERT) {
+        if (c[i][j] < INF) best = max(best, c[i][j]);
+        else wrong |= (u32)(collab[j] == labr);
+      }
+    }
+  }
+  if (CERT) cert_reduce(best, wrong, cert_bad, cert_mbg);
+}
+
+// c[i][j] = min(c[i][j], M[lr[i]][lc[j]]) for the valid pairs (M: a group's
+// closure, leading dimension ld).
+__device__ __forceinline__ void tile_min_gather(u32 (&c)[8][8], const u32* __restrict__ M, int64_t ld,
+                                                const int32_t (&lr)[8], const int32_t (&lc)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    if (lr[i] < 0) continue;
+    const u32* row = M + (int64_t)lr[i] * ld;
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+      if (lc[j] >= 0) c[i][j] = min(c[i][j], row[lc[j]]);
+  }
+}
+
+// The composition's optional stores (the build's; the test hook and level 3
+// pass none): positions, the query layout and the certificate.
+struct CompStore {
+  const int32_t* pos;        // ngroups x Vrp, NULL: identity
+  int32_t Vgp, ngroups;      // Mg and b2list leading dimension; groups
+  const int32_t *b2list, *gbg0, *bgrow, *bgnb, *bglocal, *bglabel;
+  const u32* Mg;
+  const int64_t* pairbase;
+  u32* H;
+  u32 *cert_bad, *cert_mbg;
+};
+
+// XT (m2pmax x Vrp, rows b in B2(S2), columns: positions of S1) =
+//   min over a in B2(S1) of D2[a][b] + R_S1[a][x].
+// D2 rows are level-2 ids of the sources (all of BG2, or the share's rows),
+// leading dimension ldd.  pstride = 0: D2 is dense (column = level-2 id);
+// pstride > 0: D2 is cut into one column panel per group S2, pstride
+// elements apart, whose column j is B2(S2)'s j-th vertex: the (S1, S2) block
+// a product reads is then one contiguous run instead of rows ldd apart.
+// Rows b in [m2[S2], round16(m2[S2])) are stored as INF.  The composition
+// reads rows below round16(m2[S2]) and column tiles below S1's width only,
+// so tiles past those are neither computed nor written.
+//
+// A pair flagged PAIR_SWAP reads D2[B2(s1)][B2(s2)] from the transposed
+// table D2t (rows: level-2 ids, leading dimension ldt; with a column mask,
+// as D2t's columns past B2(s2) belong to other groups).  MODE 1 (2: with the
+// certificate) also stores the tile's entries into the query layout, as
+// D(s1, s2)[x][y] for y in B2(s2) (D(s2, s1)[y][x] for a swapped pair).
+template <int MODE>
+__global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restrict__ plist, int32_t pbase,
+                                               int32_t Vrp, int32_t m2pmax,
+                                               const int32_t* __restrict__ m2,
+                                               const int32_t* __restrict__ gV,
+                                               const int32_t* __restrict__ b2off,
+                                               const u32* __restrict__ BG2, int64_t ldd,
+                                               int64_t pstride, const u32* __restrict__ D2t,
+                                               int64_t ldt,
+                                               const u32* __restrict__ R, u32* __restrict__ XT,
+                                               CompStore cs) {
   __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
   __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
   const int2 pr = plist[pbase + (int32_t)blockIdx.y];
   const bool sw = (pr.y & PAIR_SWAP) != 0;
   const int32_t s1 = pr.x, s2 = pr.y & ~PAIR_SWAP;
   const int64_t slot = blockIdx.y;
-  const int ntx = Vgp / 128;
+  const int ntx = Vrp / 128;
   const int tile = comp_tile();
   const int ti = tile / ntx, tj = tile % ntx;
-  const int32_t V1 = gV[s1], V2 = gV[s2];
-  if (ti * 128 >= V1 || tj * 128 >= V2) return;
+  const int32_t ka = m2[s1], mb = m2[s2];
+  const int32_t W1 = pos_width(gV[s1], ka, cs.pos != nullptr);
+  if (ti * 128 >= mb || tj * 128 >= W1) return;
   u32 c[8][8];
   fill_inf(c);
-  const int32_t kb = m2[s2];
-  const u32* At = XT + slot * m2pmax * Vgp + ti * 128;
-  const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
-  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB, V1 - ti * 128);
-  // the group's own closure when S1 = S2, folded in after the product: taken
-  // in first, it kept a second copy of the tile live through the K loop
-  if (s1 == s2)
-    tile_min128(c, Mg + (int64_t)s1 * Vgp * Vgp + (int64_t)ti * 128 * Vgp + tj * 128, Vgp);
-  const int tx = tid_x(), ty = tid_y();
-  const int32_t g1 = gbg0[s1], g2 = gbg0[s2];
-  if (sw) {
-    // the tile holds block (s2, s1) transposed: row x of s1 here is column x
-    // of the stored block (s2, s1), column y of s2 its row
-    u32* base = H + pairbase[(int64_t)s2 * ngroups + s1];
-    u32 rx[8], nx[8], lx[8];  // row terms of the stored block, from the columns
-    int32_t collab[8];
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int32_t y = tj * 128 + (j >> 2) * 64 + tx * 4 + (j & 3);
-      const int32_t yg = g2 + (y < V2 ? y : 0);
-      rx[j] = (u32)bgrow[yg] * (u32)V1;
-      nx[j] = (u32)bgnb[yg];
-      lx[j] = (u32)bglocal[yg];
-      if (CERT) collab[j] = bglabel[yg];
+  {
+    const u32* B = R + (int64_t)s1 * m2pmax * Vrp + tj * 128;
+    if (sw) {
+      const u32* At = D2t + (int64_t)b2off[s1] * ldt + b2off[s2] + ti * 128;
+      mp_stream128<true>(c, At, ldt, B, Vrp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB,
+                         mb - ti * 128);
+    } else {
+      const u32* At = BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd +
+                      (pstride ? 0 : b2off[s2]) + ti * 128;
+      // a panel holds INF past its group's B2 vertices: no column mask there
+      mp_stream128<true>(c, At, ldd, B, Vrp, (ka + 15) / 16 * 16, ka, pstride ? 128 : mb - ti * 128,
+                         sA, sB, mb - ti * 128);
     }
-    u32 best = 0, wrong = 0;
-#pragma unroll
-    for (int h = 0; h < 2; h++)
-#pragma unroll
-      for (int a = 0; a < 4; a++) {
-        const int32_t x = ti * 128 + h * 64 + ty * 4 + a;
-        if (x >= V1) continue;
-        const int32_t xg = g1 + x;
-        const u32 ry = (u32)bgrow[xg], ny = (u32)bgnb[xg], ly = (u32)bglocal[xg];
-        const int32_t labx = CERT ? bglabel[xg] : 0;
-        const int i = h * 4 + a;
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-          const int32_t y = tj * 128 + (j >> 2) * 64 + tx * 4 + (j & 3);
-          if (y >= V2) continue;
-          base[rx[j] + __umul24(nx[j], ry) + __umul24(lx[j], ny) + ly] = c[i][j];
-          if (CERT) {
-            if (c[i][j] < INF) best = max(best, c[i][j]);
-            else wrong |= (u32)(collab[j] == labx);
-          }
-        }
-      }
-    if (CERT) cert_reduce(best, wrong, cert_bad, cert_mbg);
-    return;
   }
-  u32* base = H + pairbase[(int64_t)s1 * ngroups + s2];
-  // column terms: rowoff(y), nb(y), loc(y) (and the label for the certificate)
-  u32 ry[8], ny[8], ly[8];
-  int32_t collab[8];
-#pragma unroll
-  for (int h2 = 0; h2 < 2; h2++)
-#pragma unroll
-    for (int a2 = 0; a2 < 4; a2++) {
-      const int32_t y = tj * 128 + h2 * 64 + tx * 4 + a2;
-      const int j = h2 * 4 + a2;
-      const int32_t yg = g2 + (y < V2 ? y : 0);
-      ry[j] = (u32)bgrow[yg];
-      ny[j] = (u32)bgnb[yg];
-      ly[j] = (u32)bglocal[yg];
-      if (CERT) collab[j] = bglabel[yg];
-    }
-  u32 best = 0, wrong = 0;
+  u32* out = XT + (slot * m2pmax + ti * 128) * Vrp + tj * 128;
+  const int tx = tid_x(), ty = tid_y();
 #pragma unroll
   for (int h = 0; h < 2; h++)
 #pragma unroll
     for (int a = 0; a < 4; a++) {
-      const int32_t x = ti * 128 + h * 64 + ty * 4 + a;
-      if (x >= V1) continue;
-      const int32_t xg = g1 + x;
-      const u32 rbase = (u32)bgrow[xg] * (u32)V2;
-      const u32 nbx = (u32)bgnb[xg], locx = (u32)bglocal[xg];
-      const int32_t labx = CERT ? bglabel[xg] : 0;
-      const int i = h * 4 + a;
+      const int row = h * 64 + ty * 4 + a;
+      const bool live = ti * 128 + row < mb;
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const int32_t y = tj * 128 + (j >> 2) * 64 + tx * 4 + (j & 3);
-        if (y >= V2) continue;
-        base[rbase + __umul24(nbx, ry[j]) + __umul24(locx, ny[j]) + ly[j]] = c[i][j];
-        if (CERT) {
-          if (c[i][j] < INF) best = max(best, c[i][j]);
-          else wrong |= (u32)(collab[j] == labx);
-        }
+      for (int h2 = 0; h2 < 2; h2++) {
+        const int i = h * 4 + a, j = h2 * 4;
+        uint4 v = live ? make_uint4(c[i][j], c[i][j + 1], c[i][j + 2], c[i][j + 3])
+                       : make_uint4(INF, INF, INF, INF);
+        *reinterpret_cast<uint4*>(out + (int64_t)row * Vrp + h2 * 64 + tx * 4) = v;
       }
     }
-  if (CERT) cert_reduce(best, wrong, cert_bad, cert_mbg);
+  if (MODE == 0) return;
+  // rows: B2 vertices of s2; columns: positions of s1
+  int32_t lr[8], lc[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const int32_t b = ti * 128 + (i >> 2) * 64 + ty * 4 + (i & 3);
+    lr[i] = b < mb ? cs.b2list[(int64_t)s2 * cs.Vgp + b] : -1;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; j++)
+    lc[j] = pos_local(cs.pos, (int64_t)s1 * Vrp, tj * 128 + (j >> 2) * 64 + tx * 4 + (j & 3), W1,
+                      gV[s1]);
+  // d_S1 between the two when S1 = S2: d_S1(b, x), the closure being symmetric
+  if (s1 == s2) tile_min_gather(c, cs.Mg + (int64_t)s1 * cs.Vgp * cs.Vgp, cs.Vgp, lr, lc);
+  u32* base = cs.H + (sw ? cs.pairbase[(int64_t)s2 * cs.ngroups + s1]
+                         : cs.pairbase[(int64_t)s1 * cs.ngroups + s2]);
+  const int32_t gr = cs.gbg0[s2], gc = cs.gbg0[s1];
+  if (sw)  // rows (group s2) are the block's rows
+    store_block<MODE == 2, true>(c, base, gr, gc, lr, lc, (u32)gV[s1], cs.bgrow, cs.bgnb, cs.bglocal,
+                                 cs.bglabel, cs.cert_bad, cs.cert_mbg);
+  else
+    store_block<MODE == 2, false>(c, base, gr, gc, lr, lc, (u32)gV[s2], cs.bgrow, cs.bgnb, cs.bglocal,
+                                  cs.bglabel, cs.cert_bad, cs.cert_mbg);
+}
+
+// D(S1,S2) tile for the pair of blockIdx.y, rows at positions of S1, columns
+// at positions of S2 past its B2 vertices (all of S2 without positions):
+//   min over b in B2(S2) of XT[b][x] + R_S2[b][y], and d_S1 when S1 = S2;
+// stored in the component-pair layout described at the top of the file.
+// CERT: the exactness certificate is fused into the store.
+template <bool CERT>
+__global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict__ plist, int32_t pbase,
+                                              int32_t Vrp, int32_t m2pmax,
+                                              const int32_t* __restrict__ m2,
+                                              const int32_t* __restrict__ gV,
+                                              const u32* __restrict__ XT, const u32* __restrict__ R,
+                                              CompStore cs) {
+  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
+  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
+  const int2 pr = plist[pbase + (int32_t)blockIdx.y];
+  const bool sw = (pr.y & PAIR_SWAP) != 0;
+  const int32_t s1 = pr.x, s2 = pr.y & ~PAIR_SWAP;
+  const int64_t slot = blockIdx.y;
+  const int ntx = Vrp / 128;
+  const int tile = comp_tile();
+  const int ti = tile / ntx, tj = tile % ntx;
+  const bool skip = cs.pos != nullptr;
+  const int32_t V1 = gV[s1], V2 = gV[s2], kb = m2[s2];
+  const int32_t W1 = pos_width(V1, m2[s1], skip), W2 = pos_width(V2, kb, skip);
+  const int32_t c0 = pos_first(kb, skip) + tj * 128;  // first column position of the tile
+  if (ti * 128 >= W1 || c0 >= W2) return;
+  u32 c[8][8];
+  fill_inf(c);
+  const u32* At = XT + slot * m2pmax * Vrp + ti * 128;
+  const u32* B = R + (int64_t)s2 * m2pmax * Vrp + c0;
+  mp_stream128<false>(c, At, Vrp, B, Vrp, (kb + 15) / 16 * 16, kb, 0, sA, sB, W1 - ti * 128);
+  const int tx = tid_x(), ty = tid_y();
+  int32_t lr[8], lc[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+    lr[i] = pos_local(cs.pos, (int64_t)s1 * Vrp, ti * 128 + (i >> 2) * 64 + ty * 4 + (i & 3), W1, V1);
+#pragma unroll
+  for (int j = 0; j < 8; j++)
+    lc[j] = pos_local(cs.pos, (int64_t)s2 * Vrp, c0 + (j >> 2) * 64 + tx * 4 + (j & 3), W2, V2);
+  // the group's own closure when S1 = S2, folded in after the product:
+  // taken in first, it kept a second copy of the tile live through the K loop
+  if (s1 == s2) tile_min_gather(c, cs.Mg + (int64_t)s1 * cs.Vgp * cs.Vgp, cs.Vgp, lr, lc);
+  u32* base = cs.H + (sw ? cs.pairbase[(int64_t)s2 * cs.ngroups + s1]
+                         : cs.pairbase[(int64_t)s1 * cs.ngroups + s2]);
+  const int32_t gr = cs.gbg0[s1], gc = cs.gbg0[s2];
+  if (sw)  // the stored block is (s2, s1): rows of s1 are its columns
+    store_block<CERT, false>(c, base, gr, gc, lr, lc, (u32)V1, cs.bgrow, cs.bgnb, cs.bglocal,
+                             cs.bglabel, cs.cert_bad, cs.cert_mbg);
+  else
+    store_block<CERT, true>(c, base, gr, gc, lr, lc, (u32)V2, cs.bgrow, cs.bgnb, cs.bglocal,
+                            cs.bglabel, cs.cert_bad, cs.cert_mbg);
 }
 
 // ------------------------------------------------------------- level 3
@@ -1150,9 +1254,16 @@ hipError_t launch_hier_level1(const HierArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The groups' positions and R_S by position.
+static void launch_rpos(const HierArgs& a, hipStream_t s) {
+  k_pos_build<<<(unsigned)a.ngroups, 256, 0, s>>>(a.gbg0, a.gV, a.b2rank, a.b2list, a.m2, a.Vgp, a.Vrp,
+                                                  a.pos);
+  k_rpos_gather<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(
+      a.Vgp, a.Vrp, a.m2pmax, a.m2, a.b2list, a.pos, a.Mg, a.R);
+}
+
 hipError_t launch_hier_level2_prep(const HierArgs& a, hipStream_t s) {
-  k_r_gather<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(a.Vgp, a.m2pmax, a.m2,
-                                                                           a.b2list, a.Mg, a.R);
+  launch_rpos(a, s);
   if (a.V2p > 0) {
     k_bg2_init<<<(unsigned)a.V2p, 256, 0, s>>>(a.V2, a.V2p, a.ngroups, a.b2off, a.b2list, a.Vgp, a.Mg,
                                                a.BG2);
@@ -1176,25 +1287,33 @@ hipError_t launch_hier_level2_close(const HierArgs& a, hipStream_t s) {
 // k_mp_y launch.  The share's BG2 rows come from its Bellman-Ford (DT^T).
 static hipError_t compose_level2(const HierArgs& a, const int32_t* bglabel, u32* cert_bad,
                                  u32* cert_mbg, hipStream_t s) {
-  const int ntx = a.Vgp / 128, ntm = a.m2pmax / 128;
+  const int32_t Vrp = a.pos ? a.Vrp : a.Vgp;
+  const int ntx = Vrp / 128, ntm = a.m2pmax / 128;
+  const CompStore cs{a.pos,     a.Vgp,    a.ngroups, a.b2list, a.gbg0,   a.bgrow,  a.bgnb,
+                     a.bglocal, bglabel,  a.Mg,      a.pairbase, a.H,    cert_bad, cert_mbg};
+  const int64_t ldd = a.d2pstride ? a.d2ld : a.V2p;
   for (int32_t p0 = 0, c = 0; p0 < a.npairs; p0 += a.chunk, c++) {
     const unsigned np = (unsigned)min(a.chunk, a.npairs - p0);
-    if (a.V2p > 0)
-      k_mp_xt<<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(
-          a.plist, p0, a.Vgp, a.m2pmax, a.m2, a.gV, a.b2off, a.BG2, a.d2pstride ? a.d2ld : a.V2p,
-          a.d2pstride, a.D2t, a.d2tld, a.R, a.XT);
+    const dim3 gx((unsigned)(ntm * ntx), np), gy((unsigned)(ntx * ntx), np);
+    if (a.V2p > 0) {
+      if (!a.pos)
+        k_mp_xt<0><<<gx, 256, 0, s>>>(a.plist, p0, Vrp, a.m2pmax, a.m2, a.gV, a.b2off, a.BG2, ldd,
+                                      a.d2pstride, a.D2t, a.d2tld, a.R, a.XT, cs);
+      else if (bglabel)
+        k_mp_xt<2><<<gx, 256, 0, s>>>(a.plist, p0, Vrp, a.m2pmax, a.m2, a.gV, a.b2off, a.BG2, ldd,
+                                      a.d2pstride, a.D2t, a.d2tld, a.R, a.XT, cs);
+      else
+        k_mp_xt<1><<<gx, 256, 0, s>>>(a.plist, p0, Vrp, a.m2pmax, a.m2, a.gV, a.b2off, a.BG2, ldd,
+                                      a.d2pstride, a.D2t, a.d2tld, a.R, a.XT, cs);
+    }
     if (a.evt) {
       hipError_t e = hipEventRecord(a.evt[2 * c], s);
       if (e != hipSuccess) return e;
     }
     if (bglabel)
-      k_mp_y<true><<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
-          a.plist, p0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase,
-          a.bgrow, a.bgnb, a.bglocal, a.H, bglabel, cert_bad, cert_mbg);
+      k_mp_y<true><<<gy, 256, 0, s>>>(a.plist, p0, Vrp, a.m2pmax, a.m2, a.gV, a.XT, a.R, cs);
     else
-      k_mp_y<false><<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
-          a.plist, p0, a.ngroups, a.Vgp, a.m2pmax, a.m2, a.gV, a.gbg0, a.XT, a.R, a.Mg, a.pairbase,
-          a.bgrow, a.bgnb, a.bglocal, a.H, nullptr, nullptr, nullptr);
+      k_mp_y<false><<<gy, 256, 0, s>>>(a.plist, p0, Vrp, a.m2pmax, a.m2, a.gV, a.XT, a.R, cs);
     if (a.evt) {
       hipError_t e = hipEventRecord(a.evt[2 * c + 1], s);
       if (e != hipSuccess) return e;
@@ -1261,9 +1380,10 @@ hipError_t launch_level3_compose(const L3Args& a, hipStream_t s) {
   for (int32_t p0 = 0; p0 < a.npairs; p0 += a.chunk) {
     const unsigned np = (unsigned)min(a.chunk, a.npairs - p0);
     if (a.V3p > 0)
-      k_mp_xt<<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(a.plist, p0, a.V3gp, a.m3pmax, a.m3,
-                                                              a.tsize, a.b3off, a.BG3, a.V3p, 0,
-                                                              nullptr, 0, a.R3, a.XT3);
+      k_mp_xt<0><<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(a.plist, p0, a.V3gp, a.m3pmax,
+                                                                 a.m3, a.tsize, a.b3off, a.BG3, a.V3p,
+                                                                 0, nullptr, 0, a.R3, a.XT3,
+                                                                 CompStore{});
     k_mp_y_dense<<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
         a.plist, p0, a.V3gp, a.m3pmax, a.m3, a.tsize, a.tbase, a.XT3, a.R3, a.M3, a.BG2, a.V2p);
   }
@@ -1282,8 +1402,7 @@ hipError_t launch_hier_row(const HierArgs& a, int32_t x, u32* out, hipStream_t s
 namespace spq {
 
 hipError_t launch_share_prepare(const HierArgs& a, const ShareBlocks& b, hipStream_t s) {
-  k_r_gather<<<dim3((unsigned)a.m2pmax, (unsigned)a.ngroups), 256, 0, s>>>(a.Vgp, a.m2pmax, a.m2,
-                                                                           a.b2list, a.Mg, a.R);
+  launch_rpos(a, s);
   k_blk_init<<<dim3((unsigned)b.bpmax, (unsigned)b.nblk), 256, 0, s>>>(a.Vgp, b.bpmax, b.bfirst,
                                                                        a.b2off, a.b2list, a.Mg,
                                                                        b.A);

@@ -92,6 +92,11 @@ struct HierArgs {
   int32_t *b2list, *b2rank, *m2;   // ngroups x Vgp, [V], [ngroups]
   const int32_t* b2off;            // [ngroups+1]
   u32 *R, *XT, *BG2, *H;
+  // the composition's positions (ngroups x Vrp, see hier.hip; NULL: local
+  // indices, R and XT of leading dimension Vgp, every column in the second
+  // product)
+  int32_t* pos = nullptr;
+  int32_t Vrp = 0;
   // BG2 as the first product reads it: dense (d2pstride = 0, leading
   // dimension V2p), or one column panel per group (share: S2p x m2pmax,
   // leading dimension d2ld = m2pmax, panels d2pstride apart)
