@@ -167,6 +167,14 @@ double mp_rows(int32_t v) {
   return rows;
 }
 
+// Columns of v valid ones that the composition kernels relax: whole
+// 128-tiles, and of the last, partial tile its first half alone when that
+// holds them all.
+double mp_cols(int32_t v) {
+  const int32_t rem = v % 128;
+  return (double)(v - rem) + (rem == 0 ? 0 : rem <= 64 ? 64 : 128);
+}
+
 }  // namespace
 
 // Fixed staging of spq_query_batch_host_static: v1, v2 and the answers of one
@@ -388,12 +396,10 @@ static void set_positions(spq_index* X) {
 // (columns: a1's positions, rows B2(a2)), the second over B2(a2) (rows: a1's
 // positions, columns: a2's vertices outside B2(a2)).
 static double xt_relax(const spq_index* X, int32_t a1, int32_t a2) {
-  return mp_rows(X->h_m2[a2]) * (double)((X->h_W[a1] + 127) / 128) * 128.0 *
-         (double)round_up(X->h_m2[a1], 16);
+  return mp_rows(X->h_m2[a2]) * mp_cols(X->h_W[a1]) * (double)round_up(X->h_m2[a1], 16);
 }
 static double y_relax(const spq_index* X, int32_t a1, int32_t a2) {
-  return mp_rows(X->h_W[a1]) * (double)((X->h_gV[a2] - X->h_m2[a2] + 127) / 128) * 128.0 *
-         (double)round_up(X->h_m2[a2], 16);
+  return mp_rows(X->h_W[a1]) * mp_cols(X->h_gV[a2] - X->h_m2[a2]) * (double)round_up(X->h_m2[a2], 16);
 }
 
 // The query kernel locates a pair block from the two vertex records alone:
@@ -1298,9 +1304,9 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       for (int32_t t1 = 0; t1 < nT; t1++)
         for (int32_t t2 = t1; t2 < nT; t2++) {
           if (X->V3p > 0)
-            X->relax_bg_exec += mp_rows(X->h_m3[t2]) * ((X->h_tsize[t1] + 127) / 128) * 128.0 *
+            X->relax_bg_exec += mp_rows(X->h_m3[t2]) * mp_cols(X->h_tsize[t1]) *
                                 (double)round_up(X->h_m3[t1], 16);
-          X->relax_bg_exec += mp_rows(X->h_tsize[t1]) * ((X->h_tsize[t2] + 127) / 128) * 128.0 *
+          X->relax_bg_exec += mp_rows(X->h_tsize[t1]) * mp_cols(X->h_tsize[t2]) *
                               (double)round_up(X->h_m3[t2], 16);
         }
       TRY(hipMemcpyAsync(X->b3off, X->h_b3off.data(), sizeof(int32_t) * (nT + 1),
@@ -1773,10 +1779,9 @@ spq_status spq_minplus_batched(int32_t layout, int32_t groups, const int32_t* nv
     pairbase[(size_t)s1 * groups + s2] = obase;
     obase += (int64_t)nv[s1] * nv[s2];
     // through B2(S1) instead of B2(S2): the products' roles exchanged
-    auto t128 = [](int32_t v) { return (double)((v + 127) / 128); };
     auto cost = [&](int32_t a, int32_t b) {
-      return mp_rows(nk[b]) * t128(nv[a]) * (double)round_up(nk[a], 16) +
-             mp_rows(nv[a]) * t128(nv[b]) * (double)round_up(nk[b], 16);
+      return mp_rows(nk[b]) * mp_cols(nv[a]) * (double)round_up(nk[a], 16) +
+             mp_rows(nv[a]) * mp_cols(nv[b]) * (double)round_up(nk[b], 16);
     };
     const bool sw = s1 != s2 && (assoc == 2 || (assoc == 1 && cost(s2, s1) < cost(s1, s2)));
     plist[p] = sw ? make_int2(s2, s1 | spq::PAIR_SWAP) : make_int2(s1, s2);

@@ -301,11 +301,11 @@ __device__ __forceinline__ uint4 mp_load_b(const u32* B, int64_t ldB, int k, int
 }
 
 // The relaxations of one LDS chunk for a thread's first NR rows (8 all, 4
-// the first half of the tile, 0 none: the wave only stages chunks).
-template <int NR>
+// the first half of the tile, 0 none: the wave only stages chunks) and its
+// first NC columns (8 all, 4 the first half).
+template <int NR, int NC = 8>
 __device__ __forceinline__ void mp_chunk(u32 (&c)[8][8], const u32* sA, const u32* sB, int K) {
-  if (NR == 8) minplus_lds<128>(c, sA, sB, K);
-  if (NR == 4) minplus_lds<128, 4>(c, sA, sB, K);
+  if (NR > 0) minplus_lds<128, NR, NC>(c, sA, sB, K);
 }
 
 // The rows a wave relaxes when only rows below rv of the tile are ever
@@ -319,7 +319,7 @@ __device__ __forceinline__ int wave_rows(int rv) {
   return (rv >= 128 || 64 + 16 * w < rv) ? 8 : (16 * w < rv) ? 4 : 0;
 }
 
-template <bool MASKED, int NR>
+template <bool MASKED, int NR, int NC>
 __device__ __forceinline__ void mp_stream128_n(u32 (&c)[8][8], const u32* At, int64_t ldA, const u32* B,
                                                int64_t ldB, int K, int kvalid, int avalid, u32* sA,
                                                u32* sB) {
@@ -346,7 +346,7 @@ __device__ __forceinline__ void mp_stream128_n(u32 (&c)[8][8], const u32* At, in
     pb0 = mp_load_b<MASKED>(B, ldB, kn + r0, c0, kvalid);
     pb1 = mp_load_b<MASKED>(B, ldB, kn + r1, c1, kvalid);
     const int cur = (ch & 1) * KC * T, nxt = ((ch + 1) & 1) * KC * T;
-    mp_chunk<NR>(c, sA + cur, sB + cur, KC);
+    mp_chunk<NR, NC>(c, sA + cur, sB + cur, KC);
     reinterpret_cast<uint4*>(sA + nxt)[e0] = pa0;
     reinterpret_cast<uint4*>(sA + nxt)[e1] = pa1;
     reinterpret_cast<uint4*>(sB + nxt)[e0] = pb0;
@@ -355,17 +355,27 @@ __device__ __forceinline__ void mp_stream128_n(u32 (&c)[8][8], const u32* At, in
   }
 }
 
+// Columns of c at or past cv are likewise left unfinished: when cv <= 64
+// every thread relaxes only its columns of the tile's first half (a branch
+// uniform over the workgroup).
 template <bool MASKED>
 __device__ __forceinline__ void mp_stream128(u32 (&c)[8][8], const u32* At, int64_t ldA, const u32* B,
                                              int64_t ldB, int K, int kvalid, int avalid, u32* sA,
-                                             u32* sB, int rv = 128) {
+                                             u32* sB, int rv = 128, int cv = 128) {
   const int nr = wave_rows(rv);
-  if (nr == 8)
-    mp_stream128_n<MASKED, 8>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
-  else if (nr == 4)
-    mp_stream128_n<MASKED, 4>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
-  else
-    mp_stream128_n<MASKED, 0>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
+  if (nr == 0)
+    mp_stream128_n<MASKED, 0, 8>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
+  else if (cv > 64) {
+    if (nr == 8)
+      mp_stream128_n<MASKED, 8, 8>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
+    else
+      mp_stream128_n<MASKED, 4, 8>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
+  } else {
+    if (nr == 8)
+      mp_stream128_n<MASKED, 8, 4>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
+    else
+      mp_stream128_n<MASKED, 4, 4>(c, At, ldA, B, ldB, K, kvalid, avalid, sA, sB);
+  }
 }
 
 // c = min(c, min over k < cnt of At[rows[k]][i] + B[bmap[rows[k]]][j]): the K
@@ -625,13 +635,13 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
     if (sw) {
       const u32* At = D2t + (int64_t)b2off[s1] * ldt + b2off[s2] + ti * 128;
       mp_stream128<true>(c, At, ldt, B, Vrp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB,
-                         mb - ti * 128);
+                         mb - ti * 128, W1 - tj * 128);
     } else {
       const u32* At = BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd +
                       (pstride ? 0 : b2off[s2]) + ti * 128;
       // a panel holds INF past its group's B2 vertices: no column mask there
       mp_stream128<true>(c, At, ldd, B, Vrp, (ka + 15) / 16 * 16, ka, pstride ? 128 : mb - ti * 128,
-                         sA, sB, mb - ti * 128);
+                         sA, sB, mb - ti * 128, W1 - tj * 128);
     }
   }
   u32* out = XT + (slot * m2pmax + ti * 128) * Vrp + tj * 128;
@@ -705,7 +715,8 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y(const int2* __restrict
   fill_inf(c);
   const u32* At = XT + slot * m2pmax * Vrp + ti * 128;
   const u32* B = R + (int64_t)s2 * m2pmax * Vrp + c0;
-  mp_stream128<false>(c, At, Vrp, B, Vrp, (kb + 15) / 16 * 16, kb, 0, sA, sB, W1 - ti * 128);
+  mp_stream128<false>(c, At, Vrp, B, Vrp, (kb + 15) / 16 * 16, kb, 0, sA, sB, W1 - ti * 128,
+                      W2 - c0);
   const int tx = tid_x(), ty = tid_y();
   int32_t lr[8], lc[8];
 #pragma unroll
@@ -819,7 +830,8 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y_dense(const int2* __re
   const int32_t kb = m2[s2];
   const u32* At = XT + slot * m2pmax * Vgp + ti * 128;
   const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
-  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB, V1 - ti * 128);
+  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB, V1 - ti * 128,
+                      V2 - tj * 128);
   // the group's own closure when S1 = S2, folded in after the product: taken
   // in first, it kept a second copy of the tile live through the K loop
   if (s1 == s2)

@@ -132,8 +132,8 @@ __device__ __forceinline__ void tile_to_lds(const u32 (&c)[T / 16][T / 16], u32*
 // order is free (a min-plus product), so two k are folded into one
 // v_min3_u32: 1.5 VALU operations per relaxation.  K is even.
 // NR: the thread's first NR rows only (NR = T/16 all of them; 4 with
-// 128-tiles: the rows of the tile's first half).
-template <int T, int NR = T / 16>
+// 128-tiles: the rows of the tile's first half); NC likewise for columns.
+template <int T, int NR = T / 16, int NC = T / 16>
 __device__ __forceinline__ void minplus_lds(u32 (&c)[T / 16][T / 16], const u32* At, const u32* B,
                                             int K) {
   constexpr int R = T / 16;
@@ -154,15 +154,17 @@ __device__ __forceinline__ void minplus_lds(u32 (&c)[T / 16][T / 16], const u32*
         a0[h * 4 + 0] = x0.x; a0[h * 4 + 1] = x0.y; a0[h * 4 + 2] = x0.z; a0[h * 4 + 3] = x0.w;
         a1[h * 4 + 0] = x1.x; a1[h * 4 + 1] = x1.y; a1[h * 4 + 2] = x1.z; a1[h * 4 + 3] = x1.w;
       }
-      uint4 y0 = *reinterpret_cast<const uint4*>(bp + k * T + h * 64);
-      uint4 y1 = *reinterpret_cast<const uint4*>(bp + (k + 1) * T + h * 64);
-      b0[h * 4 + 0] = y0.x; b0[h * 4 + 1] = y0.y; b0[h * 4 + 2] = y0.z; b0[h * 4 + 3] = y0.w;
-      b1[h * 4 + 0] = y1.x; b1[h * 4 + 1] = y1.y; b1[h * 4 + 2] = y1.z; b1[h * 4 + 3] = y1.w;
+      if (h * 4 < NC) {
+        uint4 y0 = *reinterpret_cast<const uint4*>(bp + k * T + h * 64);
+        uint4 y1 = *reinterpret_cast<const uint4*>(bp + (k + 1) * T + h * 64);
+        b0[h * 4 + 0] = y0.x; b0[h * 4 + 1] = y0.y; b0[h * 4 + 2] = y0.z; b0[h * 4 + 3] = y0.w;
+        b1[h * 4 + 0] = y1.x; b1[h * 4 + 1] = y1.y; b1[h * 4 + 2] = y1.z; b1[h * 4 + 3] = y1.w;
+      }
     }
 #pragma unroll
     for (int i = 0; i < NR; i++)
 #pragma unroll
-      for (int j = 0; j < R; j++) relax2(c[i][j], a0[i], b0[j], a1[i], b1[j]);
+      for (int j = 0; j < NC; j++) relax2(c[i][j], a0[i], b0[j], a1[i], b1[j]);
   }
 }
 
