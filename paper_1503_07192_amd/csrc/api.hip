@@ -393,10 +393,11 @@ static void set_positions(spq_index* X) {
 }
 
 // Executed relaxations of a pair's two products, the first over B2(a1)
-// (columns: a1's positions, rows B2(a2)), the second over B2(a2) (rows: a1's
-// positions, columns: a2's vertices outside B2(a2)).
+// (rows B2(a2), columns: a1's vertices outside B2(a1); its B2 columns are
+// copied from D2), the second over B2(a2) (rows: a1's positions, columns:
+// a2's vertices outside B2(a2)).
 static double xt_relax(const spq_index* X, int32_t a1, int32_t a2) {
-  return mp_rows(X->h_m2[a2]) * mp_cols(X->h_W[a1]) * (double)round_up(X->h_m2[a1], 16);
+  return mp_rows(X->h_m2[a2]) * mp_cols(X->h_gV[a1] - X->h_m2[a1]) * (double)round_up(X->h_m2[a1], 16);
 }
 static double y_relax(const spq_index* X, int32_t a1, int32_t a2) {
   return mp_rows(X->h_W[a1]) * mp_cols(X->h_gV[a2] - X->h_m2[a2]) * (double)round_up(X->h_m2[a2], 16);

@@ -527,36 +527,42 @@ __device__ __forceinline__ void store_block(const u32 (&c)[8][8], u32* base, int
                                             const int32_t* __restrict__ bglocal,
                                             const int32_t* __restrict__ bglabel, u32* cert_bad,
                                             u32* cert_mbg) {
-  // column terms: the block's y terms (rowoff, nb, loc), or with ROWS_X
-  // false its x terms (rowoff x |Y|, nb, loc)
-  u32 t0[8], t1[8], t2[8];
-  int32_t collab[8];
-#pragma unroll
-  for (int j = 0; j < 8; j++) {
-    const int32_t qg = gc + (lc[j] >= 0 ? lc[j] : 0);
-    t0[j] = ROWS_X ? (u32)bgrow[qg] : (u32)bgrow[qg] * nY;
-    t1[j] = (u32)bgnb[qg];
-    t2[j] = (u32)bglocal[qg];
-    if (CERT) collab[j] = bglabel[qg];
-  }
   u32 best = 0, wrong = 0;
+  // one half of the columns at a time (fewer live registers beside the tile)
 #pragma unroll
-  for (int i = 0; i < 8; i++) {
-    if (lr[i] < 0) continue;
-    const int32_t rg = gr + lr[i];
-    const u32 u0 = ROWS_X ? (u32)bgrow[rg] * nY : (u32)bgrow[rg];
-    const u32 u1 = (u32)bgnb[rg], u2 = (u32)bglocal[rg];
-    const int32_t labr = CERT ? bglabel[rg] : 0;
+  for (int h2 = 0; h2 < 2; h2++) {
+    // column terms: the block's y terms (rowoff, nb, loc), or with ROWS_X
+    // false its x terms (rowoff x |Y|, nb, loc); nb = 0 marks no column
+    u32 t0[4], t1[4], t2[4];
+    int32_t collab[4];
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-      if (lc[j] < 0) continue;
-      // rowoff(x) |Y| + nb(x) rowoff(y) + loc(x) nb(y) + loc(y)
-      const u32 off = ROWS_X ? u0 + __umul24(u1, t0[j]) + __umul24(u2, t1[j]) + t2[j]
-                             : t0[j] + __umul24(t1[j], u0) + __umul24(t2[j], u1) + u2;
-      base[off] = c[i][j];
-      if (CERT) {
-        if (c[i][j] < INF) best = max(best, c[i][j]);
-        else wrong |= (u32)(collab[j] == labr);
+    for (int jj = 0; jj < 4; jj++) {
+      const int32_t l = lc[h2 * 4 + jj];
+      const int32_t qg = gc + (l >= 0 ? l : 0);
+      t0[jj] = ROWS_X ? (u32)bgrow[qg] : (u32)bgrow[qg] * nY;
+      t1[jj] = l >= 0 ? (u32)bgnb[qg] : 0u;
+      t2[jj] = (u32)bglocal[qg];
+      if (CERT) collab[jj] = bglabel[qg];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      if (lr[i] < 0) continue;
+      const int32_t rg = gr + lr[i];
+      const u32 u0 = ROWS_X ? (u32)bgrow[rg] * nY : (u32)bgrow[rg];
+      const u32 u1 = (u32)bgnb[rg], u2 = (u32)bglocal[rg];
+      const int32_t labr = CERT ? bglabel[rg] : 0;
+#pragma unroll
+      for (int jj = 0; jj < 4; jj++) {
+        if (t1[jj] == 0) continue;
+        const u32 v = c[i][h2 * 4 + jj];
+        // rowoff(x) |Y| + nb(x) rowoff(y) + loc(x) nb(y) + loc(y)
+        const u32 off = ROWS_X ? u0 + __umul24(u1, t0[jj]) + __umul24(u2, t1[jj]) + t2[jj]
+                               : t0[jj] + __umul24(t1[jj], u0) + __umul24(t2[jj], u1) + u2;
+        base[off] = v;
+        if (CERT) {
+          if (v < INF) best = max(best, v);
+          else wrong |= (u32)(collab[jj] == labr);
+        }
       }
     }
   }
@@ -589,6 +595,75 @@ struct CompStore {
   u32 *cert_bad, *cert_mbg;
 };
 
+// The first product's entries at S1's B2 positions (positions only):
+// XT[b][a] = D2[a][b], the product's minimum taken at a itself
+// (d_S1(a, a) = 0; D2 is closed), stored as XT and into the query layout
+// (CERT: with the certificate).  One tile: B2 rows ti*128.. of S2 x
+// positions tj*128.. of S1; Ab = D2[B2(s1)][B2(s2)] as the product reads it
+// (row a, column b, leading dimension lda); sAB holds 8,192 words.
+template <bool CERT>
+__device__ __forceinline__ void xt_copy_tile(int32_t s1, int32_t s2, bool sw, int ti, int tj,
+                                             int32_t ka, int32_t mb, int32_t P1, const u32* Ab,
+                                             int64_t lda, u32* xt, int32_t Vrp,
+                                             const int32_t* __restrict__ gV, const CompStore& cs,
+                                             u32* sAB) {
+  const int tx = tid_x(), ty = tid_y();
+  u32 c[8][8];
+  // c holds rows a (positions tj*128 ..) and columns b, and is stored
+  // transposed.  The D2 rows are read whole (a wave reads 256 contiguous
+  // bytes), 64 rows at a time through LDS.
+  const int32_t bl = (int32_t)threadIdx.x & 127, b = ti * 128 + bl;
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    for (int q = 0; q < 32; q++) {
+      const int32_t r = 2 * q + ((int32_t)threadIdx.x >> 7), pa = tj * 128 + h * 64 + r;
+      sAB[r * 128 + bl] = (pa < ka && b < mb) ? Ab[(int64_t)pa * lda + b] : INF;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int h2 = 0; h2 < 2; h2++) {
+        const uint4 v = *reinterpret_cast<const uint4*>(sAB + (ty * 4 + a) * 128 + h2 * 64 + tx * 4);
+        c[h * 4 + a][h2 * 4] = v.x;
+        c[h * 4 + a][h2 * 4 + 1] = v.y;
+        c[h * 4 + a][h2 * 4 + 2] = v.z;
+        c[h * 4 + a][h2 * 4 + 3] = v.w;
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    u32* row = xt + (int64_t)((j >> 2) * 64 + tx * 4 + (j & 3)) * Vrp + tj * 128;
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+      if (tj * 128 + h * 64 + ty * 4 < P1)  // the product's tiles own the rest
+        *reinterpret_cast<uint4*>(row + h * 64 + ty * 4) =
+            make_uint4(c[h * 4][j], c[h * 4 + 1][j], c[h * 4 + 2][j], c[h * 4 + 3][j]);
+  }
+  int32_t lr[8], lc[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const int32_t pa = tj * 128 + (i >> 2) * 64 + ty * 4 + (i & 3);
+    lr[i] = pa < ka ? cs.pos[(int64_t)s1 * Vrp + pa] : -1;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const int32_t b = ti * 128 + (j >> 2) * 64 + tx * 4 + (j & 3);
+    lc[j] = b < mb ? cs.b2list[(int64_t)s2 * cs.Vgp + b] : -1;
+  }
+  // D(s1, s2)[a][b] = D2[a][b] (no closure term: d_S1 >= D2 on B2 pairs)
+  u32* base = cs.H + (sw ? cs.pairbase[(int64_t)s2 * cs.ngroups + s1]
+                         : cs.pairbase[(int64_t)s1 * cs.ngroups + s2]);
+  const int32_t gr = cs.gbg0[s1], gc = cs.gbg0[s2];
+  if (sw)  // the stored block is (s2, s1): rows (group s1) are its columns
+    store_block<CERT, false>(c, base, gr, gc, lr, lc, (u32)gV[s1], cs.bgrow, cs.bgnb, cs.bglocal,
+                             cs.bglabel, cs.cert_bad, cs.cert_mbg);
+  else
+    store_block<CERT, true>(c, base, gr, gc, lr, lc, (u32)gV[s2], cs.bgrow, cs.bgnb, cs.bglocal,
+                            cs.bglabel, cs.cert_bad, cs.cert_mbg);
+}
+
 // XT (m2pmax x Vrp, rows b in B2(S2), columns: positions of S1) =
 //   min over a in B2(S1) of D2[a][b] + R_S1[a][x].
 // D2 rows are level-2 ids of the sources (all of BG2, or the share's rows),
@@ -616,36 +691,48 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
                                                int64_t ldt,
                                                const u32* __restrict__ R, u32* __restrict__ XT,
                                                CompStore cs) {
-  __shared__ __attribute__((aligned(16))) u32 sA[2 * 16 * 128];
-  __shared__ __attribute__((aligned(16))) u32 sB[2 * 16 * 128];
+  __shared__ __attribute__((aligned(16))) u32 sAB[4 * 16 * 128];
+  u32* sA = sAB;
+  u32* sB = sAB + 2 * 16 * 128;
   const int2 pr = plist[pbase + (int32_t)blockIdx.y];
   const bool sw = (pr.y & PAIR_SWAP) != 0;
   const int32_t s1 = pr.x, s2 = pr.y & ~PAIR_SWAP;
   const int64_t slot = blockIdx.y;
-  const int ntx = Vrp / 128;
-  const int tile = comp_tile();
+  const bool skip = cs.pos != nullptr;
+  const int ntx = Vrp / 128, ntm = m2pmax / 128;
+  // with positions the grid holds twice ntm x ntx tiles: the product's,
+  // then as many for S1's B2 positions (copied, see xt_copy_tile).  Both
+  // halves keep the product's tile numbering, so that the tiles of one
+  // column of a pair still share an XCD.
+  int tile = comp_tile();
+  const bool copy = tile >= ntm * ntx;
+  if (copy) tile -= ntm * ntx;
   const int ti = tile / ntx, tj = tile % ntx;
   const int32_t ka = m2[s1], mb = m2[s2];
-  const int32_t W1 = pos_width(gV[s1], ka, cs.pos != nullptr);
-  if (ti * 128 >= mb || tj * 128 >= W1) return;
+  if (ti * 128 >= mb) return;
+  // with positions the product's tiles start past S1's B2 positions
+  const int32_t P1 = pos_first(ka, skip), W1 = pos_width(gV[s1], ka, skip);
+  // D2[B2(s1)][B2(s2)] as the product reads it (row a, column b)
+  const u32* Ab = sw ? D2t + (int64_t)b2off[s1] * ldt + b2off[s2]
+                     : BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd + (pstride ? 0 : b2off[s2]);
+  const int64_t lda = sw ? ldt : ldd;
+  u32* xt = XT + (slot * m2pmax + ti * 128) * Vrp;
+  if (MODE > 0 && copy) {
+    if (tj * 128 < P1)
+      xt_copy_tile<MODE == 2>(s1, s2, sw, ti, tj, ka, mb, P1, Ab, lda, xt, Vrp, gV, cs, sAB);
+    return;
+  }
+  const int tx = tid_x(), ty = tid_y();
   u32 c[8][8];
+  const int32_t p0 = P1 + tj * 128;  // first position of the tile
+  if (p0 >= W1) return;
   fill_inf(c);
   {
-    const u32* B = R + (int64_t)s1 * m2pmax * Vrp + tj * 128;
-    if (sw) {
-      const u32* At = D2t + (int64_t)b2off[s1] * ldt + b2off[s2] + ti * 128;
-      mp_stream128<true>(c, At, ldt, B, Vrp, (ka + 15) / 16 * 16, ka, mb - ti * 128, sA, sB,
-                         mb - ti * 128, W1 - tj * 128);
-    } else {
-      const u32* At = BG2 + (int64_t)s2 * pstride + (int64_t)b2off[s1] * ldd +
-                      (pstride ? 0 : b2off[s2]) + ti * 128;
-      // a panel holds INF past its group's B2 vertices: no column mask there
-      mp_stream128<true>(c, At, ldd, B, Vrp, (ka + 15) / 16 * 16, ka, pstride ? 128 : mb - ti * 128,
-                         sA, sB, mb - ti * 128, W1 - tj * 128);
-    }
+    const u32* B = R + (int64_t)s1 * m2pmax * Vrp + p0;
+    // a panel holds INF past its group's B2 vertices: no column mask there
+    mp_stream128<true>(c, Ab + ti * 128, lda, B, Vrp, (ka + 15) / 16 * 16, ka,
+                       (pstride && !sw) ? 128 : mb - ti * 128, sA, sB, mb - ti * 128, W1 - p0);
   }
-  u32* out = XT + (slot * m2pmax + ti * 128) * Vrp + tj * 128;
-  const int tx = tid_x(), ty = tid_y();
 #pragma unroll
   for (int h = 0; h < 2; h++)
 #pragma unroll
@@ -655,9 +742,11 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
 #pragma unroll
       for (int h2 = 0; h2 < 2; h2++) {
         const int i = h * 4 + a, j = h2 * 4;
+        const int32_t p = p0 + h2 * 64 + tx * 4;  // a multiple of 4: the 4 lie in one row
+        if (p >= Vrp) continue;
         uint4 v = live ? make_uint4(c[i][j], c[i][j + 1], c[i][j + 2], c[i][j + 3])
                        : make_uint4(INF, INF, INF, INF);
-        *reinterpret_cast<uint4*>(out + (int64_t)row * Vrp + h2 * 64 + tx * 4) = v;
+        *reinterpret_cast<uint4*>(xt + (int64_t)row * Vrp + p) = v;
       }
     }
   if (MODE == 0) return;
@@ -670,8 +759,7 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
   }
 #pragma unroll
   for (int j = 0; j < 8; j++)
-    lc[j] = pos_local(cs.pos, (int64_t)s1 * Vrp, tj * 128 + (j >> 2) * 64 + tx * 4 + (j & 3), W1,
-                      gV[s1]);
+    lc[j] = pos_local(cs.pos, (int64_t)s1 * Vrp, p0 + (j >> 2) * 64 + tx * 4 + (j & 3), W1, gV[s1]);
   // d_S1 between the two when S1 = S2: d_S1(b, x), the closure being symmetric
   if (s1 == s2) tile_min_gather(c, cs.Mg + (int64_t)s1 * cs.Vgp * cs.Vgp, cs.Vgp, lr, lc);
   u32* base = cs.H + (sw ? cs.pairbase[(int64_t)s2 * cs.ngroups + s1]
@@ -1306,7 +1394,8 @@ static hipError_t compose_level2(const HierArgs& a, const int32_t* bglabel, u32*
   const int64_t ldd = a.d2pstride ? a.d2ld : a.V2p;
   for (int32_t p0 = 0, c = 0; p0 < a.npairs; p0 += a.chunk, c++) {
     const unsigned np = (unsigned)min(a.chunk, a.npairs - p0);
-    const dim3 gx((unsigned)(ntm * ntx), np), gy((unsigned)(ntx * ntx), np);
+    // with positions the first product's grid holds the copied tiles too
+    const dim3 gx((unsigned)(ntm * ntx * (a.pos ? 2 : 1)), np), gy((unsigned)(ntx * ntx), np);
     if (a.V2p > 0) {
       if (!a.pos)
         k_mp_xt<0><<<gx, 256, 0, s>>>(a.plist, p0, Vrp, a.m2pmax, a.m2, a.gV, a.b2off, a.BG2, ldd,
