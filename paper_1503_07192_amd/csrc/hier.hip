@@ -1132,20 +1132,32 @@ __global__ void k_bf_cross(int32_t nxe, const int4* __restrict__ xe, int32_t S2,
     for (int q = threadIdx.x; q < ntc; q += blockDim.x) listed[q] = 0u;
     __syncthreads();
   }
-  for (int32_t i = threadIdx.x; i < S2; i += blockDim.x) {
-    const int tile = i >> 7;
+  // four consecutive columns per thread and step (one 16-byte load of each
+  // row; rows are S2p words apart, a multiple of 128, and the four lie in
+  // one column tile)
+  for (int32_t i0 = 4 * (int32_t)threadIdx.x; i0 < S2; i0 += 4 * (int32_t)blockDim.x) {
+    const int tile = i0 >> 7;
     if (!dsrc[tile]) continue;
-    const u32 v = min(src[i] + (u32)t.z, INF);
-    if (v < dst[i]) {
-      atomicMin(dst + i, v);
-      dnext[tile] = 1u;
-      dnext[ntc] = 1u;
-      if (local && atomicExch(listed + tile, 1u) != 0u) continue;
-      if (atomicExch(stamp + (int64_t)t.y * ntc + tile, round) != round) {
-        const int64_t st = (int64_t)sv * ntc + tile;
-        const int32_t slot = atomicAdd(rcnt_next + st, 1);
-        rlist_next[st * lstride + slot] = b3rank[t.y];
+    const uint4 a4 = *reinterpret_cast<const uint4*>(src + i0);
+    const uint4 d4 = *reinterpret_cast<const uint4*>(dst + i0);
+    const u32 av[4] = {a4.x, a4.y, a4.z, a4.w}, dv[4] = {d4.x, d4.y, d4.z, d4.w};
+    bool lowered = false;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const u32 v = min(av[q] + (u32)t.z, INF);
+      if (i0 + q < S2 && v < dv[q]) {
+        atomicMin(dst + i0 + q, v);
+        lowered = true;
       }
+    }
+    if (!lowered) continue;
+    dnext[tile] = 1u;
+    dnext[ntc] = 1u;
+    if (local && atomicExch(listed + tile, 1u) != 0u) continue;
+    if (atomicExch(stamp + (int64_t)t.y * ntc + tile, round) != round) {
+      const int64_t st = (int64_t)sv * ntc + tile;
+      const int32_t slot = atomicAdd(rcnt_next + st, 1);
+      rlist_next[st * lstride + slot] = b3rank[t.y];
     }
   }
 }
