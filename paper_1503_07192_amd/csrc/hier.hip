@@ -701,9 +701,9 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
   const bool skip = cs.pos != nullptr;
   const int ntx = Vrp / 128, ntm = m2pmax / 128;
   // with positions the grid holds twice ntm x ntx tiles: the product's,
-  // then as many for S1's B2 positions (copied, see xt_copy_tile).  Both
-  // halves keep the product's tile numbering, so that the tiles of one
-  // column of a pair still share an XCD.
+  // then as many for S1's B2 positions (copied, see xt_copy_tile), numbered
+  // alike, which keeps the product's tile order (the copies as extra
+  // columns of each row measured much slower)
   int tile = comp_tile();
   const bool copy = tile >= ntm * ntx;
   if (copy) tile -= ntm * ntx;
