@@ -240,6 +240,7 @@ struct spq_index {
   int64_t V3p = 0;
   std::vector<int32_t> h_tbase, h_tsize, h_m3, h_b3off;
   int32_t *tbase = nullptr, *tsize = nullptr, *b3list = nullptr, *b3rank = nullptr, *m3 = nullptr;
+  int32_t* pos3 = nullptr;  // the super-groups' positions
   int32_t* b3off = nullptr;
   uint8_t* flag3 = nullptr;
   // composition pair lists (level 2 or share, level 3)
@@ -321,7 +322,7 @@ struct spq_index {
                     sb_flag, sb_flagn, sb_list, sb_nlist, sb_rank, sb_nrank, sb_m, sb_n, sb_A3, sb_Aout,
                     xe, xcount, boff, bsize, bfirst, gblk,
                     eu_own, ev_own, w_own, tbase, tsize, b3list, b3rank, m3, b3off, flag3,
-                    M3, R3, XT3, BG3, plist, plist3, rowptr, adj, adeg, w_copy};
+                    M3, R3, XT3, BG3, plist, plist3, rowptr, adj, adeg, w_copy, pos3};
     for (void* p : ptrs) pool_release(p);
   }
 };
@@ -1299,25 +1300,39 @@ spq_status spq_build_index(int32_t n, int64_t m, const int32_t* eu, const int32_
       X->V3 = X->h_b3off[nT];
       X->V3p = round_up(X->V3, 128);
       X->m3pmax = (int32_t)std::max<int64_t>(128, round_up(m3max, 128));
-      // executed relaxations of level 3
+      // the super-groups' positions (B3 vertices first, as the groups' at
+      // level 2): widths and their bound V3rp
+      std::vector<int32_t> w3(nT);
+      int64_t w3max = 0;
+      for (int32_t t = 0; t < nT; t++) {
+        w3[t] = (int32_t)round_up(X->h_m3[t], 4) + X->h_tsize[t] - X->h_m3[t];
+        w3max = std::max<int64_t>(w3max, w3[t]);
+      }
+      const int32_t V3rp = (int32_t)std::max<int64_t>(128, round_up(w3max, 128));
+      // executed relaxations of level 3 (the first product over T1's
+      // vertices outside B3, its B3 positions being copied; the second over
+      // T2's vertices outside B3)
       X->relax_bg_exec += nT * spq::dense_fw_exec_relax(V3gp / 128, 128, X->cpivot);
       if (X->V3p > 0) X->relax_bg_exec += spq::dense_fw_exec_relax(X->V3p / 128, 128, X->cpivot);
       for (int32_t t1 = 0; t1 < nT; t1++)
         for (int32_t t2 = t1; t2 < nT; t2++) {
           if (X->V3p > 0)
-            X->relax_bg_exec += mp_rows(X->h_m3[t2]) * mp_cols(X->h_tsize[t1]) *
+            X->relax_bg_exec += mp_rows(X->h_m3[t2]) * mp_cols(X->h_tsize[t1] - X->h_m3[t1]) *
                                 (double)round_up(X->h_m3[t1], 16);
-          X->relax_bg_exec += mp_rows(X->h_tsize[t1]) * mp_cols(X->h_tsize[t2]) *
+          X->relax_bg_exec += mp_rows(w3[t1]) * mp_cols(X->h_tsize[t2] - X->h_m3[t2]) *
                               (double)round_up(X->h_m3[t2], 16);
         }
       TRY(hipMemcpyAsync(X->b3off, X->h_b3off.data(), sizeof(int32_t) * (nT + 1),
                          hipMemcpyHostToDevice, s));
-      TRY(dalloc(&X->R3, (int64_t)nT * X->m3pmax * V3gp));
+      // R3's last row is read up to 127 words past its end (as R's)
+      TRY(dalloc(&X->R3, (int64_t)nT * X->m3pmax * V3rp + 128));
+      TRY(dalloc(&X->pos3, (int64_t)nT * V3rp));
       int32_t np3 = 0, ch3 = 0;
-      TRY(make_pairs(nT, nT, true, (int64_t)X->m3pmax * V3gp, X->V2p * X->V2p / 2, &X->plist3,
+      TRY(make_pairs(nT, nT, true, (int64_t)X->m3pmax * V3rp, X->V2p * X->V2p / 2, &X->plist3,
                      &np3, &ch3, s));
-      TRY(dalloc(&X->XT3, (int64_t)ch3 * X->m3pmax * V3gp));
+      TRY(dalloc(&X->XT3, (int64_t)ch3 * X->m3pmax * V3rp));
       la.plist = X->plist3; la.npairs = np3; la.chunk = ch3;
+      la.pos3 = X->pos3; la.V3rp = V3rp;
       if (X->V3p > 0) TRY(dalloc(&X->BG3, X->V3p * X->V3p));
       la.V3 = X->V3; la.V3p = X->V3p; la.m3pmax = X->m3pmax; la.b3off = X->b3off; la.R3 = X->R3;
       la.XT3 = X->XT3; la.BG3 = X->BG3; la.side = ha.side; la.sync = ha.sync;

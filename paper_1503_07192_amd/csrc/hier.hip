@@ -583,8 +583,9 @@ __device__ __forceinline__ void tile_min_gather(u32 (&c)[8][8], const u32* __res
   }
 }
 
-// The composition's optional stores (the build's; the test hook and level 3
-// pass none): positions, the query layout and the certificate.
+// The composition's optional stores (the builds'; the test hooks pass
+// none): positions, and the query layout with the certificate or (level 3)
+// the dense BG2 matrix.
 struct CompStore {
   const int32_t* pos;        // ngroups x Vrp, NULL: identity
   int32_t Vgp, ngroups;      // Mg and b2list leading dimension; groups
@@ -593,7 +594,31 @@ struct CompStore {
   const int64_t* pairbase;
   u32* H;
   u32 *cert_bad, *cert_mbg;
+  // dense store (level 3): element (x, y) of the pair block (S1, S2) at
+  // dense[(dbase[S1] + x) * ldo + dbase[S2] + y]; NULL: the query layout
+  u32* dense = nullptr;
+  int64_t ldo = 0;
+  const int32_t* dbase = nullptr;
 };
+
+// Stores tile c into a dense matrix: row i of the thread is vertex lr[i]
+// (-1: none), column j vertex lc[j], of the groups whose first rows are gx
+// (the block's rows) and gy; ROWS_X: c's rows are the block's rows, else its
+// columns.
+template <bool ROWS_X>
+__device__ __forceinline__ void store_dense(const u32 (&c)[8][8], u32* out, int64_t ldo, int64_t gx,
+                                            int64_t gy, const int32_t (&lr)[8], const int32_t (&lc)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    if (lr[i] < 0) continue;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      if (lc[j] < 0) continue;
+      const int64_t off = ROWS_X ? (gx + lr[i]) * ldo + gy + lc[j] : (gx + lc[j]) * ldo + gy + lr[i];
+      out[off] = c[i][j];
+    }
+  }
+}
 
 // The first product's entries at S1's B2 positions (positions only):
 // XT[b][a] = D2[a][b], the product's minimum taken at a itself
@@ -653,6 +678,10 @@ __device__ __forceinline__ void xt_copy_tile(int32_t s1, int32_t s2, bool sw, in
     lc[j] = b < mb ? cs.b2list[(int64_t)s2 * cs.Vgp + b] : -1;
   }
   // D(s1, s2)[a][b] = D2[a][b] (no closure term: d_S1 >= D2 on B2 pairs)
+  if (cs.dense) {
+    store_dense<true>(c, cs.dense, cs.ldo, cs.dbase[s1], cs.dbase[s2], lr, lc);
+    return;
+  }
   u32* base = cs.H + (sw ? cs.pairbase[(int64_t)s2 * cs.ngroups + s1]
                          : cs.pairbase[(int64_t)s1 * cs.ngroups + s2]);
   const int32_t gr = cs.gbg0[s1], gc = cs.gbg0[s2];
@@ -762,6 +791,10 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_xt(const int2* __restric
     lc[j] = pos_local(cs.pos, (int64_t)s1 * Vrp, p0 + (j >> 2) * 64 + tx * 4 + (j & 3), W1, gV[s1]);
   // d_S1 between the two when S1 = S2: d_S1(b, x), the closure being symmetric
   if (s1 == s2) tile_min_gather(c, cs.Mg + (int64_t)s1 * cs.Vgp * cs.Vgp, cs.Vgp, lr, lc);
+  if (cs.dense) {  // rows: the block's columns y
+    store_dense<false>(c, cs.dense, cs.ldo, cs.dbase[s1], cs.dbase[s2], lr, lc);
+    return;
+  }
   u32* base = cs.H + (sw ? cs.pairbase[(int64_t)s2 * cs.ngroups + s1]
                          : cs.pairbase[(int64_t)s1 * cs.ngroups + s2]);
   const int32_t gr = cs.gbg0[s2], gc = cs.gbg0[s1];
@@ -891,15 +924,18 @@ __global__ void k_l3_edges(int64_t m, const int32_t* __restrict__ eu, const int3
   }
 }
 
-// d_BG2 tile for the super-group pair (T1, T2) of blockIdx.y, rows x of T1,
-// columns y of T2: min over b in B3(T2) of XT[b][x] + R_T2[b][y], and d_T1
-// when T1 = T2; stored densely (row gbase[T1] + x, column gbase[T2] + y of
-// out, leading dimension ldo).
+// D_BG2 tile for the super-group pair of blockIdx.y (T1 <= T2), rows at
+// positions of T1, columns at positions of T2 past its B3 vertices (all of
+// T2 without positions, pos NULL), into the dense matrix out (leading
+// dimension ldo, rows and columns from the super-groups' first BG2 ids
+// gbase).  XT and R have rows Vrp words long; Mg (the closures, leading
+// dimension Vgp) is folded in when T1 = T2.
 __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y_dense(const int2* __restrict__ plist, int32_t pbase,
-                                                    int32_t Vgp,
+                                                    int32_t Vgp, int32_t Vrp,
                                                     int32_t m2pmax, const int32_t* __restrict__ m2,
                                                     const int32_t* __restrict__ gV,
                                                     const int32_t* __restrict__ gbase,
+                                                    const int32_t* __restrict__ pos,
                                                     const u32* __restrict__ XT, const u32* __restrict__ R,
                                                     const u32* __restrict__ Mg, u32* __restrict__ out,
                                                     int64_t ldo) {
@@ -908,39 +944,31 @@ __global__ __launch_bounds__(256) SPQ_MP_ATTR void k_mp_y_dense(const int2* __re
   const int2 pr = plist[pbase + (int32_t)blockIdx.y];
   const int32_t s1 = pr.x, s2 = pr.y;
   const int64_t slot = blockIdx.y;
-  const int ntx = Vgp / 128;
+  const int ntx = Vrp / 128;
   const int tile = comp_tile();
   const int ti = tile / ntx, tj = tile % ntx;
-  const int32_t V1 = gV[s1], V2 = gV[s2];
-  if (ti * 128 >= V1 || tj * 128 >= V2) return;
+  const bool skip = pos != nullptr;
+  const int32_t V1 = gV[s1], V2 = gV[s2], kb = m2[s2];
+  const int32_t W1 = pos_width(V1, m2[s1], skip), W2 = pos_width(V2, kb, skip);
+  const int32_t c0 = pos_first(kb, skip) + tj * 128;  // first column position of the tile
+  if (ti * 128 >= W1 || c0 >= W2) return;
   u32 c[8][8];
   fill_inf(c);
-  const int32_t kb = m2[s2];
-  const u32* At = XT + slot * m2pmax * Vgp + ti * 128;
-  const u32* B = R + (int64_t)s2 * m2pmax * Vgp + tj * 128;
-  mp_stream128<false>(c, At, Vgp, B, Vgp, (kb + 15) / 16 * 16, kb, 0, sA, sB, V1 - ti * 128,
-                      V2 - tj * 128);
-  // the group's own closure when S1 = S2, folded in after the product: taken
-  // in first, it kept a second copy of the tile live through the K loop
-  if (s1 == s2)
-    tile_min128(c, Mg + (int64_t)s1 * Vgp * Vgp + (int64_t)ti * 128 * Vgp + tj * 128, Vgp);
+  const u32* At = XT + slot * m2pmax * Vrp + ti * 128;
+  const u32* B = R + (int64_t)s2 * m2pmax * Vrp + c0;
+  mp_stream128<false>(c, At, Vrp, B, Vrp, (kb + 15) / 16 * 16, kb, 0, sA, sB, W1 - ti * 128,
+                      W2 - c0);
   const int tx = tid_x(), ty = tid_y();
-  const int64_t col0 = gbase[s2];
+  int32_t lr[8], lc[8];
 #pragma unroll
-  for (int h = 0; h < 2; h++)
+  for (int i = 0; i < 8; i++)
+    lr[i] = pos_local(pos, (int64_t)s1 * Vrp, ti * 128 + (i >> 2) * 64 + ty * 4 + (i & 3), W1, V1);
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
-      const int32_t x = ti * 128 + h * 64 + ty * 4 + a;
-      if (x >= V1) continue;
-      u32* row = out + ((int64_t)gbase[s1] + x) * ldo + col0;
-#pragma unroll
-      for (int h2 = 0; h2 < 2; h2++)
-#pragma unroll
-        for (int a2 = 0; a2 < 4; a2++) {
-          const int32_t y = tj * 128 + h2 * 64 + tx * 4 + a2;
-          if (y < V2) row[y] = c[h * 4 + a][h2 * 4 + a2];
-        }
-    }
+  for (int j = 0; j < 8; j++)
+    lc[j] = pos_local(pos, (int64_t)s2 * Vrp, c0 + (j >> 2) * 64 + tx * 4 + (j & 3), W2, V2);
+  // the super-group's own closure when T1 = T2, folded in after the product
+  if (s1 == s2) tile_min_gather(c, Mg + (int64_t)s1 * Vgp * Vgp, Vgp, lr, lc);
+  store_dense<true>(c, out, ldo, gbase[s1], gbase[s2], lr, lc);
 }
 
 // One BG row (BG id x) gathered from the two-level store, for inspection.
@@ -1469,8 +1497,15 @@ hipError_t launch_level3_a(const L3Args& a, hipStream_t s) {
 }
 
 hipError_t launch_level3_b(const L3Args& a, hipStream_t s) {
-  k_r_gather<<<dim3((unsigned)a.m3pmax, (unsigned)a.nT), 256, 0, s>>>(a.V3gp, a.m3pmax, a.m3, a.b3list,
-                                                                       a.M3, a.R3);
+  if (a.pos3) {  // the super-groups' positions and R_T by position
+    k_pos_build<<<(unsigned)a.nT, 256, 0, s>>>(a.tbase, a.tsize, a.b3rank, a.b3list, a.m3, a.V3gp,
+                                               a.V3rp, a.pos3);
+    k_rpos_gather<<<dim3((unsigned)a.m3pmax, (unsigned)a.nT), 256, 0, s>>>(
+        a.V3gp, a.V3rp, a.m3pmax, a.m3, a.b3list, a.pos3, a.M3, a.R3);
+  } else {
+    k_r_gather<<<dim3((unsigned)a.m3pmax, (unsigned)a.nT), 256, 0, s>>>(a.V3gp, a.m3pmax, a.m3,
+                                                                         a.b3list, a.M3, a.R3);
+  }
   if (a.V3p > 0) {
     k_bg2_init<<<(unsigned)a.V3p, 256, 0, s>>>(a.V3, a.V3p, a.nT, a.b3off, a.b3list, a.V3gp, a.M3,
                                                a.BG3);
@@ -1489,16 +1524,30 @@ hipError_t launch_level3_b(const L3Args& a, hipStream_t s) {
 }
 
 hipError_t launch_level3_compose(const L3Args& a, hipStream_t s) {
-  const int ntx = a.V3gp / 128, ntm = a.m3pmax / 128;
+  // with positions (the build): the first product copies T1's B3 positions
+  // (the grid's second half) and stores the B3 columns of T2 into BG2, the
+  // second runs over T2's other vertices; without (the test hook): plain
+  const int32_t Vrp = a.pos3 ? a.V3rp : a.V3gp;
+  const int ntx = Vrp / 128, ntm = a.m3pmax / 128;
+  CompStore cs{};
+  if (a.pos3) {
+    cs.pos = a.pos3; cs.Vgp = a.V3gp; cs.ngroups = a.nT; cs.b2list = a.b3list; cs.Mg = a.M3;
+    cs.dense = a.BG2; cs.ldo = a.V2p; cs.dbase = a.tbase;
+  }
   for (int32_t p0 = 0; p0 < a.npairs; p0 += a.chunk) {
     const unsigned np = (unsigned)min(a.chunk, a.npairs - p0);
-    if (a.V3p > 0)
-      k_mp_xt<0><<<dim3((unsigned)(ntm * ntx), np), 256, 0, s>>>(a.plist, p0, a.V3gp, a.m3pmax,
-                                                                 a.m3, a.tsize, a.b3off, a.BG3, a.V3p,
-                                                                 0, nullptr, 0, a.R3, a.XT3,
-                                                                 CompStore{});
+    if (a.V3p > 0) {
+      const dim3 gx((unsigned)(ntm * ntx * (a.pos3 ? 2 : 1)), np);
+      if (a.pos3)
+        k_mp_xt<1><<<gx, 256, 0, s>>>(a.plist, p0, Vrp, a.m3pmax, a.m3, a.tsize, a.b3off, a.BG3, a.V3p, 0,
+                                      nullptr, 0, a.R3, a.XT3, cs);
+      else
+        k_mp_xt<0><<<gx, 256, 0, s>>>(a.plist, p0, Vrp, a.m3pmax, a.m3, a.tsize, a.b3off, a.BG3, a.V3p, 0,
+                                      nullptr, 0, a.R3, a.XT3, cs);
+    }
     k_mp_y_dense<<<dim3((unsigned)(ntx * ntx), np), 256, 0, s>>>(
-        a.plist, p0, a.V3gp, a.m3pmax, a.m3, a.tsize, a.tbase, a.XT3, a.R3, a.M3, a.BG2, a.V2p);
+        a.plist, p0, a.V3gp, Vrp, a.m3pmax, a.m3, a.tsize, a.tbase, a.pos3, a.XT3, a.R3, a.M3, a.BG2,
+        a.V2p);
   }
   return hipGetLastError();
 }

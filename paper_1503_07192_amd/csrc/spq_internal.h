@@ -205,8 +205,12 @@ struct L3Args {
   uint8_t* flag3;                      // [V2]
   int32_t *b3list, *b3rank, *m3;       // nT x V3gp, [V2], [nT]
   const int32_t* b3off;                // [nT+1]
-  u32 *R3, *BG3;                       // nT x m3pmax x V3gp, V3p x V3p
-  u32* XT3;                            // chunk x m3pmax x V3gp
+  u32 *R3, *BG3;                       // nT x m3pmax x V3rp, V3p x V3p
+  u32* XT3;                            // chunk x m3pmax x V3rp
+  // the super-groups' positions (nT x V3rp, as the groups' at level 2;
+  // NULL: local indices, V3rp = V3gp)
+  int32_t* pos3 = nullptr;
+  int32_t V3rp = 0;
   const int2* plist;                   // super-group pairs T1 <= T2
   int32_t npairs, chunk;               //   their count, pairs per launch
 };
